@@ -1,0 +1,315 @@
+"""Cartesian meshes, permeability fields, boundary data and sources.
+
+Every function here is seeded and deterministic.  The arrays describe the
+boundary-value problem of Section 2 of the paper (mass conservation with
+Darcy's law, K(x, p) = K0(x) kappa(p), kappa(p) = exp(alpha p), Dirichlet and
+Neumann data) on a conforming mesh given as cells and an unstructured face
+list.  Nothing here evaluates the finite-volume scheme itself.
+
+Conventions shared by both consumers of these arrays:
+  * ``face_cells[f] = (K, L)``; ``L = -1`` on a boundary face.
+  * ``face_normal[f]`` is the unit normal pointing out of cell K.
+  * ``face_point[f]`` is the collocation point x_eps (Section 2.1, remark on
+    collocation points): the face centre for these Cartesian meshes.
+  * ``face_bc``: 0 interior, 1 Dirichlet, 2 Neumann.
+  * ``source`` is the density f of the mass-conservation equation (not yet
+    multiplied by the cell measure); ``g_neumann`` is g_N = -q.n.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Mesh:
+    dim: int
+    cell_volume: np.ndarray        # [n] float64
+    cell_centroid: np.ndarray      # [n, dim] float64
+    cell_k0: np.ndarray            # [n, dim, dim] float64, K0 tensor
+    face_cells: np.ndarray         # [nf, 2] int32
+    face_area: np.ndarray          # [nf] float64
+    face_normal: np.ndarray        # [nf, dim] float64, out of K
+    face_point: np.ndarray         # [nf, dim] float64
+    face_bc: np.ndarray            # [nf] int8
+    shape: Optional[tuple] = None  # lattice shape when structured (informational)
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_volume.shape[0])
+
+    @property
+    def n_faces(self) -> int:
+        return int(self.face_area.shape[0])
+
+
+@dataclasses.dataclass
+class Problem:
+    mesh: Mesh
+    alpha: float                   # kappa(p) = exp(alpha p)
+    source: np.ndarray             # [n] density f
+    g_dirichlet: np.ndarray        # [nf] used where face_bc == 1
+    g_neumann: np.ndarray          # [nf] used where face_bc == 2
+    name: str = ""
+    # hierarchy configuration of the workload (box edge per axis, number of
+    # local eigenvectors per aggregate, number of levels)
+    box: tuple = ()
+    m: int = 1
+    n_levels: int = 2
+    dp_cap_c: float = 5.0          # cap constant c: max |dp| <= ln(c)/alpha
+
+
+# ---------------------------------------------------------------- meshes
+
+def cartesian_mesh(shape, spacing, k_cells, dirichlet=((0, 0),)) -> Mesh:
+    """Uniform Cartesian mesh with cell id = i + nx*(j + ny*k).
+
+    ``k_cells`` is [n] (isotropic K0 = k I) or [n, dim] (diagonal K0).
+    ``dirichlet`` lists (axis, side) boundary sides that carry Dirichlet
+    data; all other boundary sides are Neumann.
+    """
+    shape = tuple(int(s) for s in shape)
+    dim = len(shape)
+    h = np.asarray(spacing, dtype=np.float64)
+    assert h.shape == (dim,)
+    n = int(np.prod(shape))
+    idx = np.arange(n)
+    # lattice coordinates, x fastest
+    coords = []
+    rem = idx.copy()
+    for a in range(dim):
+        coords.append(rem % shape[a])
+        rem //= shape[a]
+    coords = np.stack(coords, axis=1)
+    centroid = (coords.astype(np.float64) + 0.5) * h[None, :]
+    vol = np.full(n, float(np.prod(h)))
+    k = np.asarray(k_cells, dtype=np.float64)
+    k0 = np.zeros((n, dim, dim))
+    if k.ndim == 1:
+        for a in range(dim):
+            k0[:, a, a] = k
+    else:
+        for a in range(dim):
+            k0[:, a, a] = k[:, a]
+
+    strides = [1]
+    for a in range(1, dim):
+        strides.append(strides[-1] * shape[a - 1])
+
+    fK, fL, farea, fnorm, fpt, fbc = [], [], [], [], [], []
+    dset = set(tuple(d) for d in dirichlet)
+    for a in range(dim):
+        area = float(np.prod(h)) / h[a]
+        e = np.zeros(dim)
+        e[a] = 1.0
+        inner = coords[:, a] < shape[a] - 1
+        K = idx[inner]
+        fK.append(K)
+        fL.append(K + strides[a])
+        farea.append(np.full(K.size, area))
+        fnorm.append(np.tile(e, (K.size, 1)))
+        pt = centroid[K].copy()
+        pt[:, a] = (coords[K, a] + 1).astype(np.float64) * h[a]
+        fpt.append(pt)
+        fbc.append(np.zeros(K.size, dtype=np.int8))
+    for a in range(dim):
+        area = float(np.prod(h)) / h[a]
+        for side in (0, 1):
+            sel = coords[:, a] == (0 if side == 0 else shape[a] - 1)
+            K = idx[sel]
+            e = np.zeros(dim)
+            e[a] = -1.0 if side == 0 else 1.0
+            fK.append(K)
+            fL.append(np.full(K.size, -1))
+            farea.append(np.full(K.size, area))
+            fnorm.append(np.tile(e, (K.size, 1)))
+            pt = centroid[K].copy()
+            pt[:, a] = 0.0 if side == 0 else shape[a] * h[a]
+            fpt.append(pt)
+            fbc.append(np.full(K.size, 1 if (a, side) in dset else 2, dtype=np.int8))
+    face_cells = np.stack([np.concatenate(fK), np.concatenate(fL)], axis=1).astype(np.int32)
+    return Mesh(dim=dim, cell_volume=vol, cell_centroid=centroid, cell_k0=k0,
+                face_cells=face_cells, face_area=np.concatenate(farea),
+                face_normal=np.concatenate(fnorm), face_point=np.concatenate(fpt),
+                face_bc=np.concatenate(fbc), shape=shape)
+
+
+def permute_mesh(prob: Problem, seed: int) -> Problem:
+    """Seeded random cell permutation, face shuffle and orientation flips.
+
+    The result is the same boundary-value problem written as an unstructured
+    face list: cell ids are scrambled, faces are listed in random order and
+    each interior face is oriented K->L or L->K at random.
+    """
+    rng = np.random.default_rng(seed)
+    m = prob.mesh
+    n, nf = m.n_cells, m.n_faces
+    new_of_old = rng.permutation(n)
+    old_of_new = np.empty(n, dtype=np.int64)
+    old_of_new[new_of_old] = np.arange(n)
+    forder = rng.permutation(nf)
+    flip = rng.random(nf) < 0.5
+    fc = m.face_cells[forder].astype(np.int64)
+    fl = flip[forder] & (fc[:, 1] >= 0)
+    K = np.where(fc[:, 0] >= 0, new_of_old[fc[:, 0]], -1)
+    L = np.where(fc[:, 1] >= 0, new_of_old[np.maximum(fc[:, 1], 0)], -1)
+    K2 = np.where(fl, L, K)
+    L2 = np.where(fl, K, L)
+    normal = m.face_normal[forder].copy()
+    normal[fl] *= -1.0
+    mesh = Mesh(dim=m.dim, cell_volume=m.cell_volume[old_of_new],
+                cell_centroid=m.cell_centroid[old_of_new], cell_k0=m.cell_k0[old_of_new],
+                face_cells=np.stack([K2, L2], axis=1).astype(np.int32),
+                face_area=m.face_area[forder], face_normal=normal,
+                face_point=m.face_point[forder], face_bc=m.face_bc[forder], shape=m.shape)
+    return dataclasses.replace(prob, mesh=mesh, source=prob.source[old_of_new],
+                               g_dirichlet=prob.g_dirichlet[forder],
+                               g_neumann=prob.g_neumann[forder])
+
+
+# ---------------------------------------------------------------- fields
+
+def gaussian_field(shape, corr_len, rng) -> np.ndarray:
+    """Standardised Gaussian random field: white noise on a 2x padded
+    lattice, smoothed by a Gaussian kernel whose standard deviation is
+    ``corr_len`` cells (product of 1-D kernels applied through FFT), cropped,
+    then shifted/scaled to sample mean 0 and standard deviation 1.  Returned
+    array is indexed [i, j(, k)] with x first."""
+    shape = tuple(int(s) for s in shape)
+    pad = tuple(2 * s for s in shape)
+    w = rng.standard_normal(pad)
+    spec = np.fft.fftn(w)
+    for a, s in enumerate(pad):
+        freq = np.fft.fftfreq(s)  # cycles per cell
+        filt = np.exp(-2.0 * (math.pi * corr_len * freq) ** 2)
+        sh = [1] * len(pad)
+        sh[a] = s
+        spec = spec * filt.reshape(sh)
+    g = np.real(np.fft.ifftn(spec))
+    g = g[tuple(slice(0, s) for s in shape)]
+    g = (g - g.mean()) / g.std()
+    return g
+
+
+def channel_field(nx, ny, nlayers, rng, k_in=1e3, k_out=1e-3, group=5) -> np.ndarray:
+    """Binary sinuous channels along y, indexed [i, j, layer].
+
+    Per group of ``group`` layers: 4..8 channels with centre
+    x_c(y) = x0 + A sin(2 pi y / lam + phi), x0 ~ U[0, nx), A ~ U[3, 12],
+    lam ~ U[40, 120], phi ~ U[0, 2 pi), half-width ~ U[1.5, 4] cells, and x0
+    jittered by U[-1, 1] per layer.  k = k_in inside a channel, k_out outside.
+    """
+    k = np.full((nx, ny, nlayers), k_out)
+    x = np.arange(nx) + 0.5
+    y = np.arange(ny) + 0.5
+    for g0 in range(0, nlayers, group):
+        nch = int(rng.integers(4, 9))
+        chans = []
+        for _ in range(nch):
+            chans.append((rng.uniform(0, nx), rng.uniform(3, 12), rng.uniform(40, 120),
+                          rng.uniform(0, 2 * math.pi), rng.uniform(1.5, 4.0)))
+        for lay in range(g0, min(g0 + group, nlayers)):
+            for (x0, A, lam, phi, hw) in chans:
+                jit = rng.uniform(-1.0, 1.0)
+                xc = x0 + jit + A * np.sin(2 * math.pi * y / lam + phi)  # [ny]
+                inside = np.abs(x[:, None] - xc[None, :]) <= hw          # [nx, ny]
+                k[:, :, lay][inside] = k_in
+    return k
+
+
+# ---------------------------------------------------------------- workloads
+
+def _flat(field):
+    """[i, j(, k)] array -> cell-id order (x fastest)."""
+    return np.asarray(field).transpose(tuple(range(field.ndim))[::-1]).reshape(-1)
+
+
+def c1_problem(seed: int = 0) -> Problem:
+    """2D unit square, 32x32 cells, cell id = i + 32 j; log10 k ~ N(0,1) per
+    cell in cell-id order; kappa = exp(p); source density +1 in cell (0,0)
+    and -1 in cell (31,31); p = 0 on x = 0, no flow elsewhere; 2 levels of
+    4x4 aggregates with 2 local eigenvectors each."""
+    rng = np.random.default_rng(seed)
+    n = 32
+    z = rng.standard_normal(n * n)
+    k = 10.0 ** z
+    mesh = cartesian_mesh((n, n), (1.0 / n, 1.0 / n), k, dirichlet=((0, 0),))
+    src = np.zeros(n * n)
+    src[0] = 1.0
+    src[n * n - 1] = -1.0
+    return Problem(mesh=mesh, alpha=1.0, source=src, g_dirichlet=np.zeros(mesh.n_faces),
+                   g_neumann=np.zeros(mesh.n_faces), name="c1_2d_32x32",
+                   box=(4, 4), m=2, n_levels=2, dp_cap_c=5.0)
+
+
+# Total well rate of the 60x220x85 workload.  Chosen so that the linear
+# (kappa = 1) pressure has max |p| of about 0.5 (stronger sinks can leave the
+# exp(p) problem without a solution); the calibration script
+# tests/golden/calibrate_c2_rate.py recomputes the figure.
+C2_WELL_RATE = 1.0
+
+
+def c2_problem(seed: int = 0, rate: Optional[float] = None, permute: bool = True,
+               shape=(60, 220, 85), spacing=(6.1, 3.05, 0.61), top_layers: int = 35) -> Problem:
+    """3D 60x220x85 hex grid (cells 6.1 x 3.05 x 0.61 m): top 35 layers
+    log-normal (ln k = 2 G, correlation length 5 cells), bottom layers binary
+    sinuous channels (k = 1e3 / 1e-3); p = 0 on y = 0, no flow elsewhere;
+    injector column at (0, 0) and producer column at (nx-1, ny-1) over all
+    layers; kappa = exp(p); stored as an unstructured face list after a seeded
+    random cell permutation.  4 levels of 4x4x4 aggregates, 3 eigenvectors."""
+    rng = np.random.default_rng(seed)
+    nx, ny, nz = shape
+    ktop = np.exp(2.0 * gaussian_field((nx, ny, min(top_layers, nz)), 5.0, rng))
+    kbot = channel_field(nx, ny, nz - min(top_layers, nz), rng) if nz > top_layers else None
+    kf = ktop if kbot is None else np.concatenate([ktop, kbot], axis=2)
+    k = _flat(kf)
+    mesh = cartesian_mesh(shape, spacing, k, dirichlet=((1, 0),))
+    q = C2_WELL_RATE if rate is None else rate
+    vol = float(mesh.cell_volume[0])
+    src = np.zeros(mesh.n_cells)
+    for kz in range(nz):
+        src[0 + nx * (0 + ny * kz)] += q / (nz * vol)
+        src[(nx - 1) + nx * ((ny - 1) + ny * kz)] -= q / (nz * vol)
+    prob = Problem(mesh=mesh, alpha=1.0, source=src, g_dirichlet=np.zeros(mesh.n_faces),
+                   g_neumann=np.zeros(mesh.n_faces), name="c2_3d_60x220x85",
+                   box=(4, 4, 4), m=3, n_levels=4, dp_cap_c=5.0)
+    if permute:
+        prob = permute_mesh(prob, seed + 1)
+    return prob
+
+
+def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=None, m=2,
+                  n_levels=2, spacing=None, g_d_scale=0.0, g_n_scale=0.0, src_scale=1.0,
+                  anisotropic=False, permute=False, dp_cap_c=5.0) -> Problem:
+    """Small seeded test problem: ln k = sigma * N(0,1) i.i.d. per cell,
+    zero-mean random source density, optional random Dirichlet and Neumann
+    data, optional diagonal anisotropic K0 and optional permutation."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(shape)
+    dim = len(shape)
+    n = int(np.prod(shape))
+    if spacing is None:
+        spacing = tuple(1.0 / s for s in shape)
+    if anisotropic:
+        k = np.exp(sigma * rng.standard_normal((n, dim)))
+    else:
+        k = np.exp(sigma * rng.standard_normal(n))
+    mesh = cartesian_mesh(shape, spacing, k, dirichlet=dirichlet)
+    src = rng.standard_normal(n)
+    src -= src.mean()
+    src *= src_scale
+    gd = g_d_scale * rng.standard_normal(mesh.n_faces)
+    gn = g_n_scale * rng.standard_normal(mesh.n_faces)
+    gd[mesh.face_bc != 1] = 0.0
+    gn[mesh.face_bc != 2] = 0.0
+    if box is None:
+        box = tuple(min(2, s) for s in shape)
+    prob = Problem(mesh=mesh, alpha=alpha, source=src, g_dirichlet=gd, g_neumann=gn,
+                   name=f"small_{'x'.join(map(str, shape))}_s{seed}", box=tuple(box), m=m,
+                   n_levels=n_levels, dp_cap_c=dp_cap_c)
+    if permute:
+        prob = permute_mesh(prob, seed + 7)
+    return prob
