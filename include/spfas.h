@@ -1,0 +1,279 @@
+/*
+ * spfas -- nonlinear spectral multigrid (FAS) for heterogeneous nonlinear
+ * diffusion, MI355X (gfx950) library.  C ABI.
+ *
+ * Method: Lee, Hamon, Castelletto, Vassilevski, White, "Nonlinear multigrid
+ * based on local spectral coarsening for heterogeneous diffusion problems"
+ * (arXiv 2005.01275).
+ *
+ * Problem (Section 2, eqs. model and kappa): find p with
+ *     div q = f,   q = -K0(x) kappa(p) grad p   in Omega,
+ *     p = g_D on the Dirichlet boundary,  -q.n = g_N on the Neumann boundary,
+ * with kappa(p) = exp(alpha p), discretised by cell-centred two-point flux
+ * finite volumes in mixed form (Section 2.1, eq. FV_matrix): one pressure per
+ * cell, one flux per interior or Dirichlet face.
+ *
+ * Conventions for every entry point:
+ *   - Return value: SPFAS_OK (0), SPFAS_NOT_CONVERGED (1, outputs written,
+ *     see stats) or a negative error code.  On a negative code the outputs
+ *     are left untouched and spfas_last_error() describes the failure.
+ *   - No exceptions cross the ABI.  One handle must not be used by two
+ *     threads at the same time.  Different handles are independent.
+ *   - "stream" is a hipStream_t passed as void*; NULL means the default
+ *     stream.  All device work of a call is enqueued on it; the calls below
+ *     return after that work has completed (convergence is decided on the
+ *     host), unless stated otherwise.
+ *   - Arrays flagged SPFAS_MEM_DEVICE are device pointers on the current
+ *     device; SPFAS_MEM_HOST arrays are ordinary host memory.  The caller
+ *     keeps ownership of every array it passes.
+ *   - Cell and face numbering of inputs and outputs is always the caller's
+ *     ("input order").  Internal renumbering is invisible except through the
+ *     parity hooks at the end of this header.
+ */
+#ifndef SPFAS_H
+#define SPFAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPFAS_API_VERSION 1
+
+typedef struct spfas_hierarchy spfas_hierarchy;   /* opaque; owns its device memory */
+
+typedef enum {
+  SPFAS_OK = 0,
+  SPFAS_NOT_CONVERGED = 1,   /* max_it reached: state and stats written   */
+  SPFAS_ERR_INVALID = -1,    /* bad argument or mesh; nothing written     */
+  SPFAS_ERR_OOM = -2,        /* device allocation failed                  */
+  SPFAS_ERR_DEVICE = -3,     /* HIP runtime error                         */
+  SPFAS_ERR_NUMERIC = -4     /* non-finite residual, kappa or solve       */
+} spfas_status;
+
+typedef enum { SPFAS_MEM_HOST = 0, SPFAS_MEM_DEVICE = 1 } spfas_mem;
+typedef enum { SPFAS_FACE_INTERIOR = 0, SPFAS_FACE_DIRICHLET = 1, SPFAS_FACE_NEUMANN = 2 } spfas_face_kind;
+typedef enum { SPFAS_NEWTON = 0, SPFAS_PICARD = 1 } spfas_smoother;
+
+/*
+ * Mesh (Section 2.1).  HOST memory, read during spfas_setup_hierarchy only.
+ *   cell_volume   [n_cells]           |tau_K| > 0
+ *   cell_centroid [n_cells*dim]       x_K, cell-major; also used to recover
+ *                                     the lattice of a Cartesian mesh for box
+ *                                     aggregation (distinct coordinate values
+ *                                     per axis, exact comparison)
+ *   cell_k0       [n_cells*dim*dim]   K0 of each cell, row-major
+ *   face_cells    [2*n_faces]         (K, L) per face; L = -1 on the boundary.
+ *                                     Interior faces are oriented K -> L and
+ *                                     sigma > 0 means flow from K to L.
+ *   face_area     [n_faces]           |eps|
+ *   face_normal   [n_faces*dim]       unit normal pointing out of K
+ *   face_point    [n_faces*dim]       collocation point x_eps
+ *   face_kind     [n_faces]           spfas_face_kind
+ * The half-transmissibilities of eq. half-transmissibility are computed from
+ * these on the device and must be positive.
+ */
+typedef struct {
+  int32_t dim;
+  int64_t n_cells;
+  int64_t n_faces;
+  const double* cell_volume;
+  const double* cell_centroid;
+  const double* cell_k0;
+  const int32_t* face_cells;
+  const double* face_area;
+  const double* face_normal;
+  const double* face_point;
+  const int8_t* face_kind;
+} spfas_mesh;
+
+/*
+ * Coarsening options (Section 3.1, Appendix A).
+ *   n_levels  number of levels including the fine one (>= 1)
+ *   box       aggregate edge per axis on each level's lattice; a remainder
+ *             block with fewer than box/2 cells merges into its neighbour
+ *   m         local eigenvectors kept per aggregate (m_A, uniform; clamped
+ *             to the number of pressure unknowns of the aggregate)
+ *   host_only nonzero: build only the host-side integer structure
+ *             (aggregates and renumbering) without touching the GPU; only
+ *             spfas_get_aggregation / spfas_get_permutation /
+ *             spfas_level_sizes / spfas_destroy accept such a handle.
+ */
+typedef struct {
+  int32_t n_levels;
+  int32_t box[3];
+  int32_t m;
+  int32_t host_only;
+} spfas_coarsen_opts;
+
+/*
+ * Problem data of one solve (Section 2, eq. model).
+ *   alpha        kappa(p) = exp(alpha p)
+ *   source       [n_cells]  density f (multiplied by |tau_K| internally)
+ *   g_dirichlet  [n_faces]  g_D, read on Dirichlet faces; NULL means 0
+ *   g_neumann    [n_faces]  g_N = -q.n, read on Neumann faces; NULL means 0
+ *   mem          where the three arrays live
+ */
+typedef struct {
+  double alpha;
+  const double* source;
+  const double* g_dirichlet;
+  const double* g_neumann;
+  int32_t mem;
+} spfas_problem;
+
+/*
+ * Solve options (Section 4 and Alg. 1).
+ *   smoother            SPFAS_NEWTON or SPFAS_PICARD (FAS only; the
+ *                       single-level entry points fix it by name)
+ *   rtol, atol          stop when ||r(x)||_2 <= max(rtol*||r(x0)||_2, atol)
+ *   max_it              V-cycles (FAS) or nonlinear steps (single level)
+ *   bt_nmax, bt_theta   Alg. 1 parameters (paper: 4 and 0.9)
+ *   dp_cap              max |delta p| per smoothing step, ln(c)/alpha in the
+ *                       paper (c = 1.5 or 5); <= 0 disables the cap
+ *   coarsest_max_steps  smoothing steps on the coarsest level (paper: 10)
+ *   lin_rtol, lin_max_it  inner Krylov tolerance and iteration limit
+ *   x0_given            nonzero: p and sigma hold the initial guess on entry
+ */
+typedef struct {
+  int32_t smoother;
+  double rtol;
+  double atol;
+  int32_t max_it;
+  int32_t bt_nmax;
+  double bt_theta;
+  double dp_cap;
+  int32_t coarsest_max_steps;
+  double lin_rtol;
+  int32_t lin_max_it;
+  int32_t x0_given;
+} spfas_solve_opts;
+
+typedef struct {
+  int32_t iterations;       /* V-cycles or nonlinear steps taken            */
+  int32_t lin_iters;        /* Krylov iterations summed over all solves     */
+  int32_t bt_halvings;      /* step halvings taken by Alg. 1                */
+  int32_t smoothing_steps;  /* smoothing steps on all levels                */
+  int32_t stopped_after_presmooth;  /* last V-cycle ended after pre-smoothing */
+  double r0;                /* ||r(x0)||                                    */
+  double r_final;           /* ||r(x)|| on return                          */
+  double solve_ms;          /* wall time of the call (host clock)           */
+} spfas_stats;
+
+/* Fills *o with the paper's settings (Section 4): Newton, rtol 1e-8, atol
+ * 1e-10, max_it 50, n_max 4, theta 0.9, no cap, 10 coarsest steps, inner
+ * rtol 1e-8 and 500 inner iterations, x0 = 0. */
+void spfas_default_solve_opts(spfas_solve_opts* o);
+
+/*
+ * Builds the multilevel hierarchy (Section 3.1, Appendix A; Prop. 1 for the
+ * static coarse local matrices; Appendix B for the projector weights):
+ * half-transmissibilities, box aggregation and renumbering on the host,
+ * then batched on the device the local spectral problems, PV traces, trace
+ * extensions, bubbles, P_sigma, P_p, Q and M^{l+1}_A, D^{l+1}_A.  The
+ * hierarchy depends on the mesh only and serves any number of solves.
+ * Errors: ERR_INVALID for a malformed mesh (index out of range, non-positive
+ * volume or half-transmissibility, no Dirichlet face, n_levels < 1, a lattice
+ * that cannot be recovered from the centroids), ERR_OOM, ERR_DEVICE.
+ * *out receives a handle to be released with spfas_destroy.
+ */
+int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts,
+                          void* stream, spfas_hierarchy** out);
+
+/*
+ * Solves the nonlinear system (eq. nonlinear_system_residual_form) with FAS
+ * V-cycles (Alg. 2): Picard or Newton smoothing with the step cap and Alg. 1,
+ * restriction R = P^T, projection Q, coarse problems
+ * r^{l+1}(y) = A^{l+1}(y) - [A^{l+1}(Q x) - R r^l(x)] (eq.
+ * coarse_level_residual) built from the coarse local matrices without
+ * visiting the fine level, and at most coarsest_max_steps smoothing steps on
+ * the coarsest level.
+ *   p      [n_cells]  in: initial guess if x0_given; out: pressure
+ *   sigma  [n_faces]  in: initial guess if x0_given (Neumann entries
+ *                     ignored); out: flux of every face, -|eps| g_N on
+ *                     Neumann faces
+ *   state_mem  where p and sigma live
+ *   stats      may be NULL
+ * Returns OK, NOT_CONVERGED (state written), ERR_INVALID, ERR_NUMERIC
+ * (state untouched), ERR_DEVICE.
+ */
+int spfas_fas_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts,
+                    double* p, double* sigma, int32_t state_mem, spfas_stats* stats, void* stream);
+
+/* Single-level Picard iteration (Section 2.2; Section 3.3 for the Picard
+ * system) on the fine level with the same cap and Alg. 1.  Arguments and
+ * errors as spfas_fas_solve; opts->smoother is ignored. */
+int spfas_picard_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts,
+                       double* p, double* sigma, int32_t state_mem, spfas_stats* stats, void* stream);
+
+/* Single-level Newton iteration (Section 2.2; Jacobian of Section 3.3,
+ * Prop. 3 on the fine level).  As spfas_picard_solve. */
+int spfas_newton_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts,
+                       double* p, double* sigma, int32_t state_mem, spfas_stats* stats, void* stream);
+
+/*
+ * Fine-level residual r(x) = A(x) - b (eqs. fine_level_residual and
+ * fine_level_operators) at the state (p, sigma), written in input order:
+ *   r_p     [n_cells]  D sigma + f
+ *   r_sigma [n_faces]  M(p) sigma + D^T p + g; 0 on Neumann faces
+ * All four arrays live in `mem`.
+ */
+int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const double* p,
+                        const double* sigma, double* r_p, double* r_sigma, int32_t mem, void* stream);
+
+/* ------------------------------------------------------------------ parity hooks
+ * Read-only views of the hierarchy used to compare it with an independent
+ * implementation.  "Canonical order" on level 0 is the input order of
+ * cells and of the non-Neumann faces; on level l+1 it is the aggregate id
+ * (boxes numbered lexicographically, x fastest) for cells and, for flux
+ * unknowns: interfaces between aggregates A < B sorted by (A, B), then
+ * Dirichlet groups by A, then bubbles by (A, j).  Pressure unknowns of a
+ * cell are consecutive.  All outputs are HOST arrays.
+ */
+
+/* Sizes of level l: cells, pressure unknowns, flux unknowns. */
+int spfas_level_sizes(const spfas_hierarchy* h, int32_t level, int64_t* n_cells, int64_t* n_p,
+                      int64_t* n_flux);
+
+/* agg[n_cells(level)]: canonical aggregate id of each canonical cell of
+ * `level` (0 <= level < n_levels-1). */
+int spfas_get_aggregation(const spfas_hierarchy* h, int32_t level, int32_t* agg);
+
+/* Renumbering of `level` (0 <= level < n_levels-1): cell_order[n_cells] and
+ * flux_order[n_flux] give, for each internal position, the canonical id.
+ * Cells are contiguous per aggregate; flux unknowns are grouped inside-
+ * aggregate / per interface / Dirichlet. */
+int spfas_get_permutation(const spfas_hierarchy* h, int32_t level, int32_t* cell_order,
+                          int32_t* flux_order);
+
+typedef enum {
+  SPFAS_OP_EIGVALS = 0,  /* level l: spectrum of each aggregate's L_A, ascending, aggregates in canonical order */
+  SPFAS_OP_PP = 1,       /* level l: P_A blocks (n_pA x m_A, row-major), canonical aggregate order          */
+  SPFAS_OP_PSIGMA = 2,   /* level l: P_sigma as dense [n_flux(l) x n_flux(l+1)], row-major, canonical      */
+  SPFAS_OP_MLOC = 3,     /* level l+1: static M^{l+1}_A blocks (k_A x k_A, row-major), canonical order     */
+  SPFAS_OP_DLOC = 4,     /* level l+1: D^{l+1}_A blocks (m_A x k_A, row-major), canonical order            */
+  SPFAS_OP_W = 5,        /* level l+1: projector weights w_A, concatenated, canonical order                */
+  SPFAS_OP_QSIGMA = 6    /* level l: Q_sigma as dense [n_flux(l+1) x n_flux(l)], row-major, canonical      */
+} spfas_level_op;
+
+/* Copies the operator `what` between `level` and level+1 into out[count]
+ * (count must equal the exact size, else ERR_INVALID reports the size
+ * needed).  Dense P_sigma / Q_sigma are meant for small test problems. */
+int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t what, double* out,
+                             size_t count);
+
+/* Releases every resource of the handle (NULL is allowed). */
+void spfas_destroy(spfas_hierarchy* h);
+
+/* Message of the last failed call on this thread; valid until the next
+ * call on this thread.  Never NULL. */
+const char* spfas_last_error(void);
+
+int spfas_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,115 @@
+"""ctypes binding of libspfas.so: the C structs of include/spfas.h and the
+entry points under the same names.  Argument marshalling only; every step
+of the method runs in the library."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libspfas.so")
+
+SPFAS_OK, SPFAS_NOT_CONVERGED = 0, 1
+SPFAS_ERR_INVALID, SPFAS_ERR_OOM, SPFAS_ERR_DEVICE, SPFAS_ERR_NUMERIC = -1, -2, -3, -4
+SPFAS_MEM_HOST, SPFAS_MEM_DEVICE = 0, 1
+SPFAS_NEWTON, SPFAS_PICARD = 0, 1
+SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SPFAS_OP_W, SPFAS_OP_QSIGMA = range(7)
+
+EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solve", "spfas_picard_solve",
+            "spfas_newton_solve", "spfas_eval_residual", "spfas_level_sizes", "spfas_get_aggregation",
+            "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
+            "spfas_version"]
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class spfas_mesh(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_cells", C.c_int64), ("n_faces", C.c_int64),
+                ("cell_volume", _dp), ("cell_centroid", _dp), ("cell_k0", _dp),
+                ("face_cells", _ip), ("face_area", _dp), ("face_normal", _dp),
+                ("face_point", _dp), ("face_kind", C.POINTER(C.c_int8))]
+
+
+class spfas_coarsen_opts(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("box", C.c_int32 * 3), ("m", C.c_int32), ("host_only", C.c_int32)]
+
+
+class spfas_problem(C.Structure):
+    _fields_ = [("alpha", C.c_double), ("source", C.c_void_p), ("g_dirichlet", C.c_void_p),
+                ("g_neumann", C.c_void_p), ("mem", C.c_int32)]
+
+
+class spfas_solve_opts(C.Structure):
+    _fields_ = [("smoother", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double), ("max_it", C.c_int32),
+                ("bt_nmax", C.c_int32), ("bt_theta", C.c_double), ("dp_cap", C.c_double),
+                ("coarsest_max_steps", C.c_int32), ("lin_rtol", C.c_double), ("lin_max_it", C.c_int32),
+                ("x0_given", C.c_int32)]
+
+
+class spfas_stats(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("lin_iters", C.c_int32), ("bt_halvings", C.c_int32),
+                ("smoothing_steps", C.c_int32), ("stopped_after_presmooth", C.c_int32),
+                ("r0", C.c_double), ("r_final", C.c_double), ("solve_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads the in-tree library; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # PyTorch ships its own HIP runtime under the same soname
+    # (libamdhip64.so.7); loading torch first makes this library bind to
+    # that one runtime instead of bringing a second copy into the process.
+    try:
+        import torch  # noqa: F401
+    except Exception:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(paper_2005_01275_amd/build.py); there is no fallback path")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.spfas_default_solve_opts.argtypes = [C.POINTER(spfas_solve_opts)]
+    L.spfas_default_solve_opts.restype = None
+    L.spfas_setup_hierarchy.argtypes = [C.POINTER(spfas_mesh), C.POINTER(spfas_coarsen_opts), vp, C.POINTER(vp)]
+    L.spfas_setup_hierarchy.restype = C.c_int
+    for nm in ("spfas_fas_solve", "spfas_picard_solve", "spfas_newton_solve"):
+        f = getattr(L, nm)
+        f.argtypes = [vp, C.POINTER(spfas_problem), C.POINTER(spfas_solve_opts), vp, vp, C.c_int32,
+                      C.POINTER(spfas_stats), vp]
+        f.restype = C.c_int
+    L.spfas_eval_residual.argtypes = [vp, C.POINTER(spfas_problem), vp, vp, vp, vp, C.c_int32, vp]
+    L.spfas_eval_residual.restype = C.c_int
+    L.spfas_level_sizes.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int64)]
+    L.spfas_level_sizes.restype = C.c_int
+    L.spfas_get_aggregation.argtypes = [vp, C.c_int32, _ip]
+    L.spfas_get_aggregation.restype = C.c_int
+    L.spfas_get_permutation.argtypes = [vp, C.c_int32, _ip, _ip]
+    L.spfas_get_permutation.restype = C.c_int
+    L.spfas_get_level_operator.argtypes = [vp, C.c_int32, C.c_int32, _dp, C.c_size_t]
+    L.spfas_get_level_operator.restype = C.c_int
+    L.spfas_destroy.argtypes = [vp]
+    L.spfas_destroy.restype = None
+    L.spfas_last_error.argtypes = []
+    L.spfas_last_error.restype = C.c_char_p
+    L.spfas_version.argtypes = []
+    L.spfas_version.restype = C.c_int
+    _lib = L
+    return L
+
+
+class SpfasError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"spfas error {code}: {msg}")
+        self.code = code
+
+
+def check(rc):
+    if rc < 0:
+        raise SpfasError(rc, lib().spfas_last_error().decode())
+    return rc

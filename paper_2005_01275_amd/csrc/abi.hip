@@ -1,0 +1,179 @@
+// C ABI of the library (include/spfas.h).  Every entry point catches the
+// library's exceptions and turns them into status codes plus a
+// thread-local message.
+#include <chrono>
+#include <cstring>
+#include <string>
+
+#include "hier.hpp"
+#include "solve.hpp"
+
+using namespace spfas;
+
+struct spfas_hierarchy {
+  Hierarchy h;
+};
+
+static thread_local std::string g_last_error = "";
+
+static int set_error(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+static int guarded(F&& fn) {
+  try {
+    g_last_error.clear();
+    return fn();
+  } catch (const Error& e) {
+    return set_error(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_error(SPFAS_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(SPFAS_ERR_INVALID, e.what());
+  }
+}
+
+extern "C" {
+
+int spfas_version(void) { return SPFAS_API_VERSION; }
+
+const char* spfas_last_error(void) { return g_last_error.c_str(); }
+
+void spfas_default_solve_opts(spfas_solve_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->smoother = SPFAS_NEWTON;
+  o->rtol = 1e-8;
+  o->atol = 1e-10;
+  o->max_it = 50;
+  o->bt_nmax = 4;
+  o->bt_theta = 0.9;
+  o->dp_cap = 0.0;
+  o->coarsest_max_steps = 10;
+  o->lin_rtol = 1e-8;
+  o->lin_max_it = 500;
+  o->x0_given = 0;
+}
+
+int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts, void* stream,
+                          spfas_hierarchy** out) {
+  return guarded([&] {
+    require(mesh && opts && out, "NULL argument");
+    auto* H = new spfas_hierarchy();
+    try {
+      H->h.stream = (hipStream_t)stream;
+      H->h.setup(*mesh, *opts);
+    } catch (...) {
+      delete H;
+      throw;
+    }
+    *out = H;
+    return SPFAS_OK;
+  });
+}
+
+void spfas_destroy(spfas_hierarchy* h) {
+  if (!h) return;
+  try {
+    if (!h->h.host_only) (void)hipStreamSynchronize(h->h.stream);
+    delete h;
+  } catch (...) {
+  }
+}
+
+static void need_device(const spfas_hierarchy* h) {
+  require(h != nullptr, "NULL hierarchy");
+  require(!h->h.host_only, "this handle was built with host_only and has no device data");
+}
+
+int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const double* p, const double* sigma,
+                        double* r_p, double* r_sigma, int32_t mem, void* stream) {
+  return guarded([&] {
+    need_device(h);
+    require(prob && p && sigma && r_p && r_sigma, "NULL argument");
+    h->h.stream = (hipStream_t)stream;
+    h->h.set_problem(*prob);
+    h->h.eval_residual(p, sigma, r_p, r_sigma, mem == SPFAS_MEM_DEVICE);
+    return SPFAS_OK;
+  });
+}
+
+static int solve_common(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
+                        double* sigma, int32_t state_mem, spfas_stats* stats, void* stream, SolveKind kind) {
+  return guarded([&] {
+    need_device(h);
+    require(prob && opts && p && sigma, "NULL argument");
+    h->h.stream = (hipStream_t)stream;
+    auto t0 = std::chrono::steady_clock::now();
+    spfas_stats st;
+    std::memset(&st, 0, sizeof st);
+    int rc = run_solve(h->h, *prob, *opts, p, sigma, state_mem == SPFAS_MEM_DEVICE, kind, st);
+    auto t1 = std::chrono::steady_clock::now();
+    st.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (stats) *stats = st;
+    if (rc == SPFAS_NOT_CONVERGED) g_last_error = "maximum number of iterations reached";
+    return rc;
+  });
+}
+
+int spfas_fas_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
+                    double* sigma, int32_t state_mem, spfas_stats* stats, void* stream) {
+  return solve_common(h, prob, opts, p, sigma, state_mem, stats, stream, SolveKind::FAS);
+}
+
+int spfas_picard_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
+                       double* sigma, int32_t state_mem, spfas_stats* stats, void* stream) {
+  return solve_common(h, prob, opts, p, sigma, state_mem, stats, stream, SolveKind::PICARD);
+}
+
+int spfas_newton_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
+                       double* sigma, int32_t state_mem, spfas_stats* stats, void* stream) {
+  return solve_common(h, prob, opts, p, sigma, state_mem, stats, stream, SolveKind::NEWTON);
+}
+
+int spfas_level_sizes(const spfas_hierarchy* h, int32_t level, int64_t* n_cells, int64_t* n_p, int64_t* n_flux) {
+  return guarded([&] {
+    require(h != nullptr, "NULL hierarchy");
+    require(level >= 0 && level < (int)h->h.topo.size(), "level out of range");
+    const Topo& t = h->h.topo[level];
+    if (n_cells) *n_cells = t.n_cells;
+    if (n_p) *n_p = t.n_p();
+    if (n_flux) *n_flux = t.n_flux;
+    return SPFAS_OK;
+  });
+}
+
+int spfas_get_aggregation(const spfas_hierarchy* h, int32_t level, int32_t* agg) {
+  return guarded([&] {
+    require(h != nullptr && agg != nullptr, "NULL argument");
+    require(level >= 0 && level + 1 < (int)h->h.topo.size(), "level must be below the coarsest level");
+    const Topo& t = h->h.topo[level];
+    for (int64_t i = 0; i < t.n_cells; ++i) agg[i] = (int32_t)t.agg[i];
+    return SPFAS_OK;
+  });
+}
+
+int spfas_get_permutation(const spfas_hierarchy* h, int32_t level, int32_t* cell_order, int32_t* flux_order) {
+  return guarded([&] {
+    require(h != nullptr && cell_order != nullptr && flux_order != nullptr, "NULL argument");
+    require(level >= 0 && level + 1 < (int)h->h.topo.size(), "level must be below the coarsest level");
+    const Topo& t = h->h.topo[level];
+    for (int64_t i = 0; i < t.n_cells; ++i) cell_order[i] = (int32_t)t.cell_order[i];
+    for (int64_t i = 0; i < t.n_flux; ++i) flux_order[i] = (int32_t)t.flux_order[i];
+    return SPFAS_OK;
+  });
+}
+
+int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t what, double* out, size_t count) {
+  return guarded([&] {
+    need_device(h);
+    require(out != nullptr, "NULL output");
+    require(level >= 0 && level + 1 < h->h.n_levels, "level must be below the coarsest level");
+    export_level_operator(h->h, level, what, out, count);
+    return SPFAS_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Shared infrastructure of the spfas library: error propagation, device
+// buffers, launch helpers.  Every HIP call is checked; failures become
+// spfas::Error exceptions that the C ABI layer turns into status codes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/spfas.h"
+
+namespace spfas {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+[[noreturn]] inline void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+inline void hip_check(hipError_t e, const char* what, const char* file, int line) {
+  if (e != hipSuccess) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf, "%s failed at %s:%d: %s", what, file, line, hipGetErrorString(e));
+    fail(e == hipErrorOutOfMemory ? SPFAS_ERR_OOM : SPFAS_ERR_DEVICE, buf);
+  }
+}
+#define HIPCHECK(x) ::spfas::hip_check((x), #x, __FILE__, __LINE__)
+#define LAUNCHCHECK() ::spfas::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
+
+// Typed device buffer; freed with the owning object.
+template <class T>
+struct DVec {
+  T* p = nullptr;
+  size_t n = 0;
+  DVec() = default;
+  DVec(const DVec&) = delete;
+  DVec& operator=(const DVec&) = delete;
+  DVec(DVec&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DVec& operator=(DVec&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DVec() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  void alloc(size_t count) {
+    release();
+    n = count;
+    if (count) HIPCHECK(hipMalloc((void**)&p, count * sizeof(T)));
+  }
+  void zero(hipStream_t s) {
+    if (n) HIPCHECK(hipMemsetAsync(p, 0, n * sizeof(T), s));
+  }
+  void upload(const std::vector<T>& v, hipStream_t s) {
+    alloc(v.size());
+    if (n) HIPCHECK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  void upload(const T* src, size_t count, hipStream_t s) {
+    alloc(count);
+    if (n) HIPCHECK(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+  }
+  std::vector<T> download(hipStream_t s) const {
+    std::vector<T> v(n);
+    if (n) {
+      HIPCHECK(hipMemcpyAsync(v.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    return v;
+  }
+};
+
+inline unsigned grid_for(size_t n, unsigned block) {
+  size_t g = (n + block - 1) / block;
+  if (g == 0) g = 1;
+  return (unsigned)g;
+}
+
+// Host-side bounds assertions used before launches.
+inline void require(bool ok, const char* msg) {
+  if (!ok) fail(SPFAS_ERR_INVALID, msg);
+}
+
+}  // namespace spfas

@@ -1,0 +1,324 @@
+// Fine-level (level 0) kernels: half-transmissibilities, the mixed TPFA
+// residual, the Picard/Newton linearisation with exact elimination of the
+// (diagonal) flux block, and the flux back-substitution.
+//
+// Layout (renumbered order: cells contiguous per aggregate, faces grouped
+// inside-aggregate / per interface / Dirichlet):
+//   state x = [sigma (nf) | p (n)], contiguous FP64
+//   faces:  K[j], L[j] (L = -1 on a Dirichlet face), TKi[j] = 1/Tb_K,
+//           TLi[j] = 1/Tb_L (0 on Dirichlet faces), g[j] (g_D or 0)
+//   cells:  f[c] (|tau| f + Neumann inflow), cell->face list cfptr/cfcode
+//           with code = (face << 1) | side, side 0: cell is K (D = -1),
+//           side 1: cell is L (D = +1); nb[k] = cell across that face
+//           (the cell itself on a Dirichlet face).
+#include "fine.hpp"
+
+#include "kern.hpp"
+
+namespace spfas {
+
+// ------------------------------------------------------------------ setup
+
+// Tb_{i,eps} = |eps| n_i . K0_i . (x_eps - x_i) / ||x_eps - x_i||^2 with
+// n_K = n_eps, n_L = -n_eps (eq. half-transmissibility).  Input order.
+__global__ void k_halftrans(int64_t nf, int dim, const int* __restrict__ fc, const double* __restrict__ area,
+                            const double* __restrict__ nrm, const double* __restrict__ pt,
+                            const double* __restrict__ cen, const double* __restrict__ k0,
+                            double* __restrict__ TK, double* __restrict__ TL, int* __restrict__ bad) {
+  int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int nbad = 0;
+  for (int side = 0; side < 2; ++side) {
+    const int c = fc[2 * f + side];
+    if (c < 0) {
+      if (side == 1) TL[f] = 0.0;
+      continue;
+    }
+    const double sg = side == 0 ? 1.0 : -1.0;
+    double d[3], kd[3];
+    double dd = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      d[a] = pt[f * dim + a] - cen[(int64_t)c * dim + a];
+      dd += d[a] * d[a];
+    }
+    double num = 0.0;
+    for (int a = 0; a < dim; ++a) {
+      kd[a] = 0.0;
+      for (int b = 0; b < dim; ++b) kd[a] += k0[((int64_t)c * dim + a) * dim + b] * d[b];
+      num += sg * nrm[f * dim + a] * kd[a];
+    }
+    const double t = area[f] * num / dd;
+    if (!(t > 0.0) || !(dd > 0.0)) nbad++;
+    if (side == 0) TK[f] = t; else TL[f] = t;
+  }
+  if (nbad) atomicAdd(bad, nbad);
+}
+
+void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, const double* nrm,
+                      const double* pt, const double* cen, const double* k0, double* TK, double* TL,
+                      int* bad, hipStream_t s) {
+  if (nf == 0) return;
+  hipLaunchKernelGGL(k_halftrans, dim3(grid_for(nf, kBlock)), dim3(kBlock), 0, s, nf, dim, fc, area, nrm, pt,
+                     cen, k0, TK, TL, bad);
+  LAUNCHCHECK();
+}
+
+// ------------------------------------------------------------------ residual
+
+// r(x + s dx) = A(x + s dx) - b with b = -[g; f] (eqs. fine_level_residual,
+// FV_matrix); items [0, nf) are faces (flux rows), [nf, nf+n) cells
+// (mass-balance rows).  Writes r if `r` is non-null and the per-block sum of
+// squares to parts[blockIdx.x].
+template <bool STEP>
+__global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double* __restrict__ x,
+                                                       const double* __restrict__ dx, double s,
+                                                       double* __restrict__ r, double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t nf = v.nf, ntot = v.nf + v.n;
+  const double* sig = x;
+  const double* p = x + nf;
+  const double* dsig = dx;
+  const double* dp = dx + nf;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+    double ri;
+    if (i < nf) {
+      const int K = v.K[i], L = v.L[i];
+      double pK = p[K], sj = sig[i];
+      if (STEP) { pK += s * dp[K]; sj += s * dsig[i]; }
+      double m = exp(-v.alpha * pK) * v.TKi[i];
+      double dtp = -pK;
+      if (L >= 0) {
+        double pL = p[L];
+        if (STEP) pL += s * dp[L];
+        m += exp(-v.alpha * pL) * v.TLi[i];
+        dtp += pL;
+      }
+      ri = m * sj + dtp + v.g[i];
+    } else {
+      const int64_t c = i - nf;
+      double div = 0.0;
+      for (int k = v.cfptr[c]; k < v.cfptr[c + 1]; ++k) {
+        const int code = v.cfcode[k];
+        const int j = code >> 1;
+        double sj = sig[j];
+        if (STEP) sj += s * dsig[j];
+        div += (code & 1) ? sj : -sj;
+      }
+      ri = div + v.f[c];
+    }
+    if (r) r[i] = ri;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+int launch_fine_resid(const FineView& v, const double* x, const double* dx, double s, double* r, double* parts,
+                      hipStream_t st) {
+  const int G = reduce_grid(v.nf + v.n);
+  if (dx)
+    hipLaunchKernelGGL(k_fine_resid<true>, dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
+  else
+    hipLaunchKernelGGL(k_fine_resid<false>, dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
+  LAUNCHCHECK();
+  return G;
+}
+
+// ------------------------------------------------------------------ linearisation
+
+// Per cell c: the row of S = D M^{-1} E (Picard: E = D^T; Newton:
+// E = N(sigma) kinv'(p) + D^T, Prop. 3 on level 0) and the right-hand side
+// rhs = r_p - D M^{-1} r_sigma of the eliminated system S dp = rhs.
+template <bool NEWTON>
+__global__ void __launch_bounds__(kBlock) k_fine_linearize(FineView v, const double* __restrict__ x,
+                                                           double* __restrict__ diag, double* __restrict__ off,
+                                                           double* __restrict__ rhs) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= v.n) return;
+  const int64_t nf = v.nf;
+  const double* sig = x;
+  const double* p = x + nf;
+  const double a_ = v.alpha;
+  double dg = 0.0, rh = v.f[c];
+  for (int k = v.cfptr[c]; k < v.cfptr[c + 1]; ++k) {
+    const int code = v.cfcode[k];
+    const int j = code >> 1;
+    const bool isL = code & 1;
+    const int K = v.K[j], L = v.L[j];
+    const double pK = p[K];
+    const double eK = exp(-a_ * pK) * v.TKi[j];
+    double eL = 0.0, pL = 0.0;
+    if (L >= 0) {
+      pL = p[L];
+      eL = exp(-a_ * pL) * v.TLi[j];
+    }
+    const double m = eK + eL;
+    const double sj = sig[j];
+    const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
+    double EK = -1.0, EL = 1.0;
+    if (NEWTON) {
+      EK -= a_ * eK * sj;
+      EL -= a_ * eL * sj;
+    }
+    const double ainv = 1.0 / m;
+    const double d = isL ? 1.0 : -1.0;
+    dg += d * ainv * (isL ? EL : EK);
+    off[k] = (L >= 0) ? d * ainv * (isL ? EK : EL) : 0.0;
+    rh += d * sj - d * ainv * rs;
+  }
+  diag[c] = dg;
+  rhs[c] = rh;
+}
+
+void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
+                           double* rhs, hipStream_t s) {
+  if (v.n == 0) return;
+  if (newton)
+    hipLaunchKernelGGL(k_fine_linearize<true>, dim3(grid_for(v.n, kBlock)), dim3(kBlock), 0, s, v, x, diag, off, rhs);
+  else
+    hipLaunchKernelGGL(k_fine_linearize<false>, dim3(grid_for(v.n, kBlock)), dim3(kBlock), 0, s, v, x, diag, off, rhs);
+  LAUNCHCHECK();
+}
+
+// dsigma = -M^{-1} (r_sigma + E dp) on faces; per-block max |dp| on cells.
+template <bool NEWTON>
+__global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const double* __restrict__ x,
+                                                         double* __restrict__ dx, double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t nf = v.nf, ntot = v.nf + v.n;
+  const double* sig = x;
+  const double* p = x + nf;
+  const double* dp = dx + nf;
+  const double a_ = v.alpha;
+  double mx = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nf) {
+      const int K = v.K[i], L = v.L[i];
+      const double pK = p[K];
+      const double eK = exp(-a_ * pK) * v.TKi[i];
+      double eL = 0.0, pL = 0.0, dpL = 0.0;
+      if (L >= 0) {
+        pL = p[L];
+        eL = exp(-a_ * pL) * v.TLi[i];
+        dpL = dp[L];
+      }
+      const double m = eK + eL;
+      const double sj = sig[i];
+      const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[i];
+      double EK = -1.0, EL = 1.0;
+      if (NEWTON) {
+        EK -= a_ * eK * sj;
+        EL -= a_ * eL * sj;
+      }
+      dx[i] = -(rs + EK * dp[K] + (L >= 0 ? EL * dpL : 0.0)) / m;
+    } else {
+      mx = fmax(mx, fabs(dp[i - nf]));
+    }
+  }
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = mx;
+}
+
+int launch_fine_backsub(const FineView& v, bool newton, const double* x, double* dx, double* parts,
+                        hipStream_t s) {
+  const int G = reduce_grid(v.nf + v.n);
+  if (newton)
+    hipLaunchKernelGGL(k_fine_backsub<true>, dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
+  else
+    hipLaunchKernelGGL(k_fine_backsub<false>, dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
+  LAUNCHCHECK();
+  return G;
+}
+
+// ------------------------------------------------------------------ problem data
+
+// f_K = |tau_K| f_K (input order source -> internal order), then the
+// Neumann inflow |eps| g_N is added by k_neumann_fold.
+__global__ void k_fine_rhs(int64_t n, const int* __restrict__ cell_in, const double* __restrict__ vol,
+                           const double* __restrict__ src, double* __restrict__ f) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) f[c] = vol[c] * src[cell_in[c]];
+}
+
+// Neumann faces of each internal cell as a CSR list (deterministic order).
+__global__ void k_neumann_fold(int64_t n, const int* __restrict__ nptr, const int* __restrict__ nface,
+                               const double* __restrict__ narea, const double* __restrict__ gN,
+                               double* __restrict__ f) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double acc = 0.0;
+  for (int k = nptr[c]; k < nptr[c + 1]; ++k) acc += narea[k] * gN[nface[k]];
+  f[c] += acc;
+}
+
+__global__ void k_fine_g(int64_t nf, const int* __restrict__ flux_in, const int* __restrict__ L,
+                         const double* __restrict__ gD, double* __restrict__ g) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nf) g[j] = (L[j] < 0 && gD) ? gD[flux_in[j]] : 0.0;
+}
+
+void launch_fine_problem(const FineView& v, const int* cell_in, const int* flux_in, const double* vol,
+                         const int* nptr, const int* nface, const double* narea, const double* src,
+                         const double* gD, const double* gN, double* f, double* g, hipStream_t s) {
+  if (v.n) {
+    hipLaunchKernelGGL(k_fine_rhs, dim3(grid_for(v.n, kBlock)), dim3(kBlock), 0, s, v.n, cell_in, vol, src, f);
+    LAUNCHCHECK();
+    if (gN) {
+      hipLaunchKernelGGL(k_neumann_fold, dim3(grid_for(v.n, kBlock)), dim3(kBlock), 0, s, v.n, nptr, nface, narea,
+                         gN, f);
+      LAUNCHCHECK();
+    }
+  }
+  if (v.nf) {
+    hipLaunchKernelGGL(k_fine_g, dim3(grid_for(v.nf, kBlock)), dim3(kBlock), 0, s, v.nf, flux_in, v.L, gD, g);
+    LAUNCHCHECK();
+  }
+}
+
+// ------------------------------------------------------------------ layout maps
+
+__global__ void k_gather(int64_t n, const int* __restrict__ map, const double* __restrict__ in,
+                         double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[map[i]];
+}
+__global__ void k_scatter(int64_t n, const int* __restrict__ map, const double* __restrict__ in,
+                          double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[map[i]] = in[i];
+}
+__global__ void k_fill(int64_t n, double v, double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = v;
+}
+// sigma = -|eps| g_N on Neumann faces (input order)
+__global__ void k_neumann_flux(int64_t nn, const int* __restrict__ nface_in, const double* __restrict__ narea_in,
+                               const double* __restrict__ gN, double* __restrict__ sig_out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) sig_out[nface_in[i]] = gN ? -narea_in[i] * gN[nface_in[i]] : 0.0;
+}
+
+void launch_gather(int64_t n, const int* map, const double* in, double* out, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_gather, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, map, in, out);
+  LAUNCHCHECK();
+}
+void launch_scatter(int64_t n, const int* map, const double* in, double* out, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_scatter, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, map, in, out);
+  LAUNCHCHECK();
+}
+void launch_fill(int64_t n, double v, double* out, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, v, out);
+  LAUNCHCHECK();
+}
+void launch_neumann_flux(int64_t nn, const int* nface_in, const double* narea_in, const double* gN, double* sig,
+                         hipStream_t s) {
+  if (!nn) return;
+  hipLaunchKernelGGL(k_neumann_flux, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, nn, nface_in, narea_in, gN, sig);
+  LAUNCHCHECK();
+}
+
+}  // namespace spfas

@@ -1,0 +1,40 @@
+// Fine-level (level 0) kernels; see fine.hip for the data layout.
+#pragma once
+
+#include "common.hpp"
+
+namespace spfas {
+
+struct FineView {
+  int64_t n = 0, nf = 0;
+  double alpha = 0.0;
+  const int* K = nullptr;
+  const int* L = nullptr;
+  const double* TKi = nullptr;
+  const double* TLi = nullptr;
+  const double* g = nullptr;
+  const double* f = nullptr;
+  const int* cfptr = nullptr;
+  const int* cfcode = nullptr;
+};
+
+void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, const double* nrm,
+                      const double* pt, const double* cen, const double* k0, double* TK, double* TL,
+                      int* bad, hipStream_t s);
+// returns the number of partial sums written
+int launch_fine_resid(const FineView& v, const double* x, const double* dx, double s, double* r,
+                      double* parts, hipStream_t st);
+void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
+                           double* rhs, hipStream_t s);
+int launch_fine_backsub(const FineView& v, bool newton, const double* x, double* dx, double* parts,
+                        hipStream_t s);
+void launch_fine_problem(const FineView& v, const int* cell_in, const int* flux_in, const double* vol,
+                         const int* nptr, const int* nface, const double* narea, const double* src,
+                         const double* gD, const double* gN, double* f, double* g, hipStream_t s);
+void launch_gather(int64_t n, const int* map, const double* in, double* out, hipStream_t s);
+void launch_scatter(int64_t n, const int* map, const double* in, double* out, hipStream_t s);
+void launch_fill(int64_t n, double v, double* out, hipStream_t s);
+void launch_neumann_flux(int64_t nn, const int* nface_in, const double* narea_in, const double* gN,
+                         double* sig, hipStream_t s);
+
+}  // namespace spfas

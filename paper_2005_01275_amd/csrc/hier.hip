@@ -1,0 +1,289 @@
+// Hierarchy setup (host orchestration) and fine-level entry points.
+#include "hier.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "coarse.hpp"
+#include "kern.hpp"
+#include "sparse.hpp"
+
+namespace spfas {
+
+__global__ void k_invgather(int64_t n, const int* __restrict__ map, const double* __restrict__ T,
+                            const int* __restrict__ L, int use_L, double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (use_L && L[i] < 0) { out[i] = 0.0; return; }
+  out[i] = 1.0 / T[map[i]];
+}
+
+Hierarchy::~Hierarchy() {
+  coarse.clear();
+  trans.clear();
+  if (hpin) (void)hipHostFree(hpin);
+}
+
+double Hierarchy::host_sum(const double* dparts, int n) {
+  HIPCHECK(hipMemcpyAsync(hpin, dparts, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += hpin[i];
+  return s;
+}
+
+double Hierarchy::host_max(const double* dparts, int n) {
+  HIPCHECK(hipMemcpyAsync(hpin, dparts, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s = std::max(s, hpin[i]);
+  return s;
+}
+
+static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
+  require(M.dim == 2 || M.dim == 3, "mesh.dim must be 2 or 3");
+  require(M.n_cells > 0, "mesh.n_cells must be positive");
+  require(M.n_faces >= 0, "mesh.n_faces must be non-negative");
+  require(M.n_cells < (int64_t)1 << 30 && M.n_faces < (int64_t)1 << 30, "mesh too large for 32-bit indices");
+  require(M.cell_volume && M.cell_centroid && M.cell_k0 && M.face_cells && M.face_area && M.face_normal &&
+              M.face_point && M.face_kind,
+          "mesh arrays must not be NULL");
+  require(o.n_levels >= 1 && o.n_levels <= 16, "n_levels must be in [1, 16]");
+  require(o.m >= 1 && o.m <= 64, "m must be in [1, 64]");
+  for (int a = 0; a < M.dim; ++a) require(o.box[a] >= 1, "box edges must be >= 1");
+  int64_t ndir = 0;
+  for (int64_t c = 0; c < M.n_cells; ++c)
+    require(M.cell_volume[c] > 0.0 && std::isfinite(M.cell_volume[c]), "cell volumes must be positive");
+  for (int64_t f = 0; f < M.n_faces; ++f) {
+    const int K = M.face_cells[2 * f], L = M.face_cells[2 * f + 1];
+    const int k = M.face_kind[f];
+    require(K >= 0 && K < M.n_cells, "face_cells: K out of range");
+    require(L >= -1 && L < M.n_cells, "face_cells: L out of range");
+    require(k >= 0 && k <= 2, "face_kind must be 0, 1 or 2");
+    require((k == SPFAS_FACE_INTERIOR) == (L >= 0), "interior faces need L >= 0, boundary faces L = -1");
+    require(L != K, "a face must join two different cells");
+    require(M.face_area[f] > 0.0, "face areas must be positive");
+    ndir += (k == SPFAS_FACE_DIRICHLET);
+  }
+  require(ndir > 0, "at least one Dirichlet face is required");
+}
+
+void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
+  validate_mesh(M, o);
+  dim = M.dim;
+  n_cells_in = M.n_cells;
+  n_faces_in = M.n_faces;
+  n_levels = o.n_levels;
+  m = o.m;
+  host_only = o.host_only != 0;
+  // ---------------- level-0 canonical topology
+  topo.clear();
+  topo.reserve(n_levels);   // references into topo stay valid below
+  topo.emplace_back();
+  Topo& t0 = topo[0];
+  t0.n_cells = M.n_cells;
+  t0.pptr.resize(M.n_cells + 1);
+  std::iota(t0.pptr.begin(), t0.pptr.end(), 0);
+  std::vector<int64_t> flux_face;
+  for (int64_t f = 0; f < M.n_faces; ++f) {
+    if (M.face_kind[f] == SPFAS_FACE_NEUMANN) continue;
+    flux_face.push_back(f);
+    t0.kind.push_back(M.face_kind[f] == SPFAS_FACE_DIRICHLET ? FK_DIRICHLET : FK_INTERIOR);
+    t0.c1.push_back(M.face_cells[2 * f]);
+    t0.c2.push_back(M.face_cells[2 * f + 1]);
+  }
+  t0.n_flux = (int64_t)flux_face.size();
+  build_cell_lists(t0);
+  if (n_levels > 1) {
+    bool ok = lattice_from_centroids(M.dim, M.n_cells, M.cell_centroid, t0.lat_shape, t0.lat_index);
+    require(ok, "box aggregation needs a Cartesian lattice of cell centroids");
+  }
+  // ---------------- coarse topologies, aggregation, renumbering
+  for (int l = 0; l + 1 < n_levels; ++l) {
+    box_aggregate(topo[l], o.box);
+    renumber(topo[l]);
+    Topo c = coarse_topology(topo[l], m);
+    topo.push_back(std::move(c));
+  }
+  if (host_only) return;
+  HIPCHECK(hipHostMalloc((void**)&hpin, kMaxParts * sizeof(double) * 4, hipHostMallocDefault));
+  parts.alloc(kMaxParts * 4);
+  // ---------------- level-0 device order
+  const int64_t n = M.n_cells, nf = t0.n_flux;
+  std::vector<int64_t> corder(n), forder(nf);
+  if (n_levels > 1) {
+    corder = t0.cell_order;
+    forder = t0.flux_order;
+  } else {
+    std::iota(corder.begin(), corder.end(), 0);
+    std::iota(forder.begin(), forder.end(), 0);
+  }
+  std::vector<int64_t> cpos(n), fpos(nf);
+  for (int64_t i = 0; i < n; ++i) cpos[corder[i]] = i;
+  for (int64_t i = 0; i < nf; ++i) fpos[forder[i]] = i;
+  fine.n = n;
+  fine.nf = nf;
+  hipStream_t s = stream;
+  {
+    std::vector<int> cell_in(n), flux_in(nf), K(nf), L(nf);
+    std::vector<double> vol(n);
+    for (int64_t i = 0; i < n; ++i) { cell_in[i] = (int)corder[i]; vol[i] = M.cell_volume[corder[i]]; }
+    for (int64_t i = 0; i < nf; ++i) {
+      const int64_t j = forder[i];
+      flux_in[i] = (int)flux_face[j];
+      K[i] = (int)cpos[t0.c1[j]];
+      L[i] = t0.c2[j] >= 0 ? (int)cpos[t0.c2[j]] : -1;
+    }
+    // cell -> face lists in internal order
+    std::vector<int> cfptr(n + 1, 0);
+    for (int64_t i = 0; i < nf; ++i) {
+      cfptr[K[i] + 1]++;
+      if (L[i] >= 0) cfptr[L[i] + 1]++;
+    }
+    for (int64_t c = 0; c < n; ++c) cfptr[c + 1] += cfptr[c];
+    std::vector<int> cfcode(cfptr[n]), nb(cfptr[n]);
+    std::vector<int> fill(cfptr.begin(), cfptr.end() - 1);
+    for (int64_t i = 0; i < nf; ++i) {
+      cfcode[fill[K[i]]] = (int)(i << 1);
+      nb[fill[K[i]]++] = L[i] >= 0 ? L[i] : K[i];
+      if (L[i] >= 0) {
+        cfcode[fill[L[i]]] = (int)((i << 1) | 1);
+        nb[fill[L[i]]++] = K[i];
+      }
+    }
+    // Neumann faces per internal cell
+    std::vector<int> nptr(n + 1, 0), nface, neu_in;
+    std::vector<double> narea, neu_area;
+    std::vector<std::vector<int>> per(n);
+    for (int64_t f = 0; f < M.n_faces; ++f)
+      if (M.face_kind[f] == SPFAS_FACE_NEUMANN) {
+        per[cpos[M.face_cells[2 * f]]].push_back((int)f);
+        neu_in.push_back((int)f);
+        neu_area.push_back(M.face_area[f]);
+      }
+    for (int64_t c = 0; c < n; ++c) {
+      for (int f : per[c]) { nface.push_back(f); narea.push_back(M.face_area[f]); }
+      nptr[c + 1] = (int)nface.size();
+    }
+    fine.cell_in.upload(cell_in, s);
+    fine.flux_in.upload(flux_in, s);
+    fine.K.upload(K, s);
+    fine.L.upload(L, s);
+    fine.cfptr.upload(cfptr, s);
+    fine.cfcode.upload(cfcode, s);
+    fine.nb.upload(nb, s);
+    fine.vol.upload(vol, s);
+    fine.nptr.upload(nptr, s);
+    fine.nface.upload(nface, s);
+    fine.narea.upload(narea, s);
+    fine.neu_in.upload(neu_in, s);
+    fine.neu_area.upload(neu_area, s);
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  // ---------------- half-transmissibilities (device, input order -> internal)
+  {
+    DVec<int> fc;
+    DVec<double> area, nrm, pt, cen, k0, TK, TL;
+    DVec<int> bad;
+    cen.upload(M.cell_centroid, M.n_cells * dim, s);
+    k0.upload(M.cell_k0, M.n_cells * dim * dim, s);
+    bad.alloc(1);
+    bad.zero(s);
+    // evaluate on the non-Neumann faces only (the ones that carry a flux)
+    std::vector<int> fcs(2 * nf);
+    std::vector<double> ar(nf), nr(nf * dim), pp(nf * dim);
+    for (int64_t j = 0; j < nf; ++j) {
+      const int64_t f = flux_face[j];
+      fcs[2 * j] = M.face_cells[2 * f];
+      fcs[2 * j + 1] = M.face_cells[2 * f + 1];
+      ar[j] = M.face_area[f];
+      for (int a = 0; a < dim; ++a) { nr[j * dim + a] = M.face_normal[f * dim + a]; pp[j * dim + a] = M.face_point[f * dim + a]; }
+    }
+    fc.upload(fcs, s);
+    area.upload(ar, s);
+    nrm.upload(nr, s);
+    pt.upload(pp, s);
+    TK.alloc(nf);
+    TL.alloc(nf);
+    launch_halftrans(nf, dim, fc.p, area.p, nrm.p, pt.p, cen.p, k0.p, TK.p, TL.p, bad.p, s);
+    std::vector<int> hb = bad.download(s);
+    require(hb[0] == 0, "non-positive half-transmissibility (check normals, collocation points and K0)");
+    // canonical flux id order -> internal
+    std::vector<int> canon(nf);
+    for (int64_t i = 0; i < nf; ++i) canon[i] = (int)forder[i];
+    DVec<int> dcanon;
+    dcanon.upload(canon, s);
+    fine.TKi.alloc(nf);
+    fine.TLi.alloc(nf);
+    if (nf) {
+      hipLaunchKernelGGL(k_invgather, dim3(grid_for(nf, kBlock)), dim3(kBlock), 0, s, nf, dcanon.p, TK.p,
+                         fine.L.p, 0, fine.TKi.p);
+      LAUNCHCHECK();
+      hipLaunchKernelGGL(k_invgather, dim3(grid_for(nf, kBlock)), dim3(kBlock), 0, s, nf, dcanon.p, TL.p,
+                         fine.L.p, 1, fine.TLi.p);
+      LAUNCHCHECK();
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  fine.f.alloc(n);
+  fine.g.alloc(nf);
+  fine.f.zero(s);
+  fine.g.zero(s);
+  // ---------------- coarse levels
+  setup_coarse_levels(*this);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+void Hierarchy::set_problem(const spfas_problem& P) {
+  require(P.source != nullptr, "problem.source must not be NULL");
+  require(std::isfinite(P.alpha), "problem.alpha must be finite");
+  fine.alpha = P.alpha;
+  hipStream_t s = stream;
+  const double *src = P.source, *gD = P.g_dirichlet, *gN = P.g_neumann;
+  DVec<double> hs, hd, hn;
+  if (P.mem == SPFAS_MEM_HOST) {
+    hs.upload(P.source, n_cells_in, s);
+    src = hs.p;
+    if (gD) { hd.upload(P.g_dirichlet, n_faces_in, s); gD = hd.p; }
+    if (gN) { hn.upload(P.g_neumann, n_faces_in, s); gN = hn.p; }
+  }
+  launch_fine_problem(fine.view(), fine.cell_in.p, fine.flux_in.p, fine.vol.p, fine.nptr.p, fine.nface.p,
+                      fine.narea.p, src, gD, gN, fine.f.p, fine.g.p, s);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+void Hierarchy::eval_residual(const double* p, const double* sig, double* rp, double* rs, bool dev) {
+  hipStream_t s = stream;
+  const int64_t n = fine.n, nf = fine.nf;
+  DVec<double> x, r, pin, sin, rpo, rso;
+  x.alloc(nf + n);
+  r.alloc(nf + n);
+  const double *pd = p, *sd = sig;
+  if (!dev) {
+    pin.upload(p, n_cells_in, s);
+    sin.upload(sig, n_faces_in, s);
+    pd = pin.p;
+    sd = sin.p;
+  }
+  launch_gather(nf, fine.flux_in.p, sd, x.p, s);
+  launch_gather(n, fine.cell_in.p, pd, x.p + nf, s);
+  launch_fine_resid(fine.view(), x.p, nullptr, 0.0, r.p, parts.p, s);
+  double *rpd = rp, *rsd = rs;
+  if (!dev) {
+    rpo.alloc(n_cells_in);
+    rso.alloc(n_faces_in);
+    rpd = rpo.p;
+    rsd = rso.p;
+  }
+  launch_fill(n_faces_in, 0.0, rsd, s);
+  launch_scatter(nf, fine.flux_in.p, r.p, rsd, s);
+  launch_scatter(n, fine.cell_in.p, r.p + nf, rpd, s);
+  if (!dev) {
+    HIPCHECK(hipMemcpyAsync(rp, rpd, n_cells_in * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(rs, rsd, n_faces_in * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+}  // namespace spfas

@@ -1,0 +1,68 @@
+// The hierarchy handle: host topology of every level, device data of the
+// fine level, the coarse levels and the transfers between them, and the
+// solver state.  Built by spfas_setup_hierarchy, used by the solve entry
+// points.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "coarse.hpp"
+#include "common.hpp"
+#include "fine.hpp"
+#include "sparse.hpp"
+#include "topo.hpp"
+
+namespace spfas {
+
+
+struct FineDev {
+  int64_t n = 0, nf = 0;
+  DVec<int> K, L, cfptr, cfcode, nb;
+  DVec<double> TKi, TLi, vol;
+  DVec<int> cell_in, flux_in;             // internal -> input ids
+  DVec<int> nptr, nface;                  // Neumann faces per internal cell (input face ids)
+  DVec<double> narea;
+  DVec<int> neu_in;                       // all Neumann faces (input ids)
+  DVec<double> neu_area;
+  DVec<double> f, g;                      // problem data of the current solve
+  double alpha = 0.0;
+  FineView view() const {
+    FineView v;
+    v.n = n; v.nf = nf; v.alpha = alpha;
+    v.K = K.p; v.L = L.p; v.TKi = TKi.p; v.TLi = TLi.p; v.g = g.p; v.f = f.p;
+    v.cfptr = cfptr.p; v.cfcode = cfcode.p;
+    return v;
+  }
+};
+
+struct Hierarchy {
+  hipStream_t stream = nullptr;
+  bool host_only = false;
+  int dim = 0;
+  int64_t n_cells_in = 0, n_faces_in = 0;
+  int n_levels = 1;
+  int m = 1;
+  std::vector<Topo> topo;                 // canonical topology per level
+  std::vector<TransferPlan> plans;        // host plans l -> l+1
+  FineDev fine;
+  std::vector<std::unique_ptr<CoarseLevel>> coarse;   // levels 1..L-1
+  std::vector<std::unique_ptr<TransferDev>> trans;    // transfers 0..L-2
+  // host copies of hierarchy numbers for the parity hooks
+  std::vector<std::vector<double>> eigvals;           // per transfer, concatenated
+  // reduction scratch
+  DVec<double> parts;
+  double* hpin = nullptr;                  // pinned host scalars
+  int launches = 0;
+
+  ~Hierarchy();
+  void setup(const spfas_mesh& mesh, const spfas_coarsen_opts& o);
+  void set_problem(const spfas_problem& prob);
+  // fine residual in input order
+  void eval_residual(const double* p, const double* sig, double* rp, double* rs, bool dev);
+  // sum of partials on the host (deterministic order)
+  double host_sum(const double* dparts, int n);
+  double host_max(const double* dparts, int n);
+};
+
+}  // namespace spfas

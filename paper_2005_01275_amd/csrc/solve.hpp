@@ -1,0 +1,16 @@
+// Nonlinear solvers: FAS V-cycle (Alg. 2), single-level Picard/Newton,
+// smoothing with the step cap and backtracking (Alg. 1).
+#pragma once
+
+#include "hier.hpp"
+
+namespace spfas {
+
+enum class SolveKind { FAS, PICARD, NEWTON };
+
+int run_solve(Hierarchy& h, const spfas_problem& prob, const spfas_solve_opts& o, double* p, double* sigma,
+              bool dev, SolveKind kind, spfas_stats& st);
+
+void export_level_operator(const Hierarchy& h, int level, int what, double* out, size_t count);
+
+}  // namespace spfas

@@ -1,0 +1,285 @@
+// Host-side integer structure of the hierarchy (see topo.hpp).
+#include "topo.hpp"
+
+#include <algorithm>
+#include <numeric>
+#include <tuple>
+
+#include "common.hpp"
+
+namespace spfas {
+
+bool lattice_from_centroids(int dim, int64_t n, const double* centroid, std::vector<int>& shape,
+                            std::vector<int64_t>& index) {
+  shape.assign(dim, 0);
+  index.assign(n, 0);
+  int64_t stride = 1;
+  std::vector<double> vals(n);
+  for (int a = 0; a < dim; ++a) {
+    for (int64_t i = 0; i < n; ++i) vals[i] = centroid[i * dim + a];
+    std::vector<double> u(vals);
+    std::sort(u.begin(), u.end());
+    u.erase(std::unique(u.begin(), u.end()), u.end());
+    shape[a] = (int)u.size();
+    for (int64_t i = 0; i < n; ++i) {
+      int64_t r = std::lower_bound(u.begin(), u.end(), vals[i]) - u.begin();
+      index[i] += r * stride;
+    }
+    stride *= (int64_t)u.size();
+  }
+  if (stride != n) return false;
+  std::vector<char> seen(n, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (seen[index[i]]) return false;
+    seen[index[i]] = 1;
+  }
+  return true;
+}
+
+int box_blocks(int n, int a) {
+  int nb = n / a, rem = n % a;
+  if (rem == 0) return std::max(nb, 1);
+  if (2 * rem < a) return std::max(nb, 1);
+  return nb + 1;
+}
+
+void box_aggregate(Topo& t, const int box[3]) {
+  const int dim = (int)t.lat_shape.size();
+  t.agg.assign(t.n_cells, 0);
+  t.agg_shape.assign(dim, 0);
+  std::vector<int> nb(dim);
+  for (int a = 0; a < dim; ++a) nb[a] = box_blocks(t.lat_shape[a], box[a]);
+  for (int64_t c = 0; c < t.n_cells; ++c) {
+    int64_t rem = t.lat_index[c], stride = 1, id = 0;
+    for (int a = 0; a < dim; ++a) {
+      int64_t coord = rem % t.lat_shape[a];
+      rem /= t.lat_shape[a];
+      int64_t blk = std::min<int64_t>(coord / box[a], nb[a] - 1);
+      id += blk * stride;
+      stride *= nb[a];
+    }
+    t.agg[c] = id;
+  }
+  t.agg_shape = nb;
+  int64_t na = 1;
+  for (int a = 0; a < dim; ++a) na *= nb[a];
+  t.n_agg = na;
+}
+
+void renumber(Topo& t) {
+  const int64_t n = t.n_cells;
+  t.cell_order.resize(n);
+  std::iota(t.cell_order.begin(), t.cell_order.end(), 0);
+  std::stable_sort(t.cell_order.begin(), t.cell_order.end(),
+                   [&](int64_t a, int64_t b) { return t.agg[a] < t.agg[b]; });
+  std::vector<int64_t> pos(n);
+  for (int64_t i = 0; i < n; ++i) pos[t.cell_order[i]] = i;
+  const int64_t nf = t.n_flux;
+  struct Key { int64_t g0, g1, g2, kr, lo, hi, id; };
+  std::vector<Key> keys(nf);
+  for (int64_t j = 0; j < nf; ++j) {
+    const int64_t a = t.c1[j], b = t.c2[j];
+    const int8_t k = t.kind[j];
+    const int64_t a1 = t.agg[a];
+    const int64_t a2 = b >= 0 ? t.agg[b] : -1;
+    const bool inside = (k == FK_BUBBLE) || (k == FK_INTERIOR && a1 == a2);
+    const bool cross = (k == FK_INTERIOR && a1 != a2);
+    Key key;
+    key.g0 = inside ? 0 : (cross ? 1 : 2);
+    key.g1 = cross ? std::min(a1, a2) : a1;
+    key.g2 = cross ? std::max(a1, a2) : 0;
+    key.kr = (k == FK_BUBBLE) ? 1 : 0;
+    const int64_t p1 = pos[a];
+    const int64_t p2 = b >= 0 ? pos[b] : p1;
+    key.lo = std::min(p1, p2);
+    key.hi = std::max(p1, p2);
+    key.id = j;
+    keys[j] = key;
+  }
+  std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
+    return std::tie(x.g0, x.g1, x.g2, x.kr, x.lo, x.hi, x.id) <
+           std::tie(y.g0, y.g1, y.g2, y.kr, y.lo, y.hi, y.id);
+  });
+  t.flux_order.resize(nf);
+  for (int64_t i = 0; i < nf; ++i) t.flux_order[i] = keys[i].id;
+}
+
+void build_cell_lists(Topo& t) {
+  std::vector<int64_t> cnt(t.n_cells + 1, 0);
+  for (int64_t j = 0; j < t.n_flux; ++j) {
+    cnt[t.c1[j] + 1]++;
+    if (t.c2[j] >= 0) cnt[t.c2[j] + 1]++;
+  }
+  for (int64_t c = 0; c < t.n_cells; ++c) cnt[c + 1] += cnt[c];
+  t.cfptr = cnt;
+  t.cfidx.assign(cnt.back(), 0);
+  std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+  for (int64_t j = 0; j < t.n_flux; ++j) {   // ascending j -> lists sorted
+    t.cfidx[fill[t.c1[j]]++] = j;
+    if (t.c2[j] >= 0) t.cfidx[fill[t.c2[j]]++] = j;
+  }
+}
+
+Topo coarse_topology(const Topo& f, int m) {
+  Topo c;
+  const int64_t na = f.n_agg;
+  c.n_cells = na;
+  std::vector<int64_t> npA(na, 0);
+  for (int64_t i = 0; i < f.n_cells; ++i) npA[f.agg[i]] += f.pptr[i + 1] - f.pptr[i];
+  c.pptr.assign(na + 1, 0);
+  std::vector<int64_t> mA(na);
+  for (int64_t A = 0; A < na; ++A) {
+    if (npA[A] == 0) fail(SPFAS_ERR_INVALID, "empty aggregate");
+    mA[A] = std::min<int64_t>(m, npA[A]);
+    c.pptr[A + 1] = c.pptr[A] + mA[A];
+  }
+  std::vector<std::pair<int64_t, int64_t>> pairs;
+  std::vector<char> hasdir(na, 0);
+  for (int64_t j = 0; j < f.n_flux; ++j) {
+    if (f.kind[j] == FK_INTERIOR) {
+      int64_t a = f.agg[f.c1[j]], b = f.agg[f.c2[j]];
+      if (a != b) pairs.emplace_back(std::min(a, b), std::max(a, b));
+    } else if (f.kind[j] == FK_DIRICHLET) {
+      hasdir[f.agg[f.c1[j]]] = 1;
+    }
+  }
+  std::sort(pairs.begin(), pairs.end());
+  pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+  int64_t nfc = 0;
+  for (auto& pr : pairs) {
+    c.kind.push_back(FK_INTERIOR);
+    c.c1.push_back(pr.first);
+    c.c2.push_back(pr.second);
+    ++nfc;
+  }
+  for (int64_t A = 0; A < na; ++A)
+    if (hasdir[A]) {
+      c.kind.push_back(FK_DIRICHLET);
+      c.c1.push_back(A);
+      c.c2.push_back(-1);
+      ++nfc;
+    }
+  for (int64_t A = 0; A < na; ++A)
+    for (int64_t j = 1; j < mA[A]; ++j) {
+      c.kind.push_back(FK_BUBBLE);
+      c.c1.push_back(A);
+      c.c2.push_back(-1);
+      ++nfc;
+    }
+  c.n_flux = nfc;
+  build_cell_lists(c);
+  c.lat_shape = f.agg_shape;
+  c.lat_index.resize(na);
+  std::iota(c.lat_index.begin(), c.lat_index.end(), 0);
+  return c;
+}
+
+TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>& dev_cell,
+                       const std::vector<int64_t>& dev_p, const std::vector<int64_t>& dev_flux,
+                       const std::vector<int64_t>& dev_cfptr,
+                       const std::vector<int64_t>& dev_cfidx) {
+  TransferPlan P;
+  const int64_t na = c.n_cells;
+  P.n_agg = na;
+  // cells of each aggregate, ascending canonical id
+  std::vector<std::vector<int64_t>> members(na);
+  for (int64_t i = 0; i < f.n_cells; ++i) members[f.agg[i]].push_back(i);
+  // coarse flux (canonical) -> level-l flux ids of its group
+  std::vector<std::vector<int64_t>> grp(c.n_flux);
+  {
+    // map (a,b) pair -> coarse face id; Dirichlet A -> coarse id
+    std::vector<int64_t> dir_id(na, -1);
+    for (int64_t J = 0; J < c.n_flux; ++J)
+      if (c.kind[J] == FK_DIRICHLET) dir_id[c.c1[J]] = J;
+    // interior pairs are sorted; binary search
+    int64_t n_pairs = 0;
+    while (n_pairs < c.n_flux && c.kind[n_pairs] == FK_INTERIOR) ++n_pairs;
+    for (int64_t j = 0; j < f.n_flux; ++j) {
+      if (f.kind[j] == FK_INTERIOR) {
+        int64_t a = f.agg[f.c1[j]], b = f.agg[f.c2[j]];
+        if (a == b) continue;
+        int64_t lo = std::min(a, b), hi = std::max(a, b);
+        int64_t L = 0, R = n_pairs;
+        while (L < R) {
+          int64_t mid = (L + R) / 2;
+          if (std::make_pair(c.c1[mid], c.c2[mid]) < std::make_pair(lo, hi)) L = mid + 1; else R = mid;
+        }
+        grp[L].push_back(j);
+      } else if (f.kind[j] == FK_DIRICHLET) {
+        grp[dir_id[f.agg[f.c1[j]]]].push_back(j);
+      }
+    }
+  }
+  // order inside a group: the renumbered order of level l
+  std::vector<int64_t> fpos(f.n_flux);
+  for (int64_t i = 0; i < f.n_flux; ++i) fpos[f.flux_order[i]] = i;
+  for (auto& g : grp) std::sort(g.begin(), g.end(), [&](int64_t a, int64_t b) { return fpos[a] < fpos[b]; });
+  // int(A) lists in renumbered order
+  std::vector<std::vector<int64_t>> ints(na);
+  for (int64_t i = 0; i < f.n_flux; ++i) {
+    int64_t j = f.flux_order[i];
+    int8_t k = f.kind[j];
+    int64_t a1 = f.agg[f.c1[j]];
+    if (k == FK_BUBBLE || (k == FK_INTERIOR && f.agg[f.c2[j]] == a1)) ints[a1].push_back(j);
+  }
+  P.cell_ptr.assign(na + 1, 0);
+  P.pd_ptr.assign(na + 1, 0);
+  P.dof_ptr.assign(na + 1, 0);
+  P.int_ptr.assign(na + 1, 0);
+  P.n_int.assign(na, 0);
+  P.mA.assign(na, 0);
+  P.fgrp_ptr.assign(c.n_flux + 1, 0);
+  P.grp_pos_A.assign(c.n_flux, -1);
+  P.grp_pos_B.assign(c.n_flux, -1);
+  for (int64_t J = 0; J < c.n_flux; ++J) P.fgrp_ptr[J + 1] = P.fgrp_ptr[J] + (int64_t)grp[J].size();
+  P.fgrp_list.resize(P.fgrp_ptr.back());
+  for (int64_t J = 0; J < c.n_flux; ++J)
+    for (size_t q = 0; q < grp[J].size(); ++q) P.fgrp_list[P.fgrp_ptr[J] + q] = dev_flux[grp[J][q]];
+  P.smap_ptr.assign(1, 0);
+  std::vector<int64_t> where(f.n_flux, -1);
+  for (int64_t A = 0; A < na; ++A) {
+    P.mA[A] = (int32_t)(c.pptr[A + 1] - c.pptr[A]);
+    for (int64_t cell : members[A]) {
+      P.cell_list.push_back(dev_cell[cell]);
+      for (int64_t q = f.pptr[cell]; q < f.pptr[cell + 1]; ++q) P.pd_list.push_back(dev_p[q]);
+    }
+    P.cell_ptr[A + 1] = (int64_t)P.cell_list.size();
+    P.pd_ptr[A + 1] = (int64_t)P.pd_list.size();
+    // dofs(A): int(A), then the groups of A's coarse faces in A's local order
+    std::vector<int64_t> dofs(ints[A]);
+    P.n_int[A] = (int32_t)ints[A].size();
+    for (int64_t q = c.cfptr[A]; q < c.cfptr[A + 1]; ++q) {
+      int64_t J = c.cfidx[q];
+      if (c.kind[J] == FK_BUBBLE) continue;
+      int64_t off = (int64_t)dofs.size();
+      if (c.c1[J] == A) P.grp_pos_A[J] = off; else P.grp_pos_B[J] = off;
+      dofs.insert(dofs.end(), grp[J].begin(), grp[J].end());
+    }
+    for (size_t q = 0; q < dofs.size(); ++q) where[dofs[q]] = (int64_t)q;
+    for (int64_t cell : members[A]) {
+      int64_t dc = dev_cell[cell];
+      // canonical list of the cell, then reorder to the device local order
+      std::vector<std::pair<int64_t, int64_t>> loc;  // (device flux id, canonical flux id)
+      for (int64_t q = f.cfptr[cell]; q < f.cfptr[cell + 1]; ++q) loc.emplace_back(dev_flux[f.cfidx[q]], f.cfidx[q]);
+      std::sort(loc.begin(), loc.end());
+      int64_t k = dev_cfptr[dc + 1] - dev_cfptr[dc];
+      if ((int64_t)loc.size() != k) fail(SPFAS_ERR_INVALID, "local flux list mismatch");
+      for (int64_t q = 0; q < k; ++q) {
+        if (dev_cfidx[dev_cfptr[dc] + q] != loc[q].first) fail(SPFAS_ERR_INVALID, "device local order mismatch");
+        int64_t w = where[loc[q].second];
+        if (w < 0) fail(SPFAS_ERR_INVALID, "flux of an aggregate cell outside dofs(A)");
+        P.smap.push_back((int32_t)w);
+      }
+      P.smap_ptr.push_back((int64_t)P.smap.size());
+    }
+    for (int64_t j : dofs) {
+      where[j] = -1;
+      P.dof_list.push_back(dev_flux[j]);
+    }
+    P.int_ptr[A + 1] = P.int_ptr[A] + P.n_int[A];
+    P.dof_ptr[A + 1] = (int64_t)P.dof_list.size();
+  }
+  return P;
+}
+
+}  // namespace spfas
