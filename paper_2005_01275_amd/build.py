@@ -18,7 +18,8 @@ OUT = os.path.join(HERE, "libspfas.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPFAS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["topo.cpp", "fine.hip", "hier.hip", "coarse_setup.hip", "solve.hip", "abi.hip"]
+SOURCES = ["topo.cpp", "fine.hip", "sparse.hip", "hier.hip", "coarse_setup.hip", "coarse.hip", "solve.hip",
+           "export.hip", "abi.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -1,0 +1,563 @@
+// Coarse levels in the solve phase (Sections 3.2-3.4 of the paper):
+//   * the level operator assembled cell by cell from the static local
+//     matrices scaled by 1/kappa of the aggregate-average pressure (Prop. 1),
+//   * Picard/Newton linearisation (Props. 2 and 3: E_c = D_c^T +
+//     (M_c sigma_c) kinv'(pbar_c) w_c^T) solved by algebraic hybridisation:
+//     local saddle blocks inverted cell by cell, multipliers on the
+//     interfaces between cells, H lambda = xi, local back-substitution,
+//   * restriction R = P^T, projection Q and prolongation P between levels.
+#include <algorithm>
+#include <cmath>
+
+#include "coarse_kern.hpp"
+#include "hier.hpp"
+#include "kern.hpp"
+
+namespace spfas {
+
+// ------------------------------------------------------------------ residual
+
+struct CView {
+  int n, np, nf;
+  const int *pptr, *lfptr, *lfidx, *mptr, *dptr, *fcell, *floc;
+  const double *M, *D, *w;
+};
+
+static CView cview(const CoarseLevel& C) {
+  CView v;
+  v.n = C.n; v.np = C.np; v.nf = C.nf;
+  v.pptr = C.pptr.p; v.lfptr = C.lfptr.p; v.lfidx = C.lfidx.p; v.mptr = C.mptr.p; v.dptr = C.dptr.p;
+  v.fcell = C.fcell.p; v.floc = C.floc.p; v.M = C.M.p; v.D = C.D.p; v.w = C.w.p;
+  return v;
+}
+
+template <bool STEP>
+__global__ void __launch_bounds__(kBlock) k_coarse_resid(CView v, double alpha, const double* __restrict__ x,
+                                                         const double* __restrict__ dx, double step,
+                                                         const double* __restrict__ b, double* __restrict__ r,
+                                                         double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  const double* sig = x;
+  const double* p = x + v.nf;
+  const double* dsig = dx;
+  const double* dp = dx + v.nf;
+  double acc2 = 0.0;
+  const int ntot = v.nf + v.n;
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x) {
+    if (it < v.nf) {
+      const int j = it;
+      double acc = 0.0;
+      for (int slot = 0; slot < 2; ++slot) {
+        const int c = v.fcell[2 * j + slot];
+        if (c < 0) continue;
+        const int li = v.floc[2 * j + slot];
+        const int k = v.lfptr[c + 1] - v.lfptr[c];
+        const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+        double pbar = 0.0;
+        for (int q = 0; q < m; ++q) pbar += v.w[p0 + q] * (STEP ? p[p0 + q] + step * dp[p0 + q] : p[p0 + q]);
+        const double sc = exp(-alpha * pbar);
+        const double* Mr = v.M + v.mptr[c] + li * k;
+        const int* lf = v.lfidx + v.lfptr[c];
+        double ms = 0.0;
+        for (int i = 0; i < k; ++i) ms += Mr[i] * (STEP ? sig[lf[i]] + step * dsig[lf[i]] : sig[lf[i]]);
+        double dtp = 0.0;
+        for (int q = 0; q < m; ++q) dtp += v.D[v.dptr[c] + q * k + li] * (STEP ? p[p0 + q] + step * dp[p0 + q] : p[p0 + q]);
+        acc += sc * ms + dtp;
+      }
+      const double ri = acc - b[j];
+      if (r) r[j] = ri;
+      acc2 += ri * ri;
+    } else {
+      const int c = it - v.nf;
+      const int k = v.lfptr[c + 1] - v.lfptr[c];
+      const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+      const int* lf = v.lfidx + v.lfptr[c];
+      for (int q = 0; q < m; ++q) {
+        const double* Dr = v.D + v.dptr[c] + q * k;
+        double acc = 0.0;
+        for (int i = 0; i < k; ++i) acc += Dr[i] * (STEP ? sig[lf[i]] + step * dsig[lf[i]] : sig[lf[i]]);
+        const double ri = acc - b[v.nf + p0 + q];
+        if (r) r[v.nf + p0 + q] = ri;
+        acc2 += ri * ri;
+      }
+    }
+  }
+  acc2 = block_sum(acc2, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = acc2;
+}
+
+int launch_coarse_resid(const CoarseLevel& C, double alpha, const double* x, const double* dx, double step,
+                        const double* b, double* r, double* parts, hipStream_t s) {
+  const int G = reduce_grid(C.nf + C.n);
+  CView v = cview(C);
+  if (dx)
+    hipLaunchKernelGGL(k_coarse_resid<true>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, step, b, r, parts);
+  else
+    hipLaunchKernelGGL(k_coarse_resid<false>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, step, b, r, parts);
+  LAUNCHCHECK();
+  return G;
+}
+
+// ------------------------------------------------------------------ hybridisation
+
+struct HView {
+  CView v;
+  const int *zptr, *invptr, *lam_of;   // lam_of: multiplier index of a flux unknown, -1 if none
+  double *inv, *tmp, *z;
+};
+
+// Per cell: build A_c, invert it (LU with partial pivoting, then the columns
+// of the inverse), z_c = A_c^{-1} g_c.
+__global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, double alpha, int newton, const double* __restrict__ x,
+                                                         const double* __restrict__ r) {
+  const CView& v = hv.v;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= v.n) return;
+  const int k = v.lfptr[c + 1] - v.lfptr[c];
+  const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+  const int nc = k + m;
+  const int* lf = v.lfidx + v.lfptr[c];
+  const double* Mc = v.M + v.mptr[c];
+  const double* Dc = v.D + v.dptr[c];
+  const double* sig = x;
+  const double* p = x + v.nf;
+  double pbar = 0.0;
+  for (int q = 0; q < m; ++q) pbar += v.w[p0 + q] * p[p0 + q];
+  const double sc = exp(-alpha * pbar);
+  const double dsc = -alpha * sc;
+  double* A = hv.tmp + hv.invptr[c];
+  double* inv = hv.inv + hv.invptr[c];
+  for (int i = 0; i < k; ++i) {
+    double ms = 0.0;
+    if (newton)
+      for (int j = 0; j < k; ++j) ms += Mc[i * k + j] * sig[lf[j]];
+    for (int j = 0; j < k; ++j) A[i * nc + j] = sc * Mc[i * k + j];
+    for (int q = 0; q < m; ++q) A[i * nc + k + q] = Dc[q * k + i] + (newton ? ms * dsc * v.w[p0 + q] : 0.0);
+  }
+  for (int q = 0; q < m; ++q) {
+    for (int j = 0; j < k; ++j) A[(k + q) * nc + j] = Dc[q * k + j];
+    for (int j = 0; j < m; ++j) A[(k + q) * nc + k + j] = 0.0;
+  }
+  int piv[64];
+  for (int kk = 0; kk < nc; ++kk) {
+    int pr = kk;
+    double best = fabs(A[kk * nc + kk]);
+    for (int i = kk + 1; i < nc; ++i)
+      if (fabs(A[i * nc + kk]) > best) { best = fabs(A[i * nc + kk]); pr = i; }
+    piv[kk] = pr;
+    if (pr != kk)
+      for (int j = 0; j < nc; ++j) { const double t = A[kk * nc + j]; A[kk * nc + j] = A[pr * nc + j]; A[pr * nc + j] = t; }
+    const double d = A[kk * nc + kk];
+    const double id = d != 0.0 ? 1.0 / d : 0.0;
+    for (int i = kk + 1; i < nc; ++i) {
+      const double l = A[i * nc + kk] * id;
+      A[i * nc + kk] = l;
+      for (int j = kk + 1; j < nc; ++j) A[i * nc + j] -= l * A[kk * nc + j];
+    }
+  }
+  for (int col = 0; col < nc; ++col) {
+    for (int i = 0; i < nc; ++i) inv[i * nc + col] = (i == col) ? 1.0 : 0.0;
+    for (int kk = 0; kk < nc; ++kk)
+      if (piv[kk] != kk) {
+        const double t = inv[kk * nc + col];
+        inv[kk * nc + col] = inv[piv[kk] * nc + col];
+        inv[piv[kk] * nc + col] = t;
+      }
+    for (int i = 0; i < nc; ++i) {
+      double s = inv[i * nc + col];
+      for (int j = 0; j < i; ++j) s -= A[i * nc + j] * inv[j * nc + col];
+      inv[i * nc + col] = s;
+    }
+    for (int i = nc - 1; i >= 0; --i) {
+      double s = inv[i * nc + col];
+      for (int j = i + 1; j < nc; ++j) s -= A[i * nc + j] * inv[j * nc + col];
+      const double d = A[i * nc + i];
+      inv[i * nc + col] = d != 0.0 ? s / d : 0.0;
+    }
+  }
+  // z_c = A_c^{-1} g_c, g = [-r_hat; -r_p]; r_hat keeps r_sigma on the first owner only
+  double* z = hv.z + hv.zptr[c];
+  for (int i = 0; i < nc; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < nc; ++j) {
+      double g;
+      if (j < k) {
+        const int fj = lf[j];
+        g = (v.fcell[2 * fj] == c) ? -r[fj] : 0.0;
+      } else {
+        g = -r[v.nf + p0 + (j - k)];
+      }
+      s += inv[i * nc + j] * g;
+    }
+    z[i] = s;
+  }
+}
+
+void launch_coarse_local(CoarseLevel& C, double alpha, bool newton, const double* x, const double* r,
+                         hipStream_t s) {
+  HView hv;
+  hv.v = cview(C);
+  hv.zptr = C.zptr.p;
+  hv.invptr = C.invptr.p;
+  hv.lam_of = nullptr;
+  hv.inv = C.inv.p;
+  hv.tmp = C.t.p;
+  hv.z = C.z.p;
+  hipLaunchKernelGGL(k_coarse_local, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, hv, alpha, newton ? 1 : 0, x, r);
+  LAUNCHCHECK();
+}
+
+// H_{ll'} = sum_c sgn sgn' X_c[i][i'] (X_c: flux block of A_c^{-1});
+// xi_l = z_{c1}[i1] - z_{c2}[i2].  Multiplier l lives on flux l (interfaces
+// come first in the canonical flux order).
+__global__ void __launch_bounds__(kBlock) k_H_assemble(CView v, const int* __restrict__ zptr, const int* __restrict__ invptr,
+                                                       const double* __restrict__ inv, const double* __restrict__ z,
+                                                       int nl, const int* __restrict__ Hptr, const int* __restrict__ Hoc,
+                                                       const int* __restrict__ Hoi, const int* __restrict__ Hoj,
+                                                       const int8_t* __restrict__ Hos, double* __restrict__ Hdiag,
+                                                       double* __restrict__ Hoff, double* __restrict__ xi) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  double d = 0.0, x0 = 0.0;
+  for (int slot = 0; slot < 2; ++slot) {
+    const int c = v.fcell[2 * l + slot];
+    if (c < 0) continue;
+    const int li = v.floc[2 * l + slot];
+    const int nc = (v.lfptr[c + 1] - v.lfptr[c]) + (v.pptr[c + 1] - v.pptr[c]);
+    d += inv[invptr[c] + li * nc + li];
+    x0 += (slot == 0 ? 1.0 : -1.0) * z[zptr[c] + li];
+  }
+  Hdiag[l] = d;
+  xi[l] = x0;
+  for (int e = Hptr[l]; e < Hptr[l + 1]; ++e) {
+    const int c = Hoc[e];
+    const int nc = (v.lfptr[c + 1] - v.lfptr[c]) + (v.pptr[c + 1] - v.pptr[c]);
+    Hoff[e] = (double)Hos[e] * inv[invptr[c] + Hoi[e] * nc + Hoj[e]];
+  }
+}
+
+void launch_H_assemble(CoarseLevel& C, hipStream_t s) {
+  if (C.nl == 0) return;
+  hipLaunchKernelGGL(k_H_assemble, dim3(grid_for(C.nl, kBlock)), dim3(kBlock), 0, s, cview(C), C.zptr.p, C.invptr.p,
+                     C.inv.p, C.z.p, C.nl, C.Hptr.p, C.Hoc.p, C.Hoi.p, C.Hoj.p, C.Hos.p, C.Hdiag.p, C.Hoff.p, C.xi.p);
+  LAUNCHCHECK();
+}
+
+// [dsigma_c; dp_c] = z_c - A_c^{-1} [C_c^T lambda; 0]; each flux takes the
+// value of its first owner.
+__global__ void __launch_bounds__(kBlock) k_coarse_backsub(CView v, const int* __restrict__ zptr,
+                                                           const int* __restrict__ invptr, const double* __restrict__ inv,
+                                                           const double* __restrict__ z, int nl,
+                                                           const double* __restrict__ lam, double* __restrict__ dx,
+                                                           double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  double mx = 0.0;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < v.n) {
+    const int k = v.lfptr[c + 1] - v.lfptr[c];
+    const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+    const int nc = k + m;
+    const int* lf = v.lfidx + v.lfptr[c];
+    const double* Ai = inv + invptr[c];
+    const double* zc = z + zptr[c];
+    double pb = 0.0;
+    for (int i = 0; i < nc; ++i) {
+      double s = zc[i];
+      for (int j = 0; j < k; ++j) {
+        const int fj = lf[j];
+        if (fj < nl) {
+          const double sg = (v.fcell[2 * fj] == c) ? 1.0 : -1.0;
+          s -= Ai[i * nc + j] * sg * lam[fj];
+        }
+      }
+      if (i < k) {
+        if (v.fcell[2 * lf[i]] == c) dx[lf[i]] = s;
+      } else {
+        dx[v.nf + p0 + (i - k)] = s;
+        pb += v.w[p0 + (i - k)] * s;
+      }
+    }
+    mx = fabs(pb);
+  }
+  mx = block_max(mx, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = mx;
+}
+
+int launch_coarse_backsub(CoarseLevel& C, const double* lam, double* dx, double* parts, hipStream_t s) {
+  const unsigned G = grid_for(C.n, kBlock);
+  require(G <= (unsigned)kMaxParts * 4, "too many coarse cells for one reduction");
+  hipLaunchKernelGGL(k_coarse_backsub, dim3(G), dim3(kBlock), 0, s, cview(C), C.zptr.p, C.invptr.p, C.inv.p, C.z.p,
+                     C.nl, lam, dx, parts);
+  LAUNCHCHECK();
+  return (int)G;
+}
+
+// ------------------------------------------------------------------ divergence
+
+__global__ void __launch_bounds__(kBlock) k_div_coarse(CView v, const double* __restrict__ sig, double* __restrict__ div) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= v.n) return;
+  const int k = v.lfptr[c + 1] - v.lfptr[c];
+  const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+  const int* lf = v.lfidx + v.lfptr[c];
+  for (int q = 0; q < m; ++q) {
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc += v.D[v.dptr[c] + q * k + i] * sig[lf[i]];
+    div[p0 + q] = acc;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_div_fine(int64_t n, const int* __restrict__ cfptr, const int* __restrict__ cfcode,
+                                                     const double* __restrict__ sig, double* __restrict__ div) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double acc = 0.0;
+  for (int k = cfptr[c]; k < cfptr[c + 1]; ++k) {
+    const int code = cfcode[k];
+    acc += (code & 1) ? sig[code >> 1] : -sig[code >> 1];
+  }
+  div[c] = acc;
+}
+
+void launch_div_coarse(const CoarseLevel& C, const double* sigma, double* div, hipStream_t s) {
+  hipLaunchKernelGGL(k_div_coarse, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, cview(C), sigma, div);
+  LAUNCHCHECK();
+}
+
+void launch_div_fine(int64_t n, const int* cfptr, const int* cfcode, const double* sigma, double* div,
+                     hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_div_fine, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, cfptr, cfcode, sigma, div);
+  LAUNCHCHECK();
+}
+
+// ------------------------------------------------------------------ transfers
+
+struct TView {
+  int n_agg, nf_f, np_f, nf_c, n_int_total;
+  const int *pd_ptr, *pd_list, *dof_ptr, *dof_list, *n_int, *mA, *fgrp_ptr, *fgrp_list, *Pptr, *Eptr;
+  const int *pd_agg, *pd_row, *int_agg, *int_row, *int_pos, *grp_of, *bub0;
+  const double *P, *E, *trace, *omega;
+  // coarse
+  const int *pptr, *lfptr, *lfidx, *fcell, *floc;
+  const int8_t* kind;
+};
+
+static TView tview(const TransferDev& T, const CoarseLevel& C) {
+  TView t;
+  t.n_agg = T.n_agg; t.nf_f = T.nf_fine; t.np_f = T.np_fine; t.nf_c = C.nf; t.n_int_total = T.n_int_total;
+  t.pd_ptr = T.pd_ptr.p; t.pd_list = T.pd_list.p; t.dof_ptr = T.dof_ptr.p; t.dof_list = T.dof_list.p;
+  t.n_int = T.n_int.p; t.mA = T.mA.p; t.fgrp_ptr = T.fgrp_ptr.p; t.fgrp_list = T.fgrp_list.p; t.Pptr = T.Pptr.p;
+  t.Eptr = T.Eptr.p; t.pd_agg = T.pd_agg.p; t.pd_row = T.pd_row.p; t.int_agg = T.int_agg.p; t.int_row = T.int_row.p;
+  t.int_pos = T.int_pos.p; t.grp_of = T.grp_of.p; t.bub0 = T.bub0.p; t.P = T.P.p; t.E = T.E.p; t.trace = T.trace.p;
+  t.omega = T.omega.p; t.pptr = C.pptr.p; t.lfptr = C.lfptr.p; t.lfidx = C.lfidx.p; t.fcell = C.fcell.p;
+  t.floc = C.floc.p; t.kind = C.kind.p;
+  return t;
+}
+
+// out = P^T in (R), or out = Q in (Q: flux moments on interfaces, divergence
+// moments of the NPV columns on bubbles) -- items: coarse flux unknowns, then
+// aggregates (pressure coefficients).
+template <bool PROJECT>
+__global__ void __launch_bounds__(kBlock) k_restrict_t(TView t, const double* __restrict__ in, const double* __restrict__ divf,
+                                                       double* __restrict__ out) {
+  const int ntot = t.nf_c + t.n_agg;
+  const double* in_s = in;
+  const double* in_p = in + t.nf_f;
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x) {
+    if (it < t.nf_c) {
+      const int J = it;
+      double acc = 0.0;
+      if (t.kind[J] != 2) {
+        for (int q = t.fgrp_ptr[J]; q < t.fgrp_ptr[J + 1]; ++q) {
+          const int g = t.fgrp_list[q];
+          acc += (PROJECT ? t.omega[g] : t.trace[g]) * in_s[g];
+        }
+      }
+      if (!PROJECT) {
+        for (int slot = 0; slot < 2; ++slot) {
+          const int A = t.fcell[2 * J + slot];
+          if (A < 0) continue;
+          const int loc = t.floc[2 * J + slot];
+          const int kA = t.lfptr[A + 1] - t.lfptr[A];
+          const double* EA = t.E + t.Eptr[A];
+          const int* dl = t.dof_list + t.dof_ptr[A];
+          const int nI = t.n_int[A];
+          for (int s = 0; s < nI; ++s) acc += EA[s * kA + loc] * in_s[dl[s]];
+        }
+      } else if (t.kind[J] == 2) {
+        const int A = t.fcell[2 * J];
+        const int j = 1 + (J - t.bub0[A]);
+        const int mA = t.mA[A];
+        const double* PA = t.P + t.Pptr[A];
+        const int* pl = t.pd_list + t.pd_ptr[A];
+        const int npA = t.pd_ptr[A + 1] - t.pd_ptr[A];
+        for (int r = 0; r < npA; ++r) acc += PA[r * mA + j] * divf[pl[r]];
+      }
+      out[J] = acc;
+    } else {
+      const int A = it - t.nf_c;
+      const int mA = t.mA[A];
+      const double* PA = t.P + t.Pptr[A];
+      const int* pl = t.pd_list + t.pd_ptr[A];
+      const int npA = t.pd_ptr[A + 1] - t.pd_ptr[A];
+      for (int i = 0; i < mA; ++i) {
+        double acc = 0.0;
+        for (int r = 0; r < npA; ++r) acc += PA[r * mA + i] * in_p[pl[r]];
+        out[t.nf_c + t.pptr[A] + i] = acc;
+      }
+    }
+  }
+}
+
+void launch_restrict(const TransferDev& T, const CoarseLevel& Cc, const double* rf, double* out, hipStream_t s) {
+  TView t = tview(T, Cc);
+  hipLaunchKernelGGL(k_restrict_t<false>, dim3(grid_for(t.nf_c + t.n_agg, kBlock)), dim3(kBlock), 0, s, t, rf,
+                     (const double*)nullptr, out);
+  LAUNCHCHECK();
+}
+
+void launch_project(const TransferDev& T, const CoarseLevel& Cc, const double* xf, const double* divf, double* out,
+                    hipStream_t s) {
+  TView t = tview(T, Cc);
+  hipLaunchKernelGGL(k_restrict_t<true>, dim3(grid_for(t.nf_c + t.n_agg, kBlock)), dim3(kBlock), 0, s, t, xf, divf,
+                     out);
+  LAUNCHCHECK();
+}
+
+// outf = P e: items = pressure unknowns of the aggregates, interior flux
+// rows, then every fine flux of an interface/Dirichlet group.
+__global__ void __launch_bounds__(kBlock) k_prolong_t(TView t, const double* __restrict__ e, double* __restrict__ outf) {
+  const int npl = t.pd_ptr[t.n_agg];
+  const int ntot = npl + t.n_int_total + t.nf_f;
+  const double* e_s = e;
+  const double* e_p = e + t.nf_c;
+  double* o_s = outf;
+  double* o_p = outf + t.nf_f;
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x) {
+    if (it < npl) {
+      const int A = t.pd_agg[it], row = t.pd_row[it];
+      const int mA = t.mA[A];
+      const double* PA = t.P + t.Pptr[A] + row * mA;
+      double acc = 0.0;
+      for (int i = 0; i < mA; ++i) acc += PA[i] * e_p[t.pptr[A] + i];
+      o_p[t.pd_list[it]] = acc;
+    } else if (it < npl + t.n_int_total) {
+      const int q = it - npl;
+      const int A = t.int_agg[q], row = t.int_row[q];
+      const int kA = t.lfptr[A + 1] - t.lfptr[A];
+      const double* EA = t.E + t.Eptr[A] + row * kA;
+      const int* lf = t.lfidx + t.lfptr[A];
+      double acc = 0.0;
+      for (int k = 0; k < kA; ++k) acc += EA[k] * e_s[lf[k]];
+      o_s[t.dof_list[t.int_pos[q]]] = acc;
+    } else {
+      const int j = it - npl - t.n_int_total;
+      const int J = t.grp_of[j];
+      if (J >= 0) o_s[j] = t.trace[j] * e_s[J];
+    }
+  }
+}
+
+void launch_prolong(const TransferDev& T, const CoarseLevel& Cc, const double* e, double* outf, hipStream_t s) {
+  TView t = tview(T, Cc);
+  const int64_t ntot = (int64_t)T.h_pd_ptr.back() + T.n_int_total + T.nf_fine;
+  hipLaunchKernelGGL(k_prolong_t, dim3(grid_for(ntot, kBlock)), dim3(kBlock), 0, s, t, e, outf);
+  LAUNCHCHECK();
+}
+
+// ------------------------------------------------------------------ solver setup
+
+void setup_coarse_solver(Hierarchy& h, int l) {
+  hipStream_t s = h.stream;
+  CoarseLevel& C = *h.coarse[l - 1];
+  const int n = C.n, nf = C.nf, np = C.np;
+  C.x.alloc(nf + np);
+  C.dx.alloc(nf + np);
+  C.b.alloc(nf + np);
+  C.r.alloc(nf + np);
+  C.div.alloc(np);
+  C.x0.alloc(nf + np);
+  C.ax.alloc(nf + np);
+  C.zeros.alloc(nf + np);
+  C.zeros.zero(s);
+  // offsets of local systems
+  std::vector<int> zptr(n + 1, 0), invptr(n + 1, 0);
+  int mxn = 0;
+  for (int c = 0; c < n; ++c) {
+    const int nc = (C.h_lfptr[c + 1] - C.h_lfptr[c]) + (C.h_pptr[c + 1] - C.h_pptr[c]);
+    mxn = std::max(mxn, nc);
+    zptr[c + 1] = zptr[c] + nc;
+    invptr[c + 1] = invptr[c] + nc * nc;
+  }
+  require(mxn <= 64, "coarse cell with more than 64 local unknowns");
+  C.nsum = zptr[n];
+  C.zptr.upload(zptr, s);
+  C.invptr.upload(invptr, s);
+  C.inv.alloc(invptr[n]);
+  C.t.alloc(std::max(invptr[n], nf + np));
+  C.z.alloc(zptr[n]);
+  // multipliers: the interior interfaces, which come first
+  int nl = 0;
+  while (nl < nf && C.h_kind[nl] == FK_INTERIOR) ++nl;
+  C.nl = nl;
+  std::vector<int> fcell(2 * nf), floc(2 * nf);
+  {
+    std::vector<int> a = C.fcell.download(s), b = C.floc.download(s);
+    fcell = a;
+    floc = b;
+  }
+  std::vector<int> Hptr(nl + 1, 0), Hcol, Hoc, Hoi, Hoj;
+  std::vector<int8_t> Hos;
+  for (int L = 0; L < nl; ++L) {
+    std::vector<std::tuple<int, int, int, int, int>> ent;   // (col, cell, li, lj, sign)
+    for (int slot = 0; slot < 2; ++slot) {
+      const int c = fcell[2 * L + slot];
+      if (c < 0) continue;
+      const int li = floc[2 * L + slot];
+      const int sgi = slot == 0 ? 1 : -1;
+      for (int q = C.h_lfptr[c]; q < C.h_lfptr[c + 1]; ++q) {
+        const int J = C.h_lfidx[q];
+        if (J == L || J >= nl) continue;
+        const int lj = q - C.h_lfptr[c];
+        const int sgj = (fcell[2 * J] == c) ? 1 : -1;
+        ent.emplace_back(J, c, li, lj, sgi * sgj);
+      }
+    }
+    std::sort(ent.begin(), ent.end());
+    for (auto& e : ent) {
+      Hcol.push_back(std::get<0>(e));
+      Hoc.push_back(std::get<1>(e));
+      Hoi.push_back(std::get<2>(e));
+      Hoj.push_back(std::get<3>(e));
+      Hos.push_back((int8_t)std::get<4>(e));
+    }
+    Hptr[L + 1] = (int)Hcol.size();
+  }
+  C.Hptr.upload(Hptr, s);
+  C.Hcol.upload(Hcol, s);
+  C.Hoc.upload(Hoc, s);
+  C.Hoi.upload(Hoi, s);
+  C.Hoj.upload(Hoj, s);
+  C.Hos.upload(Hos, s);
+  C.Hdiag.alloc(nl);
+  C.Hoff.alloc(Hcol.size());
+  C.xi.alloc(nl);
+  C.lam.alloc(nl);
+  C.H.n = nl;
+  C.H.diag = C.Hdiag.p;
+  C.H.ptr = C.Hptr.p;
+  C.H.col = C.Hcol.p;
+  C.H.val = C.Hoff.p;
+  if (nl > 0) {
+    // aggregation matrix: Picard at x = 0 (kappa = 1)
+    C.x.zero(s);
+    C.r.zero(s);
+    launch_coarse_local(C, 0.0, false, C.x.p, C.r.p, s);
+    launch_H_assemble(C, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    C.amg.setup(C.H, s);
+  }
+}
+
+}  // namespace spfas

@@ -1,0 +1,33 @@
+// Coarse-level kernels of the solve phase and the transfers (coarse.hip).
+#pragma once
+
+#include "coarse.hpp"
+
+namespace spfas {
+
+struct Hierarchy;
+
+// r = A^l(x + step dx) - b on a coarse level (Prop. 1 assembly); returns the
+// number of partial sums of r.r written to parts.
+int launch_coarse_resid(const CoarseLevel& C, double alpha, const double* x, const double* dx, double step,
+                        const double* b, double* r, double* parts, hipStream_t s);
+// local saddle blocks [s_c M_c, E_c; D_c, 0], their inverses and the local
+// solutions z_c = A_c^{-1} [-r_hat_c; -r_p,c] (algebraic hybridisation)
+void launch_coarse_local(CoarseLevel& C, double alpha, bool newton, const double* x, const double* r,
+                         hipStream_t s);
+void launch_H_assemble(CoarseLevel& C, hipStream_t s);
+// dx from the multipliers; parts = per-block max |w_c . dp_c|; returns #parts
+int launch_coarse_backsub(CoarseLevel& C, const double* lam, double* dx, double* parts, hipStream_t s);
+// divergence D^l sigma per pressure unknown (level 0 uses the face lists)
+void launch_div_coarse(const CoarseLevel& C, const double* sigma, double* div, hipStream_t s);
+void launch_div_fine(int64_t n, const int* cfptr, const int* cfcode, const double* sigma, double* div,
+                     hipStream_t s);
+// transfers between level l (nf_l flux, np_l pressure) and level l+1
+void launch_restrict(const TransferDev& T, const CoarseLevel& Cc, const double* rf, double* out, hipStream_t s);
+void launch_project(const TransferDev& T, const CoarseLevel& Cc, const double* xf, const double* divf, double* out,
+                    hipStream_t s);
+void launch_prolong(const TransferDev& T, const CoarseLevel& Cc, const double* e, double* outf, hipStream_t s);
+
+void setup_coarse_solver(Hierarchy& h, int l);
+
+}  // namespace spfas

@@ -1,5 +1,753 @@
-#include "coarse.hpp"
+// Batched hierarchy setup on the device (Appendix A of the paper):
+//   phase A, one workgroup per coarse interface: PV trace t_F from the
+//     local mixed problem on the union of its two aggregates (one-sided on
+//     Dirichlet groups);
+//   phase B, one workgroup per aggregate: local Laplacian
+//     L_A = D_int M_int^{-1} D_int^T (static matrices), full Jacobi
+//     eigen-decomposition, P_A = [q_PV, v_2..v_m], bubbles and trace
+//     extensions through the pseudo-inverse of L_A, the static coarse local
+//     matrices M^{l+1}_A = P_sigma,A^T M_A P_sigma,A and
+//     D^{l+1}_A = P_A^T D_A P_sigma,A (Prop. 1), the flux-moment weights of
+//     Q_sigma and the weights of the piecewise-constant projector (App. B).
+// Host code orchestrates the levels and builds the index plans.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "coarse_kern.hpp"
+#include "dense.hpp"
 #include "hier.hpp"
+#include "kern.hpp"
+
 namespace spfas {
-void setup_coarse_levels(Hierarchy&) {}
+
+// ------------------------------------------------------------------ local matrix access
+
+__device__ inline int lv_k(const LocalView& v, int c) {
+  return v.level0 ? v.cfptr[c + 1] - v.cfptr[c] : v.lfptr[c + 1] - v.lfptr[c];
 }
+__device__ inline int lv_m(const LocalView& v, int c) { return v.level0 ? 1 : v.pptr[c + 1] - v.pptr[c]; }
+__device__ inline double lv_M(const LocalView& v, int c, int i, int j) {
+  if (v.level0) {
+    if (i != j) return 0.0;
+    const int code = v.cfcode[v.cfptr[c] + i];
+    return (code & 1) ? v.TLi[code >> 1] : v.TKi[code >> 1];
+  }
+  const int k = v.lfptr[c + 1] - v.lfptr[c];
+  return v.M[v.mptr[c] + i * k + j];
+}
+__device__ inline double lv_D(const LocalView& v, int c, int r, int i) {
+  if (v.level0) return (v.cfcode[v.cfptr[c] + i] & 1) ? 1.0 : -1.0;
+  const int k = v.lfptr[c + 1] - v.lfptr[c];
+  return v.D[v.dptr[c] + r * k + i];
+}
+
+struct PlanView {
+  const int *cell_ptr, *cell_list, *pd_ptr, *pd_list, *dof_ptr, *dof_list, *n_int, *mA;
+  const int *fgrp_ptr, *fgrp_list, *grp_pos_A, *grp_pos_B, *smap_ptr, *smap;
+};
+
+// ------------------------------------------------------------------ phase A
+
+struct ScratchA {
+  size_t mu, du, t, l, y;   // sizes in doubles
+  size_t total;
+};
+
+__global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, int n_faces, const int* __restrict__ fc1,
+                                                     const int* __restrict__ fc2, const double* __restrict__ ones,
+                                                     double* __restrict__ trace, double* __restrict__ scratch,
+                                                     ScratchA sa, int* __restrict__ bad) {
+  __shared__ int flag;
+  __shared__ double red[2 * kBlock];
+  double* Mu = scratch + (size_t)blockIdx.x * sa.total;
+  double* Du = Mu + sa.mu;
+  double* T = Du + sa.du;
+  double* L = T + sa.t;
+  double* y = L + sa.l;
+  for (int F = blockIdx.x; F < n_faces; F += gridDim.x) {
+    const int A = fc1[F], B = fc2[F];
+    const int nIA = pl.n_int[A], nIB = B >= 0 ? pl.n_int[B] : 0;
+    const int nF = pl.fgrp_ptr[F + 1] - pl.fgrp_ptr[F];
+    const int ns = nIA + nIB + nF;
+    const int npA = pl.pd_ptr[A + 1] - pl.pd_ptr[A];
+    const int npB = B >= 0 ? pl.pd_ptr[B + 1] - pl.pd_ptr[B] : 0;
+    const int npU = npA + npB;
+    const int gA = pl.grp_pos_A[F], gB = B >= 0 ? pl.grp_pos_B[F] : -1;
+    const int ldm = lv.level0 ? 1 : ns;
+    wg_fill(Mu, lv.level0 ? ns : ns * ns, 0.0);
+    wg_fill(Du, npU * ns, 0.0);
+    // assemble cell by cell (deterministic: cells in order, entries of one cell in parallel)
+    int rowbase = 0;
+    for (int side = 0; side < (B >= 0 ? 2 : 1); ++side) {
+      const int X = side == 0 ? A : B;
+      for (int ci = pl.cell_ptr[X]; ci < pl.cell_ptr[X + 1]; ++ci) {
+        const int c = pl.cell_list[ci];
+        const int k = lv_k(lv, c), m = lv_m(lv, c);
+        const int* sm = pl.smap + pl.smap_ptr[ci];
+        auto posU = [&](int i) -> int {
+          const int q = sm[i];
+          if (side == 0) {
+            if (q < nIA) return q;
+            if (q >= gA && q < gA + nF) return nIA + nIB + (q - gA);
+            return -1;
+          }
+          if (q < nIB) return nIA + q;
+          if (q >= gB && q < gB + nF) return nIA + nIB + (q - gB);
+          return -1;
+        };
+        if (lv.level0) {
+          for (int i = threadIdx.x; i < k; i += blockDim.x) {
+            const int pi = posU(i);
+            if (pi >= 0) Mu[pi] += lv_M(lv, c, i, i);
+          }
+        } else {
+          for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+            const int i = e / k, j = e % k;
+            const int pi = posU(i), pj = posU(j);
+            if (pi >= 0 && pj >= 0) Mu[pi * ldm + pj] += lv_M(lv, c, i, j);
+          }
+        }
+        for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+          const int r = e / k, i = e % k;
+          const int pi = posU(i);
+          if (pi >= 0) Du[(rowbase + r) * ns + pi] += lv_D(lv, c, r, i);
+        }
+        rowbase += m;
+        wg_sync();
+      }
+    }
+    // T = Mu^{-1} Du^T  (ns x npU)
+    for (int e = threadIdx.x; e < ns * npU; e += blockDim.x) {
+      const int s = e / npU, r = e % npU;
+      T[s * npU + r] = lv.level0 ? Du[r * ns + s] / Mu[s] : Du[r * ns + s];
+    }
+    wg_sync();
+    if (!lv.level0) {
+      if (!wg_chol(Mu, ns, ns, &flag)) {
+        if (threadIdx.x == 0) { atomicAdd(bad, 1); bad[1] = 1; bad[2] = F; bad[3] = flag; }
+        continue;
+      }
+      wg_chol_solve(Mu, ns, ns, T, npU, npU);
+    }
+    // L = Du T (+ rho u u^T on interior interfaces: pure Neumann union)
+    wg_gemm(Du, ns, false, T, npU, false, L, npU, npU, npU, ns);
+    // right-hand side -f_F and the regularisation
+    double na = 0.0, nb = 0.0;
+    for (int r = 0; r < npA; ++r) { const double o = ones[pl.pd_list[pl.pd_ptr[A] + r]]; na += o * o; }
+    for (int r = 0; r < npB; ++r) { const double o = ones[pl.pd_list[pl.pd_ptr[B] + r]]; nb += o * o; }
+    for (int r = threadIdx.x; r < npU; r += blockDim.x) {
+      const double o = r < npA ? ones[pl.pd_list[pl.pd_ptr[A] + r]] : ones[pl.pd_list[pl.pd_ptr[B] + r - npA]];
+      y[r] = r < npA ? o / na : -o / nb;   // -f_F
+    }
+    if (B >= 0) {
+      double rho = 0.0;
+      for (int r = 0; r < npU; ++r) rho = fmax(rho, L[r * npU + r]);
+      wg_sync();   // every thread has read the diagonal before any update below
+      const double nu = na + nb;
+      for (int e = threadIdx.x; e < npU * npU; e += blockDim.x) {
+        const int r = e / npU, q = e % npU;
+        const double ur = r < npA ? ones[pl.pd_list[pl.pd_ptr[A] + r]] : ones[pl.pd_list[pl.pd_ptr[B] + r - npA]];
+        const double uq = q < npA ? ones[pl.pd_list[pl.pd_ptr[A] + q]] : ones[pl.pd_list[pl.pd_ptr[B] + q - npA]];
+        L[e] += rho * ur * uq / nu;
+      }
+    }
+    wg_sync();
+    if (!wg_chol(L, npU, npU, &flag)) {
+      if (threadIdx.x == 0) { atomicAdd(bad, 1); bad[1] = 2; bad[2] = F; bad[3] = flag; }
+      continue;
+    }
+    wg_chol_solve(L, npU, npU, y, 1, 1);
+    // sigma = -T p, restricted to F
+    for (int q = threadIdx.x; q < nF; q += blockDim.x) {
+      const int s = nIA + nIB + q;
+      double acc = 0.0;
+      for (int r = 0; r < npU; ++r) acc += T[s * npU + r] * y[r];
+      trace[pl.fgrp_list[pl.fgrp_ptr[F] + q]] = -acc;
+    }
+    wg_sync();
+  }
+}
+
+// ------------------------------------------------------------------ phase B
+
+struct ScratchB {
+  size_t ma, da, ci, t, l, v, pl, tmp, vec;
+  size_t total;
+};
+
+struct CoarseOut {
+  const int* lfptr;     // coarse local flux lists
+  const int* lfidx;
+  const int* c1;        // coarse flux cells
+  const int* pptr;
+  const int* mptr;
+  const int* dptr;
+  double* M;
+  double* D;
+  double* w;
+  double* ones;
+  double* u;
+  double* vol;
+};
+
+__global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl, int n_agg, const double* __restrict__ ones,
+                                                      const double* __restrict__ uvec, const double* __restrict__ vol,
+                                                      const double* __restrict__ trace, double* __restrict__ omega,
+                                                      const int* __restrict__ Pptr, double* __restrict__ P,
+                                                      const int* __restrict__ Eptr, double* __restrict__ E,
+                                                      double* __restrict__ eig, CoarseOut co,
+                                                      double* __restrict__ scratch, ScratchB sb, int* __restrict__ bad) {
+  __shared__ int flag;
+  __shared__ double red[2 * kBlock];
+  __shared__ double cs[2 * (kBlock + 1)];
+  __shared__ int prs[2 * (kBlock + 1)];
+  __shared__ int idx_small[64];
+  __shared__ double scal[8];
+  double* MA = scratch + (size_t)blockIdx.x * sb.total;
+  double* DA = MA + sb.ma;
+  double* Ci = DA + sb.da;
+  double* T = Ci + sb.ci;
+  double* L = T + sb.t;
+  double* V = L + sb.l;
+  double* Pl = V + sb.v;
+  double* tmp = Pl + sb.pl;
+  double* vec = tmp + sb.tmp;   // 4 vectors of length npA + one of length nd
+  for (int A = blockIdx.x; A < n_agg; A += gridDim.x) {
+    const int nI = pl.n_int[A];
+    const int nd = pl.dof_ptr[A + 1] - pl.dof_ptr[A];
+    const int npA = pl.pd_ptr[A + 1] - pl.pd_ptr[A];
+    const int mA = pl.mA[A];
+    const int kA = co.lfptr[A + 1] - co.lfptr[A];
+    const int nbub = mA - 1;
+    const int nface = kA - nbub;
+    const int* pdA = pl.pd_list + pl.pd_ptr[A];
+    double* y0 = vec;
+    double* y1 = vec + npA;
+    double* q = vec + 2 * npA;
+    double* yc = vec + 3 * npA;   // length >= nd
+    const int ldm = lv.level0 ? 1 : nd;
+    // 1. assemble M_A (over dofs(A)) and D_A
+    wg_fill(MA, lv.level0 ? nd : nd * nd, 0.0);
+    wg_fill(DA, npA * nd, 0.0);
+    int rowbase = 0;
+    for (int ci = pl.cell_ptr[A]; ci < pl.cell_ptr[A + 1]; ++ci) {
+      const int c = pl.cell_list[ci];
+      const int k = lv_k(lv, c), m = lv_m(lv, c);
+      const int* sm = pl.smap + pl.smap_ptr[ci];
+      if (lv.level0) {
+        for (int i = threadIdx.x; i < k; i += blockDim.x) MA[sm[i]] += lv_M(lv, c, i, i);
+      } else {
+        for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+          const int i = e / k, j = e % k;
+          MA[sm[i] * ldm + sm[j]] += lv_M(lv, c, i, j);
+        }
+      }
+      for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+        const int r = e / k, i = e % k;
+        DA[(rowbase + r) * nd + sm[i]] += lv_D(lv, c, r, i);
+      }
+      rowbase += m;
+      wg_sync();
+    }
+    // 2-3. T = M_int^{-1} D_int^T  (nI x npA)
+    for (int e = threadIdx.x; e < nI * npA; e += blockDim.x) {
+      const int s = e / npA, r = e % npA;
+      T[s * npA + r] = lv.level0 ? DA[r * nd + s] / MA[s] : DA[r * nd + s];
+    }
+    if (!lv.level0)
+      for (int e = threadIdx.x; e < nI * nI; e += blockDim.x) Ci[e] = MA[(e / nI) * nd + e % nI];
+    wg_sync();
+    if (!lv.level0 && nI > 0) {
+      if (!wg_chol(Ci, nI, nI, &flag)) {
+        if (threadIdx.x == 0) { atomicAdd(bad, 1); bad[1] = 3; bad[2] = A; bad[3] = flag; }
+        continue;
+      }
+      wg_chol_solve(Ci, nI, nI, T, npA, npA);
+    }
+    // L = D_int T
+    wg_gemm(DA, nd, false, T, npA, false, L, npA, npA, npA, nI);
+    // symmetrise
+    for (int e = threadIdx.x; e < npA * npA; e += blockDim.x) {
+      const int i = e / npA, j = e % npA;
+      if (i < j) {
+        const double s = 0.5 * (L[i * npA + j] + L[j * npA + i]);
+        L[i * npA + j] = s;
+        L[j * npA + i] = s;
+      }
+    }
+    wg_sync();
+    // 4. eigen-decomposition
+    wg_jacobi_eig(L, npA, V, npA, npA, cs, prs, red);
+    // 5. order the spectrum (thread 0; small sizes)
+    if (threadIdx.x == 0) {
+      double* lam = eig + pl.pd_ptr[A];
+      // insertion sort of (lambda, index) into tmp (as doubles) -> sorted eigenvalues and indices
+      int* ord = (int*)tmp;
+      for (int i = 0; i < npA; ++i) ord[i] = i;
+      for (int i = 1; i < npA; ++i) {
+        const int oi = ord[i];
+        const double li = L[oi * npA + oi];
+        int j = i - 1;
+        while (j >= 0 && L[ord[j] * npA + ord[j]] > li) { ord[j + 1] = ord[j]; --j; }
+        ord[j + 1] = oi;
+      }
+      for (int i = 0; i < npA; ++i) lam[i] = L[ord[i] * npA + ord[i]];
+      for (int i = 0; i < mA && i < 64; ++i) idx_small[i] = ord[i];
+    }
+    wg_sync();
+    const int i0 = idx_small[0];
+    // 6. P_A = [q_PV, v_2..v_m]
+    if (threadIdx.x == 0) {
+      double nn = 0.0;
+      for (int r = 0; r < npA; ++r) nn += ones[pdA[r]] * ones[pdA[r]];
+      scal[0] = sqrt(nn);
+    }
+    wg_sync();
+    for (int r = threadIdx.x; r < npA; r += blockDim.x) q[r] = ones[pdA[r]] / scal[0];
+    wg_sync();
+    double* PA = P + Pptr[A];
+    for (int r = threadIdx.x; r < npA; r += blockDim.x) PA[r * mA] = q[r];
+    for (int j = 1; j < mA; ++j) {
+      const int col = idx_small[j];
+      if (threadIdx.x == 0) {
+        double d = 0.0;
+        for (int r = 0; r < npA; ++r) d += q[r] * V[r * npA + col];
+        scal[1] = d;
+      }
+      wg_sync();
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = V[r * npA + col] - scal[1] * q[r];
+      wg_sync();
+      if (threadIdx.x == 0) {
+        double nn = 0.0, mx = 0.0;
+        for (int r = 0; r < npA; ++r) { nn += y0[r] * y0[r]; mx = fmax(mx, fabs(y0[r])); }
+        const double thr = 1e-8 * mx;
+        int k = 0;
+        while (k < npA && !(fabs(y0[k]) > thr)) ++k;
+        const double sg = (k < npA && y0[k] < 0.0) ? -1.0 : 1.0;
+        scal[2] = sg / sqrt(nn);
+      }
+      wg_sync();
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) PA[r * mA + j] = y0[r] * scal[2];
+      wg_sync();
+    }
+    // pseudo-inverse of L_A on a vector: out = sum_{i != i0} V_i (V_i . in) / lambda_i
+    auto lplus = [&](const double* in, double* out) {
+      for (int i = threadIdx.x; i < npA; i += blockDim.x) {
+        double s = 0.0;
+        if (i != i0) {
+          for (int r = 0; r < npA; ++r) s += V[r * npA + i] * in[r];
+          s /= L[i * npA + i];
+        }
+        y1[i] = s;
+      }
+      wg_sync();
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < npA; ++i) s += V[r * npA + i] * y1[i];
+        out[r] = s;
+      }
+      wg_sync();
+    };
+    // 7-9. columns of P_sigma restricted to dofs(A): Pl (nd x kA)
+    wg_fill(Pl, nd * kA, 0.0);
+    for (int j = 1; j < mA; ++j) {
+      // bubble: b = T L^+ v_j
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = PA[r * mA + j];
+      wg_sync();
+      lplus(y0, yc);
+      const int col = nface + j - 1;
+      for (int s = threadIdx.x; s < nI; s += blockDim.x) {
+        double acc = 0.0;
+        for (int r = 0; r < npA; ++r) acc += T[s * npA + r] * yc[r];
+        Pl[s * kA + col] = acc;
+      }
+      wg_sync();
+    }
+    for (int kf = 0; kf < nface; ++kf) {
+      const int J = co.lfidx[co.lfptr[A] + kf];
+      const int gpos = (co.c1[J] == A) ? pl.grp_pos_A[J] : pl.grp_pos_B[J];
+      const int nF = pl.fgrp_ptr[J + 1] - pl.fgrp_ptr[J];
+      const int* grp = pl.fgrp_list + pl.fgrp_ptr[J];
+      // trace on the group rows
+      for (int i = threadIdx.x; i < nF; i += blockDim.x) Pl[(gpos + i) * kA + kf] = trace[grp[i]];
+      // DF = D_{A,F} t  and c = q . DF
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) {
+        double acc = 0.0;
+        for (int i = 0; i < nF; ++i) acc += DA[r * nd + gpos + i] * trace[grp[i]];
+        y0[r] = acc;
+      }
+      wg_sync();
+      if (threadIdx.x == 0) {
+        double c = 0.0;
+        for (int r = 0; r < npA; ++r) c += q[r] * y0[r];
+        scal[3] = c;
+      }
+      wg_sync();
+      const double cA = scal[3];
+      // g1 = -M_{int,F} t ; h = M_int^{-1} g1 (coarse levels only)
+      double* h = Pl;   // reuse: write h into column kf of the interior rows
+      if (!lv.level0) {
+        for (int s = threadIdx.x; s < nI; s += blockDim.x) {
+          double acc = 0.0;
+          for (int i = 0; i < nF; ++i) acc -= MA[s * nd + gpos + i] * trace[grp[i]];
+          h[s * kA + kf] = acc;
+        }
+        wg_sync();
+        // T^T g1  (before solving: D_int M_int^{-1} g1 = T^T g1)
+        for (int r = threadIdx.x; r < npA; r += blockDim.x) {
+          double acc = 0.0;
+          for (int s = 0; s < nI; ++s) acc += T[s * npA + r] * h[s * kA + kf];
+          yc[r] = acc;
+        }
+        wg_sync();
+        if (nI > 0) wg_chol_solve(Ci, nI, nI, h + kf, 1, kA);
+      } else {
+        for (int r = threadIdx.x; r < npA; r += blockDim.x) yc[r] = 0.0;
+        wg_sync();
+      }
+      // rhs = T^T g1 - (c q - DF); pp = L^+ rhs
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) yc[r] = yc[r] - (cA * q[r] - y0[r]);
+      wg_sync();
+      lplus(yc, y0);
+      // sigma_int = h - T pp
+      for (int s = threadIdx.x; s < nI; s += blockDim.x) {
+        double acc = 0.0;
+        for (int r = 0; r < npA; ++r) acc += T[s * npA + r] * y0[r];
+        Pl[s * kA + kf] = (lv.level0 ? 0.0 : Pl[s * kA + kf]) - acc;
+      }
+      wg_sync();
+      // Q_sigma weights (lower aggregate of an interface, or the only one of a Dirichlet group)
+      if (co.c1[J] == A) {
+        for (int i = threadIdx.x; i < nF; i += blockDim.x) {
+          double acc = 0.0;
+          for (int r = 0; r < npA; ++r) acc += q[r] * DA[r * nd + gpos + i];
+          omega[grp[i]] = acc / cA;
+        }
+      }
+      wg_sync();
+    }
+    // 10. M^{l+1}_A = Pl^T M_A Pl
+    double* Mc = co.M + co.mptr[A];
+    if (lv.level0) {
+      for (int e = threadIdx.x; e < kA * kA; e += blockDim.x) {
+        const int a = e / kA, b = e % kA;
+        double acc = 0.0;
+        for (int s = 0; s < nd; ++s) acc += Pl[s * kA + a] * MA[s] * Pl[s * kA + b];
+        Mc[e] = acc;
+      }
+      wg_sync();
+    } else {
+      wg_gemm(MA, nd, false, Pl, kA, false, tmp, kA, nd, kA, nd);
+      wg_gemm(Pl, kA, true, tmp, kA, false, Mc, kA, kA, kA, nd);
+    }
+    // 11. D^{l+1}_A = P_A^T D_A Pl
+    wg_gemm(DA, nd, false, Pl, kA, false, tmp, kA, npA, kA, nd);
+    wg_gemm(PA, mA, true, tmp, kA, false, co.D + co.dptr[A], kA, mA, kA, npA);
+    // 12. interior block of P_sigma
+    double* EA = E + Eptr[A];
+    for (int e = threadIdx.x; e < nI * kA; e += blockDim.x) EA[e] = Pl[e];
+    // 14. projector weights and coarse 1, u, volume
+    for (int i = threadIdx.x; i < mA; i += blockDim.x) {
+      double so = 0.0, su = 0.0;
+      for (int r = 0; r < npA; ++r) {
+        so += PA[r * mA + i] * ones[pdA[r]];
+        su += PA[r * mA + i] * uvec[pdA[r]];
+      }
+      co.ones[co.pptr[A] + i] = so;
+      co.u[co.pptr[A] + i] = su;
+    }
+    if (threadIdx.x == 0) {
+      double v = 0.0;
+      for (int ci = pl.cell_ptr[A]; ci < pl.cell_ptr[A + 1]; ++ci) v += vol[pl.cell_list[ci]];
+      co.vol[A] = v;
+    }
+    wg_sync();
+    for (int i = threadIdx.x; i < mA; i += blockDim.x) co.w[co.pptr[A] + i] = co.u[co.pptr[A] + i] / co.vol[A];
+    wg_sync();
+  }
+}
+
+// ------------------------------------------------------------------ host orchestration
+
+static PlanView plan_view(const TransferDev& t) {
+  PlanView p;
+  p.cell_ptr = t.cell_ptr.p; p.cell_list = t.cell_list.p; p.pd_ptr = t.pd_ptr.p; p.pd_list = t.pd_list.p;
+  p.dof_ptr = t.dof_ptr.p; p.dof_list = t.dof_list.p; p.n_int = t.n_int.p; p.mA = t.mA.p;
+  p.fgrp_ptr = t.fgrp_ptr.p; p.fgrp_list = t.fgrp_list.p; p.grp_pos_A = t.grp_pos_A.p; p.grp_pos_B = t.grp_pos_B.p;
+  p.smap_ptr = t.smap_ptr.p; p.smap = t.smap.p;
+  return p;
+}
+
+template <class T>
+static std::vector<int> to_int(const std::vector<T>& v) {
+  std::vector<int> r(v.size());
+  for (size_t i = 0; i < v.size(); ++i) r[i] = (int)v[i];
+  return r;
+}
+
+static size_t slots_for(size_t per_slot_doubles, int items) {
+  const size_t budget = (size_t)6 << 30;   // bytes of setup scratch
+  size_t s = budget / std::max<size_t>(1, per_slot_doubles * sizeof(double));
+  s = std::max<size_t>(1, std::min<size_t>(s, 4096));
+  return std::min<size_t>(s, (size_t)std::max(1, items));
+}
+
+void setup_coarse_levels(Hierarchy& h) {
+  hipStream_t s = h.stream;
+  const int L = h.n_levels;
+  if (L < 2) return;
+  h.eigvals.assign(L - 1, {});
+  // device view of level 0
+  FineDev& f = h.fine;
+  std::vector<int> cfptr0 = f.cfptr.download(s), cfcode0 = f.cfcode.download(s);
+  std::vector<int> cell_in0 = f.cell_in.download(s);   // internal -> canonical cell id on level 0
+  const Topo& t0 = h.topo[0];
+  const int64_t n0 = t0.n_cells, nf0 = t0.n_flux;
+  // canonical -> device ids on level 0
+  std::vector<int64_t> dev_cell0(n0), dev_flux0(nf0);
+  for (int64_t i = 0; i < n0; ++i) dev_cell0[cell_in0[i]] = i;
+  for (int64_t i = 0; i < nf0; ++i) dev_flux0[t0.flux_order[i]] = i;
+  DVec<double> ones0;
+  ones0.alloc(n0);
+  launch_fill(n0, 1.0, ones0.p, s);
+  for (int l = 0; l + 1 < L; ++l) {
+    const Topo& tf = h.topo[l];
+    const Topo& tc = h.topo[l + 1];
+    std::vector<int64_t> dev_cell, dev_p, dev_flux, dcfptr, dcfidx;
+    if (l == 0) {
+      dev_cell = dev_cell0;
+      dev_p = dev_cell0;
+      dev_flux = dev_flux0;
+      dcfptr.assign(cfptr0.begin(), cfptr0.end());
+      dcfidx.resize(cfcode0.size());
+      for (size_t k = 0; k < cfcode0.size(); ++k) dcfidx[k] = cfcode0[k] >> 1;
+    } else {
+      dev_cell.resize(tf.n_cells);
+      std::iota(dev_cell.begin(), dev_cell.end(), 0);
+      dev_p.resize(tf.n_p());
+      std::iota(dev_p.begin(), dev_p.end(), 0);
+      dev_flux.resize(tf.n_flux);
+      std::iota(dev_flux.begin(), dev_flux.end(), 0);
+      dcfptr = tf.cfptr;
+      dcfidx = tf.cfidx;
+    }
+    TransferPlan plan = make_plan(tf, tc, dev_cell, dev_p, dev_flux, dcfptr, dcfidx);
+    auto tr = std::make_unique<TransferDev>();
+    TransferDev& T = *tr;
+    T.n_agg = (int)plan.n_agg;
+    T.nf_fine = (int)tf.n_flux;
+    T.np_fine = (int)tf.n_p();
+    T.cell_ptr.upload(to_int(plan.cell_ptr), s);
+    T.cell_list.upload(to_int(plan.cell_list), s);
+    T.pd_ptr.upload(to_int(plan.pd_ptr), s);
+    T.pd_list.upload(to_int(plan.pd_list), s);
+    T.dof_ptr.upload(to_int(plan.dof_ptr), s);
+    T.dof_list.upload(to_int(plan.dof_list), s);
+    T.n_int.upload(plan.n_int, s);
+    T.mA.upload(plan.mA, s);
+    T.fgrp_ptr.upload(to_int(plan.fgrp_ptr), s);
+    T.fgrp_list.upload(to_int(plan.fgrp_list), s);
+    T.grp_pos_A.upload(to_int(plan.grp_pos_A), s);
+    T.grp_pos_B.upload(to_int(plan.grp_pos_B), s);
+    T.smap_ptr.upload(to_int(plan.smap_ptr), s);
+    T.smap.upload(plan.smap, s);
+    T.h_pd_ptr = to_int(plan.pd_ptr);
+    T.h_mA = plan.mA;
+    T.h_nint = plan.n_int;
+    // ---- coarse level topology on the device
+    auto cl = std::make_unique<CoarseLevel>();
+    CoarseLevel& C = *cl;
+    C.n = (int)tc.n_cells;
+    C.np = (int)tc.n_p();
+    C.nf = (int)tc.n_flux;
+    C.h_pptr = to_int(tc.pptr);
+    C.h_lfptr = to_int(tc.cfptr);
+    C.h_lfidx = to_int(tc.cfidx);
+    C.h_c1 = to_int(tc.c1);
+    C.h_c2 = to_int(tc.c2);
+    C.h_kind = tc.kind;
+    C.h_mptr.assign(C.n + 1, 0);
+    C.h_dptr.assign(C.n + 1, 0);
+    for (int c = 0; c < C.n; ++c) {
+      const int k = C.h_lfptr[c + 1] - C.h_lfptr[c], m = C.h_pptr[c + 1] - C.h_pptr[c];
+      C.h_mptr[c + 1] = C.h_mptr[c] + k * k;
+      C.h_dptr[c + 1] = C.h_dptr[c] + m * k;
+    }
+    C.pptr.upload(C.h_pptr, s);
+    C.lfptr.upload(C.h_lfptr, s);
+    C.lfidx.upload(C.h_lfidx, s);
+    C.mptr.upload(C.h_mptr, s);
+    C.dptr.upload(C.h_dptr, s);
+    C.c1.upload(C.h_c1, s);
+    C.c2.upload(C.h_c2, s);
+    C.kind.upload(C.h_kind, s);
+    C.M.alloc(C.h_mptr[C.n]);
+    C.D.alloc(C.h_dptr[C.n]);
+    C.w.alloc(C.np);
+    C.ones.alloc(C.np);
+    C.u.alloc(C.np);
+    C.vol.alloc(C.n);
+    // contributors of each coarse flux: (cell, local index)
+    {
+      std::vector<int> fcell(2 * C.nf, -1), floc(2 * C.nf, -1);
+      for (int c = 0; c < C.n; ++c)
+        for (int q = C.h_lfptr[c]; q < C.h_lfptr[c + 1]; ++q) {
+          const int J = C.h_lfidx[q];
+          const int slot = (C.h_c1[J] == c) ? 0 : 1;
+          fcell[2 * J + slot] = c;
+          floc[2 * J + slot] = q - C.h_lfptr[c];
+        }
+      C.fcell.upload(fcell, s);
+      C.floc.upload(floc, s);
+    }
+    // ---- numeric buffers of the transfer
+    std::vector<int> Pptr(T.n_agg + 1, 0), Eptr(T.n_agg + 1, 0);
+    size_t maxA = 0;
+    size_t mx_nd = 0, mx_np = 0, mx_nI = 0, mx_k = 0;
+    for (int A = 0; A < T.n_agg; ++A) {
+      const int npA = (int)(plan.pd_ptr[A + 1] - plan.pd_ptr[A]);
+      const int nd = (int)(plan.dof_ptr[A + 1] - plan.dof_ptr[A]);
+      const int nI = plan.n_int[A];
+      const int k = C.h_lfptr[A + 1] - C.h_lfptr[A];
+      Pptr[A + 1] = Pptr[A] + npA * plan.mA[A];
+      Eptr[A + 1] = Eptr[A] + nI * k;
+      mx_nd = std::max<size_t>(mx_nd, nd);
+      mx_np = std::max<size_t>(mx_np, npA);
+      mx_nI = std::max<size_t>(mx_nI, nI);
+      mx_k = std::max<size_t>(mx_k, k);
+      (void)maxA;
+    }
+    // the Jacobi tournament keeps (n+1)/2 rotation pairs in shared arrays of kBlock+1 entries
+    require(mx_np <= 2 * kBlock, "aggregate with more than 512 pressure unknowns");
+    T.h_Pptr = Pptr;
+    T.h_Eptr = Eptr;
+    T.Pptr.upload(Pptr, s);
+    T.Eptr.upload(Eptr, s);
+    T.P.alloc(Pptr.back());
+    T.E.alloc(Eptr.back());
+    T.trace.alloc(tf.n_flux);
+    T.omega.alloc(tf.n_flux);
+    T.trace.zero(s);
+    T.omega.zero(s);
+    T.eig.alloc(tf.n_p());
+    // local view and per-level vectors of level l
+    LocalView lv;
+    const double *ones_l, *u_l, *vol_l;
+    if (l == 0) {
+      lv.level0 = 1;
+      lv.cfptr = f.cfptr.p;
+      lv.cfcode = f.cfcode.p;
+      lv.TKi = f.TKi.p;
+      lv.TLi = f.TLi.p;
+      ones_l = ones0.p;
+      u_l = f.vol.p;
+      vol_l = f.vol.p;
+    } else {
+      CoarseLevel& Fl = *h.coarse[l - 1];
+      lv = Fl.view();
+      ones_l = Fl.ones.p;
+      u_l = Fl.u.p;
+      vol_l = Fl.vol.p;
+    }
+    DVec<int> bad;
+    bad.alloc(4);
+    bad.zero(s);
+    PlanView pv = plan_view(T);
+    // ---- phase A: PV traces
+    int n_faces_c = 0;
+    while (n_faces_c < C.nf && C.h_kind[n_faces_c] != FK_BUBBLE) ++n_faces_c;
+    if (n_faces_c > 0) {
+      size_t mx_ns = 0, mx_npU = 0;
+      for (int J = 0; J < n_faces_c; ++J) {
+        const int A = C.h_c1[J], B = C.h_c2[J];
+        const size_t ns = plan.n_int[A] + (B >= 0 ? plan.n_int[B] : 0) + (plan.fgrp_ptr[J + 1] - plan.fgrp_ptr[J]);
+        const size_t npU = (plan.pd_ptr[A + 1] - plan.pd_ptr[A]) + (B >= 0 ? plan.pd_ptr[B + 1] - plan.pd_ptr[B] : 0);
+        mx_ns = std::max(mx_ns, ns);
+        mx_npU = std::max(mx_npU, npU);
+      }
+      ScratchA sa;
+      sa.mu = l == 0 ? mx_ns : mx_ns * mx_ns;
+      sa.du = mx_npU * mx_ns;
+      sa.t = mx_ns * mx_npU;
+      sa.l = mx_npU * mx_npU;
+      sa.y = mx_npU;
+      sa.total = sa.mu + sa.du + sa.t + sa.l + sa.y + 8;
+      const size_t slots = slots_for(sa.total, n_faces_c);
+      DVec<double> scr;
+      scr.alloc(slots * sa.total);
+      hipLaunchKernelGGL(k_pv_trace, dim3((unsigned)slots), dim3(kBlock), 0, s, lv, pv, n_faces_c, C.c1.p, C.c2.p,
+                         ones_l, T.trace.p, scr.p, sa, bad.p);
+      LAUNCHCHECK();
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    // ---- phase B: per aggregate
+    {
+      ScratchB sb;
+      sb.ma = l == 0 ? mx_nd : mx_nd * mx_nd;
+      sb.da = mx_np * mx_nd;
+      sb.ci = l == 0 ? 1 : mx_nI * mx_nI;
+      sb.t = std::max<size_t>(1, mx_nI * mx_np);
+      sb.l = mx_np * mx_np;
+      sb.v = mx_np * mx_np;
+      sb.pl = mx_nd * mx_k;
+      sb.tmp = std::max(mx_nd, mx_np + 8) * std::max<size_t>(mx_k, 1) + 8;
+      sb.vec = 3 * mx_np + std::max(mx_nd, mx_np) + 8;
+      sb.total = sb.ma + sb.da + sb.ci + sb.t + sb.l + sb.v + sb.pl + sb.tmp + sb.vec + 8;
+      const size_t slots = slots_for(sb.total, T.n_agg);
+      DVec<double> scr;
+      scr.alloc(slots * sb.total);
+      CoarseOut co;
+      co.lfptr = C.lfptr.p; co.lfidx = C.lfidx.p; co.c1 = C.c1.p; co.pptr = C.pptr.p; co.mptr = C.mptr.p;
+      co.dptr = C.dptr.p; co.M = C.M.p; co.D = C.D.p; co.w = C.w.p; co.ones = C.ones.p; co.u = C.u.p;
+      co.vol = C.vol.p;
+      hipLaunchKernelGGL(k_agg_setup, dim3((unsigned)slots), dim3(kBlock), 0, s, lv, pv, T.n_agg, ones_l, u_l, vol_l,
+                         T.trace.p, T.omega.p, T.Pptr.p, T.P.p, T.Eptr.p, T.E.p, T.eig.p, co, scr.p, sb, bad.p);
+      LAUNCHCHECK();
+      HIPCHECK(hipStreamSynchronize(s));
+    }
+    std::vector<int> hb = bad.download(s);
+    if (hb[0] != 0) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "local problem of the hierarchy setup is not positive definite (level %d, site %d, item %d, "
+                    "pivot %d, %d failures)", l, hb[1], hb[2], hb[3], hb[0]);
+      fail(SPFAS_ERR_INVALID, buf);
+    }
+    h.eigvals[l] = T.eig.download(s);
+    // ---- prolongation helpers
+    {
+      std::vector<int> pd_agg(plan.pd_list.size()), pd_row(plan.pd_list.size());
+      for (int A = 0; A < T.n_agg; ++A)
+        for (int64_t q = plan.pd_ptr[A]; q < plan.pd_ptr[A + 1]; ++q) { pd_agg[q] = A; pd_row[q] = (int)(q - plan.pd_ptr[A]); }
+      std::vector<int> int_agg, int_row, int_pos;
+      for (int A = 0; A < T.n_agg; ++A)
+        for (int r = 0; r < plan.n_int[A]; ++r) {
+          int_agg.push_back(A);
+          int_row.push_back(r);
+          int_pos.push_back((int)(plan.dof_ptr[A] + r));
+        }
+      std::vector<int> grp_of(tf.n_flux, -1);
+      for (int J = 0; J < C.nf; ++J)
+        for (int64_t q = plan.fgrp_ptr[J]; q < plan.fgrp_ptr[J + 1]; ++q) grp_of[plan.fgrp_list[q]] = J;
+      std::vector<int> bub0(T.n_agg, -1);
+      for (int J = C.nf - 1; J >= 0; --J)
+        if (C.h_kind[J] == FK_BUBBLE) bub0[C.h_c1[J]] = J;
+      T.pd_agg.upload(pd_agg, s);
+      T.pd_row.upload(pd_row, s);
+      T.int_agg.upload(int_agg, s);
+      T.int_row.upload(int_row, s);
+      T.int_pos.upload(int_pos, s);
+      T.grp_of.upload(grp_of, s);
+      T.bub0.upload(bub0, s);
+      T.n_int_total = (int)int_agg.size();
+    }
+    h.trans.push_back(std::move(tr));
+    h.coarse.push_back(std::move(cl));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  // hot-path work buffers and the hybridised solvers of the coarse levels
+  for (int l = 1; l < L; ++l) setup_coarse_solver(h, l);
+}
+
+}  // namespace spfas

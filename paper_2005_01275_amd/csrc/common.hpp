@@ -60,13 +60,21 @@ struct DVec {
   void zero(hipStream_t s) {
     if (n) HIPCHECK(hipMemsetAsync(p, 0, n * sizeof(T), s));
   }
+  // Uploads complete before returning: sources are often short-lived host
+  // temporaries in pageable memory.
   void upload(const std::vector<T>& v, hipStream_t s) {
     alloc(v.size());
-    if (n) HIPCHECK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+    if (n) {
+      HIPCHECK(hipMemcpyAsync(p, v.data(), n * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    }
   }
   void upload(const T* src, size_t count, hipStream_t s) {
     alloc(count);
-    if (n) HIPCHECK(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+    if (n) {
+      HIPCHECK(hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHECK(hipStreamSynchronize(s));
+    }
   }
   std::vector<T> download(hipStream_t s) const {
     std::vector<T> v(n);

@@ -7,6 +7,7 @@
 
 #include "coarse.hpp"
 #include "kern.hpp"
+#include "solve.hpp"
 #include "sparse.hpp"
 
 namespace spfas {
@@ -230,7 +231,8 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   fine.g.alloc(nf);
   fine.f.zero(s);
   fine.g.zero(s);
-  // ---------------- coarse levels
+  // ---------------- fine smoother (eliminated system and its AMG), coarse levels
+  setup_fine_solver(*this);
   setup_coarse_levels(*this);
   HIPCHECK(hipStreamSynchronize(s));
 }

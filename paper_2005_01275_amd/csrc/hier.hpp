@@ -36,6 +36,18 @@ struct FineDev {
   }
 };
 
+// Work space of the fine-level smoother: state, step, eliminated system
+// S dp = rhs (S shares the pattern of the cell->face lists), its AMG and
+// Krylov workspaces.
+struct FineWork {
+  DVec<double> x, dx, xt;                 // [nf + n]; xt holds r(x) in the V-cycle
+  DVec<double> div;                       // [n] D sigma (projection of bubbles)
+  DVec<double> Sdiag, Soff, rhs;          // S = D M^{-1} E, right-hand side
+  Amg amg;
+  Krylov kry;
+  CsrView S;
+};
+
 struct Hierarchy {
   hipStream_t stream = nullptr;
   bool host_only = false;
@@ -46,6 +58,7 @@ struct Hierarchy {
   std::vector<Topo> topo;                 // canonical topology per level
   std::vector<TransferPlan> plans;        // host plans l -> l+1
   FineDev fine;
+  FineWork fw;
   std::vector<std::unique_ptr<CoarseLevel>> coarse;   // levels 1..L-1
   std::vector<std::unique_ptr<TransferDev>> trans;    // transfers 0..L-2
   // host copies of hierarchy numbers for the parity hooks

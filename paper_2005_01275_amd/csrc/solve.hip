@@ -1,8 +1,384 @@
+// Nonlinear solvers (host control, device work): smoothing steps with the
+// step cap and Alg. 1 backtracking, single-level Picard/Newton (Section
+// 2.2) and the FAS V-cycle (Alg. 2).
 #include "solve.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <functional>
+
+#include "coarse_kern.hpp"
+#include "kern.hpp"
+
 namespace spfas {
-int run_solve(Hierarchy&, const spfas_problem&, const spfas_solve_opts&, double*, double*, bool, SolveKind,
-              spfas_stats&) {
-  fail(SPFAS_ERR_INVALID, "not built yet");
+
+// ------------------------------------------------------------------ small kernels
+
+__global__ void __launch_bounds__(kBlock) k_axpy(int64_t n, double a, const double* __restrict__ x,
+                                                 double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
 }
-void export_level_operator(const Hierarchy&, int, int, double*, size_t) { fail(SPFAS_ERR_INVALID, "not built yet"); }
+
+__global__ void __launch_bounds__(kBlock) k_neu_flux(int64_t nn, const double* __restrict__ area,
+                                                     const int* __restrict__ face, const double* __restrict__ gN,
+                                                     double* __restrict__ out) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nn) out[face[i]] = gN ? -area[i] * gN[face[i]] : 0.0;
 }
+
+void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  if (!n) return;
+  const int G = reduce_grid(n);
+  hipLaunchKernelGGL(k_axpy, dim3(G), dim3(kBlock), 0, s, n, a, x, y);
+  LAUNCHCHECK();
+}
+
+// ------------------------------------------------------------------ options
+
+struct Opts {
+  bool newton = true;
+  double rtol = 1e-8, atol = 1e-10;
+  int max_it = 50;
+  int bt_nmax = 4;
+  double bt_theta = 0.9;
+  double cap = 0.0;            // <= 0: off
+  int coarsest_max = 10;
+  double lin_rtol = 1e-8;
+  int lin_max_it = 500;
+};
+
+static Opts make_opts(const spfas_solve_opts& o, bool newton) {
+  Opts r;
+  r.newton = newton;
+  r.rtol = o.rtol;
+  r.atol = o.atol;
+  r.max_it = o.max_it;
+  r.bt_nmax = o.bt_nmax;
+  r.bt_theta = o.bt_theta;
+  r.cap = o.dp_cap;
+  r.coarsest_max = o.coarsest_max_steps;
+  r.lin_rtol = o.lin_rtol;
+  r.lin_max_it = o.lin_max_it;
+  require(r.max_it >= 0 && r.bt_nmax >= 0 && r.coarsest_max >= 0 && r.lin_max_it > 0, "negative iteration limits");
+  require(r.bt_theta > 0.0 && r.bt_theta <= 1.0, "bt_theta must be in (0, 1]");
+  require(r.rtol >= 0.0 && r.atol >= 0.0 && r.lin_rtol > 0.0, "tolerances must be non-negative");
+  return r;
+}
+
+// Alg. 1 on a residual-norm function of the step length.  Returns the step
+// taken and the residual norm there; `halvings` counts the halvings.
+static double backtrack(const std::function<double(double)>& rn, double r_x, int nmax, double theta, double& r_new,
+                        int& halvings) {
+  double s = 1.0;
+  int n = 0;
+  double r_s = rn(s);
+  while (r_s > r_x && n < nmax) {
+    const double r_half = rn(0.5 * s);
+    if (r_half > theta * r_s) break;
+    s *= 0.5;
+    ++n;
+    r_s = r_half;
+  }
+  r_new = r_s;
+  halvings += n;
+  return s;
+}
+
+static double check_finite(double v, const char* what) {
+  if (!std::isfinite(v)) fail(SPFAS_ERR_NUMERIC, std::string("non-finite ") + what);
+  return v;
+}
+
+// ------------------------------------------------------------------ fine level
+
+void setup_fine_solver(Hierarchy& h) {
+  FineWork& w = h.fw;
+  FineDev& f = h.fine;
+  hipStream_t s = h.stream;
+  const int64_t n = f.n, nf = f.nf;
+  w.x.alloc(nf + n);
+  w.dx.alloc(nf + n);
+  w.xt.alloc(nf + n);
+  w.div.alloc(n);
+  w.Sdiag.alloc(n);
+  w.Soff.alloc(f.cfcode.n);
+  w.rhs.alloc(n);
+  w.S.n = (int)n;
+  w.S.diag = w.Sdiag.p;
+  w.S.ptr = f.cfptr.p;
+  w.S.col = f.nb.p;
+  w.S.val = w.Soff.p;
+  // matrix of the aggregation: Picard at p = 0 (kappa = 1)
+  w.x.zero(s);
+  const double a = f.alpha;
+  f.alpha = 0.0;
+  launch_fine_linearize(f.view(), false, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
+  f.alpha = a;
+  HIPCHECK(hipStreamSynchronize(s));
+  w.amg.setup(w.S, s);
+}
+
+static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double step) {
+  const int G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.parts.p, h.stream);
+  return check_finite(std::sqrt(h.host_sum(h.parts.p, G)), "fine residual");
+}
+
+// One Picard or Newton step on level 0 (Section 3.3): solve the linearised
+// system (flux block eliminated exactly, M is diagonal on level 0), cap,
+// Alg. 1.  `r_x` = ||r(x)|| on entry; returns ||r|| after the step.
+static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& st) {
+  FineWork& w = h.fw;
+  FineDev& f = h.fine;
+  hipStream_t s = h.stream;
+  const int64_t n = f.n, nf = f.nf;
+  launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
+  w.amg.numeric(s);
+  double* dp = w.dx.p + nf;
+  int it;
+  if (o.newton)
+    it = w.kry.bicgstab(w.S, &w.amg, w.rhs.p, dp, o.lin_rtol, o.lin_max_it, s);
+  else
+    it = w.kry.pcg(w.S, &w.amg, w.rhs.p, dp, o.lin_rtol, o.lin_max_it, s);
+  st.lin_iters += it;
+  const int G = launch_fine_backsub(f.view(), o.newton, w.x.p, w.dx.p, h.parts.p, s);
+  const double mx = check_finite(h.host_max(h.parts.p, G), "Newton/Picard step");
+  const double scale = (o.cap > 0.0 && mx > o.cap) ? o.cap / mx : 1.0;
+  double r_new = r_x;
+  const double step = backtrack([&](double sl) { return fine_rnorm(h, w.x.p, w.dx.p, sl * scale); }, r_x,
+                                o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
+  launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
+  st.smoothing_steps++;
+  (void)n;
+  return r_new;
+}
+
+// ------------------------------------------------------------------ state I/O
+
+static void load_state(Hierarchy& h, const double* p, const double* sig, bool dev, bool given) {
+  FineDev& f = h.fine;
+  hipStream_t s = h.stream;
+  if (!given) {
+    h.fw.x.zero(s);
+    return;
+  }
+  DVec<double> pin, sin;
+  const double *pd = p, *sd = sig;
+  if (!dev) {
+    pin.upload(p, h.n_cells_in, s);
+    sin.upload(sig, h.n_faces_in, s);
+    pd = pin.p;
+    sd = sin.p;
+  }
+  launch_gather(f.nf, f.flux_in.p, sd, h.fw.x.p, s);
+  launch_gather(f.n, f.cell_in.p, pd, h.fw.x.p + f.nf, s);
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+static void store_state(Hierarchy& h, const spfas_problem& prob, double* p, double* sig, bool dev) {
+  FineDev& f = h.fine;
+  hipStream_t s = h.stream;
+  DVec<double> po, so, gn;
+  double *pd = p, *sd = sig;
+  if (!dev) {
+    po.alloc(h.n_cells_in);
+    so.alloc(h.n_faces_in);
+    pd = po.p;
+    sd = so.p;
+  }
+  const double* gN = prob.g_neumann;
+  if (gN && prob.mem == SPFAS_MEM_HOST) {
+    gn.upload(prob.g_neumann, h.n_faces_in, s);
+    gN = gn.p;
+  }
+  launch_scatter(f.nf, f.flux_in.p, h.fw.x.p, sd, s);
+  launch_scatter(f.n, f.cell_in.p, h.fw.x.p + f.nf, pd, s);
+  const int64_t nn = (int64_t)f.neu_in.n;
+  if (nn) {
+    hipLaunchKernelGGL(k_neu_flux, dim3(grid_for(nn, kBlock)), dim3(kBlock), 0, s, nn, f.neu_area.p, f.neu_in.p, gN,
+                       sd);
+    LAUNCHCHECK();
+  }
+  if (!dev) {
+    HIPCHECK(hipMemcpyAsync(p, pd, h.n_cells_in * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(sig, sd, h.n_faces_in * sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  HIPCHECK(hipStreamSynchronize(s));
+}
+
+// ------------------------------------------------------------------ drivers
+
+static int single_level(Hierarchy& h, const Opts& o, spfas_stats& st) {
+  double r = fine_rnorm(h, h.fw.x.p, nullptr, 0.0);
+  st.r0 = r;
+  const double tol = std::max(o.rtol * r, o.atol);
+  int rc = SPFAS_NOT_CONVERGED;
+  for (int it = 0;; ++it) {
+    if (r <= tol) { rc = SPFAS_OK; break; }
+    if (it >= o.max_it) break;
+    r = fine_smooth(h, o, r, st);
+    st.iterations++;
+  }
+  st.r_final = r;
+  return rc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_sub(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                                                double* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = a[i] - b[i];
+}
+
+static void launch_sub(int64_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_sub, dim3(reduce_grid(n)), dim3(kBlock), 0, s, n, a, b, out);
+  LAUNCHCHECK();
+}
+
+// ------------------------------------------------------------------ coarse levels
+
+static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* dx, double step) {
+  CoarseLevel& C = *h.coarse[l - 1];
+  const int G = launch_coarse_resid(C, h.fine.alpha, x, dx, step, C.b.p, nullptr, h.parts.p, h.stream);
+  return check_finite(std::sqrt(h.host_sum(h.parts.p, G)), "coarse residual");
+}
+
+// One Picard or Newton step on coarse level l (Section 3.3) with the linear
+// system solved by algebraic hybridisation (Section 3.4), the cap on the
+// aggregate-average pressure change and Alg. 1.
+static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfas_stats& st) {
+  CoarseLevel& C = *h.coarse[l - 1];
+  hipStream_t s = h.stream;
+  const double alpha = h.fine.alpha;
+  launch_coarse_resid(C, alpha, C.x.p, nullptr, 0.0, C.b.p, C.r.p, h.parts.p, s);
+  launch_coarse_local(C, alpha, o.newton, C.x.p, C.r.p, s);
+  if (C.nl > 0) {
+    launch_H_assemble(C, s);
+    C.amg.numeric(s);
+    int it;
+    if (o.newton)
+      it = C.kry.bicgstab(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol, o.lin_max_it, s);
+    else
+      it = C.kry.pcg(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol, o.lin_max_it, s);
+    st.lin_iters += it;
+  }
+  const int G = launch_coarse_backsub(C, C.lam.p, C.dx.p, h.parts.p, s);
+  const double mx = check_finite(h.host_max(h.parts.p, G), "coarse Newton/Picard step");
+  const double scale = (o.cap > 0.0 && mx > o.cap) ? o.cap / mx : 1.0;
+  double r_new = r_x;
+  const double step = backtrack([&](double sl) { return coarse_rnorm(h, l, C.x.p, C.dx.p, sl * scale); }, r_x,
+                                o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
+  launch_axpy(C.nf + C.np, step * scale, C.dx.p, C.x.p, s);
+  st.smoothing_steps++;
+  return r_new;
+}
+
+// Coarsest level: at most coarsest_max smoothing steps, stopping when the
+// level residual meets rtol (relative to its entry value) or atol.
+static void coarsest_solve(Hierarchy& h, int l, const Opts& o, spfas_stats& st) {
+  double r = coarse_rnorm(h, l, h.coarse[l - 1]->x.p, nullptr, 0.0);
+  const double tol = std::max(o.rtol * r, o.atol);
+  for (int i = 0; i < o.coarsest_max; ++i) {
+    if (r <= tol) break;
+    r = coarse_smooth(h, l, o, r, st);
+  }
+}
+
+// Alg. 2 on level l.  The state of level l lives in fw.x (l = 0) or
+// coarse[l-1]->x; its right-hand side in coarse[l-1]->b (level 0 uses
+// b^0 = -[g; f]).  Returns after pre-smoothing on level 0 when the fine
+// residual already meets stop_tol.
+static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, double stop_tol, bool& stopped) {
+  hipStream_t s = h.stream;
+  const int L = h.n_levels;
+  if (l == L - 1) {
+    coarsest_solve(h, l, o, st);
+    return;
+  }
+  FineWork& w = h.fw;
+  FineDev& f = h.fine;
+  const double alpha = f.alpha;
+  double* x = l == 0 ? w.x.p : h.coarse[l - 1]->x.p;
+  double* dx = l == 0 ? w.dx.p : h.coarse[l - 1]->dx.p;
+  double* r = l == 0 ? w.xt.p : h.coarse[l - 1]->r.p;
+  double* div = l == 0 ? w.div.p : h.coarse[l - 1]->div.p;
+  const int64_t nfl = l == 0 ? f.nf : h.coarse[l - 1]->nf;
+  const int64_t nl = l == 0 ? f.nf + f.n : h.coarse[l - 1]->nf + h.coarse[l - 1]->np;
+  // pre-smoothing
+  double r_x = l == 0 ? fine_rnorm(h, x, nullptr, 0.0) : coarse_rnorm(h, l, x, nullptr, 0.0);
+  double r_s = l == 0 ? fine_smooth(h, o, r_x, st) : coarse_smooth(h, l, o, r_x, st);
+  if (l == 0 && r_s <= stop_tol) {
+    stopped = true;
+    return;
+  }
+  // residual, projection and coarse right-hand side b^{l+1} = A^{l+1}(Q x) - R r^l
+  if (l == 0) {
+    launch_fine_resid(f.view(), x, nullptr, 0.0, r, h.parts.p, s);
+    launch_div_fine(f.n, f.cfptr.p, f.cfcode.p, x, div, s);
+  } else {
+    CoarseLevel& C = *h.coarse[l - 1];
+    launch_coarse_resid(C, alpha, x, nullptr, 0.0, C.b.p, r, h.parts.p, s);
+    launch_div_coarse(C, x, div, s);
+  }
+  CoarseLevel& Cc = *h.coarse[l];
+  TransferDev& T = *h.trans[l];
+  const int64_t nc = Cc.nf + Cc.np;
+  launch_project(T, Cc, x, div, Cc.x.p, s);
+  HIPCHECK(hipMemcpyAsync(Cc.x0.p, Cc.x.p, nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_restrict(T, Cc, r, Cc.b.p, s);
+  launch_coarse_resid(Cc, alpha, Cc.x.p, nullptr, 0.0, Cc.zeros.p, Cc.ax.p, h.parts.p, s);
+  launch_sub(nc, Cc.ax.p, Cc.b.p, Cc.b.p, s);
+  nonlinear_mg(h, l + 1, o, st, 0.0, stopped);
+  // coarse correction P(y - Q x) with Alg. 1 on level l
+  launch_sub(nc, Cc.x.p, Cc.x0.p, Cc.dx.p, s);
+  launch_prolong(T, Cc, Cc.dx.p, dx, s);
+  double r_new = r_s;
+  auto rn = [&](double sl) {
+    return l == 0 ? fine_rnorm(h, x, dx, sl) : coarse_rnorm(h, l, x, dx, sl);
+  };
+  const double step = backtrack(rn, r_s, o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
+  launch_axpy(nl, step, dx, x, s);
+  (void)nfl;
+  // post-smoothing
+  if (l == 0)
+    fine_smooth(h, o, r_new, st);
+  else
+    coarse_smooth(h, l, o, r_new, st);
+}
+
+int run_fas(Hierarchy& h, const Opts& o, spfas_stats& st) {
+  double r = fine_rnorm(h, h.fw.x.p, nullptr, 0.0);
+  st.r0 = r;
+  const double tol = std::max(o.rtol * r, o.atol);
+  int rc = SPFAS_NOT_CONVERGED;
+  for (int it = 0;; ++it) {
+    if (r <= tol) { rc = SPFAS_OK; break; }
+    if (it >= o.max_it) break;
+    bool stopped = false;
+    nonlinear_mg(h, 0, o, st, tol, stopped);
+    st.stopped_after_presmooth = stopped ? 1 : 0;
+    r = fine_rnorm(h, h.fw.x.p, nullptr, 0.0);
+    st.iterations++;
+  }
+  st.r_final = r;
+  return rc;
+}
+
+int run_solve(Hierarchy& h, const spfas_problem& prob, const spfas_solve_opts& so, double* p, double* sigma, bool dev,
+              SolveKind kind, spfas_stats& st) {
+  const bool newton = kind == SolveKind::NEWTON || (kind == SolveKind::FAS && so.smoother == SPFAS_NEWTON);
+  require(kind != SolveKind::FAS || so.smoother == SPFAS_NEWTON || so.smoother == SPFAS_PICARD,
+          "smoother must be SPFAS_NEWTON or SPFAS_PICARD");
+  Opts o = make_opts(so, newton);
+  h.set_problem(prob);
+  load_state(h, p, sigma, dev, so.x0_given != 0);
+  int rc;
+  if (kind == SolveKind::FAS && h.n_levels > 1)
+    rc = run_fas(h, o, st);
+  else
+    rc = single_level(h, o, st);
+  store_state(h, prob, p, sigma, dev);
+  return rc;
+}
+
+}  // namespace spfas

@@ -13,4 +13,7 @@ int run_solve(Hierarchy& h, const spfas_problem& prob, const spfas_solve_opts& o
 
 void export_level_operator(const Hierarchy& h, int level, int what, double* out, size_t count);
 
+// device work space of the fine smoother and the AMG of its eliminated system
+void setup_fine_solver(Hierarchy& h);
+
 }  // namespace spfas

@@ -1,0 +1,677 @@
+// Sparse linear solvers: SpMV, aggregation AMG, dense LU coarsest level,
+// PCG and BiCGStab with device-resident scalars (see sparse.hpp).
+#include "sparse.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "kern.hpp"
+
+namespace spfas {
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void __launch_bounds__(kBlock) k_spmv(CsrView A, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double acc = A.diag[i] * x[i];
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) acc += A.val[k] * x[A.col[k]];
+  y[i] = acc;
+}
+
+void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s) {
+  if (!A.n) return;
+  hipLaunchKernelGGL(k_spmv, dim3(grid_for(A.n, kBlock)), dim3(kBlock), 0, s, A, x, y);
+  LAUNCHCHECK();
+}
+
+// y = A x; parts = sum_i w_i y_i (w may be x itself or another vector)
+__global__ void __launch_bounds__(kBlock) k_spmv_dot(CsrView A, const double* __restrict__ x, double* __restrict__ y,
+                                                     const double* __restrict__ w, double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x) {
+    double a = A.diag[i] * x[i];
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+    y[i] = a;
+    acc += w[i] * a;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+// y = A x; parts0 = sum w0*y, parts1 = sum y*y
+__global__ void __launch_bounds__(kBlock) k_spmv_dot2(CsrView A, const double* __restrict__ x, double* __restrict__ y,
+                                                      const double* __restrict__ w0, double* __restrict__ parts0,
+                                                      double* __restrict__ parts1) {
+  __shared__ double sh[kBlock / 64];
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x) {
+    double a = A.diag[i] * x[i];
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+    y[i] = a;
+    a0 += w0[i] * a;
+    a1 += a * a;
+  }
+  a0 = block_sum(a0, sh);
+  a1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) { parts0[blockIdx.x] = a0; parts1[blockIdx.x] = a1; }
+}
+
+__global__ void __launch_bounds__(kBlock) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+                                                double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += a[i] * b[i];
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+// scal[slot] = sum of parts (fixed order)
+__global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ parts, int G, double* scal, int slot) {
+  __shared__ double sh[kBlock / 64];
+  double v = reduce_parts(parts, G, sh);
+  if (threadIdx.x == 0) scal[slot] = v;
+}
+
+// Krylov scalar slots
+enum { S_RZ0 = 0, S_RZ1, S_PQ, S_RR, S_RHO0, S_RHO1, S_RV, S_TS, S_TT, S_ALPHA, S_OMEGA, S_BB, S_NSLOT };
+
+// PCG: alpha = rz/pq; x += alpha p; r -= alpha q; parts = r.r
+__global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, const double* __restrict__ scal, int rz, double* __restrict__ x,
+                                                   double* __restrict__ r, const double* __restrict__ p,
+                                                   const double* __restrict__ q, double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  const double alpha = scal[rz] / scal[S_PQ];
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+// PCG: p = z + beta p with beta = rz_new / rz_old (beta = 0 on the first iteration)
+__global__ void __launch_bounds__(kBlock) k_pcg_p(int n, const double* __restrict__ scal, int rz_new, int rz_old,
+                                                  int first, const double* __restrict__ z, double* __restrict__ p) {
+  const double beta = first ? 0.0 : scal[rz_new] / scal[rz_old];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = z[i] + beta * p[i];
+}
+
+// BiCGStab: p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
+__global__ void __launch_bounds__(kBlock) k_bicg_p(int n, const double* __restrict__ scal, int rho, int rho_old,
+                                                   int first, const double* __restrict__ r, double* __restrict__ p,
+                                                   const double* __restrict__ v) {
+  double beta = 0.0, omega = 0.0;
+  if (!first) {
+    beta = (scal[rho] / scal[rho_old]) * (scal[S_ALPHA] / scal[S_OMEGA]);
+    omega = scal[S_OMEGA];
+  }
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = first ? r[i] : r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// alpha = rho / (rh.v); s = r - alpha v (into s); writes alpha to scal
+__global__ void __launch_bounds__(kBlock) k_bicg_s(int n, double* __restrict__ scal, int rho, const double* __restrict__ r,
+                                                   const double* __restrict__ v, double* __restrict__ s) {
+  const double alpha = scal[rho] / scal[S_RV];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) s[i] = r[i] - alpha * v[i];
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
+}
+
+// omega = (t.s)/(t.t); x += alpha y + omega z; r = s - omega t; parts = r.r
+__global__ void __launch_bounds__(kBlock) k_bicg_x(int n, const double* __restrict__ scal, double* __restrict__ x,
+                                                   const double* __restrict__ y, const double* __restrict__ z,
+                                                   double* __restrict__ r, const double* __restrict__ s,
+                                                   const double* __restrict__ t, double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  const double alpha = scal[S_ALPHA];
+  const double tt = scal[S_TT];
+  const double omega = tt > 0.0 ? scal[S_TS] / tt : 0.0;
+  double acc = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] += alpha * y[i] + omega * z[i];
+    const double ri = s[i] - omega * t[i];
+    r[i] = ri;
+    acc += ri * ri;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+__global__ void k_set_omega(double* scal) {
+  const double tt = scal[S_TT];
+  scal[S_OMEGA] = tt > 0.0 ? scal[S_TS] / tt : 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_zero(int n, double* __restrict__ b) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = 0.0;
+}
+
+// ------------------------------------------------------------------ AMG kernels
+
+__global__ void __launch_bounds__(kBlock) k_invd(CsrView A, double* __restrict__ invd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double s = 0.0;
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += fabs(A.val[k]);
+  const double d = fabs(A.diag[i]) + 0.5 * s;
+  invd[i] = d > 0.0 ? 1.0 / d : 0.0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_jacobi0(int n, const double* __restrict__ invd, const double* __restrict__ b,
+                                                    double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = invd[i] * b[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_jacobi(CsrView A, const double* __restrict__ invd, const double* __restrict__ b,
+                                                   const double* __restrict__ xin, double* __restrict__ xout) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double a = A.diag[i] * xin[i];
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * xin[A.col[k]];
+  xout[i] = xin[i] + invd[i] * (b[i] - a);
+}
+
+__global__ void __launch_bounds__(kBlock) k_resid_restrict(CsrView A, const double* __restrict__ b,
+                                                           const double* __restrict__ x, double* __restrict__ r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double a = A.diag[i] * x[i];
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+  r[i] = b[i] - a;
+}
+
+__global__ void __launch_bounds__(kBlock) k_restrict(int nc, const int* __restrict__ mptr, const int* __restrict__ mem,
+                                                     const double* __restrict__ r, double* __restrict__ bc) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  double s = 0.0;
+  for (int k = mptr[I]; k < mptr[I + 1]; ++k) s += r[mem[k]];
+  bc[I] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_prolong(int n, const int* __restrict__ agg, const double* __restrict__ xc,
+                                                    double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] += xc[agg[i]];
+}
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_off(int nnz, const int* __restrict__ gp, const int* __restrict__ gi,
+                                                         const double* __restrict__ fval, double* __restrict__ cval) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  double s = 0.0;
+  for (int k = gp[e]; k < gp[e + 1]; ++k) s += fval[gi[k]];
+  cval[e] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_diag(int nc, const int* __restrict__ gp, const int* __restrict__ gi,
+                                                          const double* __restrict__ fdiag,
+                                                          const double* __restrict__ fval, double* __restrict__ cdiag) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= nc) return;
+  double s = 0.0;
+  for (int k = gp[I]; k < gp[I + 1]; ++k) {
+    const int c = gi[k];
+    s += (c & 1) ? fval[c >> 1] : fdiag[c >> 1];
+  }
+  cdiag[I] = s;
+}
+
+// dense row-major copy of a small DIA+CSR matrix
+__global__ void __launch_bounds__(kBlock) k_dense_fill(CsrView A, double* __restrict__ M, int nd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  double* row = M + (size_t)i * nd;
+  for (int j = 0; j < nd; ++j) row[j] = 0.0;
+  row[i] = A.diag[i];
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) row[A.col[k]] += A.val[k];
+}
+
+// In-place inverse of a dense nd x nd row-major matrix by LU with partial
+// pivoting (one block), then column-by-column substitution into `inv`.
+// `M` is overwritten by the LU factors; flag[0] = 1 on a zero pivot.
+__global__ void __launch_bounds__(kBlock) k_dense_inverse(double* __restrict__ M, double* __restrict__ inv,
+                                                          int* __restrict__ piv, int nd, int* __restrict__ flag) {
+  __shared__ double sv[kBlock];
+  __shared__ int si[kBlock];
+  const int tid = threadIdx.x;
+  for (int k = 0; k < nd; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < nd; i += blockDim.x) {
+      const double a = fabs(M[(size_t)i * nd + k]);
+      if (a > best) { best = a; bi = i; }
+    }
+    sv[tid] = best;
+    si[tid] = bi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (tid < o) {
+        if (sv[tid + o] > sv[tid] || (sv[tid + o] == sv[tid] && si[tid + o] < si[tid])) {
+          sv[tid] = sv[tid + o];
+          si[tid] = si[tid + o];
+        }
+      }
+      __syncthreads();
+    }
+    const int p = si[0];
+    if (tid == 0) {
+      piv[k] = p;
+      if (!(sv[0] > 0.0)) flag[0] = 1;
+    }
+    if (p != k)
+      for (int j = tid; j < nd; j += blockDim.x) {
+        const double a = M[(size_t)k * nd + j];
+        M[(size_t)k * nd + j] = M[(size_t)p * nd + j];
+        M[(size_t)p * nd + j] = a;
+      }
+    __syncthreads();
+    const double pv = M[(size_t)k * nd + k];
+    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+    for (int i = k + 1 + tid; i < nd; i += blockDim.x) M[(size_t)i * nd + k] *= ipv;
+    __syncthreads();
+    const int rem = nd - k - 1;
+    for (int e = tid; e < rem * rem; e += blockDim.x) {
+      const int i = k + 1 + e / rem, j = k + 1 + e % rem;
+      M[(size_t)i * nd + j] -= M[(size_t)i * nd + k] * M[(size_t)k * nd + j];
+    }
+    __syncthreads();
+  }
+  // columns of the inverse: solve L U x = P e_c
+  for (int c = tid; c < nd; c += blockDim.x) {
+    // x = P e_c held in column c of inv (row-major, strided)
+    for (int i = 0; i < nd; ++i) inv[(size_t)i * nd + c] = (i == c) ? 1.0 : 0.0;
+    for (int k = 0; k < nd; ++k) {
+      const int p = piv[k];
+      if (p != k) {
+        const double a = inv[(size_t)k * nd + c];
+        inv[(size_t)k * nd + c] = inv[(size_t)p * nd + c];
+        inv[(size_t)p * nd + c] = a;
+      }
+    }
+    for (int i = 0; i < nd; ++i) {
+      double s = inv[(size_t)i * nd + c];
+      for (int j = 0; j < i; ++j) s -= M[(size_t)i * nd + j] * inv[(size_t)j * nd + c];
+      inv[(size_t)i * nd + c] = s;
+    }
+    for (int i = nd - 1; i >= 0; --i) {
+      double s = inv[(size_t)i * nd + c];
+      for (int j = i + 1; j < nd; ++j) s -= M[(size_t)i * nd + j] * inv[(size_t)j * nd + c];
+      const double d = M[(size_t)i * nd + i];
+      inv[(size_t)i * nd + c] = d != 0.0 ? s / d : 0.0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_dense_gemv(int nd, const double* __restrict__ inv, const double* __restrict__ b,
+                                                       double* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nd) return;
+  const double* row = inv + (size_t)i * nd;
+  double s = 0.0;
+  for (int j = 0; j < nd; ++j) s += row[j] * b[j];
+  x[i] = s;
+}
+
+// ------------------------------------------------------------------ AMG host
+
+namespace {
+
+struct HostCsr {
+  int n = 0;
+  std::vector<double> diag, val;
+  std::vector<int> ptr, col;
+};
+
+// Plain aggregation with symmetric strength |a_ij| >= theta sqrt(|a_ii a_jj|).
+int aggregate(const HostCsr& A, double theta, std::vector<int>& agg) {
+  const int n = A.n;
+  agg.assign(n, -1);
+  auto strong = [&](int i, int k) {
+    const int j = A.col[k];
+    if (j == i) return false;
+    const double d = std::sqrt(std::fabs(A.diag[i] * A.diag[j]));
+    return std::fabs(A.val[k]) >= theta * d && d > 0.0;
+  };
+  int nc = 0;
+  std::vector<char> phase1(n, 0);
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool ok = true;
+    bool any = false;
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (strong(i, k)) {
+        any = true;
+        if (agg[A.col[k]] >= 0) { ok = false; break; }
+      }
+    if (!ok || !any) continue;
+    agg[i] = nc;
+    phase1[i] = 1;
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (strong(i, k)) { agg[A.col[k]] = nc; phase1[A.col[k]] = 1; }
+    ++nc;
+  }
+  std::vector<int> agg1(agg);
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    double best = -1.0;
+    int bj = -1;
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      if (strong(i, k) && phase1[j] && std::fabs(A.val[k]) > best) { best = std::fabs(A.val[k]); bj = j; }
+    }
+    if (bj >= 0) agg[i] = agg1[bj];
+  }
+  for (int i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    agg[i] = nc;
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      if (strong(i, k) && agg[j] < 0) agg[j] = nc;
+    }
+    ++nc;
+  }
+  return nc;
+}
+
+}  // namespace
+
+void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
+  lv.clear();
+  lv.reserve(32);
+  lv.emplace_back();
+  lv[0].n = A0.n;
+  lv[0].view = A0;
+  HostCsr H;
+  H.n = A0.n;
+  H.diag.resize(A0.n);
+  H.ptr.resize(A0.n + 1);
+  HIPCHECK(hipMemcpyAsync(H.diag.data(), A0.diag, A0.n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipMemcpyAsync(H.ptr.data(), A0.ptr, (A0.n + 1) * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHECK(hipStreamSynchronize(s));
+  const int nnz0 = H.ptr[A0.n];
+  H.col.resize(nnz0);
+  H.val.resize(nnz0);
+  if (nnz0) {
+    HIPCHECK(hipMemcpyAsync(H.col.data(), A0.col, nnz0 * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(H.val.data(), A0.val, nnz0 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+  }
+  while (H.n > dense_max) {
+    std::vector<int> agg;
+    const int nc = aggregate(H, 0.08, agg);
+    if (nc >= H.n || nc * 10 > H.n * 9) break;   // coarsening stalled
+    AmgLevel& F = lv.back();
+    // members
+    std::vector<int> mptr(nc + 1, 0), mem(H.n);
+    for (int i = 0; i < H.n; ++i) mptr[agg[i] + 1]++;
+    for (int I = 0; I < nc; ++I) mptr[I + 1] += mptr[I];
+    {
+      std::vector<int> fill(mptr.begin(), mptr.end() - 1);
+      for (int i = 0; i < H.n; ++i) mem[fill[agg[i]]++] = i;
+    }
+    // coarse pattern and contributor lists
+    HostCsr C;
+    C.n = nc;
+    C.diag.assign(nc, 0.0);
+    C.ptr.assign(nc + 1, 0);
+    std::vector<std::vector<std::pair<int, int>>> rows(nc);   // (J, fine off index)
+    std::vector<std::vector<int>> dg(nc);                     // encoded diag contributors
+    for (int I = 0; I < nc; ++I)
+      for (int q = mptr[I]; q < mptr[I + 1]; ++q) {
+        const int i = mem[q];
+        dg[I].push_back(i << 1);
+        C.diag[I] += H.diag[i];
+        for (int k = H.ptr[i]; k < H.ptr[i + 1]; ++k) {
+          const int J = agg[H.col[k]];
+          if (J == I) {
+            dg[I].push_back((k << 1) | 1);
+            C.diag[I] += H.val[k];
+          } else {
+            rows[I].emplace_back(J, k);
+          }
+        }
+      }
+    std::vector<int> gptr(1, 0), gidx;
+    for (int I = 0; I < nc; ++I) {
+      auto& r = rows[I];
+      std::stable_sort(r.begin(), r.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
+        return a.first < b.first;
+      });
+      size_t q = 0;
+      while (q < r.size()) {
+        const int J = r[q].first;
+        double v = 0.0;
+        while (q < r.size() && r[q].first == J) {
+          gidx.push_back(r[q].second);
+          v += H.val[r[q].second];
+          ++q;
+        }
+        C.col.push_back(J);
+        C.val.push_back(v);
+        gptr.push_back((int)gidx.size());
+      }
+      C.ptr[I + 1] = (int)C.col.size();
+    }
+    std::vector<int> gdptr(1, 0), gdidx;
+    for (int I = 0; I < nc; ++I) {
+      for (int c : dg[I]) gdidx.push_back(c);
+      gdptr.push_back((int)gdidx.size());
+    }
+    F.agg.upload(agg, s);
+    F.mptr.upload(mptr, s);
+    F.mem.upload(mem, s);
+    F.goff_ptr.upload(gptr, s);
+    F.goff_idx.upload(gidx, s);
+    F.gdiag_ptr.upload(gdptr, s);
+    F.gdiag_idx.upload(gdidx, s);
+    lv.emplace_back();
+    AmgLevel& Cl = lv.back();
+    Cl.n = nc;
+    Cl.diag.alloc(nc);
+    Cl.ptr.upload(C.ptr, s);
+    Cl.col.upload(C.col, s);
+    Cl.val.alloc(C.col.size());
+    Cl.view.n = nc;
+    Cl.view.diag = Cl.diag.p;
+    Cl.view.ptr = Cl.ptr.p;
+    Cl.view.col = Cl.col.p;
+    Cl.view.val = Cl.val.p;
+    HIPCHECK(hipStreamSynchronize(s));
+    H = std::move(C);
+  }
+  nd = lv.back().n;
+  require(nd <= 4096, "AMG coarsening stalled above the dense limit");
+  lu.alloc((size_t)nd * nd);
+  for (auto& L : lv) {
+    L.invd.alloc(L.n);
+    L.x.alloc(L.n);
+    L.b.alloc(L.n);
+    L.r.alloc(L.n);
+    L.t.alloc(L.n);
+  }
+  lv.back().t.alloc((size_t)nd * nd);   // dense inverse of the coarsest matrix
+  piv.alloc(nd);
+  flag.alloc(1);
+}
+
+void Amg::numeric(hipStream_t s) {
+  for (size_t k = 0; k + 1 < lv.size(); ++k) {
+    AmgLevel& F = lv[k];
+    AmgLevel& C = lv[k + 1];
+    const int nnz = (int)C.val.n;
+    if (nnz) {
+      hipLaunchKernelGGL(k_galerkin_off, dim3(grid_for(nnz, kBlock)), dim3(kBlock), 0, s, nnz, F.goff_ptr.p,
+                         F.goff_idx.p, F.view.val, C.val.p);
+      LAUNCHCHECK();
+    }
+    hipLaunchKernelGGL(k_galerkin_diag, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.gdiag_ptr.p,
+                       F.gdiag_idx.p, F.view.diag, F.view.val, C.diag.p);
+    LAUNCHCHECK();
+  }
+  for (auto& L : lv) {
+    hipLaunchKernelGGL(k_invd, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.view, L.invd.p);
+    LAUNCHCHECK();
+  }
+  AmgLevel& Lc = lv.back();
+  hipLaunchKernelGGL(k_dense_fill, dim3(grid_for(nd, kBlock)), dim3(kBlock), 0, s, Lc.view, lu.p, nd);
+  LAUNCHCHECK();
+  flag.zero(s);
+  hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(kBlock), 0, s, lu.p, Lc.t.p, piv.p, nd, flag.p);
+  LAUNCHCHECK();
+}
+
+void Amg::apply(const double* b, double* x, hipStream_t s) {
+  // level 0 uses the caller's b and x
+  const int L = (int)lv.size();
+  const double* bl = b;
+  double* xl = x;
+  for (int k = 0; k < L - 1; ++k) {
+    AmgLevel& F = lv[k];
+    AmgLevel& C = lv[k + 1];
+    const int n = F.n;
+    const unsigned g = grid_for(n, kBlock);
+    // pre-smoothing: two Jacobi sweeps from zero
+    hipLaunchKernelGGL(k_jacobi0, dim3(g), dim3(kBlock), 0, s, n, F.invd.p, bl, F.t.p);
+    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl);
+    hipLaunchKernelGGL(k_resid_restrict, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
+    hipLaunchKernelGGL(k_restrict, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.mptr.p, F.mem.p, F.r.p,
+                       C.b.p);
+    LAUNCHCHECK();
+    bl = C.b.p;
+    xl = C.x.p;
+  }
+  AmgLevel& Lc = lv.back();
+  hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock)), dim3(kBlock), 0, s, nd, Lc.t.p, bl, xl);
+  LAUNCHCHECK();
+  for (int k = L - 2; k >= 0; --k) {
+    AmgLevel& F = lv[k];
+    AmgLevel& C = lv[k + 1];
+    const int n = F.n;
+    const unsigned g = grid_for(n, kBlock);
+    double* xf = (k == 0) ? x : F.x.p;
+    const double* bf = (k == 0) ? b : F.b.p;
+    hipLaunchKernelGGL(k_prolong, dim3(g), dim3(kBlock), 0, s, n, F.agg.p, C.x.p, xf);
+    // post-smoothing: two Jacobi sweeps (ping-pong through t)
+    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p);
+    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf);
+    LAUNCHCHECK();
+  }
+}
+
+// ------------------------------------------------------------------ Krylov
+
+Krylov::~Krylov() {
+  if (hscal) (void)hipHostFree(hscal);
+}
+
+void Krylov::alloc(int n_) {
+  if (n == n_ && hscal) return;
+  n = n_;
+  r.alloc(n); z.alloc(n); p.alloc(n); q.alloc(n); rh.alloc(n); v.alloc(n); s.alloc(n); t.alloc(n); y.alloc(n);
+  w.alloc(n);
+  parts.alloc(kMaxParts * 3);
+  scal.alloc(S_NSLOT);
+  if (!hscal) HIPCHECK(hipHostMalloc((void**)&hscal, S_NSLOT * sizeof(double), hipHostMallocDefault));
+}
+
+static double read_slot(double* hscal, const double* scal, int slot, hipStream_t st) {
+  HIPCHECK(hipMemcpyAsync(hscal + slot, scal + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  return hscal[slot];
+}
+
+int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st) {
+  alloc(A.n);
+  const int G = reduce_grid(n);
+  const unsigned g1 = grid_for(n, kBlock);
+  double* P0 = parts.p;
+  hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+  hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
+  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, P0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
+  LAUNCHCHECK();
+  const double bb = read_slot(hscal, scal.p, S_BB, st);
+  if (!(bb > 0.0)) return 0;
+  const double tol2 = rtol * rtol * bb;
+  int it = 0;
+  int cur = S_RZ0, old = S_RZ1;
+  for (; it < maxit; ++it) {
+    if (M) M->apply(r.p, z.p, st);
+    else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p, P0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
+    hipLaunchKernelGGL(k_pcg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
+    hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_PQ);
+    hipLaunchKernelGGL(k_pcg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, x, r.p, p.p, q.p, P0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
+    LAUNCHCHECK();
+    std::swap(cur, old);
+    const double rr = read_slot(hscal, scal.p, S_RR, st);
+    if (!std::isfinite(rr)) fail(SPFAS_ERR_NUMERIC, "non-finite residual in PCG");
+    if (rr <= tol2) { ++it; break; }
+  }
+  (void)g1;
+  iters += it;
+  return it;
+}
+
+int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st) {
+  alloc(A.n);
+  const int G = reduce_grid(n);
+  double* P0 = parts.p;
+  double* P1 = parts.p + kMaxParts;
+  hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+  hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
+  hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, rh.p);
+  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, P0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
+  LAUNCHCHECK();
+  const double bb = read_slot(hscal, scal.p, S_BB, st);
+  if (!(bb > 0.0)) return 0;
+  const double tol2 = rtol * rtol * bb;
+  int it = 0;
+  int cur = S_RHO0, old = S_RHO1;
+  for (; it < maxit; ++it) {
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, rh.p, r.p, P0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
+    hipLaunchKernelGGL(k_bicg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, r.p, p.p, v.p);
+    LAUNCHCHECK();
+    if (M) M->apply(p.p, y.p, st);
+    else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, p.p, y.p);
+    hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RV);
+    hipLaunchKernelGGL(k_bicg_s, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, r.p, v.p, s.p);
+    LAUNCHCHECK();
+    if (M) M->apply(s.p, z.p, st);
+    else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
+    hipLaunchKernelGGL(k_spmv_dot2, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_TS);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P1, G, scal.p, (int)S_TT);
+    hipLaunchKernelGGL(k_bicg_x, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, P0);
+    hipLaunchKernelGGL(k_set_omega, dim3(1), dim3(1), 0, st, scal.p);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
+    LAUNCHCHECK();
+    std::swap(cur, old);
+    const double rr = read_slot(hscal, scal.p, S_RR, st);
+    if (!std::isfinite(rr)) fail(SPFAS_ERR_NUMERIC, "non-finite residual in BiCGStab");
+    if (rr <= tol2) { ++it; break; }
+  }
+  iters += it;
+  return it;
+}
+
+}  // namespace spfas

@@ -1,4 +1,82 @@
+// Linear solvers for the linearised systems of the smoothers: the fine-level
+// eliminated system S dp = rhs (Section 3.4 reduced by the diagonal flux
+// block) and the hybridised multiplier system H lambda = xi on coarse
+// levels (Section 3.4, algebraic hybridisation).
+//
+// Matrix format ("DIA+CSR"): diagonal in its own array plus the
+// off-diagonal entries in CSR (ptr/col/val).  The pattern is fixed at setup;
+// values are rewritten by each linearisation.
+//
+// Preconditioner: unsmoothed-aggregation AMG.  Aggregates come from the
+// strength of connection of the matrix values at setup (kappa = 1, Picard);
+// coarse values are recomputed on the device after every linearisation as
+// fixed-order sums of fine entries (P^T A P with piecewise-constant P), the
+// coarsest level is factored by dense LU with partial pivoting.  Smoother:
+// Jacobi with weights 1 / (|a_ii| + 0.5 sum_j |a_ij|).
+//
+// Krylov: PCG (symmetric Picard systems) and BiCGStab (Newton systems); all
+// scalars stay on the device, the host reads the residual norm once per
+// iteration to stop.
 #pragma once
+
+#include <vector>
+
+#include "common.hpp"
+
 namespace spfas {
-struct SparseSolver {};
-}
+
+struct CsrView {
+  int n = 0;
+  const double* diag = nullptr;
+  const int* ptr = nullptr;
+  const int* col = nullptr;
+  const double* val = nullptr;
+};
+
+struct AmgLevel {
+  int n = 0;
+  // matrix (level 0 refers to external storage through `view`)
+  DVec<double> diag, val;
+  DVec<int> ptr, col;
+  CsrView view;
+  DVec<double> invd;                  // smoother weights
+  // aggregation to the next level
+  DVec<int> agg;                      // [n]
+  DVec<int> mptr, mem;                // members of each coarse node
+  // Galerkin contributors of the next level's entries
+  DVec<int> goff_ptr, goff_idx;       // coarse off entry -> fine off indices
+  DVec<int> gdiag_ptr, gdiag_idx;     // coarse diag -> (idx << 1 | is_off)
+  DVec<double> x, b, r, t;            // work vectors
+};
+
+struct Amg {
+  std::vector<AmgLevel> lv;           // lv[0] is the fine matrix
+  int nd = 0;                         // dense coarsest size
+  DVec<double> lu;                    // [nd*nd]
+  DVec<int> piv;                      // [nd]
+  DVec<int> flag;                     // singular-pivot flag
+  int cycles = 1;
+  // host setup from the matrix pattern and setup values
+  void setup(const CsrView& A0, hipStream_t s, int dense_max = 256);
+  void numeric(hipStream_t s);        // coarse values, weights, dense LU
+  void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
+  int n_levels() const { return (int)lv.size(); }
+};
+
+struct Krylov {
+  int n = 0;
+  DVec<double> r, z, p, q, rh, v, s, t, y, w;
+  DVec<double> parts, scal;
+  double* hscal = nullptr;
+  int iters = 0;
+  ~Krylov();
+  void alloc(int n_);
+  // returns the number of iterations; x is overwritten (zero initial guess)
+  int pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st);
+  int bicgstab(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st);
+};
+
+// y = A x
+void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s);
+
+}  // namespace spfas
