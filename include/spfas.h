@@ -264,6 +264,29 @@ typedef enum {
 int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t what, double* out,
                              size_t count);
 
+/* ------------------------------------------------------------------ measurement
+ * Kernel timing with HIP events recorded on the stream of the solve calls.
+ * Each instrumented launch is bracketed by two events; `algo_bytes` is the
+ * algorithmic HBM traffic of the launches (the minimum the method moves:
+ * per flux unknown F and cell N of level 0, residual 40F + 24N, Newton
+ * linearisation 56F + 24N, S x 24F + 24N, one Jacobi sweep 24F + 40N).
+ */
+typedef enum {
+  SPFAS_PROF_FINE_RESID = 0,      /* fine residual, also inside Alg. 1 trials   */
+  SPFAS_PROF_FINE_LINEARIZE = 1,  /* S = D M^{-1} E and its right-hand side      */
+  SPFAS_PROF_FINE_SPMV = 2,       /* S x inside the fine-level Krylov solver     */
+  SPFAS_PROF_FINE_SMOOTH = 3,     /* Jacobi sweeps on the finest AMG level       */
+  SPFAS_PROF_COUNT = 4
+} spfas_prof_kernel;
+
+/* Turns the timing on (nonzero) or off and clears the counters. */
+int spfas_profile_enable(spfas_hierarchy* h, int32_t enable);
+
+/* Totals since the last enable: number of launches, summed event time in
+ * milliseconds and summed algorithmic bytes.  Synchronises the stream. */
+int spfas_profile_read(spfas_hierarchy* h, int32_t which, int64_t* launches, double* total_ms,
+                       double* algo_bytes);
+
 /* Releases every resource of the handle (NULL is allowed). */
 void spfas_destroy(spfas_hierarchy* h);
 

@@ -164,3 +164,24 @@ class FineSystem:
         np.add.at(div, self.K, -sigma)
         np.add.at(div, self.L[self.inner], sigma[self.inner])
         return r_sig, div + self.f
+
+
+def linear_pressure(prob):
+    """Pressure of the linear problem (kappa = 1) from the reduced cell
+    system of the remark after eq. FV_matrix: eliminating sigma with the
+    diagonal M gives D M^{-1} D^T p = f - D M^{-1} g (sign of g as it follows
+    from the first block row M sigma + D^T p = -g).  Sparse direct solve."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    fs = FineSystem(prob)
+    n = fs.n_cells
+    w = 1.0 / (1.0 / fs.TK + np.where(fs.inner, 1.0 / np.where(fs.inner, fs.TL, 1.0), 0.0))
+    K, L, inner = fs.K, fs.L, fs.inner
+    rows = np.concatenate([K, L[inner], K[inner], L[inner]])
+    cols = np.concatenate([K, L[inner], L[inner], K[inner]])
+    vals = np.concatenate([w, w[inner], -w[inner], -w[inner]])
+    S = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    # D M^{-1} g: Dirichlet faces carry g on the K side with D = -1
+    dmg = np.zeros(n)
+    np.add.at(dmg, K[~inner], -w[~inner] * fs.g[~inner])
+    return spla.spsolve(S.tocsc(), fs.f - dmg)

@@ -204,6 +204,18 @@ class Hierarchy:
                                               fo.ctypes.data_as(C.POINTER(C.c_int32))))
         return co, fo
 
+    def profile_enable(self, on=True):
+        N.check(N.lib().spfas_profile_enable(self.h, int(on)))
+
+    def profile_read(self):
+        """{kernel name: (launches, total ms, algorithmic bytes)}"""
+        out = {}
+        for k, name in N.PROF_NAMES.items():
+            a, b, c = C.c_int64(), C.c_double(), C.c_double()
+            N.check(N.lib().spfas_profile_read(self.h, k, C.byref(a), C.byref(b), C.byref(c)))
+            out[name] = (a.value, b.value, c.value)
+        return out
+
     def level_operator(self, level, what, count):
         out = np.zeros(count)
         N.check(N.lib().spfas_get_level_operator(self.h, level, what, _dptr(out), count))

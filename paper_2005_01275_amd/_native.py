@@ -18,7 +18,10 @@ SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SP
 EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solve", "spfas_picard_solve",
             "spfas_newton_solve", "spfas_eval_residual", "spfas_level_sizes", "spfas_get_aggregation",
             "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
-            "spfas_version"]
+            "spfas_version", "spfas_profile_enable", "spfas_profile_read"]
+SPFAS_PROF_FINE_RESID, SPFAS_PROF_FINE_LINEARIZE, SPFAS_PROF_FINE_SPMV, SPFAS_PROF_FINE_SMOOTH = range(4)
+PROF_NAMES = {SPFAS_PROF_FINE_RESID: "fine_residual", SPFAS_PROF_FINE_LINEARIZE: "fine_linearize",
+              SPFAS_PROF_FINE_SPMV: "fine_spmv", SPFAS_PROF_FINE_SMOOTH: "fine_jacobi"}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
@@ -99,6 +102,11 @@ def lib():
     L.spfas_last_error.restype = C.c_char_p
     L.spfas_version.argtypes = []
     L.spfas_version.restype = C.c_int
+    L.spfas_profile_enable.argtypes = [vp, C.c_int32]
+    L.spfas_profile_enable.restype = C.c_int
+    L.spfas_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+    L.spfas_profile_read.restype = C.c_int
     _lib = L
     return L
 

@@ -176,4 +176,25 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
   });
 }
 
+int spfas_profile_enable(spfas_hierarchy* h, int32_t enable) {
+  return guarded([&] {
+    need_device(h);
+    h->h.prof.reset();
+    h->h.prof.on = enable != 0;
+    return SPFAS_OK;
+  });
+}
+
+int spfas_profile_read(spfas_hierarchy* h, int32_t which, int64_t* launches, double* total_ms, double* algo_bytes) {
+  return guarded([&] {
+    need_device(h);
+    require(which >= 0 && which < SPFAS_PROF_COUNT, "unknown kernel id");
+    h->h.prof.collect();
+    if (launches) *launches = h->h.prof.launches[which];
+    if (total_ms) *total_ms = h->h.prof.ms[which];
+    if (algo_bytes) *algo_bytes = h->h.prof.bytes[which];
+    return SPFAS_OK;
+  });
+}
+
 }  // extern "C"

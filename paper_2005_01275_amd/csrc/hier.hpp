@@ -11,6 +11,7 @@
 #include "common.hpp"
 #include "fine.hpp"
 #include "sparse.hpp"
+#include "prof.hpp"
 #include "topo.hpp"
 
 namespace spfas {
@@ -67,6 +68,7 @@ struct Hierarchy {
   DVec<double> parts;
   double* hpin = nullptr;                  // pinned host scalars
   int launches = 0;
+  KernelProf prof;                         // event timing of instrumented kernels
 
   ~Hierarchy();
   void setup(const spfas_mesh& mesh, const spfas_coarsen_opts& o);

@@ -117,10 +117,22 @@ void setup_fine_solver(Hierarchy& h) {
   f.alpha = a;
   HIPCHECK(hipStreamSynchronize(s));
   w.amg.setup(w.S, s);
+  // event timing hooks of the finest-level Krylov SpMV and Jacobi sweeps
+  ProfHook hk;
+  hk.prof = &h.prof;
+  hk.spmv_id = SPFAS_PROF_FINE_SPMV;
+  hk.smooth_id = SPFAS_PROF_FINE_SMOOTH;
+  hk.spmv_bytes = 24.0 * nf + 24.0 * n;
+  hk.smooth_bytes = 24.0 * nf + 40.0 * n;
+  w.kry.hook = hk;
+  w.amg.hook = hk;
 }
 
 static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double step) {
-  const int G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.parts.p, h.stream);
+  int G = 0;
+  const double bytes = 40.0 * h.fine.nf + 24.0 * h.fine.n;
+  h.prof.run(SPFAS_PROF_FINE_RESID, bytes, h.stream,
+             [&] { G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.parts.p, h.stream); });
   return check_finite(std::sqrt(h.host_sum(h.parts.p, G)), "fine residual");
 }
 
@@ -132,7 +144,8 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   FineDev& f = h.fine;
   hipStream_t s = h.stream;
   const int64_t n = f.n, nf = f.nf;
-  launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
+  h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 56.0 * nf + 24.0 * n, s,
+             [&] { launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s); });
   w.amg.numeric(s);
   double* dp = w.dx.p + nf;
   int it;

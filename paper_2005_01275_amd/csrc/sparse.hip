@@ -7,10 +7,17 @@
 #include <numeric>
 
 #include "kern.hpp"
+#include "prof.hpp"
 
 namespace spfas {
 
 // ------------------------------------------------------------------ kernels
+
+template <class F>
+static void timed(KernelProf* prof, int id, double bytes, hipStream_t s, F&& fn) {
+  if (prof) prof->run(id, bytes, s, fn);
+  else fn();
+}
 
 __global__ void __launch_bounds__(kBlock) k_spmv(CsrView A, const double* __restrict__ x, double* __restrict__ y) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -545,7 +552,8 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
     const unsigned g = grid_for(n, kBlock);
     // pre-smoothing: two Jacobi sweeps from zero
     hipLaunchKernelGGL(k_jacobi0, dim3(g), dim3(kBlock), 0, s, n, F.invd.p, bl, F.t.p);
-    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl);
+    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s,
+          [&] { hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl); });
     hipLaunchKernelGGL(k_resid_restrict, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
     hipLaunchKernelGGL(k_restrict, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.mptr.p, F.mem.p, F.r.p,
                        C.b.p);
@@ -565,8 +573,10 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
     const double* bf = (k == 0) ? b : F.b.p;
     hipLaunchKernelGGL(k_prolong, dim3(g), dim3(kBlock), 0, s, n, F.agg.p, C.x.p, xf);
     // post-smoothing: two Jacobi sweeps (ping-pong through t)
-    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p);
-    hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf);
+    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s,
+          [&] { hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p); });
+    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s,
+          [&] { hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf); });
     LAUNCHCHECK();
   }
 }
@@ -614,7 +624,8 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p, P0);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
     hipLaunchKernelGGL(k_pcg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
-    hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0);
+    timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
+          [&] { hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_PQ);
     hipLaunchKernelGGL(k_pcg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, x, r.p, p.p, q.p, P0);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
@@ -652,13 +663,15 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     LAUNCHCHECK();
     if (M) M->apply(p.p, y.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, p.p, y.p);
-    hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0);
+    timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
+          [&] { hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RV);
     hipLaunchKernelGGL(k_bicg_s, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, r.p, v.p, s.p);
     LAUNCHCHECK();
     if (M) M->apply(s.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
-    hipLaunchKernelGGL(k_spmv_dot2, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);
+    timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
+          [&] { hipLaunchKernelGGL(k_spmv_dot2, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_TS);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P1, G, scal.p, (int)S_TT);
     hipLaunchKernelGGL(k_bicg_x, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, P0);

@@ -49,8 +49,17 @@ struct AmgLevel {
   DVec<double> x, b, r, t;            // work vectors
 };
 
+struct KernelProf;
+// Optional event timing of the finest-level SpMV and smoothing launches.
+struct ProfHook {
+  KernelProf* prof = nullptr;
+  int spmv_id = -1, smooth_id = -1;
+  double spmv_bytes = 0.0, smooth_bytes = 0.0;
+};
+
 struct Amg {
   std::vector<AmgLevel> lv;           // lv[0] is the fine matrix
+  ProfHook hook;
   int nd = 0;                         // dense coarsest size
   DVec<double> lu;                    // [nd*nd]
   DVec<int> piv;                      // [nd]
@@ -65,6 +74,7 @@ struct Amg {
 
 struct Krylov {
   int n = 0;
+  ProfHook hook;
   DVec<double> r, z, p, q, rh, v, s, t, y, w;
   DVec<double> parts, scal;
   double* hscal = nullptr;

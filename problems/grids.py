@@ -245,11 +245,11 @@ def c1_problem(seed: int = 0) -> Problem:
                    box=(4, 4), m=2, n_levels=2, dp_cap_c=5.0)
 
 
-# Total well rate of the 60x220x85 workload.  Chosen so that the linear
-# (kappa = 1) pressure has max |p| of about 0.5 (stronger sinks can leave the
-# exp(p) problem without a solution); the calibration script
-# tests/golden/calibrate_c2_rate.py recomputes the figure.
-C2_WELL_RATE = 1.0
+# Total well rate of the 60x220x85 workload (seed 0).  Chosen so that the
+# linear (kappa = 1) pressure has max |p| = 0.5 (stronger sinks can leave the
+# exp(p) problem without a solution); written by the calibration script
+# tests/golden/calibrate_c2_rate.py (stored in tests/golden/c2_rate.json).
+C2_WELL_RATE = 0.033890383672807535
 
 
 def c2_problem(seed: int = 0, rate: Optional[float] = None, permute: bool = True,

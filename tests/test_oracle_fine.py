@@ -260,3 +260,25 @@ def test_c1_fas_matches_result_oracle():
         x, st = fas_solve(h, Opts(newton=newton, rtol=1e-13, atol=0.0, max_it=100))
         assert st.converged
         assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_reduced_linear_form():
+    """alpha = 0: the mixed-form root equals the reduced cell system of the
+    remark after eq. FV_matrix, D M^{-1} D^T p = f - D M^{-1} g (with g_D != 0,
+    which fixes the sign of the g term)."""
+    from oracle.fv import linear_pressure
+    prob = small_problem((7, 5), seed=3, alpha=0.0, g_d_scale=0.5, g_n_scale=0.3)
+    h = build_hierarchy(prob, n_levels=1)
+    x = result_solve(h)
+    np.testing.assert_allclose(x[h.levels[0].n_flux:], linear_pressure(prob), atol=1e-12)
+
+
+def test_c2_rate_constant_matches_calibration(golden_dir):
+    """The stored well rate of the 60x220x85 workload is the one written by
+    tests/golden/calibrate_c2_rate.py (which calls only the oracle)."""
+    import json
+    from problems.grids import C2_WELL_RATE
+    with open(os.path.join(golden_dir, "c2_rate.json")) as fh:
+        rec = json.load(fh)
+    assert C2_WELL_RATE == pytest.approx(rec["rate"], rel=1e-12)
+    assert rec["max_abs_p_at_rate_1"] * rec["rate"] == pytest.approx(0.5, rel=1e-12)
