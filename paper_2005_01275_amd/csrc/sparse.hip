@@ -342,15 +342,20 @@ struct HostCsr {
   std::vector<int> ptr, col;
 };
 
-// Plain aggregation with symmetric strength |a_ij| >= theta sqrt(|a_ii a_jj|).
+// Plain aggregation with row-relative strength |a_ij| >= theta max_k |a_ik|
+// (a threshold relative to the diagonal turns the wide stencils of coarse
+// Galerkin rows into all-weak rows and stalls the coarsening).
 int aggregate(const HostCsr& A, double theta, std::vector<int>& agg) {
   const int n = A.n;
   agg.assign(n, -1);
+  std::vector<double> rowmax(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (A.col[k] != i) rowmax[i] = std::max(rowmax[i], std::fabs(A.val[k]));
   auto strong = [&](int i, int k) {
     const int j = A.col[k];
     if (j == i) return false;
-    const double d = std::sqrt(std::fabs(A.diag[i] * A.diag[j]));
-    return std::fabs(A.val[k]) >= theta * d && d > 0.0;
+    return rowmax[i] > 0.0 && std::fabs(A.val[k]) >= theta * rowmax[i];
   };
   int nc = 0;
   std::vector<char> phase1(n, 0);
@@ -418,7 +423,7 @@ void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
   }
   while (H.n > dense_max) {
     std::vector<int> agg;
-    const int nc = aggregate(H, 0.08, agg);
+    const int nc = aggregate(H, 0.25, agg);
     if (nc >= H.n || nc * 10 > H.n * 9) break;   // coarsening stalled
     AmgLevel& F = lv.back();
     // members
