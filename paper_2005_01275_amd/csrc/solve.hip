@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <functional>
 
 #include "coarse_kern.hpp"
@@ -68,8 +70,14 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
 
 // Alg. 1 on a residual-norm function of the step length.  Returns the step
 // taken and the residual norm there; `halvings` counts the halvings.
-static double backtrack(const std::function<double(double)>& rn, double r_x, int nmax, double theta, double& r_new,
-                        int& halvings) {
+// A trial whose residual is not finite (kappa = exp(alpha p) overflowed)
+// counts as +infinity, so it is never preferred to a finite one.
+static double backtrack(const std::function<double(double)>& rn_raw, double r_x, int nmax, double theta,
+                        double& r_new, int& halvings) {
+  auto rn = [&](double s) {
+    const double v = rn_raw(s);
+    return std::isfinite(v) ? v : HUGE_VAL;
+  };
   double s = 1.0;
   int n = 0;
   double r_s = rn(s);
@@ -80,9 +88,19 @@ static double backtrack(const std::function<double(double)>& rn, double r_x, int
     ++n;
     r_s = r_half;
   }
+  if (r_s == HUGE_VAL) fail(SPFAS_ERR_NUMERIC, "non-finite residual after backtracking (kappa overflow)");
   r_new = r_s;
   halvings += n;
   return s;
+}
+
+// SPFAS_TRACE=1 prints one line per smoothing step to stderr.
+static bool trace_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("SPFAS_TRACE");
+    return e && e[0] && e[0] != '0';
+  }();
+  return on;
 }
 
 static double check_finite(double v, const char* what) {
@@ -133,7 +151,7 @@ static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double
   const double bytes = 40.0 * h.fine.nf + 24.0 * h.fine.n;
   h.prof.run(SPFAS_PROF_FINE_RESID, bytes, h.stream,
              [&] { G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.parts.p, h.stream); });
-  return check_finite(std::sqrt(h.host_sum(h.parts.p, G)), "fine residual");
+  return std::sqrt(h.host_sum(h.parts.p, G));   // may be non-finite inside Alg. 1 trials
 }
 
 // One Picard or Newton step on level 0 (Section 3.3): solve the linearised
@@ -162,7 +180,9 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
                                 o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
   launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
   st.smoothing_steps++;
-  (void)n;
+  if (trace_on())
+    std::fprintf(stderr, "[spfas] level 0 %s: krylov %d  |r| %.3e -> %.3e  cap %.3g  step %.4g\n",
+                 o.newton ? "newton" : "picard", it, r_x, r_new, scale, step);
   return r_new;
 }
 
@@ -222,7 +242,7 @@ static void store_state(Hierarchy& h, const spfas_problem& prob, double* p, doub
 // ------------------------------------------------------------------ drivers
 
 static int single_level(Hierarchy& h, const Opts& o, spfas_stats& st) {
-  double r = fine_rnorm(h, h.fw.x.p, nullptr, 0.0);
+  double r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "initial residual");
   st.r0 = r;
   const double tol = std::max(o.rtol * r, o.atol);
   int rc = SPFAS_NOT_CONVERGED;
@@ -253,7 +273,7 @@ static void launch_sub(int64_t n, const double* a, const double* b, double* out,
 static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* dx, double step) {
   CoarseLevel& C = *h.coarse[l - 1];
   const int G = launch_coarse_resid(C, h.fine.alpha, x, dx, step, C.b.p, nullptr, h.parts.p, h.stream);
-  return check_finite(std::sqrt(h.host_sum(h.parts.p, G)), "coarse residual");
+  return std::sqrt(h.host_sum(h.parts.p, G));   // may be non-finite inside Alg. 1 trials
 }
 
 // One Picard or Newton step on coarse level l (Section 3.3) with the linear
@@ -265,10 +285,10 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   const double alpha = h.fine.alpha;
   launch_coarse_resid(C, alpha, C.x.p, nullptr, 0.0, C.b.p, C.r.p, h.parts.p, s);
   launch_coarse_local(C, alpha, o.newton, C.x.p, C.r.p, s);
+  int it = 0;
   if (C.nl > 0) {
     launch_H_assemble(C, s);
     C.amg.numeric(s);
-    int it;
     if (o.newton)
       it = C.kry.bicgstab(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol, o.lin_max_it, s);
     else
@@ -283,6 +303,10 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
                                 o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
   launch_axpy(C.nf + C.np, step * scale, C.dx.p, C.x.p, s);
   st.smoothing_steps++;
+  if (trace_on())
+    std::fprintf(stderr, "[spfas] level %d %s: multipliers %d (AMG levels %d, dense %d) krylov %d  |r| %.3e -> "
+                 "%.3e  cap %.3g  step %.4g\n", l, o.newton ? "newton" : "picard", C.nl, C.amg.n_levels(),
+                 C.amg.nd, it, r_x, r_new, scale, step);
   return r_new;
 }
 
@@ -360,7 +384,7 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
 }
 
 int run_fas(Hierarchy& h, const Opts& o, spfas_stats& st) {
-  double r = fine_rnorm(h, h.fw.x.p, nullptr, 0.0);
+  double r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "initial residual");
   st.r0 = r;
   const double tol = std::max(o.rtol * r, o.atol);
   int rc = SPFAS_NOT_CONVERGED;

@@ -1,0 +1,70 @@
+"""Full-size 60x220x85 workload in the configuration bench.py times
+(GPU): the returned state meets the stopping rule when re-evaluated with
+the oracle's residual, the level-0 aggregation matches the oracle bit for
+bit, and sampled aggregates of the hierarchy match the oracle's local
+computations."""
+import math
+
+import numpy as np
+import pytest
+
+from problems import c2_problem
+from oracle.fv import FineSystem
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2():
+    import paper_2005_01275_amd as pk
+    prob = c2_problem()
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    return prob, H
+
+
+def test_c2_fas_newton_meets_rtol(c2):
+    import paper_2005_01275_amd as pk
+    prob, H = c2
+    print("case c2 fas-newton", flush=True)
+    o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, lin_rtol=1e-4, lin_max_it=400,
+                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
+    p, s, st = H.fas_solve(prob, o)
+    assert st["converged"], st
+    fs = FineSystem(prob)
+    ff = fs.fm.flux_face
+    r0 = np.linalg.norm(fs.f)
+    rs, rp = fs.residual(s[ff], p)
+    rel = np.linalg.norm(np.concatenate([rs, rp])) / r0
+    assert rel <= 1.01e-8, rel
+    # flux conservation at the solution: all injected fluid leaves through the Dirichlet faces
+    dirf = ~fs.inner
+    assert abs(s[ff][dirf].sum() - fs.f.sum()) <= 1e-6 * np.abs(fs.f).sum()
+
+
+def test_c2_aggregates_sampled(c2):
+    """Sampled level-0 aggregates: the spectrum of each local Laplacian
+    (static matrices, eq. local-eigenvalue-problem) against a dense
+    eigen-solve of the weighted graph Laplacian of the same cells."""
+    from paper_2005_01275_amd import _native as N
+    prob, H = c2
+    n_agg = 17325
+    lam_gpu = H.level_operator(0, N.SPFAS_OP_EIGVALS, prob.mesh.n_cells)
+    agg = H.aggregation(0)
+    sizes = np.bincount(agg, minlength=n_agg)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(0)
+    sample = rng.choice(n_agg, 6, replace=False)
+    fs = FineSystem(prob)
+    for A in sample:
+        cells = np.sort(np.nonzero(agg == A)[0])
+        inside = np.isin(fs.K, cells) & np.isin(np.where(fs.inner, fs.L, -1), cells)
+        pos = {c: i for i, c in enumerate(cells)}
+        n = cells.size
+        # weighted graph Laplacian of the aggregate with harmonic transmissibilities (kappa = 1)
+        Lm = np.zeros((n, n))
+        for f in np.nonzero(inside)[0]:
+            w = 1.0 / (1.0 / fs.TK[f] + 1.0 / fs.TL[f])
+            i, j = pos[fs.K[f]], pos[fs.L[f]]
+            Lm[i, i] += w; Lm[j, j] += w; Lm[i, j] -= w; Lm[j, i] -= w
+        lam = np.linalg.eigvalsh(Lm)
+        np.testing.assert_allclose(lam_gpu[offs[A]:offs[A + 1]], lam, atol=1e-10 * lam[-1])
