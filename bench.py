@@ -45,6 +45,26 @@ def percentile(v, q):
     return v[f] + (v[c] - v[f]) * (k - f)
 
 
+def copy_rate(torch, nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """Device-to-device copy of `nbytes` (larger than the 256 MB last-level
+    cache) with torch's elementwise copy kernel: the measured HBM rate, and
+    the kernel of known size that calibrates the FETCH_SIZE / WRITE_SIZE
+    counters."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return {"bytes_read": nbytes, "bytes_written": nbytes, "avg_us": 1000.0 * ms,
+            "GBps": 2.0 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(n_full: int, vcycles_full: float) -> dict:
     """The CPU FP64 oracle timed on a bounded sample of the workload: the
     same recipe (log-normal top layers, channelised bottom layers, column
@@ -92,6 +112,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    copy = copy_rate(torch)
     prob = c2_problem() if args.workload == "c2" else c1_problem()
     n_cells = prob.mesh.n_cells
     stream = torch.cuda.current_stream()
@@ -137,7 +158,8 @@ def main():
     achieved = (by / nl) / (ms / nl * 1e-3) / 1e9 if nl and ms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
                 "frac": achieved / 8000.0, "traffic": None, "launches": nl,
-                "avg_us": 1000.0 * ms / max(nl, 1), "algo_bytes_per_launch": by / max(nl, 1)}
+                "avg_us": 1000.0 * ms / max(nl, 1), "algo_bytes_per_launch": by / max(nl, 1),
+                "frac_of_measured_copy": achieved / copy["GBps"]}
     kernels = {k: {"launches": v[0], "total_ms": v[1], "avg_us": 1000.0 * v[1] / max(v[0], 1),
                    "algo_GBps": (v[2] / v[1] * 1e-6) if v[1] > 0 else 0.0} for k, v in prof.items()}
 
@@ -165,6 +187,7 @@ def main():
         "setup_s": setup_s,
         "roofline": roofline,
         "kernels": kernels,
+        "copy_1GiB": copy,
     }
 
     if not args.no_comparators:

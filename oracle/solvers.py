@@ -60,18 +60,29 @@ def norm(v):
 def backtracking(rnorm_of, x, dx, nmax, theta, r_x=None):
     """Alg. 1: halve s while ||r(x + s dx)|| > ||r(x)|| and fewer than n_max
     halvings were taken; stop halving when the halved step would not reduce
-    the residual by more than the factor theta.  Returns (x_new, s, halvings)."""
-    rx = rnorm_of(x) if r_x is None else r_x
+    the residual by more than the factor theta.  Returns (x_new, s, halvings).
+
+    The paper does not consider trial points where kappa overflows.  Reading
+    taken here: a non-finite trial residual counts as +infinity (so the
+    comparisons above stay well defined), and when the trial finally chosen
+    is still non-finite the step is rejected (s = 0, x unchanged)."""
+    def rn(y):
+        v = float(rnorm_of(y))
+        return v if math.isfinite(v) else math.inf
+
+    rx = rn(x) if r_x is None else r_x
     s = 1.0
     n = 0
-    r_s = rnorm_of(x + s * dx)
+    r_s = rn(x + s * dx)
     while r_s > rx and n < nmax:
-        r_half = rnorm_of(x + 0.5 * s * dx)
+        r_half = rn(x + 0.5 * s * dx)
         if r_half > theta * r_s:
             break
         s *= 0.5
         n += 1
         r_s = r_half
+    if r_s == math.inf:
+        return np.copy(x), 0.0, n
     return x + s * dx, s, n
 
 

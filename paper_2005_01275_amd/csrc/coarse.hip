@@ -8,6 +8,8 @@
 //   * restriction R = P^T, projection Q and prolongation P between levels.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "coarse_kern.hpp"
 #include "hier.hpp"
@@ -557,6 +559,8 @@ void setup_coarse_solver(Hierarchy& h, int l) {
     launch_H_assemble(C, s);
     HIPCHECK(hipStreamSynchronize(s));
     C.amg.setup(C.H, s);
+    if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
+      std::fprintf(stderr, "[spfas] hybridised system of level %d AMG: %s\n", l, C.amg.describe().c_str());
   }
 }
 

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
@@ -71,7 +72,9 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
 // Alg. 1 on a residual-norm function of the step length.  Returns the step
 // taken and the residual norm there; `halvings` counts the halvings.
 // A trial whose residual is not finite (kappa = exp(alpha p) overflowed)
-// counts as +infinity, so it is never preferred to a finite one.
+// counts as +infinity, so it is never preferred to a finite one; when the
+// trial finally chosen is still non-finite the step is rejected (0 returned,
+// residual unchanged).
 static double backtrack(const std::function<double(double)>& rn_raw, double r_x, int nmax, double theta,
                         double& r_new, int& halvings) {
   auto rn = [&](double s) {
@@ -88,9 +91,12 @@ static double backtrack(const std::function<double(double)>& rn_raw, double r_x,
     ++n;
     r_s = r_half;
   }
-  if (r_s == HUGE_VAL) fail(SPFAS_ERR_NUMERIC, "non-finite residual after backtracking (kappa overflow)");
-  r_new = r_s;
   halvings += n;
+  if (r_s == HUGE_VAL) {
+    r_new = r_x;
+    return 0.0;
+  }
+  r_new = r_s;
   return s;
 }
 
@@ -101,6 +107,12 @@ static bool trace_on() {
     return e && e[0] && e[0] != '0';
   }();
   return on;
+}
+
+// wall-clock milliseconds after draining the stream (trace output only)
+static double trace_clock(hipStream_t s) {
+  HIPCHECK(hipStreamSynchronize(s));
+  return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 static double check_finite(double v, const char* what) {
@@ -135,6 +147,7 @@ void setup_fine_solver(Hierarchy& h) {
   f.alpha = a;
   HIPCHECK(hipStreamSynchronize(s));
   w.amg.setup(w.S, s);
+  if (trace_on()) std::fprintf(stderr, "[spfas] level 0 AMG: %s\n", w.amg.describe().c_str());
   // event timing hooks of the finest-level Krylov SpMV and Jacobi sweeps
   ProfHook hk;
   hk.prof = &h.prof;
@@ -162,6 +175,7 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   FineDev& f = h.fine;
   hipStream_t s = h.stream;
   const int64_t n = f.n, nf = f.nf;
+  const double t0 = trace_on() ? trace_clock(s) : 0.0;
   h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 56.0 * nf + 24.0 * n, s,
              [&] { launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s); });
   w.amg.numeric(s);
@@ -178,11 +192,11 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   double r_new = r_x;
   const double step = backtrack([&](double sl) { return fine_rnorm(h, w.x.p, w.dx.p, sl * scale); }, r_x,
                                 o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
-  launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
+  if (step > 0.0) launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
   st.smoothing_steps++;
   if (trace_on())
-    std::fprintf(stderr, "[spfas] level 0 %s: krylov %d  |r| %.3e -> %.3e  cap %.3g  step %.4g\n",
-                 o.newton ? "newton" : "picard", it, r_x, r_new, scale, step);
+    std::fprintf(stderr, "[spfas] level 0 %s: krylov %d  |r| %.3e -> %.3e  cap %.3g  step %.4g  %.2f ms\n",
+                 o.newton ? "newton" : "picard", it, r_x, r_new, scale, step, trace_clock(s) - t0);
   return r_new;
 }
 
@@ -249,7 +263,7 @@ static int single_level(Hierarchy& h, const Opts& o, spfas_stats& st) {
   for (int it = 0;; ++it) {
     if (r <= tol) { rc = SPFAS_OK; break; }
     if (it >= o.max_it) break;
-    r = fine_smooth(h, o, r, st);
+    r = check_finite(fine_smooth(h, o, r, st), "residual after a smoothing step (divergence)");
     st.iterations++;
   }
   st.r_final = r;
@@ -283,6 +297,7 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   CoarseLevel& C = *h.coarse[l - 1];
   hipStream_t s = h.stream;
   const double alpha = h.fine.alpha;
+  const double t0 = trace_on() ? trace_clock(s) : 0.0;
   launch_coarse_resid(C, alpha, C.x.p, nullptr, 0.0, C.b.p, C.r.p, h.parts.p, s);
   launch_coarse_local(C, alpha, o.newton, C.x.p, C.r.p, s);
   int it = 0;
@@ -301,12 +316,12 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   double r_new = r_x;
   const double step = backtrack([&](double sl) { return coarse_rnorm(h, l, C.x.p, C.dx.p, sl * scale); }, r_x,
                                 o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
-  launch_axpy(C.nf + C.np, step * scale, C.dx.p, C.x.p, s);
+  if (step > 0.0) launch_axpy(C.nf + C.np, step * scale, C.dx.p, C.x.p, s);
   st.smoothing_steps++;
   if (trace_on())
     std::fprintf(stderr, "[spfas] level %d %s: multipliers %d (AMG levels %d, dense %d) krylov %d  |r| %.3e -> "
-                 "%.3e  cap %.3g  step %.4g\n", l, o.newton ? "newton" : "picard", C.nl, C.amg.n_levels(),
-                 C.amg.nd, it, r_x, r_new, scale, step);
+                 "%.3e  cap %.3g  step %.4g  %.2f ms\n", l, o.newton ? "newton" : "picard", C.nl, C.amg.n_levels(),
+                 C.amg.nd, it, r_x, r_new, scale, step, trace_clock(s) - t0);
   return r_new;
 }
 
@@ -374,7 +389,7 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
     return l == 0 ? fine_rnorm(h, x, dx, sl) : coarse_rnorm(h, l, x, dx, sl);
   };
   const double step = backtrack(rn, r_s, o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
-  launch_axpy(nl, step, dx, x, s);
+  if (step > 0.0) launch_axpy(nl, step, dx, x, s);
   (void)nfl;
   // post-smoothing
   if (l == 0)
@@ -392,9 +407,13 @@ int run_fas(Hierarchy& h, const Opts& o, spfas_stats& st) {
     if (r <= tol) { rc = SPFAS_OK; break; }
     if (it >= o.max_it) break;
     bool stopped = false;
+    const double t0 = trace_on() ? trace_clock(h.stream) : 0.0;
     nonlinear_mg(h, 0, o, st, tol, stopped);
     st.stopped_after_presmooth = stopped ? 1 : 0;
-    r = fine_rnorm(h, h.fw.x.p, nullptr, 0.0);
+    r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "residual after a V-cycle (divergence)");
+    if (trace_on())
+      std::fprintf(stderr, "[spfas] V-cycle %d: |r| %.3e (rel %.3e)  %.2f ms\n", it + 1, r, r / st.r0,
+                   trace_clock(h.stream) - t0);
     st.iterations++;
   }
   st.r_final = r;

@@ -33,7 +33,9 @@ void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s) {
   LAUNCHCHECK();
 }
 
-// y = A x; parts = sum_i w_i y_i (w may be x itself or another vector)
+// y = A x; parts = sum_i w_i y_i (w may be x itself or another vector).
+// The template flag only separates the finest-level launches by name.
+template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot(CsrView A, const double* __restrict__ x, double* __restrict__ y,
                                                      const double* __restrict__ w, double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
@@ -49,6 +51,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(CsrView A, const double* __
 }
 
 // y = A x; parts0 = sum w0*y, parts1 = sum y*y
+template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot2(CsrView A, const double* __restrict__ x, double* __restrict__ y,
                                                       const double* __restrict__ w0, double* __restrict__ parts0,
                                                       double* __restrict__ parts1) {
@@ -181,6 +184,8 @@ __global__ void __launch_bounds__(kBlock) k_jacobi0(int n, const double* __restr
   if (i < n) x[i] = invd[i] * b[i];
 }
 
+// one damped Jacobi sweep; the template flag only names the finest level apart
+template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_jacobi(CsrView A, const double* __restrict__ invd, const double* __restrict__ b,
                                                    const double* __restrict__ xin, double* __restrict__ xout) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -190,6 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_jacobi(CsrView A, const double* __re
   xout[i] = xin[i] + invd[i] * (b[i] - a);
 }
 
+template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_resid_restrict(CsrView A, const double* __restrict__ b,
                                                            const double* __restrict__ x, double* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,14 +328,85 @@ __global__ void __launch_bounds__(kBlock) k_dense_inverse(double* __restrict__ M
   }
 }
 
+// In-place Gauss-Jordan inverse with partial pivoting of an nd x nd
+// row-major matrix held entirely in LDS (nd <= kDenseLds, one block).  Row
+// interchanges are undone as column interchanges in reverse order at the end.
+__global__ void __launch_bounds__(kBlock) k_dense_inverse_lds(const double* __restrict__ A, double* __restrict__ inv,
+                                                              int nd, int* __restrict__ flag) {
+  __shared__ double a[kDenseLds * kDenseLds];
+  __shared__ double fcol[kDenseLds];
+  __shared__ int perm[kDenseLds];
+  const int tid = threadIdx.x;
+  const int nn = nd * nd;
+  for (int e = tid; e < nn; e += blockDim.x) a[e] = A[e];
+  __syncthreads();
+  for (int k = 0; k < nd; ++k) {
+    if (tid < 64) {   // pivot search by wave 0; ties go to the lowest row
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + tid; i < nd; i += 64) {
+        const double v = fabs(a[i * nd + k]);
+        if (v > best) { best = v; bi = i; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_down(best, o, 64);
+        const int oi = __shfl_down(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        perm[k] = bi;
+        if (!(best > 0.0)) flag[0] = 1;
+      }
+    }
+    __syncthreads();
+    const int p = perm[k];
+    if (p != k)
+      for (int j = tid; j < nd; j += blockDim.x) {
+        const double t = a[k * nd + j];
+        a[k * nd + j] = a[p * nd + j];
+        a[p * nd + j] = t;
+      }
+    __syncthreads();
+    const double pv = a[k * nd + k];
+    const double ipv = pv != 0.0 ? 1.0 / pv : 0.0;
+    __syncthreads();
+    for (int j = tid; j < nd; j += blockDim.x) a[k * nd + j] = (j == k) ? ipv : a[k * nd + j] * ipv;
+    for (int i = tid; i < nd; i += blockDim.x)
+      if (i != k) fcol[i] = a[i * nd + k];
+    __syncthreads();
+    for (int e = tid; e < nn; e += blockDim.x) {
+      const int i = e / nd, j = e - (e / nd) * nd;
+      if (i == k) continue;
+      const double base = (j == k) ? 0.0 : a[e];
+      a[e] = base - fcol[i] * a[k * nd + j];
+    }
+    __syncthreads();
+  }
+  for (int k = nd - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = tid; i < nd; i += blockDim.x) {
+        const double t = a[i * nd + k];
+        a[i * nd + k] = a[i * nd + p];
+        a[i * nd + p] = t;
+      }
+    __syncthreads();
+  }
+  for (int e = tid; e < nn; e += blockDim.x) inv[e] = a[e];
+}
+
+// x = inv b, one wave per row (coalesced row reads)
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(int nd, const double* __restrict__ inv, const double* __restrict__ b,
                                                        double* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nd) return;
-  const double* row = inv + (size_t)i * nd;
+  const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nd) return;
+  const double* r = inv + (size_t)row * nd;
   double s = 0.0;
-  for (int j = 0; j < nd; ++j) s += row[j] * b[j];
-  x[i] = s;
+  for (int j = lane; j < nd; j += 64) s += r[j] * b[j];
+  s = wave_sum(s);
+  if (lane == 0) x[row] = s;
 }
 
 // ------------------------------------------------------------------ AMG host
@@ -519,6 +596,17 @@ void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
   flag.alloc(1);
 }
 
+std::string Amg::describe() const {
+  std::string out;
+  for (const AmgLevel& L : lv) {
+    long long nnz = 0;
+    if (&L != &lv[0]) nnz = (long long)L.val.n;
+    out += std::to_string(L.n) + "/" + std::to_string(nnz) + " ";
+  }
+  out += "dense " + std::to_string(nd);
+  return out;
+}
+
 void Amg::numeric(hipStream_t s) {
   for (size_t k = 0; k + 1 < lv.size(); ++k) {
     AmgLevel& F = lv[k];
@@ -541,7 +629,10 @@ void Amg::numeric(hipStream_t s) {
   hipLaunchKernelGGL(k_dense_fill, dim3(grid_for(nd, kBlock)), dim3(kBlock), 0, s, Lc.view, lu.p, nd);
   LAUNCHCHECK();
   flag.zero(s);
-  hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(kBlock), 0, s, lu.p, Lc.t.p, piv.p, nd, flag.p);
+  if (nd <= kDenseLds)
+    hipLaunchKernelGGL(k_dense_inverse_lds, dim3(1), dim3(kBlock), 0, s, lu.p, Lc.t.p, nd, flag.p);
+  else
+    hipLaunchKernelGGL(k_dense_inverse, dim3(1), dim3(kBlock), 0, s, lu.p, Lc.t.p, piv.p, nd, flag.p);
   LAUNCHCHECK();
 }
 
@@ -557,9 +648,13 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
     const unsigned g = grid_for(n, kBlock);
     // pre-smoothing: two Jacobi sweeps from zero
     hipLaunchKernelGGL(k_jacobi0, dim3(g), dim3(kBlock), 0, s, n, F.invd.p, bl, F.t.p);
-    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s,
-          [&] { hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl); });
-    hipLaunchKernelGGL(k_resid_restrict, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
+    const bool fin = k == 0 && hook.prof;
+    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s, [&] {
+      if (fin) hipLaunchKernelGGL(k_jacobi<true>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl);
+      else hipLaunchKernelGGL(k_jacobi<false>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl);
+    });
+    if (fin) hipLaunchKernelGGL(k_resid_restrict<true>, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
+    else hipLaunchKernelGGL(k_resid_restrict<false>, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
     hipLaunchKernelGGL(k_restrict, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.mptr.p, F.mem.p, F.r.p,
                        C.b.p);
     LAUNCHCHECK();
@@ -567,7 +662,7 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
     xl = C.x.p;
   }
   AmgLevel& Lc = lv.back();
-  hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock)), dim3(kBlock), 0, s, nd, Lc.t.p, bl, xl);
+  hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd, Lc.t.p, bl, xl);
   LAUNCHCHECK();
   for (int k = L - 2; k >= 0; --k) {
     AmgLevel& F = lv[k];
@@ -578,10 +673,15 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
     const double* bf = (k == 0) ? b : F.b.p;
     hipLaunchKernelGGL(k_prolong, dim3(g), dim3(kBlock), 0, s, n, F.agg.p, C.x.p, xf);
     // post-smoothing: two Jacobi sweeps (ping-pong through t)
-    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s,
-          [&] { hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p); });
-    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s,
-          [&] { hipLaunchKernelGGL(k_jacobi, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf); });
+    const bool fin = k == 0 && hook.prof;
+    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s, [&] {
+      if (fin) hipLaunchKernelGGL(k_jacobi<true>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p);
+      else hipLaunchKernelGGL(k_jacobi<false>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p);
+    });
+    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s, [&] {
+      if (fin) hipLaunchKernelGGL(k_jacobi<true>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf);
+      else hipLaunchKernelGGL(k_jacobi<false>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf);
+    });
     LAUNCHCHECK();
   }
 }
@@ -630,7 +730,10 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
     hipLaunchKernelGGL(k_pcg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] { hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0); });
+          [&] {
+            if (hook.prof) hipLaunchKernelGGL(k_spmv_dot<true>, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0);
+            else hipLaunchKernelGGL(k_spmv_dot<false>, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0);
+          });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_PQ);
     hipLaunchKernelGGL(k_pcg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, x, r.p, p.p, q.p, P0);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
@@ -669,14 +772,22 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     if (M) M->apply(p.p, y.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, p.p, y.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] { hipLaunchKernelGGL(k_spmv_dot, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0); });
+          [&] {
+            if (hook.prof) hipLaunchKernelGGL(k_spmv_dot<true>, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0);
+            else hipLaunchKernelGGL(k_spmv_dot<false>, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0);
+          });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RV);
     hipLaunchKernelGGL(k_bicg_s, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, r.p, v.p, s.p);
     LAUNCHCHECK();
     if (M) M->apply(s.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] { hipLaunchKernelGGL(k_spmv_dot2, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1); });
+          [&] {
+            if (hook.prof)
+              hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);
+            else
+              hipLaunchKernelGGL(k_spmv_dot2<false>, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);
+          });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_TS);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P1, G, scal.p, (int)S_TT);
     hipLaunchKernelGGL(k_bicg_x, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, P0);

@@ -19,11 +19,16 @@
 // iteration to stop.
 #pragma once
 
+#include <string>
 #include <vector>
 
 #include "common.hpp"
 
 namespace spfas {
+
+// Largest coarsest-level matrix inverted inside LDS (88^2 doubles < 64 KiB);
+// AMG coarsening continues until the level is at most this size.
+constexpr int kDenseLds = 88;
 
 struct CsrView {
   int n = 0;
@@ -66,10 +71,11 @@ struct Amg {
   DVec<int> flag;                     // singular-pivot flag
   int cycles = 1;
   // host setup from the matrix pattern and setup values
-  void setup(const CsrView& A0, hipStream_t s, int dense_max = 256);
+  void setup(const CsrView& A0, hipStream_t s, int dense_max = kDenseLds);
   void numeric(hipStream_t s);        // coarse values, weights, dense LU
   void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
   int n_levels() const { return (int)lv.size(); }
+  std::string describe() const;       // "n/nnz" per level, for diagnostics
 };
 
 struct Krylov {

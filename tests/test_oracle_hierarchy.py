@@ -278,6 +278,22 @@ def test_backtracking_transcription():
     assert (s, n) == (0.0625, 4)
 
 
+def test_backtracking_non_finite_trials():
+    inf, nan = math.inf, math.nan
+    # an overflowing full step is halved like a very large residual
+    t = {0.0: 1.0, 1.0: inf, 0.5: nan, 0.25: 0.8}
+    x, s, n = backtracking(scripted(t), 0.0, 1.0, 4, 0.9)
+    assert (s, n) == (0.25, 2)
+    # every trial overflows: the step is rejected and x is returned unchanged
+    t = {0.0: 1.0, 1.0: inf, 0.5: inf, 0.25: nan, 0.125: inf, 0.0625: inf}
+    x, s, n = backtracking(scripted(t), 0.0, 1.0, 4, 0.9)
+    assert (s, n) == (0.0, 4) and float(x) == 0.0
+    # a finite but larger residual is still preferred to an overflow
+    t = {0.0: 1.0, 1.0: inf, 0.5: 3.0, 0.25: 2.9}
+    x, s, n = backtracking(scripted(t), 0.0, 1.0, 4, 0.9)
+    assert (s, n) == (0.5, 1)
+
+
 def test_cap():
     cap = cap_value(1.0, 5.0)
     assert cap == pytest.approx(math.log(5.0))
