@@ -269,14 +269,21 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * Each instrumented launch is bracketed by two events; `algo_bytes` is the
  * algorithmic HBM traffic of the launches (the minimum the method moves:
  * per flux unknown F and cell N of level 0, residual 40F + 24N, Newton
- * linearisation 56F + 24N, S x 24F + 24N, one Jacobi sweep 24F + 40N).
+ * linearisation 56F + 24N, S x 24F + 24N; on the finest AMG level, with
+ * E = stored nonzeros of S including the diagonal (FP32 value + int32
+ * column each): two-sweep pre-smoothing 8E + 24N, residual 8E + 24N,
+ * prolongation + sweep 8E + 36N, last sweep 8E + 32N).
  */
 typedef enum {
   SPFAS_PROF_FINE_RESID = 0,      /* fine residual, also inside Alg. 1 trials   */
   SPFAS_PROF_FINE_LINEARIZE = 1,  /* S = D M^{-1} E and its right-hand side      */
-  SPFAS_PROF_FINE_SPMV = 2,       /* S x inside the fine-level Krylov solver     */
-  SPFAS_PROF_FINE_SMOOTH = 3,     /* Jacobi sweeps on the finest AMG level       */
-  SPFAS_PROF_COUNT = 4
+  SPFAS_PROF_FINE_SPMV = 2,       /* S x (+ one dot) in the fine-level Krylov solver */
+  SPFAS_PROF_FINE_AMG_PRE = 3,    /* finest AMG level: two sweeps from zero      */
+  SPFAS_PROF_FINE_AMG_RESID = 4,  /* finest AMG level: residual                  */
+  SPFAS_PROF_FINE_AMG_POST1 = 5,  /* finest AMG level: prolongation + sweep      */
+  SPFAS_PROF_FINE_AMG_POST2 = 6,  /* finest AMG level: last sweep                */
+  SPFAS_PROF_FINE_SPMV2 = 7,      /* S x (+ two dots), second product of BiCGStab */
+  SPFAS_PROF_COUNT = 8
 } spfas_prof_kernel;
 
 /* Turns the timing on (nonzero) or off and clears the counters. */

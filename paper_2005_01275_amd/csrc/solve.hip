@@ -152,9 +152,12 @@ void setup_fine_solver(Hierarchy& h) {
   ProfHook hk;
   hk.prof = &h.prof;
   hk.spmv_id = SPFAS_PROF_FINE_SPMV;
-  hk.smooth_id = SPFAS_PROF_FINE_SMOOTH;
+  hk.spmv2_id = SPFAS_PROF_FINE_SPMV2;
   hk.spmv_bytes = 24.0 * nf + 24.0 * n;
-  hk.smooth_bytes = 24.0 * nf + 40.0 * n;
+  hk.pre_id = SPFAS_PROF_FINE_AMG_PRE;
+  hk.resid_id = SPFAS_PROF_FINE_AMG_RESID;
+  hk.post1_id = SPFAS_PROF_FINE_AMG_POST1;
+  hk.post2_id = SPFAS_PROF_FINE_AMG_POST2;
   w.kry.hook = hk;
   w.amg.hook = hk;
 }
@@ -195,8 +198,9 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   if (step > 0.0) launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
   st.smoothing_steps++;
   if (trace_on())
-    std::fprintf(stderr, "[spfas] level 0 %s: krylov %d  |r| %.3e -> %.3e  cap %.3g  step %.4g  %.2f ms\n",
-                 o.newton ? "newton" : "picard", it, r_x, r_new, scale, step, trace_clock(s) - t0);
+    std::fprintf(stderr, "[spfas] level 0 %s: krylov %d  |r| %.3e -> %.3e  cap %.3g  step %.4g  %.2f ms %s\n",
+                 o.newton ? "newton" : "picard", it, r_x, r_new, scale, step, trace_clock(s) - t0,
+                 w.amg.level_times().c_str());
   return r_new;
 }
 
@@ -320,8 +324,8 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   st.smoothing_steps++;
   if (trace_on())
     std::fprintf(stderr, "[spfas] level %d %s: multipliers %d (AMG levels %d, dense %d) krylov %d  |r| %.3e -> "
-                 "%.3e  cap %.3g  step %.4g  %.2f ms\n", l, o.newton ? "newton" : "picard", C.nl, C.amg.n_levels(),
-                 C.amg.nd, it, r_x, r_new, scale, step, trace_clock(s) - t0);
+                 "%.3e  cap %.3g  step %.4g  %.2f ms %s\n", l, o.newton ? "newton" : "picard", C.nl, C.amg.n_levels(),
+                 C.amg.nd, it, r_x, r_new, scale, step, trace_clock(s) - t0, C.amg.level_times().c_str());
   return r_new;
 }
 

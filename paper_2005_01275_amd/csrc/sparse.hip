@@ -3,7 +3,10 @@
 #include "sparse.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <numeric>
 
 #include "kern.hpp"
@@ -178,31 +181,180 @@ __global__ void __launch_bounds__(kBlock) k_invd(CsrView A, double* __restrict__
   invd[i] = d > 0.0 ? 1.0 / d : 0.0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_jacobi0(int n, const double* __restrict__ invd, const double* __restrict__ b,
-                                                    double* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] = invd[i] * b[i];
+// ------------------------------------------------------------------ SELL-64 cycle kernels
+
+// First stored entry and width of row i of a SELL-64 matrix.
+__device__ inline void sell_row(const SellView& A, int i, int& e, int& width) {
+  const int sl = i >> 6;
+  const int a = A.sptr[sl];
+  e = a + (i & 63);
+  width = (A.sptr[sl + 1] - a) >> 6;
 }
 
-// one damped Jacobi sweep; the template flag only names the finest level apart
+// Two Jacobi sweeps from x = 0 in one pass: x1 = w b, x2 = x1 + w (b - A x1).
+// The template flag only separates the finest-level launches by name.
 template <bool Finest>
-__global__ void __launch_bounds__(kBlock) k_jacobi(CsrView A, const double* __restrict__ invd, const double* __restrict__ b,
-                                                   const double* __restrict__ xin, double* __restrict__ xout) {
+__global__ void __launch_bounds__(kBlock) k_amg_pre(SellView A, const double* __restrict__ w,
+                                                    const double* __restrict__ b, double* __restrict__ x2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  double a = A.diag[i] * xin[i];
-  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * xin[A.col[k]];
-  xout[i] = xin[i] + invd[i] * (b[i] - a);
+  int e, width;
+  sell_row(A, i, e, width);
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < width; ++k, e += 64) {
+    const int j = A.col[e];
+    acc += (double)A.val[e] * (w[j] * b[j]);
+  }
+  const double wi = w[i], bi = b[i];
+  x2[i] = wi * bi + wi * (bi - acc);
 }
 
+// r = b - A x
 template <bool Finest>
-__global__ void __launch_bounds__(kBlock) k_resid_restrict(CsrView A, const double* __restrict__ b,
-                                                           const double* __restrict__ x, double* __restrict__ r) {
+__global__ void __launch_bounds__(kBlock) k_amg_resid(SellView A, const double* __restrict__ b,
+                                                      const double* __restrict__ x, double* __restrict__ r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  double a = A.diag[i] * x[i];
-  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
-  r[i] = b[i] - a;
+  int e, width;
+  sell_row(A, i, e, width);
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < width; ++k, e += 64) acc += (double)A.val[e] * x[A.col[e]];
+  r[i] = b[i] - acc;
+}
+
+// Prolongation of the coarse correction and one sweep in one pass:
+// y = x + ec[agg], out = y + w (b - A y).
+template <bool Finest>
+__global__ void __launch_bounds__(kBlock) k_amg_post1(SellView A, const double* __restrict__ w,
+                                                      const double* __restrict__ b, const double* __restrict__ x,
+                                                      const int* __restrict__ agg, const double* __restrict__ ec,
+                                                      double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  int e, width;
+  sell_row(A, i, e, width);
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < width; ++k, e += 64) {
+    const int j = A.col[e];
+    acc += (double)A.val[e] * (x[j] + ec[agg[j]]);
+  }
+  out[i] = (x[i] + ec[agg[i]]) + w[i] * (b[i] - acc);
+}
+
+// out = x + w (b - A x)
+template <bool Finest>
+__global__ void __launch_bounds__(kBlock) k_amg_post2(SellView A, const double* __restrict__ w,
+                                                      const double* __restrict__ b, const double* __restrict__ x,
+                                                      double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  int e, width;
+  sell_row(A, i, e, width);
+  double acc = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < width; ++k, e += 64) acc += (double)A.val[e] * x[A.col[e]];
+  out[i] = x[i] + w[i] * (b[i] - acc);
+}
+
+// Group-per-row variants for the small coarse levels, whose rows are wide
+// and few: kVecG lanes share a row of the FP64 DIA+CSR matrix, so the
+// dependent column-then-value loads of a long row run in parallel instead of
+// as one serial chain per thread.  Lane 0 of each group writes the row.
+constexpr int kVecG = 8;
+
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int o = kVecG / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kVecG);
+  return v;
+}
+
+__global__ void __launch_bounds__(kBlock) k_amgv_pre(CsrView A, const double* __restrict__ w,
+                                                     const double* __restrict__ b, double* __restrict__ x2) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= A.n) return;   // the whole group leaves together
+  double acc = 0.0;
+  for (int k = A.ptr[i] + g; k < A.ptr[i + 1]; k += kVecG) {
+    const int j = A.col[k];
+    acc += A.val[k] * (w[j] * b[j]);
+  }
+  acc = group_sum(acc);
+  if (g == 0) {
+    const double wi = w[i], bi = b[i], x1 = wi * bi;
+    x2[i] = x1 + wi * (bi - (A.diag[i] * x1 + acc));
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_amgv_resid(CsrView A, const double* __restrict__ b,
+                                                       const double* __restrict__ x, double* __restrict__ r) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= A.n) return;
+  double acc = 0.0;
+  for (int k = A.ptr[i] + g; k < A.ptr[i + 1]; k += kVecG) acc += A.val[k] * x[A.col[k]];
+  acc = group_sum(acc);
+  if (g == 0) r[i] = b[i] - (A.diag[i] * x[i] + acc);
+}
+
+__global__ void __launch_bounds__(kBlock) k_amgv_post1(CsrView A, const double* __restrict__ w,
+                                                       const double* __restrict__ b, const double* __restrict__ x,
+                                                       const int* __restrict__ agg, const double* __restrict__ ec,
+                                                       double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= A.n) return;
+  double acc = 0.0;
+  for (int k = A.ptr[i] + g; k < A.ptr[i + 1]; k += kVecG) {
+    const int j = A.col[k];
+    acc += A.val[k] * (x[j] + ec[agg[j]]);
+  }
+  acc = group_sum(acc);
+  if (g == 0) {
+    const double yi = x[i] + ec[agg[i]];
+    out[i] = yi + w[i] * (b[i] - (A.diag[i] * yi + acc));
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_amgv_post2(CsrView A, const double* __restrict__ w,
+                                                       const double* __restrict__ b, const double* __restrict__ x,
+                                                       double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= A.n) return;
+  double acc = 0.0;
+  for (int k = A.ptr[i] + g; k < A.ptr[i + 1]; k += kVecG) acc += A.val[k] * x[A.col[k]];
+  acc = group_sum(acc);
+  if (g == 0) out[i] = x[i] + w[i] * (b[i] - (A.diag[i] * x[i] + acc));
+}
+
+// bc[I] = sum of r over the members of coarse node I, a lane group per node
+__global__ void __launch_bounds__(kBlock) k_restrict_vec(int nc, const int* __restrict__ mptr,
+                                                         const int* __restrict__ mem, const double* __restrict__ r,
+                                                         double* __restrict__ bc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int I = t / kVecG, g = t % kVecG;
+  if (I >= nc) return;
+  double s = 0.0;
+  for (int k = mptr[I] + g; k < mptr[I + 1]; k += kVecG) s += r[mem[k]];
+  s = group_sum(s);
+  if (g == 0) bc[I] = s;
+}
+
+// FP32 SELL values from the FP64 DIA+CSR values of the level.
+constexpr int kSellPad = INT_MIN;
+__global__ void __launch_bounds__(kBlock) k_sell_fill(int ne, const int* __restrict__ smap,
+                                                      const double* __restrict__ diag, const double* __restrict__ off,
+                                                      float* __restrict__ val) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int m = smap[e];
+  double v = 0.0;
+  if (m >= 0) v = off[m];
+  else if (m != kSellPad) v = diag[-1 - m];
+  val[e] = (float)v;
 }
 
 __global__ void __launch_bounds__(kBlock) k_restrict(int nc, const int* __restrict__ mptr, const int* __restrict__ mem,
@@ -212,12 +364,6 @@ __global__ void __launch_bounds__(kBlock) k_restrict(int nc, const int* __restri
   double s = 0.0;
   for (int k = mptr[I]; k < mptr[I + 1]; ++k) s += r[mem[k]];
   bc[I] = s;
-}
-
-__global__ void __launch_bounds__(kBlock) k_prolong(int n, const int* __restrict__ agg, const double* __restrict__ xc,
-                                                    double* __restrict__ x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x[i] += xc[agg[i]];
 }
 
 __global__ void __launch_bounds__(kBlock) k_galerkin_off(int nnz, const int* __restrict__ gp, const int* __restrict__ gi,
@@ -475,9 +621,53 @@ int aggregate(const HostCsr& A, double theta, std::vector<int>& agg) {
   return nc;
 }
 
+// SELL-64 pattern of a level (diagonal first in every row) and the map from
+// each stored entry to its FP64 source value.
+void build_sell(const HostCsr& H, AmgLevel& F, hipStream_t s) {
+  const int n = H.n, ns = (n + 63) / 64;
+  std::vector<int> sptr(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int width = 1;
+    for (int i = sl * 64; i < std::min(n, sl * 64 + 64); ++i) width = std::max(width, 1 + H.ptr[i + 1] - H.ptr[i]);
+    require((long long)sptr[sl] + 64LL * width < INT_MAX, "AMG level too large for 32-bit SELL offsets");
+    sptr[sl + 1] = sptr[sl] + 64 * width;
+  }
+  const int ne = sptr[ns];
+  std::vector<int> col(ne, 0), map(ne, kSellPad);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int width = (sptr[sl + 1] - sptr[sl]) / 64;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int i = sl * 64 + lane;
+      const int base = sptr[sl] + lane;
+      if (i >= n) continue;   // lanes past the last row are never read
+      col[base] = i;
+      map[base] = -1 - i;
+      int k = 1;
+      for (int q = H.ptr[i]; q < H.ptr[i + 1]; ++q, ++k) {
+        col[base + 64 * k] = H.col[q];
+        map[base + 64 * k] = q;
+      }
+      for (; k < width; ++k) col[base + 64 * k] = i;
+    }
+  }
+  F.sptr.upload(sptr, s);
+  F.scol.upload(col, s);
+  F.smap.upload(map, s);
+  F.sval.alloc(ne);
+  F.sell.n = n;
+  F.sell.sptr = F.sptr.p;
+  F.sell.col = F.scol.p;
+  F.sell.val = F.sval.p;
+  F.sell_nnz = (long long)n + H.ptr[n];
+}
+
 }  // namespace
 
 void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
+  if (const char* e = std::getenv("SPFAS_TRACE"); e && std::atoi(e) >= 2) {
+    lvprof = std::make_shared<KernelProf>(64);
+    lvprof->on = true;
+  }
   lv.clear();
   lv.reserve(32);
   lv.emplace_back();
@@ -503,6 +693,8 @@ void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
     const int nc = aggregate(H, 0.25, agg);
     if (nc >= H.n || nc * 10 > H.n * 9) break;   // coarsening stalled
     AmgLevel& F = lv.back();
+    F.vec = H.n < kVecRows;
+    if (!F.vec) build_sell(H, F, s);
     // members
     std::vector<int> mptr(nc + 1, 0), mem(H.n);
     for (int i = 0; i < H.n; ++i) mptr[agg[i] + 1]++;
@@ -596,6 +788,21 @@ void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
   flag.alloc(1);
 }
 
+std::string Amg::level_times() {
+  if (!lvprof) return "";
+  lvprof->collect();
+  std::string out = "AMG ms (down/up):";
+  char buf[64];
+  for (int k = 0; k + 1 < (int)lv.size(); ++k) {
+    std::snprintf(buf, sizeof buf, " %.1f/%.1f", lvprof->ms[3 * k], lvprof->ms[3 * k + 1]);
+    out += buf;
+  }
+  std::snprintf(buf, sizeof buf, " dense %.1f", lvprof->ms[63]);
+  out += buf;
+  lvprof->reset();
+  return out;
+}
+
 std::string Amg::describe() const {
   std::string out;
   for (const AmgLevel& L : lv) {
@@ -625,6 +832,14 @@ void Amg::numeric(hipStream_t s) {
     hipLaunchKernelGGL(k_invd, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.view, L.invd.p);
     LAUNCHCHECK();
   }
+  for (size_t k = 0; k + 1 < lv.size(); ++k) {
+    AmgLevel& F = lv[k];
+    if (F.vec) continue;
+    const int ne = (int)F.sval.n;
+    hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.view.diag,
+                       F.view.val, F.sval.p);
+    LAUNCHCHECK();
+  }
   AmgLevel& Lc = lv.back();
   hipLaunchKernelGGL(k_dense_fill, dim3(grid_for(nd, kBlock)), dim3(kBlock), 0, s, Lc.view, lu.p, nd);
   LAUNCHCHECK();
@@ -637,50 +852,80 @@ void Amg::numeric(hipStream_t s) {
 }
 
 void Amg::apply(const double* b, double* x, hipStream_t s) {
-  // level 0 uses the caller's b and x
+  // level 0 uses the caller's b and x; V(2,2) with the sweep pairs fused:
+  // down: [two sweeps from zero] [residual] [restriction];
+  // up:   [prolongation + sweep] [sweep].
   const int L = (int)lv.size();
   const double* bl = b;
-  double* xl = x;
   for (int k = 0; k < L - 1; ++k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
-    const int n = F.n;
-    const unsigned g = grid_for(n, kBlock);
-    // pre-smoothing: two Jacobi sweeps from zero
-    hipLaunchKernelGGL(k_jacobi0, dim3(g), dim3(kBlock), 0, s, n, F.invd.p, bl, F.t.p);
-    const bool fin = k == 0 && hook.prof;
-    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s, [&] {
-      if (fin) hipLaunchKernelGGL(k_jacobi<true>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl);
-      else hipLaunchKernelGGL(k_jacobi<false>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p, xl);
+    const unsigned g = grid_for(F.n, kBlock);
+    KernelProf* pf = k == 0 ? hook.prof : nullptr;
+    const double E = 8.0 * (double)F.sell_nnz, n = (double)F.n;
+    if (F.vec) {
+      timed(lvprof.get(), 3 * k, 0.0, s, [&] {
+        const unsigned gv = grid_for((size_t)F.n * kVecG, kBlock);
+        hipLaunchKernelGGL(k_amgv_pre, dim3(gv), dim3(kBlock), 0, s, F.view, F.invd.p, bl, F.t.p);
+        hipLaunchKernelGGL(k_amgv_resid, dim3(gv), dim3(kBlock), 0, s, F.view, bl, F.t.p, F.r.p);
+        hipLaunchKernelGGL(k_restrict_vec, dim3(grid_for((size_t)C.n * kVecG, kBlock)), dim3(kBlock), 0, s, C.n,
+                           F.mptr.p, F.mem.p, F.r.p, C.b.p);
+      });
+      LAUNCHCHECK();
+      bl = C.b.p;
+      continue;
+    }
+    timed(lvprof.get(), 3 * k, 0.0, s, [&] {
+    timed(pf, hook.pre_id, E + 24.0 * n, s, [&] {
+      if (pf) hipLaunchKernelGGL(k_amg_pre<true>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bl, F.t.p);
+      else hipLaunchKernelGGL(k_amg_pre<false>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bl, F.t.p);
     });
-    if (fin) hipLaunchKernelGGL(k_resid_restrict<true>, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
-    else hipLaunchKernelGGL(k_resid_restrict<false>, dim3(g), dim3(kBlock), 0, s, F.view, bl, xl, F.r.p);
+    timed(pf, hook.resid_id, E + 24.0 * n, s, [&] {
+      if (pf) hipLaunchKernelGGL(k_amg_resid<true>, dim3(g), dim3(kBlock), 0, s, F.sell, bl, F.t.p, F.r.p);
+      else hipLaunchKernelGGL(k_amg_resid<false>, dim3(g), dim3(kBlock), 0, s, F.sell, bl, F.t.p, F.r.p);
+    });
     hipLaunchKernelGGL(k_restrict, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.mptr.p, F.mem.p, F.r.p,
                        C.b.p);
     LAUNCHCHECK();
+    });
     bl = C.b.p;
-    xl = C.x.p;
   }
-  AmgLevel& Lc = lv.back();
-  hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd, Lc.t.p, bl, xl);
+  double* xl = L == 1 ? x : lv.back().x.p;
+  timed(lvprof.get(), 63, 0.0, s, [&] {
+    hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd, lv.back().t.p, bl, xl);
+  });
   LAUNCHCHECK();
   for (int k = L - 2; k >= 0; --k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
-    const int n = F.n;
-    const unsigned g = grid_for(n, kBlock);
+    const unsigned g = grid_for(F.n, kBlock);
     double* xf = (k == 0) ? x : F.x.p;
     const double* bf = (k == 0) ? b : F.b.p;
-    hipLaunchKernelGGL(k_prolong, dim3(g), dim3(kBlock), 0, s, n, F.agg.p, C.x.p, xf);
-    // post-smoothing: two Jacobi sweeps (ping-pong through t)
-    const bool fin = k == 0 && hook.prof;
-    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s, [&] {
-      if (fin) hipLaunchKernelGGL(k_jacobi<true>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p);
-      else hipLaunchKernelGGL(k_jacobi<false>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, xf, F.t.p);
+    KernelProf* pf = k == 0 ? hook.prof : nullptr;
+    const double E = 8.0 * (double)F.sell_nnz, n = (double)F.n;
+    if (F.vec) {
+      timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
+        const unsigned gv = grid_for((size_t)F.n * kVecG, kBlock);
+        hipLaunchKernelGGL(k_amgv_post1, dim3(gv), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, F.agg.p, C.x.p,
+                           F.r.p);
+        hipLaunchKernelGGL(k_amgv_post2, dim3(gv), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.r.p, xf);
+      });
+      LAUNCHCHECK();
+      continue;
+    }
+    timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
+    timed(pf, hook.post1_id, E + 36.0 * n, s, [&] {
+      if (pf)
+        hipLaunchKernelGGL(k_amg_post1<true>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.t.p, F.agg.p,
+                           C.x.p, F.r.p);
+      else
+        hipLaunchKernelGGL(k_amg_post1<false>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.t.p, F.agg.p,
+                           C.x.p, F.r.p);
     });
-    timed(k == 0 ? hook.prof : nullptr, hook.smooth_id, hook.smooth_bytes, s, [&] {
-      if (fin) hipLaunchKernelGGL(k_jacobi<true>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf);
-      else hipLaunchKernelGGL(k_jacobi<false>, dim3(g), dim3(kBlock), 0, s, F.view, F.invd.p, bf, F.t.p, xf);
+    timed(pf, hook.post2_id, E + 32.0 * n, s, [&] {
+      if (pf) hipLaunchKernelGGL(k_amg_post2<true>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.r.p, xf);
+      else hipLaunchKernelGGL(k_amg_post2<false>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.r.p, xf);
+    });
     });
     LAUNCHCHECK();
   }
@@ -781,7 +1026,7 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     LAUNCHCHECK();
     if (M) M->apply(s.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
-    timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
+    timed(hook.prof, hook.spmv2_id, hook.spmv_bytes, st,
           [&] {
             if (hook.prof)
               hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);

@@ -19,6 +19,7 @@
 // iteration to stop.
 #pragma once
 
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -29,6 +30,8 @@ namespace spfas {
 // Largest coarsest-level matrix inverted inside LDS (88^2 doubles < 64 KiB);
 // AMG coarsening continues until the level is at most this size.
 constexpr int kDenseLds = 88;
+// Levels with fewer rows than this run the group-per-row cycle kernels.
+constexpr int kVecRows = 150000;
 
 struct CsrView {
   int n = 0;
@@ -38,8 +41,27 @@ struct CsrView {
   const double* val = nullptr;
 };
 
+// SELL-64 copy of a level matrix for the V-cycle kernels: rows in slices of
+// 64 (one wavefront), each slice padded to its longest row and stored
+// column-major, so entry k of row i sits at sptr[i / 64] + 64 k + i % 64.
+// The diagonal is entry 0 of every row; padding entries have col = i and
+// value 0.  Values are FP32 (the preconditioner's matrix only; every
+// vector and every Galerkin product stays FP64).
+struct SellView {
+  int n = 0;
+  const int* sptr = nullptr;   // [ceil(n/64) + 1]
+  const int* col = nullptr;
+  const float* val = nullptr;
+};
+
 struct AmgLevel {
   int n = 0;
+  // SELL-64 copy for the cycle (levels that have a coarser level)
+  DVec<int> sptr, scol, smap;         // smap: CSR off index, -1 = diagonal, -2 = padding
+  DVec<float> sval;
+  SellView sell;
+  long long sell_nnz = 0;             // stored nonzeros (diagonal + off), without padding
+  bool vec = false;                   // small level: group-per-row kernels on the FP64 CSR, no SELL
   // matrix (level 0 refers to external storage through `view`)
   DVec<double> diag, val;
   DVec<int> ptr, col;
@@ -55,11 +77,14 @@ struct AmgLevel {
 };
 
 struct KernelProf;
-// Optional event timing of the finest-level SpMV and smoothing launches.
+// Optional event timing of the finest-level launches of the Krylov solver
+// (SpMV) and of the AMG cycle (two-sweep pre-smoothing, residual,
+// prolongation + sweep, last sweep); the AMG computes its own byte counts.
 struct ProfHook {
   KernelProf* prof = nullptr;
-  int spmv_id = -1, smooth_id = -1;
-  double spmv_bytes = 0.0, smooth_bytes = 0.0;
+  int spmv_id = -1, spmv2_id = -1;
+  double spmv_bytes = 0.0;
+  int pre_id = -1, resid_id = -1, post1_id = -1, post2_id = -1;
 };
 
 struct Amg {
@@ -76,6 +101,10 @@ struct Amg {
   void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
   int n_levels() const { return (int)lv.size(); }
   std::string describe() const;       // "n/nnz" per level, for diagnostics
+  // SPFAS_TRACE=2: event time of every level's down and up legs; level_times()
+  // returns the sums since its last call and clears them
+  std::shared_ptr<KernelProf> lvprof;
+  std::string level_times();
 };
 
 struct Krylov {
