@@ -269,10 +269,11 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * Each instrumented launch is bracketed by two events; `algo_bytes` is the
  * algorithmic HBM traffic of the launches (the minimum the method moves:
  * per flux unknown F and cell N of level 0, residual 40F + 24N, Newton
- * linearisation 56F + 24N, S x 24F + 24N; on the finest AMG level, with
- * E = stored nonzeros of S including the diagonal (FP32 value + int32
- * column each): two-sweep pre-smoothing 8E + 24N, residual 8E + 24N,
- * prolongation + sweep 8E + 36N, last sweep 8E + 32N).
+ * linearisation 56F + 24N; with E = stored nonzeros of S including the
+ * diagonal: S x with its dot products 12E + 24N (FP64 value + int32
+ * column per entry); on the finest AMG level (FP32 value + int32 column):
+ * two-sweep pre-smoothing 8E + 24N, residual 8E + 24N, prolongation +
+ * sweep 8E + 36N, last sweep 8E + 32N).
  */
 typedef enum {
   SPFAS_PROF_FINE_RESID = 0,      /* fine residual, also inside Alg. 1 trials   */

@@ -65,6 +65,16 @@ __device__ inline double reduce_parts_max(const double* parts, int n, double* sh
   return block_max(v, sh);
 }
 
+// Block index remapped so that each of the 8 XCDs, which receive the blocks
+// of a launch round-robin, works on one contiguous range of logical blocks
+// (neighbouring rows then share that XCD's L2).  A bijection on
+// [0, gridDim.x) for any grid size.
+__device__ inline int xcd_block() {
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q0 = nb >> 3, r = nb & 7, x = b & 7, q = b >> 3;
+  return x * q0 + (x < r ? x : r) + q;
+}
+
 // Number of blocks of a reducing grid-stride kernel over n items.
 inline int reduce_grid(int64_t n) {
   int64_t g = (n + kBlock - 1) / kBlock;

@@ -146,20 +146,24 @@ void setup_fine_solver(Hierarchy& h) {
   launch_fine_linearize(f.view(), false, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
   f.alpha = a;
   HIPCHECK(hipStreamSynchronize(s));
-  w.amg.setup(w.S, s);
+  w.amg.setup(w.S, s, true);
   if (trace_on()) std::fprintf(stderr, "[spfas] level 0 AMG: %s\n", w.amg.describe().c_str());
   // event timing hooks of the finest-level Krylov SpMV and Jacobi sweeps
   ProfHook hk;
   hk.prof = &h.prof;
   hk.spmv_id = SPFAS_PROF_FINE_SPMV;
   hk.spmv2_id = SPFAS_PROF_FINE_SPMV2;
-  hk.spmv_bytes = 24.0 * nf + 24.0 * n;
+  hk.spmv_bytes = 24.0 * nf + 32.0 * n;
   hk.pre_id = SPFAS_PROF_FINE_AMG_PRE;
   hk.resid_id = SPFAS_PROF_FINE_AMG_RESID;
   hk.post1_id = SPFAS_PROF_FINE_AMG_POST1;
   hk.post2_id = SPFAS_PROF_FINE_AMG_POST2;
   w.kry.hook = hk;
   w.amg.hook = hk;
+  if (w.amg.lv[0].sval64.n) {   // S products read the SELL-64 copy: value + column per stored entry
+    w.kry.sell64 = &w.amg.lv[0].sell64;
+    w.kry.hook.spmv_bytes = 12.0 * (double)w.amg.lv[0].sell_nnz + 24.0 * n;
+  }
 }
 
 static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double step) {

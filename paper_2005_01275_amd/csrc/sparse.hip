@@ -36,40 +36,70 @@ void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s) {
   LAUNCHCHECK();
 }
 
+// Row products of the two matrix layouts the Krylov solvers read.
+__device__ inline double row_dot(const CsrView& A, int i, const double* __restrict__ x) {
+  double a = A.diag[i] * x[i];
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+  return a;
+}
+
+__device__ inline double row_dot(const Sell64View& A, int i, const double* __restrict__ x) {
+  const int sl = i >> 6;
+  const int a0 = A.sptr[sl];
+  const int width = (A.sptr[sl + 1] - a0) >> 6;
+  int e = a0 + (i & 63);
+  double a = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < width; ++k, e += 64) a += A.val[e] * x[A.col[e]];
+  return a;
+}
+
+// Rows [lo, hi) of the logical block: contiguous chunks (multiples of the
+// block size) in XCD-aware order.
+__device__ inline void block_rows(int n, int& lb, int& lo, int& hi) {
+  const int G = (int)gridDim.x;
+  lb = xcd_block();
+  const int chunk = ((n + G - 1) / G + kBlock - 1) / kBlock * kBlock;
+  lo = lb * chunk;
+  hi = min(n, lo + chunk);
+}
+
 // y = A x; parts = sum_i w_i y_i (w may be x itself or another vector).
 // The template flag only separates the finest-level launches by name.
-template <bool Finest>
-__global__ void __launch_bounds__(kBlock) k_spmv_dot(CsrView A, const double* __restrict__ x, double* __restrict__ y,
+template <class Mat, bool Finest>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat A, const double* __restrict__ x, double* __restrict__ y,
                                                      const double* __restrict__ w, double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
+  int lb, lo, hi;
+  block_rows(A.n, lb, lo, hi);
   double acc = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x) {
-    double a = A.diag[i] * x[i];
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
+    const double a = row_dot(A, i, x);
     y[i] = a;
     acc += w[i] * a;
   }
   acc = block_sum(acc, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+  if (threadIdx.x == 0) parts[lb] = acc;
 }
 
 // y = A x; parts0 = sum w0*y, parts1 = sum y*y
-template <bool Finest>
-__global__ void __launch_bounds__(kBlock) k_spmv_dot2(CsrView A, const double* __restrict__ x, double* __restrict__ y,
+template <class Mat, bool Finest>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot2(Mat A, const double* __restrict__ x, double* __restrict__ y,
                                                       const double* __restrict__ w0, double* __restrict__ parts0,
                                                       double* __restrict__ parts1) {
   __shared__ double sh[kBlock / 64];
+  int lb, lo, hi;
+  block_rows(A.n, lb, lo, hi);
   double a0 = 0.0, a1 = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += gridDim.x * blockDim.x) {
-    double a = A.diag[i] * x[i];
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
+    const double a = row_dot(A, i, x);
     y[i] = a;
     a0 += w0[i] * a;
     a1 += a * a;
   }
   a0 = block_sum(a0, sh);
   a1 = block_sum(a1, sh);
-  if (threadIdx.x == 0) { parts0[blockIdx.x] = a0; parts1[blockIdx.x] = a1; }
+  if (threadIdx.x == 0) { parts0[lb] = a0; parts1[lb] = a1; }
 }
 
 __global__ void __launch_bounds__(kBlock) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
@@ -196,7 +226,7 @@ __device__ inline void sell_row(const SellView& A, int i, int& e, int& width) {
 template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_amg_pre(SellView A, const double* __restrict__ w,
                                                     const double* __restrict__ b, double* __restrict__ x2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   int e, width;
   sell_row(A, i, e, width);
@@ -214,7 +244,7 @@ __global__ void __launch_bounds__(kBlock) k_amg_pre(SellView A, const double* __
 template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_amg_resid(SellView A, const double* __restrict__ b,
                                                       const double* __restrict__ x, double* __restrict__ r) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   int e, width;
   sell_row(A, i, e, width);
@@ -231,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_amg_post1(SellView A, const double* 
                                                       const double* __restrict__ b, const double* __restrict__ x,
                                                       const int* __restrict__ agg, const double* __restrict__ ec,
                                                       double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   int e, width;
   sell_row(A, i, e, width);
@@ -249,7 +279,7 @@ template <bool Finest>
 __global__ void __launch_bounds__(kBlock) k_amg_post2(SellView A, const double* __restrict__ w,
                                                       const double* __restrict__ b, const double* __restrict__ x,
                                                       double* __restrict__ out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   int e, width;
   sell_row(A, i, e, width);
@@ -347,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_restrict_vec(int nc, const int* __re
 constexpr int kSellPad = INT_MIN;
 __global__ void __launch_bounds__(kBlock) k_sell_fill(int ne, const int* __restrict__ smap,
                                                       const double* __restrict__ diag, const double* __restrict__ off,
-                                                      float* __restrict__ val) {
+                                                      float* __restrict__ val, double* __restrict__ val64) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int m = smap[e];
@@ -355,6 +385,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(int ne, const int* __restr
   if (m >= 0) v = off[m];
   else if (m != kSellPad) v = diag[-1 - m];
   val[e] = (float)v;
+  if (val64) val64[e] = v;
 }
 
 __global__ void __launch_bounds__(kBlock) k_restrict(int nc, const int* __restrict__ mptr, const int* __restrict__ mem,
@@ -663,7 +694,7 @@ void build_sell(const HostCsr& H, AmgLevel& F, hipStream_t s) {
 
 }  // namespace
 
-void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
+void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max) {
   if (const char* e = std::getenv("SPFAS_TRACE"); e && std::atoi(e) >= 2) {
     lvprof = std::make_shared<KernelProf>(64);
     lvprof->on = true;
@@ -694,7 +725,16 @@ void Amg::setup(const CsrView& A0, hipStream_t s, int dense_max) {
     if (nc >= H.n || nc * 10 > H.n * 9) break;   // coarsening stalled
     AmgLevel& F = lv.back();
     F.vec = H.n < kVecRows;
-    if (!F.vec) build_sell(H, F, s);
+    if (!F.vec) {
+      build_sell(H, F, s);
+      if (sell64 && lv.size() == 1) {
+        F.sval64.alloc(F.sval.n);
+        F.sell64.n = F.n;
+        F.sell64.sptr = F.sptr.p;
+        F.sell64.col = F.scol.p;
+        F.sell64.val = F.sval64.p;
+      }
+    }
     // members
     std::vector<int> mptr(nc + 1, 0), mem(H.n);
     for (int i = 0; i < H.n; ++i) mptr[agg[i] + 1]++;
@@ -837,7 +877,7 @@ void Amg::numeric(hipStream_t s) {
     if (F.vec) continue;
     const int ne = (int)F.sval.n;
     hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.view.diag,
-                       F.view.val, F.sval.p);
+                       F.view.val, F.sval.p, F.sval64.p);
     LAUNCHCHECK();
   }
   AmgLevel& Lc = lv.back();
@@ -933,6 +973,43 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
 
 // ------------------------------------------------------------------ Krylov
 
+template <class Mat, bool Fin>
+static void spmv_dot_as(const Mat& A, int G, hipStream_t st, const double* x, double* y, const double* w, double* P) {
+  hipLaunchKernelGGL((k_spmv_dot<Mat, Fin>), dim3(G), dim3(kBlock), 0, st, A, x, y, w, P);
+}
+
+template <class Mat, bool Fin>
+static void spmv_dot2_as(const Mat& A, int G, hipStream_t st, const double* x, double* y, const double* w,
+                         double* P0, double* P1) {
+  hipLaunchKernelGGL((k_spmv_dot2<Mat, Fin>), dim3(G), dim3(kBlock), 0, st, A, x, y, w, P0, P1);
+}
+
+// y = A x and one partial dot product w.y per block (G blocks)
+static void spmv_dot(const CsrView& A, const Sell64View* A64, bool fin, int G, hipStream_t st, const double* x,
+                     double* y, const double* w, double* P) {
+  if (A64) {
+    if (fin) spmv_dot_as<Sell64View, true>(*A64, G, st, x, y, w, P);
+    else spmv_dot_as<Sell64View, false>(*A64, G, st, x, y, w, P);
+  } else {
+    if (fin) spmv_dot_as<CsrView, true>(A, G, st, x, y, w, P);
+    else spmv_dot_as<CsrView, false>(A, G, st, x, y, w, P);
+  }
+  LAUNCHCHECK();
+}
+
+// y = A x, partials of w.y and y.y per block
+static void spmv_dot2(const CsrView& A, const Sell64View* A64, bool fin, int G, hipStream_t st, const double* x,
+                      double* y, const double* w, double* P0, double* P1) {
+  if (A64) {
+    if (fin) spmv_dot2_as<Sell64View, true>(*A64, G, st, x, y, w, P0, P1);
+    else spmv_dot2_as<Sell64View, false>(*A64, G, st, x, y, w, P0, P1);
+  } else {
+    if (fin) spmv_dot2_as<CsrView, true>(A, G, st, x, y, w, P0, P1);
+    else spmv_dot2_as<CsrView, false>(A, G, st, x, y, w, P0, P1);
+  }
+  LAUNCHCHECK();
+}
+
 Krylov::~Krylov() {
   if (hscal) (void)hipHostFree(hscal);
 }
@@ -975,10 +1052,7 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
     hipLaunchKernelGGL(k_pcg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] {
-            if (hook.prof) hipLaunchKernelGGL(k_spmv_dot<true>, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0);
-            else hipLaunchKernelGGL(k_spmv_dot<false>, dim3(G), dim3(kBlock), 0, st, A, p.p, q.p, p.p, P0);
-          });
+          [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, p.p, q.p, p.p, P0); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_PQ);
     hipLaunchKernelGGL(k_pcg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, x, r.p, p.p, q.p, P0);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
@@ -1017,22 +1091,14 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     if (M) M->apply(p.p, y.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, p.p, y.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] {
-            if (hook.prof) hipLaunchKernelGGL(k_spmv_dot<true>, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0);
-            else hipLaunchKernelGGL(k_spmv_dot<false>, dim3(G), dim3(kBlock), 0, st, A, y.p, v.p, rh.p, P0);
-          });
+          [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, y.p, v.p, rh.p, P0); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RV);
     hipLaunchKernelGGL(k_bicg_s, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, r.p, v.p, s.p);
     LAUNCHCHECK();
     if (M) M->apply(s.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
     timed(hook.prof, hook.spmv2_id, hook.spmv_bytes, st,
-          [&] {
-            if (hook.prof)
-              hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);
-            else
-              hipLaunchKernelGGL(k_spmv_dot2<false>, dim3(G), dim3(kBlock), 0, st, A, z.p, t.p, s.p, P0, P1);
-          });
+          [&] { spmv_dot2(A, sell64, hook.prof != nullptr, G, st, z.p, t.p, s.p, P0, P1); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_TS);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P1, G, scal.p, (int)S_TT);
     hipLaunchKernelGGL(k_bicg_x, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, P0);

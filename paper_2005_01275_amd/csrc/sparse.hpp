@@ -54,12 +54,23 @@ struct SellView {
   const float* val = nullptr;
 };
 
+// The same SELL-64 pattern with FP64 values (finest level of the fine
+// solver, for the Krylov products).
+struct Sell64View {
+  int n = 0;
+  const int* sptr = nullptr;
+  const int* col = nullptr;
+  const double* val = nullptr;
+};
+
 struct AmgLevel {
   int n = 0;
   // SELL-64 copy for the cycle (levels that have a coarser level)
   DVec<int> sptr, scol, smap;         // smap: CSR off index, -1 = diagonal, -2 = padding
   DVec<float> sval;
+  DVec<double> sval64;                // level 0 only, when the Krylov products use SELL
   SellView sell;
+  Sell64View sell64;
   long long sell_nnz = 0;             // stored nonzeros (diagonal + off), without padding
   bool vec = false;                   // small level: group-per-row kernels on the FP64 CSR, no SELL
   // matrix (level 0 refers to external storage through `view`)
@@ -96,7 +107,8 @@ struct Amg {
   DVec<int> flag;                     // singular-pivot flag
   int cycles = 1;
   // host setup from the matrix pattern and setup values
-  void setup(const CsrView& A0, hipStream_t s, int dense_max = kDenseLds);
+  // sell64: also keep FP64 SELL values of level 0 (for Krylov::sell64)
+  void setup(const CsrView& A0, hipStream_t s, bool sell64 = false, int dense_max = kDenseLds);
   void numeric(hipStream_t s);        // coarse values, weights, dense LU
   void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
   int n_levels() const { return (int)lv.size(); }
@@ -110,6 +122,7 @@ struct Amg {
 struct Krylov {
   int n = 0;
   ProfHook hook;
+  const Sell64View* sell64 = nullptr;  // when set (same matrix as A), products read it instead of A
   DVec<double> r, z, p, q, rh, v, s, t, y, w;
   DVec<double> parts, scal;
   double* hscal = nullptr;
