@@ -136,6 +136,13 @@ typedef struct {
  *   coarsest_max_steps  smoothing steps on the coarsest level (paper: 10)
  *   lin_rtol, lin_max_it  inner Krylov tolerance and iteration limit
  *   x0_given            nonzero: p and sigma hold the initial guess on entry
+ *   lin_rtol_coarse     inner tolerance on coarse levels (<= 0: lin_rtol)
+ *   lin_target          > 0: a level-0 smoothing step at residual norm r
+ *                       solves to max(lin_rtol, min(0.1, lin_target*tol/r)),
+ *                       tol being the outer stopping threshold, so the last
+ *                       steps are not solved far below what the stop needs
+ *                       (inexact Newton forcing; the paper leaves the inner
+ *                       tolerance open); 0 = off
  */
 typedef struct {
   int32_t smoother;
@@ -149,6 +156,8 @@ typedef struct {
   double lin_rtol;
   int32_t lin_max_it;
   int32_t x0_given;
+  double lin_rtol_coarse;
+  double lin_target;
 } spfas_solve_opts;
 
 typedef struct {
@@ -160,6 +169,8 @@ typedef struct {
   double r0;                /* ||r(x0)||                                    */
   double r_final;           /* ||r(x)|| on return                          */
   double solve_ms;          /* wall time of the call (host clock)           */
+  int32_t rejected_steps;   /* smoothing steps dropped because the linearised
+                               system or its solve was not finite            */
 } spfas_stats;
 
 /* Fills *o with the paper's settings (Section 4): Newton, rtol 1e-8, atol

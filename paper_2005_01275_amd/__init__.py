@@ -42,6 +42,8 @@ class SolveOpts:
     lin_rtol: float = 1e-8
     lin_max_it: int = 500
     x0_given: int = 0
+    lin_rtol_coarse: float = 0.0
+    lin_target: float = 0.0
 
     def c(self):
         o = N.spfas_solve_opts()

@@ -51,13 +51,14 @@ class spfas_solve_opts(C.Structure):
     _fields_ = [("smoother", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double), ("max_it", C.c_int32),
                 ("bt_nmax", C.c_int32), ("bt_theta", C.c_double), ("dp_cap", C.c_double),
                 ("coarsest_max_steps", C.c_int32), ("lin_rtol", C.c_double), ("lin_max_it", C.c_int32),
-                ("x0_given", C.c_int32)]
+                ("x0_given", C.c_int32), ("lin_rtol_coarse", C.c_double), ("lin_target", C.c_double)]
 
 
 class spfas_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("lin_iters", C.c_int32), ("bt_halvings", C.c_int32),
                 ("smoothing_steps", C.c_int32), ("stopped_after_presmooth", C.c_int32),
-                ("r0", C.c_double), ("r_final", C.c_double), ("solve_ms", C.c_double)]
+                ("r0", C.c_double), ("r_final", C.c_double), ("solve_ms", C.c_double),
+                ("rejected_steps", C.c_int32)]
 
 
 _lib = None

@@ -49,6 +49,9 @@ struct Opts {
   int coarsest_max = 10;
   double lin_rtol = 1e-8;
   int lin_max_it = 500;
+  double lin_rtol_coarse = 0.0;  // <= 0: lin_rtol
+  double lin_target = 0.0;       // inexact-Newton forcing on level 0; 0 = off
+  double stop_tol = 0.0;         // outer stopping threshold of the running solve
 };
 
 static Opts make_opts(const spfas_solve_opts& o, bool newton) {
@@ -63,6 +66,9 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
   r.coarsest_max = o.coarsest_max_steps;
   r.lin_rtol = o.lin_rtol;
   r.lin_max_it = o.lin_max_it;
+  r.lin_rtol_coarse = o.lin_rtol_coarse > 0.0 ? o.lin_rtol_coarse : o.lin_rtol;
+  r.lin_target = o.lin_target;
+  require(o.lin_target >= 0.0, "lin_target must be non-negative");
   require(r.max_it >= 0 && r.bt_nmax >= 0 && r.coarsest_max >= 0 && r.lin_max_it > 0, "negative iteration limits");
   require(r.bt_theta > 0.0 && r.bt_theta <= 1.0, "bt_theta must be in (0, 1]");
   require(r.rtol >= 0.0 && r.atol >= 0.0 && r.lin_rtol > 0.0, "tolerances must be non-negative");
@@ -188,13 +194,25 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   w.amg.numeric(s);
   double* dp = w.dx.p + nf;
   int it;
+  double eta = o.lin_rtol;
+  if (o.lin_target > 0.0 && o.stop_tol > 0.0 && r_x > 0.0)
+    eta = std::max(eta, std::min(0.1, o.lin_target * o.stop_tol / r_x));
   if (o.newton)
-    it = w.kry.bicgstab(w.S, &w.amg, w.rhs.p, dp, o.lin_rtol, o.lin_max_it, s);
+    it = w.kry.bicgstab(w.S, &w.amg, w.rhs.p, dp, eta, o.lin_max_it, s);
   else
-    it = w.kry.pcg(w.S, &w.amg, w.rhs.p, dp, o.lin_rtol, o.lin_max_it, s);
+    it = w.kry.pcg(w.S, &w.amg, w.rhs.p, dp, eta, o.lin_max_it, s);
   st.lin_iters += it;
-  const int G = launch_fine_backsub(f.view(), o.newton, w.x.p, w.dx.p, h.parts.p, s);
-  const double mx = check_finite(h.host_max(h.parts.p, G), "Newton/Picard step");
+  double mx = HUGE_VAL;
+  if (!w.kry.failed) {
+    const int G = launch_fine_backsub(f.view(), o.newton, w.x.p, w.dx.p, h.parts.p, s);
+    mx = h.host_max(h.parts.p, G);
+  }
+  if (!std::isfinite(mx)) {   // non-finite linearisation or linear solve: the step is rejected
+    st.rejected_steps++;
+    st.smoothing_steps++;
+    if (trace_on()) std::fprintf(stderr, "[spfas] level 0: step rejected (non-finite linear solve)\n");
+    return r_x;
+  }
   const double scale = (o.cap > 0.0 && mx > o.cap) ? o.cap / mx : 1.0;
   double r_new = r_x;
   const double step = backtrack([&](double sl) { return fine_rnorm(h, w.x.p, w.dx.p, sl * scale); }, r_x,
@@ -263,10 +281,12 @@ static void store_state(Hierarchy& h, const spfas_problem& prob, double* p, doub
 
 // ------------------------------------------------------------------ drivers
 
-static int single_level(Hierarchy& h, const Opts& o, spfas_stats& st) {
+static int single_level(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
   double r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "initial residual");
   st.r0 = r;
-  const double tol = std::max(o.rtol * r, o.atol);
+  const double tol = std::max(o_in.rtol * r, o_in.atol);
+  Opts o = o_in;
+  o.stop_tol = tol;
   int rc = SPFAS_NOT_CONVERGED;
   for (int it = 0;; ++it) {
     if (r <= tol) { rc = SPFAS_OK; break; }
@@ -313,13 +333,22 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
     launch_H_assemble(C, s);
     C.amg.numeric(s);
     if (o.newton)
-      it = C.kry.bicgstab(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol, o.lin_max_it, s);
+      it = C.kry.bicgstab(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o.lin_max_it, s);
     else
-      it = C.kry.pcg(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol, o.lin_max_it, s);
+      it = C.kry.pcg(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o.lin_max_it, s);
     st.lin_iters += it;
   }
-  const int G = launch_coarse_backsub(C, C.lam.p, C.dx.p, h.parts.p, s);
-  const double mx = check_finite(h.host_max(h.parts.p, G), "coarse Newton/Picard step");
+  double mx = HUGE_VAL;
+  if (!(C.nl > 0 && C.kry.failed)) {
+    const int G = launch_coarse_backsub(C, C.lam.p, C.dx.p, h.parts.p, s);
+    mx = h.host_max(h.parts.p, G);
+  }
+  if (!std::isfinite(mx)) {   // non-finite local or hybridised solve: the step is rejected
+    st.rejected_steps++;
+    st.smoothing_steps++;
+    if (trace_on()) std::fprintf(stderr, "[spfas] level %d: step rejected (non-finite linear solve)\n", l);
+    return r_x;
+  }
   const double scale = (o.cap > 0.0 && mx > o.cap) ? o.cap / mx : 1.0;
   double r_new = r_x;
   const double step = backtrack([&](double sl) { return coarse_rnorm(h, l, C.x.p, C.dx.p, sl * scale); }, r_x,
@@ -406,10 +435,12 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
     coarse_smooth(h, l, o, r_new, st);
 }
 
-int run_fas(Hierarchy& h, const Opts& o, spfas_stats& st) {
+int run_fas(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
   double r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "initial residual");
   st.r0 = r;
-  const double tol = std::max(o.rtol * r, o.atol);
+  const double tol = std::max(o_in.rtol * r, o_in.atol);
+  Opts o = o_in;
+  o.stop_tol = tol;
   int rc = SPFAS_NOT_CONVERGED;
   for (int it = 0;; ++it) {
     if (r <= tol) { rc = SPFAS_OK; break; }

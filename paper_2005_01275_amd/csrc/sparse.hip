@@ -1041,7 +1041,8 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
   LAUNCHCHECK();
   const double bb = read_slot(hscal, scal.p, S_BB, st);
-  if (!(bb > 0.0)) return 0;
+  failed = !std::isfinite(bb);
+  if (!(bb > 0.0) || failed) return 0;
   const double tol2 = rtol * rtol * bb;
   int it = 0;
   int cur = S_RZ0, old = S_RZ1;
@@ -1059,7 +1060,12 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     LAUNCHCHECK();
     std::swap(cur, old);
     const double rr = read_slot(hscal, scal.p, S_RR, st);
-    if (!std::isfinite(rr)) fail(SPFAS_ERR_NUMERIC, "non-finite residual in PCG");
+    if (!std::isfinite(rr)) {   // breakdown or non-finite operator: report, leave x = 0
+      failed = true;
+      hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+      ++it;
+      break;
+    }
     if (rr <= tol2) { ++it; break; }
   }
   (void)g1;
@@ -1079,7 +1085,8 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
   LAUNCHCHECK();
   const double bb = read_slot(hscal, scal.p, S_BB, st);
-  if (!(bb > 0.0)) return 0;
+  failed = !std::isfinite(bb);
+  if (!(bb > 0.0) || failed) return 0;
   const double tol2 = rtol * rtol * bb;
   int it = 0;
   int cur = S_RHO0, old = S_RHO1;
@@ -1107,7 +1114,12 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     LAUNCHCHECK();
     std::swap(cur, old);
     const double rr = read_slot(hscal, scal.p, S_RR, st);
-    if (!std::isfinite(rr)) fail(SPFAS_ERR_NUMERIC, "non-finite residual in BiCGStab");
+    if (!std::isfinite(rr)) {   // breakdown or non-finite operator: report, leave x = 0
+      failed = true;
+      hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+      ++it;
+      break;
+    }
     if (rr <= tol2) { ++it; break; }
   }
   iters += it;

@@ -127,6 +127,7 @@ struct Krylov {
   DVec<double> parts, scal;
   double* hscal = nullptr;
   int iters = 0;
+  bool failed = false;                // last solve met a non-finite value (x returned as 0)
   ~Krylov();
   void alloc(int n_);
   // returns the number of iterations; x is overwritten (zero initial guess)
