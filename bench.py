@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0, help="seed of the synthetic fields (the workload is seed 0)")
     ap.add_argument("--lin-rtol", type=float, default=1e-4)
     ap.add_argument("--lin-rtol-coarse", type=float, default=1e-2, help="<= 0: same as --lin-rtol")
-    ap.add_argument("--lin-target", type=float, default=0.0, help="level-0 inexact-Newton forcing, 0 = off")
+    ap.add_argument("--lin-target", type=float, default=0.03, help="level-0 inexact-Newton forcing, 0 = off")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     return ap.parse_args()

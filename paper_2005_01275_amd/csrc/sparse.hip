@@ -167,30 +167,60 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s(int n, double* __restrict__ s
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
 }
 
-// omega = (t.s)/(t.t); x += alpha y + omega z; r = s - omega t; parts = r.r
-__global__ void __launch_bounds__(kBlock) k_bicg_x(int n, const double* __restrict__ scal, double* __restrict__ x,
-                                                   const double* __restrict__ y, const double* __restrict__ z,
-                                                   double* __restrict__ r, const double* __restrict__ s,
-                                                   const double* __restrict__ t, double* __restrict__ parts) {
+// scal[slot0] = sum parts0, scal[slot1] = sum parts1 (fixed order); with
+// omega != 0 also scal[S_OMEGA] = TS / TT from the two new values.
+__global__ void __launch_bounds__(kBlock) k_finalize2(const double* __restrict__ parts0,
+                                                      const double* __restrict__ parts1, int G, double* scal,
+                                                      int slot0, int slot1, int omega) {
   __shared__ double sh[kBlock / 64];
-  const double alpha = scal[S_ALPHA];
-  const double tt = scal[S_TT];
-  const double omega = tt > 0.0 ? scal[S_TS] / tt : 0.0;
+  const double v0 = reduce_parts(parts0, G, sh);
+  const double v1 = reduce_parts(parts1, G, sh);
+  if (threadIdx.x == 0) {
+    scal[slot0] = v0;
+    scal[slot1] = v1;
+    if (omega) scal[S_OMEGA] = v1 > 0.0 ? v0 / v1 : 0.0;
+  }
+}
+
+// BiCGStab start: x = 0, r = rh = b, parts = b.b
+__global__ void __launch_bounds__(kBlock) k_bicg_init(int n, const double* __restrict__ b, double* __restrict__ x,
+                                                      double* __restrict__ r, double* __restrict__ rh,
+                                                      double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    x[i] += alpha * y[i] + omega * z[i];
-    const double ri = s[i] - omega * t[i];
-    r[i] = ri;
-    acc += ri * ri;
+    const double bi = b[i];
+    x[i] = 0.0;
+    r[i] = bi;
+    rh[i] = bi;
+    acc += bi * bi;
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
 }
 
-__global__ void k_set_omega(double* scal) {
-  const double tt = scal[S_TT];
-  scal[S_OMEGA] = tt > 0.0 ? scal[S_TS] / tt : 0.0;
+// x += alpha y + omega z; r = s - omega t; parts0 = r.r, parts1 = rh.r
+__global__ void __launch_bounds__(kBlock) k_bicg_xr(int n, const double* __restrict__ scal, double* __restrict__ x,
+                                                    const double* __restrict__ y, const double* __restrict__ z,
+                                                    double* __restrict__ r, const double* __restrict__ s,
+                                                    const double* __restrict__ t, const double* __restrict__ rh,
+                                                    double* __restrict__ parts0, double* __restrict__ parts1) {
+  __shared__ double sh[kBlock / 64];
+  const double alpha = scal[S_ALPHA];
+  const double omega = scal[S_OMEGA];
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    x[i] += alpha * y[i] + omega * z[i];
+    const double ri = s[i] - omega * t[i];
+    r[i] = ri;
+    a0 += ri * ri;
+    a1 += rh[i] * ri;
+  }
+  a0 = block_sum(a0, sh);
+  a1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) { parts0[blockIdx.x] = a0; parts1[blockIdx.x] = a1; }
 }
+
 
 __global__ void __launch_bounds__(kBlock) k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
@@ -1078,21 +1108,17 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   const int G = reduce_grid(n);
   double* P0 = parts.p;
   double* P1 = parts.p + kMaxParts;
-  hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
-  hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
-  hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, rh.p);
-  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, P0);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
+  int cur = S_RHO0, old = S_RHO1;
+  // x = 0, r = rh = b; ||b||^2 is also rho_0 = rh.r
+  hipLaunchKernelGGL(k_bicg_init, dim3(G), dim3(kBlock), 0, st, n, b, x, r.p, rh.p, P0);
+  hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P0, G, scal.p, (int)S_BB, cur, 0);
   LAUNCHCHECK();
   const double bb = read_slot(hscal, scal.p, S_BB, st);
   failed = !std::isfinite(bb);
   if (!(bb > 0.0) || failed) return 0;
   const double tol2 = rtol * rtol * bb;
   int it = 0;
-  int cur = S_RHO0, old = S_RHO1;
   for (; it < maxit; ++it) {
-    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, rh.p, r.p, P0);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
     hipLaunchKernelGGL(k_bicg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, r.p, p.p, v.p);
     LAUNCHCHECK();
     if (M) M->apply(p.p, y.p, st);
@@ -1106,11 +1132,11 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
     timed(hook.prof, hook.spmv2_id, hook.spmv_bytes, st,
           [&] { spmv_dot2(A, sell64, hook.prof != nullptr, G, st, z.p, t.p, s.p, P0, P1); });
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_TS);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P1, G, scal.p, (int)S_TT);
-    hipLaunchKernelGGL(k_bicg_x, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, P0);
-    hipLaunchKernelGGL(k_set_omega, dim3(1), dim3(1), 0, st, scal.p);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
+    // TS, TT and omega = TS / TT in one launch
+    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_TS, (int)S_TT, 1);
+    hipLaunchKernelGGL(k_bicg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, rh.p, P0, P1);
+    // ||r||^2 and the next rho = rh.r (into the slot of the previous rho)
+    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_RR, old, 0);
     LAUNCHCHECK();
     std::swap(cur, old);
     const double rr = read_slot(hscal, scal.p, S_RR, st);
