@@ -68,6 +68,23 @@ def copy_rate(torch, nbytes: int = 1 << 30, reps: int = 5) -> dict:
             "GBps": 2.0 * nbytes / (ms * 1e-3) / 1e9}
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary of this workload (each counter scaled by
+    what it reads for a 1 GiB copy), or None when there is no entry or the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_c2_60x220x85.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in t["sources"])
+    if hashlib.sha256(src).hexdigest() != t["sources_sha256"] or kernel not in t["kernels"]:
+        return None
+    return t["kernels"][kernel]["bytes_per_launch"]
+
+
 def cpu_baseline(n_full: int, vcycles_full: float) -> dict:
     """The CPU FP64 oracle timed on a bounded sample of the workload: the
     same recipe (log-normal top layers, channelised bottom layers, column
@@ -160,8 +177,9 @@ def main():
     dom = max(prof, key=lambda k: prof[k][1])
     nl, ms, by = prof[dom]
     achieved = (by / nl) / (ms / nl * 1e-3) / 1e9 if nl and ms > 0 else 0.0
+    traffic = measured_traffic(dom) if args.workload == "c2" and args.seed == 0 else None
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": 8000.0, "unit": "GB/s",
-                "frac": achieved / 8000.0, "traffic": None, "launches": nl,
+                "frac": achieved / 8000.0, "traffic": traffic, "traffic_unit": "HBM bytes per launch", "launches": nl,
                 "avg_us": 1000.0 * ms / max(nl, 1), "algo_bytes_per_launch": by / max(nl, 1),
                 "frac_of_measured_copy": achieved / copy["GBps"]}
     kernels = {k: {"launches": v[0], "total_ms": v[1], "avg_us": 1000.0 * v[1] / max(v[0], 1),
