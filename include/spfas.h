@@ -143,6 +143,11 @@ typedef struct {
  *                       steps are not solved far below what the stop needs
  *                       (inexact Newton forcing; the paper leaves the inner
  *                       tolerance open); 0 = off
+ *   newton_pcg          nonzero: Newton systems are first tried with PCG
+ *                       (they are nearly symmetric: the non-symmetric part
+ *                       is the kappa' term of E), falling back to BiCGStab
+ *                       from scratch on a breakdown or without convergence;
+ *                       0: BiCGStab only
  */
 typedef struct {
   int32_t smoother;
@@ -158,6 +163,7 @@ typedef struct {
   int32_t x0_given;
   double lin_rtol_coarse;
   double lin_target;
+  int32_t newton_pcg;
 } spfas_solve_opts;
 
 typedef struct {

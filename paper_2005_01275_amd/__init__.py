@@ -44,6 +44,7 @@ class SolveOpts:
     x0_given: int = 0
     lin_rtol_coarse: float = 0.0
     lin_target: float = 0.0
+    newton_pcg: int = 0
 
     def c(self):
         o = N.spfas_solve_opts()

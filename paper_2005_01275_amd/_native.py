@@ -51,7 +51,8 @@ class spfas_solve_opts(C.Structure):
     _fields_ = [("smoother", C.c_int32), ("rtol", C.c_double), ("atol", C.c_double), ("max_it", C.c_int32),
                 ("bt_nmax", C.c_int32), ("bt_theta", C.c_double), ("dp_cap", C.c_double),
                 ("coarsest_max_steps", C.c_int32), ("lin_rtol", C.c_double), ("lin_max_it", C.c_int32),
-                ("x0_given", C.c_int32), ("lin_rtol_coarse", C.c_double), ("lin_target", C.c_double)]
+                ("x0_given", C.c_int32), ("lin_rtol_coarse", C.c_double), ("lin_target", C.c_double),
+                ("newton_pcg", C.c_int32)]
 
 
 class spfas_stats(C.Structure):

@@ -52,6 +52,7 @@ struct Opts {
   double lin_rtol_coarse = 0.0;  // <= 0: lin_rtol
   double lin_target = 0.0;       // inexact-Newton forcing on level 0; 0 = off
   double stop_tol = 0.0;         // outer stopping threshold of the running solve
+  bool newton_pcg = false;       // PCG first on Newton systems, BiCGStab as fallback
 };
 
 static Opts make_opts(const spfas_solve_opts& o, bool newton) {
@@ -68,6 +69,7 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
   r.lin_max_it = o.lin_max_it;
   r.lin_rtol_coarse = o.lin_rtol_coarse > 0.0 ? o.lin_rtol_coarse : o.lin_rtol;
   r.lin_target = o.lin_target;
+  r.newton_pcg = o.newton_pcg != 0;
   require(o.lin_target >= 0.0, "lin_target must be non-negative");
   require(r.max_it >= 0 && r.bt_nmax >= 0 && r.coarsest_max >= 0 && r.lin_max_it > 0, "negative iteration limits");
   require(r.bt_theta > 0.0 && r.bt_theta <= 1.0, "bt_theta must be in (0, 1]");
@@ -104,6 +106,20 @@ static double backtrack(const std::function<double(double)>& rn_raw, double r_x,
   }
   r_new = r_s;
   return s;
+}
+
+// Krylov solve of a linearised system: PCG for Picard (symmetric);
+// BiCGStab for Newton, or PCG first with BiCGStab from scratch when PCG
+// breaks down or does not converge within the iteration limit.
+static int krylov_solve(Krylov& kry, const CsrView& A, Amg* M, const double* b, double* x, double rtol,
+                        const Opts& o, hipStream_t s) {
+  if (!o.newton) return kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
+  if (o.newton_pcg) {
+    const int it = kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
+    if (kry.converged) return it;
+    return it + kry.bicgstab(A, M, b, x, rtol, o.lin_max_it, s);
+  }
+  return kry.bicgstab(A, M, b, x, rtol, o.lin_max_it, s);
 }
 
 // SPFAS_TRACE=1 prints one line per smoothing step to stderr.
@@ -197,10 +213,7 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   double eta = o.lin_rtol;
   if (o.lin_target > 0.0 && o.stop_tol > 0.0 && r_x > 0.0)
     eta = std::max(eta, std::min(0.1, o.lin_target * o.stop_tol / r_x));
-  if (o.newton)
-    it = w.kry.bicgstab(w.S, &w.amg, w.rhs.p, dp, eta, o.lin_max_it, s);
-  else
-    it = w.kry.pcg(w.S, &w.amg, w.rhs.p, dp, eta, o.lin_max_it, s);
+  it = krylov_solve(w.kry, w.S, &w.amg, w.rhs.p, dp, eta, o, s);
   st.lin_iters += it;
   double mx = HUGE_VAL;
   if (!w.kry.failed) {
@@ -332,10 +345,7 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   if (C.nl > 0) {
     launch_H_assemble(C, s);
     C.amg.numeric(s);
-    if (o.newton)
-      it = C.kry.bicgstab(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o.lin_max_it, s);
-    else
-      it = C.kry.pcg(C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o.lin_max_it, s);
+    it = krylov_solve(C.kry, C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o, s);
     st.lin_iters += it;
   }
   double mx = HUGE_VAL;

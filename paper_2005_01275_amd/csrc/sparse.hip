@@ -1054,8 +1054,8 @@ void Krylov::alloc(int n_) {
   if (!hscal) HIPCHECK(hipHostMalloc((void**)&hscal, S_NSLOT * sizeof(double), hipHostMallocDefault));
 }
 
-static double read_slot(double* hscal, const double* scal, int slot, hipStream_t st) {
-  HIPCHECK(hipMemcpyAsync(hscal + slot, scal + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+static double read_slot(double* hscal, const double* scal, int slot, hipStream_t st, int count = 1) {
+  HIPCHECK(hipMemcpyAsync(hscal + slot, scal + slot, count * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   return hscal[slot];
 }
@@ -1072,10 +1072,12 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   LAUNCHCHECK();
   const double bb = read_slot(hscal, scal.p, S_BB, st);
   failed = !std::isfinite(bb);
+  converged = bb == 0.0;
   if (!(bb > 0.0) || failed) return 0;
   const double tol2 = rtol * rtol * bb;
   int it = 0;
   int cur = S_RZ0, old = S_RZ1;
+  static_assert(S_RR == S_PQ + 1, "p.Ap and r.r are read together");
   for (; it < maxit; ++it) {
     if (M) M->apply(r.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
@@ -1089,14 +1091,15 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
     LAUNCHCHECK();
     std::swap(cur, old);
-    const double rr = read_slot(hscal, scal.p, S_RR, st);
-    if (!std::isfinite(rr)) {   // breakdown or non-finite operator: report, leave x = 0
+    read_slot(hscal, scal.p, S_PQ, st, 2);
+    const double pq = hscal[S_PQ], rr = hscal[S_RR];
+    if (!std::isfinite(rr) || !(pq > 0.0)) {   // breakdown (p.Ap <= 0) or non-finite operator: x = 0
       failed = true;
       hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
       ++it;
       break;
     }
-    if (rr <= tol2) { ++it; break; }
+    if (rr <= tol2) { ++it; converged = true; break; }
   }
   (void)g1;
   iters += it;
@@ -1115,6 +1118,7 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   LAUNCHCHECK();
   const double bb = read_slot(hscal, scal.p, S_BB, st);
   failed = !std::isfinite(bb);
+  converged = bb == 0.0;
   if (!(bb > 0.0) || failed) return 0;
   const double tol2 = rtol * rtol * bb;
   int it = 0;
@@ -1146,7 +1150,7 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
       ++it;
       break;
     }
-    if (rr <= tol2) { ++it; break; }
+    if (rr <= tol2) { ++it; converged = true; break; }
   }
   iters += it;
   return it;

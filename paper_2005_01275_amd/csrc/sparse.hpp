@@ -127,7 +127,8 @@ struct Krylov {
   DVec<double> parts, scal;
   double* hscal = nullptr;
   int iters = 0;
-  bool failed = false;                // last solve met a non-finite value (x returned as 0)
+  bool failed = false;                // last solve met a non-finite value or a PCG breakdown (x returned as 0)
+  bool converged = false;             // last solve reached its tolerance
   ~Krylov();
   void alloc(int n_);
   // returns the number of iterations; x is overwritten (zero initial guess)

@@ -100,3 +100,32 @@ def test_operational_rtol_c1(smoother):
         assert st["converged"]
         rs, rp = fs.residual(s[ff], p)
         assert np.linalg.norm(np.concatenate([rs, rp])) <= 1.01e-8 * r0
+
+
+@pytest.mark.parametrize("kw", CASES + ["c1"])
+def test_newton_pcg_converged_and_vcycle(kw):
+    """Newton systems solved by PCG first (BiCGStab fallback) reach the same
+    root x* and, with near-exact inner solves, the same one-V-cycle map."""
+    import paper_2005_01275_amd as pk
+    print("case", kw, flush=True)
+    prob = problem(kw)
+    h, p_star, s_star = oracle_root(prob)
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    for fn in (H.fas_solve, H.newton_solve):
+        o = opts(pk.SPFAS_NEWTON, prob)
+        o.newton_pcg = 1
+        p, s, st = fn(prob, o)
+        assert st["converged"], st
+        assert np.linalg.norm(p - p_star) <= 1e-10 * np.linalg.norm(p_star)
+        assert np.linalg.norm(s - s_star) <= 1e-10 * np.linalg.norm(s_star)
+    o = Opts(newton=True, rtol=1e-8, atol=0.0, cap_c=prob.dp_cap_c)
+    lev = h.levels[0]
+    x0 = np.zeros(lev.n)
+    from oracle.levels import residual
+    r0 = np.linalg.norm(residual(lev, x0, h.b0, h.alpha))
+    x1 = nonlinear_mg(h, 0, x0, h.b0, o, stop_tol=o.rtol * r0)
+    so = opts(pk.SPFAS_NEWTON, prob, rtol=1e-8, lin=1e-14, max_it=1)
+    so.newton_pcg = 1
+    p, s, st = H.fas_solve(prob, so)
+    ref_p = x1[lev.n_flux:]
+    assert np.linalg.norm(p - ref_p) <= 1e-10 * np.linalg.norm(ref_p)
