@@ -11,6 +11,9 @@
 //     Q_sigma and the weights of the piecewise-constant projector (App. B).
 // Host code orchestrates the levels and builds the index plans.
 #include <algorithm>
+#include <cstdlib>
+#include <cstdio>
+#include <chrono>
 #include <cmath>
 #include <numeric>
 
@@ -654,6 +657,11 @@ void setup_coarse_levels(Hierarchy& h) {
     bad.alloc(4);
     bad.zero(s);
     PlanView pv = plan_view(T);
+    const bool tr_on = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
+    auto now_ms = [] {
+      return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    };
+    double t_a = now_ms();
     // ---- phase A: PV traces
     int n_faces_c = 0;
     while (n_faces_c < C.nf && C.h_kind[n_faces_c] != FK_BUBBLE) ++n_faces_c;
@@ -680,7 +688,11 @@ void setup_coarse_levels(Hierarchy& h) {
                          ones_l, T.trace.p, scr.p, sa, bad.p);
       LAUNCHCHECK();
       HIPCHECK(hipStreamSynchronize(s));
+      if (tr_on)
+        std::fprintf(stderr, "[spfas] setup level %d->%d PV traces: %d interfaces, max ns %zu, max npU %zu, %zu "
+                     "workgroups: %.1f ms\n", l, l + 1, n_faces_c, mx_ns, mx_npU, slots, now_ms() - t_a);
     }
+    const double t_b = now_ms();
     // ---- phase B: per aggregate
     {
       ScratchB sb;
@@ -705,6 +717,9 @@ void setup_coarse_levels(Hierarchy& h) {
                          T.trace.p, T.omega.p, T.Pptr.p, T.P.p, T.Eptr.p, T.E.p, T.eig.p, co, scr.p, sb, bad.p);
       LAUNCHCHECK();
       HIPCHECK(hipStreamSynchronize(s));
+      if (tr_on)
+        std::fprintf(stderr, "[spfas] setup level %d->%d aggregates: %d, max np %zu, max nd %zu, max nI %zu, %zu "
+                     "workgroups: %.1f ms\n", l, l + 1, T.n_agg, mx_np, mx_nd, mx_nI, slots, now_ms() - t_b);
     }
     std::vector<int> hb = bad.download(s);
     if (hb[0] != 0) {

@@ -2,6 +2,9 @@
 #include "hier.hpp"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 #include <numeric>
 
@@ -71,6 +74,7 @@ static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
 }
 
 void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
+  const double t_start = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
   validate_mesh(M, o);
   dim = M.dim;
   n_cells_in = M.n_cells;
@@ -107,6 +111,10 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
     Topo c = coarse_topology(topo[l], m);
     topo.push_back(std::move(c));
   }
+  if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
+    std::fprintf(stderr, "[spfas] setup: host topology, aggregation, renumbering %.1f ms\n",
+                 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() -
+                     t_start);
   if (host_only) return;
   HIPCHECK(hipHostMalloc((void**)&hpin, kMaxParts * sizeof(double) * 4, hipHostMallocDefault));
   parts.alloc(kMaxParts * 4);
@@ -232,8 +240,16 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   fine.f.zero(s);
   fine.g.zero(s);
   // ---------------- fine smoother (eliminated system and its AMG), coarse levels
+  const bool tr_on = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
+  auto now_ms = [] {
+    return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  };
+  double tp = now_ms();
   setup_fine_solver(*this);
+  if (tr_on) std::fprintf(stderr, "[spfas] setup: fine solver (S pattern, AMG) %.1f ms\n", now_ms() - tp);
+  tp = now_ms();
   setup_coarse_levels(*this);
+  if (tr_on) std::fprintf(stderr, "[spfas] setup: coarse levels %.1f ms\n", now_ms() - tp);
   HIPCHECK(hipStreamSynchronize(s));
 }
 

@@ -751,7 +751,7 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max) {
   }
   while (H.n > dense_max) {
     std::vector<int> agg;
-    const int nc = aggregate(H, 0.25, agg);
+    const int nc = aggregate(H, kStrength, agg);
     if (nc >= H.n || nc * 10 > H.n * 9) break;   // coarsening stalled
     AmgLevel& F = lv.back();
     F.vec = H.n < kVecRows;

@@ -30,6 +30,8 @@ namespace spfas {
 // Largest coarsest-level matrix inverted inside LDS (88^2 doubles < 64 KiB);
 // AMG coarsening continues until the level is at most this size.
 constexpr int kDenseLds = 88;
+// Strength of connection of the aggregation: |a_ij| >= kStrength max_k |a_ik|.
+constexpr double kStrength = 0.1;
 // Levels with fewer rows than this run the group-per-row cycle kernels.
 constexpr int kVecRows = 150000;
 
