@@ -15,15 +15,84 @@ __device__ inline void wg_fill(double* a, int n, double v) {
   wg_sync();
 }
 
-// In-place lower Cholesky A = L L^T (upper part left untouched).  Returns
-// false (in every thread) when a pivot is not positive.
-__device__ inline bool wg_chol(double* A, int n, int ld, int* flag) {
-  if (threadIdx.x == 0) *flag = 0;
-  wg_sync();
+// The routines below assume blockDim.x == 256 (the setup kernels' block).
+constexpr int kGemmTile = 64;   // output tile edge of the tiled product
+constexpr int kGemmKc = 16;     // depth of one staged slice
+constexpr int kCholNb = 32;     // panel width of the blocked factorisation and solves
+
+// C (m x n) = alpha op(A) op(B) + beta C, op = transpose when the flag is set
+// (A is m x k or k x m, B is k x n or n x k).  64 x 64 output tiles, 4 x 4
+// per thread, depth-16 slices of A and B staged in LDS.  lower_only skips
+// the tiles strictly above the diagonal (updates whose upper part is never
+// read).  C is not read when beta == 0: it may hold any bit pattern.
+__device__ inline void wg_gemm_acc(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
+                                   int ldc, int m, int n, int k, double alpha, double beta, bool lower_only) {
+  __shared__ double As[kGemmKc][kGemmTile + 1];
+  __shared__ double Bs[kGemmKc][kGemmTile + 1];
+  const int t = threadIdx.x;
+  const int tr = t >> 4, tc = t & 15;
+  for (int i0 = 0; i0 < m; i0 += kGemmTile)
+    for (int j0 = 0; j0 < n; j0 += kGemmTile) {
+      if (lower_only && j0 > i0) continue;
+      double acc[4][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+      for (int q0 = 0; q0 < k; q0 += kGemmKc) {
+        for (int e = t; e < kGemmKc * kGemmTile; e += 256) {
+          // contiguous memory runs along the fastest-varying index of the thread
+          int q, i;
+          if (ta) { q = e / kGemmTile; i = e % kGemmTile; } else { i = e / kGemmKc; q = e % kGemmKc; }
+          const int gi = i0 + i, gq = q0 + q;
+          As[q][i] = (gi < m && gq < k) ? (ta ? A[(size_t)gq * lda + gi] : A[(size_t)gi * lda + gq]) : 0.0;
+          int j, q2;
+          if (tb) { j = e / kGemmKc; q2 = e % kGemmKc; } else { q2 = e / kGemmTile; j = e % kGemmTile; }
+          const int gj = j0 + j, gq2 = q0 + q2;
+          Bs[q2][j] = (gj < n && gq2 < k) ? (tb ? B[(size_t)gj * ldb + gq2] : B[(size_t)gq2 * ldb + gj]) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int q = 0; q < kGemmKc; ++q) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) av[r] = As[q][tr * 4 + r];
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bv[c] = Bs[q][tc * 4 + c];
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[r][c] += av[r] * bv[c];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int gi = i0 + tr * 4 + r, gj = j0 + tc * 4 + c;
+          if (gi < m && gj < n) {
+            double* cp = C + (size_t)gi * ldc + gj;
+            *cp = (beta == 0.0) ? alpha * acc[r][c] : beta * *cp + alpha * acc[r][c];
+          }
+        }
+    }
+  __syncthreads();
+}
+
+// C (m x n) = op(A) op(B) (+ beta C); see wg_gemm_acc.
+__device__ inline void wg_gemm(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
+                               int ldc, int m, int n, int k, double beta = 0.0) {
+  wg_gemm_acc(A, lda, ta, B, ldb, tb, C, ldc, m, n, k, 1.0, beta, false);
+}
+
+// Unblocked in-place lower Cholesky of an n x n block; on a non-positive
+// pivot sets *flag = base + (1-based pivot index) and returns false.
+__device__ inline bool wg_chol_unblocked(double* A, int n, int ld, int* flag, int base) {
   for (int k = 0; k < n; ++k) {
     const double d = A[k * ld + k];
     if (!(d > 0.0)) {
-      if (threadIdx.x == 0) *flag = k + 1;   // 1-based index of the failing pivot
+      if (threadIdx.x == 0) *flag = base + k + 1;
       wg_sync();
       return false;
     }
@@ -39,50 +108,74 @@ __device__ inline bool wg_chol(double* A, int n, int ld, int* flag) {
     }
     wg_sync();
   }
+  return true;
+}
+
+// In-place lower Cholesky A = L L^T (upper part left untouched): right-
+// looking with 32-column panels; the trailing updates run on the tiled
+// product.  Returns false (in every thread) when a pivot is not positive,
+// with *flag = 1-based index of that pivot.
+__device__ inline bool wg_chol(double* A, int n, int ld, int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+  wg_sync();
+  for (int k0 = 0; k0 < n; k0 += kCholNb) {
+    const int kb = min(kCholNb, n - k0);
+    double* A11 = A + (size_t)k0 * ld + k0;
+    if (!wg_chol_unblocked(A11, kb, ld, flag, k0)) return false;
+    const int rem = n - k0 - kb;
+    if (rem <= 0) break;
+    // panel: every row below solves x L11^T = a
+    for (int i = threadIdx.x; i < rem; i += blockDim.x) {
+      double* row = A + (size_t)(k0 + kb + i) * ld + k0;
+      for (int j = 0; j < kb; ++j) {
+        double v = row[j];
+        for (int l = 0; l < j; ++l) v -= row[l] * A11[j * ld + l];
+        row[j] = v / A11[j * ld + j];
+      }
+    }
+    wg_sync();
+    double* L21 = A + (size_t)(k0 + kb) * ld + k0;
+    wg_gemm_acc(L21, ld, false, L21, ld, true, A + (size_t)(k0 + kb) * ld + k0 + kb, ld, rem, rem, kb, -1.0, 1.0,
+                true);
+  }
   return *flag == 0;
 }
 
-// B <- (L L^T)^{-1} B for B of n rows and nrhs columns (row-major, ldb).
+// B <- (L L^T)^{-1} B for B of n rows and nrhs columns (row-major, ldb):
+// forward then backward substitution in 32-row blocks, the off-diagonal
+// block updates on the tiled product.
 __device__ inline void wg_chol_solve(const double* L, int n, int ld, double* B, int nrhs, int ldb) {
-  for (int k = 0; k < n; ++k) {
-    const double d = L[k * ld + k];
-    for (int c = threadIdx.x; c < nrhs; c += blockDim.x) B[k * ldb + c] /= d;
+  for (int k0 = 0; k0 < n; k0 += kCholNb) {
+    const int kb = min(kCholNb, n - k0);
+    const double* L11 = L + (size_t)k0 * ld + k0;
+    for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+      for (int j = 0; j < kb; ++j) {
+        double v = B[(size_t)(k0 + j) * ldb + c];
+        for (int l = 0; l < j; ++l) v -= L11[j * ld + l] * B[(size_t)(k0 + l) * ldb + c];
+        B[(size_t)(k0 + j) * ldb + c] = v / L11[j * ld + j];
+      }
     wg_sync();
-    const int rem = n - k - 1;
-    for (int e = threadIdx.x; e < rem * nrhs; e += blockDim.x) {
-      const int i = k + 1 + e / nrhs, c = e % nrhs;
-      B[i * ldb + c] -= L[i * ld + k] * B[k * ldb + c];
-    }
-    wg_sync();
+    const int rem = n - k0 - kb;
+    if (rem > 0)
+      wg_gemm_acc(L + (size_t)(k0 + kb) * ld + k0, ld, false, B + (size_t)k0 * ldb, ldb, false,
+                  B + (size_t)(k0 + kb) * ldb, ldb, rem, nrhs, kb, -1.0, 1.0, false);
   }
-  for (int k = n - 1; k >= 0; --k) {
-    const double d = L[k * ld + k];
-    for (int c = threadIdx.x; c < nrhs; c += blockDim.x) B[k * ldb + c] /= d;
+  const int nblk = (n + kCholNb - 1) / kCholNb;
+  for (int bk = nblk - 1; bk >= 0; --bk) {
+    const int k0 = bk * kCholNb;
+    const int kb = min(kCholNb, n - k0);
+    const double* L11 = L + (size_t)k0 * ld + k0;
+    for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+      for (int j = kb - 1; j >= 0; --j) {
+        double v = B[(size_t)(k0 + j) * ldb + c];
+        for (int l = j + 1; l < kb; ++l) v -= L11[l * ld + j] * B[(size_t)(k0 + l) * ldb + c];
+        B[(size_t)(k0 + j) * ldb + c] = v / L11[j * ld + j];
+      }
     wg_sync();
-    for (int e = threadIdx.x; e < k * nrhs; e += blockDim.x) {
-      const int i = e / nrhs, c = e % nrhs;
-      B[i * ldb + c] -= L[k * ld + i] * B[k * ldb + c];
-    }
-    wg_sync();
+    if (k0 > 0)
+      wg_gemm_acc(L + (size_t)k0 * ld, ld, true, B + (size_t)k0 * ldb, ldb, false, B, ldb, k0, nrhs, kb, -1.0, 1.0,
+                  false);
   }
-}
-
-// C (m x n) = op(A) op(B) with op = transpose when the flag is set.
-// A is (m x k) or (k x m), B is (k x n) or (n x k).
-__device__ inline void wg_gemm(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
-                               int ldc, int m, int n, int k, double beta = 0.0) {
-  for (int e = threadIdx.x; e < m * n; e += blockDim.x) {
-    const int i = e / n, j = e % n;
-    double s = 0.0;
-    for (int q = 0; q < k; ++q) {
-      const double a = ta ? A[q * lda + i] : A[i * lda + q];
-      const double b = tb ? B[j * ldb + q] : B[q * ldb + j];
-      s += a * b;
-    }
-    // C is not read when beta == 0: it may hold any bit pattern (NaN included)
-    C[i * ldc + j] = (beta == 0.0) ? s : beta * C[i * ldc + j] + s;
-  }
-  wg_sync();
 }
 
 // Symmetric eigen-decomposition by the cyclic Jacobi method with the

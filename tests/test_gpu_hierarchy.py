@@ -16,6 +16,9 @@ CASES = [
          dirichlet=((0, 0), (1, 1)), permute=True),
     dict(shape=(6, 4, 4), box=(2, 2, 2), m=3, n_levels=3, seed=3, anisotropic=True, permute=True),
     dict(shape=(9, 7), box=(4, 3), m=2, n_levels=3, seed=4, sigma=1.5),
+    # level-1 -> 2 local problems of 64 coarse cells (192 pressure unknowns,
+    # interface problems of 384): the blocked dense routines of the setup
+    dict(shape=(32, 16, 16), box=(4, 4, 4), m=3, n_levels=3, seed=5, anisotropic=True, permute=True),
 ]
 
 
