@@ -266,7 +266,7 @@ int spfas_get_permutation(const spfas_hierarchy* h, int32_t level, int32_t* cell
                           int32_t* flux_order);
 
 typedef enum {
-  SPFAS_OP_EIGVALS = 0,  /* level l: spectrum of each aggregate's L_A, ascending, aggregates in canonical order */
+  SPFAS_OP_EIGVALS = 0,  /* level l: the m_A smallest eigenvalues of each aggregate's L_A, ascending, aggregates in canonical order */
   SPFAS_OP_PP = 1,       /* level l: P_A blocks (n_pA x m_A, row-major), canonical aggregate order          */
   SPFAS_OP_PSIGMA = 2,   /* level l: P_sigma as dense [n_flux(l) x n_flux(l+1)], row-major, canonical      */
   SPFAS_OP_MLOC = 3,     /* level l+1: static M^{l+1}_A blocks (k_A x k_A, row-major), canonical order     */

@@ -175,9 +175,14 @@ __global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, 
 // ------------------------------------------------------------------ phase B
 
 struct ScratchB {
-  size_t ma, da, ci, t, l, v, pl, tmp, vec;
+  size_t ma, da, ci, t, l, v, pl, tmp, vec, ev;
   size_t total;
 };
+
+// Local problems with more pressure unknowns than this use block inverse
+// iteration for their smallest eigenpairs (falling back to the full Jacobi
+// decomposition if it does not converge); smaller ones use Jacobi.
+constexpr int kSmallEig = 32;
 
 struct CoarseOut {
   const int* lfptr;     // coarse local flux lists
@@ -200,7 +205,8 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
                                                       const int* __restrict__ Pptr, double* __restrict__ P,
                                                       const int* __restrict__ Eptr, double* __restrict__ E,
                                                       double* __restrict__ eig, CoarseOut co,
-                                                      double* __restrict__ scratch, ScratchB sb, int* __restrict__ bad) {
+                                                      double* __restrict__ scratch, ScratchB sb, int* __restrict__ bad,
+                                                      unsigned long long* __restrict__ phase_ns) {
   __shared__ int flag;
   __shared__ double red[2 * kBlock];
   __shared__ double cs[2 * (kBlock + 1)];
@@ -216,6 +222,23 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
   double* Pl = V + sb.v;
   double* tmp = Pl + sb.pl;
   double* vec = tmp + sb.tmp;   // 4 vectors of length npA + one of length nd
+  double* EX = vec + sb.vec;     // subspace iteration: X, Y, LX (npA x kSubMax), G, W, theta
+  double* EY = EX + 2 * kBlock * kSubMax;
+  double* ELX = EY + 2 * kBlock * kSubMax;
+  double* EG = ELX + 2 * kBlock * kSubMax;
+  double* EW = EG + kSubMax * kSubMax;
+  double* Eth = EW + kSubMax * kSubMax;
+  // optional phase timing (diagnostics): wall-clock ticks (10 ns) per phase, summed by thread 0
+  unsigned long long tick = wall_clock64();
+  auto phase = [&](int id) {
+    if (!phase_ns) return;
+    wg_sync();
+    if (threadIdx.x == 0) {
+      const unsigned long long now = wall_clock64();
+      atomicAdd(phase_ns + id, (now - tick) * 10ull);
+      tick = now;
+    }
+  };
   for (int A = blockIdx.x; A < n_agg; A += gridDim.x) {
     const int nI = pl.n_int[A];
     const int nd = pl.dof_ptr[A + 1] - pl.dof_ptr[A];
@@ -253,6 +276,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       rowbase += m;
       wg_sync();
     }
+    phase(0);
     // 2-3. T = M_int^{-1} D_int^T  (nI x npA)
     for (int e = threadIdx.x; e < nI * npA; e += blockDim.x) {
       const int s = e / npA, r = e % npA;
@@ -280,46 +304,75 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       }
     }
     wg_sync();
-    // 4. eigen-decomposition
-    wg_jacobi_eig(L, npA, V, npA, npA, cs, prs, red);
-    // 5. order the spectrum (thread 0; small sizes)
-    if (threadIdx.x == 0) {
-      double* lam = eig + pl.pd_ptr[A];
-      // insertion sort of (lambda, index) into tmp (as doubles) -> sorted eigenvalues and indices
-      int* ord = (int*)tmp;
-      for (int i = 0; i < npA; ++i) ord[i] = i;
-      for (int i = 1; i < npA; ++i) {
-        const int oi = ord[i];
-        const double li = L[oi * npA + oi];
-        int j = i - 1;
-        while (j >= 0 && L[ord[j] * npA + ord[j]] > li) { ord[j + 1] = ord[j]; --j; }
-        ord[j + 1] = oi;
-      }
-      for (int i = 0; i < npA; ++i) lam[i] = L[ord[i] * npA + ord[i]];
-      for (int i = 0; i < mA && i < 64; ++i) idx_small[i] = ord[i];
-    }
-    wg_sync();
-    const int i0 = idx_small[0];
-    // 6. P_A = [q_PV, v_2..v_m]
+    phase(1);
+    // q_PV = 1^l|_A / ||1^l|_A||
     if (threadIdx.x == 0) {
       double nn = 0.0;
       for (int r = 0; r < npA; ++r) nn += ones[pdA[r]] * ones[pdA[r]];
       scal[0] = sqrt(nn);
+      double rho = 0.0;
+      for (int r = 0; r < npA; ++r) rho = fmax(rho, L[r * npA + r]);
+      scal[4] = rho;
     }
     wg_sync();
     for (int r = threadIdx.x; r < npA; r += blockDim.x) q[r] = ones[pdA[r]] / scal[0];
     wg_sync();
+    // 4-5. the mA smallest eigenpairs of L_A: lambda_1 = 0 with eigenvector q,
+    // then block inverse iteration on L_A + rho q q^T (Cholesky factor in V);
+    // small or non-converging problems take the full Jacobi decomposition.
+    const int nev = mA - 1;
+    const int nbs = min(npA - 1, min(kSubMax, nev + 6));
+    bool sub = false;
+    if (npA > kSmallEig && nev >= 1) {
+      const double rho = scal[4];
+      for (int e = threadIdx.x; e < npA * npA; e += blockDim.x) V[e] = L[e] + rho * q[e / npA] * q[e % npA];
+      wg_sync();
+      if (wg_chol(V, npA, npA, &flag))
+        sub = wg_subspace_eig(L, V, q, npA, nbs, nev, rho, 1e-12, 300, EX, EY, ELX, EG, EW, Eth, cs, prs, red, &flag);
+    }
+    double* lam = eig + pl.pd_ptr[A];
+    if (sub) {
+      if (threadIdx.x == 0) {
+        double qlq = 0.0;
+        for (int r = 0; r < npA; ++r)
+          for (int c = 0; c < npA; ++c) qlq += q[r] * L[r * npA + c] * q[c];
+        lam[0] = qlq;
+        for (int j = 1; j < mA; ++j) lam[j] = Eth[j - 1];
+        for (int j = 0; j < mA && j < 64; ++j) idx_small[j] = j;
+      }
+    } else {
+      wg_jacobi_eig(L, npA, V, npA, npA, cs, prs, red);
+      // order the spectrum (thread 0; small sizes)
+      if (threadIdx.x == 0) {
+        int* ord = (int*)tmp;
+        for (int i = 0; i < npA; ++i) ord[i] = i;
+        for (int i = 1; i < npA; ++i) {
+          const int oi = ord[i];
+          const double li = L[oi * npA + oi];
+          int j = i - 1;
+          while (j >= 0 && L[ord[j] * npA + ord[j]] > li) { ord[j + 1] = ord[j]; --j; }
+          ord[j + 1] = oi;
+        }
+        for (int i = 0; i < mA; ++i) lam[i] = L[ord[i] * npA + ord[i]];
+        for (int i = 0; i < mA && i < 64; ++i) idx_small[i] = ord[i];
+      }
+    }
+    wg_sync();
+    const int i0 = idx_small[0];
+    // eigenvector j >= 1 of the ascending order, entry r
+    auto evec = [&](int r, int j) -> double { return sub ? EX[r * nbs + (j - 1)] : V[r * npA + idx_small[j]]; };
+    phase(2);
+    // 6. P_A = [q_PV, v_2..v_m]
     double* PA = P + Pptr[A];
     for (int r = threadIdx.x; r < npA; r += blockDim.x) PA[r * mA] = q[r];
     for (int j = 1; j < mA; ++j) {
-      const int col = idx_small[j];
       if (threadIdx.x == 0) {
         double d = 0.0;
-        for (int r = 0; r < npA; ++r) d += q[r] * V[r * npA + col];
+        for (int r = 0; r < npA; ++r) d += q[r] * evec(r, j);
         scal[1] = d;
       }
       wg_sync();
-      for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = V[r * npA + col] - scal[1] * q[r];
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = evec(r, j) - scal[1] * q[r];
       wg_sync();
       if (threadIdx.x == 0) {
         double nn = 0.0, mx = 0.0;
@@ -335,7 +388,28 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       wg_sync();
     }
     // pseudo-inverse of L_A on a vector: out = sum_{i != i0} V_i (V_i . in) / lambda_i
+    // (Jacobi path), or out = P (L_A + rho q q^T)^{-1} P in with P = I - q q^T
     auto lplus = [&](const double* in, double* out) {
+      if (sub) {
+        if (threadIdx.x == 0) {
+          double d = 0.0;
+          for (int r = 0; r < npA; ++r) d += q[r] * in[r];
+          scal[5] = d;
+        }
+        wg_sync();
+        for (int r = threadIdx.x; r < npA; r += blockDim.x) out[r] = in[r] - scal[5] * q[r];
+        wg_sync();
+        wg_chol_solve(V, npA, npA, out, 1, 1);
+        if (threadIdx.x == 0) {
+          double d = 0.0;
+          for (int r = 0; r < npA; ++r) d += q[r] * out[r];
+          scal[5] = d;
+        }
+        wg_sync();
+        for (int r = threadIdx.x; r < npA; r += blockDim.x) out[r] -= scal[5] * q[r];
+        wg_sync();
+        return;
+      }
       for (int i = threadIdx.x; i < npA; i += blockDim.x) {
         double s = 0.0;
         if (i != i0) {
@@ -352,6 +426,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       }
       wg_sync();
     };
+    phase(3);
     // 7-9. columns of P_sigma restricted to dofs(A): Pl (nd x kA)
     wg_fill(Pl, nd * kA, 0.0);
     for (int j = 1; j < mA; ++j) {
@@ -367,6 +442,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       }
       wg_sync();
     }
+    phase(4);
     for (int kf = 0; kf < nface; ++kf) {
       const int J = co.lfidx[co.lfptr[A] + kf];
       const int gpos = (co.c1[J] == A) ? pl.grp_pos_A[J] : pl.grp_pos_B[J];
@@ -430,6 +506,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       }
       wg_sync();
     }
+    phase(5);
     // 10. M^{l+1}_A = Pl^T M_A Pl
     double* Mc = co.M + co.mptr[A];
     if (lv.level0) {
@@ -450,6 +527,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
     // 12. interior block of P_sigma
     double* EA = E + Eptr[A];
     for (int e = threadIdx.x; e < nI * kA; e += blockDim.x) EA[e] = Pl[e];
+    phase(6);
     // 14. projector weights and coarse 1, u, volume
     for (int i = threadIdx.x; i < mA; i += blockDim.x) {
       double so = 0.0, su = 0.0;
@@ -468,6 +546,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
     wg_sync();
     for (int i = threadIdx.x; i < mA; i += blockDim.x) co.w[co.pptr[A] + i] = co.u[co.pptr[A] + i] / co.vol[A];
     wg_sync();
+    phase(7);
   }
 }
 
@@ -705,18 +784,33 @@ void setup_coarse_levels(Hierarchy& h) {
       sb.pl = mx_nd * mx_k;
       sb.tmp = std::max(mx_nd, mx_np + 8) * std::max<size_t>(mx_k, 1) + 8;
       sb.vec = 3 * mx_np + std::max(mx_nd, mx_np) + 8;
-      sb.total = sb.ma + sb.da + sb.ci + sb.t + sb.l + sb.v + sb.pl + sb.tmp + sb.vec + 8;
+      sb.ev = 3 * (size_t)(2 * kBlock) * kSubMax + 2 * kSubMax * kSubMax + kSubMax + 8;
+      sb.total = sb.ma + sb.da + sb.ci + sb.t + sb.l + sb.v + sb.pl + sb.tmp + sb.vec + sb.ev + 8;
       const size_t slots = slots_for(sb.total, T.n_agg);
       DVec<double> scr;
       scr.alloc(slots * sb.total);
+      DVec<unsigned long long> phase_ns;
+      if (tr_on) {
+        phase_ns.alloc(8);
+        phase_ns.zero(s);
+      }
       CoarseOut co;
       co.lfptr = C.lfptr.p; co.lfidx = C.lfidx.p; co.c1 = C.c1.p; co.pptr = C.pptr.p; co.mptr = C.mptr.p;
       co.dptr = C.dptr.p; co.M = C.M.p; co.D = C.D.p; co.w = C.w.p; co.ones = C.ones.p; co.u = C.u.p;
       co.vol = C.vol.p;
       hipLaunchKernelGGL(k_agg_setup, dim3((unsigned)slots), dim3(kBlock), 0, s, lv, pv, T.n_agg, ones_l, u_l, vol_l,
-                         T.trace.p, T.omega.p, T.Pptr.p, T.P.p, T.Eptr.p, T.E.p, T.eig.p, co, scr.p, sb, bad.p);
+                         T.trace.p, T.omega.p, T.Pptr.p, T.P.p, T.Eptr.p, T.E.p, T.eig.p, co, scr.p, sb, bad.p,
+                         tr_on ? phase_ns.p : nullptr);
       LAUNCHCHECK();
       HIPCHECK(hipStreamSynchronize(s));
+      if (tr_on) {
+        const std::vector<unsigned long long> ph = phase_ns.download(s);
+        std::fprintf(stderr, "[spfas] setup level %d->%d aggregate phases (ms per workgroup): assemble %.2f, local "
+                     "Laplacian %.2f, eigen %.2f, P_A %.2f, bubbles %.2f, traces/extensions %.2f, coarse M/D %.2f, "
+                     "weights %.2f\n", l, l + 1, ph[0] * 1e-6 / slots, ph[1] * 1e-6 / slots, ph[2] * 1e-6 / slots,
+                     ph[3] * 1e-6 / slots, ph[4] * 1e-6 / slots, ph[5] * 1e-6 / slots, ph[6] * 1e-6 / slots,
+                     ph[7] * 1e-6 / slots);
+      }
       if (tr_on)
         std::fprintf(stderr, "[spfas] setup level %d->%d aggregates: %d, max np %zu, max nd %zu, max nI %zu, %zu "
                      "workgroups: %.1f ms\n", l, l + 1, T.n_agg, mx_np, mx_nd, mx_nI, slots, now_ms() - t_b);
@@ -729,7 +823,13 @@ void setup_coarse_levels(Hierarchy& h) {
                     "pivot %d, %d failures)", l, hb[1], hb[2], hb[3], hb[0]);
       fail(SPFAS_ERR_INVALID, buf);
     }
-    h.eigvals[l] = T.eig.download(s);
+    {   // the mA smallest eigenvalues of every aggregate, ascending
+      const std::vector<double> all = T.eig.download(s);
+      std::vector<double>& ev = h.eigvals[l];
+      ev.clear();
+      for (int A = 0; A < T.n_agg; ++A)
+        for (int j = 0; j < plan.mA[A]; ++j) ev.push_back(all[plan.pd_ptr[A] + j]);
+    }
     // ---- prolongation helpers
     {
       std::vector<int> pd_agg(plan.pd_list.size()), pd_row(plan.pd_list.size());

@@ -269,4 +269,116 @@ __device__ inline void wg_jacobi_eig(double* A, int lda, double* V, int ldv, int
   }
 }
 
+
+// ------------------------------------------------------------------ smallest eigenpairs
+
+constexpr int kSubMax = 16;   // largest block of the subspace iteration
+
+// Y (n x nb, ld nb) <- Y - q (q^T Y) for a unit vector q.
+__device__ inline void wg_project_out(const double* q, double* Y, int n, int nb) {
+  __shared__ double dots[kSubMax];
+  for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += q[i] * Y[i * nb + c];
+    dots[c] = s;
+  }
+  wg_sync();
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) Y[e] -= q[e / nb] * dots[e % nb];
+  wg_sync();
+}
+
+// Orthonormal columns by Cholesky QR: G = Y^T Y = R^T R, Y <- Y R^{-1}.
+// Returns false when G is not numerically positive definite.
+__device__ inline bool wg_cholqr(double* Y, int n, int nb, double* G, int* flag) {
+  wg_gemm(Y, nb, true, Y, nb, false, G, nb, nb, nb, n);
+  if (threadIdx.x == 0) *flag = 0;
+  wg_sync();
+  if (!wg_chol_unblocked(G, nb, nb, flag, 0)) return false;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double* row = Y + i * nb;
+    for (int j = 0; j < nb; ++j) {
+      double v = row[j];
+      for (int l = 0; l < j; ++l) v -= row[l] * G[j * nb + l];
+      row[j] = v / G[j * nb + j];
+    }
+  }
+  wg_sync();
+  return true;
+}
+
+// Smallest eigenpairs, other than the null vector, of a symmetric positive
+// semidefinite L (n x n, row-major) whose null space is spanned by the unit
+// vector q: block inverse iteration on Lreg = L + rho q q^T (C = its lower
+// Cholesky factor) with a Rayleigh-Ritz step every iteration; the nb
+// iterated vectors are kept orthogonal to q.  On success X (n x nb, ld nb)
+// holds the Ritz vectors and theta[0..nb) the Ritz values, ascending, and
+// the first nev pairs satisfy ||L x - theta x||_2 <= tol * rho.  Returns
+// false when that is not reached within maxit iterations (or the block
+// loses rank).  Scratch: Y, LX (n x nb), G, W (nb x nb); cs, pr, red as for
+// wg_jacobi_eig.
+__device__ inline bool wg_subspace_eig(const double* L, const double* C, const double* q, int n, int nb, int nev,
+                                       double rho, double tol, int maxit, double* X, double* Y, double* LX, double* G,
+                                       double* W, double* theta, double* cs, int* pr, double* red, int* flag) {
+  __shared__ int ord[kSubMax];
+  __shared__ int done;
+  // deterministic start: distinct low-discrepancy columns, then orthogonal to q
+  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
+    const int i = e / nb, j = e % nb;
+    const double u = (double)((i + 1) * (2 * j + 3) % 97) / 97.0;
+    X[e] = u - 0.5 + 0.01 * (double)(j + 1) * (double)((i % (j + 2)) == 0);
+  }
+  wg_sync();
+  wg_project_out(q, X, n, nb);
+  if (!wg_cholqr(X, n, nb, G, flag)) return false;
+  for (int it = 0; it < maxit; ++it) {
+    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) Y[e] = X[e];
+    wg_sync();
+    wg_chol_solve(C, n, n, Y, nb, nb);
+    wg_project_out(q, Y, n, nb);
+    if (!wg_cholqr(Y, n, nb, G, flag) || !wg_cholqr(Y, n, nb, G, flag)) return false;
+    // Rayleigh-Ritz: G = Y^T L Y, eigenvectors W
+    wg_gemm(L, n, false, Y, nb, false, LX, nb, n, nb, n);
+    wg_gemm(Y, nb, true, LX, nb, false, G, nb, nb, nb, n);
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+      const int i = e / nb, j = e % nb;
+      if (i < j) {
+        const double sy = 0.5 * (G[i * nb + j] + G[j * nb + i]);
+        G[i * nb + j] = sy;
+        G[j * nb + i] = sy;
+      }
+    }
+    wg_sync();
+    wg_jacobi_eig(G, nb, W, nb, nb, cs, pr, red);
+    if (threadIdx.x == 0) {
+      for (int i = 0; i < nb; ++i) ord[i] = i;
+      for (int i = 1; i < nb; ++i) {
+        const int oi = ord[i];
+        int j = i - 1;
+        while (j >= 0 && G[ord[j] * nb + ord[j]] > G[oi * nb + oi]) { ord[j + 1] = ord[j]; --j; }
+        ord[j + 1] = oi;
+      }
+      for (int i = 0; i < nb; ++i) theta[i] = G[ord[i] * nb + ord[i]];
+    }
+    wg_sync();
+    // X = Y W, LX = (L Y) W with the columns of W in ascending order
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) G[e] = W[(e / nb) * nb + ord[e % nb]];
+    wg_sync();
+    wg_gemm(Y, nb, false, G, nb, false, X, nb, n, nb, nb);
+    wg_gemm(LX, nb, false, G, nb, false, Y, nb, n, nb, nb);   // Y <- L X
+    if (threadIdx.x == 0) done = 1;
+    wg_sync();
+    for (int c = threadIdx.x; c < nev; c += blockDim.x) {
+      double r2 = 0.0;
+      for (int i = 0; i < n; ++i) {
+        const double d = Y[i * nb + c] - theta[c] * X[i * nb + c];
+        r2 += d * d;
+      }
+      if (!(sqrt(r2) <= tol * rho)) done = 0;
+    }
+    wg_sync();
+    if (done) return true;
+  }
+  return false;
+}
+
 }  // namespace spfas
