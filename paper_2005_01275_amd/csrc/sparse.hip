@@ -126,7 +126,8 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, const double* __restri
                                                    double* __restrict__ r, const double* __restrict__ p,
                                                    const double* __restrict__ q, double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
-  const double alpha = scal[rz] / scal[S_PQ];
+  const double pq = scal[S_PQ];
+  const double alpha = pq != 0.0 ? scal[rz] / pq : 0.0;
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     x[i] += alpha * p[i];
@@ -141,7 +142,7 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, const double* __restri
 // PCG: p = z + beta p with beta = rz_new / rz_old (beta = 0 on the first iteration)
 __global__ void __launch_bounds__(kBlock) k_pcg_p(int n, const double* __restrict__ scal, int rz_new, int rz_old,
                                                   int first, const double* __restrict__ z, double* __restrict__ p) {
-  const double beta = first ? 0.0 : scal[rz_new] / scal[rz_old];
+  const double beta = (first || scal[rz_old] == 0.0) ? 0.0 : scal[rz_new] / scal[rz_old];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     p[i] = z[i] + beta * p[i];
 }
@@ -1042,6 +1043,9 @@ static void spmv_dot2(const CsrView& A, const Sell64View* A64, bool fin, int G, 
 
 Krylov::~Krylov() {
   if (hscal) (void)hipHostFree(hscal);
+  if (hlag) (void)hipHostFree(hlag);
+  for (hipEvent_t& e : ev)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void Krylov::alloc(int n_) {
@@ -1052,6 +1056,9 @@ void Krylov::alloc(int n_) {
   parts.alloc(kMaxParts * 3);
   scal.alloc(S_NSLOT);
   if (!hscal) HIPCHECK(hipHostMalloc((void**)&hscal, S_NSLOT * sizeof(double), hipHostMallocDefault));
+  if (!hlag) HIPCHECK(hipHostMalloc((void**)&hlag, 4 * sizeof(double), hipHostMallocDefault));
+  for (hipEvent_t& e : ev)
+    if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 static double read_slot(double* hscal, const double* scal, int slot, hipStream_t st, int count = 1) {
@@ -1078,6 +1085,18 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   int it = 0;
   int cur = S_RZ0, old = S_RZ1;
   static_assert(S_RR == S_PQ + 1, "p.Ap and r.r are read together");
+  // While the residual is far above the tolerance, the residual of
+  // iteration k is checked while iteration k + 1 is already queued, so the
+  // device never waits for the host; within a factor 10 of the tolerance
+  // each iteration is checked as soon as it completes, so the solve stops
+  // at the first iteration that meets it (or one later, if it jumps there).
+  auto lagged = [&](int k, double& pq, double& rr) {
+    HIPCHECK(hipEventSynchronize(ev[k & 1]));
+    pq = hlag[2 * (k & 1)];
+    rr = hlag[2 * (k & 1) + 1];
+  };
+  auto bad = [&](double pq, double rr) { return !std::isfinite(rr) || !(pq > 0.0); };
+  bool near = false;   // within a factor 10 of the tolerance: check every iteration at once
   for (; it < maxit; ++it) {
     if (M) M->apply(r.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
@@ -1091,15 +1110,31 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
     LAUNCHCHECK();
     std::swap(cur, old);
-    read_slot(hscal, scal.p, S_PQ, st, 2);
-    const double pq = hscal[S_PQ], rr = hscal[S_RR];
-    if (!std::isfinite(rr) || !(pq > 0.0)) {   // breakdown (p.Ap <= 0) or non-finite operator: x = 0
-      failed = true;
-      hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
-      ++it;
-      break;
+    HIPCHECK(hipMemcpyAsync(hlag + 2 * (it & 1), scal.p + S_PQ, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipEventRecord(ev[it & 1], st));
+    double pq, rr;
+    if (!near && it > 0) {
+      lagged(it - 1, pq, rr);
+      if (bad(pq, rr)) { failed = true; ++it; break; }
+      if (rr <= tol2) { converged = true; ++it; break; }
+      near = rr <= 100.0 * tol2;
     }
-    if (rr <= tol2) { ++it; converged = true; break; }
+    if (near || it == 0) {
+      lagged(it, pq, rr);
+      if (bad(pq, rr)) { failed = true; ++it; break; }
+      if (rr <= tol2) { converged = true; ++it; break; }
+      near = rr <= 100.0 * tol2;
+    }
+  }
+  if (!failed && !converged && it > 0 && !near) {   // the last iteration has not been checked yet
+    double pq, rr;
+    lagged(it - 1, pq, rr);
+    if (bad(pq, rr)) failed = true;
+    else if (rr <= tol2) converged = true;
+  }
+  if (failed) {   // breakdown (p.Ap <= 0) or non-finite operator: x = 0
+    hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+    LAUNCHCHECK();
   }
   (void)g1;
   iters += it;

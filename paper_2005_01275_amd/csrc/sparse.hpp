@@ -128,6 +128,8 @@ struct Krylov {
   DVec<double> r, z, p, q, rh, v, s, t, y, w;
   DVec<double> parts, scal;
   double* hscal = nullptr;
+  double* hlag = nullptr;             // pinned: p.Ap and r.r of the last two PCG iterations
+  hipEvent_t ev[2] = {nullptr, nullptr};
   int iters = 0;
   bool failed = false;                // last solve met a non-finite value or a PCG breakdown (x returned as 0)
   bool converged = false;             // last solve reached its tolerance

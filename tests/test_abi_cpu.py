@@ -112,3 +112,30 @@ def test_c2_level0_topology_bit_exact():
     assert H.level_sizes(1) == (17325, 51975, 84645)
     assert H.level_sizes(2)[0] == 280
     assert H.level_sizes(3)[0] == 4
+
+
+def test_invalid_options_and_empty_mesh_rejected():
+    import paper_2005_01275_amd as pk
+    prob = small_problem((4, 4), seed=0)
+    m = prob.mesh
+    for n_levels, box, mm, what in [(0, (2, 2), 2, "n_levels"), (17, (2, 2), 2, "n_levels"),
+                                    (2, (2, 2), 0, "m must"), (2, (0, 2), 2, "box")]:
+        with pytest.raises(pk.SpfasError, match=what):
+            pk.Hierarchy(m, n_levels, box, mm, host_only=True)
+    empty = type(m)(**{**m.__dict__, "cell_volume": m.cell_volume[:0], "cell_centroid": m.cell_centroid[:0],
+                       "cell_k0": m.cell_k0[:0], "face_cells": m.face_cells[:0], "face_area": m.face_area[:0],
+                       "face_normal": m.face_normal[:0], "face_point": m.face_point[:0], "face_bc": m.face_bc[:0]})
+    with pytest.raises(pk.SpfasError, match="n_cells"):
+        pk.Hierarchy(empty, 1, (2, 2), 1, host_only=True)
+
+
+def test_levels_beyond_the_lattice_keep_one_aggregate():
+    """Asking for more levels than the boxes can coarsen leaves single-cell
+    levels (each the one aggregate of the level above), as in the oracle."""
+    import paper_2005_01275_amd as pk
+    prob = small_problem((4, 4), seed=0, box=(2, 2), m=2, n_levels=5)
+    H = pk.Hierarchy(prob.mesh, 5, (2, 2), 2, host_only=True)
+    h = build_hierarchy(prob)
+    for l in range(1, 5):
+        lev = h.levels[l]
+        assert H.level_sizes(l) == (lev.n_cells, lev.n_p, lev.n_flux)

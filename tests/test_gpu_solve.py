@@ -129,3 +129,48 @@ def test_newton_pcg_converged_and_vcycle(kw):
     p, s, st = H.fas_solve(prob, so)
     ref_p = x1[lev.n_flux:]
     assert np.linalg.norm(p - ref_p) <= 1e-10 * np.linalg.norm(ref_p)
+
+
+EDGE = [
+    # more levels than the lattice coarsens: the last levels hold one aggregate each
+    dict(shape=(4, 4), seed=0, box=(2, 2), m=2, n_levels=5),
+    # m = 1: piecewise-constant coarse pressure
+    dict(shape=(8, 8), seed=1, box=(4, 4), m=1, n_levels=2),
+    # alpha = 0: the linear problem
+    dict(shape=(6, 6), seed=2, box=(3, 3), m=1, n_levels=3, alpha=0.0),
+    # a single level: FAS reduces to the smoother iterated on level 0
+    dict(shape=(5, 3), seed=3, box=(2, 2), m=2, n_levels=1),
+    # ragged 3-D boxes with a remainder layer
+    dict(shape=(5, 4, 3), seed=4, box=(2, 2, 2), m=2, n_levels=2, permute=True, anisotropic=True),
+]
+
+
+@pytest.mark.parametrize("kw", EDGE)
+def test_edge_cases_reach_the_root(kw):
+    import paper_2005_01275_amd as pk
+    print("case", kw, flush=True)
+    prob = small_problem(**kw)
+    h, p_star, s_star = oracle_root(prob)
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    for fn, sm in ((H.fas_solve, pk.SPFAS_NEWTON), (H.fas_solve, pk.SPFAS_PICARD), (H.newton_solve, pk.SPFAS_NEWTON)):
+        p, s, st = fn(prob, opts(sm, prob, rtol=1e-10))
+        assert st["converged"], st
+        assert np.linalg.norm(p - p_star) <= 1e-8 * np.linalg.norm(p_star)
+        assert np.linalg.norm(s - s_star) <= 1e-8 * np.linalg.norm(s_star)
+    if prob.alpha == 0.0:
+        # the linear limit: the reduced cell system solved by a library routine
+        from oracle.fv import linear_pressure
+        p_lin = linear_pressure(prob)
+        assert np.linalg.norm(p - p_lin) <= 1e-8 * np.linalg.norm(p_lin)
+
+
+def test_warm_start_at_the_root_takes_no_cycle():
+    import paper_2005_01275_amd as pk
+    prob = small_problem((8, 8), seed=5, box=(4, 4), m=2, n_levels=2, src_scale=2.0)
+    h, p_star, s_star = oracle_root(prob)
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    o = opts(pk.SPFAS_NEWTON, prob, rtol=1e-8)
+    o.atol = 1e-12
+    p, s, st = H.fas_solve(prob, o, p0=p_star, sigma0=s_star)
+    assert st["converged"] and st["iterations"] == 0, st
+    np.testing.assert_array_equal(p, p_star)
