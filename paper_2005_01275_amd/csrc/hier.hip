@@ -99,17 +99,30 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
     t0.c2.push_back(M.face_cells[2 * f + 1]);
   }
   t0.n_flux = (int64_t)flux_face.size();
+  const bool trace = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
+  auto stamp = [&](const char* what) {
+    if (trace)
+      std::fprintf(stderr, "[spfas] setup host: %s at %.1f ms\n", what,
+                   1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() -
+                       t_start);
+  };
+  stamp("level-0 face lists");
   build_cell_lists(t0);
+  stamp("cell lists");
   if (n_levels > 1) {
     bool ok = lattice_from_centroids(M.dim, M.n_cells, M.cell_centroid, t0.lat_shape, t0.lat_index);
     require(ok, "box aggregation needs a Cartesian lattice of cell centroids");
   }
+  stamp("lattice");
   // ---------------- coarse topologies, aggregation, renumbering
   for (int l = 0; l + 1 < n_levels; ++l) {
     box_aggregate(topo[l], o.box);
+    stamp("box aggregation");
     renumber(topo[l]);
+    stamp("renumbering");
     Topo c = coarse_topology(topo[l], m);
     topo.push_back(std::move(c));
+    stamp("coarse topology");
   }
   if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
     std::fprintf(stderr, "[spfas] setup: host topology, aggregation, renumbering %.1f ms\n",

@@ -68,10 +68,14 @@ void box_aggregate(Topo& t, const int box[3]) {
 
 void renumber(Topo& t) {
   const int64_t n = t.n_cells;
+  // cells by aggregate, ascending id inside an aggregate (counting sort)
   t.cell_order.resize(n);
-  std::iota(t.cell_order.begin(), t.cell_order.end(), 0);
-  std::stable_sort(t.cell_order.begin(), t.cell_order.end(),
-                   [&](int64_t a, int64_t b) { return t.agg[a] < t.agg[b]; });
+  {
+    std::vector<int64_t> cnt(t.n_agg + 1, 0);
+    for (int64_t i = 0; i < n; ++i) cnt[t.agg[i] + 1]++;
+    for (int64_t a = 0; a < t.n_agg; ++a) cnt[a + 1] += cnt[a];
+    for (int64_t i = 0; i < n; ++i) t.cell_order[cnt[t.agg[i]]++] = i;
+  }
   std::vector<int64_t> pos(n);
   for (int64_t i = 0; i < n; ++i) pos[t.cell_order[i]] = i;
   const int64_t nf = t.n_flux;
@@ -96,12 +100,24 @@ void renumber(Topo& t) {
     key.id = j;
     keys[j] = key;
   }
-  std::sort(keys.begin(), keys.end(), [](const Key& x, const Key& y) {
-    return std::tie(x.g0, x.g1, x.g2, x.kr, x.lo, x.hi, x.id) <
-           std::tie(y.g0, y.g1, y.g2, y.kr, y.lo, y.hi, y.id);
-  });
+  // Same order as sorting the whole key tuple, in two passes: a counting
+  // sort on (group, first aggregate), then a sort of each (small) bucket on
+  // the remaining fields.
+  const int64_t na = t.n_agg;
+  std::vector<int64_t> bptr(3 * na + 1, 0);
+  for (const Key& k : keys) bptr[k.g0 * na + k.g1 + 1]++;
+  for (int64_t b = 0; b < 3 * na; ++b) bptr[b + 1] += bptr[b];
+  std::vector<Key> sorted(nf);
+  {
+    std::vector<int64_t> fill(bptr.begin(), bptr.end() - 1);
+    for (const Key& k : keys) sorted[fill[k.g0 * na + k.g1]++] = k;
+  }
+  for (int64_t b = 0; b < 3 * na; ++b)
+    std::sort(sorted.begin() + bptr[b], sorted.begin() + bptr[b + 1], [](const Key& x, const Key& y) {
+      return std::tie(x.g2, x.kr, x.lo, x.hi, x.id) < std::tie(y.g2, y.kr, y.lo, y.hi, y.id);
+    });
   t.flux_order.resize(nf);
-  for (int64_t i = 0; i < nf; ++i) t.flux_order[i] = keys[i].id;
+  for (int64_t i = 0; i < nf; ++i) t.flux_order[i] = sorted[i].id;
 }
 
 void build_cell_lists(Topo& t) {
