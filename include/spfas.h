@@ -288,20 +288,20 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * per flux unknown F and cell N of level 0, residual 40F + 24N, Newton
  * linearisation 56F + 24N; with E = stored nonzeros of S including the
  * diagonal: S x with its dot products 12E + 24N (FP64 value + int32
- * column per entry); on the finest AMG level (FP32 value + int32 column):
- * two-sweep pre-smoothing 8E + 24N, residual 8E + 24N, prolongation +
- * sweep 8E + 36N, last sweep 8E + 32N).
+ * column per entry); on the finest level of the classical AMG (FP32 value
+ * + int32 column per stored entry, N_c coarse points, E_w = E, E_R =
+ * entries of P, E_AP = entries of A P): pre-sweep + residual 8E_w + 16N,
+ * restriction 8E_R + 8N + 8N_c, prolongation + sweep 8E_AP + 32N + 8N_c).
  */
 typedef enum {
-  SPFAS_PROF_FINE_RESID = 0,      /* fine residual, also inside Alg. 1 trials   */
-  SPFAS_PROF_FINE_LINEARIZE = 1,  /* S = D M^{-1} E and its right-hand side      */
-  SPFAS_PROF_FINE_SPMV = 2,       /* S x (+ one dot) in the fine-level Krylov solver */
-  SPFAS_PROF_FINE_AMG_PRE = 3,    /* finest AMG level: two sweeps from zero      */
-  SPFAS_PROF_FINE_AMG_RESID = 4,  /* finest AMG level: residual                  */
-  SPFAS_PROF_FINE_AMG_POST1 = 5,  /* finest AMG level: prolongation + sweep      */
-  SPFAS_PROF_FINE_AMG_POST2 = 6,  /* finest AMG level: last sweep                */
-  SPFAS_PROF_FINE_SPMV2 = 7,      /* S x (+ two dots), second product of BiCGStab */
-  SPFAS_PROF_COUNT = 8
+  SPFAS_PROF_FINE_RESID = 0,         /* fine residual, also inside Alg. 1 trials   */
+  SPFAS_PROF_FINE_LINEARIZE = 1,     /* S = D M^{-1} E and its right-hand side      */
+  SPFAS_PROF_FINE_SPMV = 2,          /* S x (+ one dot) in the fine-level Krylov solver */
+  SPFAS_PROF_FINE_AMG_DOWN = 3,      /* finest AMG level: pre-smoothing + residual  */
+  SPFAS_PROF_FINE_AMG_RESTRICT = 4,  /* finest AMG level: restriction               */
+  SPFAS_PROF_FINE_AMG_UP = 5,        /* finest AMG level: prolongation + smoothing  */
+  SPFAS_PROF_FINE_SPMV2 = 6,         /* S x (+ two dots), second product of BiCGStab */
+  SPFAS_PROF_COUNT = 7
 } spfas_prof_kernel;
 
 /* Turns the timing on (nonzero) or off and clears the counters. */

@@ -13,7 +13,8 @@
                        b^{l+1} = A^{l+1}(Q x) - R(A^l(x) - b^l) (eq.
                        coarse_level_residual); the coarsest level takes at
                        most 10 smoothing steps, stopping early on convergence
-                       (Section 4).
+                       (Section 4) or when a step no longer lowers its
+                       residual.
 * ``fas_solve`` / ``single_level_solve`` -- outer loops with the stopping rule
   of Section 4: relative residual below rtol or absolute below atol (2-norm
   of the whole residual vector; relative to the residual of the initial
@@ -117,12 +118,19 @@ def smooth(level, x, b, alpha, opts: Opts, stats: Stats = None):
 
 
 def coarsest_solve(level, x, b, alpha, opts: Opts, stats=None):
-    r0 = norm(residual(level, x, b, alpha))
-    tol = max(opts.rtol * r0, opts.atol)
+    """At most ``coarsest_max`` smoothing steps; stops when the level
+    residual meets rtol (relative to its entry value) or atol, or when a step
+    did not lower it (rounding level reached, or Alg. 1 rejected the step)."""
+    r = norm(residual(level, x, b, alpha))
+    tol = max(opts.rtol * r, opts.atol)
     for _ in range(opts.coarsest_max):
-        if norm(residual(level, x, b, alpha)) <= tol:
+        if r <= tol:
             break
         x = smooth(level, x, b, alpha, opts, stats)
+        r_new = norm(residual(level, x, b, alpha))
+        if not r_new < r:
+            break
+        r = r_new
     return x
 
 

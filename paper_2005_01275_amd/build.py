@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libspfas.so")
 BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPFAS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["topo.cpp", "fine.hip", "sparse.hip", "hier.hip", "coarse_setup.hip", "coarse.hip", "solve.hip",
+SOURCES = ["topo.cpp", "amg_classical.cpp", "fine.hip", "sparse.hip", "hier.hip", "coarse_setup.hip", "coarse.hip", "solve.hip",
            "export.hip", "abi.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -1,0 +1,56 @@
+// Host-side AMG setup structures (no device code).
+//
+// Classical AMG for the level-0 eliminated system: PMIS coarsening on the
+// strong negative couplings, extended+i interpolation with truncation, and
+// Galerkin coarse operators P^T A P.  The interpolation is computed once from
+// the setup matrix and kept; the device recomputes A P and P^T (A P) after
+// every linearisation from the product lists built here.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace spfas {
+
+// DIA+CSR matrix on the host: diagonal separately, off-diagonal entries in CSR.
+struct HostCsr {
+  int n = 0;
+  std::vector<double> diag, val;
+  std::vector<int> ptr, col;
+};
+
+// Entry codes of a DIA+CSR matrix in product lists: (i << 1) for the
+// diagonal of row i, (k << 1) | 1 for off-diagonal entry k.
+inline int dia_code(int i) { return i << 1; }
+inline int off_code(int k) { return (k << 1) | 1; }
+
+struct ClassicalLevel {
+  int n = 0, nc = 0;
+  // interpolation P (n x nc), CSR with ascending columns in each row
+  std::vector<int> pptr, pcol;
+  std::vector<double> pval;
+  // R = P^T (nc x n), CSR; rsrc[e] = P entry of R entry e
+  std::vector<int> rptr, rcol, rsrc;
+  // A P (n x nc): CSR pattern with ascending columns; products per entry
+  // (A entry code, P entry); appidx[e] = P entry at the same position or -1
+  std::vector<int> apptr, apcol, aplptr, apla, aplp, appidx;
+  // next level: DIA+CSR matrix and products per entry, off-diagonal entries
+  // first (in CSR order) then the diagonal: (P entry, A P entry)
+  HostCsr C;
+  std::vector<int> clptr, clr, clq;
+};
+
+// Strength of connection of the classical coarsening: j is a strong
+// dependence of i when -a_ij >= theta * max_k (-a_ik) > 0.
+constexpr double kClassicalStrength = 0.25;
+// Truncation of interpolation rows: drop |w| < kTruncRel * max |w|, keep at
+// most kTruncMax entries, rescale to the row sum before truncation.
+constexpr double kTruncRel = 0.2;
+constexpr int kTruncMax = 4;
+
+// One coarsening step of A.  Returns false when the coarsening stalls (no
+// C-point or more than 90 % of the points kept); `seed` fixes the PMIS
+// tie-breaking measure.
+bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLevel& L);
+
+}  // namespace spfas

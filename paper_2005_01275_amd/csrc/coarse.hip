@@ -108,9 +108,239 @@ struct HView {
   double *inv, *tmp, *z;
 };
 
+// ---- block elimination with the static M_c^{-1} (cells with m_c <= kLocM)
+//
+// A_c = [[sc M_c, E_c], [D_c, 0]] with sc = 1/kappa(pbar_c) and E_c = D_c^T
+// (Picard) or D_c^T + (M_c sigma_c) dsc w_c^T (Newton, dsc = d sc / d pbar).
+// M_c is static, so with Minv = M_c^{-1}, G = Minv D_c^T and DG = D_c G kept
+// from setup:  Y = (sc M_c)^{-1} E_c = (G + sigma_c dsc w_c^T) / sc,
+// S = D_c Y = (DG + (D_c sigma_c) dsc w_c^T) / sc, and
+//   A_c^{-1} = [[Minv/sc - Y S^{-1} G^T/sc, Y S^{-1}], [S^{-1} G^T/sc, -S^{-1}]].
+constexpr int kLocM = 8;
+
+struct LocStatic {
+  const int* gptr;       // offset of G_c (k_c x m_c, row-major)
+  const int* sgptr;      // offset of DG_c (m_c x m_c)
+  const double* Minv;    // at mptr[c], k_c x k_c
+  const double* G;
+  const double* DG;
+};
+
+__device__ inline double wave_allsum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Setup: Minv (Gauss-Jordan without pivoting; M_c is symmetric positive
+// definite, a non-positive pivot sets *flag), symmetrised; G; DG.  One wave
+// per cell, rows padded to 65 doubles in LDS (no bank conflicts).
+__global__ void __launch_bounds__(64) k_local_static(CView v, LocStatic ls, double* __restrict__ Minv,
+                                                     double* __restrict__ G, double* __restrict__ DG,
+                                                     int* __restrict__ flag) {
+  __shared__ double a[64 * 65];
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const int k = v.lfptr[c + 1] - v.lfptr[c];
+  const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+  const double* Mc = v.M + v.mptr[c];
+  const double* Dc = v.D + v.dptr[c];
+  for (int i = 0; i < k; ++i)
+    if (lane < k) a[i * 65 + lane] = Mc[i * k + lane];
+  __syncthreads();
+  for (int kk = 0; kk < k; ++kk) {
+    const double pv = a[kk * 65 + kk];
+    const double f = (lane < k && lane != kk) ? a[lane * 65 + kk] : 0.0;
+    __syncthreads();
+    if (lane == 0 && !(pv > 0.0)) flag[0] = 1;
+    const double ip = 1.0 / pv;
+    if (lane < k && lane != kk) {
+      for (int j = 0; j < k; ++j)
+        if (j != kk) a[lane * 65 + j] -= f * ip * a[kk * 65 + j];
+      a[lane * 65 + kk] = -f * ip;
+    }
+    __syncthreads();
+    if (lane < k) a[kk * 65 + lane] = lane == kk ? ip : a[kk * 65 + lane] * ip;
+    __syncthreads();
+  }
+  double* Mi = Minv + v.mptr[c];
+  for (int i = 0; i < k; ++i)
+    if (lane < k) Mi[i * k + lane] = 0.5 * (a[i * 65 + lane] + a[lane * 65 + i]);
+  __syncthreads();
+  // G = Minv D^T (row `lane`), DG = D G
+  double g[kLocM];
+#pragma unroll
+  for (int q = 0; q < kLocM; ++q) g[q] = 0.0;
+  if (lane < k)
+    for (int j = 0; j < k; ++j) {
+      const double mij = 0.5 * (a[lane * 65 + j] + a[j * 65 + lane]);
+#pragma unroll
+      for (int q = 0; q < kLocM; ++q)
+        if (q < m) g[q] += mij * Dc[q * k + j];
+    }
+  double* Gc = G + ls.gptr[c];
+#pragma unroll
+  for (int q = 0; q < kLocM; ++q)
+    if (q < m && lane < k) Gc[lane * m + q] = g[q];
+  double* DGc = DG + ls.sgptr[c];
+#pragma unroll
+  for (int q = 0; q < kLocM; ++q)
+#pragma unroll
+    for (int r = 0; r < kLocM; ++r)
+      if (q < m && r < m) {
+        const double t = wave_allsum(lane < k ? Dc[q * k + lane] * g[r] : 0.0);
+        if (lane == 0) DGc[q * m + r] = t;
+      }
+}
+
+// Per cell (one wave): A_c^{-1} by block elimination, z_c = A_c^{-1} g_c with
+// g = [-r_hat; -r_p] (r_hat keeps r_sigma on the first owner only).
+__global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, LocStatic ls, double alpha, int newton,
+                                                         const double* __restrict__ x, const double* __restrict__ r) {
+  __shared__ double sT[kBlock / 64][64 * kLocM];
+  __shared__ double sS[kBlock / 64][kLocM * kLocM];
+  __shared__ double sg[kBlock / 64][64];
+  const CView& v = hv.v;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * (kBlock / 64) + wv;
+  const bool act = c < v.n;
+  int k = 0, m = 0, p0 = 0;
+  double isc = 1.0, dsc = 0.0;
+  double Gj[kLocM], Yj[kLocM], z2[kLocM];
+  if (act) {
+    k = v.lfptr[c + 1] - v.lfptr[c];
+    p0 = v.pptr[c];
+    m = v.pptr[c + 1] - p0;
+    const int* lf = v.lfidx + v.lfptr[c];
+    const double* sig = x;
+    const double* p = x + v.nf;
+    const double* w = v.w + p0;
+    double pbar = 0.0;
+    for (int q = 0; q < m; ++q) pbar += w[q] * p[p0 + q];
+    const double sc = exp(-alpha * pbar);
+    dsc = -alpha * sc;
+    isc = 1.0 / sc;
+    double sj = 0.0, g1 = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q) Gj[q] = 0.0;
+    if (lane < k) {
+      const int fj = lf[lane];
+      if (newton) sj = sig[fj];
+      g1 = (v.fcell[2 * fj] == c) ? -r[fj] : 0.0;
+      const double* Gr = ls.G + ls.gptr[c] + lane * m;
+#pragma unroll
+      for (int q = 0; q < kLocM; ++q)
+        if (q < m) Gj[q] = Gr[q];
+    }
+    sg[wv][lane] = g1;
+    // D sigma and G^T g1 (wave sums; m is uniform over the wave)
+    double dsig[kLocM], u[kLocM];
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q) {
+      dsig[q] = 0.0;
+      u[q] = 0.0;
+      if (q < m) {
+        dsig[q] = wave_allsum(lane < k ? v.D[v.dptr[c] + q * k + lane] * sj : 0.0);
+        u[q] = wave_allsum(Gj[q] * g1) * isc + r[v.nf + p0 + q];   // G^T g1 / sc - g2
+      }
+    }
+    // S, padded with the identity to kLocM, inverted in place (Gauss-Jordan)
+    const double* DG = ls.DG + ls.sgptr[c];
+    double S[kLocM][kLocM];
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q)
+#pragma unroll
+      for (int j = 0; j < kLocM; ++j)
+        S[q][j] = (q < m && j < m) ? (DG[q * m + j] + dsig[q] * dsc * w[j]) * isc : (q == j ? 1.0 : 0.0);
+#pragma unroll
+    for (int kk = 0; kk < kLocM; ++kk) {
+      const double ip = 1.0 / S[kk][kk];
+      S[kk][kk] = 1.0;
+#pragma unroll
+      for (int j = 0; j < kLocM; ++j) S[kk][j] *= ip;
+#pragma unroll
+      for (int q = 0; q < kLocM; ++q) {
+        if (q == kk) continue;
+        const double f = S[q][kk];
+        S[q][kk] = 0.0;
+#pragma unroll
+        for (int j = 0; j < kLocM; ++j) S[q][j] -= f * S[kk][j];
+      }
+    }
+    // Y row, T = Y S^{-1} row, z2 = S^{-1} (G^T g1 / sc - g2)
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q) Yj[q] = q < m ? (Gj[q] + sj * dsc * w[q]) * isc : 0.0;
+    if (lane < k) {
+#pragma unroll
+      for (int j = 0; j < kLocM; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < kLocM; ++q) t += Yj[q] * S[q][j];
+        sT[wv][lane * kLocM + j] = t;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < kLocM; ++j) t += S[q][j] * u[j];
+      z2[q] = t;
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < kLocM; ++q)
+#pragma unroll
+        for (int j = 0; j < kLocM; ++j) sS[wv][q * kLocM + j] = S[q][j];
+    }
+  }
+  __syncthreads();
+  if (!act) return;
+  const int nc = k + m;
+  double* inv = hv.inv + hv.invptr[c];
+  const double* Mi = ls.Minv + v.mptr[c];
+  double h = 0.0;   // (Minv g1)[lane]: Minv is symmetric
+  for (int i = 0; i < k; ++i) {
+    const double* Ti = &sT[wv][i * kLocM];
+    if (lane < k) {
+      const double mij = Mi[i * k + lane];
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < kLocM; ++j) t += Ti[j] * Gj[j];
+      inv[i * nc + lane] = (mij - t) * isc;
+      h += mij * sg[wv][i];
+    } else if (lane < nc) {
+      inv[i * nc + lane] = Ti[lane - k];
+    }
+  }
+  for (int q = 0; q < m; ++q) {
+    const double* Sq = &sS[wv][q * kLocM];
+    if (lane < k) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < kLocM; ++j) t += Sq[j] * Gj[j];
+      inv[(k + q) * nc + lane] = t * isc;
+    } else if (lane < nc) {
+      inv[(k + q) * nc + lane] = -Sq[lane - k];
+    }
+  }
+  double* z = hv.z + hv.zptr[c];
+  if (lane < k) {
+    double t = h * isc;
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q) t -= Yj[q] * z2[q];
+    z[lane] = t;
+  } else if (lane < nc) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kLocM; ++q)
+      if (lane - k == q) t = z2[q];
+    z[lane] = t;
+  }
+}
+
+// ---- general cells: LU of the whole saddle block
 // Per cell: build A_c, invert it (LU with partial pivoting, then the columns
 // of the inverse), z_c = A_c^{-1} g_c.
-__global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, double alpha, int newton, const double* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_coarse_local_lu(HView hv, double alpha, int newton, const double* __restrict__ x,
                                                          const double* __restrict__ r) {
   const CView& v = hv.v;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,7 +435,14 @@ void launch_coarse_local(CoarseLevel& C, double alpha, bool newton, const double
   hv.inv = C.inv.p;
   hv.tmp = C.t.p;
   hv.z = C.z.p;
-  hipLaunchKernelGGL(k_coarse_local, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, hv, alpha, newton ? 1 : 0, x, r);
+  if (C.fast_local) {
+    const LocStatic ls{C.gptr.p, C.sgptr.p, C.Minv.p, C.G.p, C.DG.p};
+    hipLaunchKernelGGL(k_coarse_local, dim3(grid_for(C.n, kBlock / 64)), dim3(kBlock), 0, s, hv, ls, alpha,
+                       newton ? 1 : 0, x, r);
+  } else {
+    hipLaunchKernelGGL(k_coarse_local_lu, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, hv, alpha, newton ? 1 : 0,
+                       x, r);
+  }
   LAUNCHCHECK();
 }
 
@@ -493,6 +730,32 @@ void setup_coarse_solver(Hierarchy& h, int l) {
     invptr[c + 1] = invptr[c] + nc * nc;
   }
   require(mxn <= 64, "coarse cell with more than 64 local unknowns");
+  // static parts of the block elimination (cells with at most kLocM pressure unknowns)
+  {
+    std::vector<int> gptr(n + 1, 0), sgptr(n + 1, 0);
+    int mxm = 0;
+    for (int c = 0; c < n; ++c) {
+      const int k = C.h_lfptr[c + 1] - C.h_lfptr[c], m = C.h_pptr[c + 1] - C.h_pptr[c];
+      mxm = std::max(mxm, m);
+      gptr[c + 1] = gptr[c] + k * m;
+      sgptr[c + 1] = sgptr[c] + m * m;
+    }
+    C.fast_local = false;
+    if (mxm <= kLocM && n > 0) {
+      C.gptr.upload(gptr, s);
+      C.sgptr.upload(sgptr, s);
+      C.Minv.alloc(C.M.n);
+      C.G.alloc(std::max(gptr[n], 1));
+      C.DG.alloc(std::max(sgptr[n], 1));
+      DVec<int> flag;
+      flag.alloc(1);
+      flag.zero(s);
+      const LocStatic ls{C.gptr.p, C.sgptr.p, C.Minv.p, C.G.p, C.DG.p};
+      hipLaunchKernelGGL(k_local_static, dim3(n), dim3(64), 0, s, cview(C), ls, C.Minv.p, C.G.p, C.DG.p, flag.p);
+      LAUNCHCHECK();
+      C.fast_local = flag.download(s)[0] == 0;   // otherwise LU of the whole local block
+    }
+  }
   C.nsum = zptr[n];
   C.zptr.upload(zptr, s);
   C.invptr.upload(invptr, s);

@@ -46,6 +46,10 @@ struct CoarseLevel {
   DVec<int> fcell, floc;          // [2*nf]
   int nsum = 0;                   // sum over cells of (k_c + m_c)
   DVec<int> zptr, invptr;         // offsets of local solution vectors / inverses
+  // block elimination of the local saddle blocks with the static M_c^{-1}
+  bool fast_local = false;
+  DVec<int> gptr, sgptr;          // offsets of G_c = M_c^{-1} D_c^T and D_c G_c
+  DVec<double> Minv, G, DG;
   // hybridisation: multipliers on interior interfaces
   int nl = 0;
   std::vector<int> h_lam_flux;    // multiplier -> flux id

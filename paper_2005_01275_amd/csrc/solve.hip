@@ -168,18 +168,17 @@ void setup_fine_solver(Hierarchy& h) {
   launch_fine_linearize(f.view(), false, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
   f.alpha = a;
   HIPCHECK(hipStreamSynchronize(s));
-  w.amg.setup(w.S, s, true);
+  w.amg.setup(w.S, s, true, kDenseLds, true);
   if (trace_on()) std::fprintf(stderr, "[spfas] level 0 AMG: %s\n", w.amg.describe().c_str());
-  // event timing hooks of the finest-level Krylov SpMV and Jacobi sweeps
+  // event timing hooks of the finest-level Krylov SpMV and AMG cycle kernels
   ProfHook hk;
   hk.prof = &h.prof;
   hk.spmv_id = SPFAS_PROF_FINE_SPMV;
   hk.spmv2_id = SPFAS_PROF_FINE_SPMV2;
   hk.spmv_bytes = 24.0 * nf + 32.0 * n;
-  hk.pre_id = SPFAS_PROF_FINE_AMG_PRE;
-  hk.resid_id = SPFAS_PROF_FINE_AMG_RESID;
-  hk.post1_id = SPFAS_PROF_FINE_AMG_POST1;
-  hk.post2_id = SPFAS_PROF_FINE_AMG_POST2;
+  hk.down_id = SPFAS_PROF_FINE_AMG_DOWN;
+  hk.restrict_id = SPFAS_PROF_FINE_AMG_RESTRICT;
+  hk.up_id = SPFAS_PROF_FINE_AMG_UP;
   w.kry.hook = hk;
   w.amg.hook = hk;
   if (w.amg.lv[0].sval64.n) {   // S products read the SELL-64 copy: value + column per stored entry
@@ -373,13 +372,16 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
 }
 
 // Coarsest level: at most coarsest_max smoothing steps, stopping when the
-// level residual meets rtol (relative to its entry value) or atol.
+// level residual meets rtol (relative to its entry value) or atol, or when a
+// step did not lower it (rounding level reached, or the step was rejected).
 static void coarsest_solve(Hierarchy& h, int l, const Opts& o, spfas_stats& st) {
   double r = coarse_rnorm(h, l, h.coarse[l - 1]->x.p, nullptr, 0.0);
   const double tol = std::max(o.rtol * r, o.atol);
   for (int i = 0; i < o.coarsest_max; ++i) {
     if (r <= tol) break;
-    r = coarse_smooth(h, l, o, r, st);
+    const double r_new = coarse_smooth(h, l, o, r, st);
+    if (!(r_new < r)) break;
+    r = r_new;
   }
 }
 

@@ -1,5 +1,6 @@
-// Sparse linear solvers: SpMV, aggregation AMG, dense LU coarsest level,
-// PCG and BiCGStab with device-resident scalars (see sparse.hpp).
+// Sparse linear solvers: SpMV, classical and aggregation AMG, dense
+// coarsest level, PCG and BiCGStab with device-resident scalars (see
+// sparse.hpp).
 #include "sparse.hpp"
 
 #include <algorithm>
@@ -9,6 +10,7 @@
 #include <cstdlib>
 #include <numeric>
 
+#include "amg_host.hpp"
 #include "kern.hpp"
 #include "prof.hpp"
 
@@ -233,14 +235,7 @@ __global__ void __launch_bounds__(kBlock) k_zero(int n, double* __restrict__ b) 
 
 // ------------------------------------------------------------------ AMG kernels
 
-__global__ void __launch_bounds__(kBlock) k_invd(CsrView A, double* __restrict__ invd) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
-  double s = 0.0;
-  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += fabs(A.val[k]);
-  const double d = fabs(A.diag[i]) + 0.5 * s;
-  invd[i] = d > 0.0 ? 1.0 / d : 0.0;
-}
+
 
 // ------------------------------------------------------------------ SELL-64 cycle kernels
 
@@ -391,6 +386,20 @@ __global__ void __launch_bounds__(kBlock) k_amgv_post2(CsrView A, const double* 
   if (g == 0) out[i] = x[i] + w[i] * (b[i] - (A.diag[i] * x[i] + acc));
 }
 
+// smoother weights 1 / (|a_ii| + 0.5 sum_j |a_ij|), a lane group per row
+__global__ void __launch_bounds__(kBlock) k_invd(CsrView A, double* __restrict__ invd) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= A.n) return;
+  double s = 0.0;
+  for (int k = A.ptr[i] + g; k < A.ptr[i + 1]; k += kVecG) s += fabs(A.val[k]);
+  s = group_sum(s);
+  if (g == 0) {
+    const double d = fabs(A.diag[i]) + 0.5 * s;
+    invd[i] = d > 0.0 ? 1.0 / d : 0.0;
+  }
+}
+
 // bc[I] = sum of r over the members of coarse node I, a lane group per node
 __global__ void __launch_bounds__(kBlock) k_restrict_vec(int nc, const int* __restrict__ mptr,
                                                          const int* __restrict__ mem, const double* __restrict__ r,
@@ -415,7 +424,7 @@ __global__ void __launch_bounds__(kBlock) k_sell_fill(int ne, const int* __restr
   double v = 0.0;
   if (m >= 0) v = off[m];
   else if (m != kSellPad) v = diag[-1 - m];
-  val[e] = (float)v;
+  if (val) val[e] = (float)v;
   if (val64) val64[e] = v;
 }
 
@@ -448,6 +457,148 @@ __global__ void __launch_bounds__(kBlock) k_galerkin_diag(int nc, const int* __r
     s += (c & 1) ? fval[c >> 1] : fdiag[c >> 1];
   }
   cdiag[I] = s;
+}
+
+// ------------------------------------------------------------------ classical AMG kernels
+
+// A P values: the products of each entry, summed in a fixed order.
+// Product codes address the DIA+CSR matrix (dia_code / off_code).
+__global__ void __launch_bounds__(kBlock) k_ap_numeric(int ne, const int* __restrict__ lptr,
+                                                       const int* __restrict__ la, const int* __restrict__ lp,
+                                                       CsrView A, const double* __restrict__ pval,
+                                                       double* __restrict__ apv) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int t = lptr[e]; t < lptr[e + 1]; ++t) {
+    const int c = la[t];
+    const double a = (c & 1) ? A.val[c >> 1] : A.diag[c >> 1];
+    s += a * pval[lp[t]];
+  }
+  apv[e] = s;
+}
+
+// P^T (A P): entries [0, noff) are the next level's off-diagonal values,
+// [noff, noff + nc) its diagonal.
+__global__ void __launch_bounds__(kBlock) k_rap_numeric(int noff, int nc, const int* __restrict__ lptr,
+                                                        const int* __restrict__ lr, const int* __restrict__ lq,
+                                                        const double* __restrict__ pval,
+                                                        const double* __restrict__ apv, double* __restrict__ cval,
+                                                        double* __restrict__ cdiag) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= noff + nc) return;
+  double s = 0.0;
+  for (int t = lptr[e]; t < lptr[e + 1]; ++t) s += pval[lr[t]] * apv[lq[t]];
+  if (e < noff) cval[e] = s;
+  else cdiag[e - noff] = s;
+}
+
+// Stored slots of row i of a cycle operator: e, e + step, ... < end.
+template <bool Sell>
+__device__ inline void cyc_row(const CycView& M, int i, int& e, int& end, int& step) {
+  if constexpr (Sell) {
+    const int sl = i >> 6;
+    const int a = M.ptr[sl];
+    e = a + (i & 63);
+    end = e + (M.ptr[sl + 1] - a);
+    step = 64;
+  } else {
+    e = M.ptr[i];
+    end = M.ptr[i + 1];
+    step = 1;
+  }
+}
+
+// A diag(w) in FP32, one thread per stored slot: a(src) * w[col]
+__global__ void __launch_bounds__(kBlock) k_fill_aw(int ne, const int* __restrict__ col, const int* __restrict__ src,
+                                                    CsrView A, const double* __restrict__ w, float* __restrict__ val) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int c = src[e];
+  double v = 0.0;
+  if (c >= 0) v = ((c & 1) ? A.val[c >> 1] : A.diag[c >> 1]) * w[col[e]];
+  val[e] = (float)v;
+}
+
+// P - diag(w) A P in FP32 on the pattern of A P (which contains that of P):
+// SELL thread per row, CSR lane group per row.
+__device__ inline float cm_value(int q, const int* __restrict__ appidx, const double* __restrict__ pval,
+                                 const double* __restrict__ apv, double wi) {
+  if (q < 0) return 0.0f;
+  const int pi = appidx[q];
+  return (float)((pi >= 0 ? pval[pi] : 0.0) - wi * apv[q]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_cm(CycView M, const int* __restrict__ src,
+                                                    const int* __restrict__ appidx, const double* __restrict__ pval,
+                                                    const double* __restrict__ apv, const double* __restrict__ w,
+                                                    float* __restrict__ val) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M.n) return;
+  int e, end, step;
+  cyc_row<true>(M, i, e, end, step);
+  const double wi = w[i];
+  for (; e < end; e += step) val[e] = cm_value(src[e], appidx, pval, apv, wi);
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_cmv(CycView M, const int* __restrict__ src,
+                                                     const int* __restrict__ appidx, const double* __restrict__ pval,
+                                                     const double* __restrict__ apv, const double* __restrict__ w,
+                                                     float* __restrict__ val) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= M.n) return;
+  const double wi = w[i];
+  for (int e = M.ptr[i] + g; e < M.ptr[i + 1]; e += kVecG) val[e] = cm_value(src[e], appidx, pval, apv, wi);
+}
+
+// R = P^T in FP32 (filled once at setup), one thread per stored slot
+__global__ void __launch_bounds__(kBlock) k_fill_rm(int ne, const int* __restrict__ src,
+                                                    const double* __restrict__ pval, float* __restrict__ val) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  val[e] = src[e] >= 0 ? (float)pval[src[e]] : 0.0f;
+}
+
+// The three kernels of a classical V(1,1) level, on SELL-64 (thread per row):
+//   Op 0: y = b - M b               pre-sweep from zero + residual, M = A diag(w)
+//   Op 1: y = M x                   restriction, M = P^T
+//   Op 2: y = w (b + r) + M x       prolongation + post-sweep, M = P - diag(w) A P
+// (with x1 = w b and r = b - A x1, the post-sweep of y = x1 + P e is
+// y + w (b - A y) = w (b + r) + (P - diag(w) A P) e).  The template flag
+// only separates the finest-level launches by name.
+template <int Op, bool Finest>
+__global__ void __launch_bounds__(kBlock) k_cyc(CycView M, const double* __restrict__ x,
+                                                const double* __restrict__ b, const double* __restrict__ r,
+                                                const double* __restrict__ w, double* __restrict__ y) {
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
+  if (i >= M.n) return;
+  int e, end, step;
+  cyc_row<true>(M, i, e, end, step);
+  double acc = 0.0;
+#pragma unroll 4
+  for (; e < end; e += 64) acc += (double)M.val[e] * x[M.col[e]];
+  if constexpr (Op == 0) y[i] = b[i] - acc;
+  else if constexpr (Op == 1) y[i] = acc;
+  else y[i] = w[i] * (b[i] + r[i]) + acc;
+}
+
+// The same on CSR with a lane group per row (small levels).
+template <int Op>
+__global__ void __launch_bounds__(kBlock) k_cycv(CycView M, const double* __restrict__ x,
+                                                 const double* __restrict__ b, const double* __restrict__ r,
+                                                 const double* __restrict__ w, double* __restrict__ y) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / kVecG, g = t % kVecG;
+  if (i >= M.n) return;   // the whole group leaves together
+  double acc = 0.0;
+  for (int e = M.ptr[i] + g; e < M.ptr[i + 1]; e += kVecG) acc += (double)M.val[e] * x[M.col[e]];
+  acc = group_sum(acc);
+  if (g == 0) {
+    if constexpr (Op == 0) y[i] = b[i] - acc;
+    else if constexpr (Op == 1) y[i] = acc;
+    else y[i] = w[i] * (b[i] + r[i]) + acc;
+  }
 }
 
 // dense row-major copy of a small DIA+CSR matrix
@@ -583,11 +734,13 @@ __global__ void __launch_bounds__(kBlock) k_dense_inverse_lds(const double* __re
     for (int i = tid; i < nd; i += blockDim.x)
       if (i != k) fcol[i] = a[i * nd + k];
     __syncthreads();
-    for (int e = tid; e < nn; e += blockDim.x) {
-      const int i = e / nd, j = e - (e / nd) * nd;
+    for (int i = tid >> 5; i < nd; i += kBlock / 32) {   // 8 rows x 32 columns per pass
       if (i == k) continue;
-      const double base = (j == k) ? 0.0 : a[e];
-      a[e] = base - fcol[i] * a[k * nd + j];
+      const double fi = fcol[i];
+      for (int j = tid & 31; j < nd; j += 32) {
+        const double base = (j == k) ? 0.0 : a[i * nd + j];
+        a[i * nd + j] = base - fi * a[k * nd + j];
+      }
     }
     __syncthreads();
   }
@@ -620,12 +773,6 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(int nd, const double* __r
 // ------------------------------------------------------------------ AMG host
 
 namespace {
-
-struct HostCsr {
-  int n = 0;
-  std::vector<double> diag, val;
-  std::vector<int> ptr, col;
-};
 
 // Plain aggregation with row-relative strength |a_ij| >= theta max_k |a_ik|
 // (a threshold relative to the diagonal turns the wide stencils of coarse
@@ -723,9 +870,73 @@ void build_sell(const HostCsr& H, AmgLevel& F, hipStream_t s) {
   F.sell_nnz = (long long)n + H.ptr[n];
 }
 
+// Cycle operator from CSR rows (col, src per entry): SELL-64 for at least
+// kVecRows rows, else CSR.  Padding slots read column `pad_col` of their
+// row (its first column, or 0 for an empty row) with value 0.
+void build_cyc(int n, const std::vector<int>& ptr, const std::vector<int>& col, const std::vector<int>& src,
+               CycMat& M, hipStream_t s) {
+  M.n = n;
+  M.nnz = ptr[n];
+  M.sell = n >= kVecRows;
+  if (!M.sell) {
+    M.ptr.upload(ptr, s);
+    M.col.upload(col, s);
+    M.src.upload(src, s);
+    M.val.alloc(std::max<size_t>(col.size(), 1));
+    return;
+  }
+  const int ns = (n + 63) / 64;
+  std::vector<int> sptr(ns + 1, 0);
+  for (int sl = 0; sl < ns; ++sl) {
+    int width = 1;
+    for (int i = sl * 64; i < std::min(n, sl * 64 + 64); ++i) width = std::max(width, ptr[i + 1] - ptr[i]);
+    require((long long)sptr[sl] + 64LL * width < INT_MAX, "AMG operator too large for 32-bit SELL offsets");
+    sptr[sl + 1] = sptr[sl] + 64 * width;
+  }
+  const int ne = sptr[ns];
+  std::vector<int> scol(ne, 0), ssrc(ne, -1);
+  for (int sl = 0; sl < ns; ++sl) {
+    const int width = (sptr[sl + 1] - sptr[sl]) / 64;
+    for (int lane = 0; lane < 64; ++lane) {
+      const int i = sl * 64 + lane;
+      if (i >= n) continue;
+      const int pad = ptr[i + 1] > ptr[i] ? col[ptr[i]] : 0;
+      for (int k = 0; k < width; ++k) {
+        const int slot = sptr[sl] + 64 * k + lane;
+        if (ptr[i] + k < ptr[i + 1]) {
+          scol[slot] = col[ptr[i] + k];
+          ssrc[slot] = src[ptr[i] + k];
+        } else {
+          scol[slot] = pad;
+        }
+      }
+    }
+  }
+  M.ptr.upload(sptr, s);
+  M.col.upload(scol, s);
+  M.src.upload(ssrc, s);
+  M.val.alloc(ne);
+}
+
+CycView cyc_view(const CycMat& M) { return CycView{M.n, M.ptr.p, M.col.p, M.val.p}; }
+
+// device storage of a coarse level's DIA+CSR matrix (values filled by numeric())
+void coarse_storage(AmgLevel& Cl, const HostCsr& C, hipStream_t s) {
+  Cl.n = C.n;
+  Cl.diag.alloc(C.n);
+  Cl.ptr.upload(C.ptr, s);
+  Cl.col.upload(C.col, s);
+  Cl.val.alloc(C.col.size());
+  Cl.view.n = C.n;
+  Cl.view.diag = Cl.diag.p;
+  Cl.view.ptr = Cl.ptr.p;
+  Cl.view.col = Cl.col.p;
+  Cl.view.val = Cl.val.p;
+}
+
 }  // namespace
 
-void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max) {
+void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bool classical_) {
   if (const char* e = std::getenv("SPFAS_TRACE"); e && std::atoi(e) >= 2) {
     lvprof = std::make_shared<KernelProf>(64);
     lvprof->on = true;
@@ -750,7 +961,61 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max) {
     HIPCHECK(hipMemcpyAsync(H.val.data(), A0.val, nnz0 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHECK(hipStreamSynchronize(s));
   }
-  while (H.n > dense_max) {
+  classical = classical_;
+  while (classical && H.n > dense_max) {
+    ClassicalLevel CL;
+    if (!classical_level(H, kClassicalStrength, 0x5EED0000ULL + lv.size(), CL)) break;
+    AmgLevel& F = lv.back();
+    {   // A diag(w): every row as [diagonal, off-diagonal entries]
+      std::vector<int> p(H.n + 1, 0), c, src;
+      c.reserve(H.n + H.col.size());
+      src.reserve(H.n + H.col.size());
+      for (int i = 0; i < H.n; ++i) {
+        c.push_back(i);
+        src.push_back(dia_code(i));
+        for (int k = H.ptr[i]; k < H.ptr[i + 1]; ++k) {
+          c.push_back(H.col[k]);
+          src.push_back(off_code(k));
+        }
+        p[i + 1] = (int)c.size();
+      }
+      build_cyc(H.n, p, c, src, F.aw, s);
+    }
+    build_cyc(CL.nc, CL.rptr, CL.rcol, CL.rsrc, F.rm, s);
+    {
+      std::vector<int> src(CL.apcol.size());
+      std::iota(src.begin(), src.end(), 0);
+      build_cyc(H.n, CL.apptr, CL.apcol, src, F.cm, s);
+    }
+    if (sell64 && lv.size() == 1) {   // FP64 SELL copy of level 0 for the Krylov products
+      build_sell(H, F, s);
+      F.sval.release();
+      F.sell.val = nullptr;
+      F.sval64.alloc(F.scol.n);
+      F.sell64.n = F.n;
+      F.sell64.sptr = F.sptr.p;
+      F.sell64.col = F.scol.p;
+      F.sell64.val = F.sval64.p;
+    }
+    F.pval.upload(CL.pval, s);
+    F.aplptr.upload(CL.aplptr, s);
+    F.apla.upload(CL.apla, s);
+    F.aplp.upload(CL.aplp, s);
+    F.appidx.upload(CL.appidx, s);
+    F.apv.alloc(std::max<size_t>(CL.apcol.size(), 1));
+    F.clptr.upload(CL.clptr, s);
+    F.clr.upload(CL.clr, s);
+    F.clq.upload(CL.clq, s);
+    hipLaunchKernelGGL(k_fill_rm, dim3(grid_for(F.rm.src.n, kBlock)), dim3(kBlock), 0, s, (int)F.rm.src.n,
+                       F.rm.src.p, F.pval.p, F.rm.val.p);
+    LAUNCHCHECK();
+    lv.emplace_back();
+    coarse_storage(lv.back(), CL.C, s);
+    HIPCHECK(hipStreamSynchronize(s));
+    H = std::move(CL.C);
+  }
+  if (classical && lv.size() == 1 && H.n > dense_max) classical = false;   // no classical coarsening: aggregation
+  while (!classical && H.n > dense_max) {
     std::vector<int> agg;
     const int nc = aggregate(H, kStrength, agg);
     if (nc >= H.n || nc * 10 > H.n * 9) break;   // coarsening stalled
@@ -886,6 +1151,10 @@ std::string Amg::describe() const {
 }
 
 void Amg::numeric(hipStream_t s) {
+  if (classical) {
+    numeric_classical(s);
+    return;
+  }
   for (size_t k = 0; k + 1 < lv.size(); ++k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
@@ -900,7 +1169,7 @@ void Amg::numeric(hipStream_t s) {
     LAUNCHCHECK();
   }
   for (auto& L : lv) {
-    hipLaunchKernelGGL(k_invd, dim3(grid_for(L.n, kBlock)), dim3(kBlock), 0, s, L.view, L.invd.p);
+    hipLaunchKernelGGL(k_invd, dim3(grid_for((size_t)L.n * kVecG, kBlock)), dim3(kBlock), 0, s, L.view, L.invd.p);
     LAUNCHCHECK();
   }
   for (size_t k = 0; k + 1 < lv.size(); ++k) {
@@ -911,6 +1180,52 @@ void Amg::numeric(hipStream_t s) {
                        F.view.val, F.sval.p, F.sval64.p);
     LAUNCHCHECK();
   }
+  dense_numeric(s);
+}
+
+void Amg::numeric_classical(hipStream_t s) {
+  const int L = (int)lv.size();
+  for (int k = 0; k + 1 < L; ++k) {
+    AmgLevel& F = lv[k];
+    AmgLevel& C = lv[k + 1];
+    const int ne = (int)(F.aplptr.n - 1);
+    if (ne > 0) {
+      hipLaunchKernelGGL(k_ap_numeric, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.aplptr.p, F.apla.p,
+                         F.aplp.p, F.view, F.pval.p, F.apv.p);
+      LAUNCHCHECK();
+    }
+    const int noff = (int)C.col.n;
+    hipLaunchKernelGGL(k_rap_numeric, dim3(grid_for(noff + C.n, kBlock)), dim3(kBlock), 0, s, noff, C.n, F.clptr.p,
+                       F.clr.p, F.clq.p, F.pval.p, F.apv.p, C.val.p, C.diag.p);
+    LAUNCHCHECK();
+  }
+  for (auto& Lv : lv) {
+    hipLaunchKernelGGL(k_invd, dim3(grid_for((size_t)Lv.n * kVecG, kBlock)), dim3(kBlock), 0, s, Lv.view, Lv.invd.p);
+    LAUNCHCHECK();
+  }
+  for (int k = 0; k + 1 < L; ++k) {
+    AmgLevel& F = lv[k];
+    hipLaunchKernelGGL(k_fill_aw, dim3(grid_for(F.aw.src.n, kBlock)), dim3(kBlock), 0, s, (int)F.aw.src.n,
+                       F.aw.col.p, F.aw.src.p, F.view, F.invd.p, F.aw.val.p);
+    LAUNCHCHECK();
+    if (F.cm.sell)
+      hipLaunchKernelGGL(k_fill_cm, dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm), F.cm.src.p,
+                         F.appidx.p, F.pval.p, F.apv.p, F.invd.p, F.cm.val.p);
+    else
+      hipLaunchKernelGGL(k_fill_cmv, dim3(grid_for((size_t)F.n * kVecG, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm),
+                         F.cm.src.p, F.appidx.p, F.pval.p, F.apv.p, F.invd.p, F.cm.val.p);
+    LAUNCHCHECK();
+    if (F.sval64.n) {
+      const int ne = (int)F.sval64.n;
+      hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.view.diag,
+                         F.view.val, (float*)nullptr, F.sval64.p);
+      LAUNCHCHECK();
+    }
+  }
+  dense_numeric(s);
+}
+
+void Amg::dense_numeric(hipStream_t s) {
   AmgLevel& Lc = lv.back();
   hipLaunchKernelGGL(k_dense_fill, dim3(grid_for(nd, kBlock)), dim3(kBlock), 0, s, Lc.view, lu.p, nd);
   LAUNCHCHECK();
@@ -922,7 +1237,76 @@ void Amg::numeric(hipStream_t s) {
   LAUNCHCHECK();
 }
 
+// One V(1,1) cycle of the classical hierarchy, three kernels per level:
+// down [pre-sweep + residual] [restriction], up [prolongation + post-sweep].
+void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
+  const int L = (int)lv.size();
+  const double* bl = b;
+  for (int k = 0; k < L - 1; ++k) {
+    AmgLevel& F = lv[k];
+    AmgLevel& C = lv[k + 1];
+    KernelProf* pf = k == 0 ? hook.prof : nullptr;
+    timed(lvprof.get(), 3 * k, 0.0, s, [&] {
+      const double n = (double)F.n;
+      timed(pf, hook.down_id, 8.0 * (double)F.aw.nnz + 16.0 * n, s, [&] {
+        if (!F.aw.sell)
+          hipLaunchKernelGGL(k_cycv<0>, dim3(grid_for((size_t)F.n * kVecG, kBlock)), dim3(kBlock), 0, s,
+                             cyc_view(F.aw), bl, bl, nullptr, nullptr, F.r.p);
+        else if (pf)
+          hipLaunchKernelGGL((k_cyc<0, true>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.aw), bl,
+                             bl, nullptr, nullptr, F.r.p);
+        else
+          hipLaunchKernelGGL((k_cyc<0, false>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.aw), bl,
+                             bl, nullptr, nullptr, F.r.p);
+      });
+      timed(pf, hook.restrict_id, 8.0 * (double)F.rm.nnz + 8.0 * n + 8.0 * C.n, s, [&] {
+        if (!F.rm.sell)
+          hipLaunchKernelGGL(k_cycv<1>, dim3(grid_for((size_t)C.n * kVecG, kBlock)), dim3(kBlock), 0, s,
+                             cyc_view(F.rm), F.r.p, nullptr, nullptr, nullptr, C.b.p);
+        else if (pf)
+          hipLaunchKernelGGL((k_cyc<1, true>), dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.rm),
+                             F.r.p, nullptr, nullptr, nullptr, C.b.p);
+        else
+          hipLaunchKernelGGL((k_cyc<1, false>), dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.rm),
+                             F.r.p, nullptr, nullptr, nullptr, C.b.p);
+      });
+    });
+    LAUNCHCHECK();
+    bl = C.b.p;
+  }
+  double* xl = L == 1 ? x : lv.back().x.p;
+  timed(lvprof.get(), 63, 0.0, s, [&] {
+    hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd, lv.back().t.p, bl, xl);
+  });
+  LAUNCHCHECK();
+  for (int k = L - 2; k >= 0; --k) {
+    AmgLevel& F = lv[k];
+    AmgLevel& C = lv[k + 1];
+    double* xf = (k == 0) ? x : F.x.p;
+    const double* bf = (k == 0) ? b : F.b.p;
+    KernelProf* pf = k == 0 ? hook.prof : nullptr;
+    timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
+      timed(pf, hook.up_id, 8.0 * (double)F.cm.nnz + 32.0 * F.n + 8.0 * C.n, s, [&] {
+        if (!F.cm.sell)
+          hipLaunchKernelGGL(k_cycv<2>, dim3(grid_for((size_t)F.n * kVecG, kBlock)), dim3(kBlock), 0, s,
+                             cyc_view(F.cm), C.x.p, bf, F.r.p, F.invd.p, xf);
+        else if (pf)
+          hipLaunchKernelGGL((k_cyc<2, true>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm), C.x.p,
+                             bf, F.r.p, F.invd.p, xf);
+        else
+          hipLaunchKernelGGL((k_cyc<2, false>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm),
+                             C.x.p, bf, F.r.p, F.invd.p, xf);
+      });
+    });
+    LAUNCHCHECK();
+  }
+}
+
 void Amg::apply(const double* b, double* x, hipStream_t s) {
+  if (classical) {
+    apply_classical(b, x, s);
+    return;
+  }
   // level 0 uses the caller's b and x; V(2,2) with the sweep pairs fused:
   // down: [two sweeps from zero] [residual] [restriction];
   // up:   [prolongation + sweep] [sweep].
@@ -947,16 +1331,16 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
       continue;
     }
     timed(lvprof.get(), 3 * k, 0.0, s, [&] {
-    timed(pf, hook.pre_id, E + 24.0 * n, s, [&] {
+    timed(pf, hook.down_id, 2.0 * E + 48.0 * n, s, [&] {
       if (pf) hipLaunchKernelGGL(k_amg_pre<true>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bl, F.t.p);
       else hipLaunchKernelGGL(k_amg_pre<false>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bl, F.t.p);
-    });
-    timed(pf, hook.resid_id, E + 24.0 * n, s, [&] {
       if (pf) hipLaunchKernelGGL(k_amg_resid<true>, dim3(g), dim3(kBlock), 0, s, F.sell, bl, F.t.p, F.r.p);
       else hipLaunchKernelGGL(k_amg_resid<false>, dim3(g), dim3(kBlock), 0, s, F.sell, bl, F.t.p, F.r.p);
     });
-    hipLaunchKernelGGL(k_restrict, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.mptr.p, F.mem.p, F.r.p,
-                       C.b.p);
+    timed(pf, hook.restrict_id, 12.0 * n + 8.0 * C.n, s, [&] {
+      hipLaunchKernelGGL(k_restrict, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, C.n, F.mptr.p, F.mem.p, F.r.p,
+                         C.b.p);
+    });
     LAUNCHCHECK();
     });
     bl = C.b.p;
@@ -985,15 +1369,13 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
       continue;
     }
     timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
-    timed(pf, hook.post1_id, E + 36.0 * n, s, [&] {
+    timed(pf, hook.up_id, 2.0 * E + 68.0 * n, s, [&] {
       if (pf)
         hipLaunchKernelGGL(k_amg_post1<true>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.t.p, F.agg.p,
                            C.x.p, F.r.p);
       else
         hipLaunchKernelGGL(k_amg_post1<false>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.t.p, F.agg.p,
                            C.x.p, F.r.p);
-    });
-    timed(pf, hook.post2_id, E + 32.0 * n, s, [&] {
       if (pf) hipLaunchKernelGGL(k_amg_post2<true>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.r.p, xf);
       else hipLaunchKernelGGL(k_amg_post2<false>, dim3(g), dim3(kBlock), 0, s, F.sell, F.invd.p, bf, F.r.p, xf);
     });

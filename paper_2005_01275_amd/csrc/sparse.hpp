@@ -7,12 +7,18 @@
 // off-diagonal entries in CSR (ptr/col/val).  The pattern is fixed at setup;
 // values are rewritten by each linearisation.
 //
-// Preconditioner: unsmoothed-aggregation AMG.  Aggregates come from the
-// strength of connection of the matrix values at setup (kappa = 1, Picard);
-// coarse values are recomputed on the device after every linearisation as
-// fixed-order sums of fine entries (P^T A P with piecewise-constant P), the
-// coarsest level is factored by dense LU with partial pivoting.  Smoother:
-// Jacobi with weights 1 / (|a_ii| + 0.5 sum_j |a_ij|).
+// Preconditioners (both rebuilt numerically after every linearisation on a
+// pattern and transfer fixed at setup from the matrix values at setup):
+//  * classical AMG (level-0 eliminated system): PMIS coarsening,
+//    extended+i interpolation P kept from setup, Galerkin coarse values
+//    P^T A P recomputed on the device from per-entry product lists;
+//    V(1,1) with one l1-Jacobi sweep on each side, fused into three kernels
+//    per level (pre-sweep + residual, restriction, prolongation + sweep
+//    through the stored A P);
+//  * unsmoothed-aggregation AMG (hybridised coarse systems): piecewise-
+//    constant P, V(2,2).
+// Smoother weights 1 / (|a_ii| + 0.5 sum_j |a_ij|); the coarsest level is
+// inverted densely.
 //
 // Krylov: PCG (symmetric Picard systems) and BiCGStab (Newton systems); all
 // scalars stay on the device, the host reads the residual norm once per
@@ -65,6 +71,25 @@ struct Sell64View {
   const double* val = nullptr;
 };
 
+// A sparse operator of the classical cycle with FP32 values: SELL-64
+// (thread per row, `sell`) for large row counts, else CSR read by a lane
+// group per row.  Padding slots of SELL have col = row and src = -1.
+struct CycMat {
+  int n = 0;
+  bool sell = false;
+  DVec<int> ptr, col;                 // SELL: slice offsets [ceil(n/64)+1]; CSR: row pointers [n+1]
+  DVec<float> val;
+  DVec<int> src;                      // per stored slot: source entry of the value, -1 = padding
+  long long nnz = 0;                  // stored entries without padding
+};
+
+struct CycView {
+  int n;
+  const int* ptr;
+  const int* col;
+  const float* val;
+};
+
 struct AmgLevel {
   int n = 0;
   // SELL-64 copy for the cycle (levels that have a coarser level)
@@ -86,22 +111,32 @@ struct AmgLevel {
   // Galerkin contributors of the next level's entries
   DVec<int> goff_ptr, goff_idx;       // coarse off entry -> fine off indices
   DVec<int> gdiag_ptr, gdiag_idx;     // coarse diag -> (idx << 1 | is_off)
+  // classical interpolation to the next level (kept from setup) and the
+  // product lists of A P and of the next level's entries
+  DVec<double> pval;                  // P values, CSR order
+  DVec<int> aplptr, apla, aplp;       // A P entry -> (A entry code, P entry) products
+  DVec<int> appidx;                   // A P entry -> P entry at the same position, -1
+  DVec<double> apv;                   // A P values
+  DVec<int> clptr, clr, clq;          // next level's off entries then diagonal -> (P entry, A P entry)
+  CycMat aw, rm, cm;                  // cycle operators A diag(w), R = P^T, P - diag(w) A P
   DVec<double> x, b, r, t;            // work vectors
 };
 
 struct KernelProf;
 // Optional event timing of the finest-level launches of the Krylov solver
-// (SpMV) and of the AMG cycle (two-sweep pre-smoothing, residual,
-// prolongation + sweep, last sweep); the AMG computes its own byte counts.
+// (SpMV) and of the AMG cycle (smoothing + residual on the way down,
+// restriction, prolongation + smoothing on the way up); the AMG computes
+// its own byte counts.
 struct ProfHook {
   KernelProf* prof = nullptr;
   int spmv_id = -1, spmv2_id = -1;
   double spmv_bytes = 0.0;
-  int pre_id = -1, resid_id = -1, post1_id = -1, post2_id = -1;
+  int down_id = -1, restrict_id = -1, up_id = -1;
 };
 
 struct Amg {
   std::vector<AmgLevel> lv;           // lv[0] is the fine matrix
+  bool classical = false;             // classical levels (else aggregation)
   ProfHook hook;
   int nd = 0;                         // dense coarsest size
   DVec<double> lu;                    // [nd*nd]
@@ -110,9 +145,15 @@ struct Amg {
   int cycles = 1;
   // host setup from the matrix pattern and setup values
   // sell64: also keep FP64 SELL values of level 0 (for Krylov::sell64)
-  void setup(const CsrView& A0, hipStream_t s, bool sell64 = false, int dense_max = kDenseLds);
+  // classical: classical coarsening (falls back to aggregation when the first
+  // classical step stalls)
+  void setup(const CsrView& A0, hipStream_t s, bool sell64 = false, int dense_max = kDenseLds,
+             bool classical = false);
   void numeric(hipStream_t s);        // coarse values, weights, dense LU
   void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
+  void numeric_classical(hipStream_t s);
+  void apply_classical(const double* b, double* x, hipStream_t s);
+  void dense_numeric(hipStream_t s);
   int n_levels() const { return (int)lv.size(); }
   std::string describe() const;       // "n/nnz" per level, for diagnostics
   // SPFAS_TRACE=2: event time of every level's down and up legs; level_times()
