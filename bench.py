@@ -31,11 +31,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
     ap.add_argument("--seed", type=int, default=0, help="seed of the synthetic fields (the workload is seed 0)")
-    ap.add_argument("--lin-rtol", type=float, default=1e-4)
+    ap.add_argument("--lin-rtol", type=float, default=1e-5)
     ap.add_argument("--lin-rtol-coarse", type=float, default=1e-2, help="<= 0: same as --lin-rtol")
     ap.add_argument("--lin-target", type=float, default=0.03, help="level-0 inexact-Newton forcing, 0 = off")
     ap.add_argument("--newton-krylov", default="pcg", choices=["pcg", "bicgstab"],
                     help="pcg: PCG first with BiCGStab fallback on Newton systems")
+    ap.add_argument("--amg-reuse", type=int, default=-1,
+                    help="linearisations that may reuse AMG values while the Krylov count stays low "
+                         "(0 = off, < 0 = no limit)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     return ap.parse_args()
@@ -150,7 +153,8 @@ def main():
     cap = math.log(prob.dp_cap_c) / prob.alpha
     opts = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=args.lin_rtol,
                         lin_max_it=400, dp_cap=cap, lin_rtol_coarse=args.lin_rtol_coarse,
-                        lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"))
+                        lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"),
+                        amg_reuse=args.amg_reuse)
 
     def solve():
         return H.fas_solve(prob, opts, device=True, cprob=cprob, out=(p, s), stream=stream.cuda_stream)
@@ -203,7 +207,7 @@ def main():
         "config": {"workload": prob.name + " FAS-Newton, 4 levels of 4x4x4 aggregates, m=3, rtol 1e-8",
                    "cells": n_cells, "levels": prob.n_levels, "smoother": "newton",
                    "lin_rtol": args.lin_rtol, "lin_rtol_coarse": args.lin_rtol_coarse or args.lin_rtol,
-                   "lin_target": args.lin_target, "newton_krylov": args.newton_krylov},
+                   "lin_target": args.lin_target, "newton_krylov": args.newton_krylov, "amg_reuse": args.amg_reuse},
         "cell_updates_per_s": cell_updates,
         "latency_ms_p50": 1000.0 * percentile(lat, 0.5),
         "latency_ms_p99": 1000.0 * percentile(lat, 0.99),
@@ -219,7 +223,8 @@ def main():
         comp = {}
         for name, fn, sm in (("newton", H.newton_solve, pk.SPFAS_NEWTON), ("picard", H.picard_solve, pk.SPFAS_PICARD)):
             o = pk.SolveOpts(smoother=sm, rtol=1e-8, atol=0.0, max_it=200, lin_rtol=args.lin_rtol, lin_max_it=400,
-                             dp_cap=cap, lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"))
+                             dp_cap=cap, lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"),
+                             amg_reuse=args.amg_reuse)
             torch.cuda.synchronize()
             a = time.perf_counter()
             _, _, st = fn(prob, o, device=True, cprob=cprob, out=(p, s), stream=stream.cuda_stream)

@@ -146,8 +146,18 @@ typedef struct {
  *   newton_pcg          nonzero: Newton systems are first tried with PCG
  *                       (they are nearly symmetric: the non-symmetric part
  *                       is the kappa' term of E), falling back to BiCGStab
- *                       from scratch on a breakdown or without convergence;
- *                       0: BiCGStab only
+ *                       from scratch on a breakdown, on a stall (||r||
+ *                       lowered less than 2x over 10 iterations) or
+ *                       without convergence; 0: BiCGStab only
+ *   amg_reuse           > 0: the AMG values of a level's preconditioner are
+ *                       kept for up to amg_reuse further linearisations of
+ *                       the same solve (< 0: no limit), as long as its
+ *                       Krylov solves take at most f + max(2, f/2)
+ *                       iterations, f being the count right after the values
+ *                       were last recomputed; the Krylov products always use
+ *                       the current matrix, so only the inner iteration
+ *                       changes, never the system solved.  0: recomputed
+ *                       after every linearisation
  */
 typedef struct {
   int32_t smoother;
@@ -164,6 +174,7 @@ typedef struct {
   double lin_rtol_coarse;
   double lin_target;
   int32_t newton_pcg;
+  int32_t amg_reuse;
 } spfas_solve_opts;
 
 typedef struct {

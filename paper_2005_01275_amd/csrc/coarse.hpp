@@ -59,6 +59,7 @@ struct CoarseLevel {
   DVec<double> Hdiag, Hoff, xi, lam;
   CsrView H;
   Amg amg;
+  PrecReuse prec;
   Krylov kry;
   // nonlinear work
   DVec<double> x, dx, b, r, t, inv, z, div, x0, ax, zeros;

@@ -45,6 +45,7 @@ struct FineWork {
   DVec<double> div;                       // [n] D sigma (projection of bubbles)
   DVec<double> Sdiag, Soff, rhs;          // S = D M^{-1} E, right-hand side
   Amg amg;
+  PrecReuse prec;
   Krylov kry;
   CsrView S;
 };

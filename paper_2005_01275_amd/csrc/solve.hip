@@ -53,6 +53,7 @@ struct Opts {
   double lin_target = 0.0;       // inexact-Newton forcing on level 0; 0 = off
   double stop_tol = 0.0;         // outer stopping threshold of the running solve
   bool newton_pcg = false;       // PCG first on Newton systems, BiCGStab as fallback
+  int amg_reuse = 0;             // linearisations that may reuse AMG values (0 = none, < 0 = no limit)
 };
 
 static Opts make_opts(const spfas_solve_opts& o, bool newton) {
@@ -70,6 +71,7 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
   r.lin_rtol_coarse = o.lin_rtol_coarse > 0.0 ? o.lin_rtol_coarse : o.lin_rtol;
   r.lin_target = o.lin_target;
   r.newton_pcg = o.newton_pcg != 0;
+  r.amg_reuse = o.amg_reuse;
   require(o.lin_target >= 0.0, "lin_target must be non-negative");
   require(r.max_it >= 0 && r.bt_nmax >= 0 && r.coarsest_max >= 0 && r.lin_max_it > 0, "negative iteration limits");
   require(r.bt_theta > 0.0 && r.bt_theta <= 1.0, "bt_theta must be in (0, 1]");
@@ -108,6 +110,10 @@ static double backtrack(const std::function<double(double)>& rn_raw, double r_x,
   return s;
 }
 
+// PCG on a (non-symmetric) Newton system hands over to BiCGStab when ||r||
+// fell less than 2x over this many iterations.
+constexpr int kPcgStall = 10;
+
 // Krylov solve of a linearised system: PCG for Picard (symmetric);
 // BiCGStab for Newton, or PCG first with BiCGStab from scratch when PCG
 // breaks down or does not converge within the iteration limit.
@@ -115,11 +121,39 @@ static int krylov_solve(Krylov& kry, const CsrView& A, Amg* M, const double* b, 
                         const Opts& o, hipStream_t s) {
   if (!o.newton) return kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
   if (o.newton_pcg) {
-    const int it = kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
+    const int it = kry.pcg(A, M, b, x, rtol, o.lin_max_it, s, kPcgStall);
     if (kry.converged) return it;
-    return it + kry.bicgstab(A, M, b, x, rtol, o.lin_max_it, s);
+    const int it2 = kry.bicgstab(A, M, b, x, rtol, o.lin_max_it, s);
+    if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
+      std::fprintf(stderr, "[spfas] PCG stopped after %d iterations without convergence; BiCGStab %d\n", it, it2);
+    return it + it2;
   }
   return kry.bicgstab(A, M, b, x, rtol, o.lin_max_it, s);
+}
+
+// Preconditioner values for the next linearised solve: recomputed unless
+// they were computed at most amg_reuse linearisations ago (any number when
+// amg_reuse < 0) and the last solve
+// stayed within f + max(2, f/2) iterations (f: the count right after the
+// last recomputation).  The operator copy the Krylov products read is
+// refreshed either way.
+static bool prec_refresh(Amg& amg, PrecReuse& pr, const Opts& o, hipStream_t s) {
+  const bool aged = o.amg_reuse >= 0 && pr.age >= o.amg_reuse;
+  const bool fresh = !pr.valid || aged || pr.last > pr.fresh + std::max(2, pr.fresh / 2);
+  if (fresh) amg.numeric(s);
+  else amg.operator_values(s);
+  return fresh;
+}
+
+static void prec_record(PrecReuse& pr, bool fresh, int it, bool failed) {
+  pr.last = it;
+  if (fresh) {
+    pr.fresh = it;
+    pr.age = 0;
+  } else {
+    pr.age++;
+  }
+  pr.valid = !failed;
 }
 
 // SPFAS_TRACE=1 prints one line per smoothing step to stderr.
@@ -206,13 +240,14 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   const double t0 = trace_on() ? trace_clock(s) : 0.0;
   h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 56.0 * nf + 24.0 * n, s,
              [&] { launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s); });
-  w.amg.numeric(s);
+  const bool fresh = prec_refresh(w.amg, w.prec, o, s);
   double* dp = w.dx.p + nf;
   int it;
   double eta = o.lin_rtol;
   if (o.lin_target > 0.0 && o.stop_tol > 0.0 && r_x > 0.0)
     eta = std::max(eta, std::min(0.1, o.lin_target * o.stop_tol / r_x));
   it = krylov_solve(w.kry, w.S, &w.amg, w.rhs.p, dp, eta, o, s);
+  prec_record(w.prec, fresh, it, w.kry.failed);
   st.lin_iters += it;
   double mx = HUGE_VAL;
   if (!w.kry.failed) {
@@ -293,7 +328,14 @@ static void store_state(Hierarchy& h, const spfas_problem& prob, double* p, doub
 
 // ------------------------------------------------------------------ drivers
 
+// every solve starts with freshly computed preconditioner values
+static void prec_reset(Hierarchy& h) {
+  h.fw.prec = PrecReuse();
+  for (auto& c : h.coarse) c->prec = PrecReuse();
+}
+
 static int single_level(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
+  prec_reset(h);
   double r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "initial residual");
   st.r0 = r;
   const double tol = std::max(o_in.rtol * r, o_in.atol);
@@ -343,8 +385,9 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   int it = 0;
   if (C.nl > 0) {
     launch_H_assemble(C, s);
-    C.amg.numeric(s);
+    const bool fresh = prec_refresh(C.amg, C.prec, o, s);
     it = krylov_solve(C.kry, C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o, s);
+    prec_record(C.prec, fresh, it, C.kry.failed);
     st.lin_iters += it;
   }
   double mx = HUGE_VAL;
@@ -448,6 +491,7 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
 }
 
 int run_fas(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
+  prec_reset(h);
   double r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "initial residual");
   st.r0 = r;
   const double tol = std::max(o_in.rtol * r, o_in.atol);

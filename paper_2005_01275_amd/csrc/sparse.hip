@@ -1183,6 +1183,15 @@ void Amg::numeric(hipStream_t s) {
   dense_numeric(s);
 }
 
+void Amg::operator_values(hipStream_t s) {
+  AmgLevel& F = lv[0];
+  if (!F.sval64.n) return;
+  const int ne = (int)F.sval64.n;
+  hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.view.diag,
+                     F.view.val, (float*)nullptr, F.sval64.p);
+  LAUNCHCHECK();
+}
+
 void Amg::numeric_classical(hipStream_t s) {
   const int L = (int)lv.size();
   for (int k = 0; k + 1 < L; ++k) {
@@ -1449,7 +1458,8 @@ static double read_slot(double* hscal, const double* scal, int slot, hipStream_t
   return hscal[slot];
 }
 
-int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st) {
+int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st,
+                int stall) {
   alloc(A.n);
   const int G = reduce_grid(n);
   const unsigned g1 = grid_for(n, kBlock);
@@ -1478,6 +1488,16 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     rr = hlag[2 * (k & 1) + 1];
   };
   auto bad = [&](double pq, double rr) { return !std::isfinite(rr) || !(pq > 0.0); };
+  // stall > 0: give up (neither converged nor failed) once r.r of an
+  // iteration is above a quarter of its value `stall` iterations earlier
+  std::vector<double> hist;
+  auto stalled = [&](int k, double rr) {
+    if (stall <= 0) return false;
+    if ((int)hist.size() <= k) hist.resize(k + 1, HUGE_VAL);
+    hist[k] = rr;
+    return k >= stall && rr > 0.25 * hist[k - stall];
+  };
+  bool stop = false;
   bool near = false;   // within a factor 10 of the tolerance: check every iteration at once
   for (; it < maxit; ++it) {
     if (M) M->apply(r.p, z.p, st);
@@ -1499,16 +1519,18 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
       lagged(it - 1, pq, rr);
       if (bad(pq, rr)) { failed = true; ++it; break; }
       if (rr <= tol2) { converged = true; ++it; break; }
+      if (stalled(it - 1, rr)) { stop = true; ++it; break; }
       near = rr <= 100.0 * tol2;
     }
     if (near || it == 0) {
       lagged(it, pq, rr);
       if (bad(pq, rr)) { failed = true; ++it; break; }
       if (rr <= tol2) { converged = true; ++it; break; }
+      if (stalled(it, rr)) { stop = true; ++it; break; }
       near = rr <= 100.0 * tol2;
     }
   }
-  if (!failed && !converged && it > 0 && !near) {   // the last iteration has not been checked yet
+  if (!failed && !converged && !stop && it > 0 && !near) {   // the last iteration has not been checked yet
     double pq, rr;
     lagged(it - 1, pq, rr);
     if (bad(pq, rr)) failed = true;

@@ -122,6 +122,14 @@ struct AmgLevel {
   DVec<double> x, b, r, t;            // work vectors
 };
 
+// Reuse state of a preconditioner across the linearisations of one solve.
+struct PrecReuse {
+  bool valid = false;                 // values computed in this solve and the last solve did not fail
+  int fresh = 0;                      // Krylov iterations right after the last recomputation
+  int last = 0;                       // Krylov iterations of the last solve
+  int age = 0;                        // linearisations since the last recomputation
+};
+
 struct KernelProf;
 // Optional event timing of the finest-level launches of the Krylov solver
 // (SpMV) and of the AMG cycle (smoothing + residual on the way down,
@@ -150,6 +158,7 @@ struct Amg {
   void setup(const CsrView& A0, hipStream_t s, bool sell64 = false, int dense_max = kDenseLds,
              bool classical = false);
   void numeric(hipStream_t s);        // coarse values, weights, dense LU
+  void operator_values(hipStream_t s);   // only the FP64 SELL copy of level 0 (Krylov operator)
   void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
   void numeric_classical(hipStream_t s);
   void apply_classical(const double* b, double* x, hipStream_t s);
@@ -177,7 +186,10 @@ struct Krylov {
   ~Krylov();
   void alloc(int n_);
   // returns the number of iterations; x is overwritten (zero initial guess)
-  int pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st);
+  // stall > 0: stop without convergence when ||r|| fell less than 2x over
+  // the last `stall` iterations (for a caller with a fallback method)
+  int pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st,
+          int stall = 0);
   int bicgstab(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st);
 };
 

@@ -131,6 +131,27 @@ def test_newton_pcg_converged_and_vcycle(kw):
     assert np.linalg.norm(p - ref_p) <= 1e-10 * np.linalg.norm(ref_p)
 
 
+@pytest.mark.parametrize("kw", CASES + ["c1"])
+def test_amg_reuse_reaches_the_same_root(kw):
+    """Keeping the AMG values across linearisations (amg_reuse) only changes
+    the inner iteration: FAS-Newton and FAS-Picard still reach the oracle's
+    root x*, with and without an age limit."""
+    import paper_2005_01275_amd as pk
+    print("case", kw, flush=True)
+    prob = problem(kw)
+    h, p_star, s_star = oracle_root(prob)
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    for sm in (pk.SPFAS_NEWTON, pk.SPFAS_PICARD):
+        for reuse in (-1, 2):
+            o = opts(sm, prob)
+            o.newton_pcg = 1
+            o.amg_reuse = reuse
+            p, s, st = H.fas_solve(prob, o)
+            assert st["converged"], (sm, reuse, st)
+            assert np.linalg.norm(p - p_star) <= 1e-10 * np.linalg.norm(p_star), (sm, reuse)
+            assert np.linalg.norm(s - s_star) <= 1e-10 * np.linalg.norm(s_star), (sm, reuse)
+
+
 EDGE = [
     # more levels than the lattice coarsens: the last levels hold one aggregate each
     dict(shape=(4, 4), seed=0, box=(2, 2), m=2, n_levels=5),
