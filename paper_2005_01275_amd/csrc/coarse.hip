@@ -596,62 +596,72 @@ static TView tview(const TransferDev& T, const CoarseLevel& C) {
 
 // out = P^T in (R), or out = Q in (Q: flux moments on interfaces, divergence
 // moments of the NPV columns on bubbles) -- items: coarse flux unknowns, then
-// aggregates (pressure coefficients).
+// aggregates (pressure coefficients).  One wave per item: the lanes split the
+// item's sums (fine fluxes of the group, interior dofs of the adjacent
+// aggregates, cells of the aggregate) and a fixed-order wave reduction
+// combines them.
+__device__ inline double wave_allsum_t(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 template <bool PROJECT>
 __global__ void __launch_bounds__(kBlock) k_restrict_t(TView t, const double* __restrict__ in, const double* __restrict__ divf,
                                                        double* __restrict__ out) {
-  const int ntot = t.nf_c + t.n_agg;
+  const int it = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (it >= t.nf_c + t.n_agg) return;   // whole wave
   const double* in_s = in;
   const double* in_p = in + t.nf_f;
-  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x) {
-    if (it < t.nf_c) {
-      const int J = it;
-      double acc = 0.0;
-      if (t.kind[J] != 2) {
-        for (int q = t.fgrp_ptr[J]; q < t.fgrp_ptr[J + 1]; ++q) {
-          const int g = t.fgrp_list[q];
-          acc += (PROJECT ? t.omega[g] : t.trace[g]) * in_s[g];
-        }
+  if (it < t.nf_c) {
+    const int J = it;
+    double acc = 0.0;
+    if (t.kind[J] != 2)
+      for (int q = t.fgrp_ptr[J] + lane; q < t.fgrp_ptr[J + 1]; q += 64) {
+        const int g = t.fgrp_list[q];
+        acc += (PROJECT ? t.omega[g] : t.trace[g]) * in_s[g];
       }
-      if (!PROJECT) {
-        for (int slot = 0; slot < 2; ++slot) {
-          const int A = t.fcell[2 * J + slot];
-          if (A < 0) continue;
-          const int loc = t.floc[2 * J + slot];
-          const int kA = t.lfptr[A + 1] - t.lfptr[A];
-          const double* EA = t.E + t.Eptr[A];
-          const int* dl = t.dof_list + t.dof_ptr[A];
-          const int nI = t.n_int[A];
-          for (int s = 0; s < nI; ++s) acc += EA[s * kA + loc] * in_s[dl[s]];
-        }
-      } else if (t.kind[J] == 2) {
-        const int A = t.fcell[2 * J];
-        const int j = 1 + (J - t.bub0[A]);
-        const int mA = t.mA[A];
-        const double* PA = t.P + t.Pptr[A];
-        const int* pl = t.pd_list + t.pd_ptr[A];
-        const int npA = t.pd_ptr[A + 1] - t.pd_ptr[A];
-        for (int r = 0; r < npA; ++r) acc += PA[r * mA + j] * divf[pl[r]];
+    if (!PROJECT) {
+      for (int slot = 0; slot < 2; ++slot) {
+        const int A = t.fcell[2 * J + slot];
+        if (A < 0) continue;
+        const int loc = t.floc[2 * J + slot];
+        const int kA = t.lfptr[A + 1] - t.lfptr[A];
+        const double* EA = t.E + t.Eptr[A];
+        const int* dl = t.dof_list + t.dof_ptr[A];
+        const int nI = t.n_int[A];
+        for (int q = lane; q < nI; q += 64) acc += EA[q * kA + loc] * in_s[dl[q]];
       }
-      out[J] = acc;
-    } else {
-      const int A = it - t.nf_c;
+    } else if (t.kind[J] == 2) {
+      const int A = t.fcell[2 * J];
+      const int j = 1 + (J - t.bub0[A]);
       const int mA = t.mA[A];
       const double* PA = t.P + t.Pptr[A];
       const int* pl = t.pd_list + t.pd_ptr[A];
       const int npA = t.pd_ptr[A + 1] - t.pd_ptr[A];
-      for (int i = 0; i < mA; ++i) {
-        double acc = 0.0;
-        for (int r = 0; r < npA; ++r) acc += PA[r * mA + i] * in_p[pl[r]];
-        out[t.nf_c + t.pptr[A] + i] = acc;
-      }
+      for (int r = lane; r < npA; r += 64) acc += PA[r * mA + j] * divf[pl[r]];
+    }
+    acc = wave_allsum_t(acc);
+    if (lane == 0) out[J] = acc;
+  } else {
+    const int A = it - t.nf_c;
+    const int mA = t.mA[A];
+    const double* PA = t.P + t.Pptr[A];
+    const int* pl = t.pd_list + t.pd_ptr[A];
+    const int npA = t.pd_ptr[A + 1] - t.pd_ptr[A];
+    for (int i = 0; i < mA; ++i) {
+      double acc = 0.0;
+      for (int r = lane; r < npA; r += 64) acc += PA[r * mA + i] * in_p[pl[r]];
+      acc = wave_allsum_t(acc);
+      if (lane == 0) out[t.nf_c + t.pptr[A] + i] = acc;
     }
   }
 }
 
 void launch_restrict(const TransferDev& T, const CoarseLevel& Cc, const double* rf, double* out, hipStream_t s) {
   TView t = tview(T, Cc);
-  hipLaunchKernelGGL(k_restrict_t<false>, dim3(grid_for(t.nf_c + t.n_agg, kBlock)), dim3(kBlock), 0, s, t, rf,
+  hipLaunchKernelGGL(k_restrict_t<false>, dim3(grid_for(t.nf_c + t.n_agg, kBlock / 64)), dim3(kBlock), 0, s, t, rf,
                      (const double*)nullptr, out);
   LAUNCHCHECK();
 }
@@ -659,8 +669,8 @@ void launch_restrict(const TransferDev& T, const CoarseLevel& Cc, const double* 
 void launch_project(const TransferDev& T, const CoarseLevel& Cc, const double* xf, const double* divf, double* out,
                     hipStream_t s) {
   TView t = tview(T, Cc);
-  hipLaunchKernelGGL(k_restrict_t<true>, dim3(grid_for(t.nf_c + t.n_agg, kBlock)), dim3(kBlock), 0, s, t, xf, divf,
-                     out);
+  hipLaunchKernelGGL(k_restrict_t<true>, dim3(grid_for(t.nf_c + t.n_agg, kBlock / 64)), dim3(kBlock), 0, s, t, xf,
+                     divf, out);
   LAUNCHCHECK();
 }
 
