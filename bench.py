@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--lin-rtol", type=float, default=1e-5)
     ap.add_argument("--lin-rtol-coarse", type=float, default=1e-2, help="<= 0: same as --lin-rtol")
     ap.add_argument("--lin-target", type=float, default=0.03, help="level-0 inexact-Newton forcing, 0 = off")
+    ap.add_argument("--lin-max-it-coarse", type=int, default=10,
+                    help="iteration limit of each coarse-level Krylov method (<= 0: same as level 0)")
     ap.add_argument("--newton-krylov", default="pcg", choices=["pcg", "bicgstab"],
                     help="pcg: PCG first with BiCGStab fallback on Newton systems")
     ap.add_argument("--amg-reuse", type=int, default=-1,
@@ -154,7 +156,7 @@ def main():
     opts = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=args.lin_rtol,
                         lin_max_it=400, dp_cap=cap, lin_rtol_coarse=args.lin_rtol_coarse,
                         lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"),
-                        amg_reuse=args.amg_reuse)
+                        amg_reuse=args.amg_reuse, lin_max_it_coarse=args.lin_max_it_coarse)
 
     def solve():
         return H.fas_solve(prob, opts, device=True, cprob=cprob, out=(p, s), stream=stream.cuda_stream)
@@ -207,7 +209,8 @@ def main():
         "config": {"workload": prob.name + " FAS-Newton, 4 levels of 4x4x4 aggregates, m=3, rtol 1e-8",
                    "cells": n_cells, "levels": prob.n_levels, "smoother": "newton",
                    "lin_rtol": args.lin_rtol, "lin_rtol_coarse": args.lin_rtol_coarse or args.lin_rtol,
-                   "lin_target": args.lin_target, "newton_krylov": args.newton_krylov, "amg_reuse": args.amg_reuse},
+                   "lin_target": args.lin_target, "newton_krylov": args.newton_krylov, "amg_reuse": args.amg_reuse,
+                   "lin_max_it_coarse": args.lin_max_it_coarse},
         "cell_updates_per_s": cell_updates,
         "latency_ms_p50": 1000.0 * percentile(lat, 0.5),
         "latency_ms_p99": 1000.0 * percentile(lat, 0.99),
@@ -224,7 +227,7 @@ def main():
         for name, fn, sm in (("newton", H.newton_solve, pk.SPFAS_NEWTON), ("picard", H.picard_solve, pk.SPFAS_PICARD)):
             o = pk.SolveOpts(smoother=sm, rtol=1e-8, atol=0.0, max_it=200, lin_rtol=args.lin_rtol, lin_max_it=400,
                              dp_cap=cap, lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"),
-                             amg_reuse=args.amg_reuse)
+                             amg_reuse=args.amg_reuse, lin_max_it_coarse=args.lin_max_it_coarse)
             torch.cuda.synchronize()
             a = time.perf_counter()
             _, _, st = fn(prob, o, device=True, cprob=cprob, out=(p, s), stream=stream.cuda_stream)

@@ -147,7 +147,7 @@ typedef struct {
  *                       (they are nearly symmetric: the non-symmetric part
  *                       is the kappa' term of E), falling back to BiCGStab
  *                       from scratch on a breakdown, on a stall (||r||
- *                       lowered less than 2x over 10 iterations) or
+ *                       lowered less than 2x over 5 iterations) or
  *                       without convergence; 0: BiCGStab only
  *   amg_reuse           > 0: the AMG values of a level's preconditioner are
  *                       kept for up to amg_reuse further linearisations of
@@ -158,6 +158,10 @@ typedef struct {
  *                       the current matrix, so only the inner iteration
  *                       changes, never the system solved.  0: recomputed
  *                       after every linearisation
+ *   lin_max_it_coarse   iteration limit of each coarse-level Krylov method
+ *                       (<= 0: lin_max_it); a solve that reaches it hands
+ *                       its current iterate to the smoothing step, whose
+ *                       direction Alg. 1 then checks
  */
 typedef struct {
   int32_t smoother;
@@ -175,6 +179,7 @@ typedef struct {
   double lin_target;
   int32_t newton_pcg;
   int32_t amg_reuse;
+  int32_t lin_max_it_coarse;
 } spfas_solve_opts;
 
 typedef struct {

@@ -46,6 +46,7 @@ class SolveOpts:
     lin_target: float = 0.0
     newton_pcg: int = 0
     amg_reuse: int = 0
+    lin_max_it_coarse: int = 0
 
     def c(self):
         o = N.spfas_solve_opts()

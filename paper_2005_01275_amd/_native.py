@@ -52,7 +52,8 @@ class spfas_solve_opts(C.Structure):
                 ("bt_nmax", C.c_int32), ("bt_theta", C.c_double), ("dp_cap", C.c_double),
                 ("coarsest_max_steps", C.c_int32), ("lin_rtol", C.c_double), ("lin_max_it", C.c_int32),
                 ("x0_given", C.c_int32), ("lin_rtol_coarse", C.c_double), ("lin_target", C.c_double),
-                ("newton_pcg", C.c_int32), ("amg_reuse", C.c_int32)]
+                ("newton_pcg", C.c_int32), ("amg_reuse", C.c_int32),
+                ("lin_max_it_coarse", C.c_int32)]
 
 
 class spfas_stats(C.Structure):

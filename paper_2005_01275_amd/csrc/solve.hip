@@ -49,6 +49,7 @@ struct Opts {
   int coarsest_max = 10;
   double lin_rtol = 1e-8;
   int lin_max_it = 500;
+  int lin_max_it_coarse = 500;   // iteration limit of the coarse-level Krylov solves
   double lin_rtol_coarse = 0.0;  // <= 0: lin_rtol
   double lin_target = 0.0;       // inexact-Newton forcing on level 0; 0 = off
   double stop_tol = 0.0;         // outer stopping threshold of the running solve
@@ -68,6 +69,7 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
   r.coarsest_max = o.coarsest_max_steps;
   r.lin_rtol = o.lin_rtol;
   r.lin_max_it = o.lin_max_it;
+  r.lin_max_it_coarse = o.lin_max_it_coarse > 0 ? o.lin_max_it_coarse : o.lin_max_it;
   r.lin_rtol_coarse = o.lin_rtol_coarse > 0.0 ? o.lin_rtol_coarse : o.lin_rtol;
   r.lin_target = o.lin_target;
   r.newton_pcg = o.newton_pcg != 0;
@@ -112,7 +114,7 @@ static double backtrack(const std::function<double(double)>& rn_raw, double r_x,
 
 // PCG on a (non-symmetric) Newton system hands over to BiCGStab when ||r||
 // fell less than 2x over this many iterations.
-constexpr int kPcgStall = 10;
+constexpr int kPcgStall = 5;
 
 // Krylov solve of a linearised system: PCG for Picard (symmetric);
 // BiCGStab for Newton, or PCG first with BiCGStab from scratch when PCG
@@ -386,7 +388,9 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   if (C.nl > 0) {
     launch_H_assemble(C, s);
     const bool fresh = prec_refresh(C.amg, C.prec, o, s);
-    it = krylov_solve(C.kry, C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, o, s);
+    Opts oc = o;
+    oc.lin_max_it = o.lin_max_it_coarse;
+    it = krylov_solve(C.kry, C.H, &C.amg, C.xi.p, C.lam.p, o.lin_rtol_coarse, oc, s);
     prec_record(C.prec, fresh, it, C.kry.failed);
     st.lin_iters += it;
   }

@@ -133,21 +133,22 @@ def test_newton_pcg_converged_and_vcycle(kw):
 
 @pytest.mark.parametrize("kw", CASES + ["c1"])
 def test_amg_reuse_reaches_the_same_root(kw):
-    """Keeping the AMG values across linearisations (amg_reuse) only changes
-    the inner iteration: FAS-Newton and FAS-Picard still reach the oracle's
-    root x*, with and without an age limit."""
+    """Keeping the AMG values across linearisations (amg_reuse) and capping
+    the coarse-level Krylov iterations only change the inner iteration:
+    FAS-Newton and FAS-Picard still reach the oracle's root x*."""
     import paper_2005_01275_amd as pk
     print("case", kw, flush=True)
     prob = problem(kw)
     h, p_star, s_star = oracle_root(prob)
     H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
     for sm in (pk.SPFAS_NEWTON, pk.SPFAS_PICARD):
-        for reuse in (-1, 2):
+        for reuse, cap in ((-1, 0), (2, 0), (-1, 10)):
             o = opts(sm, prob)
             o.newton_pcg = 1
             o.amg_reuse = reuse
+            o.lin_max_it_coarse = cap   # 10: coarse Krylov solves stop early, the FAS cycle still converges
             p, s, st = H.fas_solve(prob, o)
-            assert st["converged"], (sm, reuse, st)
+            assert st["converged"], (sm, reuse, cap, st)
             assert np.linalg.norm(p - p_star) <= 1e-10 * np.linalg.norm(p_star), (sm, reuse)
             assert np.linalg.norm(s - s_star) <= 1e-10 * np.linalg.norm(s_star), (sm, reuse)
 
