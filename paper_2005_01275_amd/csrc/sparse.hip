@@ -123,12 +123,40 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
 // Krylov scalar slots
 enum { S_RZ0 = 0, S_RZ1, S_PQ, S_RR, S_RHO0, S_RHO1, S_RV, S_TS, S_TT, S_ALPHA, S_OMEGA, S_BB, S_NSLOT };
 
-// PCG: alpha = rz/pq; x += alpha p; r -= alpha q; parts = r.r
-__global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, const double* __restrict__ scal, int rz, double* __restrict__ x,
-                                                   double* __restrict__ r, const double* __restrict__ p,
-                                                   const double* __restrict__ q, double* __restrict__ parts) {
+// Sum of parts[0..G) computed by every block in the same fixed order (so all
+// blocks, and k_finalize, obtain the same value); valid in every thread.
+__device__ inline double all_parts(const double* __restrict__ parts, int G, double* sh, double* bc) {
+  const double v = reduce_parts(parts, G, sh);
+  if (threadIdx.x == 0) *bc = v;
+  __syncthreads();
+  return *bc;
+}
+
+// PCG with the reductions folded in: rz = sum of the r.z partials (block 0
+// stores it in slot `cur`), beta = rz / scal[old] (0 on the first
+// iteration), p = z + beta p.
+__global__ void __launch_bounds__(kBlock) k_pcg_p2(int n, const double* __restrict__ prz, int G, double* scal, int cur,
+                                                   int old, int first, const double* __restrict__ z,
+                                                   double* __restrict__ p) {
   __shared__ double sh[kBlock / 64];
-  const double pq = scal[S_PQ];
+  __shared__ double bc;
+  const double rz = all_parts(prz, G, sh, &bc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[cur] = rz;
+  const double ro = scal[old];
+  const double beta = (first || ro == 0.0) ? 0.0 : rz / ro;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+}
+
+// pq = sum of the p.q partials (block 0 stores it in S_PQ), alpha = rz / pq,
+// x += alpha p, r -= alpha q, r.r partials.
+__global__ void __launch_bounds__(kBlock) k_pcg_xr2(int n, const double* __restrict__ ppq, int G, double* scal, int rz,
+                                                    double* __restrict__ x, double* __restrict__ r,
+                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  __shared__ double bc;
+  const double pq = all_parts(ppq, G, sh, &bc);
+  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_PQ] = pq;
   const double alpha = pq != 0.0 ? scal[rz] / pq : 0.0;
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -139,14 +167,6 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr(int n, const double* __restri
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
-}
-
-// PCG: p = z + beta p with beta = rz_new / rz_old (beta = 0 on the first iteration)
-__global__ void __launch_bounds__(kBlock) k_pcg_p(int n, const double* __restrict__ scal, int rz_new, int rz_old,
-                                                  int first, const double* __restrict__ z, double* __restrict__ p) {
-  const double beta = (first || scal[rz_old] == 0.0) ? 0.0 : scal[rz_new] / scal[rz_old];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = z[i] + beta * p[i];
 }
 
 // BiCGStab: p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
@@ -1464,6 +1484,9 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   const int G = reduce_grid(n);
   const unsigned g1 = grid_for(n, kBlock);
   double* P0 = parts.p;
+  double* P1 = parts.p + kMaxParts;
+  double* P2 = parts.p + 2 * kMaxParts;
+  require(G <= kMaxParts, "reduction grid larger than the partial-sum buffers");
   hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
   hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
   hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, P0);
@@ -1502,14 +1525,13 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   for (; it < maxit; ++it) {
     if (M) M->apply(r.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
+    // partial sums: P0 r.z, P1 p.q, P2 r.r (each consumed by the next kernel)
     hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p, P0);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, cur);
-    hipLaunchKernelGGL(k_pcg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
+    hipLaunchKernelGGL(k_pcg_p2, dim3(G), dim3(kBlock), 0, st, n, P0, G, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, p.p, q.p, p.p, P0); });
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_PQ);
-    hipLaunchKernelGGL(k_pcg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, x, r.p, p.p, q.p, P0);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RR);
+          [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, p.p, q.p, p.p, P1); });
+    hipLaunchKernelGGL(k_pcg_xr2, dim3(G), dim3(kBlock), 0, st, n, P1, G, scal.p, cur, x, r.p, p.p, q.p, P2);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P2, G, scal.p, (int)S_RR);
     LAUNCHCHECK();
     std::swap(cur, old);
     HIPCHECK(hipMemcpyAsync(hlag + 2 * (it & 1), scal.p + S_PQ, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
