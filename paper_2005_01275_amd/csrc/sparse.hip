@@ -529,30 +529,33 @@ __device__ inline void cyc_row(const CycView& M, int i, int& e, int& end, int& s
   }
 }
 
-// A diag(w) in FP32, one thread per stored slot: a(src) * w[col]
+// FP16 value of an operator entry, saturated to the finite FP16 range
+__device__ inline cyc_t to_cyc(double v) { return (cyc_t)fmin(fmax(v, -65504.0), 65504.0); }
+
+// A diag(w) in FP16, one thread per stored slot: a(src) * w[col]
 __global__ void __launch_bounds__(kBlock) k_fill_aw(int ne, const int* __restrict__ col, const int* __restrict__ src,
-                                                    CsrView A, const double* __restrict__ w, float* __restrict__ val) {
+                                                    CsrView A, const double* __restrict__ w, cyc_t* __restrict__ val) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int c = src[e];
   double v = 0.0;
   if (c >= 0) v = ((c & 1) ? A.val[c >> 1] : A.diag[c >> 1]) * w[col[e]];
-  val[e] = (float)v;
+  val[e] = to_cyc(v);
 }
 
-// P - diag(w) A P in FP32 on the pattern of A P (which contains that of P):
+// P - diag(w) A P in FP16 on the pattern of A P (which contains that of P):
 // SELL thread per row, CSR lane group per row.
-__device__ inline float cm_value(int q, const int* __restrict__ appidx, const double* __restrict__ pval,
+__device__ inline cyc_t cm_value(int q, const int* __restrict__ appidx, const double* __restrict__ pval,
                                  const double* __restrict__ apv, double wi) {
-  if (q < 0) return 0.0f;
+  if (q < 0) return (cyc_t)0.0;
   const int pi = appidx[q];
-  return (float)((pi >= 0 ? pval[pi] : 0.0) - wi * apv[q]);
+  return to_cyc((pi >= 0 ? pval[pi] : 0.0) - wi * apv[q]);
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_cm(CycView M, const int* __restrict__ src,
                                                     const int* __restrict__ appidx, const double* __restrict__ pval,
                                                     const double* __restrict__ apv, const double* __restrict__ w,
-                                                    float* __restrict__ val) {
+                                                    cyc_t* __restrict__ val) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M.n) return;
   int e, end, step;
@@ -564,7 +567,7 @@ __global__ void __launch_bounds__(kBlock) k_fill_cm(CycView M, const int* __rest
 __global__ void __launch_bounds__(kBlock) k_fill_cmv(CycView M, const int* __restrict__ src,
                                                      const int* __restrict__ appidx, const double* __restrict__ pval,
                                                      const double* __restrict__ apv, const double* __restrict__ w,
-                                                     float* __restrict__ val) {
+                                                     cyc_t* __restrict__ val) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = t / kVecG, g = t % kVecG;
   if (i >= M.n) return;
@@ -572,12 +575,12 @@ __global__ void __launch_bounds__(kBlock) k_fill_cmv(CycView M, const int* __res
   for (int e = M.ptr[i] + g; e < M.ptr[i + 1]; e += kVecG) val[e] = cm_value(src[e], appidx, pval, apv, wi);
 }
 
-// R = P^T in FP32 (filled once at setup), one thread per stored slot
+// R = P^T in FP16 (filled once at setup), one thread per stored slot
 __global__ void __launch_bounds__(kBlock) k_fill_rm(int ne, const int* __restrict__ src,
-                                                    const double* __restrict__ pval, float* __restrict__ val) {
+                                                    const double* __restrict__ pval, cyc_t* __restrict__ val) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
-  val[e] = src[e] >= 0 ? (float)pval[src[e]] : 0.0f;
+  val[e] = src[e] >= 0 ? to_cyc(pval[src[e]]) : (cyc_t)0.0;
 }
 
 // The three kernels of a classical V(1,1) level, on SELL-64 (thread per row):
@@ -1277,7 +1280,7 @@ void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
     KernelProf* pf = k == 0 ? hook.prof : nullptr;
     timed(lvprof.get(), 3 * k, 0.0, s, [&] {
       const double n = (double)F.n;
-      timed(pf, hook.down_id, 8.0 * (double)F.aw.nnz + 16.0 * n, s, [&] {
+      timed(pf, hook.down_id, 6.0 * (double)F.aw.nnz + 16.0 * n, s, [&] {
         if (!F.aw.sell)
           hipLaunchKernelGGL(k_cycv<0>, dim3(grid_for((size_t)F.n * kVecG, kBlock)), dim3(kBlock), 0, s,
                              cyc_view(F.aw), bl, bl, nullptr, nullptr, F.r.p);
@@ -1288,7 +1291,7 @@ void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
           hipLaunchKernelGGL((k_cyc<0, false>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.aw), bl,
                              bl, nullptr, nullptr, F.r.p);
       });
-      timed(pf, hook.restrict_id, 8.0 * (double)F.rm.nnz + 8.0 * n + 8.0 * C.n, s, [&] {
+      timed(pf, hook.restrict_id, 6.0 * (double)F.rm.nnz + 8.0 * n + 8.0 * C.n, s, [&] {
         if (!F.rm.sell)
           hipLaunchKernelGGL(k_cycv<1>, dim3(grid_for((size_t)C.n * kVecG, kBlock)), dim3(kBlock), 0, s,
                              cyc_view(F.rm), F.r.p, nullptr, nullptr, nullptr, C.b.p);
@@ -1315,7 +1318,7 @@ void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
     const double* bf = (k == 0) ? b : F.b.p;
     KernelProf* pf = k == 0 ? hook.prof : nullptr;
     timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
-      timed(pf, hook.up_id, 8.0 * (double)F.cm.nnz + 32.0 * F.n + 8.0 * C.n, s, [&] {
+      timed(pf, hook.up_id, 6.0 * (double)F.cm.nnz + 32.0 * F.n + 8.0 * C.n, s, [&] {
         if (!F.cm.sell)
           hipLaunchKernelGGL(k_cycv<2>, dim3(grid_for((size_t)F.n * kVecG, kBlock)), dim3(kBlock), 0, s,
                              cyc_view(F.cm), C.x.p, bf, F.r.p, F.invd.p, xf);

@@ -71,14 +71,19 @@ struct Sell64View {
   const double* val = nullptr;
 };
 
-// A sparse operator of the classical cycle with FP32 values: SELL-64
+// Values of the classical cycle operators: FP16 (the operators A diag(w),
+// P^T and P - diag(w) A P are scaled to O(1) entries; products and vectors
+// stay FP64).
+using cyc_t = _Float16;
+
+// A sparse operator of the classical cycle with FP16 values: SELL-64
 // (thread per row, `sell`) for large row counts, else CSR read by a lane
 // group per row.  Padding slots of SELL have col = row and src = -1.
 struct CycMat {
   int n = 0;
   bool sell = false;
   DVec<int> ptr, col;                 // SELL: slice offsets [ceil(n/64)+1]; CSR: row pointers [n+1]
-  DVec<float> val;
+  DVec<cyc_t> val;
   DVec<int> src;                      // per stored slot: source entry of the value, -1 = padding
   long long nnz = 0;                  // stored entries without padding
 };
@@ -87,7 +92,7 @@ struct CycView {
   int n;
   const int* ptr;
   const int* col;
-  const float* val;
+  const cyc_t* val;
 };
 
 struct AmgLevel {
