@@ -301,7 +301,8 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * Kernel timing with HIP events recorded on the stream of the solve calls.
  * Each instrumented launch is bracketed by two events; `algo_bytes` is the
  * algorithmic HBM traffic of the launches (the minimum the method moves:
- * per flux unknown F and cell N of level 0, residual 40F + 24N, Newton
+ * per flux unknown F, cell N and cell-face incidence I of level 0,
+ * residual 40F + 20N + 4I, at a trial point x + s dx 48F + 28N + 4I, Newton
  * linearisation 56F + 24N; with E = stored nonzeros of S including the
  * diagonal: S x with its dot products 12E + 24N (FP64 value + int32
  * column per entry); on the finest level of the classical AMG (FP16 value

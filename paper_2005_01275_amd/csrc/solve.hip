@@ -225,7 +225,10 @@ void setup_fine_solver(Hierarchy& h) {
 
 static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double step) {
   int G = 0;
-  const double bytes = 40.0 * h.fine.nf + 24.0 * h.fine.n;
+  // distinct data read: per face K, L, 1/T_K, 1/T_L, g, sigma (+ d sigma);
+  // per cell p (+ dp), f, the list offset; 4 bytes per cell-face incidence
+  const double F = (double)h.fine.nf, N = (double)h.fine.n, I = (double)h.fine.cfcode.n;
+  const double bytes = dx ? 48.0 * F + 28.0 * N + 4.0 * I : 40.0 * F + 20.0 * N + 4.0 * I;
   h.prof.run(SPFAS_PROF_FINE_RESID, bytes, h.stream,
              [&] { G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.parts.p, h.stream); });
   return std::sqrt(h.host_sum(h.parts.p, G));   // may be non-finite inside Alg. 1 trials
