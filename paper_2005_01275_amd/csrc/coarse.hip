@@ -483,50 +483,53 @@ void launch_H_assemble(CoarseLevel& C, hipStream_t s) {
 }
 
 // [dsigma_c; dp_c] = z_c - A_c^{-1} [C_c^T lambda; 0]; each flux takes the
-// value of its first owner.
-__global__ void __launch_bounds__(kBlock) k_coarse_backsub(CView v, const int* __restrict__ zptr,
-                                                           const int* __restrict__ invptr, const double* __restrict__ inv,
-                                                           const double* __restrict__ z, int nl,
-                                                           const double* __restrict__ lam, double* __restrict__ dx,
-                                                           double* __restrict__ parts) {
-  __shared__ double sh[kBlock / 64];
+// value of its first owner.  One wave per cell, a lane per local row; the
+// per-block maximum of |Pi~ dp_c| over the block's cells goes to parts.
+constexpr int kBacksubBlock = 1024;
+
+__global__ void __launch_bounds__(kBacksubBlock) k_coarse_backsub(CView v, const int* __restrict__ zptr,
+                                                                  const int* __restrict__ invptr,
+                                                                  const double* __restrict__ inv,
+                                                                  const double* __restrict__ z, int nl,
+                                                                  const double* __restrict__ lam,
+                                                                  double* __restrict__ dx, double* __restrict__ parts) {
+  __shared__ double sh[kBacksubBlock / 64];
+  const int lane = threadIdx.x & 63;
+  const int c = blockIdx.x * (kBacksubBlock / 64) + (threadIdx.x >> 6);
   double mx = 0.0;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c < v.n) {
     const int k = v.lfptr[c + 1] - v.lfptr[c];
     const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
     const int nc = k + m;
     const int* lf = v.lfidx + v.lfptr[c];
-    const double* Ai = inv + invptr[c];
-    const double* zc = z + zptr[c];
-    double pb = 0.0;
-    for (int i = 0; i < nc; ++i) {
-      double s = zc[i];
+    double pbv = 0.0;
+    if (lane < nc) {
+      const double* Ai = inv + invptr[c] + lane * nc;
+      double s = z[zptr[c] + lane];
       for (int j = 0; j < k; ++j) {
         const int fj = lf[j];
-        if (fj < nl) {
-          const double sg = (v.fcell[2 * fj] == c) ? 1.0 : -1.0;
-          s -= Ai[i * nc + j] * sg * lam[fj];
-        }
+        if (fj < nl) s -= Ai[j] * ((v.fcell[2 * fj] == c) ? lam[fj] : -lam[fj]);
       }
-      if (i < k) {
-        if (v.fcell[2 * lf[i]] == c) dx[lf[i]] = s;
+      if (lane < k) {
+        if (v.fcell[2 * lf[lane]] == c) dx[lf[lane]] = s;
       } else {
-        dx[v.nf + p0 + (i - k)] = s;
-        pb += v.w[p0 + (i - k)] * s;
+        dx[v.nf + p0 + (lane - k)] = s;
+        pbv = v.w[p0 + (lane - k)] * s;
       }
     }
-    mx = fabs(pb);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pbv += __shfl_xor(pbv, o, 64);
+    mx = fabs(pbv);
   }
   mx = block_max(mx, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = mx;
 }
 
 int launch_coarse_backsub(CoarseLevel& C, const double* lam, double* dx, double* parts, hipStream_t s) {
-  const unsigned G = grid_for(C.n, kBlock);
+  const unsigned G = grid_for(C.n, kBacksubBlock / 64);
   require(G <= (unsigned)kMaxParts * 4, "too many coarse cells for one reduction");
-  hipLaunchKernelGGL(k_coarse_backsub, dim3(G), dim3(kBlock), 0, s, cview(C), C.zptr.p, C.invptr.p, C.inv.p, C.z.p,
-                     C.nl, lam, dx, parts);
+  hipLaunchKernelGGL(k_coarse_backsub, dim3(G), dim3(kBacksubBlock), 0, s, cview(C), C.zptr.p, C.invptr.p, C.inv.p,
+                     C.z.p, C.nl, lam, dx, parts);
   LAUNCHCHECK();
   return (int)G;
 }
