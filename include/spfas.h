@@ -303,7 +303,7 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * algorithmic HBM traffic of the launches (the minimum the method moves:
  * per flux unknown F, cell N and cell-face incidence I of level 0,
  * residual 40F + 20N + 4I, at a trial point x + s dx 48F + 28N + 4I, Newton
- * linearisation 56F + 24N; with E = stored nonzeros of S including the
+ * linearisation 40F + 36N + 12I; with E = stored nonzeros of S including the
  * diagonal: S x with its dot products 12E + 24N (FP64 value + int32
  * column per entry); on the finest level of the classical AMG (FP16 value
  * + int32 column per stored entry, N_c coarse points, E_w = E, E_R =

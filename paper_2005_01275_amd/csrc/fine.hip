@@ -127,57 +127,99 @@ int launch_fine_resid(const FineView& v, const double* x, const double* dx, doub
 
 // ------------------------------------------------------------------ linearisation
 
-// Per cell c: the row of S = D M^{-1} E (Picard: E = D^T; Newton:
+// The row of S = D M^{-1} E of every cell (Picard: E = D^T; Newton:
 // E = N(sigma) kinv'(p) + D^T, Prop. 3 on level 0) and the right-hand side
-// rhs = r_p - D M^{-1} r_sigma of the eliminated system S dp = rhs.
+// rhs = r_p - D M^{-1} r_sigma of the eliminated system S dp = rhs, in two
+// passes.  Face pass (one thread per face j, coalesced): with m_j the
+// diagonal of M, E_K and E_L the entries of E on the face's cells and r_j its
+// flux residual, store u_K = E_K / m_j, u_L = E_L / m_j and
+// v = sigma_j - r_j / m_j.  Cell pass (one thread per cell): each face
+// contributes with the orientation d = -1 (cell K) or +1 (cell L):
+// diag += d u_own, off = d u_other, rhs += d v (summed in a fixed order).
 template <bool NEWTON>
-__global__ void __launch_bounds__(kBlock) k_fine_linearize(FineView v, const double* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_fine_lin_faces(FineView v, const double* __restrict__ x,
+                                                           double* __restrict__ uk, double* __restrict__ ul,
+                                                           double* __restrict__ vs) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= v.nf) return;
+  const double* sig = x;
+  const double* p = x + v.nf;
+  const double a_ = v.alpha;
+  const int K = v.K[j], L = v.L[j];
+  const double pK = p[K];
+  const double eK = exp(-a_ * pK) * v.TKi[j];
+  double eL = 0.0, pL = 0.0;
+  if (L >= 0) {
+    pL = p[L];
+    eL = exp(-a_ * pL) * v.TLi[j];
+  }
+  const double m = eK + eL;
+  const double sj = sig[j];
+  const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
+  double EK = -1.0, EL = 1.0;
+  if (NEWTON) {
+    EK -= a_ * eK * sj;
+    EL -= a_ * eL * sj;
+  }
+  const double ainv = 1.0 / m;
+  uk[j] = ainv * EK;
+  ul[j] = ainv * EL;
+  vs[j] = sj - ainv * rs;
+}
+
+// Cell pass: a group of kLinG lanes per cell, one incidence per lane
+// (coalesced writes of the off-diagonal values), group sums for the
+// diagonal and the right-hand side.
+constexpr int kLinG = 8;
+
+__global__ void __launch_bounds__(kBlock) k_fine_linearize(FineView v, const double* __restrict__ uk,
+                                                           const double* __restrict__ ul, const double* __restrict__ vs,
                                                            double* __restrict__ diag, double* __restrict__ off,
                                                            double* __restrict__ rhs) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= v.n) return;
-  const int64_t nf = v.nf;
-  const double* sig = x;
-  const double* p = x + nf;
-  const double a_ = v.alpha;
-  double dg = 0.0, rh = v.f[c];
-  for (int k = v.cfptr[c]; k < v.cfptr[c + 1]; ++k) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / kLinG;
+  const int g = (int)(t % kLinG);
+  if (c >= v.n) return;   // the whole group leaves together
+  double dg = 0.0, rh = 0.0;
+  for (int k = v.cfptr[c] + g; k < v.cfptr[c + 1]; k += kLinG) {
     const int code = v.cfcode[k];
     const int j = code >> 1;
-    const bool isL = code & 1;
-    const int K = v.K[j], L = v.L[j];
-    const double pK = p[K];
-    const double eK = exp(-a_ * pK) * v.TKi[j];
-    double eL = 0.0, pL = 0.0;
-    if (L >= 0) {
-      pL = p[L];
-      eL = exp(-a_ * pL) * v.TLi[j];
+    if (code & 1) {
+      dg += ul[j];
+      off[k] = uk[j];
+      rh += vs[j];
+    } else {
+      dg -= uk[j];
+      off[k] = v.L[j] >= 0 ? -ul[j] : 0.0;
+      rh -= vs[j];
     }
-    const double m = eK + eL;
-    const double sj = sig[j];
-    const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
-    double EK = -1.0, EL = 1.0;
-    if (NEWTON) {
-      EK -= a_ * eK * sj;
-      EL -= a_ * eL * sj;
-    }
-    const double ainv = 1.0 / m;
-    const double d = isL ? 1.0 : -1.0;
-    dg += d * ainv * (isL ? EL : EK);
-    off[k] = (L >= 0) ? d * ainv * (isL ? EK : EL) : 0.0;
-    rh += d * sj - d * ainv * rs;
   }
-  diag[c] = dg;
-  rhs[c] = rh;
+#pragma unroll
+  for (int o = kLinG / 2; o > 0; o >>= 1) {
+    dg += __shfl_xor(dg, o, kLinG);
+    rh += __shfl_xor(rh, o, kLinG);
+  }
+  if (g == 0) {
+    diag[c] = dg;
+    rhs[c] = v.f[c] + rh;
+  }
 }
 
 void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
-                           double* rhs, hipStream_t s) {
+                           double* rhs, double* work, hipStream_t s) {
   if (v.n == 0) return;
-  if (newton)
-    hipLaunchKernelGGL(k_fine_linearize<true>, dim3(grid_for(v.n, kBlock)), dim3(kBlock), 0, s, v, x, diag, off, rhs);
-  else
-    hipLaunchKernelGGL(k_fine_linearize<false>, dim3(grid_for(v.n, kBlock)), dim3(kBlock), 0, s, v, x, diag, off, rhs);
+  double* uk = work;
+  double* ul = work + v.nf;
+  double* vs = work + 2 * v.nf;
+  if (v.nf > 0) {
+    if (newton)
+      hipLaunchKernelGGL(k_fine_lin_faces<true>, dim3(grid_for(v.nf, kBlock)), dim3(kBlock), 0, s, v, x, uk, ul, vs);
+    else
+      hipLaunchKernelGGL(k_fine_lin_faces<false>, dim3(grid_for(v.nf, kBlock)), dim3(kBlock), 0, s, v, x, uk, ul, vs);
+    LAUNCHCHECK();
+  }
+  hipLaunchKernelGGL(k_fine_linearize, dim3(grid_for((size_t)v.n * kLinG, kBlock)), dim3(kBlock), 0, s, v, uk, ul, vs,
+                     diag, off, rhs);
   LAUNCHCHECK();
 }
 

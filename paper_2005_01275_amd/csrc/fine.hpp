@@ -24,8 +24,9 @@ void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, co
 // returns the number of partial sums written
 int launch_fine_resid(const FineView& v, const double* x, const double* dx, double s, double* r,
                       double* parts, hipStream_t st);
+// work: 3 nf doubles of per-face coefficients
 void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
-                           double* rhs, hipStream_t s);
+                           double* rhs, double* work, hipStream_t s);
 int launch_fine_backsub(const FineView& v, bool newton, const double* x, double* dx, double* parts,
                         hipStream_t s);
 void launch_fine_problem(const FineView& v, const int* cell_in, const int* flux_in, const double* vol,

@@ -192,6 +192,7 @@ void setup_fine_solver(Hierarchy& h) {
   w.Sdiag.alloc(n);
   w.Soff.alloc(f.cfcode.n);
   w.rhs.alloc(n);
+  w.lin.alloc(std::max<int64_t>(3 * nf, 1));
   w.S.n = (int)n;
   w.S.diag = w.Sdiag.p;
   w.S.ptr = f.cfptr.p;
@@ -201,7 +202,7 @@ void setup_fine_solver(Hierarchy& h) {
   w.x.zero(s);
   const double a = f.alpha;
   f.alpha = 0.0;
-  launch_fine_linearize(f.view(), false, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
+  launch_fine_linearize(f.view(), false, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, w.lin.p, s);
   f.alpha = a;
   HIPCHECK(hipStreamSynchronize(s));
   w.amg.setup(w.S, s, true, kDenseLds, true);
@@ -243,8 +244,10 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   hipStream_t s = h.stream;
   const int64_t n = f.n, nf = f.nf;
   const double t0 = trace_on() ? trace_clock(s) : 0.0;
-  h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 56.0 * nf + 24.0 * n, s,
-             [&] { launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, s); });
+  // inputs K, L, 1/T_K, 1/T_L, g, sigma per face, p and f per cell, the cell-face
+  // codes; outputs the values of S (diagonal + one per incidence) and rhs
+  h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 40.0 * nf + 36.0 * n + 12.0 * (double)f.cfcode.n, s,
+             [&] { launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, w.lin.p, s); });
   const bool fresh = prec_refresh(w.amg, w.prec, o, s);
   double* dp = w.dx.p + nf;
   int it;
