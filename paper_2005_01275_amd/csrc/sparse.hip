@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(const double* __restrict__ 
 }
 
 // Krylov scalar slots
-enum { S_RZ0 = 0, S_RZ1, S_PQ, S_RR, S_RHO0, S_RHO1, S_RV, S_TS, S_TT, S_ALPHA, S_OMEGA, S_BB, S_NSLOT };
+enum { S_RZ0 = 0, S_RZ1, S_PQ, S_RR, S_BB, S_RHO0, S_RHO1, S_RV, S_TS, S_TT, S_ALPHA, S_OMEGA, S_NSLOT };
 
 // Sum of parts[0..G) computed by every block in the same fixed order (so all
 // blocks, and k_finalize, obtain the same value); valid in every thread.
@@ -1470,7 +1470,7 @@ void Krylov::alloc(int n_) {
   parts.alloc(kMaxParts * 3);
   scal.alloc(S_NSLOT);
   if (!hscal) HIPCHECK(hipHostMalloc((void**)&hscal, S_NSLOT * sizeof(double), hipHostMallocDefault));
-  if (!hlag) HIPCHECK(hipHostMalloc((void**)&hlag, 4 * sizeof(double), hipHostMallocDefault));
+  if (!hlag) HIPCHECK(hipHostMalloc((void**)&hlag, 6 * sizeof(double), hipHostMallocDefault));
   for (hipEvent_t& e : ev)
     if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -1495,14 +1495,14 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, P0);
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
   LAUNCHCHECK();
-  const double bb = read_slot(hscal, scal.p, S_BB, st);
-  failed = !std::isfinite(bb);
-  converged = bb == 0.0;
-  if (!(bb > 0.0) || failed) return 0;
-  const double tol2 = rtol * rtol * bb;
+  // b.b reaches the host with the scalars of iteration 0 (no wait of its own)
+  failed = false;
+  converged = false;
+  double tol2 = 0.0;
+  bool have_bb = false;
   int it = 0;
   int cur = S_RZ0, old = S_RZ1;
-  static_assert(S_RR == S_PQ + 1, "p.Ap and r.r are read together");
+  static_assert(S_RR == S_PQ + 1 && S_BB == S_RR + 1, "p.Ap, r.r and b.b are read together");
   // While the residual is far above the tolerance, the residual of
   // iteration k is checked while iteration k + 1 is already queued, so the
   // device never waits for the host; within a factor 10 of the tolerance
@@ -1510,8 +1510,15 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   // at the first iteration that meets it (or one later, if it jumps there).
   auto lagged = [&](int k, double& pq, double& rr) {
     HIPCHECK(hipEventSynchronize(ev[k & 1]));
-    pq = hlag[2 * (k & 1)];
-    rr = hlag[2 * (k & 1) + 1];
+    pq = hlag[3 * (k & 1)];
+    rr = hlag[3 * (k & 1) + 1];
+    if (!have_bb) {
+      have_bb = true;
+      const double bb = hlag[3 * (k & 1) + 2];
+      tol2 = rtol * rtol * bb;
+      return !std::isfinite(bb) ? 2 : (bb == 0.0 ? 1 : 0);   // 2: non-finite b, 1: b = 0
+    }
+    return 0;
   };
   auto bad = [&](double pq, double rr) { return !std::isfinite(rr) || !(pq > 0.0); };
   // stall > 0: give up (neither converged nor failed) once r.r of an
@@ -1537,7 +1544,7 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P2, G, scal.p, (int)S_RR);
     LAUNCHCHECK();
     std::swap(cur, old);
-    HIPCHECK(hipMemcpyAsync(hlag + 2 * (it & 1), scal.p + S_PQ, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(hlag + 3 * (it & 1), scal.p + S_PQ, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipEventRecord(ev[it & 1], st));
     double pq, rr;
     if (!near && it > 0) {
@@ -1548,7 +1555,9 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
       near = rr <= 100.0 * tol2;
     }
     if (near || it == 0) {
-      lagged(it, pq, rr);
+      const int zb = lagged(it, pq, rr);   // it == 0 always comes here first
+      if (zb == 2) { failed = true; it = 0; break; }
+      if (zb == 1) { converged = true; it = 0; break; }   // b = 0: x = 0 (alpha was 0)
       if (bad(pq, rr)) { failed = true; ++it; break; }
       if (rr <= tol2) { converged = true; ++it; break; }
       if (stalled(it, rr)) { stop = true; ++it; break; }
