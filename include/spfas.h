@@ -302,7 +302,8 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * Each instrumented launch is bracketed by two events; `algo_bytes` is the
  * algorithmic HBM traffic of the launches (the minimum the method moves:
  * per flux unknown F, cell N and cell-face incidence I of level 0,
- * residual 40F + 20N + 4I, at a trial point x + s dx 48F + 28N + 4I, Newton
+ * residual 40F + 20N + 4I, at a trial point x + s dx 48F + 28N + 4I (also for
+ * the multi-step pass, which reads the same data once), Newton
  * linearisation 40F + 36N + 12I; with E = stored nonzeros of S including the
  * diagonal: S x with its dot products 12E + 24N (FP64 value + int32
  * column per entry); on the finest level of the classical AMG (FP16 value
@@ -318,7 +319,8 @@ typedef enum {
   SPFAS_PROF_FINE_AMG_RESTRICT = 4,  /* finest AMG level: restriction               */
   SPFAS_PROF_FINE_AMG_UP = 5,        /* finest AMG level: prolongation + smoothing  */
   SPFAS_PROF_FINE_SPMV2 = 6,         /* S x (+ two dots), second product of BiCGStab */
-  SPFAS_PROF_COUNT = 7
+  SPFAS_PROF_FINE_RESID_TRIALS = 7,  /* fine residual norms at up to 4 step lengths in one pass (Alg. 1 halvings) */
+  SPFAS_PROF_COUNT = 8
 } spfas_prof_kernel;
 
 /* Turns the timing on (nonzero) or off and clears the counters. */

@@ -20,12 +20,12 @@ EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solv
             "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
             "spfas_version", "spfas_profile_enable", "spfas_profile_read"]
 (SPFAS_PROF_FINE_RESID, SPFAS_PROF_FINE_LINEARIZE, SPFAS_PROF_FINE_SPMV, SPFAS_PROF_FINE_AMG_DOWN,
- SPFAS_PROF_FINE_AMG_RESTRICT, SPFAS_PROF_FINE_AMG_UP, SPFAS_PROF_FINE_SPMV2) = range(7)
+ SPFAS_PROF_FINE_AMG_RESTRICT, SPFAS_PROF_FINE_AMG_UP, SPFAS_PROF_FINE_SPMV2, SPFAS_PROF_FINE_RESID_TRIALS) = range(8)
 # names match the kernels as a profiler reports them (classical finest AMG level)
 PROF_NAMES = {SPFAS_PROF_FINE_RESID: "k_fine_resid", SPFAS_PROF_FINE_LINEARIZE: "k_fine_linearize",
               SPFAS_PROF_FINE_SPMV: "k_spmv_dot<true>", SPFAS_PROF_FINE_SPMV2: "k_spmv_dot2<true>",
               SPFAS_PROF_FINE_AMG_DOWN: "k_cyc<0, true>", SPFAS_PROF_FINE_AMG_RESTRICT: "k_cyc<1, true>",
-              SPFAS_PROF_FINE_AMG_UP: "k_cyc<2, true>"}
+              SPFAS_PROF_FINE_AMG_UP: "k_cyc<2, true>", SPFAS_PROF_FINE_RESID_TRIALS: "k_fine_resid_trials"}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

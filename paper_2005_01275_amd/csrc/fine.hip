@@ -67,8 +67,24 @@ void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, co
 
 // r(x + s dx) = A(x + s dx) - b with b = -[g; f] (eqs. fine_level_residual,
 // FV_matrix); items [0, nf) are faces (flux rows), [nf, nf+n) cells
-// (mass-balance rows).  Writes r if `r` is non-null and the per-block sum of
-// squares to parts[blockIdx.x].
+// (mass-balance rows).  The row values come from the two routines below,
+// shared by the single-step and the multi-step kernels so that a trial step
+// gives the same bits in both.
+__device__ inline double flux_row(const FineView& v, int64_t i, double pK, double pL, double sj) {
+  double m = exp(-v.alpha * pK) * v.TKi[i];
+  double dtp = -pK;
+  if (v.L[i] >= 0) {
+    m += exp(-v.alpha * pL) * v.TLi[i];
+    dtp += pL;
+  }
+  return m * sj + dtp + v.g[i];
+}
+
+// x + s dx component: explicit fma, the same in every kernel
+__device__ inline double stepped(double a, double s, double d) { return fma(s, d, a); }
+
+// Writes r if `r` is non-null and the per-block sum of squares to
+// parts[blockIdx.x].
 template <bool STEP>
 __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double* __restrict__ x,
                                                        const double* __restrict__ dx, double s,
@@ -84,17 +100,13 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double*
     double ri;
     if (i < nf) {
       const int K = v.K[i], L = v.L[i];
-      double pK = p[K], sj = sig[i];
-      if (STEP) { pK += s * dp[K]; sj += s * dsig[i]; }
-      double m = exp(-v.alpha * pK) * v.TKi[i];
-      double dtp = -pK;
-      if (L >= 0) {
-        double pL = p[L];
-        if (STEP) pL += s * dp[L];
-        m += exp(-v.alpha * pL) * v.TLi[i];
-        dtp += pL;
+      double pK = p[K], pL = L >= 0 ? p[L] : 0.0, sj = sig[i];
+      if (STEP) {
+        pK = stepped(pK, s, dp[K]);
+        if (L >= 0) pL = stepped(pL, s, dp[L]);
+        sj = stepped(sj, s, dsig[i]);
       }
-      ri = m * sj + dtp + v.g[i];
+      ri = flux_row(v, i, pK, pL, sj);
     } else {
       const int64_t c = i - nf;
       double div = 0.0;
@@ -102,7 +114,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double*
         const int code = v.cfcode[k];
         const int j = code >> 1;
         double sj = sig[j];
-        if (STEP) sj += s * dsig[j];
+        if (STEP) sj = stepped(sj, s, dsig[j]);
         div += (code & 1) ? sj : -sj;
       }
       ri = div + v.f[c];
@@ -112,6 +124,82 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double*
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
+}
+
+// The same sums of squares at NT step lengths in one pass over the data
+// (the remaining trials of Alg. 1): parts[t * gridDim.x + block].
+struct TrialSteps {
+  double s[kMaxTrials];
+};
+
+template <int NT>
+__global__ void __launch_bounds__(kBlock) k_fine_resid_trials(FineView v, const double* __restrict__ x,
+                                                              const double* __restrict__ dx, TrialSteps st,
+                                                              double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  const int64_t nf = v.nf, ntot = v.nf + v.n;
+  const double* sig = x;
+  const double* p = x + nf;
+  const double* dsig = dx;
+  const double* dp = dx + nf;
+  double acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < nf) {
+      const int K = v.K[i], L = v.L[i];
+      const double pK0 = p[K], dK = dp[K], sj0 = sig[i], ds = dsig[i];
+      const double pL0 = L >= 0 ? p[L] : 0.0, dL = L >= 0 ? dp[L] : 0.0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double pL = L >= 0 ? stepped(pL0, st.s[t], dL) : 0.0;
+        const double ri = flux_row(v, i, stepped(pK0, st.s[t], dK), pL, stepped(sj0, st.s[t], ds));
+        acc[t] += ri * ri;
+      }
+    } else {
+      const int64_t c = i - nf;
+      double div[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) div[t] = 0.0;
+      for (int k = v.cfptr[c]; k < v.cfptr[c + 1]; ++k) {
+        const int code = v.cfcode[k];
+        const int j = code >> 1;
+        const double s0 = sig[j], d0 = dsig[j];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          const double sj = stepped(s0, st.s[t], d0);
+          div[t] += (code & 1) ? sj : -sj;
+        }
+      }
+      const double fc = v.f[c];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const double ri = div[t] + fc;
+        acc[t] += ri * ri;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double a = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) parts[(int64_t)t * gridDim.x + blockIdx.x] = a;
+  }
+}
+
+int launch_fine_resid_trials(const FineView& v, const double* x, const double* dx, const double* steps, int nt,
+                             double* parts, hipStream_t st) {
+  require(nt >= 1 && nt <= kMaxTrials, "number of trial steps out of range");
+  const int G = reduce_grid(v.nf + v.n);
+  TrialSteps ts{};
+  for (int t = 0; t < nt; ++t) ts.s[t] = steps[t];
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_fine_resid_trials<1>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+    case 2: hipLaunchKernelGGL(k_fine_resid_trials<2>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+    case 3: hipLaunchKernelGGL(k_fine_resid_trials<3>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+    default: hipLaunchKernelGGL(k_fine_resid_trials<4>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+  }
+  LAUNCHCHECK();
+  return G;
 }
 
 int launch_fine_resid(const FineView& v, const double* x, const double* dx, double s, double* r, double* parts,

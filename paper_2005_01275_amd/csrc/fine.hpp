@@ -21,9 +21,15 @@ struct FineView {
 void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, const double* nrm,
                       const double* pt, const double* cen, const double* k0, double* TK, double* TL,
                       int* bad, hipStream_t s);
+// Step lengths one multi-step residual launch evaluates.
+constexpr int kMaxTrials = 4;
 // returns the number of partial sums written
 int launch_fine_resid(const FineView& v, const double* x, const double* dx, double s, double* r,
                       double* parts, hipStream_t st);
+// sums of squares of r(x + s_t dx) for t < nt (nt <= kMaxTrials) in one pass;
+// partials of trial t at parts[t G, (t+1) G); returns G
+int launch_fine_resid_trials(const FineView& v, const double* x, const double* dx, const double* steps, int nt,
+                             double* parts, hipStream_t st);
 // work: 3 nf doubles of per-face coefficients
 void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
                            double* rhs, double* work, hipStream_t s);

@@ -37,6 +37,17 @@ double Hierarchy::host_sum(const double* dparts, int n) {
   return s;
 }
 
+void Hierarchy::host_sums(const double* dparts, int n, int k, double* out) {
+  require((size_t)n * k <= (size_t)kMaxParts * 4, "too many partial sums");
+  HIPCHECK(hipMemcpyAsync(hpin, dparts, (size_t)n * k * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCHECK(hipStreamSynchronize(stream));
+  for (int t = 0; t < k; ++t) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += hpin[(size_t)t * n + i];
+    out[t] = s;
+  }
+}
+
 double Hierarchy::host_max(const double* dparts, int n) {
   HIPCHECK(hipMemcpyAsync(hpin, dparts, n * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHECK(hipStreamSynchronize(stream));

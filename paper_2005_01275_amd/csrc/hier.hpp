@@ -80,6 +80,8 @@ struct Hierarchy {
   // sum of partials on the host (deterministic order)
   double host_sum(const double* dparts, int n);
   double host_max(const double* dparts, int n);
+  // k sums of n consecutive partials each (one copy, one wait)
+  void host_sums(const double* dparts, int n, int k, double* out);
 };
 
 }  // namespace spfas

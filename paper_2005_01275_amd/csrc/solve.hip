@@ -87,17 +87,28 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
 // counts as +infinity, so it is never preferred to a finite one; when the
 // trial finally chosen is still non-finite the step is rejected (0 returned,
 // residual unchanged).
+// `rn_batch`, when given, evaluates several step lengths in one pass: after a
+// rejected full step it supplies the norms at 1/2, 1/4, ... (the same values
+// the single evaluations would give), so the halvings need no further waits.
+using NormBatch = std::function<void(const double*, int, double*)>;
 static double backtrack(const std::function<double(double)>& rn_raw, double r_x, int nmax, double theta,
-                        double& r_new, int& halvings) {
-  auto rn = [&](double s) {
-    const double v = rn_raw(s);
-    return std::isfinite(v) ? v : HUGE_VAL;
-  };
+                        double& r_new, int& halvings, const NormBatch& rn_batch = nullptr) {
+  auto fin = [](double v) { return std::isfinite(v) ? v : HUGE_VAL; };
+  auto rn = [&](double s) { return fin(rn_raw(s)); };
   double s = 1.0;
   int n = 0;
   double r_s = rn(s);
+  std::vector<double> pre;   // norms at 1/2, 1/4, ... from one batched evaluation
+  if (rn_batch && r_s > r_x && nmax > 0) {
+    const int k = std::min(nmax, kMaxTrials);
+    std::vector<double> sl(k);
+    double t = 1.0;
+    for (int i = 0; i < k; ++i) sl[i] = (t *= 0.5);
+    pre.resize(k);
+    rn_batch(sl.data(), k, pre.data());
+  }
   while (r_s > r_x && n < nmax) {
-    const double r_half = rn(0.5 * s);
+    const double r_half = n < (int)pre.size() ? fin(pre[n]) : rn(0.5 * s);
     if (r_half > theta * r_s) break;
     s *= 0.5;
     ++n;
@@ -224,6 +235,19 @@ void setup_fine_solver(Hierarchy& h) {
   }
 }
 
+// ||r(x + s_t dx)|| for t < k in one pass (Alg. 1 halvings): the same values
+// as fine_rnorm at each step
+static void fine_rnorm_trials(Hierarchy& h, const double* x, const double* dx, const double* steps, int k,
+                              double* out) {
+  int G = 0;
+  const double F = (double)h.fine.nf, N = (double)h.fine.n, I = (double)h.fine.cfcode.n;
+  h.prof.run(SPFAS_PROF_FINE_RESID_TRIALS, 48.0 * F + 28.0 * N + 4.0 * I, h.stream, [&] {
+    G = launch_fine_resid_trials(h.fine.view(), x, dx, steps, k, h.parts.p, h.stream);
+  });
+  h.host_sums(h.parts.p, G, k, out);
+  for (int t = 0; t < k; ++t) out[t] = std::sqrt(out[t]);
+}
+
 static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double step) {
   int G = 0;
   // distinct data read: per face K, L, 1/T_K, 1/T_L, g, sigma (+ d sigma);
@@ -270,8 +294,13 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   }
   const double scale = (o.cap > 0.0 && mx > o.cap) ? o.cap / mx : 1.0;
   double r_new = r_x;
+  const NormBatch batch = [&](const double* sl, int k, double* out) {
+    double st_[kMaxTrials];
+    for (int t = 0; t < k; ++t) st_[t] = sl[t] * scale;
+    fine_rnorm_trials(h, w.x.p, w.dx.p, st_, k, out);
+  };
   const double step = backtrack([&](double sl) { return fine_rnorm(h, w.x.p, w.dx.p, sl * scale); }, r_x,
-                                o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
+                                o.bt_nmax, o.bt_theta, r_new, st.bt_halvings, batch);
   if (step > 0.0) launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
   st.smoothing_steps++;
   if (trace_on())
@@ -490,7 +519,9 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
   auto rn = [&](double sl) {
     return l == 0 ? fine_rnorm(h, x, dx, sl) : coarse_rnorm(h, l, x, dx, sl);
   };
-  const double step = backtrack(rn, r_s, o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
+  NormBatch batch = nullptr;
+  if (l == 0) batch = [&](const double* sl, int k, double* out) { fine_rnorm_trials(h, x, dx, sl, k, out); };
+  const double step = backtrack(rn, r_s, o.bt_nmax, o.bt_theta, r_new, st.bt_halvings, batch);
   if (step > 0.0) launch_axpy(nl, step, dx, x, s);
   (void)nfl;
   // post-smoothing
