@@ -33,59 +33,121 @@ static CView cview(const CoarseLevel& C) {
   return v;
 }
 
+// One residual row (coarse flux `it` < nf, or the m_c pressure rows of cell
+// it - nf) at NT step lengths: acc[t] += the squares of its entries of
+// r(x + s_t dx).  Shared by the single-step and the multi-step kernels, with
+// every multiply-add written as an explicit fma, so a step gives the same
+// bits in both whatever the compiler would contract.
+template <bool STEP, int NT>
+__device__ inline void coarse_row(const CView& v, double alpha, int it, const double* __restrict__ sig,
+                                  const double* __restrict__ p, const double* __restrict__ dsig,
+                                  const double* __restrict__ dp, const double* steps,
+                                  const double* __restrict__ b, double* __restrict__ r, double* acc) {
+  auto stp = [&](const double* a, const double* d, int i, int t) { return STEP ? fma(steps[t], d[i], a[i]) : a[i]; };
+  if (it < v.nf) {
+    const int j = it;
+    double val[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) val[t] = 0.0;
+    for (int slot = 0; slot < 2; ++slot) {
+      const int c = v.fcell[2 * j + slot];
+      if (c < 0) continue;
+      const int li = v.floc[2 * j + slot];
+      const int k = v.lfptr[c + 1] - v.lfptr[c];
+      const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+      const double* Mr = v.M + v.mptr[c] + li * k;
+      const int* lf = v.lfidx + v.lfptr[c];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        double pbar = 0.0;
+        for (int q = 0; q < m; ++q) pbar = fma(v.w[p0 + q], stp(p, dp, p0 + q, t), pbar);
+        const double sc = exp(-alpha * pbar);
+        double ms = 0.0;
+        for (int i = 0; i < k; ++i) ms = fma(Mr[i], stp(sig, dsig, lf[i], t), ms);
+        double dtp = 0.0;
+        for (int q = 0; q < m; ++q) dtp = fma(v.D[v.dptr[c] + q * k + li], stp(p, dp, p0 + q, t), dtp);
+        val[t] = val[t] + fma(sc, ms, dtp);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double ri = val[t] - b[j];
+      if (r) r[j] = ri;
+      acc[t] = fma(ri, ri, acc[t]);
+    }
+  } else {
+    const int c = it - v.nf;
+    const int k = v.lfptr[c + 1] - v.lfptr[c];
+    const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
+    const int* lf = v.lfidx + v.lfptr[c];
+    for (int q = 0; q < m; ++q) {
+      const double* Dr = v.D + v.dptr[c] + q * k;
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        double a = 0.0;
+        for (int i = 0; i < k; ++i) a = fma(Dr[i], stp(sig, dsig, lf[i], t), a);
+        const double ri = a - b[v.nf + p0 + q];
+        if (r) r[v.nf + p0 + q] = ri;
+        acc[t] = fma(ri, ri, acc[t]);
+      }
+    }
+  }
+}
+
 template <bool STEP>
 __global__ void __launch_bounds__(kBlock) k_coarse_resid(CView v, double alpha, const double* __restrict__ x,
                                                          const double* __restrict__ dx, double step,
                                                          const double* __restrict__ b, double* __restrict__ r,
                                                          double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
-  const double* sig = x;
-  const double* p = x + v.nf;
-  const double* dsig = dx;
-  const double* dp = dx + v.nf;
-  double acc2 = 0.0;
+  double acc[1] = {0.0};
   const int ntot = v.nf + v.n;
-  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x) {
-    if (it < v.nf) {
-      const int j = it;
-      double acc = 0.0;
-      for (int slot = 0; slot < 2; ++slot) {
-        const int c = v.fcell[2 * j + slot];
-        if (c < 0) continue;
-        const int li = v.floc[2 * j + slot];
-        const int k = v.lfptr[c + 1] - v.lfptr[c];
-        const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
-        double pbar = 0.0;
-        for (int q = 0; q < m; ++q) pbar += v.w[p0 + q] * (STEP ? p[p0 + q] + step * dp[p0 + q] : p[p0 + q]);
-        const double sc = exp(-alpha * pbar);
-        const double* Mr = v.M + v.mptr[c] + li * k;
-        const int* lf = v.lfidx + v.lfptr[c];
-        double ms = 0.0;
-        for (int i = 0; i < k; ++i) ms += Mr[i] * (STEP ? sig[lf[i]] + step * dsig[lf[i]] : sig[lf[i]]);
-        double dtp = 0.0;
-        for (int q = 0; q < m; ++q) dtp += v.D[v.dptr[c] + q * k + li] * (STEP ? p[p0 + q] + step * dp[p0 + q] : p[p0 + q]);
-        acc += sc * ms + dtp;
-      }
-      const double ri = acc - b[j];
-      if (r) r[j] = ri;
-      acc2 += ri * ri;
-    } else {
-      const int c = it - v.nf;
-      const int k = v.lfptr[c + 1] - v.lfptr[c];
-      const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
-      const int* lf = v.lfidx + v.lfptr[c];
-      for (int q = 0; q < m; ++q) {
-        const double* Dr = v.D + v.dptr[c] + q * k;
-        double acc = 0.0;
-        for (int i = 0; i < k; ++i) acc += Dr[i] * (STEP ? sig[lf[i]] + step * dsig[lf[i]] : sig[lf[i]]);
-        const double ri = acc - b[v.nf + p0 + q];
-        if (r) r[v.nf + p0 + q] = ri;
-        acc2 += ri * ri;
-      }
-    }
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x)
+    coarse_row<STEP, 1>(v, alpha, it, x, x + v.nf, dx, STEP ? dx + v.nf : nullptr, &step, b, r, acc);
+  const double a = block_sum(acc[0], sh);
+  if (threadIdx.x == 0) parts[blockIdx.x] = a;
+}
+
+struct CoarseSteps {
+  double s[kMaxTrials];
+};
+
+// Sums of squares of r(x + s_t dx) for NT step lengths in one pass:
+// parts[t * gridDim.x + block].
+template <int NT>
+__global__ void __launch_bounds__(kBlock) k_coarse_resid_trials(CView v, double alpha, const double* __restrict__ x,
+                                                                const double* __restrict__ dx, CoarseSteps st,
+                                                                const double* __restrict__ b,
+                                                                double* __restrict__ parts) {
+  __shared__ double sh[kBlock / 64];
+  double acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = 0.0;
+  const int ntot = v.nf + v.n;
+  for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x)
+    coarse_row<true, NT>(v, alpha, it, x, x + v.nf, dx, dx + v.nf, st.s, b, nullptr, acc);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const double a = block_sum(acc[t], sh);
+    if (threadIdx.x == 0) parts[t * gridDim.x + blockIdx.x] = a;
   }
-  acc2 = block_sum(acc2, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = acc2;
+}
+
+int launch_coarse_resid_trials(const CoarseLevel& C, double alpha, const double* x, const double* dx,
+                               const double* steps, int nt, const double* b, double* parts, hipStream_t s) {
+  require(nt >= 1 && nt <= kMaxTrials, "number of trial steps out of range");
+  const int G = reduce_grid(C.nf + C.n);
+  CView v = cview(C);
+  CoarseSteps cs{};
+  for (int t = 0; t < nt; ++t) cs.s[t] = steps[t];
+  switch (nt) {
+    case 1: hipLaunchKernelGGL(k_coarse_resid_trials<1>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
+    case 2: hipLaunchKernelGGL(k_coarse_resid_trials<2>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
+    case 3: hipLaunchKernelGGL(k_coarse_resid_trials<3>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
+    default: hipLaunchKernelGGL(k_coarse_resid_trials<4>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
+  }
+  LAUNCHCHECK();
+  return G;
 }
 
 int launch_coarse_resid(const CoarseLevel& C, double alpha, const double* x, const double* dx, double step,

@@ -11,6 +11,10 @@ struct Hierarchy;
 // number of partial sums of r.r written to parts.
 int launch_coarse_resid(const CoarseLevel& C, double alpha, const double* x, const double* dx, double step,
                         const double* b, double* r, double* parts, hipStream_t s);
+// sums of squares of r(x + s_t dx) for t < nt (nt <= kMaxTrials) in one pass;
+// partials of trial t at parts[t G, (t+1) G); returns G
+int launch_coarse_resid_trials(const CoarseLevel& C, double alpha, const double* x, const double* dx,
+                               const double* steps, int nt, const double* b, double* parts, hipStream_t s);
 // local saddle blocks [s_c M_c, E_c; D_c, 0], their inverses and the local
 // solutions z_c = A_c^{-1} [-r_hat_c; -r_p,c] (algebraic hybridisation)
 void launch_coarse_local(CoarseLevel& C, double alpha, bool newton, const double* x, const double* r,

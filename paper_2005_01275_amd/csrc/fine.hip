@@ -68,16 +68,16 @@ void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, co
 // r(x + s dx) = A(x + s dx) - b with b = -[g; f] (eqs. fine_level_residual,
 // FV_matrix); items [0, nf) are faces (flux rows), [nf, nf+n) cells
 // (mass-balance rows).  The row values come from the two routines below,
-// shared by the single-step and the multi-step kernels so that a trial step
-// gives the same bits in both.
+// shared by the single-step and the multi-step kernels (multiply-adds as
+// explicit fma) so that a trial step gives the same bits in both.
 __device__ inline double flux_row(const FineView& v, int64_t i, double pK, double pL, double sj) {
   double m = exp(-v.alpha * pK) * v.TKi[i];
   double dtp = -pK;
   if (v.L[i] >= 0) {
-    m += exp(-v.alpha * pL) * v.TLi[i];
+    m = fma(exp(-v.alpha * pL), v.TLi[i], m);
     dtp += pL;
   }
-  return m * sj + dtp + v.g[i];
+  return fma(m, sj, dtp) + v.g[i];
 }
 
 // x + s dx component: explicit fma, the same in every kernel
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double*
       ri = div + v.f[c];
     }
     if (r) r[i] = ri;
-    acc += ri * ri;
+    acc = fma(ri, ri, acc);
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
@@ -154,7 +154,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid_trials(FineView v, const 
       for (int t = 0; t < NT; ++t) {
         const double pL = L >= 0 ? stepped(pL0, st.s[t], dL) : 0.0;
         const double ri = flux_row(v, i, stepped(pK0, st.s[t], dK), pL, stepped(sj0, st.s[t], ds));
-        acc[t] += ri * ri;
+        acc[t] = fma(ri, ri, acc[t]);
       }
     } else {
       const int64_t c = i - nf;
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid_trials(FineView v, const 
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const double ri = div[t] + fc;
-        acc[t] += ri * ri;
+        acc[t] = fma(ri, ri, acc[t]);
       }
     }
   }

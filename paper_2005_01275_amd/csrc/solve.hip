@@ -409,6 +409,16 @@ static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* d
   return std::sqrt(h.host_sum(h.parts.p, G));   // may be non-finite inside Alg. 1 trials
 }
 
+// ||r(x + s_t dx)|| on coarse level l for t < k in one pass (same values as
+// coarse_rnorm at each step)
+static void coarse_rnorm_trials(Hierarchy& h, int l, const double* x, const double* dx, const double* steps, int k,
+                                double* out) {
+  CoarseLevel& C = *h.coarse[l - 1];
+  const int G = launch_coarse_resid_trials(C, h.fine.alpha, x, dx, steps, k, C.b.p, h.parts.p, h.stream);
+  h.host_sums(h.parts.p, G, k, out);
+  for (int t = 0; t < k; ++t) out[t] = std::sqrt(out[t]);
+}
+
 // One Picard or Newton step on coarse level l (Section 3.3) with the linear
 // system solved by algebraic hybridisation (Section 3.4), the cap on the
 // aggregate-average pressure change and Alg. 1.
@@ -442,8 +452,13 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   }
   const double scale = (o.cap > 0.0 && mx > o.cap) ? o.cap / mx : 1.0;
   double r_new = r_x;
+  const NormBatch batch = [&](const double* sl, int k, double* out) {
+    double st_[kMaxTrials];
+    for (int t = 0; t < k; ++t) st_[t] = sl[t] * scale;
+    coarse_rnorm_trials(h, l, C.x.p, C.dx.p, st_, k, out);
+  };
   const double step = backtrack([&](double sl) { return coarse_rnorm(h, l, C.x.p, C.dx.p, sl * scale); }, r_x,
-                                o.bt_nmax, o.bt_theta, r_new, st.bt_halvings);
+                                o.bt_nmax, o.bt_theta, r_new, st.bt_halvings, batch);
   if (step > 0.0) launch_axpy(C.nf + C.np, step * scale, C.dx.p, C.x.p, s);
   st.smoothing_steps++;
   if (trace_on())
@@ -519,8 +534,9 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
   auto rn = [&](double sl) {
     return l == 0 ? fine_rnorm(h, x, dx, sl) : coarse_rnorm(h, l, x, dx, sl);
   };
-  NormBatch batch = nullptr;
+  NormBatch batch;
   if (l == 0) batch = [&](const double* sl, int k, double* out) { fine_rnorm_trials(h, x, dx, sl, k, out); };
+  else batch = [&](const double* sl, int k, double* out) { coarse_rnorm_trials(h, l, x, dx, sl, k, out); };
   const double step = backtrack(rn, r_s, o.bt_nmax, o.bt_theta, r_new, st.bt_halvings, batch);
   if (step > 0.0) launch_axpy(nl, step, dx, x, s);
   (void)nfl;
