@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(kBacksubBlock) k_coarse_backsub(CView v, const
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) pbv += __shfl_xor(pbv, o, 64);
-    mx = fabs(pbv);
+    mx = pbv == pbv ? fabs(pbv) : HUGE_VAL;   // a NaN counts as non-finite (fmax would drop it)
   }
   mx = block_max(mx, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = mx;

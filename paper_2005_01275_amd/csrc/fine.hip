@@ -343,7 +343,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const doubl
       }
       dx[i] = -(rs + EK * dp[K] + (L >= 0 ? EL * dpL : 0.0)) / m;
     } else {
-      mx = fmax(mx, fabs(dp[i - nf]));
+      const double d = fabs(dp[i - nf]);
+      mx = d == d ? fmax(mx, d) : HUGE_VAL;   // a NaN counts as non-finite (fmax would drop it)
     }
   }
   mx = block_max(mx, sh);

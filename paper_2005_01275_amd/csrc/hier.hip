@@ -29,30 +29,30 @@ Hierarchy::~Hierarchy() {
   if (hpin) (void)hipHostFree(hpin);
 }
 
-double Hierarchy::host_sum(const double* dparts, int n) {
-  HIPCHECK(hipMemcpyAsync(hpin, dparts, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+double Hierarchy::host_sum(int n) {
   HIPCHECK(hipStreamSynchronize(stream));
+  const volatile double* v = hpin;
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s += hpin[i];
+  for (int i = 0; i < n; ++i) s += v[i];
   return s;
 }
 
-void Hierarchy::host_sums(const double* dparts, int n, int k, double* out) {
+void Hierarchy::host_sums(int n, int k, double* out) {
   require((size_t)n * k <= (size_t)kMaxParts * 4, "too many partial sums");
-  HIPCHECK(hipMemcpyAsync(hpin, dparts, (size_t)n * k * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCHECK(hipStreamSynchronize(stream));
+  const volatile double* v = hpin;
   for (int t = 0; t < k; ++t) {
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += hpin[(size_t)t * n + i];
+    for (int i = 0; i < n; ++i) s += v[(size_t)t * n + i];
     out[t] = s;
   }
 }
 
-double Hierarchy::host_max(const double* dparts, int n) {
-  HIPCHECK(hipMemcpyAsync(hpin, dparts, n * sizeof(double), hipMemcpyDeviceToHost, stream));
+double Hierarchy::host_max(int n) {
   HIPCHECK(hipStreamSynchronize(stream));
+  const volatile double* v = hpin;
   double s = 0.0;
-  for (int i = 0; i < n; ++i) s = std::max(s, hpin[i]);
+  for (int i = 0; i < n; ++i) s = std::max(s, (double)v[i]);
   return s;
 }
 
@@ -140,7 +140,8 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
                  1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() -
                      t_start);
   if (host_only) return;
-  HIPCHECK(hipHostMalloc((void**)&hpin, kMaxParts * sizeof(double) * 4, hipHostMallocDefault));
+  HIPCHECK(hipHostMalloc((void**)&hpin, kMaxParts * sizeof(double) * 4, hipHostMallocMapped | hipHostMallocCoherent));
+  HIPCHECK(hipHostGetDevicePointer((void**)&dpin, hpin, 0));
   parts.alloc(kMaxParts * 4);
   // ---------------- level-0 device order
   const int64_t n = M.n_cells, nf = t0.n_flux;

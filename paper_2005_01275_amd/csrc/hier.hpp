@@ -66,9 +66,12 @@ struct Hierarchy {
   std::vector<std::unique_ptr<TransferDev>> trans;    // transfers 0..L-2
   // host copies of hierarchy numbers for the parity hooks
   std::vector<std::vector<double>> eigvals;           // per transfer, concatenated
-  // reduction scratch
+  // reduction scratch: partials that stay on the device, and partials the
+  // host adds up, which the kernels write straight into coherent host-mapped
+  // memory (hpin on the host, dpin its device address: no copy launch)
   DVec<double> parts;
-  double* hpin = nullptr;                  // pinned host scalars
+  double* hpin = nullptr;
+  double* dpin = nullptr;
   int launches = 0;
   KernelProf prof;                         // event timing of instrumented kernels
 
@@ -77,11 +80,12 @@ struct Hierarchy {
   void set_problem(const spfas_problem& prob);
   // fine residual in input order
   void eval_residual(const double* p, const double* sig, double* rp, double* rs, bool dev);
-  // sum of partials on the host (deterministic order)
-  double host_sum(const double* dparts, int n);
-  double host_max(const double* dparts, int n);
-  // k sums of n consecutive partials each (one copy, one wait)
-  void host_sums(const double* dparts, int n, int k, double* out);
+  // wait for the stream, then the sum (max) of the n partials at dpin, in
+  // index order
+  double host_sum(int n);
+  double host_max(int n);
+  // k sums of n consecutive partials each (one wait)
+  void host_sums(int n, int k, double* out);
 };
 
 }  // namespace spfas

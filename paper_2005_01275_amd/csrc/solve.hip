@@ -242,9 +242,9 @@ static void fine_rnorm_trials(Hierarchy& h, const double* x, const double* dx, c
   int G = 0;
   const double F = (double)h.fine.nf, N = (double)h.fine.n, I = (double)h.fine.cfcode.n;
   h.prof.run(SPFAS_PROF_FINE_RESID_TRIALS, 48.0 * F + 28.0 * N + 4.0 * I, h.stream, [&] {
-    G = launch_fine_resid_trials(h.fine.view(), x, dx, steps, k, h.parts.p, h.stream);
+    G = launch_fine_resid_trials(h.fine.view(), x, dx, steps, k, h.dpin, h.stream);
   });
-  h.host_sums(h.parts.p, G, k, out);
+  h.host_sums(G, k, out);
   for (int t = 0; t < k; ++t) out[t] = std::sqrt(out[t]);
 }
 
@@ -255,8 +255,8 @@ static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double
   const double F = (double)h.fine.nf, N = (double)h.fine.n, I = (double)h.fine.cfcode.n;
   const double bytes = dx ? 48.0 * F + 28.0 * N + 4.0 * I : 40.0 * F + 20.0 * N + 4.0 * I;
   h.prof.run(SPFAS_PROF_FINE_RESID, bytes, h.stream,
-             [&] { G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.parts.p, h.stream); });
-  return std::sqrt(h.host_sum(h.parts.p, G));   // may be non-finite inside Alg. 1 trials
+             [&] { G = launch_fine_resid(h.fine.view(), x, dx, step, nullptr, h.dpin, h.stream); });
+  return std::sqrt(h.host_sum(G));   // may be non-finite inside Alg. 1 trials
 }
 
 // One Picard or Newton step on level 0 (Section 3.3): solve the linearised
@@ -283,8 +283,8 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   st.lin_iters += it;
   double mx = HUGE_VAL;
   if (!w.kry.failed) {
-    const int G = launch_fine_backsub(f.view(), o.newton, w.x.p, w.dx.p, h.parts.p, s);
-    mx = h.host_max(h.parts.p, G);
+    const int G = launch_fine_backsub(f.view(), o.newton, w.x.p, w.dx.p, h.dpin, s);
+    mx = h.host_max(G);
   }
   if (!std::isfinite(mx)) {   // non-finite linearisation or linear solve: the step is rejected
     st.rejected_steps++;
@@ -405,8 +405,8 @@ static void launch_sub(int64_t n, const double* a, const double* b, double* out,
 
 static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* dx, double step) {
   CoarseLevel& C = *h.coarse[l - 1];
-  const int G = launch_coarse_resid(C, h.fine.alpha, x, dx, step, C.b.p, nullptr, h.parts.p, h.stream);
-  return std::sqrt(h.host_sum(h.parts.p, G));   // may be non-finite inside Alg. 1 trials
+  const int G = launch_coarse_resid(C, h.fine.alpha, x, dx, step, C.b.p, nullptr, h.dpin, h.stream);
+  return std::sqrt(h.host_sum(G));   // may be non-finite inside Alg. 1 trials
 }
 
 // ||r(x + s_t dx)|| on coarse level l for t < k in one pass (same values as
@@ -414,8 +414,8 @@ static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* d
 static void coarse_rnorm_trials(Hierarchy& h, int l, const double* x, const double* dx, const double* steps, int k,
                                 double* out) {
   CoarseLevel& C = *h.coarse[l - 1];
-  const int G = launch_coarse_resid_trials(C, h.fine.alpha, x, dx, steps, k, C.b.p, h.parts.p, h.stream);
-  h.host_sums(h.parts.p, G, k, out);
+  const int G = launch_coarse_resid_trials(C, h.fine.alpha, x, dx, steps, k, C.b.p, h.dpin, h.stream);
+  h.host_sums(G, k, out);
   for (int t = 0; t < k; ++t) out[t] = std::sqrt(out[t]);
 }
 
@@ -441,8 +441,8 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   }
   double mx = HUGE_VAL;
   if (!(C.nl > 0 && C.kry.failed)) {
-    const int G = launch_coarse_backsub(C, C.lam.p, C.dx.p, h.parts.p, s);
-    mx = h.host_max(h.parts.p, G);
+    const int G = launch_coarse_backsub(C, C.lam.p, C.dx.p, h.dpin, s);
+    mx = h.host_max(G);
   }
   if (!std::isfinite(mx)) {   // non-finite local or hybridised solve: the step is rejected
     st.rejected_steps++;

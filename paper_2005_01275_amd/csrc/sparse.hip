@@ -147,16 +147,19 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p2(int n, const double* __restri
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
 }
 
-// pq = sum of the p.q partials (block 0 stores it in S_PQ), alpha = rz / pq,
-// x += alpha p, r -= alpha q, r.r partials.
+// pq = sum of the p.q partials (block 0 stores it in S_PQ and in *hpq),
+// alpha = rz / pq, x += alpha p, r -= alpha q, r.r partials.
 __global__ void __launch_bounds__(kBlock) k_pcg_xr2(int n, const double* __restrict__ ppq, int G, double* scal, int rz,
                                                     double* __restrict__ x, double* __restrict__ r,
                                                     const double* __restrict__ p, const double* __restrict__ q,
-                                                    double* __restrict__ parts) {
+                                                    double* __restrict__ parts, double* __restrict__ hpq) {
   __shared__ double sh[kBlock / 64];
   __shared__ double bc;
   const double pq = all_parts(ppq, G, sh, &bc);
-  if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_PQ] = pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    scal[S_PQ] = pq;
+    *hpq = pq;
+  }
   const double alpha = pq != 0.0 ? scal[rz] / pq : 0.0;
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
@@ -1455,6 +1458,9 @@ static void spmv_dot2(const CsrView& A, const Sell64View* A64, bool fin, int G, 
   LAUNCHCHECK();
 }
 
+// doubles of Krylov::hlag
+constexpr int kLagDoubles = 2 + 3 * kMaxParts;
+
 Krylov::~Krylov() {
   if (hscal) (void)hipHostFree(hscal);
   if (hlag) (void)hipHostFree(hlag);
@@ -1470,7 +1476,10 @@ void Krylov::alloc(int n_) {
   parts.alloc(kMaxParts * 3);
   scal.alloc(S_NSLOT);
   if (!hscal) HIPCHECK(hipHostMalloc((void**)&hscal, S_NSLOT * sizeof(double), hipHostMallocDefault));
-  if (!hlag) HIPCHECK(hipHostMalloc((void**)&hlag, 6 * sizeof(double), hipHostMallocDefault));
+  if (!hlag) {   // coherent host-mapped: the kernels write what the host checks there directly
+    HIPCHECK(hipHostMalloc((void**)&hlag, kLagDoubles * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+    HIPCHECK(hipHostGetDevicePointer((void**)&dlag, hlag, 0));
+  }
   for (hipEvent_t& e : ev)
     if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
@@ -1488,12 +1497,15 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   const unsigned g1 = grid_for(n, kBlock);
   double* P0 = parts.p;
   double* P1 = parts.p + kMaxParts;
-  double* P2 = parts.p + 2 * kMaxParts;
   require(G <= kMaxParts, "reduction grid larger than the partial-sum buffers");
+  // host-mapped: [p.q of the last two iterations | b.b partials | r.r
+  // partials of the last two iterations], written by the kernels
+  const volatile double* hl = hlag;
+  double* d_bb = dlag + 2;
+  double* d_rr = dlag + 2 + kMaxParts;
   hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
   hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
-  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, P0);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_BB);
+  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, d_bb);
   LAUNCHCHECK();
   // b.b reaches the host with the scalars of iteration 0 (no wait of its own)
   failed = false;
@@ -1508,13 +1520,18 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   // device never waits for the host; within a factor 10 of the tolerance
   // each iteration is checked as soon as it completes, so the solve stops
   // at the first iteration that meets it (or one later, if it jumps there).
+  auto host_total = [&](const volatile double* v) {   // partials in block order
+    double t = 0.0;
+    for (int i = 0; i < G; ++i) t += v[i];
+    return t;
+  };
   auto lagged = [&](int k, double& pq, double& rr) {
     HIPCHECK(hipEventSynchronize(ev[k & 1]));
-    pq = hlag[3 * (k & 1)];
-    rr = hlag[3 * (k & 1) + 1];
+    pq = hl[k & 1];
+    rr = host_total(hl + 2 + kMaxParts * (1 + (k & 1)));
     if (!have_bb) {
       have_bb = true;
-      const double bb = hlag[3 * (k & 1) + 2];
+      const double bb = host_total(hl + 2);
       tol2 = rtol * rtol * bb;
       return !std::isfinite(bb) ? 2 : (bb == 0.0 ? 1 : 0);   // 2: non-finite b, 1: b = 0
     }
@@ -1535,16 +1552,16 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   for (; it < maxit; ++it) {
     if (M) M->apply(r.p, z.p, st);
     else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
-    // partial sums: P0 r.z, P1 p.q, P2 r.r (each consumed by the next kernel)
+    // partial sums: P0 r.z, P1 p.q (each consumed by the next kernel), r.r
+    // (host-mapped, for the host's check)
     hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p, P0);
     hipLaunchKernelGGL(k_pcg_p2, dim3(G), dim3(kBlock), 0, st, n, P0, G, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
           [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, p.p, q.p, p.p, P1); });
-    hipLaunchKernelGGL(k_pcg_xr2, dim3(G), dim3(kBlock), 0, st, n, P1, G, scal.p, cur, x, r.p, p.p, q.p, P2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P2, G, scal.p, (int)S_RR);
+    hipLaunchKernelGGL(k_pcg_xr2, dim3(G), dim3(kBlock), 0, st, n, P1, G, scal.p, cur, x, r.p, p.p, q.p,
+                       d_rr + kMaxParts * (it & 1), dlag + (it & 1));
     LAUNCHCHECK();
     std::swap(cur, old);
-    HIPCHECK(hipMemcpyAsync(hlag + 3 * (it & 1), scal.p + S_PQ, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipEventRecord(ev[it & 1], st));
     double pq, rr;
     if (!near && it > 0) {

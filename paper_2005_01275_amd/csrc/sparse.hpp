@@ -183,7 +183,10 @@ struct Krylov {
   DVec<double> r, z, p, q, rh, v, s, t, y, w;
   DVec<double> parts, scal;
   double* hscal = nullptr;
-  double* hlag = nullptr;             // pinned: p.Ap and r.r of the last two PCG iterations
+  // host-mapped PCG checks: p.Ap of the last two iterations, the b.b
+  // partials, the r.r partials of the last two iterations
+  double* hlag = nullptr;
+  double* dlag = nullptr;             // device address of hlag
   hipEvent_t ev[2] = {nullptr, nullptr};
   int iters = 0;
   bool failed = false;                // last solve met a non-finite value or a PCG breakdown (x returned as 0)
