@@ -194,16 +194,18 @@ __global__ void __launch_bounds__(kBlock) k_bicg_s(int n, double* __restrict__ s
 }
 
 // scal[slot0] = sum parts0, scal[slot1] = sum parts1 (fixed order); with
-// omega != 0 also scal[S_OMEGA] = TS / TT from the two new values.
+// omega != 0 also scal[S_OMEGA] = TS / TT from the two new values; the first
+// value also to *hout (host-mapped) if hout is non-null.
 __global__ void __launch_bounds__(kBlock) k_finalize2(const double* __restrict__ parts0,
                                                       const double* __restrict__ parts1, int G, double* scal,
-                                                      int slot0, int slot1, int omega) {
+                                                      int slot0, int slot1, int omega, double* hout) {
   __shared__ double sh[kBlock / 64];
   const double v0 = reduce_parts(parts0, G, sh);
   const double v1 = reduce_parts(parts1, G, sh);
   if (threadIdx.x == 0) {
     scal[slot0] = v0;
     scal[slot1] = v1;
+    if (hout) *hout = v0;
     if (omega) scal[S_OMEGA] = v1 > 0.0 ? v0 / v1 : 0.0;
   }
 }
@@ -1462,32 +1464,24 @@ static void spmv_dot2(const CsrView& A, const Sell64View* A64, bool fin, int G, 
 constexpr int kLagDoubles = 2 + 3 * kMaxParts;
 
 Krylov::~Krylov() {
-  if (hscal) (void)hipHostFree(hscal);
   if (hlag) (void)hipHostFree(hlag);
   for (hipEvent_t& e : ev)
     if (e) (void)hipEventDestroy(e);
 }
 
 void Krylov::alloc(int n_) {
-  if (n == n_ && hscal) return;
+  if (n == n_ && hlag) return;
   n = n_;
   r.alloc(n); z.alloc(n); p.alloc(n); q.alloc(n); rh.alloc(n); v.alloc(n); s.alloc(n); t.alloc(n); y.alloc(n);
   w.alloc(n);
   parts.alloc(kMaxParts * 3);
   scal.alloc(S_NSLOT);
-  if (!hscal) HIPCHECK(hipHostMalloc((void**)&hscal, S_NSLOT * sizeof(double), hipHostMallocDefault));
   if (!hlag) {   // coherent host-mapped: the kernels write what the host checks there directly
     HIPCHECK(hipHostMalloc((void**)&hlag, kLagDoubles * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
     HIPCHECK(hipHostGetDevicePointer((void**)&dlag, hlag, 0));
   }
   for (hipEvent_t& e : ev)
     if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-}
-
-static double read_slot(double* hscal, const double* scal, int slot, hipStream_t st, int count = 1) {
-  HIPCHECK(hipMemcpyAsync(hscal + slot, scal + slot, count * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHECK(hipStreamSynchronize(st));
-  return hscal[slot];
 }
 
 int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st,
@@ -1602,11 +1596,14 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   double* P0 = parts.p;
   double* P1 = parts.p + kMaxParts;
   int cur = S_RHO0, old = S_RHO1;
+  // the host's checks: b.b, then r.r of each iteration (host-mapped)
+  const volatile double* hl = hlag;
   // x = 0, r = rh = b; ||b||^2 is also rho_0 = rh.r
   hipLaunchKernelGGL(k_bicg_init, dim3(G), dim3(kBlock), 0, st, n, b, x, r.p, rh.p, P0);
-  hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P0, G, scal.p, (int)S_BB, cur, 0);
+  hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P0, G, scal.p, (int)S_BB, cur, 0, dlag);
   LAUNCHCHECK();
-  const double bb = read_slot(hscal, scal.p, S_BB, st);
+  HIPCHECK(hipStreamSynchronize(st));
+  const double bb = hl[0];
   failed = !std::isfinite(bb);
   converged = bb == 0.0;
   if (!(bb > 0.0) || failed) return 0;
@@ -1627,13 +1624,15 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     timed(hook.prof, hook.spmv2_id, hook.spmv_bytes, st,
           [&] { spmv_dot2(A, sell64, hook.prof != nullptr, G, st, z.p, t.p, s.p, P0, P1); });
     // TS, TT and omega = TS / TT in one launch
-    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_TS, (int)S_TT, 1);
+    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_TS, (int)S_TT, 1,
+                       nullptr);
     hipLaunchKernelGGL(k_bicg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, rh.p, P0, P1);
     // ||r||^2 and the next rho = rh.r (into the slot of the previous rho)
-    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_RR, old, 0);
+    hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_RR, old, 0, dlag);
     LAUNCHCHECK();
     std::swap(cur, old);
-    const double rr = read_slot(hscal, scal.p, S_RR, st);
+    HIPCHECK(hipStreamSynchronize(st));
+    const double rr = hl[0];
     if (!std::isfinite(rr)) {   // breakdown or non-finite operator: report, leave x = 0
       failed = true;
       hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);

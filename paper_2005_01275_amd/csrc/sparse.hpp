@@ -182,9 +182,9 @@ struct Krylov {
   const Sell64View* sell64 = nullptr;  // when set (same matrix as A), products read it instead of A
   DVec<double> r, z, p, q, rh, v, s, t, y, w;
   DVec<double> parts, scal;
-  double* hscal = nullptr;
-  // host-mapped PCG checks: p.Ap of the last two iterations, the b.b
-  // partials, the r.r partials of the last two iterations
+  // host-mapped values the host checks, written by the kernels: for PCG
+  // p.Ap of the last two iterations, the b.b partials, the r.r partials of
+  // the last two iterations; for BiCGStab b.b, then r.r, in the first slot
   double* hlag = nullptr;
   double* dlag = nullptr;             // device address of hlag
   hipEvent_t ev[2] = {nullptr, nullptr};
