@@ -907,13 +907,13 @@ void build_sell(const HostCsr& H, AmgLevel& F, hipStream_t s) {
 }
 
 // Cycle operator from CSR rows (col, src per entry): SELL-64 for at least
-// kVecRows rows, else CSR.  Padding slots read column `pad_col` of their
+// kSellRows rows, else CSR.  Padding slots read column `pad_col` of their
 // row (its first column, or 0 for an empty row) with value 0.
 void build_cyc(int n, const std::vector<int>& ptr, const std::vector<int>& col, const std::vector<int>& src,
                CycMat& M, hipStream_t s) {
   M.n = n;
   M.nnz = ptr[n];
-  M.sell = n >= kVecRows;
+  M.sell = n >= kSellRows;
   if (!M.sell) {
     M.ptr.upload(ptr, s);
     M.col.upload(col, s);

@@ -38,8 +38,14 @@ namespace spfas {
 constexpr int kDenseLds = 88;
 // Strength of connection of the aggregation: |a_ij| >= kStrength max_k |a_ik|.
 constexpr double kStrength = 0.1;
-// Levels with fewer rows than this run the group-per-row cycle kernels.
+// Aggregation-AMG levels with fewer rows than this run the group-per-row
+// cycle kernels.
 constexpr int kVecRows = 150000;
+// Classical-AMG cycle operators with at least this many rows are stored as
+// SELL-64 (one thread per row), smaller ones as CSR with a lane group per row.
+// On the 60x220x85 hierarchy the 207,000-row level pads SELL-64 to about
+// twice its entries and runs faster as CSR.
+constexpr int kSellRows = 250000;
 
 struct CsrView {
   int n = 0;
