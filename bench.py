@@ -35,7 +35,8 @@ def parse():
     ap.add_argument("--lin-rtol-coarse", type=float, default=1e-2, help="<= 0: same as --lin-rtol")
     ap.add_argument("--lin-target", type=float, default=0.03, help="level-0 inexact-Newton forcing, 0 = off")
     ap.add_argument("--lin-max-it-coarse", type=int, default=10,
-                    help="iteration limit of each coarse-level Krylov method (<= 0: same as level 0)")
+                    help="iteration limit of each coarse-level linear solve, PCG and its BiCGStab "
+                         "fallback together (<= 0: same as level 0)")
     ap.add_argument("--newton-krylov", default="pcg", choices=["pcg", "bicgstab"],
                     help="pcg: PCG first with BiCGStab fallback on Newton systems")
     ap.add_argument("--amg-reuse", type=int, default=-1,

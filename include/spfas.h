@@ -134,7 +134,9 @@ typedef struct {
  *   dp_cap              max |delta p| per smoothing step, ln(c)/alpha in the
  *                       paper (c = 1.5 or 5); <= 0 disables the cap
  *   coarsest_max_steps  smoothing steps on the coarsest level (paper: 10)
- *   lin_rtol, lin_max_it  inner Krylov tolerance and iteration limit
+ *   lin_rtol, lin_max_it  inner Krylov tolerance and iteration limit of
+ *                       one linear solve (PCG and its BiCGStab fallback
+ *                       together)
  *   x0_given            nonzero: p and sigma hold the initial guess on entry
  *   lin_rtol_coarse     inner tolerance on coarse levels (<= 0: lin_rtol)
  *   lin_target          > 0: a level-0 smoothing step at residual norm r
@@ -148,7 +150,8 @@ typedef struct {
  *                       is the kappa' term of E), falling back to BiCGStab
  *                       from scratch on a breakdown, on a stall (||r||
  *                       lowered less than 2x over 5 iterations) or
- *                       without convergence; 0: BiCGStab only
+ *                       without convergence, with the iterations the limit
+ *                       has left; 0: BiCGStab only
  *   amg_reuse           > 0: the AMG values of a level's preconditioner are
  *                       kept for up to amg_reuse further linearisations of
  *                       the same solve (< 0: no limit), as long as its
@@ -158,7 +161,7 @@ typedef struct {
  *                       the current matrix, so only the inner iteration
  *                       changes, never the system solved.  0: recomputed
  *                       after every linearisation
- *   lin_max_it_coarse   iteration limit of each coarse-level Krylov method
+ *   lin_max_it_coarse   iteration limit of each coarse-level linear solve
  *                       (<= 0: lin_max_it); a solve that reaches it hands
  *                       its current iterate to the smoothing step, whose
  *                       direction Alg. 1 then checks

@@ -129,14 +129,18 @@ constexpr int kPcgStall = 5;
 
 // Krylov solve of a linearised system: PCG for Picard (symmetric);
 // BiCGStab for Newton, or PCG first with BiCGStab from scratch when PCG
-// breaks down or does not converge within the iteration limit.
+// breaks down, stalls or does not converge; the limit counts the iterations
+// of both.
 static int krylov_solve(Krylov& kry, const CsrView& A, Amg* M, const double* b, double* x, double rtol,
                         const Opts& o, hipStream_t s) {
   if (!o.newton) return kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
   if (o.newton_pcg) {
     const int it = kry.pcg(A, M, b, x, rtol, o.lin_max_it, s, kPcgStall);
     if (kry.converged) return it;
-    const int it2 = kry.bicgstab(A, M, b, x, rtol, o.lin_max_it, s);
+    // the hand-over gets what is left of the solve's iteration limit
+    const int left = o.lin_max_it - it;
+    if (left <= 0) return it;
+    const int it2 = kry.bicgstab(A, M, b, x, rtol, left, s);
     if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
       std::fprintf(stderr, "[spfas] PCG stopped after %d iterations without convergence; BiCGStab %d\n", it, it2);
     return it + it2;
