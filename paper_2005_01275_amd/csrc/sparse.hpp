@@ -92,6 +92,7 @@ struct CycMat {
   DVec<cyc_t> val;
   DVec<int> src;                      // per stored slot: source entry of the value, -1 = padding
   long long nnz = 0;                  // stored entries without padding
+  int lanes = 8;                      // CSR: lanes per row of the cycle products
 };
 
 struct CycView {
