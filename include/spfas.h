@@ -311,8 +311,10 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
  * diagonal: S x with its dot products 12E + 24N (FP64 value + int32
  * column per entry); on the finest level of the classical AMG (FP16 value
  * + int32 column per stored entry, N_c coarse points, E_w = E, E_R =
- * entries of P, E_AP = entries of A P): pre-sweep + residual 6E_w + 16N,
- * restriction 6E_R + 8N + 8N_c, prolongation + sweep 6E_AP + 32N + 8N_c).
+ * entries of P, E_AP = entries of A P; the cycle's input and output are
+ * FP64, its residual and coarse vectors FP32): pre-sweep + residual
+ * 6E_w + 12N, restriction 6E_R + 4N + 4N_c, prolongation + sweep
+ * 6E_AP + 28N + 4N_c).
  */
 typedef enum {
   SPFAS_PROF_FINE_RESID = 0,         /* fine residual, also inside Alg. 1 trials   */

@@ -603,38 +603,45 @@ __global__ void __launch_bounds__(kBlock) k_fill_rm(int ne, const int* __restric
 // (with x1 = w b and r = b - A x1, the post-sweep of y = x1 + P e is
 // y + w (b - A y) = w (b + r) + (P - diag(w) A P) e).  The template flag
 // only separates the finest-level launches by name.
-template <int Op, bool Finest>
-__global__ void __launch_bounds__(kBlock) k_cyc(CycView M, const double* __restrict__ x,
-                                                const double* __restrict__ b, const double* __restrict__ r,
-                                                const double* __restrict__ w, double* __restrict__ y) {
+// Vectors inside the classical cycle are FP32 (residuals, restricted
+// right-hand sides, coarse corrections); the cycle's input b and output on
+// level 0 are the Krylov solver's FP64 vectors (TB, TY); products and sums
+// are FP64.  Op 0 gathers x = b; Ops 1 and 2 gather FP32 vectors.
+template <int Op, class TB>
+using CycX = std::conditional_t<Op == 0, TB, float>;
+
+template <int Op, bool Finest, class TB, class TY>
+__global__ void __launch_bounds__(kBlock) k_cyc(CycView M, const CycX<Op, TB>* __restrict__ x,
+                                                const TB* __restrict__ b, const float* __restrict__ r,
+                                                const double* __restrict__ w, TY* __restrict__ y) {
   const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= M.n) return;
   int e, end, step;
   cyc_row<true>(M, i, e, end, step);
   double acc = 0.0;
 #pragma unroll 4
-  for (; e < end; e += 64) acc += (double)M.val[e] * x[M.col[e]];
-  if constexpr (Op == 0) y[i] = b[i] - acc;
-  else if constexpr (Op == 1) y[i] = acc;
-  else y[i] = w[i] * (b[i] + r[i]) + acc;
+  for (; e < end; e += 64) acc += (double)M.val[e] * (double)x[M.col[e]];
+  if constexpr (Op == 0) y[i] = (TY)((double)b[i] - acc);
+  else if constexpr (Op == 1) y[i] = (TY)acc;
+  else y[i] = (TY)(w[i] * ((double)b[i] + (double)r[i]) + acc);
 }
 
 // The same on CSR with a group of LG lanes per row (smaller levels).
-template <int Op, int LG>
-__global__ void __launch_bounds__(kBlock) k_cycv(CycView M, const double* __restrict__ x,
-                                                 const double* __restrict__ b, const double* __restrict__ r,
-                                                 const double* __restrict__ w, double* __restrict__ y) {
+template <int Op, int LG, class TB, class TY>
+__global__ void __launch_bounds__(kBlock) k_cycv(CycView M, const CycX<Op, TB>* __restrict__ x,
+                                                 const TB* __restrict__ b, const float* __restrict__ r,
+                                                 const double* __restrict__ w, TY* __restrict__ y) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = t / LG, g = t % LG;
   if (i >= M.n) return;   // the whole group leaves together
   double acc = 0.0;
-  for (int e = M.ptr[i] + g; e < M.ptr[i + 1]; e += LG) acc += (double)M.val[e] * x[M.col[e]];
+  for (int e = M.ptr[i] + g; e < M.ptr[i + 1]; e += LG) acc += (double)M.val[e] * (double)x[M.col[e]];
 #pragma unroll
   for (int o = LG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LG);
   if (g == 0) {
-    if constexpr (Op == 0) y[i] = b[i] - acc;
-    else if constexpr (Op == 1) y[i] = acc;
-    else y[i] = w[i] * (b[i] + r[i]) + acc;
+    if constexpr (Op == 0) y[i] = (TY)((double)b[i] - acc);
+    else if constexpr (Op == 1) y[i] = (TY)acc;
+    else y[i] = (TY)(w[i] * ((double)b[i] + (double)r[i]) + acc);
   }
 }
 
@@ -795,16 +802,17 @@ __global__ void __launch_bounds__(kBlock) k_dense_inverse_lds(const double* __re
 }
 
 // x = inv b, one wave per row (coalesced row reads)
-__global__ void __launch_bounds__(kBlock) k_dense_gemv(int nd, const double* __restrict__ inv, const double* __restrict__ b,
-                                                       double* __restrict__ x) {
+template <class TB, class TY>
+__global__ void __launch_bounds__(kBlock) k_dense_gemv(int nd, const double* __restrict__ inv, const TB* __restrict__ b,
+                                                       TY* __restrict__ x) {
   const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nd) return;
   const double* r = inv + (size_t)row * nd;
   double s = 0.0;
-  for (int j = lane; j < nd; j += 64) s += r[j] * b[j];
+  for (int j = lane; j < nd; j += 64) s += r[j] * (double)b[j];
   s = wave_sum(s);
-  if (lane == 0) x[row] = s;
+  if (lane == 0) x[row] = (TY)s;
 }
 
 // ------------------------------------------------------------------ AMG host
@@ -1159,10 +1167,16 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bo
   lu.alloc((size_t)nd * nd);
   for (auto& L : lv) {
     L.invd.alloc(L.n);
-    L.x.alloc(L.n);
-    L.b.alloc(L.n);
-    L.r.alloc(L.n);
     L.t.alloc(L.n);
+    if (classical) {
+      L.x32.alloc(L.n);
+      L.b32.alloc(L.n);
+      L.r32.alloc(L.n);
+    } else {
+      L.x.alloc(L.n);
+      L.b.alloc(L.n);
+      L.r.alloc(L.n);
+    }
   }
   lv.back().t.alloc((size_t)nd * nd);   // dense inverse of the coarsest matrix
   piv.alloc(nd);
@@ -1293,74 +1307,70 @@ void Amg::dense_numeric(hipStream_t s) {
 
 // One V(1,1) cycle of the classical hierarchy, three kernels per level:
 // down [pre-sweep + residual] [restriction], up [prolongation + post-sweep].
-// CSR cycle product with the lane-group width chosen for the operator
-template <int Op>
-static void launch_cycv(const CycMat& M, const double* x, const double* b, const double* r, const double* w,
-                        double* y, hipStream_t s) {
+// One cycle product on operator M: SELL-64 (thread per row; the `Finest`
+// flag only names the level-0 launches apart) or CSR with the lane-group
+// width chosen for the operator.
+template <int Op, class TB, class TY>
+static void launch_cyc(const CycMat& M, bool finest, const CycX<Op, TB>* x, const TB* b, const float* r,
+                       const double* w, TY* y, hipStream_t s) {
   const CycView v = cyc_view(M);
+  if (M.sell) {
+    const unsigned g = grid_for(M.n, kBlock);
+    if (finest) hipLaunchKernelGGL((k_cyc<Op, true, TB, TY>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y);
+    else hipLaunchKernelGGL((k_cyc<Op, false, TB, TY>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y);
+    return;
+  }
   const unsigned g = grid_for((size_t)M.n * M.lanes, kBlock);
   switch (M.lanes) {
-    case 4: hipLaunchKernelGGL((k_cycv<Op, 4>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
-    case 16: hipLaunchKernelGGL((k_cycv<Op, 16>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
-    case 32: hipLaunchKernelGGL((k_cycv<Op, 32>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
-    default: hipLaunchKernelGGL((k_cycv<Op, 8>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
+    case 16: hipLaunchKernelGGL((k_cycv<Op, 16, TB, TY>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
+    case 32: hipLaunchKernelGGL((k_cycv<Op, 32, TB, TY>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
+    default: hipLaunchKernelGGL((k_cycv<Op, 8, TB, TY>), dim3(g), dim3(kBlock), 0, s, v, x, b, r, w, y); break;
   }
 }
 
+// V(1,1): FP64 b and x on level 0, FP32 vectors on the levels below and
+// for the level-0 residual.
 void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
   const int L = (int)lv.size();
-  const double* bl = b;
+  if (L == 1) {   // dense solve only
+    timed(lvprof.get(), 63, 0.0, s, [&] {
+      hipLaunchKernelGGL((k_dense_gemv<double, double>), dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd,
+                         lv.back().t.p, b, x);
+    });
+    LAUNCHCHECK();
+    return;
+  }
   for (int k = 0; k < L - 1; ++k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
     KernelProf* pf = k == 0 ? hook.prof : nullptr;
     timed(lvprof.get(), 3 * k, 0.0, s, [&] {
       const double n = (double)F.n;
-      timed(pf, hook.down_id, 6.0 * (double)F.aw.nnz + 16.0 * n, s, [&] {
-        if (!F.aw.sell)
-          launch_cycv<0>(F.aw, bl, bl, nullptr, nullptr, F.r.p, s);
-        else if (pf)
-          hipLaunchKernelGGL((k_cyc<0, true>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.aw), bl,
-                             bl, nullptr, nullptr, F.r.p);
-        else
-          hipLaunchKernelGGL((k_cyc<0, false>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.aw), bl,
-                             bl, nullptr, nullptr, F.r.p);
+      // r = b - A diag(w) b: b read (8 bytes on level 0, 4 below), r written in FP32
+      timed(pf, hook.down_id, 6.0 * (double)F.aw.nnz + 12.0 * n, s, [&] {
+        if (k == 0) launch_cyc<0, double, float>(F.aw, true, b, b, nullptr, nullptr, F.r32.p, s);
+        else launch_cyc<0, float, float>(F.aw, false, F.b32.p, F.b32.p, nullptr, nullptr, F.r32.p, s);
       });
-      timed(pf, hook.restrict_id, 6.0 * (double)F.rm.nnz + 8.0 * n + 8.0 * C.n, s, [&] {
-        if (!F.rm.sell)
-          launch_cycv<1>(F.rm, F.r.p, nullptr, nullptr, nullptr, C.b.p, s);
-        else if (pf)
-          hipLaunchKernelGGL((k_cyc<1, true>), dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.rm),
-                             F.r.p, nullptr, nullptr, nullptr, C.b.p);
-        else
-          hipLaunchKernelGGL((k_cyc<1, false>), dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.rm),
-                             F.r.p, nullptr, nullptr, nullptr, C.b.p);
+      timed(pf, hook.restrict_id, 6.0 * (double)F.rm.nnz + 4.0 * n + 4.0 * C.n, s, [&] {
+        launch_cyc<1, float, float>(F.rm, k == 0, F.r32.p, nullptr, nullptr, nullptr, C.b32.p, s);
       });
     });
     LAUNCHCHECK();
-    bl = C.b.p;
   }
-  double* xl = L == 1 ? x : lv.back().x.p;
   timed(lvprof.get(), 63, 0.0, s, [&] {
-    hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd, lv.back().t.p, bl, xl);
+    hipLaunchKernelGGL((k_dense_gemv<float, float>), dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd,
+                       lv.back().t.p, lv.back().b32.p, lv.back().x32.p);
   });
   LAUNCHCHECK();
   for (int k = L - 2; k >= 0; --k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
-    double* xf = (k == 0) ? x : F.x.p;
-    const double* bf = (k == 0) ? b : F.b.p;
     KernelProf* pf = k == 0 ? hook.prof : nullptr;
     timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
-      timed(pf, hook.up_id, 6.0 * (double)F.cm.nnz + 32.0 * F.n + 8.0 * C.n, s, [&] {
-        if (!F.cm.sell)
-          launch_cycv<2>(F.cm, C.x.p, bf, F.r.p, F.invd.p, xf, s);
-        else if (pf)
-          hipLaunchKernelGGL((k_cyc<2, true>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm), C.x.p,
-                             bf, F.r.p, F.invd.p, xf);
-        else
-          hipLaunchKernelGGL((k_cyc<2, false>), dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm),
-                             C.x.p, bf, F.r.p, F.invd.p, xf);
+      // w, b, r, x: 8 + 8 + 4 + 8 bytes per row on level 0; e gathered in FP32
+      timed(pf, hook.up_id, 6.0 * (double)F.cm.nnz + 28.0 * F.n + 4.0 * C.n, s, [&] {
+        if (k == 0) launch_cyc<2, double, double>(F.cm, true, C.x32.p, b, F.r32.p, F.invd.p, x, s);
+        else launch_cyc<2, float, float>(F.cm, false, C.x32.p, F.b32.p, F.r32.p, F.invd.p, F.x32.p, s);
       });
     });
     LAUNCHCHECK();
@@ -1412,7 +1422,8 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
   }
   double* xl = L == 1 ? x : lv.back().x.p;
   timed(lvprof.get(), 63, 0.0, s, [&] {
-    hipLaunchKernelGGL(k_dense_gemv, dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd, lv.back().t.p, bl, xl);
+    hipLaunchKernelGGL((k_dense_gemv<double, double>), dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd,
+                       lv.back().t.p, bl, xl);
   });
   LAUNCHCHECK();
   for (int k = L - 2; k >= 0; --k) {

@@ -131,7 +131,8 @@ struct AmgLevel {
   DVec<double> apv;                   // A P values
   DVec<int> clptr, clr, clq;          // next level's off entries then diagonal -> (P entry, A P entry)
   CycMat aw, rm, cm;                  // cycle operators A diag(w), R = P^T, P - diag(w) A P
-  DVec<double> x, b, r, t;            // work vectors
+  DVec<double> x, b, r, t;            // work vectors (x, b, r: aggregation AMG)
+  DVec<float> x32, b32, r32;          // classical cycle: FP32 vectors inside the cycle
 };
 
 // Reuse state of a preconditioner across the linearisations of one solve.

@@ -1,8 +1,8 @@
-"""Full-size 60x220x85 workload in the configuration bench.py times
-(GPU): the returned state meets the stopping rule when re-evaluated with
-the oracle's residual, the level-0 aggregation matches the oracle bit for
-bit, and sampled aggregates of the hierarchy match the oracle's local
-computations."""
+"""Full-size 60x220x85 workload, with plain inner solves and with the
+inner-solver options bench.py times (GPU): the returned state meets the
+stopping rule when re-evaluated with the oracle's residual, the level-0
+aggregation matches the oracle bit for bit, and sampled aggregates of the
+hierarchy match the oracle's local computations."""
 import math
 
 import numpy as np
@@ -22,12 +22,21 @@ def c2():
     return prob, H
 
 
-def test_c2_fas_newton_meets_rtol(c2):
+# the inner-solver options bench.py times (level-0 tolerance 1e-5 with
+# forcing 0.03, coarse tolerance 1e-2 with at most 10 iterations, PCG first
+# on Newton systems, AMG values reused)
+BENCH_INNER = dict(lin_rtol=1e-5, lin_max_it=400, lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1,
+                   amg_reuse=-1, lin_max_it_coarse=10)
+
+
+@pytest.mark.parametrize("inner", ["plain", "bench"])
+def test_c2_fas_newton_meets_rtol(c2, inner):
     import paper_2005_01275_amd as pk
     prob, H = c2
-    print("case c2 fas-newton", flush=True)
-    o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, lin_rtol=1e-4, lin_max_it=400,
-                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
+    print(f"case c2 fas-newton {inner}", flush=True)
+    kw = dict(lin_rtol=1e-4, lin_max_it=400) if inner == "plain" else BENCH_INNER
+    o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50,
+                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha, **kw)
     p, s, st = H.fas_solve(prob, o)
     assert st["converged"], st
     fs = FineSystem(prob)
