@@ -65,6 +65,13 @@ __device__ inline double reduce_parts_max(const double* parts, int n, double* sh
   return block_max(v, sh);
 }
 
+// Load of data a launch streams through once (SELL-64 matrix values and
+// column indices): marked non-temporal so it does not displace the gathered
+// vectors from the caches (4-6 % faster SELL products; slower for the CSR
+// lane-group kernels and the fine residual, which keep plain loads).
+template <class T>
+__device__ inline T ld_stream(const T* p) { return __builtin_nontemporal_load(p); }
+
 // Block index remapped so that each of the 8 XCDs, which receive the blocks
 // of a launch round-robin, works on one contiguous range of logical blocks
 // (neighbouring rows then share that XCD's L2).  A bijection on

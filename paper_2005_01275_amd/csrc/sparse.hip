@@ -52,7 +52,7 @@ __device__ inline double row_dot(const Sell64View& A, int i, const double* __res
   int e = a0 + (i & 63);
   double a = 0.0;
 #pragma unroll 4
-  for (int k = 0; k < width; ++k, e += 64) a += A.val[e] * x[A.col[e]];
+  for (int k = 0; k < width; ++k, e += 64) a += ld_stream(A.val + e) * x[ld_stream(A.col + e)];
   return a;
 }
 
@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(kBlock) k_cyc(CycView M, const CycX<Op, TB>* _
   cyc_row<true>(M, i, e, end, step);
   double acc = 0.0;
 #pragma unroll 4
-  for (; e < end; e += 64) acc += (double)M.val[e] * (double)x[M.col[e]];
+  for (; e < end; e += 64) acc += (double)ld_stream(M.val + e) * (double)x[ld_stream(M.col + e)];
   if constexpr (Op == 0) y[i] = (TY)((double)b[i] - acc);
   else if constexpr (Op == 1) y[i] = (TY)acc;
   else y[i] = (TY)(w[i] * ((double)b[i] + (double)r[i]) + acc);
