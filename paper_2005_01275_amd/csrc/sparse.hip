@@ -1305,8 +1305,6 @@ void Amg::dense_numeric(hipStream_t s) {
   LAUNCHCHECK();
 }
 
-// One V(1,1) cycle of the classical hierarchy, three kernels per level:
-// down [pre-sweep + residual] [restriction], up [prolongation + post-sweep].
 // One cycle product on operator M: SELL-64 (thread per row; the `Finest`
 // flag only names the level-0 launches apart) or CSR with the lane-group
 // width chosen for the operator.
@@ -1328,8 +1326,10 @@ static void launch_cyc(const CycMat& M, bool finest, const CycX<Op, TB>* x, cons
   }
 }
 
-// V(1,1): FP64 b and x on level 0, FP32 vectors on the levels below and
-// for the level-0 residual.
+// One V(1,1) cycle of the classical hierarchy, three kernels per level:
+// down [pre-sweep + residual] [restriction], up [prolongation + post-sweep].
+// FP64 b and x on level 0, FP32 vectors on the levels below and for the
+// level-0 residual.
 void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
   const int L = (int)lv.size();
   if (L == 1) {   // dense solve only
