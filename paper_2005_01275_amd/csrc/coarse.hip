@@ -43,7 +43,8 @@ __device__ inline void coarse_row(const CView& v, double alpha, int it, const do
                                   const double* __restrict__ p, const double* __restrict__ dsig,
                                   const double* __restrict__ dp, const double* steps,
                                   const double* __restrict__ b, double* __restrict__ r, double* acc) {
-  auto stp = [&](const double* a, const double* d, int i, int t) { return STEP ? fma(steps[t], d[i], a[i]) : a[i]; };
+  // value of component i at step t: a_i + s_t d_i (explicit fma)
+  auto stp = [&](double a, double d, int t) { return STEP ? fma(steps[t], d, a) : a; };
   if (it < v.nf) {
     const int j = it;
     double val[NT];
@@ -57,17 +58,29 @@ __device__ inline void coarse_row(const CView& v, double alpha, int it, const do
       const int p0 = v.pptr[c], m = v.pptr[c + 1] - p0;
       const double* Mr = v.M + v.mptr[c] + li * k;
       const int* lf = v.lfidx + v.lfptr[c];
+      // every sum runs over its index in the same order for each step, so a
+      // step gives the same bits whatever NT is; each datum is loaded once
+      double pbar[NT], ms[NT], dtp[NT];
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        double pbar = 0.0;
-        for (int q = 0; q < m; ++q) pbar = fma(v.w[p0 + q], stp(p, dp, p0 + q, t), pbar);
-        const double sc = exp(-alpha * pbar);
-        double ms = 0.0;
-        for (int i = 0; i < k; ++i) ms = fma(Mr[i], stp(sig, dsig, lf[i], t), ms);
-        double dtp = 0.0;
-        for (int q = 0; q < m; ++q) dtp = fma(v.D[v.dptr[c] + q * k + li], stp(p, dp, p0 + q, t), dtp);
-        val[t] = val[t] + fma(sc, ms, dtp);
+      for (int t = 0; t < NT; ++t) pbar[t] = ms[t] = dtp[t] = 0.0;
+      for (int q = 0; q < m; ++q) {
+        const double wq = v.w[p0 + q], dq = v.D[v.dptr[c] + q * k + li];
+        const double a = p[p0 + q], d = STEP ? dp[p0 + q] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          pbar[t] = fma(wq, stp(a, d, t), pbar[t]);
+          dtp[t] = fma(dq, stp(a, d, t), dtp[t]);
+        }
       }
+      for (int i = 0; i < k; ++i) {
+        const double mi = Mr[i];
+        const int f = lf[i];
+        const double a = sig[f], d = STEP ? dsig[f] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ms[t] = fma(mi, stp(a, d, t), ms[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) val[t] = val[t] + fma(exp(-alpha * pbar[t]), ms[t], dtp[t]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -82,11 +95,20 @@ __device__ inline void coarse_row(const CView& v, double alpha, int it, const do
     const int* lf = v.lfidx + v.lfptr[c];
     for (int q = 0; q < m; ++q) {
       const double* Dr = v.D + v.dptr[c] + q * k;
+      double dv[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) dv[t] = 0.0;
+      for (int i = 0; i < k; ++i) {
+        const double di = Dr[i];
+        const int f = lf[i];
+        const double a = sig[f], d = STEP ? dsig[f] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) dv[t] = fma(di, stp(a, d, t), dv[t]);
+      }
+      const double bq = b[v.nf + p0 + q];
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
-        double a = 0.0;
-        for (int i = 0; i < k; ++i) a = fma(Dr[i], stp(sig, dsig, lf[i], t), a);
-        const double ri = a - b[v.nf + p0 + q];
+        const double ri = dv[t] - bq;
         if (r) r[v.nf + p0 + q] = ri;
         acc[t] = fma(ri, ri, acc[t]);
       }
