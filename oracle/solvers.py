@@ -15,6 +15,15 @@
                        most 10 smoothing steps, stopping early on convergence
                        (Section 4) or when a step no longer lowers its
                        residual.
+* ``cascadic_solve`` -- nonlinear cascadic multigrid (Section 4.2, Table 4):
+                       the right-hand side restricted level by level
+                       (b^{l+1} = R b^l), the coarsest problem solved from
+                       zero with smoothing steps until it converges, its
+                       solution prolongated (P) as the initial guess of the
+                       next finer level, and so on up to level 0.  Reading:
+                       each level stops on the same rule as the fine level,
+                       relative to the residual of the zero state
+                       (||r^l(0)|| = ||b^l||), and takes at most max_it steps.
 * ``fas_solve`` / ``single_level_solve`` -- outer loops with the stopping rule
   of Section 4: relative residual below rtol or absolute below atol (2-norm
   of the whole residual vector; relative to the residual of the initial
@@ -198,6 +207,50 @@ def single_level_solve(h, opts: Opts, x0=None):
         st.residuals.append(norm(residual(lev, x, h.b0, h.alpha)))
     else:
         st.converged = st.residuals[-1] <= tol
+    return x, st
+
+
+@dataclasses.dataclass
+class CascadicStats:
+    level_steps: List[int] = dataclasses.field(default_factory=list)   # per level, finest first
+    level_converged: List[bool] = dataclasses.field(default_factory=list)
+    level_x: List[np.ndarray] = dataclasses.field(default_factory=list)   # final state of each level
+    bt_steps: int = 0
+    r0: float = 0.0
+    r_final: float = 0.0
+    converged: bool = False
+
+
+def cascadic_solve(h, opts: Opts):
+    """Nonlinear cascadic multigrid from the zero state; returns the fine
+    state and per-level step counts (finest level first)."""
+    L = len(h.levels)
+    a = h.alpha
+    rhs = [h.b0]
+    for l in range(L - 1):
+        rhs.append(h.transfers[l].R(rhs[l], h.levels[l].n_flux))
+    st = CascadicStats(level_steps=[0] * L, level_converged=[False] * L, level_x=[None] * L)
+    x = np.zeros(h.levels[L - 1].n)
+    for l in range(L - 1, -1, -1):
+        lev = h.levels[l]
+        if l < L - 1:
+            x = h.transfers[l].P(x, h.levels[l + 1].n_flux)
+        tol = max(opts.rtol * norm(rhs[l]), opts.atol)
+        r = norm(residual(lev, x, rhs[l], a))
+        if l == 0:
+            st.r0 = norm(rhs[0])
+        for _ in range(opts.max_it):
+            if r <= tol:
+                break
+            x = smooth(lev, x, rhs[l], a, opts, st)
+            st.level_steps[l] += 1
+            r = norm(residual(lev, x, rhs[l], a))
+            if not math.isfinite(r):
+                break
+        st.level_converged[l] = r <= tol
+        st.level_x[l] = x.copy()
+    st.r_final = r
+    st.converged = st.level_converged[0]
     return x, st
 
 
