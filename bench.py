@@ -236,6 +236,20 @@ def main():
             comp[name] = {"time_s": time.perf_counter() - a, "iterations": st["iterations"],
                           "converged": st["converged"], "krylov_iters": st["lin_iters"]}
         out["gpu_single_level"] = comp
+        # nonlinear cascadic multigrid (Newton smoothing, the same inner options)
+        o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=200, lin_rtol=args.lin_rtol,
+                         lin_max_it=400, dp_cap=cap, lin_rtol_coarse=args.lin_rtol_coarse, lin_target=args.lin_target,
+                         newton_pcg=int(args.newton_krylov == "pcg"), amg_reuse=args.amg_reuse,
+                         lin_max_it_coarse=args.lin_max_it_coarse)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        try:
+            _, _, st = H.cascadic_solve(prob, o, device=True, cprob=cprob, out=(p, s), stream=stream.cuda_stream)
+            torch.cuda.synchronize()
+            out["gpu_cascadic"] = {"time_s": time.perf_counter() - a, "level_steps": st["level_steps"],
+                                   "converged": st["converged"], "krylov_iters": st["lin_iters"]}
+        except pk.SpfasError as e:   # a comparator's failure is reported, not fatal
+            out["gpu_cascadic"] = {"error": str(e)}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n_cells, float(np.mean(vcycles)))

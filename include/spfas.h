@@ -249,6 +249,25 @@ int spfas_picard_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfa
 int spfas_newton_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts,
                        double* p, double* sigma, int32_t state_mem, spfas_stats* stats, void* stream);
 
+/* Nonlinear cascadic multigrid (Section 4.2, Table 4): the right-hand side
+ * is restricted to every level (b^{l+1} = R b^l = P^T b^l), the coarsest
+ * problem is solved from zero with smoothing steps (opts->smoother, the cap
+ * and Alg. 1 as in spfas_fas_solve) until it converges, and each finer level
+ * starts from the prolongated (P) solution of the level below and is
+ * smoothed until it converges, up to level 0.  "Converges" on level l means
+ * ||r^l|| <= max(rtol ||b^l||, atol), with at most max_it smoothing steps per
+ * level; a coarse level also stops after a step that did not lower its
+ * residual, and hands its state up either way.
+ * p, sigma: as spfas_fas_solve, outputs only; opts->x0_given must be 0
+ * (ERR_INVALID otherwise).  level_steps: host array of n_levels int32, the
+ * smoothing steps taken on each level (finest first), or NULL.
+ * stats->iterations counts the level-0 steps, stats->r0 = ||b^0||.
+ * Returns SPFAS_OK when level 0 converged, SPFAS_NOT_CONVERGED when it
+ * reached max_it; other errors as spfas_fas_solve. */
+int spfas_cascadic_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts,
+                         double* p, double* sigma, int32_t state_mem, spfas_stats* stats, int32_t* level_steps,
+                         void* stream);
+
 /*
  * Fine-level residual r(x) = A(x) - b (eqs. fine_level_residual and
  * fine_level_operators) at the state (p, sigma), written in input order:

@@ -23,7 +23,10 @@
                        next finer level, and so on up to level 0.  Reading:
                        each level stops on the same rule as the fine level,
                        relative to the residual of the zero state
-                       (||r^l(0)|| = ||b^l||), and takes at most max_it steps.
+                       (||r^l(0)|| = ||b^l||), and takes at most max_it steps;
+                       a coarse level also stops after a step that did not
+                       lower its residual (its rounding level, as on the
+                       coarsest level of the V-cycle).
 * ``fas_solve`` / ``single_level_solve`` -- outer loops with the stopping rule
   of Section 4: relative residual below rtol or absolute below atol (2-norm
   of the whole residual vector; relative to the residual of the initial
@@ -244,8 +247,10 @@ def cascadic_solve(h, opts: Opts):
                 break
             x = smooth(lev, x, rhs[l], a, opts, st)
             st.level_steps[l] += 1
-            r = norm(residual(lev, x, rhs[l], a))
-            if not math.isfinite(r):
+            r_new = norm(residual(lev, x, rhs[l], a))
+            stalled = l > 0 and not r_new < r
+            r = r_new
+            if not math.isfinite(r) or stalled:
                 break
         st.level_converged[l] = r <= tol
         st.level_x[l] = x.copy()

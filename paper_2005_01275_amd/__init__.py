@@ -148,7 +148,7 @@ class Hierarchy:
 
     # ---------------------------------------------------------------- solves
     def _solve(self, fn, prob, opts: SolveOpts, p0=None, sigma0=None, device=False, cprob=None, stream=None,
-               out=None):
+               out=None, extra=()):
         L = N.lib()
         st = N.spfas_stats()
         o = opts.c()
@@ -166,7 +166,7 @@ class Hierarchy:
                 s.copy_(torch.as_tensor(sigma0, dtype=torch.float64))
                 o.x0_given = 1
             rc = getattr(L, fn)(self.h, C.byref(cprob), C.byref(o), p.data_ptr(), s.data_ptr(), SPFAS_MEM_DEVICE,
-                                C.byref(st), _stream_handle(stream))
+                                C.byref(st), *extra, _stream_handle(stream))
         else:
             cprob, keep = self._problem(prob, device=False)
             p = np.zeros(self.n_cells) if p0 is None else np.array(p0, dtype=np.float64)
@@ -174,7 +174,7 @@ class Hierarchy:
             if p0 is not None:
                 o.x0_given = 1
             rc = getattr(L, fn)(self.h, C.byref(cprob), C.byref(o), p.ctypes.data, s.ctypes.data, SPFAS_MEM_HOST,
-                                C.byref(st), _stream_handle(stream))
+                                C.byref(st), *extra, _stream_handle(stream))
         N.check(rc)
         stats = {f: getattr(st, f) for f, _ in N.spfas_stats._fields_}
         stats["converged"] = rc == SPFAS_OK
@@ -188,6 +188,17 @@ class Hierarchy:
 
     def newton_solve(self, prob, opts: SolveOpts, **kw):
         return self._solve("spfas_newton_solve", prob, opts, **kw)
+
+    def cascadic_solve(self, prob, opts: SolveOpts, **kw):
+        """Nonlinear cascadic multigrid (spfas_cascadic_solve); starts from
+        zero, so p0/sigma0 are not accepted.  stats["level_steps"] lists the
+        smoothing steps per level, finest first."""
+        if kw.get("p0") is not None or kw.get("sigma0") is not None:
+            raise ValueError("the cascadic solve starts from zero on the coarsest level")
+        steps = (C.c_int32 * self.n_levels)()
+        p, s, stats = self._solve("spfas_cascadic_solve", prob, opts, extra=(steps,), **kw)
+        stats["level_steps"] = list(steps)
+        return p, s, stats
 
     # ---------------------------------------------------------------- parity hooks
     def level_sizes(self, level):

@@ -106,7 +106,8 @@ int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const dou
 }
 
 static int solve_common(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
-                        double* sigma, int32_t state_mem, spfas_stats* stats, void* stream, SolveKind kind) {
+                        double* sigma, int32_t state_mem, spfas_stats* stats, void* stream, SolveKind kind,
+                        int32_t* level_steps = nullptr) {
   return guarded([&] {
     need_device(h);
     require(prob && opts && p && sigma, "NULL argument");
@@ -114,7 +115,7 @@ static int solve_common(spfas_hierarchy* h, const spfas_problem* prob, const spf
     auto t0 = std::chrono::steady_clock::now();
     spfas_stats st;
     std::memset(&st, 0, sizeof st);
-    int rc = run_solve(h->h, *prob, *opts, p, sigma, state_mem == SPFAS_MEM_DEVICE, kind, st);
+    int rc = run_solve(h->h, *prob, *opts, p, sigma, state_mem == SPFAS_MEM_DEVICE, kind, st, level_steps);
     auto t1 = std::chrono::steady_clock::now();
     st.solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     if (stats) *stats = st;
@@ -136,6 +137,11 @@ int spfas_picard_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfa
 int spfas_newton_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
                        double* sigma, int32_t state_mem, spfas_stats* stats, void* stream) {
   return solve_common(h, prob, opts, p, sigma, state_mem, stats, stream, SolveKind::NEWTON);
+}
+
+int spfas_cascadic_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
+                         double* sigma, int32_t state_mem, spfas_stats* stats, int32_t* level_steps, void* stream) {
+  return solve_common(h, prob, opts, p, sigma, state_mem, stats, stream, SolveKind::CASCADIC, level_steps);
 }
 
 int spfas_level_sizes(const spfas_hierarchy* h, int32_t level, int64_t* n_cells, int64_t* n_p, int64_t* n_flux) {

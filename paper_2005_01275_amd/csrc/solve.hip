@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
+#include <vector>
 
 #include "coarse_kern.hpp"
 #include "kern.hpp"
@@ -576,16 +577,92 @@ int run_fas(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
   return rc;
 }
 
+// Nonlinear cascadic multigrid (Section 4.2, Table 4).  The right-hand
+// sides are restricted level by level, b^{l+1} = R b^l, which is the FAS
+// right-hand side A^{l+1}(Q x) - R r^l(x) at the zero state (A^l(0) = 0 on
+// every level, so r^l(0) = -b^l).  The coarsest problem is solved from zero;
+// each finer level starts from the prolongated solution of the level below
+// and takes smoothing steps until ||r^l|| <= max(rtol ||b^l||, atol) or
+// max_it steps; a coarse level also stops after a step that did not lower
+// its residual.  The return code reports the fine level's test.
+static int run_cascadic(Hierarchy& h, const Opts& o_in, spfas_stats& st, int32_t* level_steps) {
+  prec_reset(h);
+  hipStream_t s = h.stream;
+  const int L = h.n_levels;
+  FineWork& w = h.fw;
+  FineDev& f = h.fine;
+  const double alpha = f.alpha;
+  auto state = [&](int l) { return l == 0 ? w.x.p : h.coarse[l - 1]->x.p; };
+  auto size = [&](int l) -> int64_t {
+    return l == 0 ? f.nf + f.n : h.coarse[l - 1]->nf + h.coarse[l - 1]->np;
+  };
+  auto rnorm = [&](int l) {
+    return l == 0 ? fine_rnorm(h, w.x.p, nullptr, 0.0) : coarse_rnorm(h, l, state(l), nullptr, 0.0);
+  };
+  // zero states; ||b^l|| = ||r^l(0)|| and b^{l+1} = -R r^l(0)
+  std::vector<double> bnorm(L);
+  w.x.zero(s);
+  for (int l = 0; l < L; ++l) {
+    bnorm[l] = check_finite(rnorm(l), "right-hand side");
+    if (l + 1 == L) break;
+    CoarseLevel& Cc = *h.coarse[l];
+    double* r = l == 0 ? w.xt.p : h.coarse[l - 1]->r.p;
+    if (l == 0) {
+      launch_fine_resid(f.view(), w.x.p, nullptr, 0.0, r, h.parts.p, s);
+    } else {
+      CoarseLevel& C = *h.coarse[l - 1];
+      launch_coarse_resid(C, alpha, C.x.p, nullptr, 0.0, C.b.p, r, h.parts.p, s);
+    }
+    launch_restrict(*h.trans[l], Cc, r, Cc.b.p, s);
+    launch_sub(Cc.nf + Cc.np, Cc.zeros.p, Cc.b.p, Cc.b.p, s);
+    Cc.x.zero(s);
+  }
+  st.r0 = bnorm[0];
+  int rc = SPFAS_NOT_CONVERGED;
+  for (int l = L - 1; l >= 0; --l) {
+    if (l + 1 < L) {   // initial guess P x^{l+1}
+      launch_fill(size(l), 0.0, state(l), s);
+      launch_prolong(*h.trans[l], *h.coarse[l], state(l + 1), state(l), s);
+    }
+    Opts o = o_in;
+    const double tol = std::max(o.rtol * bnorm[l], o.atol);
+    o.stop_tol = tol;
+    double r = check_finite(rnorm(l), "residual of the prolongated state");
+    int k = 0;
+    while (k < o.max_it && r > tol) {
+      const double r_new = l == 0 ? fine_smooth(h, o, r, st) : coarse_smooth(h, l, o, r, st);
+      check_finite(r_new, "residual after a smoothing step (divergence)");
+      ++k;
+      const bool stalled = l > 0 && !(r_new < r);   // a coarse level at its rounding level
+      r = r_new;
+      if (stalled) break;
+    }
+    if (level_steps) level_steps[l] = k;
+    if (trace_on()) std::fprintf(stderr, "[spfas] cascadic level %d: %d steps, |r| %.3e (tol %.3e)\n", l, k, r, tol);
+    if (l == 0) {
+      st.iterations = k;
+      st.r_final = r;
+      rc = r <= tol ? SPFAS_OK : SPFAS_NOT_CONVERGED;
+    }
+  }
+  return rc;
+}
+
 int run_solve(Hierarchy& h, const spfas_problem& prob, const spfas_solve_opts& so, double* p, double* sigma, bool dev,
-              SolveKind kind, spfas_stats& st) {
-  const bool newton = kind == SolveKind::NEWTON || (kind == SolveKind::FAS && so.smoother == SPFAS_NEWTON);
-  require(kind != SolveKind::FAS || so.smoother == SPFAS_NEWTON || so.smoother == SPFAS_PICARD,
+              SolveKind kind, spfas_stats& st, int32_t* level_steps) {
+  const bool multilevel = kind == SolveKind::FAS || kind == SolveKind::CASCADIC;
+  const bool newton = kind == SolveKind::NEWTON || (multilevel && so.smoother == SPFAS_NEWTON);
+  require(!multilevel || so.smoother == SPFAS_NEWTON || so.smoother == SPFAS_PICARD,
           "smoother must be SPFAS_NEWTON or SPFAS_PICARD");
+  require(kind != SolveKind::CASCADIC || so.x0_given == 0,
+          "the cascadic solve starts from zero on the coarsest level: x0_given must be 0");
   Opts o = make_opts(so, newton);
   h.set_problem(prob);
   load_state(h, p, sigma, dev, so.x0_given != 0);
   int rc;
-  if (kind == SolveKind::FAS && h.n_levels > 1)
+  if (kind == SolveKind::CASCADIC)
+    rc = run_cascadic(h, o, st, level_steps);
+  else if (kind == SolveKind::FAS && h.n_levels > 1)
     rc = run_fas(h, o, st);
   else
     rc = single_level(h, o, st);
