@@ -76,3 +76,15 @@ def test_cascadic_linear_problem():
     assert st["converged"] and st["level_steps"] == [1, 1, 1], st
     p_lin = linear_pressure(prob)
     assert np.linalg.norm(p - p_lin) <= 1e-8 * np.linalg.norm(p_lin)
+
+
+def test_cascadic_one_level_is_single_level_newton():
+    import paper_2005_01275_amd as pk
+    prob = small_problem((5, 3), seed=3, box=(2, 2), m=2, n_levels=1, src_scale=2.0)
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    o = opts(pk.SPFAS_NEWTON, prob, rtol=1e-10)
+    pc, sc, stc = H.cascadic_solve(prob, o)
+    pn, sn, stn = H.newton_solve(prob, o)
+    assert stc["converged"] and stc["level_steps"] == [stn["iterations"]], (stc, stn)
+    np.testing.assert_array_equal(pc, pn)
+    np.testing.assert_array_equal(sc, sn)
