@@ -62,7 +62,6 @@ __global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, 
                                                      double* __restrict__ trace, double* __restrict__ scratch,
                                                      ScratchA sa, int* __restrict__ bad) {
   __shared__ int flag;
-  __shared__ double red[2 * kBlock];
   double* Mu = scratch + (size_t)blockIdx.x * sa.total;
   double* Du = Mu + sa.mu;
   double* T = Du + sa.du;

@@ -50,6 +50,24 @@ def test_c2_fas_newton_meets_rtol(c2, inner):
     assert abs(s[ff][dirf].sum() - fs.f.sum()) <= 1e-6 * np.abs(fs.f).sum()
 
 
+def test_c2_cascadic_meets_rtol(c2):
+    """The nonlinear cascadic solve bench.py reports beside FAS-Newton, with
+    the same inner options: every level hands a state up and the fine state
+    meets the stopping rule under the oracle's residual."""
+    import paper_2005_01275_amd as pk
+    prob, H = c2
+    print("case c2 cascadic", flush=True)
+    o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=200,
+                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha, **BENCH_INNER)
+    p, s, st = H.cascadic_solve(prob, o)
+    assert st["converged"] and len(st["level_steps"]) == prob.n_levels, st
+    fs = FineSystem(prob)
+    ff = fs.fm.flux_face
+    rs, rp = fs.residual(s[ff], p)
+    rel = np.linalg.norm(np.concatenate([rs, rp])) / np.linalg.norm(fs.f)
+    assert rel <= 1.01e-8, rel
+
+
 def test_c2_aggregates_sampled(c2):
     """Sampled level-0 aggregates: the m = 3 smallest eigenvalues of each
     local Laplacian (static matrices, eq. local-eigenvalue-problem) against a
