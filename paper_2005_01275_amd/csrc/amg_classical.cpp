@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <numeric>
+#include <thread>
 
 namespace spfas {
 
@@ -88,6 +89,55 @@ std::vector<int> pmis(const Strength& S, int n, uint64_t seed) {
 }
 
 }  // namespace
+
+// Host threads for the row-parallel product construction (at most 16).
+static int host_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hc));
+}
+
+// f(t, lo, hi) on nth contiguous, ordered chunks of [0, n), one thread each.
+template <class F>
+static void parallel_chunks(int n, int nth, F&& f) {
+  std::vector<std::thread> th;
+  const int per = (n + nth - 1) / nth;
+  for (int t = 0; t < nth; ++t) {
+    const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    th.emplace_back([&f, t, lo, hi] { f(t, lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// Groups the products of one output row by column: columns ascending, each
+// column's products in generation order; start[c] ends column c's products.
+struct RowGrouper {
+  struct Item { int key, a, b; };
+  std::vector<Item> items, grouped;
+  std::vector<int> mark, slot, cols, start;
+  explicit RowGrouper(int ncols) : mark(ncols, -1), slot(ncols, 0) {}
+  void group(int tag) {
+    cols.clear();
+    for (const Item& it : items)
+      if (mark[it.key] != tag) { mark[it.key] = tag; cols.push_back(it.key); }
+    std::sort(cols.begin(), cols.end());
+    for (size_t c = 0; c < cols.size(); ++c) slot[cols[c]] = (int)c;
+    start.assign(cols.size() + 1, 0);
+    for (const Item& it : items) start[slot[it.key] + 1]++;
+    for (size_t c = 0; c < cols.size(); ++c) start[c + 1] += start[c];
+    grouped.resize(items.size());
+    for (const Item& it : items) grouped[start[slot[it.key]]++] = it;
+  }
+};
+
+// Per-chunk lists of the A P and P^T (A P) constructions.
+struct ApChunk {
+  std::vector<int> col, pidx, nprod, la, lp, rowlen;
+  std::vector<double> val;
+};
+struct RapChunk {
+  std::vector<int> col, nprod, r, q, dr, dq, rowlen, ndiag;
+  std::vector<double> val;
+};
 
 bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLevel& L) {
   const int n = A.n;
@@ -203,91 +253,122 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
 
   // Products of one output row are generated in a fixed order and grouped
   // by column: columns ascending, each column's products in generation order.
-  struct Item { int key, a, b; };
-  std::vector<Item> items, grouped;
-  std::vector<int> mark(nc, -1), slot(nc, 0), cols, start;
-  auto group_row = [&](int tag) {
-    cols.clear();
-    for (const Item& it : items)
-      if (mark[it.key] != tag) { mark[it.key] = tag; cols.push_back(it.key); }
-    std::sort(cols.begin(), cols.end());
-    for (size_t c = 0; c < cols.size(); ++c) slot[cols[c]] = (int)c;
-    start.assign(cols.size() + 1, 0);
-    for (const Item& it : items) start[slot[it.key] + 1]++;
-    for (size_t c = 0; c < cols.size(); ++c) start[c + 1] += start[c];
-    grouped.resize(items.size());
-    for (const Item& it : items) grouped[start[slot[it.key]]++] = it;
-    // start[c] is now the end of column c's products
-  };
-
-  // ---- A P: pattern, products, values (for the next level's setup)
+  // Rows are processed in contiguous chunks on host threads; every chunk
+  // fills lists of its own and the chunks are joined in row order, so the
+  // result does not depend on the number of threads.
+  const int nth = host_threads();
+  std::vector<ApChunk> apc(nth);
+  parallel_chunks(n, nth, [&](int t, int lo, int hi) {
+    ApChunk& ch = apc[t];
+    RowGrouper g(nc);
+    for (int i = lo; i < hi; ++i) {
+      g.items.clear();
+      for (int p = L.pptr[i]; p < L.pptr[i + 1]; ++p) g.items.push_back({L.pcol[p], dia_code(i), p});
+      for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
+        const int j = A.col[q];
+        for (int p = L.pptr[j]; p < L.pptr[j + 1]; ++p) g.items.push_back({L.pcol[p], off_code(q), p});
+      }
+      g.group(i);
+      int k = 0;
+      for (size_t c = 0; c < g.cols.size(); ++c) {
+        const int J = g.cols[c];
+        double v = 0.0;
+        const int k0 = k;
+        for (; k < g.start[c]; ++k) {
+          const int code = g.grouped[k].a;
+          v += ((code & 1) ? A.val[code >> 1] : A.diag[code >> 1]) * L.pval[g.grouped[k].b];
+          ch.la.push_back(code);
+          ch.lp.push_back(g.grouped[k].b);
+        }
+        int pidx = -1;
+        for (int p = L.pptr[i]; p < L.pptr[i + 1]; ++p)
+          if (L.pcol[p] == J) pidx = p;
+        ch.col.push_back(J);
+        ch.pidx.push_back(pidx);
+        ch.nprod.push_back(k - k0);
+        ch.val.push_back(v);
+      }
+      ch.rowlen.push_back((int)g.cols.size());
+    }
+  });
+  // ---- A P: pattern, products, values (joined in row order)
   L.apptr.assign(n + 1, 0);
   L.aplptr.assign(1, 0);
   std::vector<double> apv;
-  for (int i = 0; i < n; ++i) {
-    items.clear();
-    for (int p = L.pptr[i]; p < L.pptr[i + 1]; ++p) items.push_back({L.pcol[p], dia_code(i), p});
-    for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
-      const int j = A.col[q];
-      for (int p = L.pptr[j]; p < L.pptr[j + 1]; ++p) items.push_back({L.pcol[p], off_code(q), p});
+  {
+    int row = 0;
+    for (const ApChunk& ch : apc) {
+      for (int len : ch.rowlen) { L.apptr[row + 1] = L.apptr[row] + len; ++row; }
+      L.apcol.insert(L.apcol.end(), ch.col.begin(), ch.col.end());
+      L.appidx.insert(L.appidx.end(), ch.pidx.begin(), ch.pidx.end());
+      apv.insert(apv.end(), ch.val.begin(), ch.val.end());
+      L.apla.insert(L.apla.end(), ch.la.begin(), ch.la.end());
+      L.aplp.insert(L.aplp.end(), ch.lp.begin(), ch.lp.end());
+      for (int np : ch.nprod) L.aplptr.push_back(L.aplptr.back() + np);
     }
-    group_row(i);
-    int t = 0;
-    for (size_t c = 0; c < cols.size(); ++c) {
-      const int J = cols[c];
-      double v = 0.0;
-      for (; t < start[c]; ++t) {
-        const int code = grouped[t].a;
-        v += ((code & 1) ? A.val[code >> 1] : A.diag[code >> 1]) * L.pval[grouped[t].b];
-        L.apla.push_back(code);
-        L.aplp.push_back(grouped[t].b);
-      }
-      int pidx = -1;
-      for (int p = L.pptr[i]; p < L.pptr[i + 1]; ++p)
-        if (L.pcol[p] == J) pidx = p;
-      L.apcol.push_back(J);
-      L.appidx.push_back(pidx);
-      L.aplptr.push_back((int)L.apla.size());
-      apv.push_back(v);
-    }
-    L.apptr[i + 1] = (int)L.apcol.size();
+    apc.clear();
   }
 
   // ---- P^T (A P): coarse pattern, products (off-diagonal entries, then the diagonal), values
-  std::fill(mark.begin(), mark.end(), -1);
   HostCsr& C = L.C;
   C.n = nc;
   C.diag.assign(nc, 0.0);
   C.ptr.assign(nc + 1, 0);
+  std::vector<RapChunk> rpc(nth);
+  parallel_chunks(nc, nth, [&](int t, int lo, int hi) {
+    RapChunk& ch = rpc[t];
+    RowGrouper g(nc);
+    for (int I = lo; I < hi; ++I) {
+      g.items.clear();
+      for (int e = L.rptr[I]; e < L.rptr[I + 1]; ++e) {
+        const int i = L.rcol[e], p = L.rsrc[e];
+        for (int q = L.apptr[i]; q < L.apptr[i + 1]; ++q) g.items.push_back({L.apcol[q], p, q});
+      }
+      g.group(I);
+      int k = 0, noff = 0, ndg = 0;
+      for (size_t c = 0; c < g.cols.size(); ++c) {
+        const int J = g.cols[c];
+        const bool dg = J == I;
+        double v = 0.0;
+        const int k0 = k;
+        for (; k < g.start[c]; ++k) {
+          v += L.pval[g.grouped[k].a] * apv[g.grouped[k].b];
+          if (dg) { ch.dr.push_back(g.grouped[k].a); ch.dq.push_back(g.grouped[k].b); }
+          else { ch.r.push_back(g.grouped[k].a); ch.q.push_back(g.grouped[k].b); }
+        }
+        if (dg) {
+          C.diag[I] = v;   // rows are disjoint between chunks
+          ndg += k - k0;
+        } else {
+          ch.col.push_back(J);
+          ch.val.push_back(v);
+          ch.nprod.push_back(k - k0);
+          ++noff;
+        }
+      }
+      ch.rowlen.push_back(noff);
+      ch.ndiag.push_back(ndg);
+    }
+  });
   std::vector<int> dptr(nc + 1, 0), dr, dq;
   L.clptr.assign(1, 0);
-  for (int I = 0; I < nc; ++I) {
-    items.clear();
-    for (int e = L.rptr[I]; e < L.rptr[I + 1]; ++e) {
-      const int i = L.rcol[e], p = L.rsrc[e];
-      for (int q = L.apptr[i]; q < L.apptr[i + 1]; ++q) items.push_back({L.apcol[q], p, q});
-    }
-    group_row(I);
-    int t = 0;
-    for (size_t c = 0; c < cols.size(); ++c) {
-      const int J = cols[c];
-      const bool dg = J == I;
-      double v = 0.0;
-      for (; t < start[c]; ++t) {
-        v += L.pval[grouped[t].a] * apv[grouped[t].b];
-        if (dg) { dr.push_back(grouped[t].a); dq.push_back(grouped[t].b); }
-        else { L.clr.push_back(grouped[t].a); L.clq.push_back(grouped[t].b); }
+  {
+    int row = 0;
+    for (const RapChunk& ch : rpc) {
+      for (size_t t = 0; t < ch.rowlen.size(); ++t) {
+        C.ptr[row + 1] = C.ptr[row] + ch.rowlen[t];
+        dptr[row + 1] = dptr[row] + ch.ndiag[t];
+        ++row;
       }
-      if (dg) {
-        C.diag[I] = v;
-      } else {
-        C.col.push_back(J);
-        C.val.push_back(v);
-        L.clptr.push_back((int)L.clr.size());
-      }
+      C.col.insert(C.col.end(), ch.col.begin(), ch.col.end());
+      C.val.insert(C.val.end(), ch.val.begin(), ch.val.end());
+      L.clr.insert(L.clr.end(), ch.r.begin(), ch.r.end());
+      L.clq.insert(L.clq.end(), ch.q.begin(), ch.q.end());
+      for (int np : ch.nprod) L.clptr.push_back(L.clptr.back() + np);
+      dr.insert(dr.end(), ch.dr.begin(), ch.dr.end());
+      dq.insert(dq.end(), ch.dq.begin(), ch.dq.end());
     }
-    C.ptr[I + 1] = (int)C.col.size();
-    dptr[I + 1] = (int)dr.size();
+    rpc.clear();
   }
   const int base = (int)L.clr.size();
   for (int I = 0; I < nc; ++I) L.clptr.push_back(base + dptr[I + 1]);
