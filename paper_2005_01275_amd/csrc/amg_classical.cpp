@@ -152,88 +152,108 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
   if (nc == 0 || (long long)nc * 10 > (long long)n * 9) return false;
   L.nc = nc;
 
-  // ---- extended+i interpolation, truncated
+  // ---- extended+i interpolation, truncated (rows in contiguous chunks on
+  // host threads, joined in row order)
+  const int nth = host_threads();
+  struct PChunk {
+    std::vector<int> col, rowlen;
+    std::vector<double> val;
+  };
+  std::vector<PChunk> pch(nth);
+  parallel_chunks(n, nth, [&](int t, int lo, int hi) {
+    PChunk& out = pch[t];
+    std::vector<int> smark(n, -1), cmark(n, -1), cpos(n, 0);
+    std::vector<int> hat;          // C-hat_i
+    std::vector<double> w;         // accumulated numerators over C-hat_i
+    std::vector<std::pair<int, double>> row;
+    for (int i = lo; i < hi; ++i) {
+      const size_t len0 = out.col.size();
+      if (state[i] == 1) {
+        out.col.push_back(cidx[i]);
+        out.val.push_back(1.0);
+        out.rowlen.push_back(1);
+        continue;
+      }
+      hat.clear();
+      for (int q = S.ptr[i]; q < S.ptr[i + 1]; ++q) smark[S.col[q]] = i;
+      auto add_hat = [&](int j) {
+        if (cmark[j] != i) { cmark[j] = i; cpos[j] = (int)hat.size(); hat.push_back(j); }
+      };
+      for (int q = S.ptr[i]; q < S.ptr[i + 1]; ++q) {
+        const int k = S.col[q];
+        if (state[k] == 1) add_hat(k);
+        else
+          for (int qq = S.ptr[k]; qq < S.ptr[k + 1]; ++qq)
+            if (state[S.col[qq]] == 1) add_hat(S.col[qq]);
+      }
+      if (!hat.empty()) {
+        w.assign(hat.size(), 0.0);
+        double aii = A.diag[i];
+        for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
+          const int j = A.col[q];
+          const double a = A.val[q];
+          if (j == i) { aii += a; continue; }
+          if (cmark[j] == i) { w[cpos[j]] += a; continue; }
+          if (smark[j] != i) { aii += a; continue; }   // weak neighbour: lumped into the diagonal
+          // strong F neighbour k = j: distributed over C-hat_i and i with the
+          // entries of row k of sign opposite to its diagonal
+          const int k = j;
+          const double sk = A.diag[k];
+          auto bar = [&](double v) { return (v < 0.0) != (sk < 0.0) && v != 0.0 ? v : 0.0; };
+          double den = 0.0;
+          for (int qq = A.ptr[k]; qq < A.ptr[k + 1]; ++qq) {
+            const int l = A.col[qq];
+            if (l == i || cmark[l] == i) den += bar(A.val[qq]);
+          }
+          if (den == 0.0) { aii += a; continue; }
+          for (int qq = A.ptr[k]; qq < A.ptr[k + 1]; ++qq) {
+            const int l = A.col[qq];
+            const double b = bar(A.val[qq]);
+            if (b == 0.0) continue;
+            if (l == i) aii += a * b / den;
+            else if (cmark[l] == i) w[cpos[l]] += a * b / den;
+          }
+        }
+        row.clear();
+        if (aii != 0.0)
+          for (size_t t = 0; t < hat.size(); ++t)
+            if (w[t] != 0.0) row.emplace_back(cidx[hat[t]], -w[t] / aii);
+        // truncation
+        if (!row.empty()) {
+          double sum = 0.0, mx = 0.0;
+          for (auto& e : row) { sum += e.second; mx = std::max(mx, std::fabs(e.second)); }
+          std::vector<std::pair<int, double>> kept;
+          for (auto& e : row)
+            if (std::fabs(e.second) >= kTruncRel * mx) kept.push_back(e);
+          if ((int)kept.size() > kTruncMax) {
+            std::stable_sort(kept.begin(), kept.end(), [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
+              return std::fabs(a.second) > std::fabs(b.second);
+            });
+            kept.resize(kTruncMax);
+          }
+          double ks = 0.0;
+          for (auto& e : kept) ks += e.second;
+          const double sc = ks != 0.0 ? sum / ks : 1.0;
+          std::sort(kept.begin(), kept.end());
+          for (auto& e : kept) {
+            out.col.push_back(e.first);
+            out.val.push_back(e.second * sc);
+          }
+        }
+      }
+      out.rowlen.push_back((int)(out.col.size() - len0));
+    }
+  });
   L.pptr.assign(n + 1, 0);
-  std::vector<int> smark(n, -1), cmark(n, -1), cpos(n, 0);
-  std::vector<int> hat;          // C-hat_i
-  std::vector<double> w;         // accumulated numerators over C-hat_i
-  std::vector<std::pair<int, double>> row;
-  for (int i = 0; i < n; ++i) {
-    if (state[i] == 1) {
-      L.pcol.push_back(cidx[i]);
-      L.pval.push_back(1.0);
-      L.pptr[i + 1] = (int)L.pcol.size();
-      continue;
+  {
+    int r = 0;
+    for (const PChunk& ch : pch) {
+      for (int len : ch.rowlen) { L.pptr[r + 1] = L.pptr[r] + len; ++r; }
+      L.pcol.insert(L.pcol.end(), ch.col.begin(), ch.col.end());
+      L.pval.insert(L.pval.end(), ch.val.begin(), ch.val.end());
     }
-    hat.clear();
-    for (int q = S.ptr[i]; q < S.ptr[i + 1]; ++q) smark[S.col[q]] = i;
-    auto add_hat = [&](int j) {
-      if (cmark[j] != i) { cmark[j] = i; cpos[j] = (int)hat.size(); hat.push_back(j); }
-    };
-    for (int q = S.ptr[i]; q < S.ptr[i + 1]; ++q) {
-      const int k = S.col[q];
-      if (state[k] == 1) add_hat(k);
-      else
-        for (int qq = S.ptr[k]; qq < S.ptr[k + 1]; ++qq)
-          if (state[S.col[qq]] == 1) add_hat(S.col[qq]);
-    }
-    if (!hat.empty()) {
-      w.assign(hat.size(), 0.0);
-      double aii = A.diag[i];
-      for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) {
-        const int j = A.col[q];
-        const double a = A.val[q];
-        if (j == i) { aii += a; continue; }
-        if (cmark[j] == i) { w[cpos[j]] += a; continue; }
-        if (smark[j] != i) { aii += a; continue; }   // weak neighbour: lumped into the diagonal
-        // strong F neighbour k = j: distributed over C-hat_i and i with the
-        // entries of row k of sign opposite to its diagonal
-        const int k = j;
-        const double sk = A.diag[k];
-        auto bar = [&](double v) { return (v < 0.0) != (sk < 0.0) && v != 0.0 ? v : 0.0; };
-        double den = 0.0;
-        for (int qq = A.ptr[k]; qq < A.ptr[k + 1]; ++qq) {
-          const int l = A.col[qq];
-          if (l == i || cmark[l] == i) den += bar(A.val[qq]);
-        }
-        if (den == 0.0) { aii += a; continue; }
-        for (int qq = A.ptr[k]; qq < A.ptr[k + 1]; ++qq) {
-          const int l = A.col[qq];
-          const double b = bar(A.val[qq]);
-          if (b == 0.0) continue;
-          if (l == i) aii += a * b / den;
-          else if (cmark[l] == i) w[cpos[l]] += a * b / den;
-        }
-      }
-      row.clear();
-      if (aii != 0.0)
-        for (size_t t = 0; t < hat.size(); ++t)
-          if (w[t] != 0.0) row.emplace_back(cidx[hat[t]], -w[t] / aii);
-      // truncation
-      if (!row.empty()) {
-        double sum = 0.0, mx = 0.0;
-        for (auto& e : row) { sum += e.second; mx = std::max(mx, std::fabs(e.second)); }
-        std::vector<std::pair<int, double>> kept;
-        for (auto& e : row)
-          if (std::fabs(e.second) >= kTruncRel * mx) kept.push_back(e);
-        if ((int)kept.size() > kTruncMax) {
-          std::stable_sort(kept.begin(), kept.end(), [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
-            return std::fabs(a.second) > std::fabs(b.second);
-          });
-          kept.resize(kTruncMax);
-        }
-        double ks = 0.0;
-        for (auto& e : kept) ks += e.second;
-        const double sc = ks != 0.0 ? sum / ks : 1.0;
-        std::sort(kept.begin(), kept.end());
-        for (auto& e : kept) {
-          L.pcol.push_back(e.first);
-          L.pval.push_back(e.second * sc);
-        }
-      }
-    }
-    L.pptr[i + 1] = (int)L.pcol.size();
   }
+
 
   // ---- R = P^T
   L.rptr.assign(nc + 1, 0);
@@ -256,7 +276,6 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
   // Rows are processed in contiguous chunks on host threads; every chunk
   // fills lists of its own and the chunks are joined in row order, so the
   // result does not depend on the number of threads.
-  const int nth = host_threads();
   std::vector<ApChunk> apc(nth);
   parallel_chunks(n, nth, [&](int t, int lo, int hi) {
     ApChunk& ch = apc[t];
