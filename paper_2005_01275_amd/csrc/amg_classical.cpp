@@ -315,6 +315,14 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
   L.aplptr.assign(1, 0);
   std::vector<double> apv;
   {
+    size_t ne = 0, np = 0;
+    for (const ApChunk& ch : apc) { ne += ch.col.size(); np += ch.la.size(); }
+    L.apcol.reserve(ne);
+    L.appidx.reserve(ne);
+    apv.reserve(ne);
+    L.aplptr.reserve(ne + 1);
+    L.apla.reserve(np);
+    L.aplp.reserve(np);
     int row = 0;
     for (const ApChunk& ch : apc) {
       for (int len : ch.rowlen) { L.apptr[row + 1] = L.apptr[row] + len; ++row; }
@@ -372,6 +380,15 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
   std::vector<int> dptr(nc + 1, 0), dr, dq;
   L.clptr.assign(1, 0);
   {
+    size_t ne = 0, np = 0, nd = 0;
+    for (const RapChunk& ch : rpc) { ne += ch.col.size(); np += ch.r.size(); nd += ch.dr.size(); }
+    C.col.reserve(ne);
+    C.val.reserve(ne);
+    L.clptr.reserve(ne + nc + 1);
+    L.clr.reserve(np + nd);
+    L.clq.reserve(np + nd);
+    dr.reserve(nd);
+    dq.reserve(nd);
     int row = 0;
     for (const RapChunk& ch : rpc) {
       for (size_t t = 0; t < ch.rowlen.size(); ++t) {
