@@ -21,7 +21,7 @@ namespace spfas {
 __global__ void __launch_bounds__(kBlock) k_axpy(int64_t n, double a, const double* __restrict__ x,
                                                  double* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    y[i] += a * x[i];
+    y[i] = fma(a, x[i], y[i]);   // the rounding of the trial points x + s dx in the residual kernels
 }
 
 __global__ void __launch_bounds__(kBlock) k_neu_flux(int64_t nn, const double* __restrict__ area,
@@ -491,12 +491,16 @@ static void coarsest_solve(Hierarchy& h, int l, const Opts& o, spfas_stats& st) 
 // coarse[l-1]->x; its right-hand side in coarse[l-1]->b (level 0 uses
 // b^0 = -[g; f]).  Returns after pre-smoothing on level 0 when the fine
 // residual already meets stop_tol.
-static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, double stop_tol, bool& stopped) {
+// r_in >= 0: the residual norm of the level's state on entry (not
+// recomputed).  Returns the residual norm of the state on return (NaN on
+// the coarsest level, which does not track it).
+static double nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, double stop_tol, bool& stopped,
+                           double r_in = -1.0) {
   hipStream_t s = h.stream;
   const int L = h.n_levels;
   if (l == L - 1) {
     coarsest_solve(h, l, o, st);
-    return;
+    return std::nan("");
   }
   FineWork& w = h.fw;
   FineDev& f = h.fine;
@@ -508,11 +512,11 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
   const int64_t nfl = l == 0 ? f.nf : h.coarse[l - 1]->nf;
   const int64_t nl = l == 0 ? f.nf + f.n : h.coarse[l - 1]->nf + h.coarse[l - 1]->np;
   // pre-smoothing
-  double r_x = l == 0 ? fine_rnorm(h, x, nullptr, 0.0) : coarse_rnorm(h, l, x, nullptr, 0.0);
+  double r_x = r_in >= 0.0 ? r_in : l == 0 ? fine_rnorm(h, x, nullptr, 0.0) : coarse_rnorm(h, l, x, nullptr, 0.0);
   double r_s = l == 0 ? fine_smooth(h, o, r_x, st) : coarse_smooth(h, l, o, r_x, st);
   if (l == 0 && r_s <= stop_tol) {
     stopped = true;
-    return;
+    return r_s;
   }
   // residual, projection and coarse right-hand side b^{l+1} = A^{l+1}(Q x) - R r^l
   if (l == 0) {
@@ -546,10 +550,7 @@ static void nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, do
   if (step > 0.0) launch_axpy(nl, step, dx, x, s);
   (void)nfl;
   // post-smoothing
-  if (l == 0)
-    fine_smooth(h, o, r_new, st);
-  else
-    coarse_smooth(h, l, o, r_new, st);
+  return l == 0 ? fine_smooth(h, o, r_new, st) : coarse_smooth(h, l, o, r_new, st);
 }
 
 int run_fas(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
@@ -565,9 +566,10 @@ int run_fas(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
     if (it >= o.max_it) break;
     bool stopped = false;
     const double t0 = trace_on() ? trace_clock(h.stream) : 0.0;
-    nonlinear_mg(h, 0, o, st, tol, stopped);
+    // the V-cycle starts from the norm of the last one and returns that of
+    // its final state (the norm Alg. 1 or the smoother evaluated there)
+    r = check_finite(nonlinear_mg(h, 0, o, st, tol, stopped, r), "residual after a V-cycle (divergence)");
     st.stopped_after_presmooth = stopped ? 1 : 0;
-    r = check_finite(fine_rnorm(h, h.fw.x.p, nullptr, 0.0), "residual after a V-cycle (divergence)");
     if (trace_on())
       std::fprintf(stderr, "[spfas] V-cycle %d: |r| %.3e (rel %.3e)  %.2f ms\n", it + 1, r, r / st.r0,
                    trace_clock(h.stream) - t0);
