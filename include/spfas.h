@@ -225,7 +225,8 @@ int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts
  * r^{l+1}(y) = A^{l+1}(y) - [A^{l+1}(Q x) - R r^l(x)] (eq.
  * coarse_level_residual) built from the coarse local matrices without
  * visiting the fine level, and at most coarsest_max_steps smoothing steps on
- * the coarsest level.
+ * the coarsest level (fewer when its residual falls to rtol times its value
+ * on entry, or to atol, or after a step Alg. 1 rejected).
  *   p      [n_cells]  in: initial guess if x0_given; out: pressure
  *   sigma  [n_faces]  in: initial guess if x0_given (Neumann entries
  *                     ignored); out: flux of every face, -|eps| g_N on
@@ -256,8 +257,8 @@ int spfas_newton_solve(spfas_hierarchy* h, const spfas_problem* prob, const spfa
  * starts from the prolongated (P) solution of the level below and is
  * smoothed until it converges, up to level 0.  "Converges" on level l means
  * ||r^l|| <= max(rtol ||b^l||, atol), with at most max_it smoothing steps per
- * level; a coarse level also stops after a step that did not lower its
- * residual, and hands its state up either way.
+ * level; a level also stops after a step that Alg. 1 rejected (state
+ * unchanged), and hands its state up either way.
  * p, sigma: as spfas_fas_solve, outputs only; opts->x0_given must be 0
  * (ERR_INVALID otherwise).  level_steps: host array of n_levels int32, the
  * smoothing steps taken on each level (finest first), or NULL.

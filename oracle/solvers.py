@@ -13,8 +13,11 @@
                        b^{l+1} = A^{l+1}(Q x) - R(A^l(x) - b^l) (eq.
                        coarse_level_residual); the coarsest level takes at
                        most 10 smoothing steps, stopping early on convergence
-                       (Section 4) or when a step no longer lowers its
-                       residual.
+                       (Section 4).  A step that Alg. 1 rejected (s = 0: the
+                       chosen trial was not finite) leaves the state as it
+                       was, so every further step would repeat it; the loop
+                       stops there too.  A step that Alg. 1 accepted while
+                       it raised the residual does not stop the loop.
 * ``cascadic_solve`` -- nonlinear cascadic multigrid (Section 4.2, Table 4):
                        the right-hand side restricted level by level
                        (b^{l+1} = R b^l), the coarsest problem solved from
@@ -24,9 +27,9 @@
                        each level stops on the same rule as the fine level,
                        relative to the residual of the zero state
                        (||r^l(0)|| = ||b^l||), and takes at most max_it steps;
-                       a coarse level also stops after a step that did not
-                       lower its residual (its rounding level, as on the
-                       coarsest level of the V-cycle).
+                       like the coarsest level of the V-cycle, a level also
+                       stops after a step that Alg. 1 rejected (s = 0, state
+                       unchanged).
 * ``fas_solve`` / ``single_level_solve`` -- outer loops with the stopping rule
   of Section 4: relative residual below rtol or absolute below atol (2-norm
   of the whole residual vector; relative to the residual of the initial
@@ -113,10 +116,12 @@ def cap_value(alpha: float, c: float) -> float:
     return math.log(c) / alpha
 
 
-def smooth(level, x, b, alpha, opts: Opts, stats: Stats = None):
+def smooth_step(level, x, b, alpha, opts: Opts, stats: Stats = None):
     """One Picard or Newton step on a level (Section 3.3).  Picard solves
     [M(Pi~p) D^T; D 0] x_P = b and steps along x_P - x, which is the same as
-    solving that matrix against -r(x); Newton solves J dx = -r(x)."""
+    solving that matrix against -r(x); Newton solves J dx = -r(x).
+    Returns (x_new, s): s is the step length Alg. 1 chose, 0 when it
+    rejected the step (x_new is then x)."""
     r = residual(level, x, b, alpha)
     J = jacobian(level, x, alpha, opts.newton)
     dx = spla.spsolve(J, -r)
@@ -126,23 +131,28 @@ def smooth(level, x, b, alpha, opts: Opts, stats: Stats = None):
     xn, s, n = backtracking(rn, x, dx, opts.bt_nmax, opts.bt_theta, r_x=norm(r))
     if stats is not None:
         stats.bt_steps += n
-    return xn
+    return xn, s
+
+
+def smooth(level, x, b, alpha, opts: Opts, stats: Stats = None):
+    """``smooth_step`` without the step length."""
+    return smooth_step(level, x, b, alpha, opts, stats)[0]
 
 
 def coarsest_solve(level, x, b, alpha, opts: Opts, stats=None):
-    """At most ``coarsest_max`` smoothing steps; stops when the level
-    residual meets rtol (relative to its entry value) or atol, or when a step
-    did not lower it (rounding level reached, or Alg. 1 rejected the step)."""
+    """Section 4: at most ``coarsest_max`` smoothing steps, fewer when the
+    level residual meets rtol (relative to its value on entry) or atol.
+    The loop also ends after a step Alg. 1 rejected (s = 0): the state is
+    then unchanged and the next step would be the same one."""
     r = norm(residual(level, x, b, alpha))
     tol = max(opts.rtol * r, opts.atol)
     for _ in range(opts.coarsest_max):
         if r <= tol:
             break
-        x = smooth(level, x, b, alpha, opts, stats)
-        r_new = norm(residual(level, x, b, alpha))
-        if not r_new < r:
+        x, s = smooth_step(level, x, b, alpha, opts, stats)
+        if s == 0.0:
             break
-        r = r_new
+        r = norm(residual(level, x, b, alpha))
     return x
 
 
@@ -245,13 +255,11 @@ def cascadic_solve(h, opts: Opts):
         for _ in range(opts.max_it):
             if r <= tol:
                 break
-            x = smooth(lev, x, rhs[l], a, opts, st)
+            x, s = smooth_step(lev, x, rhs[l], a, opts, st)
             st.level_steps[l] += 1
-            r_new = norm(residual(lev, x, rhs[l], a))
-            stalled = l > 0 and not r_new < r
-            r = r_new
-            if not math.isfinite(r) or stalled:
+            if s == 0.0:
                 break
+            r = norm(residual(lev, x, rhs[l], a))
         st.level_converged[l] = r <= tol
         st.level_x[l] = x.copy()
     st.r_final = r

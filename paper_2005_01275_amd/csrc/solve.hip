@@ -267,7 +267,8 @@ static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double
 // One Picard or Newton step on level 0 (Section 3.3): solve the linearised
 // system (flux block eliminated exactly, M is diagonal on level 0), cap,
 // Alg. 1.  `r_x` = ||r(x)|| on entry; returns ||r|| after the step.
-static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& st) {
+static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& st, bool* moved = nullptr) {
+  if (moved) *moved = false;
   FineWork& w = h.fw;
   FineDev& f = h.fine;
   hipStream_t s = h.stream;
@@ -307,6 +308,7 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   const double step = backtrack([&](double sl) { return fine_rnorm(h, w.x.p, w.dx.p, sl * scale); }, r_x,
                                 o.bt_nmax, o.bt_theta, r_new, st.bt_halvings, batch);
   if (step > 0.0) launch_axpy(nf + n, step * scale, w.dx.p, w.x.p, s);
+  if (moved) *moved = step > 0.0;
   st.smoothing_steps++;
   if (trace_on())
     std::fprintf(stderr, "[spfas] level 0 %s: krylov %d  |r| %.3e -> %.3e  cap %.3g  step %.4g  %.2f ms %s\n",
@@ -427,7 +429,8 @@ static void coarse_rnorm_trials(Hierarchy& h, int l, const double* x, const doub
 // One Picard or Newton step on coarse level l (Section 3.3) with the linear
 // system solved by algebraic hybridisation (Section 3.4), the cap on the
 // aggregate-average pressure change and Alg. 1.
-static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfas_stats& st) {
+static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfas_stats& st, bool* moved = nullptr) {
+  if (moved) *moved = false;
   CoarseLevel& C = *h.coarse[l - 1];
   hipStream_t s = h.stream;
   const double alpha = h.fine.alpha;
@@ -465,6 +468,7 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   const double step = backtrack([&](double sl) { return coarse_rnorm(h, l, C.x.p, C.dx.p, sl * scale); }, r_x,
                                 o.bt_nmax, o.bt_theta, r_new, st.bt_halvings, batch);
   if (step > 0.0) launch_axpy(C.nf + C.np, step * scale, C.dx.p, C.x.p, s);
+  if (moved) *moved = step > 0.0;
   st.smoothing_steps++;
   if (trace_on())
     std::fprintf(stderr, "[spfas] level %d %s: multipliers %d (AMG levels %d, dense %d) krylov %d  |r| %.3e -> "
@@ -473,17 +477,19 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   return r_new;
 }
 
-// Coarsest level: at most coarsest_max smoothing steps, stopping when the
-// level residual meets rtol (relative to its entry value) or atol, or when a
-// step did not lower it (rounding level reached, or the step was rejected).
+// Coarsest level (Section 4): at most coarsest_max smoothing steps, fewer
+// when the level residual meets rtol (relative to its value on entry) or
+// atol.  A step Alg. 1 rejected (or whose linear solve was not finite)
+// leaves the state unchanged, so the next one would repeat it: the loop ends
+// there.  A step Alg. 1 accepted while the residual rose does not end it.
 static void coarsest_solve(Hierarchy& h, int l, const Opts& o, spfas_stats& st) {
   double r = coarse_rnorm(h, l, h.coarse[l - 1]->x.p, nullptr, 0.0);
   const double tol = std::max(o.rtol * r, o.atol);
   for (int i = 0; i < o.coarsest_max; ++i) {
     if (r <= tol) break;
-    const double r_new = coarse_smooth(h, l, o, r, st);
-    if (!(r_new < r)) break;
-    r = r_new;
+    bool moved = false;
+    r = coarse_smooth(h, l, o, r, st, &moved);
+    if (!moved) break;
   }
 }
 
@@ -585,8 +591,9 @@ int run_fas(Hierarchy& h, const Opts& o_in, spfas_stats& st) {
 // every level, so r^l(0) = -b^l).  The coarsest problem is solved from zero;
 // each finer level starts from the prolongated solution of the level below
 // and takes smoothing steps until ||r^l|| <= max(rtol ||b^l||, atol) or
-// max_it steps; a coarse level also stops after a step that did not lower
-// its residual.  The return code reports the fine level's test.
+// max_it steps; like the coarsest level of the V-cycle, a level also stops
+// after a rejected step (state unchanged).  The return code reports the
+// fine level's test.
 static int run_cascadic(Hierarchy& h, const Opts& o_in, spfas_stats& st, int32_t* level_steps) {
   prec_reset(h);
   hipStream_t s = h.stream;
@@ -632,12 +639,11 @@ static int run_cascadic(Hierarchy& h, const Opts& o_in, spfas_stats& st, int32_t
     double r = check_finite(rnorm(l), "residual of the prolongated state");
     int k = 0;
     while (k < o.max_it && r > tol) {
-      const double r_new = l == 0 ? fine_smooth(h, o, r, st) : coarse_smooth(h, l, o, r, st);
-      check_finite(r_new, "residual after a smoothing step (divergence)");
+      bool moved = false;
+      r = l == 0 ? fine_smooth(h, o, r, st, &moved) : coarse_smooth(h, l, o, r, st, &moved);
+      check_finite(r, "residual after a smoothing step (divergence)");
       ++k;
-      const bool stalled = l > 0 && !(r_new < r);   // a coarse level at its rounding level
-      r = r_new;
-      if (stalled) break;
+      if (!moved) break;
     }
     if (level_steps) level_steps[l] = k;
     if (trace_on()) std::fprintf(stderr, "[spfas] cascadic level %d: %d steps, |r| %.3e (tol %.3e)\n", l, k, r, tol);
