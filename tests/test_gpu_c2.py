@@ -50,22 +50,45 @@ def test_c2_fas_newton_meets_rtol(c2, inner):
     assert abs(s[ff][dirf].sum() - fs.f.sum()) <= 1e-6 * np.abs(fs.f).sum()
 
 
+# the cascadic solve needs every coarse level solved to its own tolerance
+# (Section 4.2), which the FAS coarse options (1e-2, at most 10 Krylov
+# iterations) do not reach on level 2: the benchmark runs it with coarse
+# linear solves to 1e-6 and no coarse iteration limit
+CASCADIC_INNER = dict(BENCH_INNER, lin_rtol_coarse=1e-6, lin_max_it_coarse=0)
+
+
 def test_c2_cascadic_meets_rtol(c2):
-    """The nonlinear cascadic solve bench.py reports beside FAS-Newton, with
-    the same inner options: every level hands a state up and the fine state
-    meets the stopping rule under the oracle's residual."""
+    """The nonlinear cascadic solve bench.py reports beside FAS-Newton: every
+    level converges to its own tolerance and the fine state meets the
+    stopping rule under the oracle's residual."""
     import paper_2005_01275_amd as pk
     prob, H = c2
     print("case c2 cascadic", flush=True)
     o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=200,
-                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha, **BENCH_INNER)
+                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha, **CASCADIC_INNER)
     p, s, st = H.cascadic_solve(prob, o)
     assert st["converged"] and len(st["level_steps"]) == prob.n_levels, st
+    assert max(st["level_steps"]) < 200, st
     fs = FineSystem(prob)
     ff = fs.fm.flux_face
     rs, rp = fs.residual(s[ff], p)
     rel = np.linalg.norm(np.concatenate([rs, rp])) / np.linalg.norm(fs.f)
     assert rel <= 1.01e-8, rel
+
+
+def test_c2_aggregation_bit_exact(c2):
+    """The device-built hierarchy's level-0 aggregation and renumbering equal
+    the oracle's box rule on the lattice recovered from the centroids."""
+    from oracle.fv import lattice_from_centroids
+    from oracle.coarsen import box_aggregate
+    prob, H = c2
+    shape, index = lattice_from_centroids(prob.mesh.cell_centroid)
+    agg, cshape = box_aggregate(shape, index, prob.box)
+    assert cshape == (15, 55, 21)
+    np.testing.assert_array_equal(H.aggregation(0), agg)
+    c, _ = H.permutation(0)
+    # cells contiguous per aggregate, ascending id inside each one
+    np.testing.assert_array_equal(c, np.lexsort((np.arange(agg.size), agg)))
 
 
 def test_c2_aggregates_sampled(c2):

@@ -10,6 +10,7 @@ from problems import small_problem, c1_problem
 from oracle.coarsen import build_hierarchy
 from oracle.fv import full_flux
 from oracle.solvers import Opts, result_solve, cascadic_solve, cap_value
+from parity_util import assert_elementwise
 
 pytestmark = pytest.mark.gpu
 
@@ -49,9 +50,8 @@ def test_cascadic_reaches_the_root(kw):
         assert st["converged"], (name, st)
         assert len(st["level_steps"]) == prob.n_levels and min(st["level_steps"]) >= 0, st
         assert st["iterations"] == st["level_steps"][0], st
-        ep = np.linalg.norm(p - p_star) / np.linalg.norm(p_star)
-        es = np.linalg.norm(s - s_star) / np.linalg.norm(s_star)
-        assert ep <= 1e-10 and es <= 1e-10, (name, ep, es, st)
+        assert_elementwise(p, p_star, 1e-10, f"cascadic {name} p")
+        assert_elementwise(s, s_star, 1e-10, f"cascadic {name} sigma")
 
 
 @pytest.mark.parametrize("kw", CASES[:3])
@@ -75,7 +75,7 @@ def test_cascadic_linear_problem():
     p, s, st = H.cascadic_solve(prob, opts(pk.SPFAS_NEWTON, prob, rtol=1e-10))
     assert st["converged"] and st["level_steps"] == [1, 1, 1], st
     p_lin = linear_pressure(prob)
-    assert np.linalg.norm(p - p_lin) <= 1e-8 * np.linalg.norm(p_lin)
+    assert_elementwise(p, p_lin, 1e-10, "cascadic linear p")
 
 
 def test_cascadic_one_level_is_single_level_newton():

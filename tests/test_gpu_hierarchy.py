@@ -1,7 +1,9 @@
 """Hierarchy built by the HIP setup kernels against the oracle (GPU):
 spectra of the local Laplacians, P_A, P_sigma, Q_sigma, the static coarse
 local matrices M^{l+1}_A and D^{l+1}_A (Prop. 1) and the projector weights
-(Appendix B), in canonical order."""
+(Appendix B), in canonical order.  Eigenvalues agree to 1e-12 of each
+aggregate's largest eigenvalue, the other operators element by element to
+1e-10 of their largest entry."""
 import numpy as np
 import pytest
 
@@ -47,22 +49,22 @@ def test_hierarchy_parity(kw):
         lam = np.concatenate([ad.lam[:m] for ad, m in zip(tr.aggs, ms)])
         g = H.level_operator(l, N.SPFAS_OP_EIGVALS, lam.size)
         for ad, m, seg in zip(tr.aggs, ms, np.split(g, np.cumsum(ms)[:-1])):
-            np.testing.assert_allclose(seg, ad.lam[:m], atol=1e-11 * max(1.0, abs(ad.lam[-1])))
+            np.testing.assert_allclose(seg, ad.lam[:m], rtol=0.0, atol=1e-12 * max(1e-300, abs(ad.lam[-1])))
         P = np.concatenate([ad.P.ravel() for ad in tr.aggs])
         gP = H.level_operator(l, N.SPFAS_OP_PP, P.size)
-        assert rel(gP, P) < 1e-9, rel(gP, P)
+        assert rel(gP, P) <= 1e-10, rel(gP, P)
         Ps = tr.P_sig.toarray()
         gPs = H.level_operator(l, N.SPFAS_OP_PSIGMA, Ps.size).reshape(Ps.shape)
-        assert rel(gPs, Ps) < 1e-9, rel(gPs, Ps)
+        assert rel(gPs, Ps) <= 1e-10, rel(gPs, Ps)
         Qs = tr.Q_sig.toarray()
         gQs = H.level_operator(l, N.SPFAS_OP_QSIGMA, Qs.size).reshape(Qs.shape)
-        assert rel(gQs, Qs) < 1e-9, rel(gQs, Qs)
+        assert rel(gQs, Qs) <= 1e-10, rel(gQs, Qs)
         M = np.concatenate([m.ravel() for m in clev.M_loc])
         gM = H.level_operator(l, N.SPFAS_OP_MLOC, M.size)
-        assert rel(gM, M) < 1e-9, rel(gM, M)
+        assert rel(gM, M) <= 1e-10, rel(gM, M)
         D = np.concatenate([d.ravel() for d in clev.D_loc])
         gD = H.level_operator(l, N.SPFAS_OP_DLOC, D.size)
-        assert rel(gD, D) < 1e-9, rel(gD, D)
+        assert rel(gD, D) <= 1e-10, rel(gD, D)
         w = np.concatenate(clev.w)
         gw = H.level_operator(l, N.SPFAS_OP_W, w.size)
-        assert rel(gw, w) < 1e-11, rel(gw, w)
+        assert rel(gw, w) <= 1e-11, rel(gw, w)
