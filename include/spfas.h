@@ -279,6 +279,26 @@ int spfas_cascadic_solve(spfas_hierarchy* h, const spfas_problem* prob, const sp
 int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const double* p,
                         const double* sigma, double* r_p, double* r_sigma, int32_t mem, void* stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * fine-level residual of spfas_eval_residual, on DEVICE arrays only
+ * (prob->mem must be SPFAS_MEM_DEVICE; p, sigma, r_p, r_sigma are device
+ * pointers in input order, as in spfas_eval_residual with mem =
+ * SPFAS_MEM_DEVICE), computed with no hipMalloc, hipFree or other allocating
+ * call.  The state and the residual in internal order are staged in a
+ * static device array of 96 MiB that the library holds on each device it
+ * runs on until the process ends; the level-0 problem may have at most
+ * 6,291,456 unknowns (flux + cells), larger ones are rejected with
+ * ERR_INVALID before any work.  The current device must be the one the
+ * hierarchy was built on (ERR_INVALID otherwise).  All calls on one GPU
+ * share that array: calls that overlap in time on one GPU (on any stream or
+ * thread, any hierarchy) race and must not be made.  Returns after the work
+ * has completed.
+ */
+int spfas_eval_residual_noalloc(spfas_hierarchy* h, const spfas_problem* prob, const double* p,
+                                const double* sigma, double* r_p, double* r_sigma, void* stream);
+
 /* ------------------------------------------------------------------ parity hooks
  * Read-only views of the hierarchy used to compare it with an independent
  * implementation.  "Canonical order" on level 0 is the input order of

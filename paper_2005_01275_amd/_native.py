@@ -16,7 +16,8 @@ SPFAS_NEWTON, SPFAS_PICARD = 0, 1
 SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SPFAS_OP_W, SPFAS_OP_QSIGMA = range(7)
 
 EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solve", "spfas_cascadic_solve",
-            "spfas_picard_solve", "spfas_newton_solve", "spfas_eval_residual", "spfas_level_sizes",
+            "spfas_picard_solve", "spfas_newton_solve", "spfas_eval_residual", "spfas_eval_residual_noalloc",
+            "spfas_level_sizes",
             "spfas_get_aggregation",
             "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
             "spfas_version", "spfas_profile_enable", "spfas_profile_read"]
@@ -98,6 +99,8 @@ def lib():
     L.spfas_cascadic_solve.restype = C.c_int
     L.spfas_eval_residual.argtypes = [vp, C.POINTER(spfas_problem), vp, vp, vp, vp, C.c_int32, vp]
     L.spfas_eval_residual.restype = C.c_int
+    L.spfas_eval_residual_noalloc.argtypes = [vp, C.POINTER(spfas_problem), vp, vp, vp, vp, vp]
+    L.spfas_eval_residual_noalloc.restype = C.c_int
     L.spfas_level_sizes.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]
     L.spfas_level_sizes.restype = C.c_int

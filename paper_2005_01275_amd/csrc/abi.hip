@@ -105,6 +105,24 @@ int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const dou
   });
 }
 
+int spfas_eval_residual_noalloc(spfas_hierarchy* h, const spfas_problem* prob, const double* p,
+                                const double* sigma, double* r_p, double* r_sigma, void* stream) {
+  return guarded([&] {
+    need_device(h);
+    require(prob && p && sigma && r_p && r_sigma, "NULL argument");
+    require(prob->mem == SPFAS_MEM_DEVICE, "spfas_eval_residual_noalloc needs the problem data in device memory");
+    const int64_t nu = h->h.fine.nf + h->h.fine.n;
+    if ((size_t)nu > noalloc_max_unknowns())
+      fail(SPFAS_ERR_INVALID, "spfas_eval_residual_noalloc: " + std::to_string(nu) +
+                                  " level-0 unknowns exceed the scratch capacity of " +
+                                  std::to_string(noalloc_max_unknowns()));
+    h->h.stream = (hipStream_t)stream;
+    h->h.set_problem(*prob);
+    h->h.eval_residual_noalloc(p, sigma, r_p, r_sigma);
+    return SPFAS_OK;
+  });
+}
+
 static int solve_common(spfas_hierarchy* h, const spfas_problem* prob, const spfas_solve_opts* opts, double* p,
                         double* sigma, int32_t state_mem, spfas_stats* stats, void* stream, SolveKind kind,
                         int32_t* level_steps = nullptr) {

@@ -93,6 +93,7 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   n_levels = o.n_levels;
   m = o.m;
   host_only = o.host_only != 0;
+  if (!host_only) HIPCHECK(hipGetDevice(&device));
   // ---------------- level-0 canonical topology
   topo.clear();
   topo.reserve(n_levels);   // references into topo stay valid below

@@ -53,6 +53,7 @@ struct FineWork {
 
 struct Hierarchy {
   hipStream_t stream = nullptr;
+  int device = -1;                        // device current at setup
   bool host_only = false;
   int dim = 0;
   int64_t n_cells_in = 0, n_faces_in = 0;
@@ -80,6 +81,9 @@ struct Hierarchy {
   void set_problem(const spfas_problem& prob);
   // fine residual in input order
   void eval_residual(const double* p, const double* sig, double* rp, double* rs, bool dev);
+  // the same on device arrays, staging through a static device array
+  // instead of allocating (noalloc.hip)
+  void eval_residual_noalloc(const double* p, const double* sig, double* rp, double* rs);
   // wait for the stream, then the sum (max) of the n partials at dpin, in
   // index order
   double host_sum(int n);
@@ -87,5 +91,8 @@ struct Hierarchy {
   // k sums of n consecutive partials each (one wait)
   void host_sums(int n, int k, double* out);
 };
+
+// capacity of eval_residual_noalloc in level-0 unknowns (flux + cells)
+size_t noalloc_max_unknowns();
 
 }  // namespace spfas
