@@ -90,22 +90,64 @@ typedef struct {
 } spfas_mesh;
 
 /*
+ * Device memory of a hierarchy.  When given, every device buffer the
+ * hierarchy allocates (at setup and in later calls on the handle) comes from
+ * alloc(bytes, stream, ctx) and is returned with free(ptr, bytes, stream,
+ * ctx), where stream is the stream of the call that allocates; alloc returns
+ * NULL on failure (the call then fails with ERR_OOM).  The callbacks may be
+ * called from the thread that calls the library only, and must stay valid
+ * until spfas_destroy returns.  Lets a framework's caching allocator (e.g.
+ * PyTorch's) own the memory.  NULL allocator: hipMalloc / hipFree.
+ */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} spfas_allocator;
+
+/* How the cells of each level are grouped into aggregates (Section 3.1:
+ * connected, non-overlapping aggregates; the paper partitions with METIS). */
+typedef enum {
+  SPFAS_AGG_BOX = 0,     /* boxes of box[] cells on the level lattice (Cartesian meshes) */
+  SPFAS_AGG_USER = 1,    /* given by the caller for every coarsened level  */
+  SPFAS_AGG_GREEDY = 2   /* greedy graph growth of about greedy_size cells   */
+} spfas_agg_kind;
+
+/*
  * Coarsening options (Section 3.1, Appendix A).
  *   n_levels  number of levels including the fine one (>= 1)
- *   box       aggregate edge per axis on each level's lattice; a remainder
- *             block with fewer than box/2 cells merges into its neighbour
+ *   box       BOX: aggregate edge per axis on each level's lattice; a
+ *             remainder block with fewer than box/2 cells merges into its
+ *             neighbour
  *   m         local eigenvectors kept per aggregate (m_A, uniform; clamped
  *             to the number of pressure unknowns of the aggregate)
  *   host_only nonzero: build only the host-side integer structure
  *             (aggregates and renumbering) without touching the GPU; only
  *             spfas_get_aggregation / spfas_get_permutation /
  *             spfas_level_sizes / spfas_destroy accept such a handle.
+ *   agg_kind  spfas_agg_kind
+ *   user_agg  USER: host array of the aggregate id of every cell of levels
+ *             0 .. n_levels-2, concatenated (level l has as many cells as
+ *             level l-1 has aggregates; level 0 is the mesh); ids of a level
+ *             run over 0 .. n_agg-1, each used, each aggregate connected
+ *             through the level's interior faces (ERR_INVALID otherwise)
+ *   user_agg_len  number of entries of user_agg
+ *   greedy_size   GREEDY: target aggregate size in cells of each level: seeds
+ *             taken in ascending cell id grow breadth-first through
+ *             neighbours in ascending id up to greedy_size cells; then every
+ *             aggregate below greedy_size/2 cells, in ascending id, joins the
+ *             neighbouring aggregate it shares the most interior faces with
+ *             (ties: lower id); ids are compacted in ascending order
  */
 typedef struct {
   int32_t n_levels;
   int32_t box[3];
   int32_t m;
   int32_t host_only;
+  int32_t agg_kind;
+  const int32_t* user_agg;
+  int64_t user_agg_len;
+  int32_t greedy_size;
 } spfas_coarsen_opts;
 
 /*
@@ -206,17 +248,23 @@ void spfas_default_solve_opts(spfas_solve_opts* o);
 /*
  * Builds the multilevel hierarchy (Section 3.1, Appendix A; Prop. 1 for the
  * static coarse local matrices; Appendix B for the projector weights):
- * half-transmissibilities, box aggregation and renumbering on the host,
- * then batched on the device the local spectral problems, PV traces, trace
+ * half-transmissibilities, aggregation and renumbering on the host, then
+ * batched on the device the local spectral problems, PV traces, trace
  * extensions, bubbles, P_sigma, P_p, Q and M^{l+1}_A, D^{l+1}_A.  The
  * hierarchy depends on the mesh only and serves any number of solves.
+ * allocator: see spfas_allocator; NULL for hipMalloc / hipFree.
  * Errors: ERR_INVALID for a malformed mesh (index out of range, non-positive
  * volume or half-transmissibility, no Dirichlet face, n_levels < 1, a lattice
- * that cannot be recovered from the centroids), ERR_OOM, ERR_DEVICE.
+ * that cannot be recovered from the centroids for BOX, a malformed USER
+ * aggregation), ERR_OOM, ERR_DEVICE.
  * *out receives a handle to be released with spfas_destroy.
  */
 int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts,
-                          void* stream, spfas_hierarchy** out);
+                          const spfas_allocator* allocator, void* stream, spfas_hierarchy** out);
+
+/* Device bytes the hierarchy holds now (*bytes) and at most held so far
+ * (*peak), counting everything allocated through its allocator. */
+int spfas_hierarchy_device_bytes(const spfas_hierarchy* h, int64_t* bytes, int64_t* peak);
 
 /*
  * Solves the nonlinear system (eq. nonlinear_system_residual_form) with FAS

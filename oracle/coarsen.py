@@ -76,6 +76,71 @@ def box_aggregate(shape, index, box):
     return agg, tuple(cshape)
 
 
+def greedy_aggregate(level: Level, target: int) -> np.ndarray:
+    """Greedy graph aggregation of a level (the paper partitions with METIS;
+    this rule is the build's deterministic stand-in for unstructured meshes):
+    seeds in ascending cell id grow breadth first, visiting neighbours in
+    ascending id, until the aggregate holds ``target`` cells; then every
+    aggregate with fewer than target/2 cells, in ascending id, joins the
+    neighbouring aggregate with which it shares the most interior flux
+    unknowns (ties: the lower id); ids are renumbered in ascending order of
+    the surviving aggregates.  Neighbours are cells that share an interior
+    flux unknown of the level."""
+    from collections import deque
+    n = level.n_cells
+    fc = level.flux_cells
+    inner = np.nonzero((level.flux_kind == INTERIOR) & (fc[:, 1] >= 0))[0]
+    nbr = [set() for _ in range(n)]
+    for j in inner:
+        a, b = int(fc[j, 0]), int(fc[j, 1])
+        nbr[a].add(b)
+        nbr[b].add(a)
+    nbr = [sorted(x) for x in nbr]
+    agg = np.full(n, -1, dtype=np.int64)
+    members = []
+    for seed in range(n):
+        if agg[seed] >= 0:
+            continue
+        A = len(members)
+        group = [seed]
+        agg[seed] = A
+        queue = deque([seed])
+        while queue and len(group) < target:
+            u = queue.popleft()
+            for v in nbr[u]:
+                if len(group) >= target:
+                    break
+                if agg[v] < 0:
+                    agg[v] = A
+                    group.append(v)
+                    queue.append(v)
+        members.append(group)
+    na0 = len(members)
+    label = np.arange(na0)
+    size = np.array([len(g) for g in members])
+    for A in range(na0):
+        if label[A] != A or 2 * size[A] >= target:
+            continue
+        la = label[agg[fc[inner, 0]]]
+        lb = label[agg[fc[inner, 1]]]
+        shared = {}
+        for x, y in zip(la, lb):
+            if x == A and y != A:
+                shared[int(y)] = shared.get(int(y), 0) + 1
+            elif y == A and x != A:
+                shared[int(x)] = shared.get(int(x), 0) + 1
+        if not shared:
+            continue
+        best = min(shared, key=lambda B: (-shared[B], B))
+        label[label == A] = best
+        size[best] += size[A]
+        size[A] = 0
+    survivors = np.unique(label)
+    newid = np.full(na0, -1, dtype=np.int64)
+    newid[survivors] = np.arange(survivors.size)
+    return newid[label[agg]]
+
+
 def renumber(level: Level, agg: np.ndarray):
     """Cells contiguous per aggregate (stable by (aggregate, id)); flux
     unknowns grouped [inside each aggregate] [per coarse interface, by
@@ -408,16 +473,29 @@ class Hierarchy:
     finemap: object
 
 
-def build_hierarchy(prob, n_levels=None, box=None, m=None) -> Hierarchy:
+def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, user_agg=None) -> Hierarchy:
+    """Levels and transfers of ``prob``.  Aggregation: boxes on the level
+    lattice by default; ``greedy_size`` > 0 selects ``greedy_aggregate``;
+    ``user_agg`` (one array per coarsened level) gives it explicitly.
+    Defaults come from the problem's own configuration."""
     from .fv import fine_level
     n_levels = prob.n_levels if n_levels is None else n_levels
     box = prob.box if box is None else box
     m = prob.m if m is None else m
+    if greedy_size is None:
+        greedy_size = getattr(prob, "greedy_size", 0)
     lev, b0, fm = fine_level(prob)
     levels, transfers = [lev], []
-    for _ in range(n_levels - 1):
+    for l in range(n_levels - 1):
         cur = levels[-1]
-        agg, cshape = box_aggregate(cur.lattice_shape, cur.lattice_index, box)
+        if user_agg is not None:
+            agg, cshape = np.asarray(user_agg[l], dtype=np.int64), ()
+        elif greedy_size:
+            agg, cshape = greedy_aggregate(cur, greedy_size), ()
+        else:
+            if cur.lattice_shape is None:
+                raise ValueError("box aggregation needs a Cartesian lattice")
+            agg, cshape = box_aggregate(cur.lattice_shape, cur.lattice_index, box)
         coarse, tr = coarsen(cur, agg, cshape, m)
         levels.append(coarse)
         transfers.append(tr)

@@ -104,6 +104,8 @@ def fine_level(prob):
         D_loc.append(cs[s][None, :].copy())
         w.append(np.ones(1))
     shape, index = lattice_from_centroids(mesh.cell_centroid)
+    if int(np.prod(np.array(shape, dtype=np.float64))) != n or np.unique(index).size != n:
+        shape, index = None, None   # not a Cartesian lattice (box aggregation unavailable)
     lev = Level(n_cells=n, pdof_ptr=np.arange(n + 1), n_flux=nflux, flux_kind=kind,
                 flux_cells=np.stack([K, np.where(L >= 0, L, -1)], axis=1),
                 cell_flux=cell_flux, M_loc=M_loc, D_loc=D_loc, w=w,

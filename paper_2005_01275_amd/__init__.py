@@ -71,7 +71,12 @@ class Hierarchy:
     """Owns an spfas_hierarchy built from a mesh with the fields of
     ``problems.Mesh`` (numpy host arrays)."""
 
-    def __init__(self, mesh, n_levels: int, box, m: int, host_only: bool = False, stream=None):
+    def __init__(self, mesh, n_levels: int, box=(), m: int = 1, host_only: bool = False, stream=None,
+                 agg_kind: int = N.SPFAS_AGG_BOX, user_agg=None, greedy_size: int = 0, allocator=None):
+        """allocator: None (hipMalloc) or "torch" (PyTorch's caching
+        allocator owns the hierarchy's device memory).  user_agg: for
+        agg_kind USER, the aggregation of every coarsened level,
+        concatenated."""
         L = N.lib()
         self._keep = []
         cen = np.ascontiguousarray(mesh.cell_centroid, dtype=np.float64)
@@ -88,9 +93,19 @@ class Hierarchy:
                           face_normal=_dptr(nrm), face_point=_dptr(pt),
                           face_kind=kind.ctypes.data_as(C.POINTER(C.c_int8)))
         box = tuple(box) + (1,) * (3 - len(box))
-        op = N.spfas_coarsen_opts(n_levels=n_levels, box=(C.c_int32 * 3)(*box), m=m, host_only=int(host_only))
+        ua = None
+        if user_agg is not None:
+            ua = np.ascontiguousarray(user_agg, dtype=np.int32)
+            self._keep.append(ua)
+        op = N.spfas_coarsen_opts(n_levels=n_levels, box=(C.c_int32 * 3)(*box), m=m, host_only=int(host_only),
+                                  agg_kind=agg_kind,
+                                  user_agg=ua.ctypes.data_as(C.POINTER(C.c_int32)) if ua is not None else None,
+                                  user_agg_len=0 if ua is None else ua.size, greedy_size=greedy_size)
+        if allocator not in (None, "torch"):
+            raise ValueError("allocator must be None or 'torch'")
+        alloc = C.byref(N.TORCH_ALLOCATOR) if allocator == "torch" else None
         h = C.c_void_p()
-        N.check(L.spfas_setup_hierarchy(C.byref(ms), C.byref(op), _stream_handle(stream) if not host_only
+        N.check(L.spfas_setup_hierarchy(C.byref(ms), C.byref(op), alloc, _stream_handle(stream) if not host_only
                                         else C.c_void_p(0), C.byref(h)))
         self.h = h
         self.n_cells = vol.size
@@ -231,6 +246,12 @@ class Hierarchy:
             N.check(N.lib().spfas_profile_read(self.h, k, C.byref(a), C.byref(b), C.byref(c)))
             out[name] = (a.value, b.value, c.value)
         return out
+
+    def device_bytes(self):
+        """(bytes held now, peak) of the hierarchy's device memory."""
+        a, b = C.c_int64(), C.c_int64()
+        N.check(N.lib().spfas_hierarchy_device_bytes(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def level_operator(self, level, what, count):
         out = np.zeros(count)

@@ -13,11 +13,12 @@ SPFAS_OK, SPFAS_NOT_CONVERGED = 0, 1
 SPFAS_ERR_INVALID, SPFAS_ERR_OOM, SPFAS_ERR_DEVICE, SPFAS_ERR_NUMERIC = -1, -2, -3, -4
 SPFAS_MEM_HOST, SPFAS_MEM_DEVICE = 0, 1
 SPFAS_NEWTON, SPFAS_PICARD = 0, 1
+SPFAS_AGG_BOX, SPFAS_AGG_USER, SPFAS_AGG_GREEDY = 0, 1, 2
 SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SPFAS_OP_W, SPFAS_OP_QSIGMA = range(7)
 
 EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solve", "spfas_cascadic_solve",
             "spfas_picard_solve", "spfas_newton_solve", "spfas_eval_residual", "spfas_eval_residual_noalloc",
-            "spfas_level_sizes",
+            "spfas_level_sizes", "spfas_hierarchy_device_bytes",
             "spfas_get_aggregation",
             "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
             "spfas_version", "spfas_profile_enable", "spfas_profile_read"]
@@ -41,7 +42,17 @@ class spfas_mesh(C.Structure):
 
 
 class spfas_coarsen_opts(C.Structure):
-    _fields_ = [("n_levels", C.c_int32), ("box", C.c_int32 * 3), ("m", C.c_int32), ("host_only", C.c_int32)]
+    _fields_ = [("n_levels", C.c_int32), ("box", C.c_int32 * 3), ("m", C.c_int32), ("host_only", C.c_int32),
+                ("agg_kind", C.c_int32), ("user_agg", _ip), ("user_agg_len", C.c_int64),
+                ("greedy_size", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+
+
+class spfas_allocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
 class spfas_problem(C.Structure):
@@ -87,7 +98,8 @@ def lib():
     vp = C.c_void_p
     L.spfas_default_solve_opts.argtypes = [C.POINTER(spfas_solve_opts)]
     L.spfas_default_solve_opts.restype = None
-    L.spfas_setup_hierarchy.argtypes = [C.POINTER(spfas_mesh), C.POINTER(spfas_coarsen_opts), vp, C.POINTER(vp)]
+    L.spfas_setup_hierarchy.argtypes = [C.POINTER(spfas_mesh), C.POINTER(spfas_coarsen_opts),
+                                        C.POINTER(spfas_allocator), vp, C.POINTER(vp)]
     L.spfas_setup_hierarchy.restype = C.c_int
     for nm in ("spfas_fas_solve", "spfas_picard_solve", "spfas_newton_solve"):
         f = getattr(L, nm)
@@ -104,6 +116,8 @@ def lib():
     L.spfas_level_sizes.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                     C.POINTER(C.c_int64)]
     L.spfas_level_sizes.restype = C.c_int
+    L.spfas_hierarchy_device_bytes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+    L.spfas_hierarchy_device_bytes.restype = C.c_int
     L.spfas_get_aggregation.argtypes = [vp, C.c_int32, _ip]
     L.spfas_get_aggregation.restype = C.c_int
     L.spfas_get_permutation.argtypes = [vp, C.c_int32, _ip, _ip]
@@ -123,6 +137,24 @@ def lib():
     L.spfas_profile_read.restype = C.c_int
     _lib = L
     return L
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0))
+    except Exception:
+        return None
+
+
+def _torch_free(ptr, nbytes, stream, ctx):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+# callbacks that hand the hierarchy's device memory to PyTorch's caching
+# allocator (kept alive for the life of the process)
+TORCH_ALLOCATOR = spfas_allocator(alloc=ALLOC_FN(_torch_alloc), free=FREE_FN(_torch_free), ctx=None)
 
 
 class SpfasError(RuntimeError):

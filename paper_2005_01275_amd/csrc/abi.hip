@@ -62,19 +62,31 @@ void spfas_default_solve_opts(spfas_solve_opts* o) {
   o->lin_max_it_coarse = 0;
 }
 
-int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts, void* stream,
-                          spfas_hierarchy** out) {
+int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts, const spfas_allocator* allocator,
+                          void* stream, spfas_hierarchy** out) {
   return guarded([&] {
     require(mesh && opts && out, "NULL argument");
+    require(!allocator || (allocator->alloc && allocator->free), "allocator: both callbacks are needed");
     auto* H = new spfas_hierarchy();
     try {
-      H->h.stream = (hipStream_t)stream;
+      if (allocator) H->h.mem.user = *allocator;
+      H->h.use_stream((hipStream_t)stream);
+      AllocScope scope(&H->h.mem);
       H->h.setup(*mesh, *opts);
     } catch (...) {
       delete H;
       throw;
     }
     *out = H;
+    return SPFAS_OK;
+  });
+}
+
+int spfas_hierarchy_device_bytes(const spfas_hierarchy* h, int64_t* bytes, int64_t* peak) {
+  return guarded([&] {
+    require(h != nullptr, "NULL hierarchy");
+    if (bytes) *bytes = h->h.mem.bytes.load();
+    if (peak) *peak = h->h.mem.peak.load();
     return SPFAS_OK;
   });
 }
@@ -98,7 +110,8 @@ int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const dou
   return guarded([&] {
     need_device(h);
     require(prob && p && sigma && r_p && r_sigma, "NULL argument");
-    h->h.stream = (hipStream_t)stream;
+    h->h.use_stream((hipStream_t)stream);
+    AllocScope scope(&h->h.mem);
     h->h.set_problem(*prob);
     h->h.eval_residual(p, sigma, r_p, r_sigma, mem == SPFAS_MEM_DEVICE);
     return SPFAS_OK;
@@ -116,7 +129,7 @@ int spfas_eval_residual_noalloc(spfas_hierarchy* h, const spfas_problem* prob, c
       fail(SPFAS_ERR_INVALID, "spfas_eval_residual_noalloc: " + std::to_string(nu) +
                                   " level-0 unknowns exceed the scratch capacity of " +
                                   std::to_string(noalloc_max_unknowns()));
-    h->h.stream = (hipStream_t)stream;
+    h->h.use_stream((hipStream_t)stream);
     h->h.set_problem(*prob);
     h->h.eval_residual_noalloc(p, sigma, r_p, r_sigma);
     return SPFAS_OK;
@@ -129,7 +142,8 @@ static int solve_common(spfas_hierarchy* h, const spfas_problem* prob, const spf
   return guarded([&] {
     need_device(h);
     require(prob && opts && p && sigma, "NULL argument");
-    h->h.stream = (hipStream_t)stream;
+    h->h.use_stream((hipStream_t)stream);
+    AllocScope scope(&h->h.mem);
     auto t0 = std::chrono::steady_clock::now();
     spfas_stats st;
     std::memset(&st, 0, sizeof st);
@@ -200,6 +214,7 @@ int spfas_get_level_operator(const spfas_hierarchy* h, int32_t level, int32_t wh
     need_device(h);
     require(out != nullptr, "NULL output");
     require(level >= 0 && level + 1 < h->h.n_levels, "level must be below the coarsest level");
+    AllocScope scope(const_cast<AllocCtx*>(&h->h.mem));
     export_level_operator(h->h, level, what, out, count);
     return SPFAS_OK;
   });

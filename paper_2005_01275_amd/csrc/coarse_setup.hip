@@ -327,7 +327,12 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       for (int e = threadIdx.x; e < npA * npA; e += blockDim.x) V[e] = L[e] + rho * q[e / npA] * q[e % npA];
       wg_sync();
       if (wg_chol(V, npA, npA, &flag))
-        sub = wg_subspace_eig(L, V, q, npA, nbs, nev, rho, 1e-12, 300, EX, EY, ELX, EG, EW, Eth, cs, prs, red, &flag);
+        // residual tolerance a few times the rounding level of an npA-row
+        // product: the eigenvector error is about residual / gap, and the
+        // gaps below lambda_m can be 1e-3 rho and smaller on irregular
+        // aggregates
+        sub = wg_subspace_eig(L, V, q, npA, nbs, nev, rho, fmax(1e-14, 4.4e-16 * npA), 300, EX, EY, ELX, EG, EW, Eth,
+                              cs, prs, red, &flag);
     }
     double* lam = eig + pl.pd_ptr[A];
     if (sub) {

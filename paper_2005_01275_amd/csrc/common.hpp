@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -33,29 +34,80 @@ inline void hip_check(hipError_t e, const char* what, const char* file, int line
 #define HIPCHECK(x) ::spfas::hip_check((x), #x, __FILE__, __LINE__)
 #define LAUNCHCHECK() ::spfas::hip_check(hipGetLastError(), "kernel launch", __FILE__, __LINE__)
 
-// Typed device buffer; freed with the owning object.
+// Where a hierarchy's device memory comes from: the caller's allocator
+// callbacks (spfas_allocator), or hipMalloc / hipFree when none was given.
+// Bytes are counted either way.
+struct AllocCtx {
+  spfas_allocator user{};              // user.alloc == nullptr: hipMalloc / hipFree
+  hipStream_t stream = nullptr;        // stream handed to the callbacks
+  std::atomic<int64_t> bytes{0};       // allocated now
+  std::atomic<int64_t> peak{0};
+};
+
+// Allocation context of the calling thread: device buffers allocated while
+// an AllocScope is active come from (and return to) its context.
+inline thread_local AllocCtx* tl_alloc = nullptr;
+struct AllocScope {
+  AllocCtx* prev;
+  explicit AllocScope(AllocCtx* c) : prev(tl_alloc) { tl_alloc = c; }
+  ~AllocScope() { tl_alloc = prev; }
+  AllocScope(const AllocScope&) = delete;
+  AllocScope& operator=(const AllocScope&) = delete;
+};
+
+inline void* dev_alloc(AllocCtx* c, size_t bytes) {
+  void* p = nullptr;
+  if (c && c->user.alloc) {
+    p = c->user.alloc(bytes, (void*)c->stream, c->user.ctx);
+    if (!p) fail(SPFAS_ERR_OOM, "the caller's allocator returned NULL for " + std::to_string(bytes) + " bytes");
+  } else {
+    HIPCHECK(hipMalloc(&p, bytes));
+  }
+  if (c) {
+    const int64_t now = c->bytes.fetch_add((int64_t)bytes) + (int64_t)bytes;
+    int64_t pk = c->peak.load();
+    while (now > pk && !c->peak.compare_exchange_weak(pk, now)) {
+    }
+  }
+  return p;
+}
+
+inline void dev_free(AllocCtx* c, void* p, size_t bytes) noexcept {
+  if (!p) return;
+  if (c && c->user.alloc) {
+    if (c->user.free) c->user.free(p, bytes, (void*)c->stream, c->user.ctx);
+  } else {
+    (void)hipFree(p);
+  }
+  if (c) c->bytes.fetch_sub((int64_t)bytes);
+}
+
+// Typed device buffer; freed with the owning object, through the allocation
+// context that was active when it was allocated.
 template <class T>
 struct DVec {
   T* p = nullptr;
   size_t n = 0;
+  AllocCtx* ctx = nullptr;
   DVec() = default;
   DVec(const DVec&) = delete;
   DVec& operator=(const DVec&) = delete;
-  DVec(DVec&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DVec(DVec&& o) noexcept : p(o.p), n(o.n), ctx(o.ctx) { o.p = nullptr; o.n = 0; }
   DVec& operator=(DVec&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; ctx = o.ctx; o.p = nullptr; o.n = 0; }
     return *this;
   }
   ~DVec() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) dev_free(ctx, p, n * sizeof(T));
     p = nullptr;
     n = 0;
   }
   void alloc(size_t count) {
     release();
+    ctx = tl_alloc;
+    if (count) p = static_cast<T*>(dev_alloc(ctx, count * sizeof(T)));
     n = count;
-    if (count) HIPCHECK(hipMalloc((void**)&p, count * sizeof(T)));
   }
   void zero(hipStream_t s) {
     if (n) HIPCHECK(hipMemsetAsync(p, 0, n * sizeof(T), s));

@@ -66,7 +66,8 @@ static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
           "mesh arrays must not be NULL");
   require(o.n_levels >= 1 && o.n_levels <= 16, "n_levels must be in [1, 16]");
   require(o.m >= 1 && o.m <= 64, "m must be in [1, 64]");
-  for (int a = 0; a < M.dim; ++a) require(o.box[a] >= 1, "box edges must be >= 1");
+  if (o.agg_kind == SPFAS_AGG_BOX)
+    for (int a = 0; a < M.dim; ++a) require(o.box[a] >= 1, "box edges must be >= 1");
   int64_t ndir = 0;
   for (int64_t c = 0; c < M.n_cells; ++c)
     require(M.cell_volume[c] > 0.0 && std::isfinite(M.cell_volume[c]), "cell volumes must be positive");
@@ -121,15 +122,26 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   stamp("level-0 face lists");
   build_cell_lists(t0);
   stamp("cell lists");
-  if (n_levels > 1) {
+  require(o.agg_kind == SPFAS_AGG_BOX || o.agg_kind == SPFAS_AGG_USER || o.agg_kind == SPFAS_AGG_GREEDY,
+          "agg_kind must be SPFAS_AGG_BOX, SPFAS_AGG_USER or SPFAS_AGG_GREEDY");
+  if (n_levels > 1 && o.agg_kind == SPFAS_AGG_BOX) {
     bool ok = lattice_from_centroids(M.dim, M.n_cells, M.cell_centroid, t0.lat_shape, t0.lat_index);
     require(ok, "box aggregation needs a Cartesian lattice of cell centroids");
   }
   stamp("lattice");
   // ---------------- coarse topologies, aggregation, renumbering
+  int64_t user_off = 0;
   for (int l = 0; l + 1 < n_levels; ++l) {
-    box_aggregate(topo[l], o.box);
-    stamp("box aggregation");
+    if (o.agg_kind == SPFAS_AGG_USER) {
+      require(user_off + topo[l].n_cells <= o.user_agg_len, "user_agg is shorter than the cells of a coarsened level");
+      user_aggregate(topo[l], o.user_agg + user_off, topo[l].n_cells);
+      user_off += topo[l].n_cells;
+    } else if (o.agg_kind == SPFAS_AGG_GREEDY) {
+      greedy_aggregate(topo[l], o.greedy_size);
+    } else {
+      box_aggregate(topo[l], o.box);
+    }
+    stamp("aggregation");
     renumber(topo[l]);
     stamp("renumbering");
     Topo c = coarse_topology(topo[l], m);

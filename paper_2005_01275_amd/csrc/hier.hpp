@@ -52,6 +52,8 @@ struct FineWork {
 };
 
 struct Hierarchy {
+  // first member: destroyed after every buffer that returns memory to it
+  AllocCtx mem;
   hipStream_t stream = nullptr;
   int device = -1;                        // device current at setup
   bool host_only = false;
@@ -78,6 +80,8 @@ struct Hierarchy {
 
   ~Hierarchy();
   void setup(const spfas_mesh& mesh, const spfas_coarsen_opts& o);
+  // stream of the current call, also handed to the allocator callbacks
+  void use_stream(hipStream_t s) { stream = s; mem.stream = s; }
   void set_problem(const spfas_problem& prob);
   // fine residual in input order
   void eval_residual(const double* p, const double* sig, double* rp, double* rs, bool dev);

@@ -66,6 +66,131 @@ void box_aggregate(Topo& t, const int box[3]) {
   t.n_agg = na;
 }
 
+// Interior neighbours of each cell (ascending, without repeats), from the
+// level's interior flux unknowns.
+static void cell_neighbours(const Topo& t, std::vector<int64_t>& ptr, std::vector<int64_t>& nb) {
+  const int64_t n = t.n_cells;
+  std::vector<std::vector<int64_t>> lists(n);
+  for (int64_t j = 0; j < t.n_flux; ++j)
+    if (t.kind[j] == FK_INTERIOR && t.c2[j] >= 0) {
+      lists[t.c1[j]].push_back(t.c2[j]);
+      lists[t.c2[j]].push_back(t.c1[j]);
+    }
+  ptr.assign(n + 1, 0);
+  nb.clear();
+  for (int64_t c = 0; c < n; ++c) {
+    auto& v = lists[c];
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    nb.insert(nb.end(), v.begin(), v.end());
+    ptr[c + 1] = (int64_t)nb.size();
+  }
+}
+
+void user_aggregate(Topo& t, const int32_t* agg, int64_t len) {
+  require(agg != nullptr, "user_agg is NULL");
+  require(len == t.n_cells, "user_agg is shorter than the cells of a coarsened level");
+  int64_t na = 0;
+  for (int64_t c = 0; c < t.n_cells; ++c) {
+    require(agg[c] >= 0, "user_agg holds a negative aggregate id");
+    na = std::max<int64_t>(na, (int64_t)agg[c] + 1);
+  }
+  require(na < t.n_cells || t.n_cells == 1, "user_agg does not coarsen the level");
+  std::vector<int64_t> size(na, 0);
+  for (int64_t c = 0; c < t.n_cells; ++c) size[agg[c]]++;
+  for (int64_t A = 0; A < na; ++A) require(size[A] > 0, "user_agg leaves an aggregate id unused");
+  // connectedness: union-find over interior faces inside one aggregate
+  std::vector<int64_t> up(t.n_cells);
+  std::iota(up.begin(), up.end(), 0);
+  auto find = [&](int64_t x) {
+    while (up[x] != x) x = up[x] = up[up[x]];
+    return x;
+  };
+  for (int64_t j = 0; j < t.n_flux; ++j)
+    if (t.kind[j] == FK_INTERIOR && t.c2[j] >= 0 && agg[t.c1[j]] == agg[t.c2[j]]) {
+      const int64_t a = find(t.c1[j]), b = find(t.c2[j]);
+      if (a != b) up[std::max(a, b)] = std::min(a, b);
+    }
+  std::vector<int64_t> root(na, -1);
+  for (int64_t c = 0; c < t.n_cells; ++c) {
+    const int64_t r = find(c);
+    if (root[agg[c]] < 0) root[agg[c]] = r;
+    else require(root[agg[c]] == r, "user_agg holds an aggregate that is not connected");
+  }
+  t.agg.assign(agg, agg + t.n_cells);
+  t.n_agg = na;
+  t.agg_shape.clear();
+}
+
+void greedy_aggregate(Topo& t, int target) {
+  require(target >= 2, "greedy_size must be at least 2");
+  const int64_t n = t.n_cells;
+  std::vector<int64_t> nptr, nb;
+  cell_neighbours(t, nptr, nb);
+  // growth: seeds in ascending id, breadth first, neighbours in ascending id
+  std::vector<int64_t> agg(n, -1), queue;
+  std::vector<std::vector<int64_t>> members;
+  for (int64_t s = 0; s < n; ++s) {
+    if (agg[s] >= 0) continue;
+    const int64_t A = (int64_t)members.size();
+    members.emplace_back();
+    auto& mem = members.back();
+    agg[s] = A;
+    mem.push_back(s);
+    queue.assign(1, s);
+    for (size_t head = 0; head < queue.size() && (int64_t)mem.size() < target; ++head) {
+      const int64_t u = queue[head];
+      for (int64_t k = nptr[u]; k < nptr[u + 1] && (int64_t)mem.size() < target; ++k) {
+        const int64_t v = nb[k];
+        if (agg[v] >= 0) continue;
+        agg[v] = A;
+        mem.push_back(v);
+        queue.push_back(v);
+      }
+    }
+  }
+  const int64_t na0 = (int64_t)members.size();
+  // fragments below target/2 join the neighbour sharing the most interior
+  // faces (ties: lower id), in ascending id; labels stay original ids of
+  // the surviving aggregates
+  std::vector<int64_t> label(na0);
+  std::iota(label.begin(), label.end(), 0);
+  std::vector<char> alive(na0, 1);
+  std::vector<int64_t> count(na0, 0), touched;
+  for (int64_t A = 0; A < na0; ++A) {
+    if (!alive[A] || 2 * (int64_t)members[A].size() >= target) continue;
+    touched.clear();
+    for (int64_t u : members[A])
+      for (int64_t k = t.cfptr[u]; k < t.cfptr[u + 1]; ++k) {
+        const int64_t j = t.cfidx[k];
+        if (t.kind[j] != FK_INTERIOR || t.c2[j] < 0) continue;
+        const int64_t v = t.c1[j] == u ? t.c2[j] : t.c1[j];
+        const int64_t B = label[agg[v]];
+        if (B == A) continue;
+        if (count[B]++ == 0) touched.push_back(B);
+      }
+    int64_t best = -1;
+    for (int64_t B : touched)
+      if (best < 0 || count[B] > count[best] || (count[B] == count[best] && B < best)) best = B;
+    for (int64_t B : touched) count[B] = 0;
+    if (best < 0) continue;   // no neighbour: the fragment stays
+    for (int64_t u : members[A]) members[best].push_back(u);
+    members[A].clear();
+    alive[A] = 0;
+    for (int64_t X = 0; X < na0; ++X)
+      if (label[X] == A) label[X] = best;
+  }
+  // compact ids in ascending order of the surviving labels
+  std::vector<int64_t> newid(na0, -1);
+  int64_t na = 0;
+  for (int64_t A = 0; A < na0; ++A)
+    if (alive[A]) newid[A] = na++;
+  t.agg.resize(n);
+  for (int64_t c = 0; c < n; ++c) t.agg[c] = newid[label[agg[c]]];
+  t.n_agg = na;
+  t.agg_shape.clear();
+}
+
 void renumber(Topo& t) {
   const int64_t n = t.n_cells;
   // cells by aggregate, ascending id inside an aggregate (counting sort)

@@ -39,6 +39,10 @@ bool lattice_from_centroids(int dim, int64_t n, const double* centroid, std::vec
 
 int box_blocks(int n, int a);
 void box_aggregate(Topo& t, const int box[3]);
+// aggregation given by the caller (validated: ids dense, aggregates connected)
+void user_aggregate(Topo& t, const int32_t* agg, int64_t len);
+// greedy graph aggregation of about `target` cells (rule in include/spfas.h)
+void greedy_aggregate(Topo& t, int target);
 void renumber(Topo& t);
 void build_cell_lists(Topo& t);  // cfptr/cfidx from c1/c2
 // Coarse topology from an aggregated level; m = eigenvectors per aggregate.

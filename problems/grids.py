@@ -60,6 +60,7 @@ class Problem:
     m: int = 1
     n_levels: int = 2
     dp_cap_c: float = 5.0          # cap constant c: max |dp| <= ln(c)/alpha
+    greedy_size: int = 0           # > 0: greedy aggregates of about this many cells (unstructured meshes)
 
 
 # ---------------------------------------------------------------- meshes
@@ -135,6 +136,63 @@ def cartesian_mesh(shape, spacing, k_cells, dirichlet=((0, 0),)) -> Mesh:
                 face_cells=face_cells, face_area=np.concatenate(farea),
                 face_normal=np.concatenate(fnorm), face_point=np.concatenate(fpt),
                 face_bc=np.concatenate(fbc), shape=shape)
+
+
+def voronoi_mesh(points: np.ndarray, k_cells: np.ndarray, dirichlet_x0: bool = True) -> Mesh:
+    """Bounded Voronoi tessellation of the unit square from generator
+    points: each point is mirrored across the four sides, so the cells of
+    the original points are clipped to the square (qhull through SciPy).
+
+    Geometry as the two-point flux needs it on a Voronoi mesh: the cell
+    "centroid" is its generator point (the face between two cells is then
+    perpendicular to the segment joining them), the face point is the
+    midpoint of that segment (on the bisector), the normal points from K to
+    L, the face measure is the Voronoi edge length.  Boundary faces are the
+    edges shared with a mirror point.  Dirichlet on the side x = 0 when
+    ``dirichlet_x0``, Neumann elsewhere.  Cell volumes are polygon areas."""
+    from scipy.spatial import Voronoi
+    pts = np.asarray(points, dtype=np.float64)
+    n = pts.shape[0]
+    mir = [pts, np.c_[-pts[:, 0], pts[:, 1]], np.c_[2.0 - pts[:, 0], pts[:, 1]],
+           np.c_[pts[:, 0], -pts[:, 1]], np.c_[pts[:, 0], 2.0 - pts[:, 1]]]
+    vor = Voronoi(np.concatenate(mir))
+    V = vor.vertices
+    # cell areas by the shoelace formula over each region's ordered vertices
+    vol = np.empty(n)
+    for i in range(n):
+        reg = vor.regions[vor.point_region[i]]
+        xy = V[reg]
+        vol[i] = 0.5 * abs(np.dot(xy[:, 0], np.roll(xy[:, 1], -1)) - np.dot(xy[:, 1], np.roll(xy[:, 0], -1)))
+    rp = vor.ridge_points
+    rv = np.asarray(vor.ridge_vertices, dtype=np.int64)
+    a, b = rp[:, 0], rp[:, 1]
+    keep = (a < n) | (b < n)
+    a, b, rv = a[keep], b[keep], rv[keep]
+    # orient every ridge with an original point first
+    sw = a >= n
+    a, b = np.where(sw, b, a), np.where(sw, a, b)
+    length = np.linalg.norm(V[rv[:, 0]] - V[rv[:, 1]], axis=1)
+    inner = b < n
+    # drop degenerate ridges (zero length) between two original cells
+    ok = length > 1e-14
+    a, b, length, inner = a[ok], b[ok], length[ok], inner[ok]
+    other = np.concatenate(mir)[b]   # the neighbour's generator (or the mirror image across the boundary)
+    d = other - pts[a]
+    normal = d / np.linalg.norm(d, axis=1)[:, None]
+    point = 0.5 * (pts[a] + other)
+    L = np.where(inner, b, -1)
+    bc = np.zeros(a.size, dtype=np.int8)
+    on_x0 = (~inner) & (np.abs(point[:, 0]) < 1e-12)
+    bc[~inner] = 2
+    if dirichlet_x0:
+        bc[on_x0] = 1
+    k = np.asarray(k_cells, dtype=np.float64)
+    k0 = np.zeros((n, 2, 2))
+    k0[:, 0, 0] = k
+    k0[:, 1, 1] = k
+    return Mesh(dim=2, cell_volume=vol, cell_centroid=pts.copy(), cell_k0=k0,
+                face_cells=np.stack([a, L], axis=1).astype(np.int32), face_area=length,
+                face_normal=normal, face_point=point, face_bc=bc, shape=None)
 
 
 def permute_mesh(prob: Problem, seed: int) -> Problem:
@@ -279,6 +337,54 @@ def c2_problem(seed: int = 0, rate: Optional[float] = None, permute: bool = True
     if permute:
         prob = permute_mesh(prob, seed + 1)
     return prob
+
+
+def bilinear_sample(field: np.ndarray, xy: np.ndarray) -> np.ndarray:
+    """Values of a field given on the cell centres of a uniform lattice over
+    the unit square ([i, j], x first) at points xy, by bilinear
+    interpolation (clamped at the border)."""
+    nx, ny = field.shape
+    fx = np.clip(xy[:, 0] * nx - 0.5, 0.0, nx - 1.0)
+    fy = np.clip(xy[:, 1] * ny - 0.5, 0.0, ny - 1.0)
+    i0 = np.minimum(np.floor(fx).astype(np.int64), nx - 2)
+    j0 = np.minimum(np.floor(fy).astype(np.int64), ny - 2)
+    tx, ty = fx - i0, fy - j0
+    return ((1 - tx) * (1 - ty) * field[i0, j0] + tx * (1 - ty) * field[i0 + 1, j0]
+            + (1 - tx) * ty * field[i0, j0 + 1] + tx * ty * field[i0 + 1, j0 + 1])
+
+
+def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, corr_len: float = 0.01,
+                    alpha: float = 2.0, lattice: int = 0, rate: Optional[float] = None, n_levels: int = 3,
+                    greedy_size: int = 64, m: int = 3) -> Problem:
+    """Unstructured 2-D problem on the Voronoi mesh of ``n_points`` seeded
+    uniform points in the unit square: ln k = sigma G, G a standardised
+    Gaussian random field of correlation length ``corr_len`` (in units of
+    the square) sampled from a lattice of ``lattice``^2 cells (default: 4
+    cells per point spacing, at most 4096) by bilinear interpolation;
+    kappa = exp(alpha p); p = 0 on x = 0, no flow elsewhere; a source and a
+    sink of equal total rate in the cells whose generators are nearest to
+    (0.05, 0.05) and (0.95, 0.95).  The caller chooses the rate (default
+    1.0): with kappa = exp(alpha p) a strong sink leaves the problem without a
+    solution, and the rule used with these meshes is alpha max|p| = 0.5 for
+    the kappa = 1 pressure (p is linear in the rate there).  Greedy
+    aggregates of about ``greedy_size`` cells, m local eigenvectors."""
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n_points, 2))
+    if lattice <= 0:
+        lattice = int(min(4096, max(64, 4 * math.sqrt(n_points))))
+    g = gaussian_field((lattice, lattice), corr_len * lattice, rng)
+    k = np.exp(sigma * bilinear_sample(g, pts))
+    mesh = voronoi_mesh(pts, k)
+    src = np.zeros(n_points)
+    q = 1.0 if rate is None else rate
+    i_in = int(np.argmin(np.sum((pts - np.array([0.05, 0.05])) ** 2, axis=1)))
+    i_out = int(np.argmin(np.sum((pts - np.array([0.95, 0.95])) ** 2, axis=1)))
+    src[i_in] += q / mesh.cell_volume[i_in]
+    src[i_out] -= q / mesh.cell_volume[i_out]
+    prob = Problem(mesh=mesh, alpha=alpha, source=src, g_dirichlet=np.zeros(mesh.n_faces),
+                   g_neumann=np.zeros(mesh.n_faces), name=f"voronoi_2d_{n_points}", box=(), m=m,
+                   n_levels=n_levels, dp_cap_c=5.0)
+    return dataclasses.replace(prob, greedy_size=greedy_size)
 
 
 def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=None, m=2,

@@ -1,0 +1,113 @@
+"""Unstructured meshes with greedy aggregation (GPU): the device-built
+hierarchy on a Voronoi mesh against the oracle's (aggregation and
+renumbering bit for bit, eigenvalues to 1e-12 of each aggregate's largest,
+the other operators to 1e-10), and FAS roots against the oracle's root
+element by element; the same on a greedy-aggregated Cartesian grid; a
+hierarchy whose device memory comes from PyTorch's caching allocator gives
+the same bits as one on hipMalloc, and torch accounts for its bytes."""
+import math
+
+import numpy as np
+import pytest
+
+from problems import small_problem
+from problems.grids import voronoi_problem
+from oracle.coarsen import build_hierarchy
+from oracle.fv import full_flux
+from oracle.solvers import result_solve
+from parity_util import assert_elementwise, max_rel_err
+
+pytestmark = pytest.mark.gpu
+
+def voronoi(**kw):
+    """Voronoi problem with its rate set so that alpha max|p| = 0.5 for the
+    kappa = 1 pressure (stronger sinks can leave exp(alpha p) without a root)."""
+    from oracle.fv import linear_pressure
+    prob = voronoi_problem(**kw)
+    rate = 0.5 / (kw["alpha"] * np.abs(linear_pressure(prob)).max())
+    return voronoi_problem(**kw, rate=rate)
+
+
+# ln k = sigma G with sigma = 1 keeps the local problems of the hierarchy
+# well enough conditioned for the 1e-10 operator parity; sigma = 3 (the
+# unstructured workload's field) is checked through the root below
+CASES = {
+    "voronoi": lambda: (voronoi(n_points=2000, seed=1, n_levels=3, m=3, alpha=2.0, sigma=1.0), 64),
+    "voronoi-m2": lambda: (voronoi(n_points=1200, seed=4, n_levels=2, m=2, alpha=1.0, sigma=1.0), 32),
+    "cart-greedy": lambda: (small_problem((12, 10), seed=2, m=2, n_levels=3, permute=True, alpha=1.5,
+                                          src_scale=2.0), 8),
+}
+ROOT_CASES = dict(CASES, **{
+    "voronoi-sigma3": lambda: (voronoi(n_points=2000, seed=5, n_levels=3, m=3, alpha=2.0, sigma=3.0), 64)})
+
+
+def gpu_hierarchy(prob, target, **kw):
+    import paper_2005_01275_amd as pk
+    from paper_2005_01275_amd import _native as N
+    return pk.Hierarchy(prob.mesh, prob.n_levels, m=prob.m, agg_kind=N.SPFAS_AGG_GREEDY, greedy_size=target, **kw)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_greedy_hierarchy_parity(case):
+    from paper_2005_01275_amd import _native as N
+    print("case", case, flush=True)
+    prob, target = CASES[case]()
+    h = build_hierarchy(prob, greedy_size=target)
+    H = gpu_hierarchy(prob, target)
+    for l, tr in enumerate(h.transfers):
+        np.testing.assert_array_equal(H.aggregation(l), tr.agg)
+        clev = h.levels[l + 1]
+        assert H.level_sizes(l + 1) == (clev.n_cells, clev.n_p, clev.n_flux)
+        ms = [ad.P.shape[1] for ad in tr.aggs]
+        g = H.level_operator(l, N.SPFAS_OP_EIGVALS, sum(ms))
+        for ad, m, seg in zip(tr.aggs, ms, np.split(g, np.cumsum(ms)[:-1])):
+            np.testing.assert_allclose(seg, ad.lam[:m], rtol=0.0, atol=1e-12 * abs(ad.lam[-1]))
+        Ps = tr.P_sig.toarray()
+        assert max_rel_err(H.level_operator(l, N.SPFAS_OP_PSIGMA, Ps.size).reshape(Ps.shape), Ps) <= 1e-10
+        M = np.concatenate([m.ravel() for m in clev.M_loc])
+        assert max_rel_err(H.level_operator(l, N.SPFAS_OP_MLOC, M.size), M) <= 1e-10
+        D = np.concatenate([d.ravel() for d in clev.D_loc])
+        assert max_rel_err(H.level_operator(l, N.SPFAS_OP_DLOC, D.size), D) <= 1e-10
+
+
+@pytest.mark.parametrize("case", list(ROOT_CASES))
+def test_greedy_fas_reaches_the_root(case):
+    import paper_2005_01275_amd as pk
+    print("case", case, flush=True)
+    prob, target = ROOT_CASES[case]()
+    h = build_hierarchy(prob, n_levels=1)
+    xs = result_solve(h)
+    nf = h.levels[0].n_flux
+    p_star, s_star = xs[nf:], full_flux(prob, h.finemap, xs[:nf])
+    H = gpu_hierarchy(prob, target)
+    for sm in (pk.SPFAS_NEWTON, pk.SPFAS_PICARD):
+        o = pk.SolveOpts(smoother=sm, rtol=1e-13, atol=0.0, max_it=200, lin_rtol=1e-13, lin_max_it=4000,
+                         dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
+        p, s, st = H.fas_solve(prob, o)
+        assert st["converged"], (sm, st)
+        assert_elementwise(p, p_star, 1e-10, f"{case} {sm} p")
+        assert_elementwise(s, s_star, 1e-10, f"{case} {sm} sigma")
+
+
+def test_torch_allocator_owns_the_hierarchy():
+    import torch
+    import paper_2005_01275_amd as pk
+    prob = small_problem((12, 8), seed=2, box=(4, 4), m=3, n_levels=3, g_d_scale=0.3, g_n_scale=0.2,
+                         dirichlet=((0, 0), (1, 1)), permute=True, alpha=1.5, src_scale=2.0)
+    o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-12, atol=0.0, max_it=100, lin_rtol=1e-13, lin_max_it=2000,
+                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
+    Hh = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    p_ref, s_ref, st_ref = Hh.fas_solve(prob, o)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    Ht = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m, allocator="torch")
+    held, peak = Ht.device_bytes()
+    assert held > 0 and peak >= held
+    assert torch.cuda.memory_allocated() - before >= held
+    p, s, st = Ht.fas_solve(prob, o)
+    assert st["converged"] and st["iterations"] == st_ref["iterations"]
+    np.testing.assert_array_equal(p, p_ref)
+    np.testing.assert_array_equal(s, s_ref)
+    Ht.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() <= before
