@@ -347,6 +347,74 @@ int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const dou
 int spfas_eval_residual_noalloc(spfas_hierarchy* h, const spfas_problem* prob, const double* p,
                                 const double* sigma, double* r_p, double* r_sigma, void* stream);
 
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of solve requests on one GPU.  Models (a mesh and its
+ * coarsening options) are registered once; their hierarchies are built on
+ * first use and kept in device memory.  A fixed number of worker threads,
+ * each with its own HIP stream, take requests from one queue: a request is
+ * admitted as soon as a worker is free and its model's hierarchy is cached
+ * and idle, or can be built within the device-memory budget (idle
+ * hierarchies of other models are evicted, least recently used first, to
+ * make room; the footprint of a model is estimated from its sizes until its
+ * first build measures it).  Requests that cannot be admitted yet do not
+ * hold back later ones.  Solves of different requests overlap on the GPU; a
+ * request's result does not depend on what else is in flight.  Each model
+ * has at most one cached hierarchy: requests on the same model run one
+ * after the other.  All problem data and results are host memory.  Server
+ * functions are thread-safe; errors are reported by
+ * spfas_server_last_error().
+ */
+typedef struct spfas_server spfas_server;
+
+typedef struct {
+  int32_t n_slots;       /* worker threads = solves in flight (1..64)                */
+  int64_t hbm_budget;    /* device bytes for cached hierarchies; <= 0: 80% of free */
+  int32_t device;        /* HIP device ordinal                                      */
+} spfas_server_opts;
+
+typedef enum { SPFAS_SOLVE_FAS = 0, SPFAS_SOLVE_NEWTON = 1, SPFAS_SOLVE_PICARD = 2 } spfas_solve_kind;
+
+typedef struct {
+  double queue_ms;       /* submission to admission                     */
+  double setup_ms;       /* hierarchy build (0 on a cache hit)          */
+  double solve_ms;       /* the solve, host state copies included       */
+  double total_ms;       /* submission to completion                    */
+  int32_t cache_hit;     /* the hierarchy was already cached            */
+} spfas_request_info;
+
+typedef struct {
+  int64_t submitted, completed, setups, cache_hits, evictions;
+  int64_t peak_bytes;    /* largest device bytes held by cached hierarchies */
+  int64_t cached_bytes;  /* held now                                         */
+  int64_t budget_bytes;
+} spfas_server_counters;
+
+int spfas_server_create(const spfas_server_opts* opts, spfas_server** out);
+
+/* Registers a model; the mesh (and a USER aggregation) is copied. */
+int spfas_server_add_model(spfas_server* s, const spfas_mesh* mesh, const spfas_coarsen_opts* coarsen,
+                           int64_t* model_id);
+
+/* Queues one solve (kind: spfas_solve_kind) of the model from x0 = 0; the
+ * problem arrays (host) are copied.  Returns at once with a ticket. */
+int spfas_server_submit(spfas_server* s, int64_t model_id, const spfas_problem* prob, const spfas_solve_opts* opts,
+                        int32_t kind, int64_t* ticket);
+
+/* Blocks until the ticket's solve is done, then writes p [n_cells] and
+ * sigma [n_faces] (host, input order; either may be NULL), stats and info
+ * (may be NULL) and releases the ticket.  Returns the solve's status
+ * (ERR_OOM when the model cannot fit under the budget at all). */
+int spfas_server_wait(spfas_server* s, int64_t ticket, double* p, double* sigma, spfas_stats* stats,
+                      spfas_request_info* info);
+
+int spfas_server_counters_get(spfas_server* s, spfas_server_counters* counters);
+
+/* Stops the workers and releases every hierarchy; collect every ticket
+ * first. */
+void spfas_server_destroy(spfas_server* s);
+
+const char* spfas_server_last_error(void);
+
 /* ------------------------------------------------------------------ parity hooks
  * Read-only views of the hierarchy used to compare it with an independent
  * implementation.  "Canonical order" on level 0 is the input order of

@@ -67,6 +67,25 @@ def _stream_handle(stream):
     return C.c_void_p(int(stream))
 
 
+def _mesh_struct(mesh):
+    """spfas_mesh over contiguous copies of a ``problems.Mesh`` (the copies
+    are returned to keep them alive)."""
+    cen = np.ascontiguousarray(mesh.cell_centroid, dtype=np.float64)
+    k0 = np.ascontiguousarray(mesh.cell_k0, dtype=np.float64)
+    vol = np.ascontiguousarray(mesh.cell_volume, dtype=np.float64)
+    fc = np.ascontiguousarray(mesh.face_cells, dtype=np.int32)
+    area = np.ascontiguousarray(mesh.face_area, dtype=np.float64)
+    nrm = np.ascontiguousarray(mesh.face_normal, dtype=np.float64)
+    pt = np.ascontiguousarray(mesh.face_point, dtype=np.float64)
+    kind = np.ascontiguousarray(mesh.face_bc, dtype=np.int8)
+    ms = N.spfas_mesh(dim=mesh.dim, n_cells=vol.size, n_faces=area.size, cell_volume=_dptr(vol),
+                      cell_centroid=_dptr(cen), cell_k0=_dptr(k0),
+                      face_cells=fc.ctypes.data_as(C.POINTER(C.c_int32)), face_area=_dptr(area),
+                      face_normal=_dptr(nrm), face_point=_dptr(pt),
+                      face_kind=kind.ctypes.data_as(C.POINTER(C.c_int8)))
+    return ms, (cen, k0, vol, fc, area, nrm, pt, kind)
+
+
 class Hierarchy:
     """Owns an spfas_hierarchy built from a mesh with the fields of
     ``problems.Mesh`` (numpy host arrays)."""
@@ -79,19 +98,8 @@ class Hierarchy:
         concatenated."""
         L = N.lib()
         self._keep = []
-        cen = np.ascontiguousarray(mesh.cell_centroid, dtype=np.float64)
-        k0 = np.ascontiguousarray(mesh.cell_k0, dtype=np.float64)
-        vol = np.ascontiguousarray(mesh.cell_volume, dtype=np.float64)
-        fc = np.ascontiguousarray(mesh.face_cells, dtype=np.int32)
-        area = np.ascontiguousarray(mesh.face_area, dtype=np.float64)
-        nrm = np.ascontiguousarray(mesh.face_normal, dtype=np.float64)
-        pt = np.ascontiguousarray(mesh.face_point, dtype=np.float64)
-        kind = np.ascontiguousarray(mesh.face_bc, dtype=np.int8)
-        ms = N.spfas_mesh(dim=mesh.dim, n_cells=vol.size, n_faces=area.size, cell_volume=_dptr(vol),
-                          cell_centroid=_dptr(cen), cell_k0=_dptr(k0),
-                          face_cells=fc.ctypes.data_as(C.POINTER(C.c_int32)), face_area=_dptr(area),
-                          face_normal=_dptr(nrm), face_point=_dptr(pt),
-                          face_kind=kind.ctypes.data_as(C.POINTER(C.c_int8)))
+        ms, arrays = _mesh_struct(mesh)
+        vol, area = arrays[2], arrays[4]
         box = tuple(box) + (1,) * (3 - len(box))
         ua = None
         if user_agg is not None:

@@ -21,7 +21,10 @@ EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solv
             "spfas_level_sizes", "spfas_hierarchy_device_bytes",
             "spfas_get_aggregation",
             "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
-            "spfas_version", "spfas_profile_enable", "spfas_profile_read"]
+            "spfas_version", "spfas_profile_enable", "spfas_profile_read",
+            "spfas_server_create", "spfas_server_add_model", "spfas_server_submit", "spfas_server_wait",
+            "spfas_server_counters_get", "spfas_server_destroy", "spfas_server_last_error"]
+SPFAS_SOLVE_FAS, SPFAS_SOLVE_NEWTON, SPFAS_SOLVE_PICARD = 0, 1, 2
 (SPFAS_PROF_FINE_RESID, SPFAS_PROF_FINE_LINEARIZE, SPFAS_PROF_FINE_SPMV, SPFAS_PROF_FINE_AMG_DOWN,
  SPFAS_PROF_FINE_AMG_RESTRICT, SPFAS_PROF_FINE_AMG_UP, SPFAS_PROF_FINE_SPMV2, SPFAS_PROF_FINE_RESID_TRIALS) = range(8)
 # names match the kernels as a profiler reports them (classical finest AMG level)
@@ -74,6 +77,21 @@ class spfas_stats(C.Structure):
                 ("smoothing_steps", C.c_int32), ("stopped_after_presmooth", C.c_int32),
                 ("r0", C.c_double), ("r_final", C.c_double), ("solve_ms", C.c_double),
                 ("rejected_steps", C.c_int32)]
+
+
+class spfas_server_opts(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("hbm_budget", C.c_int64), ("device", C.c_int32)]
+
+
+class spfas_request_info(C.Structure):
+    _fields_ = [("queue_ms", C.c_double), ("setup_ms", C.c_double), ("solve_ms", C.c_double),
+                ("total_ms", C.c_double), ("cache_hit", C.c_int32)]
+
+
+class spfas_server_counters(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("setups", C.c_int64),
+                ("cache_hits", C.c_int64), ("evictions", C.c_int64), ("peak_bytes", C.c_int64),
+                ("cached_bytes", C.c_int64), ("budget_bytes", C.c_int64)]
 
 
 _lib = None
@@ -135,6 +153,22 @@ def lib():
     L.spfas_profile_read.argtypes = [vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
     L.spfas_profile_read.restype = C.c_int
+    L.spfas_server_create.argtypes = [C.POINTER(spfas_server_opts), C.POINTER(vp)]
+    L.spfas_server_create.restype = C.c_int
+    L.spfas_server_add_model.argtypes = [vp, C.POINTER(spfas_mesh), C.POINTER(spfas_coarsen_opts),
+                                         C.POINTER(C.c_int64)]
+    L.spfas_server_add_model.restype = C.c_int
+    L.spfas_server_submit.argtypes = [vp, C.c_int64, C.POINTER(spfas_problem), C.POINTER(spfas_solve_opts),
+                                      C.c_int32, C.POINTER(C.c_int64)]
+    L.spfas_server_submit.restype = C.c_int
+    L.spfas_server_wait.argtypes = [vp, C.c_int64, vp, vp, C.POINTER(spfas_stats), C.POINTER(spfas_request_info)]
+    L.spfas_server_wait.restype = C.c_int
+    L.spfas_server_counters_get.argtypes = [vp, C.POINTER(spfas_server_counters)]
+    L.spfas_server_counters_get.restype = C.c_int
+    L.spfas_server_destroy.argtypes = [vp]
+    L.spfas_server_destroy.restype = None
+    L.spfas_server_last_error.argtypes = []
+    L.spfas_server_last_error.restype = C.c_char_p
     _lib = L
     return L
 

@@ -19,7 +19,7 @@ BUILD = os.path.join(HERE, "_build")
 ARCH = os.environ.get("SPFAS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["topo.cpp", "amg_classical.cpp", "fine.hip", "sparse.hip", "hier.hip", "coarse_setup.hip", "coarse.hip", "solve.hip",
-           "export.hip", "noalloc.hip", "abi.hip"]
+           "export.hip", "noalloc.hip", "abi.hip", "server.cpp"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

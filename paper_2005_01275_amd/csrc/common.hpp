@@ -7,6 +7,8 @@
 
 #include <atomic>
 #include <cstdint>
+#include <cstdlib>
+#include <type_traits>
 #include <cstdio>
 #include <cstring>
 #include <stdexcept>
@@ -82,6 +84,14 @@ inline void dev_free(AllocCtx* c, void* p, size_t bytes) noexcept {
   if (c) c->bytes.fetch_sub((int64_t)bytes);
 }
 
+inline bool poison_on() {
+  static const bool on = [] {
+    const char* e = std::getenv("SPFAS_POISON");
+    return e && e[0] == '1';
+  }();
+  return on;
+}
+
 // Typed device buffer; freed with the owning object, through the allocation
 // context that was active when it was allocated.
 template <class T>
@@ -108,6 +118,10 @@ struct DVec {
     ctx = tl_alloc;
     if (count) p = static_cast<T*>(dev_alloc(ctx, count * sizeof(T)));
     n = count;
+    // SPFAS_POISON=1 (diagnostics): floating-point buffers start as NaN, so
+    // a read before the first write shows up in the results
+    if constexpr (std::is_floating_point<T>::value || std::is_same<T, _Float16>::value)
+      if (count && poison_on()) HIPCHECK(hipMemset(p, 0xFF, count * sizeof(T)));
   }
   void zero(hipStream_t s) {
     if (n) HIPCHECK(hipMemsetAsync(p, 0, n * sizeof(T), s));

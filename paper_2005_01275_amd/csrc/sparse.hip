@@ -142,7 +142,8 @@ __device__ inline double all_parts(const double* __restrict__ parts, int G, doub
 
 // PCG with the reductions folded in: rz = sum of the r.z partials (block 0
 // stores it in slot `cur`), beta = rz / scal[old] (0 on the first
-// iteration), p = z + beta p.
+// iteration), p = z + beta p (p = z on the first iteration, whatever p
+// held before).
 __global__ void __launch_bounds__(kBlock) k_pcg_p2(int n, const double* __restrict__ prz, int G, double* scal, int cur,
                                                    int old, int first, const double* __restrict__ z,
                                                    double* __restrict__ p) {
@@ -152,7 +153,16 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p2(int n, const double* __restri
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[cur] = rz;
   const double ro = scal[old];
   const double beta = (first || ro == 0.0) ? 0.0 : rz / ro;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = z[i] + beta * p[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    p[i] = first ? z[i] : z[i] + beta * p[i];
+}
+
+// Takes back the last PCG update of x: x -= (rz / pq) p with the alpha
+// k_pcg_xr2 used (rz in scal[rz_slot], pq its p.q).
+__global__ void __launch_bounds__(kBlock) k_pcg_undo(int n, const double* __restrict__ scal, int rz_slot, double pq,
+                                                     double* __restrict__ x, const double* __restrict__ p) {
+  const double alpha = pq != 0.0 ? scal[rz_slot] / pq : 0.0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] -= alpha * p[i];
 }
 
 // pq = sum of the p.q partials (block 0 stores it in S_PQ and in *hpq),
@@ -1600,7 +1610,24 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     if (!near && it > 0) {
       lagged(it - 1, pq, rr);
       if (bad(pq, rr)) { failed = true; ++it; break; }
-      if (rr <= tol2) { converged = true; ++it; break; }
+      if (rr <= tol2) {
+        // iteration it is already in x: keep it only if its p.Ap is sound
+        // (Newton systems are not symmetric, so p.Ap can be <= 0), else take
+        // it back and return the iterate that met the tolerance
+        converged = true;
+        HIPCHECK(hipEventSynchronize(ev[it & 1]));
+        const double pq_it = hl[it & 1];
+        if (!std::isfinite(pq_it)) {
+          failed = true;
+          converged = false;
+        } else if (!(pq_it > 0.0)) {
+          hipLaunchKernelGGL(k_pcg_undo, dim3(G), dim3(kBlock), 0, st, n, scal.p, old, pq_it, x, p.p);
+          LAUNCHCHECK();
+          break;   // `it` iterations were kept
+        }
+        ++it;
+        break;
+      }
       if (stalled(it - 1, rr)) { stop = true; ++it; break; }
       near = rr <= 100.0 * tol2;
     }
