@@ -39,6 +39,9 @@ def parse():
                          "fallback together (<= 0: same as level 0)")
     ap.add_argument("--newton-krylov", default="pcg", choices=["pcg", "bicgstab"],
                     help="pcg: PCG first with BiCGStab fallback on Newton systems")
+    ap.add_argument("--coarsest-atol", type=float, default=1e-10,
+                    help="absolute floor of the coarsest level's convergence test (Section 4: 1e-10); "
+                         "the outer stop stays relative")
     ap.add_argument("--amg-reuse", type=int, default=-1,
                     help="linearisations that may reuse AMG values while the Krylov count stays low "
                          "(0 = off, < 0 = no limit)")
@@ -157,7 +160,8 @@ def main():
     opts = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=args.lin_rtol,
                         lin_max_it=400, dp_cap=cap, lin_rtol_coarse=args.lin_rtol_coarse,
                         lin_target=args.lin_target, newton_pcg=int(args.newton_krylov == "pcg"),
-                        amg_reuse=args.amg_reuse, lin_max_it_coarse=args.lin_max_it_coarse)
+                        amg_reuse=args.amg_reuse, lin_max_it_coarse=args.lin_max_it_coarse,
+                        coarsest_atol=args.coarsest_atol)
 
     def solve():
         return H.fas_solve(prob, opts, device=True, cprob=cprob, out=(p, s), stream=stream.cuda_stream)

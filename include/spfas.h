@@ -207,6 +207,11 @@ typedef struct {
  *                       (<= 0: lin_max_it); a solve that reaches it hands
  *                       its current iterate to the smoothing step, whose
  *                       direction Alg. 1 then checks
+ *   coarsest_atol       absolute tolerance of the coarsest level's own
+ *                       convergence test (Section 4: relative 1e-8 or
+ *                       absolute 1e-10); < 0: atol.  Lets the outer solve run
+ *                       with atol = 0 (a pure relative stop) while the
+ *                       coarsest level keeps the paper's absolute floor
  */
 typedef struct {
   int32_t smoother;
@@ -225,6 +230,7 @@ typedef struct {
   int32_t newton_pcg;
   int32_t amg_reuse;
   int32_t lin_max_it_coarse;
+  double coarsest_atol;
 } spfas_solve_opts;
 
 typedef struct {
@@ -241,8 +247,8 @@ typedef struct {
 } spfas_stats;
 
 /* Fills *o with the paper's settings (Section 4): Newton, rtol 1e-8, atol
- * 1e-10, max_it 50, n_max 4, theta 0.9, no cap, 10 coarsest steps, inner
- * rtol 1e-8 and 500 inner iterations, x0 = 0. */
+ * 1e-10, max_it 50, n_max 4, theta 0.9, no cap, 10 coarsest steps (coarsest
+ * atol = atol), inner rtol 1e-8 and 500 inner iterations, x0 = 0. */
 void spfas_default_solve_opts(spfas_solve_opts* o);
 
 /*

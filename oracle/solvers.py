@@ -58,6 +58,7 @@ class Opts:
     bt_theta: float = 0.9
     cap_c: float = 5.0            # max |dp| <= ln(cap_c)/alpha; <= 1 disables
     coarsest_max: int = 10
+    coarsest_atol: float = None   # absolute floor of the coarsest level's test; None: atol
 
 
 @dataclasses.dataclass
@@ -141,11 +142,14 @@ def smooth(level, x, b, alpha, opts: Opts, stats: Stats = None):
 
 def coarsest_solve(level, x, b, alpha, opts: Opts, stats=None):
     """Section 4: at most ``coarsest_max`` smoothing steps, fewer when the
-    level residual meets rtol (relative to its value on entry) or atol.
-    The loop also ends after a step Alg. 1 rejected (s = 0): the state is
-    then unchanged and the next step would be the same one."""
+    level residual meets rtol (relative to its value on entry) or the
+    absolute tolerance (the paper's pair: relative 1e-8 or absolute 1e-10;
+    ``coarsest_atol`` when set, else atol).  The loop also ends after a step
+    Alg. 1 rejected (s = 0): the state is then unchanged and the next step
+    would be the same one."""
     r = norm(residual(level, x, b, alpha))
-    tol = max(opts.rtol * r, opts.atol)
+    atol = opts.atol if opts.coarsest_atol is None else opts.coarsest_atol
+    tol = max(opts.rtol * r, atol)
     for _ in range(opts.coarsest_max):
         if r <= tol:
             break

@@ -47,6 +47,7 @@ class SolveOpts:
     newton_pcg: int = 0
     amg_reuse: int = 0
     lin_max_it_coarse: int = 0
+    coarsest_atol: float = -1.0
 
     def c(self):
         o = N.spfas_solve_opts()

@@ -28,7 +28,7 @@ SPFAS_SOLVE_FAS, SPFAS_SOLVE_NEWTON, SPFAS_SOLVE_PICARD = 0, 1, 2
 (SPFAS_PROF_FINE_RESID, SPFAS_PROF_FINE_LINEARIZE, SPFAS_PROF_FINE_SPMV, SPFAS_PROF_FINE_AMG_DOWN,
  SPFAS_PROF_FINE_AMG_RESTRICT, SPFAS_PROF_FINE_AMG_UP, SPFAS_PROF_FINE_SPMV2, SPFAS_PROF_FINE_RESID_TRIALS) = range(8)
 # names match the kernels as a profiler reports them (classical finest AMG level)
-PROF_NAMES = {SPFAS_PROF_FINE_RESID: "k_fine_resid", SPFAS_PROF_FINE_LINEARIZE: "k_fine_linearize",
+PROF_NAMES = {SPFAS_PROF_FINE_RESID: "k_fine_resid", SPFAS_PROF_FINE_LINEARIZE: "k_fine_lin_cells",
               SPFAS_PROF_FINE_SPMV: "k_spmv_dot<true>", SPFAS_PROF_FINE_SPMV2: "k_spmv_dot2<true>",
               SPFAS_PROF_FINE_AMG_DOWN: "k_cyc<0, true>", SPFAS_PROF_FINE_AMG_RESTRICT: "k_cyc<1, true>",
               SPFAS_PROF_FINE_AMG_UP: "k_cyc<2, true>", SPFAS_PROF_FINE_RESID_TRIALS: "k_fine_resid_trials"}
@@ -69,7 +69,7 @@ class spfas_solve_opts(C.Structure):
                 ("coarsest_max_steps", C.c_int32), ("lin_rtol", C.c_double), ("lin_max_it", C.c_int32),
                 ("x0_given", C.c_int32), ("lin_rtol_coarse", C.c_double), ("lin_target", C.c_double),
                 ("newton_pcg", C.c_int32), ("amg_reuse", C.c_int32),
-                ("lin_max_it_coarse", C.c_int32)]
+                ("lin_max_it_coarse", C.c_int32), ("coarsest_atol", C.c_double)]
 
 
 class spfas_stats(C.Structure):

@@ -215,72 +215,72 @@ int launch_fine_resid(const FineView& v, const double* x, const double* dx, doub
 
 // ------------------------------------------------------------------ linearisation
 
-// The row of S = D M^{-1} E of every cell (Picard: E = D^T; Newton:
-// E = N(sigma) kinv'(p) + D^T, Prop. 3 on level 0) and the right-hand side
-// rhs = r_p - D M^{-1} r_sigma of the eliminated system S dp = rhs, in two
-// passes.  Face pass (one thread per face j, coalesced): with m_j the
-// diagonal of M, E_K and E_L the entries of E on the face's cells and r_j its
-// flux residual, store u_K = E_K / m_j, u_L = E_L / m_j and
-// v = sigma_j - r_j / m_j.  Cell pass (one thread per cell): each face
-// contributes with the orientation d = -1 (cell K) or +1 (cell L):
-// diag += d u_own, off = d u_other, rhs += d v (summed in a fixed order).
-template <bool NEWTON>
-__global__ void __launch_bounds__(kBlock) k_fine_lin_faces(FineView v, const double* __restrict__ x,
-                                                           double* __restrict__ uk, double* __restrict__ ul,
-                                                           double* __restrict__ vs) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= v.nf) return;
-  const double* sig = x;
-  const double* p = x + v.nf;
-  const double a_ = v.alpha;
-  const int K = v.K[j], L = v.L[j];
-  const double pK = p[K];
-  const double eK = exp(-a_ * pK) * v.TKi[j];
-  double eL = 0.0, pL = 0.0;
-  if (L >= 0) {
-    pL = p[L];
-    eL = exp(-a_ * pL) * v.TLi[j];
-  }
-  const double m = eK + eL;
-  const double sj = sig[j];
-  const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
-  double EK = -1.0, EL = 1.0;
-  if (NEWTON) {
-    EK -= a_ * eK * sj;
-    EL -= a_ * eL * sj;
-  }
-  const double ainv = 1.0 / m;
-  uk[j] = ainv * EK;
-  ul[j] = ainv * EL;
-  vs[j] = sj - ainv * rs;
-}
-
-// Cell pass: a group of kLinG lanes per cell, one incidence per lane
-// (coalesced writes of the off-diagonal values), group sums for the
-// diagonal and the right-hand side.
+// Linearisation (Section 3.3) with the flux block eliminated (M is diagonal
+// on level 0): S = D M^{-1} E (Picard: E = D^T; Newton:
+// E = N(sigma) kinv'(p) + D^T, Prop. 3 on level 0) and rhs = r_p -
+// D M^{-1} r_sigma of the eliminated system S dp = rhs.  With m_j the diagonal of M on face j, E_K
+// and E_L the entries of E on its cells and r_j its flux residual, the face
+// contributes u_K = E_K / m_j, u_L = E_L / m_j and v = sigma_j - r_j / m_j
+// with the orientation d = -1 (cell K) or +1 (cell L): diag += d u_own,
+// off = d u_other, rhs += d v.
+// One pass over the cells, a group of kLinG lanes per cell and one
+// incidence per lane: each lane evaluates the coefficients of its face
+// (a face's m, E_K, E_L and r are computed by both of its cells instead of
+// being stored and gathered back) and writes its entry of the cell's row
+// of S straight into the layout the Krylov products read: the SELL-64 slots
+// of the level-0 matrix (diagonal in entry 0, the incidences in list order
+// in entries 1, 2, ...), or the DIA+CSR arrays when there is no SELL copy.
+// The diagonal and the right-hand side are group sums (fixed order).
 constexpr int kLinG = 8;
 
-__global__ void __launch_bounds__(kBlock) k_fine_linearize(FineView v, const double* __restrict__ uk,
-                                                           const double* __restrict__ ul, const double* __restrict__ vs,
-                                                           double* __restrict__ diag, double* __restrict__ off,
-                                                           double* __restrict__ rhs) {
+template <bool NEWTON, bool SELL>
+__global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const double* __restrict__ x,
+                                                           const int* __restrict__ sptr, double* __restrict__ diag,
+                                                           double* __restrict__ off, double* __restrict__ rhs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = t / kLinG;
   const int g = (int)(t % kLinG);
   if (c >= v.n) return;   // the whole group leaves together
+  const double* sig = x;
+  const double* p = x + v.nf;
+  const double a_ = v.alpha;
+  const int k0 = v.cfptr[c], k1 = v.cfptr[c + 1];
+  double* row = nullptr;
+  if constexpr (SELL) row = off + sptr[c >> 6] + (c & 63);   // slot k of the row: row[64 k]
   double dg = 0.0, rh = 0.0;
-  for (int k = v.cfptr[c] + g; k < v.cfptr[c + 1]; k += kLinG) {
+  for (int k = k0 + g; k < k1; k += kLinG) {
     const int code = v.cfcode[k];
     const int j = code >> 1;
-    if (code & 1) {
-      dg += ul[j];
-      off[k] = uk[j];
-      rh += vs[j];
-    } else {
-      dg -= uk[j];
-      off[k] = v.L[j] >= 0 ? -ul[j] : 0.0;
-      rh -= vs[j];
+    const int K = v.K[j], L = v.L[j];
+    const double pK = p[K];
+    const double eK = exp(-a_ * pK) * v.TKi[j];
+    double eL = 0.0, pL = 0.0;
+    if (L >= 0) {
+      pL = p[L];
+      eL = exp(-a_ * pL) * v.TLi[j];
     }
+    const double m = eK + eL;
+    const double sj = sig[j];
+    const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
+    double EK = -1.0, EL = 1.0;
+    if (NEWTON) {
+      EK -= a_ * eK * sj;
+      EL -= a_ * eL * sj;
+    }
+    const double ainv = 1.0 / m;
+    const double uk = ainv * EK, ul = ainv * EL, vs = sj - ainv * rs;
+    double o;
+    if (code & 1) {   // this cell is L
+      dg += ul;
+      o = uk;
+      rh += vs;
+    } else {          // this cell is K
+      dg -= uk;
+      o = L >= 0 ? -ul : 0.0;
+      rh -= vs;
+    }
+    if constexpr (SELL) row[(size_t)(1 + k - k0) << 6] = o;
+    else off[k] = o;
   }
 #pragma unroll
   for (int o = kLinG / 2; o > 0; o >>= 1) {
@@ -288,26 +288,23 @@ __global__ void __launch_bounds__(kBlock) k_fine_linearize(FineView v, const dou
     rh += __shfl_xor(rh, o, kLinG);
   }
   if (g == 0) {
-    diag[c] = dg;
+    if constexpr (SELL) row[0] = dg;
+    else diag[c] = dg;
     rhs[c] = v.f[c] + rh;
   }
 }
 
-void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
-                           double* rhs, double* work, hipStream_t s) {
+void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
+                                 double* sell_val, double* diag, double* off, double* rhs, hipStream_t s) {
   if (v.n == 0) return;
-  double* uk = work;
-  double* ul = work + v.nf;
-  double* vs = work + 2 * v.nf;
-  if (v.nf > 0) {
-    if (newton)
-      hipLaunchKernelGGL(k_fine_lin_faces<true>, dim3(grid_for(v.nf, kBlock)), dim3(kBlock), 0, s, v, x, uk, ul, vs);
-    else
-      hipLaunchKernelGGL(k_fine_lin_faces<false>, dim3(grid_for(v.nf, kBlock)), dim3(kBlock), 0, s, v, x, uk, ul, vs);
-    LAUNCHCHECK();
+  const dim3 g(grid_for((size_t)v.n * kLinG, kBlock)), b(kBlock);
+  if (sell_ptr) {
+    if (newton) hipLaunchKernelGGL((k_fine_lin_cells<true, true>), g, b, 0, s, v, x, sell_ptr, nullptr, sell_val, rhs);
+    else hipLaunchKernelGGL((k_fine_lin_cells<false, true>), g, b, 0, s, v, x, sell_ptr, nullptr, sell_val, rhs);
+  } else {
+    if (newton) hipLaunchKernelGGL((k_fine_lin_cells<true, false>), g, b, 0, s, v, x, nullptr, diag, off, rhs);
+    else hipLaunchKernelGGL((k_fine_lin_cells<false, false>), g, b, 0, s, v, x, nullptr, diag, off, rhs);
   }
-  hipLaunchKernelGGL(k_fine_linearize, dim3(grid_for((size_t)v.n * kLinG, kBlock)), dim3(kBlock), 0, s, v, uk, ul, vs,
-                     diag, off, rhs);
   LAUNCHCHECK();
 }
 

@@ -30,9 +30,12 @@ int launch_fine_resid(const FineView& v, const double* x, const double* dx, doub
 // partials of trial t at parts[t G, (t+1) G); returns G
 int launch_fine_resid_trials(const FineView& v, const double* x, const double* dx, const double* steps, int nt,
                              double* parts, hipStream_t st);
-// work: 3 nf doubles of per-face coefficients
-void launch_fine_linearize(const FineView& v, bool newton, const double* x, double* diag, double* off,
-                           double* rhs, double* work, hipStream_t s);
+// S = D M^{-1} E (Picard: E = D^T) and its right-hand side in one cell
+// pass, written into the SELL-64 slots of the level-0 matrix
+// (sell_ptr/sell_val of its Sell64View) when sell_ptr is given, else into
+// diag/off (DIA+CSR on the cell-face lists).
+void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
+                                 double* sell_val, double* diag, double* off, double* rhs, hipStream_t s);
 int launch_fine_backsub(const FineView& v, bool newton, const double* x, double* dx, double* parts,
                         hipStream_t s);
 void launch_fine_problem(const FineView& v, const int* cell_in, const int* flux_in, const double* vol,

@@ -44,7 +44,6 @@ struct FineWork {
   DVec<double> x, dx, xt;                 // [nf + n]; xt holds r(x) in the V-cycle
   DVec<double> div;                       // [n] D sigma (projection of bubbles)
   DVec<double> Sdiag, Soff, rhs;          // S = D M^{-1} E, right-hand side
-  DVec<double> lin;                       // [3 nf] per-face coefficients of the linearisation
   Amg amg;
   PrecReuse prec;
   Krylov kry;

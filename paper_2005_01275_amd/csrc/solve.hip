@@ -31,6 +31,19 @@ __global__ void __launch_bounds__(kBlock) k_neu_flux(int64_t nn, const double* _
   if (i < nn) out[face[i]] = gN ? -area[i] * gN[face[i]] : 0.0;
 }
 
+__global__ void __launch_bounds__(kBlock) k_copy_vec(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = x[i];
+}
+
+// y = x on the device (a kernel: cheaper than a copy engine transfer for
+// the small coarse vectors)
+static void launch_copy(int64_t n, const double* x, double* y, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_copy_vec, dim3(reduce_grid(n)), dim3(kBlock), 0, s, n, x, y);
+  LAUNCHCHECK();
+}
+
 void launch_axpy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
   if (!n) return;
   const int G = reduce_grid(n);
@@ -56,6 +69,7 @@ struct Opts {
   double stop_tol = 0.0;         // outer stopping threshold of the running solve
   bool newton_pcg = false;       // PCG first on Newton systems, BiCGStab as fallback
   int amg_reuse = 0;             // linearisations that may reuse AMG values (0 = none, < 0 = no limit)
+  double coarsest_atol = 1e-10;  // absolute floor of the coarsest level's test
 };
 
 static Opts make_opts(const spfas_solve_opts& o, bool newton) {
@@ -75,6 +89,7 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
   r.lin_target = o.lin_target;
   r.newton_pcg = o.newton_pcg != 0;
   r.amg_reuse = o.amg_reuse;
+  r.coarsest_atol = o.coarsest_atol >= 0.0 ? o.coarsest_atol : o.atol;
   require(o.lin_target >= 0.0, "lin_target must be non-negative");
   require(r.max_it >= 0 && r.bt_nmax >= 0 && r.coarsest_max >= 0 && r.lin_max_it > 0, "negative iteration limits");
   require(r.bt_theta > 0.0 && r.bt_theta <= 1.0, "bt_theta must be in (0, 1]");
@@ -208,7 +223,6 @@ void setup_fine_solver(Hierarchy& h) {
   w.Sdiag.alloc(n);
   w.Soff.alloc(f.cfcode.n);
   w.rhs.alloc(n);
-  w.lin.alloc(std::max<int64_t>(3 * nf, 1));
   w.S.n = (int)n;
   w.S.diag = w.Sdiag.p;
   w.S.ptr = f.cfptr.p;
@@ -218,7 +232,7 @@ void setup_fine_solver(Hierarchy& h) {
   w.x.zero(s);
   const double a = f.alpha;
   f.alpha = 0.0;
-  launch_fine_linearize(f.view(), false, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, w.lin.p, s);
+  launch_fine_linearize_cells(f.view(), false, w.x.p, nullptr, nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
   f.alpha = a;
   HIPCHECK(hipStreamSynchronize(s));
   w.amg.setup(w.S, s, true, kDenseLds, true);
@@ -237,6 +251,11 @@ void setup_fine_solver(Hierarchy& h) {
   if (w.amg.lv[0].sval64.n) {   // S products read the SELL-64 copy: value + column per stored entry
     w.kry.sell64 = &w.amg.lv[0].sell64;
     w.kry.hook.spmv_bytes = 12.0 * (double)w.amg.lv[0].sell_nnz + 24.0 * n;
+    // the linearisation writes S straight into that copy; its padding slots
+    // stay zero
+    w.amg.sell_source = true;
+    w.amg.lv[0].sval64.zero(s);
+    HIPCHECK(hipStreamSynchronize(s));
   }
 }
 
@@ -276,8 +295,12 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   const double t0 = trace_on() ? trace_clock(s) : 0.0;
   // inputs K, L, 1/T_K, 1/T_L, g, sigma per face, p and f per cell, the cell-face
   // codes; outputs the values of S (diagonal + one per incidence) and rhs
-  h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 40.0 * nf + 36.0 * n + 12.0 * (double)f.cfcode.n, s,
-             [&] { launch_fine_linearize(f.view(), o.newton, w.x.p, w.Sdiag.p, w.Soff.p, w.rhs.p, w.lin.p, s); });
+  // one pass over the cells; with a SELL copy S goes straight into it
+  const Sell64View* sv = w.amg.sell_source ? &w.amg.lv[0].sell64 : nullptr;
+  h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 40.0 * nf + 36.0 * n + 12.0 * (double)f.cfcode.n, s, [&] {
+    launch_fine_linearize_cells(f.view(), o.newton, w.x.p, sv ? sv->sptr : nullptr, sv ? const_cast<double*>(sv->val)
+                                : nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
+  });
   const bool fresh = prec_refresh(w.amg, w.prec, o, s);
   double* dp = w.dx.p + nf;
   int it;
@@ -484,7 +507,7 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
 // there.  A step Alg. 1 accepted while the residual rose does not end it.
 static void coarsest_solve(Hierarchy& h, int l, const Opts& o, spfas_stats& st) {
   double r = coarse_rnorm(h, l, h.coarse[l - 1]->x.p, nullptr, 0.0);
-  const double tol = std::max(o.rtol * r, o.atol);
+  const double tol = std::max(o.rtol * r, o.coarsest_atol);
   for (int i = 0; i < o.coarsest_max; ++i) {
     if (r <= tol) break;
     bool moved = false;
@@ -537,7 +560,7 @@ static double nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, 
   TransferDev& T = *h.trans[l];
   const int64_t nc = Cc.nf + Cc.np;
   launch_project(T, Cc, x, div, Cc.x.p, s);
-  HIPCHECK(hipMemcpyAsync(Cc.x0.p, Cc.x.p, nc * sizeof(double), hipMemcpyDeviceToDevice, s));
+  launch_copy(nc, Cc.x.p, Cc.x0.p, s);
   launch_restrict(T, Cc, r, Cc.b.p, s);
   launch_coarse_resid(Cc, alpha, Cc.x.p, nullptr, 0.0, Cc.zeros.p, Cc.ax.p, h.parts.p, s);
   launch_sub(nc, Cc.ax.p, Cc.b.p, Cc.b.p, s);

@@ -456,6 +456,12 @@ __global__ void __launch_bounds__(kBlock) k_restrict_vec(int nc, const int* __re
   if (g == 0) bc[I] = s;
 }
 
+// DIA+CSR values of a level from its FP64 SELL copy (the inverse of
+// k_sell_fill; padding slots are skipped).
+__global__ void __launch_bounds__(kBlock) k_sell_to_csr(int ne, const int* __restrict__ smap,
+                                                        const double* __restrict__ val64, double* __restrict__ diag,
+                                                        double* __restrict__ off);
+
 // FP32 SELL values from the FP64 DIA+CSR values of the level.
 constexpr int kSellPad = INT_MIN;
 __global__ void __launch_bounds__(kBlock) k_sell_fill(int ne, const int* __restrict__ smap,
@@ -1224,6 +1230,7 @@ void Amg::numeric(hipStream_t s) {
     numeric_classical(s);
     return;
   }
+  if (sell_source) sell_to_csr(s);
   for (size_t k = 0; k + 1 < lv.size(); ++k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
@@ -1252,9 +1259,28 @@ void Amg::numeric(hipStream_t s) {
   dense_numeric(s);
 }
 
+__global__ void __launch_bounds__(kBlock) k_sell_to_csr(int ne, const int* __restrict__ smap,
+                                                        const double* __restrict__ val64, double* __restrict__ diag,
+                                                        double* __restrict__ off) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  const int m = smap[e];
+  if (m >= 0) off[m] = val64[e];
+  else if (m != kSellPad) diag[-1 - m] = val64[e];
+}
+
+void Amg::sell_to_csr(hipStream_t s) {
+  AmgLevel& F = lv[0];
+  const int ne = (int)F.sval64.n;
+  require(ne > 0, "sell_to_csr without a SELL copy");
+  hipLaunchKernelGGL(k_sell_to_csr, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.sval64.p,
+                     const_cast<double*>(F.view.diag), const_cast<double*>(F.view.val));
+  LAUNCHCHECK();
+}
+
 void Amg::operator_values(hipStream_t s) {
   AmgLevel& F = lv[0];
-  if (!F.sval64.n) return;
+  if (!F.sval64.n || sell_source) return;   // SELL source: the Krylov operator is already current
   const int ne = (int)F.sval64.n;
   hipLaunchKernelGGL(k_sell_fill, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.view.diag,
                      F.view.val, (float*)nullptr, F.sval64.p);
@@ -1263,6 +1289,7 @@ void Amg::operator_values(hipStream_t s) {
 
 void Amg::numeric_classical(hipStream_t s) {
   const int L = (int)lv.size();
+  if (sell_source) sell_to_csr(s);
   for (int k = 0; k + 1 < L; ++k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];

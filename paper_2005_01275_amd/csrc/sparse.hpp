@@ -164,6 +164,11 @@ struct Amg {
   DVec<int> piv;                      // [nd]
   DVec<int> flag;                     // singular-pivot flag
   int cycles = 1;
+  // level-0 values are written by the caller into the FP64 SELL copy
+  // (sval64); the DIA+CSR arrays of `view` are refreshed from it only when
+  // the preconditioner values are recomputed
+  bool sell_source = false;
+  void sell_to_csr(hipStream_t s);
   // host setup from the matrix pattern and setup values
   // sell64: also keep FP64 SELL values of level 0 (for Krylov::sell64)
   // classical: classical coarsening (falls back to aggregation when the first

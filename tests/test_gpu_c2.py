@@ -26,7 +26,7 @@ def c2():
 # forcing 0.03, coarse tolerance 1e-2 with at most 10 iterations, PCG first
 # on Newton systems, AMG values reused)
 BENCH_INNER = dict(lin_rtol=1e-5, lin_max_it=400, lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1,
-                   amg_reuse=-1, lin_max_it_coarse=10)
+                   amg_reuse=-1, lin_max_it_coarse=10, coarsest_atol=1e-10)
 
 
 @pytest.mark.parametrize("inner", ["plain", "bench"])

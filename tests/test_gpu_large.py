@@ -74,7 +74,7 @@ def test_512_bench_options_meet_rtol(case):
     prob, H, p_star, _ = case
     o = pk.SolveOpts(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=1e-5, lin_max_it=400,
                      lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1, amg_reuse=-1, lin_max_it_coarse=10,
-                     dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
+                     coarsest_atol=1e-10, dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
     p, s, st = H.fas_solve(prob, o)
     assert st["converged"], st
     fs = FineSystem(prob)

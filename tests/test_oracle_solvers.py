@@ -46,8 +46,8 @@ def script(monkeypatch):
     return make
 
 
-def run_coarsest(sc, rtol=1e-8, atol=0.0, cmax=10):
-    o = S.Opts(rtol=rtol, atol=atol, coarsest_max=cmax)
+def run_coarsest(sc, rtol=1e-8, atol=0.0, cmax=10, catol=None):
+    o = S.Opts(rtol=rtol, atol=atol, coarsest_max=cmax, coarsest_atol=catol)
     x = S.coarsest_solve(None, 0, None, 1.0, o)
     return int(x), sc.steps
 
@@ -75,6 +75,11 @@ def test_coarsest_tolerance_is_relative_to_the_entry_residual(script):
     # atol above rtol * entry decides
     sc = script([1.0, 1e-3, 5e-5, 1e-9])
     assert run_coarsest(sc, atol=1e-4) == (2, 2)
+    # the coarsest level's own absolute floor replaces atol when given
+    sc = script([1.0, 1e-3, 5e-5, 1e-9])
+    assert run_coarsest(sc, atol=0.0, catol=1e-4) == (2, 2)
+    sc = script([1.0, 1e-3, 5e-5, 1e-9])
+    assert run_coarsest(sc, atol=1e-4, catol=0.0) == (3, 3)
 
 
 def test_coarsest_stops_on_a_rejected_step(script):
