@@ -56,6 +56,7 @@ typedef enum {
 typedef enum { SPFAS_MEM_HOST = 0, SPFAS_MEM_DEVICE = 1 } spfas_mem;
 typedef enum { SPFAS_FACE_INTERIOR = 0, SPFAS_FACE_DIRICHLET = 1, SPFAS_FACE_NEUMANN = 2 } spfas_face_kind;
 typedef enum { SPFAS_NEWTON = 0, SPFAS_PICARD = 1 } spfas_smoother;
+typedef enum { SPFAS_PREC_FP64 = 0, SPFAS_PREC_MIXED = 1 } spfas_precision;
 
 /*
  * Mesh (Section 2.1).  HOST memory, read during spfas_setup_hierarchy only.
@@ -212,6 +213,16 @@ typedef struct {
  *                       absolute 1e-10); < 0: atol.  Lets the outer solve run
  *                       with atol = 0 (a pure relative stop) while the
  *                       coarsest level keeps the paper's absolute floor
+ *   precision           SPFAS_PREC_FP64, or SPFAS_PREC_MIXED: the level-0
+ *                       linearised systems are stored (S in its SELL layout
+ *                       and the right-hand side) and solved (Krylov vectors,
+ *                       AMG cycle input and output) in FP32, while the
+ *                       residual, the Jacobian entries, the flux
+ *                       back-substitution, Alg. 1 and the state update stay
+ *                       FP64: every smoothing step corrects the FP64 defect,
+ *                       so the solve reaches the same FP64 root.  Coarse
+ *                       levels are unchanged (FP64).  A level-0 AMG that is
+ *                       not classical keeps the FP64 path.
  */
 typedef struct {
   int32_t smoother;
@@ -231,6 +242,7 @@ typedef struct {
   int32_t amg_reuse;
   int32_t lin_max_it_coarse;
   double coarsest_atol;
+  int32_t precision;
 } spfas_solve_opts;
 
 typedef struct {

@@ -16,7 +16,7 @@ import numpy as np
 
 from . import _native as N
 from ._native import (SPFAS_OK, SPFAS_NOT_CONVERGED, SPFAS_MEM_HOST, SPFAS_MEM_DEVICE, SPFAS_NEWTON,
-                      SPFAS_PICARD, SpfasError)
+                      SPFAS_PICARD, SPFAS_PREC_FP64, SPFAS_PREC_MIXED, SpfasError)
 
 __all__ = ["Hierarchy", "SolveOpts", "SpfasError", "SPFAS_NEWTON", "SPFAS_PICARD", "lib"]
 
@@ -48,6 +48,7 @@ class SolveOpts:
     amg_reuse: int = 0
     lin_max_it_coarse: int = 0
     coarsest_atol: float = -1.0
+    precision: int = N.SPFAS_PREC_FP64
 
     def c(self):
         o = N.spfas_solve_opts()

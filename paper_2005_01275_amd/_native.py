@@ -13,6 +13,7 @@ SPFAS_OK, SPFAS_NOT_CONVERGED = 0, 1
 SPFAS_ERR_INVALID, SPFAS_ERR_OOM, SPFAS_ERR_DEVICE, SPFAS_ERR_NUMERIC = -1, -2, -3, -4
 SPFAS_MEM_HOST, SPFAS_MEM_DEVICE = 0, 1
 SPFAS_NEWTON, SPFAS_PICARD = 0, 1
+SPFAS_PREC_FP64, SPFAS_PREC_MIXED = 0, 1
 SPFAS_AGG_BOX, SPFAS_AGG_USER, SPFAS_AGG_GREEDY = 0, 1, 2
 SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SPFAS_OP_W, SPFAS_OP_QSIGMA = range(7)
 
@@ -69,7 +70,7 @@ class spfas_solve_opts(C.Structure):
                 ("coarsest_max_steps", C.c_int32), ("lin_rtol", C.c_double), ("lin_max_it", C.c_int32),
                 ("x0_given", C.c_int32), ("lin_rtol_coarse", C.c_double), ("lin_target", C.c_double),
                 ("newton_pcg", C.c_int32), ("amg_reuse", C.c_int32),
-                ("lin_max_it_coarse", C.c_int32), ("coarsest_atol", C.c_double)]
+                ("lin_max_it_coarse", C.c_int32), ("coarsest_atol", C.c_double), ("precision", C.c_int32)]
 
 
 class spfas_stats(C.Structure):

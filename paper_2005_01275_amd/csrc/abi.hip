@@ -61,6 +61,7 @@ void spfas_default_solve_opts(spfas_solve_opts* o) {
   o->amg_reuse = 0;
   o->lin_max_it_coarse = 0;
   o->coarsest_atol = -1.0;
+  o->precision = SPFAS_PREC_FP64;
 }
 
 int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts, const spfas_allocator* allocator,

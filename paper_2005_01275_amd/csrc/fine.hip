@@ -233,10 +233,13 @@ int launch_fine_resid(const FineView& v, const double* x, const double* dx, doub
 // The diagonal and the right-hand side are group sums (fixed order).
 constexpr int kLinG = 8;
 
-template <bool NEWTON, bool SELL>
+// TV: storage of the SELL values and of the right-hand side (FP64, or FP32
+// in mixed precision); everything is computed in FP64.
+template <bool NEWTON, bool SELL, class TV>
 __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const double* __restrict__ x,
                                                            const int* __restrict__ sptr, double* __restrict__ diag,
-                                                           double* __restrict__ off, double* __restrict__ rhs) {
+                                                           double* __restrict__ off, TV* __restrict__ sval,
+                                                           TV* __restrict__ rhs) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = t / kLinG;
   const int g = (int)(t % kLinG);
@@ -245,8 +248,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
   const double* p = x + v.nf;
   const double a_ = v.alpha;
   const int k0 = v.cfptr[c], k1 = v.cfptr[c + 1];
-  double* row = nullptr;
-  if constexpr (SELL) row = off + sptr[c >> 6] + (c & 63);   // slot k of the row: row[64 k]
+  TV* row = nullptr;
+  if constexpr (SELL) row = sval + sptr[c >> 6] + (c & 63);   // slot k of the row: row[64 k]
   double dg = 0.0, rh = 0.0;
   for (int k = k0 + g; k < k1; k += kLinG) {
     const int code = v.cfcode[k];
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
       o = L >= 0 ? -ul : 0.0;
       rh -= vs;
     }
-    if constexpr (SELL) row[(size_t)(1 + k - k0) << 6] = o;
+    if constexpr (SELL) row[(size_t)(1 + k - k0) << 6] = (TV)o;
     else off[k] = o;
   }
 #pragma unroll
@@ -288,23 +291,51 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
     rh += __shfl_xor(rh, o, kLinG);
   }
   if (g == 0) {
-    if constexpr (SELL) row[0] = dg;
+    if constexpr (SELL) row[0] = (TV)dg;
     else diag[c] = dg;
-    rhs[c] = v.f[c] + rh;
+    rhs[c] = (TV)(v.f[c] + rh);
   }
+}
+
+template <class TV>
+static void lin_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr, TV* sell_val,
+                      double* diag, double* off, TV* rhs, hipStream_t s) {
+  if (v.n == 0) return;
+  const dim3 g(grid_for((size_t)v.n * kLinG, kBlock)), b(kBlock);
+  if (sell_ptr) {
+    if (newton)
+      hipLaunchKernelGGL((k_fine_lin_cells<true, true, TV>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr, sell_val,
+                         rhs);
+    else
+      hipLaunchKernelGGL((k_fine_lin_cells<false, true, TV>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr, sell_val,
+                         rhs);
+  } else {
+    if (newton)
+      hipLaunchKernelGGL((k_fine_lin_cells<true, false, TV>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
+    else
+      hipLaunchKernelGGL((k_fine_lin_cells<false, false, TV>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
+  }
+  LAUNCHCHECK();
 }
 
 void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
                                  double* sell_val, double* diag, double* off, double* rhs, hipStream_t s) {
-  if (v.n == 0) return;
-  const dim3 g(grid_for((size_t)v.n * kLinG, kBlock)), b(kBlock);
-  if (sell_ptr) {
-    if (newton) hipLaunchKernelGGL((k_fine_lin_cells<true, true>), g, b, 0, s, v, x, sell_ptr, nullptr, sell_val, rhs);
-    else hipLaunchKernelGGL((k_fine_lin_cells<false, true>), g, b, 0, s, v, x, sell_ptr, nullptr, sell_val, rhs);
-  } else {
-    if (newton) hipLaunchKernelGGL((k_fine_lin_cells<true, false>), g, b, 0, s, v, x, nullptr, diag, off, rhs);
-    else hipLaunchKernelGGL((k_fine_lin_cells<false, false>), g, b, 0, s, v, x, nullptr, diag, off, rhs);
-  }
+  lin_cells<double>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
+}
+
+void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
+                                 float* sell_val, double* diag, double* off, float* rhs, hipStream_t s) {
+  lin_cells<float>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
+}
+
+__global__ void __launch_bounds__(kBlock) k_widen(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = (double)a[i];
+}
+
+void launch_widen(int64_t n, const float* a, double* b, hipStream_t s) {
+  if (!n) return;
+  hipLaunchKernelGGL(k_widen, dim3(reduce_grid(n)), dim3(kBlock), 0, s, n, a, b);
   LAUNCHCHECK();
 }
 

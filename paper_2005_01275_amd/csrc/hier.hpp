@@ -48,6 +48,11 @@ struct FineWork {
   PrecReuse prec;
   Krylov kry;
   CsrView S;
+  // mixed precision: FP32 copy of S in the SELL layout, FP32 right-hand
+  // side and correction, FP32 Krylov vectors
+  Krylov32 kry32;
+  DVec<float> sval32, rhs32, dp32;
+  Sell32View S32;
 };
 
 struct Hierarchy {

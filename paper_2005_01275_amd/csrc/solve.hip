@@ -70,6 +70,7 @@ struct Opts {
   bool newton_pcg = false;       // PCG first on Newton systems, BiCGStab as fallback
   int amg_reuse = 0;             // linearisations that may reuse AMG values (0 = none, < 0 = no limit)
   double coarsest_atol = 1e-10;  // absolute floor of the coarsest level's test
+  bool mixed = false;            // FP32 level-0 linear solves inside the FP64 residual and update
 };
 
 static Opts make_opts(const spfas_solve_opts& o, bool newton) {
@@ -90,6 +91,9 @@ static Opts make_opts(const spfas_solve_opts& o, bool newton) {
   r.newton_pcg = o.newton_pcg != 0;
   r.amg_reuse = o.amg_reuse;
   r.coarsest_atol = o.coarsest_atol >= 0.0 ? o.coarsest_atol : o.atol;
+  require(o.precision == SPFAS_PREC_FP64 || o.precision == SPFAS_PREC_MIXED,
+          "precision must be SPFAS_PREC_FP64 or SPFAS_PREC_MIXED");
+  r.mixed = o.precision == SPFAS_PREC_MIXED;
   require(o.lin_target >= 0.0, "lin_target must be non-negative");
   require(r.max_it >= 0 && r.bt_nmax >= 0 && r.coarsest_max >= 0 && r.lin_max_it > 0, "negative iteration limits");
   require(r.bt_theta > 0.0 && r.bt_theta <= 1.0, "bt_theta must be in (0, 1]");
@@ -147,8 +151,9 @@ constexpr int kPcgStall = 5;
 // BiCGStab for Newton, or PCG first with BiCGStab from scratch when PCG
 // breaks down, stalls or does not converge; the limit counts the iterations
 // of both.
-static int krylov_solve(Krylov& kry, const CsrView& A, Amg* M, const double* b, double* x, double rtol,
-                        const Opts& o, hipStream_t s) {
+template <class T>
+static int krylov_solve(KrylovT<T>& kry, const CsrView& A, Amg* M, const T* b, T* x, double rtol, const Opts& o,
+                        hipStream_t s) {
   if (!o.newton) return kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
   if (o.newton_pcg) {
     const int it = kry.pcg(A, M, b, x, rtol, o.lin_max_it, s, kPcgStall);
@@ -249,14 +254,32 @@ void setup_fine_solver(Hierarchy& h) {
   w.kry.hook = hk;
   w.amg.hook = hk;
   if (w.amg.lv[0].sval64.n) {   // S products read the SELL-64 copy: value + column per stored entry
-    w.kry.sell64 = &w.amg.lv[0].sell64;
+    w.kry.sell = &w.amg.lv[0].sell64;
     w.kry.hook.spmv_bytes = 12.0 * (double)w.amg.lv[0].sell_nnz + 24.0 * n;
     // the linearisation writes S straight into that copy; its padding slots
     // stay zero
     w.amg.sell_source = true;
     w.amg.lv[0].sval64.zero(s);
-    HIPCHECK(hipStreamSynchronize(s));
   }
+  // mixed precision (classical AMG only): FP32 twins of the SELL values,
+  // the right-hand side, the correction and the Krylov vectors
+  if (w.amg.classical) {
+    w.rhs32.alloc(n);
+    w.dp32.alloc(n);
+    w.kry32.hook = w.kry.hook;
+    if (w.amg.sell_source) {
+      const AmgLevel& F0 = w.amg.lv[0];
+      w.sval32.alloc(F0.sval64.n);
+      w.sval32.zero(s);
+      w.S32.n = F0.sell64.n;
+      w.S32.sptr = F0.sell64.sptr;
+      w.S32.col = F0.sell64.col;
+      w.S32.val = w.sval32.p;
+      w.kry32.sell = &w.S32;
+      w.kry32.hook.spmv_bytes = 8.0 * (double)F0.sell_nnz + 12.0 * n;
+    }
+  }
+  HIPCHECK(hipStreamSynchronize(s));
 }
 
 // ||r(x + s_t dx)|| for t < k in one pass (Alg. 1 halvings): the same values
@@ -295,11 +318,21 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   const double t0 = trace_on() ? trace_clock(s) : 0.0;
   // inputs K, L, 1/T_K, 1/T_L, g, sigma per face, p and f per cell, the cell-face
   // codes; outputs the values of S (diagonal + one per incidence) and rhs
-  // one pass over the cells; with a SELL copy S goes straight into it
+  // one pass over the cells; with a SELL copy S goes straight into it.
+  // Mixed precision: S (in the SELL layout) and the right-hand side are
+  // stored in FP32 and the linear system is solved in FP32; the residual,
+  // the back-substitution, Alg. 1 and the update stay FP64, so each step
+  // corrects the FP64 defect (defect correction).
+  const bool mixed = o.mixed && w.amg.classical;
   const Sell64View* sv = w.amg.sell_source ? &w.amg.lv[0].sell64 : nullptr;
+  w.amg.sell_src32 = mixed && sv ? w.sval32.p : nullptr;
   h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 40.0 * nf + 36.0 * n + 12.0 * (double)f.cfcode.n, s, [&] {
-    launch_fine_linearize_cells(f.view(), o.newton, w.x.p, sv ? sv->sptr : nullptr, sv ? const_cast<double*>(sv->val)
-                                : nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
+    if (mixed)
+      launch_fine_linearize_cells(f.view(), o.newton, w.x.p, sv ? sv->sptr : nullptr, sv ? w.sval32.p : nullptr,
+                                  w.Sdiag.p, w.Soff.p, w.rhs32.p, s);
+    else
+      launch_fine_linearize_cells(f.view(), o.newton, w.x.p, sv ? sv->sptr : nullptr,
+                                  sv ? const_cast<double*>(sv->val) : nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
   });
   const bool fresh = prec_refresh(w.amg, w.prec, o, s);
   double* dp = w.dx.p + nf;
@@ -307,11 +340,19 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   double eta = o.lin_rtol;
   if (o.lin_target > 0.0 && o.stop_tol > 0.0 && r_x > 0.0)
     eta = std::max(eta, std::min(0.1, o.lin_target * o.stop_tol / r_x));
-  it = krylov_solve(w.kry, w.S, &w.amg, w.rhs.p, dp, eta, o, s);
-  prec_record(w.prec, fresh, it, w.kry.failed);
+  bool failed;
+  if (mixed) {
+    it = krylov_solve(w.kry32, w.S, &w.amg, w.rhs32.p, w.dp32.p, eta, o, s);
+    failed = w.kry32.failed;
+    if (!failed) launch_widen(n, w.dp32.p, dp, s);
+  } else {
+    it = krylov_solve(w.kry, w.S, &w.amg, w.rhs.p, dp, eta, o, s);
+    failed = w.kry.failed;
+  }
+  prec_record(w.prec, fresh, it, failed);
   st.lin_iters += it;
   double mx = HUGE_VAL;
-  if (!w.kry.failed) {
+  if (!failed) {
     const int G = launch_fine_backsub(f.view(), o.newton, w.x.p, w.dx.p, h.dpin, s);
     mx = h.host_max(G);
   }

@@ -39,22 +39,30 @@ void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s) {
 }
 
 // Row products of the two matrix layouts the Krylov solvers read.
-__device__ inline double row_dot(const CsrView& A, int i, const double* __restrict__ x) {
-  double a = A.diag[i] * x[i];
-  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * x[A.col[k]];
+// Products are summed in FP64 whatever the storage of values and vectors.
+template <class T>
+__device__ inline double row_dot(const CsrView& A, int i, const T* __restrict__ x) {
+  double a = A.diag[i] * (double)x[i];
+  for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) a += A.val[k] * (double)x[A.col[k]];
   return a;
 }
 
-__device__ inline double row_dot(const Sell64View& A, int i, const double* __restrict__ x) {
+template <class Mat, class T>
+__device__ inline double row_dot_sell(const Mat& A, int i, const T* __restrict__ x) {
   const int sl = i >> 6;
   const int a0 = A.sptr[sl];
   const int width = (A.sptr[sl + 1] - a0) >> 6;
   int e = a0 + (i & 63);
   double a = 0.0;
 #pragma unroll 4
-  for (int k = 0; k < width; ++k, e += 64) a += ld_stream(A.val + e) * x[ld_stream(A.col + e)];
+  for (int k = 0; k < width; ++k, e += 64) a += (double)ld_stream(A.val + e) * (double)x[ld_stream(A.col + e)];
   return a;
 }
+
+template <class T>
+__device__ inline double row_dot(const Sell64View& A, int i, const T* __restrict__ x) { return row_dot_sell(A, i, x); }
+template <class T>
+__device__ inline double row_dot(const Sell32View& A, int i, const T* __restrict__ x) { return row_dot_sell(A, i, x); }
 
 // Rows [lo, hi) of the logical block: contiguous chunks (multiples of
 // `align` rows) in XCD-aware order.
@@ -70,31 +78,32 @@ __device__ inline void block_rows(int n, int& lb, int& lo, int& hi, int align = 
 // matrix (about 6 % faster there than 256 or 1024), kBlock elsewhere.
 template <class Mat> struct SpmvBlock { static constexpr int v = kBlock; };
 template <> struct SpmvBlock<Sell64View> { static constexpr int v = 512; };
+template <> struct SpmvBlock<Sell32View> { static constexpr int v = 512; };
 
 // y = A x; parts = sum_i w_i y_i (w may be x itself or another vector).
 // The template flag only separates the finest-level launches by name.
-template <class Mat, bool Finest>
-__global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_spmv_dot(Mat A, const double* __restrict__ x,
-                                                                double* __restrict__ y, const double* __restrict__ w,
+template <class Mat, bool Finest, class T>
+__global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_spmv_dot(Mat A, const T* __restrict__ x,
+                                                                T* __restrict__ y, const T* __restrict__ w,
                                                                 double* __restrict__ parts) {
   __shared__ double sh[SpmvBlock<Mat>::v / 64];
   int lb, lo, hi;
   block_rows(A.n, lb, lo, hi, 64);
   double acc = 0.0;
   for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
-    const double a = row_dot(A, i, x);
+    const T a = (T)row_dot(A, i, x);
     y[i] = a;
-    acc += w[i] * a;
+    acc += (double)w[i] * (double)a;
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[lb] = acc;
 }
 
 // y = A x; parts0 = sum w0*y, parts1 = sum y*y
-template <class Mat, bool Finest>
-__global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_spmv_dot2(Mat A, const double* __restrict__ x,
-                                                                 double* __restrict__ y,
-                                                                 const double* __restrict__ w0,
+template <class Mat, bool Finest, class T>
+__global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_spmv_dot2(Mat A, const T* __restrict__ x,
+                                                                 T* __restrict__ y,
+                                                                 const T* __restrict__ w0,
                                                                  double* __restrict__ parts0,
                                                                  double* __restrict__ parts1) {
   __shared__ double sh[SpmvBlock<Mat>::v / 64];
@@ -102,21 +111,23 @@ __global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_spmv_dot2(Mat A, const do
   block_rows(A.n, lb, lo, hi, 64);
   double a0 = 0.0, a1 = 0.0;
   for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
-    const double a = row_dot(A, i, x);
+    const T a = (T)row_dot(A, i, x);
     y[i] = a;
-    a0 += w0[i] * a;
-    a1 += a * a;
+    a0 += (double)w0[i] * (double)a;
+    a1 += (double)a * (double)a;
   }
   a0 = block_sum(a0, sh);
   a1 = block_sum(a1, sh);
   if (threadIdx.x == 0) { parts0[lb] = a0; parts1[lb] = a1; }
 }
 
-__global__ void __launch_bounds__(kBlock) k_dot(int n, const double* __restrict__ a, const double* __restrict__ b,
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot(int n, const T* __restrict__ a, const T* __restrict__ b,
                                                 double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
   double acc = 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) acc += a[i] * b[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    acc += (double)a[i] * (double)b[i];
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
 }
@@ -144,9 +155,10 @@ __device__ inline double all_parts(const double* __restrict__ parts, int G, doub
 // stores it in slot `cur`), beta = rz / scal[old] (0 on the first
 // iteration), p = z + beta p (p = z on the first iteration, whatever p
 // held before).
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_pcg_p2(int n, const double* __restrict__ prz, int G, double* scal, int cur,
-                                                   int old, int first, const double* __restrict__ z,
-                                                   double* __restrict__ p) {
+                                                   int old, int first, const T* __restrict__ z,
+                                                   T* __restrict__ p) {
   __shared__ double sh[kBlock / 64];
   __shared__ double bc;
   const double rz = all_parts(prz, G, sh, &bc);
@@ -154,22 +166,25 @@ __global__ void __launch_bounds__(kBlock) k_pcg_p2(int n, const double* __restri
   const double ro = scal[old];
   const double beta = (first || ro == 0.0) ? 0.0 : rz / ro;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = first ? z[i] : z[i] + beta * p[i];
+    p[i] = first ? z[i] : (T)((double)z[i] + beta * (double)p[i]);
 }
 
 // Takes back the last PCG update of x: x -= (rz / pq) p with the alpha
 // k_pcg_xr2 used (rz in scal[rz_slot], pq its p.q).
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_pcg_undo(int n, const double* __restrict__ scal, int rz_slot, double pq,
-                                                     double* __restrict__ x, const double* __restrict__ p) {
+                                                     T* __restrict__ x, const T* __restrict__ p) {
   const double alpha = pq != 0.0 ? scal[rz_slot] / pq : 0.0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[i] -= alpha * p[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    x[i] = (T)((double)x[i] - alpha * (double)p[i]);
 }
 
 // pq = sum of the p.q partials (block 0 stores it in S_PQ and in *hpq),
 // alpha = rz / pq, x += alpha p, r -= alpha q, r.r partials.
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_pcg_xr2(int n, const double* __restrict__ ppq, int G, double* scal, int rz,
-                                                    double* __restrict__ x, double* __restrict__ r,
-                                                    const double* __restrict__ p, const double* __restrict__ q,
+                                                    T* __restrict__ x, T* __restrict__ r,
+                                                    const T* __restrict__ p, const T* __restrict__ q,
                                                     double* __restrict__ parts, double* __restrict__ hpq) {
   __shared__ double sh[kBlock / 64];
   __shared__ double bc;
@@ -181,33 +196,36 @@ __global__ void __launch_bounds__(kBlock) k_pcg_xr2(int n, const double* __restr
   const double alpha = pq != 0.0 ? scal[rz] / pq : 0.0;
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+    x[i] = (T)((double)x[i] + alpha * (double)p[i]);
+    const T ri = (T)((double)r[i] - alpha * (double)q[i]);
     r[i] = ri;
-    acc += ri * ri;
+    acc += (double)ri * (double)ri;
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
 }
 
 // BiCGStab: p = r + beta (p - omega v), beta = (rho/rho_old)(alpha/omega)
+template <class T>
 __global__ void __launch_bounds__(kBlock) k_bicg_p(int n, const double* __restrict__ scal, int rho, int rho_old,
-                                                   int first, const double* __restrict__ r, double* __restrict__ p,
-                                                   const double* __restrict__ v) {
+                                                   int first, const T* __restrict__ r, T* __restrict__ p,
+                                                   const T* __restrict__ v) {
   double beta = 0.0, omega = 0.0;
   if (!first) {
     beta = (scal[rho] / scal[rho_old]) * (scal[S_ALPHA] / scal[S_OMEGA]);
     omega = scal[S_OMEGA];
   }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    p[i] = first ? r[i] : r[i] + beta * (p[i] - omega * v[i]);
+    p[i] = first ? r[i] : (T)((double)r[i] + beta * ((double)p[i] - omega * (double)v[i]));
 }
 
 // alpha = rho / (rh.v); s = r - alpha v (into s); writes alpha to scal
-__global__ void __launch_bounds__(kBlock) k_bicg_s(int n, double* __restrict__ scal, int rho, const double* __restrict__ r,
-                                                   const double* __restrict__ v, double* __restrict__ s) {
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_bicg_s(int n, double* __restrict__ scal, int rho, const T* __restrict__ r,
+                                                   const T* __restrict__ v, T* __restrict__ s) {
   const double alpha = scal[rho] / scal[S_RV];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) s[i] = r[i] - alpha * v[i];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    s[i] = (T)((double)r[i] - alpha * (double)v[i]);
   if (blockIdx.x == 0 && threadIdx.x == 0) scal[S_ALPHA] = alpha;
 }
 
@@ -229,38 +247,40 @@ __global__ void __launch_bounds__(kBlock) k_finalize2(const double* __restrict__
 }
 
 // BiCGStab start: x = 0, r = rh = b, parts = b.b
-__global__ void __launch_bounds__(kBlock) k_bicg_init(int n, const double* __restrict__ b, double* __restrict__ x,
-                                                      double* __restrict__ r, double* __restrict__ rh,
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_bicg_init(int n, const T* __restrict__ b, T* __restrict__ x,
+                                                      T* __restrict__ r, T* __restrict__ rh,
                                                       double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
   double acc = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double bi = b[i];
-    x[i] = 0.0;
+    const T bi = b[i];
+    x[i] = (T)0;
     r[i] = bi;
     rh[i] = bi;
-    acc += bi * bi;
+    acc += (double)bi * (double)bi;
   }
   acc = block_sum(acc, sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = acc;
 }
 
 // x += alpha y + omega z; r = s - omega t; parts0 = r.r, parts1 = rh.r
-__global__ void __launch_bounds__(kBlock) k_bicg_xr(int n, const double* __restrict__ scal, double* __restrict__ x,
-                                                    const double* __restrict__ y, const double* __restrict__ z,
-                                                    double* __restrict__ r, const double* __restrict__ s,
-                                                    const double* __restrict__ t, const double* __restrict__ rh,
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_bicg_xr(int n, const double* __restrict__ scal, T* __restrict__ x,
+                                                    const T* __restrict__ y, const T* __restrict__ z,
+                                                    T* __restrict__ r, const T* __restrict__ s,
+                                                    const T* __restrict__ t, const T* __restrict__ rh,
                                                     double* __restrict__ parts0, double* __restrict__ parts1) {
   __shared__ double sh[kBlock / 64];
   const double alpha = scal[S_ALPHA];
   const double omega = scal[S_OMEGA];
   double a0 = 0.0, a1 = 0.0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    x[i] += alpha * y[i] + omega * z[i];
-    const double ri = s[i] - omega * t[i];
+    x[i] = (T)((double)x[i] + (alpha * (double)y[i] + omega * (double)z[i]));
+    const T ri = (T)((double)s[i] - omega * (double)t[i]);
     r[i] = ri;
-    a0 += ri * ri;
-    a1 += rh[i] * ri;
+    a0 += (double)ri * (double)ri;
+    a1 += (double)rh[i] * (double)ri;
   }
   a0 = block_sum(a0, sh);
   a1 = block_sum(a1, sh);
@@ -268,11 +288,13 @@ __global__ void __launch_bounds__(kBlock) k_bicg_xr(int n, const double* __restr
 }
 
 
-__global__ void __launch_bounds__(kBlock) k_copy(int n, const double* __restrict__ a, double* __restrict__ b) {
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_copy(int n, const T* __restrict__ a, T* __restrict__ b) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = a[i];
 }
 
-__global__ void __launch_bounds__(kBlock) k_zero(int n, double* __restrict__ b) {
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_zero(int n, T* __restrict__ b) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) b[i] = 0.0;
 }
 
@@ -458,8 +480,9 @@ __global__ void __launch_bounds__(kBlock) k_restrict_vec(int nc, const int* __re
 
 // DIA+CSR values of a level from its FP64 SELL copy (the inverse of
 // k_sell_fill; padding slots are skipped).
+template <class V>
 __global__ void __launch_bounds__(kBlock) k_sell_to_csr(int ne, const int* __restrict__ smap,
-                                                        const double* __restrict__ val64, double* __restrict__ diag,
+                                                        const V* __restrict__ val, double* __restrict__ diag,
                                                         double* __restrict__ off);
 
 // FP32 SELL values from the FP64 DIA+CSR values of the level.
@@ -1259,22 +1282,29 @@ void Amg::numeric(hipStream_t s) {
   dense_numeric(s);
 }
 
+template <class V>
 __global__ void __launch_bounds__(kBlock) k_sell_to_csr(int ne, const int* __restrict__ smap,
-                                                        const double* __restrict__ val64, double* __restrict__ diag,
+                                                        const V* __restrict__ val, double* __restrict__ diag,
                                                         double* __restrict__ off) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int m = smap[e];
-  if (m >= 0) off[m] = val64[e];
-  else if (m != kSellPad) diag[-1 - m] = val64[e];
+  if (m >= 0) off[m] = (double)val[e];
+  else if (m != kSellPad) diag[-1 - m] = (double)val[e];
 }
 
 void Amg::sell_to_csr(hipStream_t s) {
   AmgLevel& F = lv[0];
   const int ne = (int)F.sval64.n;
   require(ne > 0, "sell_to_csr without a SELL copy");
-  hipLaunchKernelGGL(k_sell_to_csr, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.sval64.p,
-                     const_cast<double*>(F.view.diag), const_cast<double*>(F.view.val));
+  double* diag = const_cast<double*>(F.view.diag);
+  double* off = const_cast<double*>(F.view.val);
+  if (sell_src32)
+    hipLaunchKernelGGL(k_sell_to_csr<float>, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, sell_src32,
+                       diag, off);
+  else
+    hipLaunchKernelGGL(k_sell_to_csr<double>, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p,
+                       F.sval64.p, diag, off);
   LAUNCHCHECK();
 }
 
@@ -1367,11 +1397,12 @@ static void launch_cyc(const CycMat& M, bool finest, const CycX<Op, TB>* x, cons
 // down [pre-sweep + residual] [restriction], up [prolongation + post-sweep].
 // FP64 b and x on level 0, FP32 vectors on the levels below and for the
 // level-0 residual.
-void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
+template <class T>
+void Amg::apply_classical(const T* b, T* x, hipStream_t s) {
   const int L = (int)lv.size();
   if (L == 1) {   // dense solve only
     timed(lvprof.get(), 63, 0.0, s, [&] {
-      hipLaunchKernelGGL((k_dense_gemv<double, double>), dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd,
+      hipLaunchKernelGGL((k_dense_gemv<T, T>), dim3(grid_for(nd, kBlock / 64)), dim3(kBlock), 0, s, nd,
                          lv.back().t.p, b, x);
     });
     LAUNCHCHECK();
@@ -1385,7 +1416,7 @@ void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
       const double n = (double)F.n;
       // r = b - A diag(w) b: b read (8 bytes on level 0, 4 below), r written in FP32
       timed(pf, hook.down_id, 6.0 * (double)F.aw.nnz + 12.0 * n, s, [&] {
-        if (k == 0) launch_cyc<0, double, float>(F.aw, true, b, b, nullptr, nullptr, F.r32.p, s);
+        if (k == 0) launch_cyc<0, T, float>(F.aw, true, b, b, nullptr, nullptr, F.r32.p, s);
         else launch_cyc<0, float, float>(F.aw, false, F.b32.p, F.b32.p, nullptr, nullptr, F.r32.p, s);
       });
       timed(pf, hook.restrict_id, 6.0 * (double)F.rm.nnz + 4.0 * n + 4.0 * C.n, s, [&] {
@@ -1406,7 +1437,7 @@ void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
     timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
       // w, b, r, x: 8 + 8 + 4 + 8 bytes per row on level 0; e gathered in FP32
       timed(pf, hook.up_id, 6.0 * (double)F.cm.nnz + 28.0 * F.n + 4.0 * C.n, s, [&] {
-        if (k == 0) launch_cyc<2, double, double>(F.cm, true, C.x32.p, b, F.r32.p, F.invd.p, x, s);
+        if (k == 0) launch_cyc<2, T, T>(F.cm, true, C.x32.p, b, F.r32.p, F.invd.p, x, s);
         else launch_cyc<2, float, float>(F.cm, false, C.x32.p, F.b32.p, F.r32.p, F.invd.p, F.x32.p, s);
       });
     });
@@ -1414,9 +1445,14 @@ void Amg::apply_classical(const double* b, double* x, hipStream_t s) {
   }
 }
 
+void Amg::apply(const float* b, float* x, hipStream_t s) {
+  require(classical, "FP32 preconditioner input needs the classical AMG");
+  apply_classical<float>(b, x, s);
+}
+
 void Amg::apply(const double* b, double* x, hipStream_t s) {
   if (classical) {
-    apply_classical(b, x, s);
+    apply_classical<double>(b, x, s);
     return;
   }
   // level 0 uses the caller's b and x; V(2,2) with the sweep pairs fused:
@@ -1499,23 +1535,23 @@ void Amg::apply(const double* b, double* x, hipStream_t s) {
 
 // ------------------------------------------------------------------ Krylov
 
-template <class Mat, bool Fin>
-static void spmv_dot_as(const Mat& A, int G, hipStream_t st, const double* x, double* y, const double* w, double* P) {
-  hipLaunchKernelGGL((k_spmv_dot<Mat, Fin>), dim3(G), dim3(SpmvBlock<Mat>::v), 0, st, A, x, y, w, P);
+template <class Mat, bool Fin, class T>
+static void spmv_dot_as(const Mat& A, int G, hipStream_t st, const T* x, T* y, const T* w, double* P) {
+  hipLaunchKernelGGL((k_spmv_dot<Mat, Fin, T>), dim3(G), dim3(SpmvBlock<Mat>::v), 0, st, A, x, y, w, P);
 }
 
-template <class Mat, bool Fin>
-static void spmv_dot2_as(const Mat& A, int G, hipStream_t st, const double* x, double* y, const double* w,
-                         double* P0, double* P1) {
-  hipLaunchKernelGGL((k_spmv_dot2<Mat, Fin>), dim3(G), dim3(SpmvBlock<Mat>::v), 0, st, A, x, y, w, P0, P1);
+template <class Mat, bool Fin, class T>
+static void spmv_dot2_as(const Mat& A, int G, hipStream_t st, const T* x, T* y, const T* w, double* P0, double* P1) {
+  hipLaunchKernelGGL((k_spmv_dot2<Mat, Fin, T>), dim3(G), dim3(SpmvBlock<Mat>::v), 0, st, A, x, y, w, P0, P1);
 }
 
 // y = A x and one partial dot product w.y per block (G blocks)
-static void spmv_dot(const CsrView& A, const Sell64View* A64, bool fin, int G, hipStream_t st, const double* x,
-                     double* y, const double* w, double* P) {
-  if (A64) {
-    if (fin) spmv_dot_as<Sell64View, true>(*A64, G, st, x, y, w, P);
-    else spmv_dot_as<Sell64View, false>(*A64, G, st, x, y, w, P);
+template <class T, class SellT>
+static void spmv_dot(const CsrView& A, const SellT* As, bool fin, int G, hipStream_t st, const T* x, T* y,
+                     const T* w, double* P) {
+  if (As) {
+    if (fin) spmv_dot_as<SellT, true>(*As, G, st, x, y, w, P);
+    else spmv_dot_as<SellT, false>(*As, G, st, x, y, w, P);
   } else {
     if (fin) spmv_dot_as<CsrView, true>(A, G, st, x, y, w, P);
     else spmv_dot_as<CsrView, false>(A, G, st, x, y, w, P);
@@ -1524,11 +1560,12 @@ static void spmv_dot(const CsrView& A, const Sell64View* A64, bool fin, int G, h
 }
 
 // y = A x, partials of w.y and y.y per block
-static void spmv_dot2(const CsrView& A, const Sell64View* A64, bool fin, int G, hipStream_t st, const double* x,
-                      double* y, const double* w, double* P0, double* P1) {
-  if (A64) {
-    if (fin) spmv_dot2_as<Sell64View, true>(*A64, G, st, x, y, w, P0, P1);
-    else spmv_dot2_as<Sell64View, false>(*A64, G, st, x, y, w, P0, P1);
+template <class T, class SellT>
+static void spmv_dot2(const CsrView& A, const SellT* As, bool fin, int G, hipStream_t st, const T* x, T* y,
+                      const T* w, double* P0, double* P1) {
+  if (As) {
+    if (fin) spmv_dot2_as<SellT, true>(*As, G, st, x, y, w, P0, P1);
+    else spmv_dot2_as<SellT, false>(*As, G, st, x, y, w, P0, P1);
   } else {
     if (fin) spmv_dot2_as<CsrView, true>(A, G, st, x, y, w, P0, P1);
     else spmv_dot2_as<CsrView, false>(A, G, st, x, y, w, P0, P1);
@@ -1539,13 +1576,15 @@ static void spmv_dot2(const CsrView& A, const Sell64View* A64, bool fin, int G, 
 // doubles of Krylov::hlag
 constexpr int kLagDoubles = 2 + 3 * kMaxParts;
 
-Krylov::~Krylov() {
+template <class T>
+KrylovT<T>::~KrylovT() {
   if (hlag) (void)hipHostFree(hlag);
   for (hipEvent_t& e : ev)
     if (e) (void)hipEventDestroy(e);
 }
 
-void Krylov::alloc(int n_) {
+template <class T>
+void KrylovT<T>::alloc(int n_) {
   if (n == n_ && hlag) return;
   n = n_;
   r.alloc(n); z.alloc(n); p.alloc(n); q.alloc(n); rh.alloc(n); v.alloc(n); s.alloc(n); t.alloc(n); y.alloc(n);
@@ -1560,8 +1599,8 @@ void Krylov::alloc(int n_) {
     if (!e) HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
-int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st,
-                int stall) {
+template <class T>
+int KrylovT<T>::pcg(const CsrView& A, Amg* M, const T* b, T* x, double rtol, int maxit, hipStream_t st, int stall) {
   alloc(A.n);
   const int G = reduce_grid(n);
   const unsigned g1 = grid_for(n, kBlock);
@@ -1573,9 +1612,9 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   const volatile double* hl = hlag;
   double* d_bb = dlag + 2;
   double* d_rr = dlag + 2 + kMaxParts;
-  hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
-  hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
-  hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, b, b, d_bb);
+  hipLaunchKernelGGL(k_zero<T>, dim3(G), dim3(kBlock), 0, st, n, x);
+  hipLaunchKernelGGL(k_copy<T>, dim3(G), dim3(kBlock), 0, st, n, b, r.p);
+  hipLaunchKernelGGL(k_dot<T>, dim3(G), dim3(kBlock), 0, st, n, b, b, d_bb);
   LAUNCHCHECK();
   // b.b reaches the host with the scalars of iteration 0 (no wait of its own)
   failed = false;
@@ -1621,14 +1660,14 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   bool near = false;   // within a factor 10 of the tolerance: check every iteration at once
   for (; it < maxit; ++it) {
     if (M) M->apply(r.p, z.p, st);
-    else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
+    else hipLaunchKernelGGL(k_copy<T>, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p);
     // partial sums: P0 r.z, P1 p.q (each consumed by the next kernel), r.r
     // (host-mapped, for the host's check)
-    hipLaunchKernelGGL(k_dot, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p, P0);
-    hipLaunchKernelGGL(k_pcg_p2, dim3(G), dim3(kBlock), 0, st, n, P0, G, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
+    hipLaunchKernelGGL(k_dot<T>, dim3(G), dim3(kBlock), 0, st, n, r.p, z.p, P0);
+    hipLaunchKernelGGL(k_pcg_p2<T>, dim3(G), dim3(kBlock), 0, st, n, P0, G, scal.p, cur, old, it == 0 ? 1 : 0, z.p, p.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, p.p, q.p, p.p, P1); });
-    hipLaunchKernelGGL(k_pcg_xr2, dim3(G), dim3(kBlock), 0, st, n, P1, G, scal.p, cur, x, r.p, p.p, q.p,
+          [&] { spmv_dot(A, sell, hook.prof != nullptr, G, st, p.p, q.p, p.p, P1); });
+    hipLaunchKernelGGL(k_pcg_xr2<T>, dim3(G), dim3(kBlock), 0, st, n, P1, G, scal.p, cur, x, r.p, p.p, q.p,
                        d_rr + kMaxParts * (it & 1), dlag + (it & 1));
     LAUNCHCHECK();
     std::swap(cur, old);
@@ -1648,7 +1687,7 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
           failed = true;
           converged = false;
         } else if (!(pq_it > 0.0)) {
-          hipLaunchKernelGGL(k_pcg_undo, dim3(G), dim3(kBlock), 0, st, n, scal.p, old, pq_it, x, p.p);
+          hipLaunchKernelGGL(k_pcg_undo<T>, dim3(G), dim3(kBlock), 0, st, n, scal.p, old, pq_it, x, p.p);
           LAUNCHCHECK();
           break;   // `it` iterations were kept
         }
@@ -1675,7 +1714,7 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
     else if (rr <= tol2) converged = true;
   }
   if (failed) {   // breakdown (p.Ap <= 0) or non-finite operator: x = 0
-    hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+    hipLaunchKernelGGL(k_zero<T>, dim3(G), dim3(kBlock), 0, st, n, x);
     LAUNCHCHECK();
   }
   (void)g1;
@@ -1683,7 +1722,8 @@ int Krylov::pcg(const CsrView& A, Amg* M, const double* b, double* x, double rto
   return it;
 }
 
-int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st) {
+template <class T>
+int KrylovT<T>::bicgstab(const CsrView& A, Amg* M, const T* b, T* x, double rtol, int maxit, hipStream_t st) {
   alloc(A.n);
   const int G = reduce_grid(n);
   double* P0 = parts.p;
@@ -1692,7 +1732,7 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   // the host's checks: b.b, then r.r of each iteration (host-mapped)
   const volatile double* hl = hlag;
   // x = 0, r = rh = b; ||b||^2 is also rho_0 = rh.r
-  hipLaunchKernelGGL(k_bicg_init, dim3(G), dim3(kBlock), 0, st, n, b, x, r.p, rh.p, P0);
+  hipLaunchKernelGGL(k_bicg_init<T>, dim3(G), dim3(kBlock), 0, st, n, b, x, r.p, rh.p, P0);
   hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P0, G, scal.p, (int)S_BB, cur, 0, dlag);
   LAUNCHCHECK();
   HIPCHECK(hipStreamSynchronize(st));
@@ -1703,23 +1743,23 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   const double tol2 = rtol * rtol * bb;
   int it = 0;
   for (; it < maxit; ++it) {
-    hipLaunchKernelGGL(k_bicg_p, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, r.p, p.p, v.p);
+    hipLaunchKernelGGL(k_bicg_p<T>, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, old, it == 0 ? 1 : 0, r.p, p.p, v.p);
     LAUNCHCHECK();
     if (M) M->apply(p.p, y.p, st);
-    else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, p.p, y.p);
+    else hipLaunchKernelGGL(k_copy<T>, dim3(G), dim3(kBlock), 0, st, n, p.p, y.p);
     timed(hook.prof, hook.spmv_id, hook.spmv_bytes, st,
-          [&] { spmv_dot(A, sell64, hook.prof != nullptr, G, st, y.p, v.p, rh.p, P0); });
+          [&] { spmv_dot(A, sell, hook.prof != nullptr, G, st, y.p, v.p, rh.p, P0); });
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, st, P0, G, scal.p, (int)S_RV);
-    hipLaunchKernelGGL(k_bicg_s, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, r.p, v.p, s.p);
+    hipLaunchKernelGGL(k_bicg_s<T>, dim3(G), dim3(kBlock), 0, st, n, scal.p, cur, r.p, v.p, s.p);
     LAUNCHCHECK();
     if (M) M->apply(s.p, z.p, st);
-    else hipLaunchKernelGGL(k_copy, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
+    else hipLaunchKernelGGL(k_copy<T>, dim3(G), dim3(kBlock), 0, st, n, s.p, z.p);
     timed(hook.prof, hook.spmv2_id, hook.spmv_bytes, st,
-          [&] { spmv_dot2(A, sell64, hook.prof != nullptr, G, st, z.p, t.p, s.p, P0, P1); });
+          [&] { spmv_dot2(A, sell, hook.prof != nullptr, G, st, z.p, t.p, s.p, P0, P1); });
     // TS, TT and omega = TS / TT in one launch
     hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_TS, (int)S_TT, 1,
                        nullptr);
-    hipLaunchKernelGGL(k_bicg_xr, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, rh.p, P0, P1);
+    hipLaunchKernelGGL(k_bicg_xr<T>, dim3(G), dim3(kBlock), 0, st, n, scal.p, x, y.p, z.p, r.p, s.p, t.p, rh.p, P0, P1);
     // ||r||^2 and the next rho = rh.r (into the slot of the previous rho)
     hipLaunchKernelGGL(k_finalize2, dim3(1), dim3(kBlock), 0, st, P0, P1, G, scal.p, (int)S_RR, old, 0, dlag);
     LAUNCHCHECK();
@@ -1728,7 +1768,7 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
     const double rr = hl[0];
     if (!std::isfinite(rr)) {   // breakdown or non-finite operator: report, leave x = 0
       failed = true;
-      hipLaunchKernelGGL(k_zero, dim3(G), dim3(kBlock), 0, st, n, x);
+      hipLaunchKernelGGL(k_zero<T>, dim3(G), dim3(kBlock), 0, st, n, x);
       ++it;
       break;
     }
@@ -1737,5 +1777,8 @@ int Krylov::bicgstab(const CsrView& A, Amg* M, const double* b, double* x, doubl
   iters += it;
   return it;
 }
+
+template struct KrylovT<double>;
+template struct KrylovT<float>;
 
 }  // namespace spfas

@@ -77,6 +77,14 @@ struct Sell64View {
   const double* val = nullptr;
 };
 
+// The same pattern with FP32 values (level 0 in mixed precision).
+struct Sell32View {
+  int n = 0;
+  const int* sptr = nullptr;
+  const int* col = nullptr;
+  const float* val = nullptr;
+};
+
 // Values of the classical cycle operators: FP16 (the operators A diag(w),
 // P^T and P - diag(w) A P are scaled to O(1) entries; products and vectors
 // stay FP64).
@@ -178,8 +186,13 @@ struct Amg {
   void numeric(hipStream_t s);        // coarse values, weights, dense LU
   void operator_values(hipStream_t s);   // only the FP64 SELL copy of level 0 (Krylov operator)
   void apply(const double* b, double* x, hipStream_t s);   // x = B^{-1} b (one V-cycle)
+  void apply(const float* b, float* x, hipStream_t s);     // FP32 input and output (classical only)
   void numeric_classical(hipStream_t s);
-  void apply_classical(const double* b, double* x, hipStream_t s);
+  template <class T>
+  void apply_classical(const T* b, T* x, hipStream_t s);
+  // level-0 values the caller writes in FP32 (mixed precision): sell_to_csr
+  // reads them instead of sval64
+  const float* sell_src32 = nullptr;
   void dense_numeric(hipStream_t s);
   int n_levels() const { return (int)lv.size(); }
   std::string describe() const;       // "n/nnz" per level, for diagnostics
@@ -189,11 +202,20 @@ struct Amg {
   std::string level_times();
 };
 
-struct Krylov {
+// SELL layout of the Krylov products for vectors of type T.
+template <class T> struct KrylovSell;
+template <> struct KrylovSell<double> { using type = Sell64View; };
+template <> struct KrylovSell<float> { using type = Sell32View; };
+
+// Krylov solvers with vectors of type T (FP64, or FP32 in mixed precision);
+// dot products and scalars are FP64 either way.
+template <class T>
+struct KrylovT {
+  using SellT = typename KrylovSell<T>::type;
   int n = 0;
   ProfHook hook;
-  const Sell64View* sell64 = nullptr;  // when set (same matrix as A), products read it instead of A
-  DVec<double> r, z, p, q, rh, v, s, t, y, w;
+  const SellT* sell = nullptr;        // when set (same matrix as A), products read it instead of A
+  DVec<T> r, z, p, q, rh, v, s, t, y, w;
   DVec<double> parts, scal;
   // host-mapped values the host checks, written by the kernels: for PCG
   // p.Ap of the last two iterations, the b.b partials, the r.r partials of
@@ -204,15 +226,19 @@ struct Krylov {
   int iters = 0;
   bool failed = false;                // last solve met a non-finite value or a PCG breakdown (x returned as 0)
   bool converged = false;             // last solve reached its tolerance
-  ~Krylov();
+  KrylovT() = default;
+  KrylovT(const KrylovT&) = delete;
+  KrylovT& operator=(const KrylovT&) = delete;
+  ~KrylovT();
   void alloc(int n_);
   // returns the number of iterations; x is overwritten (zero initial guess)
   // stall > 0: stop without convergence when ||r|| fell less than 2x over
   // the last `stall` iterations (for a caller with a fallback method)
-  int pcg(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st,
-          int stall = 0);
-  int bicgstab(const CsrView& A, Amg* M, const double* b, double* x, double rtol, int maxit, hipStream_t st);
+  int pcg(const CsrView& A, Amg* M, const T* b, T* x, double rtol, int maxit, hipStream_t st, int stall = 0);
+  int bicgstab(const CsrView& A, Amg* M, const T* b, T* x, double rtol, int maxit, hipStream_t st);
 };
+using Krylov = KrylovT<double>;
+using Krylov32 = KrylovT<float>;
 
 // y = A x
 void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s);
