@@ -387,6 +387,35 @@ def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, cor
     return dataclasses.replace(prob, greedy_size=greedy_size)
 
 
+def served_problem(seed: int, n_min: int = 32 ** 2, n_max: int = 64 ** 3, dims=(2, 3), sigma: float = 2.0,
+                   corr_len: float = 3.0) -> Problem:
+    """One model of the served and batched workloads: dimension drawn from
+    ``dims``, cell count log-uniform in [n_min, n_max], side = round(N^(1/d))
+    on the unit square / cube; ln k = sigma G, G a standardised Gaussian
+    random field of correlation length ``corr_len`` cells; kappa = exp(p);
+    p = 0 on x = 0, no flow elsewhere; zero-mean random source density (the
+    caller scales it: a strong sink can leave exp(p) without a root, and the
+    rule used is max|p| = 0.5 for the kappa = 1 pressure); box aggregates of 4 cells per axis with 2 local eigenvectors, levels
+    until the coarsest has at most a few hundred cells."""
+    rng = np.random.default_rng(seed)
+    d = int(rng.choice(dims))
+    n = math.exp(rng.uniform(math.log(n_min), math.log(n_max)))
+    side = max(8, int(round(n ** (1.0 / d))))
+    shape = (side,) * d
+    nc = side ** d
+    k = np.exp(sigma * _flat(gaussian_field(shape, corr_len, rng)))
+    mesh = cartesian_mesh(shape, tuple(1.0 / side for _ in shape), k, dirichlet=((0, 0),))
+    src = rng.standard_normal(nc)
+    src -= src.mean()
+    levels, c = 1, nc
+    while c > 400 and levels < 8:
+        c //= 4 ** d
+        levels += 1
+    return Problem(mesh=mesh, alpha=1.0, source=src, g_dirichlet=np.zeros(mesh.n_faces),
+                   g_neumann=np.zeros(mesh.n_faces), name=f"served_{d}d_{side}_s{seed}", box=(4,) * d, m=2,
+                   n_levels=levels, dp_cap_c=5.0)
+
+
 def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=None, m=2,
                   n_levels=2, spacing=None, g_d_scale=0.0, g_n_scale=0.0, src_scale=1.0,
                   anisotropic=False, permute=False, dp_cap_c=5.0) -> Problem:
