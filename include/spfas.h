@@ -499,7 +499,10 @@ typedef enum {
   SPFAS_PROF_FINE_AMG_UP = 5,        /* finest AMG level: prolongation + smoothing  */
   SPFAS_PROF_FINE_SPMV2 = 6,         /* S x (+ two dots), second product of BiCGStab */
   SPFAS_PROF_FINE_RESID_TRIALS = 7,  /* fine residual norms at up to 4 step lengths in one pass (Alg. 1 halvings) */
-  SPFAS_PROF_COUNT = 8
+  SPFAS_PROF_AMG_TAIL_DOWN = 8,      /* the same three phases summed over the level-0 AMG's levels below the */
+  SPFAS_PROF_AMG_TAIL_RESTRICT = 9,  /*   finest (FP32 vectors: pre-sweep 6E + 8N, restriction 6E_R + 4N +  */
+  SPFAS_PROF_AMG_TAIL_UP = 10,       /*   4N_c, prolongation + sweep 6E_AP + 20N + 4N_c per level)          */
+  SPFAS_PROF_COUNT = 11
 } spfas_prof_kernel;
 
 /* Turns the timing on (nonzero) or off and clears the counters. */

@@ -27,12 +27,15 @@ EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solv
             "spfas_server_counters_get", "spfas_server_destroy", "spfas_server_last_error"]
 SPFAS_SOLVE_FAS, SPFAS_SOLVE_NEWTON, SPFAS_SOLVE_PICARD = 0, 1, 2
 (SPFAS_PROF_FINE_RESID, SPFAS_PROF_FINE_LINEARIZE, SPFAS_PROF_FINE_SPMV, SPFAS_PROF_FINE_AMG_DOWN,
- SPFAS_PROF_FINE_AMG_RESTRICT, SPFAS_PROF_FINE_AMG_UP, SPFAS_PROF_FINE_SPMV2, SPFAS_PROF_FINE_RESID_TRIALS) = range(8)
+ SPFAS_PROF_FINE_AMG_RESTRICT, SPFAS_PROF_FINE_AMG_UP, SPFAS_PROF_FINE_SPMV2, SPFAS_PROF_FINE_RESID_TRIALS,
+ SPFAS_PROF_AMG_TAIL_DOWN, SPFAS_PROF_AMG_TAIL_RESTRICT, SPFAS_PROF_AMG_TAIL_UP) = range(11)
 # names match the kernels as a profiler reports them (classical finest AMG level)
 PROF_NAMES = {SPFAS_PROF_FINE_RESID: "k_fine_resid", SPFAS_PROF_FINE_LINEARIZE: "k_fine_lin_cells",
               SPFAS_PROF_FINE_SPMV: "k_spmv_dot<true>", SPFAS_PROF_FINE_SPMV2: "k_spmv_dot2<true>",
               SPFAS_PROF_FINE_AMG_DOWN: "k_cyc<0, true>", SPFAS_PROF_FINE_AMG_RESTRICT: "k_cyc<1, true>",
-              SPFAS_PROF_FINE_AMG_UP: "k_cyc<2, true>", SPFAS_PROF_FINE_RESID_TRIALS: "k_fine_resid_trials"}
+              SPFAS_PROF_FINE_AMG_UP: "k_cyc<2, true>", SPFAS_PROF_FINE_RESID_TRIALS: "k_fine_resid_trials",
+              SPFAS_PROF_AMG_TAIL_DOWN: "amg_tail_down", SPFAS_PROF_AMG_TAIL_RESTRICT: "amg_tail_restrict",
+              SPFAS_PROF_AMG_TAIL_UP: "amg_tail_up"}
 
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)

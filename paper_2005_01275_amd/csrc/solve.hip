@@ -251,6 +251,9 @@ void setup_fine_solver(Hierarchy& h) {
   hk.down_id = SPFAS_PROF_FINE_AMG_DOWN;
   hk.restrict_id = SPFAS_PROF_FINE_AMG_RESTRICT;
   hk.up_id = SPFAS_PROF_FINE_AMG_UP;
+  hk.tail_down_id = SPFAS_PROF_AMG_TAIL_DOWN;
+  hk.tail_restrict_id = SPFAS_PROF_AMG_TAIL_RESTRICT;
+  hk.tail_up_id = SPFAS_PROF_AMG_TAIL_UP;
   w.kry.hook = hk;
   w.amg.hook = hk;
   if (w.amg.lv[0].sval64.n) {   // S products read the SELL-64 copy: value + column per stored entry

@@ -20,7 +20,7 @@ namespace spfas {
 
 template <class F>
 static void timed(KernelProf* prof, int id, double bytes, hipStream_t s, F&& fn) {
-  if (prof) prof->run(id, bytes, s, fn);
+  if (prof && id >= 0) prof->run(id, bytes, s, fn);
   else fn();
 }
 
@@ -1411,15 +1411,16 @@ void Amg::apply_classical(const T* b, T* x, hipStream_t s) {
   for (int k = 0; k < L - 1; ++k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
-    KernelProf* pf = k == 0 ? hook.prof : nullptr;
     timed(lvprof.get(), 3 * k, 0.0, s, [&] {
       const double n = (double)F.n;
-      // r = b - A diag(w) b: b read (8 bytes on level 0, 4 below), r written in FP32
-      timed(pf, hook.down_id, 6.0 * (double)F.aw.nnz + 12.0 * n, s, [&] {
+      // r = b - A diag(w) b: b read (sizeof(T) bytes on level 0, 4 below), r written in FP32
+      const double bsz = k == 0 ? (double)sizeof(T) : 4.0;
+      timed(hook.prof, k == 0 ? hook.down_id : hook.tail_down_id, 6.0 * (double)F.aw.nnz + (bsz + 4.0) * n, s, [&] {
         if (k == 0) launch_cyc<0, T, float>(F.aw, true, b, b, nullptr, nullptr, F.r32.p, s);
         else launch_cyc<0, float, float>(F.aw, false, F.b32.p, F.b32.p, nullptr, nullptr, F.r32.p, s);
       });
-      timed(pf, hook.restrict_id, 6.0 * (double)F.rm.nnz + 4.0 * n + 4.0 * C.n, s, [&] {
+      timed(hook.prof, k == 0 ? hook.restrict_id : hook.tail_restrict_id,
+            6.0 * (double)F.rm.nnz + 4.0 * n + 4.0 * C.n, s, [&] {
         launch_cyc<1, float, float>(F.rm, k == 0, F.r32.p, nullptr, nullptr, nullptr, C.b32.p, s);
       });
     });
@@ -1433,10 +1434,11 @@ void Amg::apply_classical(const T* b, T* x, hipStream_t s) {
   for (int k = L - 2; k >= 0; --k) {
     AmgLevel& F = lv[k];
     AmgLevel& C = lv[k + 1];
-    KernelProf* pf = k == 0 ? hook.prof : nullptr;
     timed(lvprof.get(), 3 * k + 1, 0.0, s, [&] {
-      // w, b, r, x: 8 + 8 + 4 + 8 bytes per row on level 0; e gathered in FP32
-      timed(pf, hook.up_id, 6.0 * (double)F.cm.nnz + 28.0 * F.n + 4.0 * C.n, s, [&] {
+      // w (8), b, r (4), x per row: b and x sizeof(T) on level 0, 4 below; e gathered in FP32
+      const double vsz = k == 0 ? (double)sizeof(T) : 4.0;
+      timed(hook.prof, k == 0 ? hook.up_id : hook.tail_up_id,
+            6.0 * (double)F.cm.nnz + (12.0 + 2.0 * vsz) * F.n + 4.0 * C.n, s, [&] {
         if (k == 0) launch_cyc<2, T, T>(F.cm, true, C.x32.p, b, F.r32.p, F.invd.p, x, s);
         else launch_cyc<2, float, float>(F.cm, false, C.x32.p, F.b32.p, F.r32.p, F.invd.p, F.x32.p, s);
       });

@@ -161,6 +161,8 @@ struct ProfHook {
   int spmv_id = -1, spmv2_id = -1;
   double spmv_bytes = 0.0;
   int down_id = -1, restrict_id = -1, up_id = -1;
+  // the same three phases summed over the levels below the finest
+  int tail_down_id = -1, tail_restrict_id = -1, tail_up_id = -1;
 };
 
 struct Amg {
