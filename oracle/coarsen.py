@@ -40,7 +40,7 @@ from typing import Dict, List, Tuple
 import numpy as np
 import scipy.sparse as sp
 
-from .levels import Level, INTERIOR, DIRICHLET, BUBBLE
+from .levels import Level, INTERIOR, DIRICHLET, BUBBLE, kappa_of
 
 
 # ------------------------------------------------------------- aggregation
@@ -456,6 +456,10 @@ def coarsen(level: Level, agg: np.ndarray, cshape, m: int):
                    cell_flux=cell_flux, M_loc=M_loc, D_loc=D_loc, w=w, ones=ones_c, u=u_c,
                    vol=vol_c, lattice_shape=tuple(cshape),
                    lattice_index=np.arange(n_agg)).finalize()
+    if level.shift is not None:
+        # volume-weighted mean of the level-0 shift over each coarse cell
+        coarse.shift = np.array([(level.vol[ads[A].cells] * level.shift[ads[A].cells]).sum() / vol_c[A]
+                                 for A in range(n_agg)])
     tr = Transfer(P_sig=P_sig, P_p=P_p, Q_sig=Q_sig, agg=agg, cell_order=cell_order,
                   flux_order=flux_order, aggs=[ads[A] for A in range(n_agg)],
                   coarse_faces=faces, traces=traces)
@@ -469,7 +473,7 @@ class Hierarchy:
     levels: List[Level]
     transfers: List[Transfer]
     b0: np.ndarray
-    alpha: float
+    alpha: object                  # exponent of kappa = exp(alpha p), or a levels.Kappa
     finemap: object
 
 
@@ -499,4 +503,4 @@ def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, use
         coarse, tr = coarsen(cur, agg, cshape, m)
         levels.append(coarse)
         transfers.append(tr)
-    return Hierarchy(levels=levels, transfers=transfers, b0=b0, alpha=prob.alpha, finemap=fm)
+    return Hierarchy(levels=levels, transfers=transfers, b0=b0, alpha=kappa_of(prob), finemap=fm)

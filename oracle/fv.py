@@ -111,6 +111,8 @@ def fine_level(prob):
                 cell_flux=cell_flux, M_loc=M_loc, D_loc=D_loc, w=w,
                 ones=np.ones(n), u=mesh.cell_volume.copy(), vol=mesh.cell_volume.copy(),
                 lattice_shape=shape, lattice_index=index).finalize()
+    sh = getattr(prob, "shift", None)
+    lev.shift = None if sh is None else np.asarray(sh, dtype=np.float64).copy()
     # right-hand side
     g = np.where(kind == DIRICHLET, prob.g_dirichlet[ff], 0.0)
     f = mesh.cell_volume * prob.source
@@ -147,7 +149,10 @@ class FineSystem:
         self.TL = TL[ff]
         self.n_cells = mesh.n_cells
         self.n_flux = ff.size
-        self.alpha = prob.alpha
+        from .levels import kappa_of
+        self.alpha = kappa_of(prob)
+        sh = getattr(prob, "shift", None)
+        self.shift = np.zeros(mesh.n_cells) if sh is None else np.asarray(sh, dtype=np.float64)
         self.g = np.where(self.inner, 0.0, prob.g_dirichlet[ff])
         f = mesh.cell_volume * prob.source
         nf_ = self.fm.neumann_faces
@@ -156,10 +161,12 @@ class FineSystem:
 
     def residual(self, sigma, p):
         """r_sigma = M(p) sigma + D^T p + g, r_p = D sigma + f."""
+        from .levels import kinv
         a = self.alpha
         Li = np.where(self.inner, self.L, 0)
-        m = np.exp(-a * p[self.K]) / self.TK
-        m = m + np.where(self.inner, np.exp(-a * p[Li]) / np.where(self.inner, self.TL, 1.0), 0.0)
+        psi = p - self.shift
+        m = kinv(psi[self.K], a) / self.TK
+        m = m + np.where(self.inner, kinv(psi[Li], a) / np.where(self.inner, self.TL, 1.0), 0.0)
         dtp = np.where(self.inner, p[Li], 0.0) - p[self.K]
         r_sig = m * sigma + dtp + self.g
         div = np.zeros(self.n_cells)

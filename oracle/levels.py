@@ -46,6 +46,10 @@ class Level:
     vol: np.ndarray                 # [n_cells] cell measures
     lattice_shape: Optional[tuple] = None
     lattice_index: Optional[np.ndarray] = None   # [n_cells]
+    # shift z of the kappa argument per cell (kappa(Pi~ p - z)); level 0:
+    # the problem's field, coarse levels: its volume-weighted mean over the
+    # level-0 cells of each coarse cell.  None: no shift.
+    shift: Optional[np.ndarray] = None
     # assembled operators (filled by finalize)
     W: Optional[sp.csr_matrix] = None
     Mhat: Optional[sp.csr_matrix] = None
@@ -92,13 +96,64 @@ class Level:
 
 # ------------------------------------------------------------- kappa family
 
-def kinv(pbar: np.ndarray, alpha: float) -> np.ndarray:
-    """1/kappa(p) for kappa(p) = exp(alpha p) (Section 2, eq. for kappa)."""
+@dataclasses.dataclass(frozen=True)
+class Kappa:
+    """The scalar multiplier kappa of K(x, p) = K0(x) kappa (eq. kappa), as a
+    function of the shifted pressure psi = p - z(x):
+      * "exp":      kappa(psi) = exp(alpha psi) (Section 2, the model problem);
+      * "richards": kappa(psi) = a / (a + |psi|^beta) (Example 3, eq.
+        permeability_function_richards, with the pressure head psi = p - z
+        and z the height; the paper's alpha is ``a`` here).
+    The shift z is a per-cell field of the level (``Level.shift``); None is
+    z = 0.  Only 1/kappa and its derivative enter the method (Prop. 1,
+    Props. 2-3)."""
+    kind: str = "exp"
+    alpha: float = 0.0
+    a: float = 1.0
+    beta: float = 2.0
+
+    def kinv(self, psi: np.ndarray) -> np.ndarray:
+        if self.kind == "exp":
+            return np.exp(-self.alpha * psi)
+        if self.kind == "richards":
+            return 1.0 + np.abs(psi) ** self.beta / self.a
+        raise ValueError(f"unknown kappa family {self.kind!r}")
+
+    def dkinv(self, psi: np.ndarray) -> np.ndarray:
+        """d(1/kappa)/d psi."""
+        if self.kind == "exp":
+            return -self.alpha * np.exp(-self.alpha * psi)
+        if self.kind == "richards":
+            return np.sign(psi) * self.beta * np.abs(psi) ** (self.beta - 1.0) / self.a
+        raise ValueError(f"unknown kappa family {self.kind!r}")
+
+
+def as_kappa(alpha) -> Kappa:
+    """A number is the exponent of the exponential family."""
+    return alpha if isinstance(alpha, Kappa) else Kappa("exp", float(alpha))
+
+
+def kappa_of(prob):
+    """The kappa model of a problem: its alpha for the plain exponential,
+    else a Kappa."""
+    kind = getattr(prob, "kappa_kind", "exp")
+    if kind == "exp":
+        return prob.alpha
+    return Kappa(kind, prob.alpha, getattr(prob, "kappa_a", 1.0), getattr(prob, "kappa_beta", 2.0))
+
+
+def kinv(pbar: np.ndarray, alpha) -> np.ndarray:
+    """1/kappa(p) for kappa(p) = exp(alpha p) (Section 2, eq. for kappa), or
+    for the family of a Kappa."""
+    if isinstance(alpha, Kappa):
+        return alpha.kinv(pbar)
     return np.exp(-alpha * pbar)
 
 
-def dkinv(pbar: np.ndarray, alpha: float) -> np.ndarray:
-    """d(1/kappa)/dp for kappa(p) = exp(alpha p)."""
+def dkinv(pbar: np.ndarray, alpha) -> np.ndarray:
+    """d(1/kappa)/dp for kappa(p) = exp(alpha p), or for a Kappa."""
+    if isinstance(alpha, Kappa):
+        return alpha.dkinv(pbar)
     return -alpha * np.exp(-alpha * pbar)
 
 
@@ -113,9 +168,15 @@ def pwc(level: Level, p: np.ndarray) -> np.ndarray:
     return level.Pi @ p
 
 
+def psi_of(level: Level, p: np.ndarray) -> np.ndarray:
+    """The argument of kappa per cell: Pi~ p minus the level's shift."""
+    pb = pwc(level, p)
+    return pb if level.shift is None else pb - level.shift
+
+
 def M_of(level: Level, p: np.ndarray, alpha: float) -> sp.csr_matrix:
     """M^l(Pi~ p) = W^T Mhat diag(W_sp kinv(Pi~ p)) W (Prop. 1, eq. assemble)."""
-    s = level.Wsp @ kinv(pwc(level, p), alpha)
+    s = level.Wsp @ kinv(psi_of(level, p), alpha)
     return (level.W.T @ (level.Mhat @ sp.diags(s)) @ level.W).tocsr()
 
 
@@ -141,7 +202,7 @@ def E_of(level: Level, x: np.ndarray, alpha: float, newton: bool) -> sp.csr_matr
     sig, p = split(level, x)
     E = level.D.T.tocsr()
     if newton:
-        E = E + N_of(level, sig) @ sp.diags(dkinv(pwc(level, p), alpha)) @ level.Pi
+        E = E + N_of(level, sig) @ sp.diags(dkinv(psi_of(level, p), alpha)) @ level.Pi
     return E.tocsr()
 
 

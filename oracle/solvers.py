@@ -45,7 +45,7 @@ from typing import List
 import numpy as np
 import scipy.sparse.linalg as spla
 
-from .levels import residual, jacobian, pwc, apply_A
+from .levels import residual, jacobian, pwc, apply_A, Kappa
 
 
 @dataclasses.dataclass
@@ -111,7 +111,13 @@ def cap_scale(dpbar: np.ndarray, cap: float) -> float:
     return cap / mx if mx > cap else 1.0
 
 
-def cap_value(alpha: float, c: float) -> float:
+def cap_value(alpha, c: float) -> float:
+    """ln(c)/alpha for kappa = exp(alpha p) (Section 4.1); other kappa
+    families take no cap (Example 3 uses Alg. 1 alone)."""
+    if isinstance(alpha, Kappa):
+        if alpha.kind != "exp":
+            return math.inf
+        alpha = alpha.alpha
     if alpha <= 0 or c <= 1:
         return math.inf
     return math.log(c) / alpha

@@ -3,7 +3,8 @@
 Every function here is seeded and deterministic.  The arrays describe the
 boundary-value problem of Section 2 of the paper (mass conservation with
 Darcy's law, K(x, p) = K0(x) kappa(p), kappa(p) = exp(alpha p), Dirichlet and
-Neumann data) on a conforming mesh given as cells and an unstructured face
+Neumann data; or the Richards-type family of Example 3, kappa evaluated at
+p - z with a per-cell shift z) on a conforming mesh given as cells and an unstructured face
 list.  Nothing here evaluates the finite-volume scheme itself.
 
 Conventions shared by both consumers of these arrays:
@@ -61,6 +62,12 @@ class Problem:
     n_levels: int = 2
     dp_cap_c: float = 5.0          # cap constant c: max |dp| <= ln(c)/alpha
     greedy_size: int = 0           # > 0: greedy aggregates of about this many cells (unstructured meshes)
+    # kappa family: "exp" (exp(alpha psi)) or "richards" (a / (a + |psi|^beta)),
+    # evaluated at psi = p - shift (shift per cell, None = 0)
+    kappa_kind: str = "exp"
+    kappa_a: float = 1.0
+    kappa_beta: float = 2.0
+    shift: Optional[np.ndarray] = None
 
 
 # ---------------------------------------------------------------- meshes
@@ -225,7 +232,8 @@ def permute_mesh(prob: Problem, seed: int) -> Problem:
                 face_point=m.face_point[forder], face_bc=m.face_bc[forder], shape=m.shape)
     return dataclasses.replace(prob, mesh=mesh, source=prob.source[old_of_new],
                                g_dirichlet=prob.g_dirichlet[forder],
-                               g_neumann=prob.g_neumann[forder])
+                               g_neumann=prob.g_neumann[forder],
+                               shift=None if prob.shift is None else prob.shift[old_of_new])
 
 
 # ---------------------------------------------------------------- fields
@@ -445,6 +453,43 @@ def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=
     prob = Problem(mesh=mesh, alpha=alpha, source=src, g_dirichlet=gd, g_neumann=gn,
                    name=f"small_{'x'.join(map(str, shape))}_s{seed}", box=tuple(box), m=m,
                    n_levels=n_levels, dp_cap_c=dp_cap_c)
+    if permute:
+        prob = permute_mesh(prob, seed + 7)
+    return prob
+
+
+# Hydraulic parameters of Example 3's table (a, beta, k0 in cm/day).
+RICHARDS_MEDIA = {"loam": (1.246e2, 1.77, 1.067), "sand": (1.175e6, 4.74, 8.160e2)}
+
+
+def richards_problem(shape=(40, 10), size=(400.0, 100.0), medium="loam", seed=0, sigma=0.0,
+                     psi_dry=-300.0, psi_wet=-20.0, wet_frac=0.25, box=(4, 4), m=2, n_levels=2,
+                     permute=False) -> Problem:
+    """Static Richards-type problem on a vertical 2-D section (cm): the
+    conductivity K0 kappa(psi) with kappa = a / (a + |psi|^beta) of the
+    medium, the pressure head psi = p - z and z the height (cell centroid).
+    Zero source; water table psi = 0 on the bottom (p = 0); on the top the
+    head psi_wet over the first wet_frac of the width and psi_dry elsewhere
+    (p = psi + height); no flow through the sides.  K0 = k0 exp(sigma G)
+    with G i.i.d. standard normal (sigma = 0: the homogeneous medium).  The
+    paper's boundary layout is given only as a figure, so this one is a
+    stand-in with the same kind of wet/dry contrast."""
+    a, beta, k0 = RICHARDS_MEDIA[medium]
+    rng = np.random.default_rng(seed)
+    shape = tuple(int(v) for v in shape)
+    spacing = tuple(size[d] / shape[d] for d in range(2))
+    n = shape[0] * shape[1]
+    k = k0 * np.exp(sigma * rng.standard_normal(n))
+    mesh = cartesian_mesh(shape, spacing, k, dirichlet=((1, 0), (1, 1)))
+    gd = np.zeros(mesh.n_faces)
+    top = (mesh.face_bc == 1) & (mesh.face_point[:, 1] > 0.5 * size[1])
+    wet = top & (mesh.face_point[:, 0] < wet_frac * size[0])
+    gd[top] = psi_dry + size[1]
+    gd[wet] = psi_wet + size[1]
+    prob = Problem(mesh=mesh, alpha=0.0, source=np.zeros(n), g_dirichlet=gd, g_neumann=np.zeros(mesh.n_faces),
+                   name=f"richards_{medium}_{shape[0]}x{shape[1]}_s{seed}", box=tuple(box), m=m,
+                   n_levels=n_levels, kappa_kind="richards", kappa_a=a, kappa_beta=beta,
+                   shift=mesh.cell_centroid[:, 1].copy())
     if permute:
         prob = permute_mesh(prob, seed + 7)
     return prob
