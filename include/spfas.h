@@ -157,14 +157,32 @@ typedef struct {
  *   source       [n_cells]  density f (multiplied by |tau_K| internally)
  *   g_dirichlet  [n_faces]  g_D, read on Dirichlet faces; NULL means 0
  *   g_neumann    [n_faces]  g_N = -q.n, read on Neumann faces; NULL means 0
- *   mem          where the three arrays live
+ *   mem          where the arrays live (source, g_*, shift)
+ * kappa family (a zero-initialised tail gives the exponential above):
+ *   kappa_kind   SPFAS_KAPPA_EXP: kappa(psi) = exp(alpha psi);
+ *                SPFAS_KAPPA_RICHARDS: kappa(psi) = a / (a + |psi|^beta)
+ *                (Example 3, eq. permeability_function_richards), with
+ *                kappa_a > 0 and kappa_beta >= 1
+ *   shift        [n_cells] or NULL: kappa is evaluated at psi = p - shift
+ *                (Example 3: p = psi + z, shift = the height z).  Coarse
+ *                levels use the volume-weighted mean of the shift over the
+ *                level-0 cells of each coarse cell, at the aggregate-mean
+ *                pressure of Prop. 1.
+ * The cap of spfas_solve_opts.dp_cap is the caller's: ln(c)/alpha belongs
+ * to the exponential family (Section 4.1); pass 0 (no cap) for the other.
  */
+typedef enum { SPFAS_KAPPA_EXP = 0, SPFAS_KAPPA_RICHARDS = 1 } spfas_kappa_kind;
+
 typedef struct {
   double alpha;
   const double* source;
   const double* g_dirichlet;
   const double* g_neumann;
   int32_t mem;
+  int32_t kappa_kind;
+  double kappa_a;
+  double kappa_beta;
+  const double* shift;
 } spfas_problem;
 
 /*
@@ -356,7 +374,8 @@ int spfas_eval_residual(spfas_hierarchy* h, const spfas_problem* prob, const dou
  * static device array of 96 MiB that the library holds on each device it
  * runs on until the process ends; the level-0 problem may have at most
  * 6,291,456 unknowns (flux + cells), larger ones are rejected with
- * ERR_INVALID before any work.  The current device must be the one the
+ * ERR_INVALID before any work, and so is a problem with a kappa shift
+ * (prob->shift must be NULL).  The current device must be the one the
  * hierarchy was built on (ERR_INVALID otherwise).  All calls on one GPU
  * share that array: calls that overlap in time on one GPU (on any stream or
  * thread, any hierarchy) race and must not be made.  Returns after the work

@@ -139,20 +139,27 @@ class Hierarchy:
     def _problem(prob, device: bool):
         """spfas_problem for a ``problems.Problem``; device=True passes
         torch CUDA tensors (kept alive by the returned tuple)."""
+        kind = N.KAPPA_KINDS[getattr(prob, "kappa_kind", "exp")]
+        ka, kb = float(getattr(prob, "kappa_a", 1.0)), float(getattr(prob, "kappa_beta", 2.0))
+        shift = getattr(prob, "shift", None)
         if device:
             import torch
             src = torch.as_tensor(prob.source, dtype=torch.float64, device="cuda")
             gd = torch.as_tensor(prob.g_dirichlet, dtype=torch.float64, device="cuda")
             gn = torch.as_tensor(prob.g_neumann, dtype=torch.float64, device="cuda")
+            sh = None if shift is None else torch.as_tensor(shift, dtype=torch.float64, device="cuda")
             cp = N.spfas_problem(alpha=prob.alpha, source=src.data_ptr(), g_dirichlet=gd.data_ptr(),
-                                 g_neumann=gn.data_ptr(), mem=SPFAS_MEM_DEVICE)
-            return cp, (src, gd, gn)
+                                 g_neumann=gn.data_ptr(), mem=SPFAS_MEM_DEVICE, kappa_kind=kind, kappa_a=ka,
+                                 kappa_beta=kb, shift=None if sh is None else sh.data_ptr())
+            return cp, (src, gd, gn, sh)
         src = np.ascontiguousarray(prob.source, dtype=np.float64)
         gd = np.ascontiguousarray(prob.g_dirichlet, dtype=np.float64)
         gn = np.ascontiguousarray(prob.g_neumann, dtype=np.float64)
+        sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
         cp = N.spfas_problem(alpha=prob.alpha, source=src.ctypes.data, g_dirichlet=gd.ctypes.data,
-                             g_neumann=gn.ctypes.data, mem=SPFAS_MEM_HOST)
-        return cp, (src, gd, gn)
+                             g_neumann=gn.ctypes.data, mem=SPFAS_MEM_HOST, kappa_kind=kind, kappa_a=ka,
+                             kappa_beta=kb, shift=None if sh is None else sh.ctypes.data)
+        return cp, (src, gd, gn, sh)
 
     def eval_residual(self, prob, p, sigma):
         """Fine residual at host arrays (p [n_cells], sigma [n_faces])."""

@@ -62,9 +62,14 @@ class spfas_allocator(C.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
+SPFAS_KAPPA_EXP, SPFAS_KAPPA_RICHARDS = 0, 1
+KAPPA_KINDS = {"exp": SPFAS_KAPPA_EXP, "richards": SPFAS_KAPPA_RICHARDS}
+
+
 class spfas_problem(C.Structure):
     _fields_ = [("alpha", C.c_double), ("source", C.c_void_p), ("g_dirichlet", C.c_void_p),
-                ("g_neumann", C.c_void_p), ("mem", C.c_int32)]
+                ("g_neumann", C.c_void_p), ("mem", C.c_int32), ("kappa_kind", C.c_int32),
+                ("kappa_a", C.c_double), ("kappa_beta", C.c_double), ("shift", C.c_void_p)]
 
 
 class spfas_solve_opts(C.Structure):

@@ -126,6 +126,7 @@ int spfas_eval_residual_noalloc(spfas_hierarchy* h, const spfas_problem* prob, c
     need_device(h);
     require(prob && p && sigma && r_p && r_sigma, "NULL argument");
     require(prob->mem == SPFAS_MEM_DEVICE, "spfas_eval_residual_noalloc needs the problem data in device memory");
+    require(prob->shift == nullptr, "spfas_eval_residual_noalloc takes no kappa shift (its buffer would be allocated)");
     const int64_t nu = h->h.fine.nf + h->h.fine.n;
     if ((size_t)nu > noalloc_max_unknowns())
       fail(SPFAS_ERR_INVALID, "spfas_eval_residual_noalloc: " + std::to_string(nu) +

@@ -13,6 +13,7 @@
 
 #include "coarse_kern.hpp"
 #include "hier.hpp"
+#include "kappa.hpp"
 #include "kern.hpp"
 
 namespace spfas {
@@ -23,6 +24,7 @@ struct CView {
   int n, np, nf;
   const int *pptr, *lfptr, *lfidx, *mptr, *dptr, *fcell, *floc;
   const double *M, *D, *w;
+  const double* z;   // shift of kappa per cell (volume mean of the level-0 shift), nullptr: none
 };
 
 static CView cview(const CoarseLevel& C) {
@@ -30,6 +32,7 @@ static CView cview(const CoarseLevel& C) {
   v.n = C.n; v.np = C.np; v.nf = C.nf;
   v.pptr = C.pptr.p; v.lfptr = C.lfptr.p; v.lfidx = C.lfidx.p; v.mptr = C.mptr.p; v.dptr = C.dptr.p;
   v.fcell = C.fcell.p; v.floc = C.floc.p; v.M = C.M.p; v.D = C.D.p; v.w = C.w.p;
+  v.z = C.has_shift ? C.zbar.p : nullptr;
   return v;
 }
 
@@ -39,7 +42,7 @@ static CView cview(const CoarseLevel& C) {
 // every multiply-add written as an explicit fma, so a step gives the same
 // bits in both whatever the compiler would contract.
 template <bool STEP, int NT>
-__device__ inline void coarse_row(const CView& v, double alpha, int it, const double* __restrict__ sig,
+__device__ inline void coarse_row(const CView& v, const KappaFam& kf, int it, const double* __restrict__ sig,
                                   const double* __restrict__ p, const double* __restrict__ dsig,
                                   const double* __restrict__ dp, const double* steps,
                                   const double* __restrict__ b, double* __restrict__ r, double* acc) {
@@ -80,7 +83,7 @@ __device__ inline void coarse_row(const CView& v, double alpha, int it, const do
         for (int t = 0; t < NT; ++t) ms[t] = fma(mi, stp(a, d, t), ms[t]);
       }
 #pragma unroll
-      for (int t = 0; t < NT; ++t) val[t] = val[t] + fma(exp(-alpha * pbar[t]), ms[t], dtp[t]);
+      for (int t = 0; t < NT; ++t) val[t] = val[t] + fma(kap_inv(kf, kap_psi(v.z, pbar[t], c)), ms[t], dtp[t]);
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -117,7 +120,7 @@ __device__ inline void coarse_row(const CView& v, double alpha, int it, const do
 }
 
 template <bool STEP>
-__global__ void __launch_bounds__(kBlock) k_coarse_resid(CView v, double alpha, const double* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_coarse_resid(CView v, KappaFam kf, const double* __restrict__ x,
                                                          const double* __restrict__ dx, double step,
                                                          const double* __restrict__ b, double* __restrict__ r,
                                                          double* __restrict__ parts) {
@@ -125,7 +128,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_resid(CView v, double alpha, 
   double acc[1] = {0.0};
   const int ntot = v.nf + v.n;
   for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x)
-    coarse_row<STEP, 1>(v, alpha, it, x, x + v.nf, dx, STEP ? dx + v.nf : nullptr, &step, b, r, acc);
+    coarse_row<STEP, 1>(v, kf, it, x, x + v.nf, dx, STEP ? dx + v.nf : nullptr, &step, b, r, acc);
   const double a = block_sum(acc[0], sh);
   if (threadIdx.x == 0) parts[blockIdx.x] = a;
 }
@@ -137,7 +140,7 @@ struct CoarseSteps {
 // Sums of squares of r(x + s_t dx) for NT step lengths in one pass:
 // parts[t * gridDim.x + block].
 template <int NT>
-__global__ void __launch_bounds__(kBlock) k_coarse_resid_trials(CView v, double alpha, const double* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_coarse_resid_trials(CView v, KappaFam kf, const double* __restrict__ x,
                                                                 const double* __restrict__ dx, CoarseSteps st,
                                                                 const double* __restrict__ b,
                                                                 double* __restrict__ parts) {
@@ -147,7 +150,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_resid_trials(CView v, double 
   for (int t = 0; t < NT; ++t) acc[t] = 0.0;
   const int ntot = v.nf + v.n;
   for (int it = blockIdx.x * blockDim.x + threadIdx.x; it < ntot; it += gridDim.x * blockDim.x)
-    coarse_row<true, NT>(v, alpha, it, x, x + v.nf, dx, dx + v.nf, st.s, b, nullptr, acc);
+    coarse_row<true, NT>(v, kf, it, x, x + v.nf, dx, dx + v.nf, st.s, b, nullptr, acc);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const double a = block_sum(acc[t], sh);
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_resid_trials(CView v, double 
   }
 }
 
-int launch_coarse_resid_trials(const CoarseLevel& C, double alpha, const double* x, const double* dx,
+int launch_coarse_resid_trials(const CoarseLevel& C, const KappaFam& kf, const double* x, const double* dx,
                                const double* steps, int nt, const double* b, double* parts, hipStream_t s) {
   require(nt >= 1 && nt <= kMaxTrials, "number of trial steps out of range");
   const int G = reduce_grid(C.nf + C.n);
@@ -163,23 +166,23 @@ int launch_coarse_resid_trials(const CoarseLevel& C, double alpha, const double*
   CoarseSteps cs{};
   for (int t = 0; t < nt; ++t) cs.s[t] = steps[t];
   switch (nt) {
-    case 1: hipLaunchKernelGGL(k_coarse_resid_trials<1>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
-    case 2: hipLaunchKernelGGL(k_coarse_resid_trials<2>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
-    case 3: hipLaunchKernelGGL(k_coarse_resid_trials<3>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
-    default: hipLaunchKernelGGL(k_coarse_resid_trials<4>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, cs, b, parts); break;
+    case 1: hipLaunchKernelGGL(k_coarse_resid_trials<1>, dim3(G), dim3(kBlock), 0, s, v, kf, x, dx, cs, b, parts); break;
+    case 2: hipLaunchKernelGGL(k_coarse_resid_trials<2>, dim3(G), dim3(kBlock), 0, s, v, kf, x, dx, cs, b, parts); break;
+    case 3: hipLaunchKernelGGL(k_coarse_resid_trials<3>, dim3(G), dim3(kBlock), 0, s, v, kf, x, dx, cs, b, parts); break;
+    default: hipLaunchKernelGGL(k_coarse_resid_trials<4>, dim3(G), dim3(kBlock), 0, s, v, kf, x, dx, cs, b, parts); break;
   }
   LAUNCHCHECK();
   return G;
 }
 
-int launch_coarse_resid(const CoarseLevel& C, double alpha, const double* x, const double* dx, double step,
+int launch_coarse_resid(const CoarseLevel& C, const KappaFam& kf, const double* x, const double* dx, double step,
                         const double* b, double* r, double* parts, hipStream_t s) {
   const int G = reduce_grid(C.nf + C.n);
   CView v = cview(C);
   if (dx)
-    hipLaunchKernelGGL(k_coarse_resid<true>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, step, b, r, parts);
+    hipLaunchKernelGGL(k_coarse_resid<true>, dim3(G), dim3(kBlock), 0, s, v, kf, x, dx, step, b, r, parts);
   else
-    hipLaunchKernelGGL(k_coarse_resid<false>, dim3(G), dim3(kBlock), 0, s, v, alpha, x, dx, step, b, r, parts);
+    hipLaunchKernelGGL(k_coarse_resid<false>, dim3(G), dim3(kBlock), 0, s, v, kf, x, dx, step, b, r, parts);
   LAUNCHCHECK();
   return G;
 }
@@ -278,7 +281,7 @@ __global__ void __launch_bounds__(64) k_local_static(CView v, LocStatic ls, doub
 
 // Per cell (one wave): A_c^{-1} by block elimination, z_c = A_c^{-1} g_c with
 // g = [-r_hat; -r_p] (r_hat keeps r_sigma on the first owner only).
-__global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, LocStatic ls, double alpha, int newton,
+__global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, LocStatic ls, KappaFam kf, int newton,
                                                          const double* __restrict__ x, const double* __restrict__ r) {
   __shared__ double sT[kBlock / 64][64 * kLocM];
   __shared__ double sS[kBlock / 64][kLocM * kLocM];
@@ -300,8 +303,9 @@ __global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, LocStatic ls,
     const double* w = v.w + p0;
     double pbar = 0.0;
     for (int q = 0; q < m; ++q) pbar += w[q] * p[p0 + q];
-    const double sc = exp(-alpha * pbar);
-    dsc = -alpha * sc;
+    const double ps = kap_psi(v.z, pbar, c);
+    const double sc = kap_inv(kf, ps);
+    dsc = kap_dinv(kf, ps, sc);
     isc = 1.0 / sc;
     double sj = 0.0, g1 = 0.0;
 #pragma unroll
@@ -424,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_local(HView hv, LocStatic ls,
 // ---- general cells: LU of the whole saddle block
 // Per cell: build A_c, invert it (LU with partial pivoting, then the columns
 // of the inverse), z_c = A_c^{-1} g_c.
-__global__ void __launch_bounds__(kBlock) k_coarse_local_lu(HView hv, double alpha, int newton, const double* __restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_coarse_local_lu(HView hv, KappaFam kf, int newton, const double* __restrict__ x,
                                                          const double* __restrict__ r) {
   const CView& v = hv.v;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -439,8 +443,9 @@ __global__ void __launch_bounds__(kBlock) k_coarse_local_lu(HView hv, double alp
   const double* p = x + v.nf;
   double pbar = 0.0;
   for (int q = 0; q < m; ++q) pbar += v.w[p0 + q] * p[p0 + q];
-  const double sc = exp(-alpha * pbar);
-  const double dsc = -alpha * sc;
+  const double ps = kap_psi(v.z, pbar, c);
+  const double sc = kap_inv(kf, ps);
+  const double dsc = kap_dinv(kf, ps, sc);
   double* A = hv.tmp + hv.invptr[c];
   double* inv = hv.inv + hv.invptr[c];
   for (int i = 0; i < k; ++i) {
@@ -509,7 +514,7 @@ __global__ void __launch_bounds__(kBlock) k_coarse_local_lu(HView hv, double alp
   }
 }
 
-void launch_coarse_local(CoarseLevel& C, double alpha, bool newton, const double* x, const double* r,
+void launch_coarse_local(CoarseLevel& C, const KappaFam& kf, bool newton, const double* x, const double* r,
                          hipStream_t s) {
   HView hv;
   hv.v = cview(C);
@@ -521,10 +526,10 @@ void launch_coarse_local(CoarseLevel& C, double alpha, bool newton, const double
   hv.z = C.z.p;
   if (C.fast_local) {
     const LocStatic ls{C.gptr.p, C.sgptr.p, C.Minv.p, C.G.p, C.DG.p};
-    hipLaunchKernelGGL(k_coarse_local, dim3(grid_for(C.n, kBlock / 64)), dim3(kBlock), 0, s, hv, ls, alpha,
+    hipLaunchKernelGGL(k_coarse_local, dim3(grid_for(C.n, kBlock / 64)), dim3(kBlock), 0, s, hv, ls, kf,
                        newton ? 1 : 0, x, r);
   } else {
-    hipLaunchKernelGGL(k_coarse_local_lu, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, hv, alpha, newton ? 1 : 0,
+    hipLaunchKernelGGL(k_coarse_local_lu, dim3(grid_for(C.n, kBlock)), dim3(kBlock), 0, s, hv, kf, newton ? 1 : 0,
                        x, r);
   }
   LAUNCHCHECK();
@@ -746,6 +751,29 @@ __global__ void __launch_bounds__(kBlock) k_restrict_t(TView t, const double* __
   }
 }
 
+// out[A] = sum over the level-l cells c of A of vol_l[c] z_l[c], over vol_c[A]
+// (the cells in the plan's list order, a thread per aggregate)
+__global__ void k_volume_mean(int n_agg, const int* __restrict__ cell_ptr, const int* __restrict__ cell_list,
+                              const double* __restrict__ vol_l, const double* __restrict__ z_l,
+                              const double* __restrict__ vol_c, double* __restrict__ out) {
+  const int A = blockIdx.x * blockDim.x + threadIdx.x;
+  if (A >= n_agg) return;
+  double acc = 0.0;
+  for (int i = cell_ptr[A]; i < cell_ptr[A + 1]; ++i) {
+    const int c = cell_list[i];
+    acc = fma(vol_l[c], z_l[c], acc);
+  }
+  out[A] = acc / vol_c[A];
+}
+
+void launch_volume_mean(const TransferDev& T, const double* vol_l, const double* z_l, const double* vol_c,
+                        double* out, hipStream_t s) {
+  if (T.n_agg == 0) return;
+  hipLaunchKernelGGL(k_volume_mean, dim3(grid_for(T.n_agg, kBlock)), dim3(kBlock), 0, s, T.n_agg, T.cell_ptr.p,
+                     T.cell_list.p, vol_l, z_l, vol_c, out);
+  LAUNCHCHECK();
+}
+
 void launch_restrict(const TransferDev& T, const CoarseLevel& Cc, const double* rf, double* out, hipStream_t s) {
   TView t = tview(T, Cc);
   hipLaunchKernelGGL(k_restrict_t<false>, dim3(grid_for(t.nf_c + t.n_agg, kBlock / 64)), dim3(kBlock), 0, s, t, rf,
@@ -915,7 +943,7 @@ void setup_coarse_solver(Hierarchy& h, int l) {
     // aggregation matrix: Picard at x = 0 (kappa = 1)
     C.x.zero(s);
     C.r.zero(s);
-    launch_coarse_local(C, 0.0, false, C.x.p, C.r.p, s);
+    launch_coarse_local(C, KappaFam{}, false, C.x.p, C.r.p, s);   // exp(0 psi) = 1
     launch_H_assemble(C, s);
     HIPCHECK(hipStreamSynchronize(s));
     C.amg.setup(C.H, s);

@@ -43,6 +43,8 @@ struct CoarseLevel {
   DVec<int> pptr, lfptr, lfidx, mptr, dptr, c1, c2;
   DVec<int8_t> kind;
   DVec<double> M, D, w, ones, u, vol;
+  DVec<double> zbar;              // kappa shift per cell of the current problem (when has_shift)
+  bool has_shift = false;
   DVec<int> fcell, floc;          // [2*nf]
   int nsum = 0;                   // sum over cells of (k_c + m_c)
   DVec<int> zptr, invptr;         // offsets of local solution vectors / inverses

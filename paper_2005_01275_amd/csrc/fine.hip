@@ -12,6 +12,7 @@
 //           side 1: cell is L (D = +1); nb[k] = cell across that face
 //           (the cell itself on a Dirichlet face).
 #include "fine.hpp"
+#include "kappa.hpp"
 
 #include "kern.hpp"
 
@@ -71,10 +72,11 @@ void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, co
 // shared by the single-step and the multi-step kernels (multiply-adds as
 // explicit fma) so that a trial step gives the same bits in both.
 __device__ inline double flux_row(const FineView& v, int64_t i, double pK, double pL, double sj) {
-  double m = exp(-v.alpha * pK) * v.TKi[i];
+  const int K = v.K[i], L = v.L[i];
+  double m = kap_inv(v.kf, kap_psi(v.z, pK, K)) * v.TKi[i];
   double dtp = -pK;
-  if (v.L[i] >= 0) {
-    m = fma(exp(-v.alpha * pL), v.TLi[i], m);
+  if (L >= 0) {
+    m = fma(kap_inv(v.kf, kap_psi(v.z, pL, L)), v.TLi[i], m);
     dtp += pL;
   }
   return fma(m, sj, dtp) + v.g[i];
@@ -246,7 +248,6 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
   if (c >= v.n) return;   // the whole group leaves together
   const double* sig = x;
   const double* p = x + v.nf;
-  const double a_ = v.alpha;
   const int k0 = v.cfptr[c], k1 = v.cfptr[c + 1];
   TV* row = nullptr;
   if constexpr (SELL) row = sval + sptr[c >> 6] + (c & 63);   // slot k of the row: row[64 k]
@@ -256,19 +257,23 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
     const int j = code >> 1;
     const int K = v.K[j], L = v.L[j];
     const double pK = p[K];
-    const double eK = exp(-a_ * pK) * v.TKi[j];
-    double eL = 0.0, pL = 0.0;
+    const double psK = kap_psi(v.z, pK, K);
+    const double iK = kap_inv(v.kf, psK);
+    const double eK = iK * v.TKi[j];
+    double eL = 0.0, pL = 0.0, psL = 0.0, iL = 0.0;
     if (L >= 0) {
       pL = p[L];
-      eL = exp(-a_ * pL) * v.TLi[j];
+      psL = kap_psi(v.z, pL, L);
+      iL = kap_inv(v.kf, psL);
+      eL = iL * v.TLi[j];
     }
     const double m = eK + eL;
     const double sj = sig[j];
     const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
     double EK = -1.0, EL = 1.0;
-    if (NEWTON) {
-      EK -= a_ * eK * sj;
-      EL -= a_ * eL * sj;
+    if (NEWTON) {   // d r_sigma / d p_K = d(1/kappa_K)/dp Tbar_K^{-1} sigma - 1 (Prop. 3 on level 0)
+      EK += kap_dinv(v.kf, psK, iK) * v.TKi[j] * sj;
+      if (L >= 0) EL += kap_dinv(v.kf, psL, iL) * v.TLi[j] * sj;
     }
     const double ainv = 1.0 / m;
     const double uk = ainv * EK, ul = ainv * EL, vs = sj - ainv * rs;
@@ -348,17 +353,20 @@ __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const doubl
   const double* sig = x;
   const double* p = x + nf;
   const double* dp = dx + nf;
-  const double a_ = v.alpha;
   double mx = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ntot; i += (int64_t)gridDim.x * blockDim.x) {
     if (i < nf) {
       const int K = v.K[i], L = v.L[i];
       const double pK = p[K];
-      const double eK = exp(-a_ * pK) * v.TKi[i];
-      double eL = 0.0, pL = 0.0, dpL = 0.0;
+      const double psK = kap_psi(v.z, pK, K);
+      const double iK = kap_inv(v.kf, psK);
+      const double eK = iK * v.TKi[i];
+      double eL = 0.0, pL = 0.0, dpL = 0.0, psL = 0.0, iL = 0.0;
       if (L >= 0) {
         pL = p[L];
-        eL = exp(-a_ * pL) * v.TLi[i];
+        psL = kap_psi(v.z, pL, L);
+        iL = kap_inv(v.kf, psL);
+        eL = iL * v.TLi[i];
         dpL = dp[L];
       }
       const double m = eK + eL;
@@ -366,8 +374,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const doubl
       const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[i];
       double EK = -1.0, EL = 1.0;
       if (NEWTON) {
-        EK -= a_ * eK * sj;
-        EL -= a_ * eL * sj;
+        EK += kap_dinv(v.kf, psK, iK) * v.TKi[i] * sj;
+        if (L >= 0) EL += kap_dinv(v.kf, psL, iL) * v.TLi[i] * sj;
       }
       dx[i] = -(rs + EK * dp[K] + (L >= 0 ? EL * dpL : 0.0)) / m;
     } else {

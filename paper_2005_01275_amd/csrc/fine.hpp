@@ -5,9 +5,18 @@
 
 namespace spfas {
 
+// kappa of K(x, p) = K0(x) kappa(p - z(x)), z a per-cell shift:
+// kind 0: exp(alpha psi) (Section 2, the model problem);
+// kind 1: a / (a + |psi|^beta) (Example 3, Richards-type conductivity).
+struct KappaFam {
+  int kind = 0;
+  double alpha = 0.0, a = 1.0, beta = 2.0;
+};
+
 struct FineView {
   int64_t n = 0, nf = 0;
-  double alpha = 0.0;
+  KappaFam kf;
+  const double* z = nullptr;   // [n] shift per internal cell, nullptr: none
   const int* K = nullptr;
   const int* L = nullptr;
   const double* TKi = nullptr;

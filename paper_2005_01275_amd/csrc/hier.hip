@@ -9,6 +9,7 @@
 #include <numeric>
 
 #include "coarse.hpp"
+#include "coarse_kern.hpp"
 #include "kern.hpp"
 #include "solve.hpp"
 #include "sparse.hpp"
@@ -294,18 +295,46 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
 void Hierarchy::set_problem(const spfas_problem& P) {
   require(P.source != nullptr, "problem.source must not be NULL");
   require(std::isfinite(P.alpha), "problem.alpha must be finite");
-  fine.alpha = P.alpha;
+  require(P.kappa_kind == SPFAS_KAPPA_EXP || P.kappa_kind == SPFAS_KAPPA_RICHARDS,
+          "problem.kappa_kind must be SPFAS_KAPPA_EXP or SPFAS_KAPPA_RICHARDS");
+  KappaFam kf;
+  kf.kind = P.kappa_kind;
+  kf.alpha = P.alpha;
+  if (P.kappa_kind == SPFAS_KAPPA_RICHARDS) {
+    require(std::isfinite(P.kappa_a) && P.kappa_a > 0.0, "problem.kappa_a must be finite and > 0");
+    require(std::isfinite(P.kappa_beta) && P.kappa_beta >= 1.0, "problem.kappa_beta must be finite and >= 1");
+    kf.a = P.kappa_a;
+    kf.beta = P.kappa_beta;
+  }
+  fine.kf = kf;
   hipStream_t s = stream;
-  const double *src = P.source, *gD = P.g_dirichlet, *gN = P.g_neumann;
-  DVec<double> hs, hd, hn;
+  const double *src = P.source, *gD = P.g_dirichlet, *gN = P.g_neumann, *sh = P.shift;
+  DVec<double> hs, hd, hn, hz;
   if (P.mem == SPFAS_MEM_HOST) {
     hs.upload(P.source, n_cells_in, s);
     src = hs.p;
     if (gD) { hd.upload(P.g_dirichlet, n_faces_in, s); gD = hd.p; }
     if (gN) { hn.upload(P.g_neumann, n_faces_in, s); gN = hn.p; }
+    if (sh) { hz.upload(P.shift, n_cells_in, s); sh = hz.p; }
   }
   launch_fine_problem(fine.view(), fine.cell_in.p, fine.flux_in.p, fine.vol.p, fine.nptr.p, fine.nface.p,
                       fine.narea.p, src, gD, gN, fine.f.p, fine.g.p, s);
+  // shift of kappa: level 0 in internal order, coarse levels the volume
+  // means over their level-0 cells (level by level: the mean of the finer
+  // level's means weighted by the finer cells' volumes)
+  fine.has_shift = sh != nullptr;
+  for (auto& C : coarse) C->has_shift = fine.has_shift;
+  if (sh) {
+    if (fine.z.n != fine.n) fine.z.alloc(fine.n);
+    launch_gather(fine.n, fine.cell_in.p, sh, fine.z.p, s);
+    for (int l = 0; l + 1 < n_levels; ++l) {
+      CoarseLevel& C = *coarse[l];
+      if (C.zbar.n != C.n) C.zbar.alloc(C.n);
+      const double* vol_l = l == 0 ? fine.vol.p : coarse[l - 1]->vol.p;
+      const double* z_l = l == 0 ? fine.z.p : coarse[l - 1]->zbar.p;
+      launch_volume_mean(*trans[l], vol_l, z_l, C.vol.p, C.zbar.p, s);
+    }
+  }
   HIPCHECK(hipStreamSynchronize(s));
 }
 

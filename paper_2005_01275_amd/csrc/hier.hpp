@@ -27,10 +27,12 @@ struct FineDev {
   DVec<int> neu_in;                       // all Neumann faces (input ids)
   DVec<double> neu_area;
   DVec<double> f, g;                      // problem data of the current solve
-  double alpha = 0.0;
+  KappaFam kf;                            // kappa family of the current solve
+  DVec<double> z;                         // its shift per internal cell (when has_shift)
+  bool has_shift = false;
   FineView view() const {
     FineView v;
-    v.n = n; v.nf = nf; v.alpha = alpha;
+    v.n = n; v.nf = nf; v.kf = kf; v.z = has_shift ? z.p : nullptr;
     v.K = K.p; v.L = L.p; v.TKi = TKi.p; v.TLi = TLi.p; v.g = g.p; v.f = f.p;
     v.cfptr = cfptr.p; v.cfcode = cfcode.p;
     return v;

@@ -80,8 +80,10 @@ struct Request {
   int64_t model = 0;
   int32_t kind = SPFAS_SOLVE_FAS;
   double alpha = 0.0;
-  std::vector<double> src, gd, gn;
-  bool has_gd = false, has_gn = false;
+  int32_t kappa_kind = SPFAS_KAPPA_EXP;
+  double kappa_a = 1.0, kappa_beta = 2.0;
+  std::vector<double> src, gd, gn, shift;
+  bool has_gd = false, has_gn = false, has_shift = false;
   spfas_solve_opts opts{};
   std::vector<double> p, sigma;
   spfas_stats st{};
@@ -196,6 +198,10 @@ struct spfas_server {
         pb.g_dirichlet = r->has_gd ? r->gd.data() : nullptr;
         pb.g_neumann = r->has_gn ? r->gn.data() : nullptr;
         pb.mem = SPFAS_MEM_HOST;
+        pb.kappa_kind = r->kappa_kind;
+        pb.kappa_a = r->kappa_a;
+        pb.kappa_beta = r->kappa_beta;
+        pb.shift = r->has_shift ? r->shift.data() : nullptr;
         r->p.assign(m->n_cells, 0.0);
         r->sigma.assign(m->n_faces, 0.0);
         switch (r->kind) {
@@ -340,6 +346,10 @@ int spfas_server_submit(spfas_server* S, int64_t model_id, const spfas_problem* 
     r->src.assign(prob->source, prob->source + m.n_cells);
     if (prob->g_dirichlet) { r->gd.assign(prob->g_dirichlet, prob->g_dirichlet + m.n_faces); r->has_gd = true; }
     if (prob->g_neumann) { r->gn.assign(prob->g_neumann, prob->g_neumann + m.n_faces); r->has_gn = true; }
+    if (prob->shift) { r->shift.assign(prob->shift, prob->shift + m.n_cells); r->has_shift = true; }
+    r->kappa_kind = prob->kappa_kind;
+    r->kappa_a = prob->kappa_a;
+    r->kappa_beta = prob->kappa_beta;
     r->model = model_id;
     r->kind = kind;
     r->alpha = prob->alpha;

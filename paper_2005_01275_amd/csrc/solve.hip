@@ -235,10 +235,10 @@ void setup_fine_solver(Hierarchy& h) {
   w.S.val = w.Soff.p;
   // matrix of the aggregation: Picard at p = 0 (kappa = 1)
   w.x.zero(s);
-  const double a = f.alpha;
-  f.alpha = 0.0;
-  launch_fine_linearize_cells(f.view(), false, w.x.p, nullptr, nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
-  f.alpha = a;
+  FineView v1 = f.view();
+  v1.kf = KappaFam{};   // exp(0 psi) = 1
+  v1.z = nullptr;
+  launch_fine_linearize_cells(v1, false, w.x.p, nullptr, nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
   HIPCHECK(hipStreamSynchronize(s));
   w.amg.setup(w.S, s, true, kDenseLds, true);
   if (trace_on()) std::fprintf(stderr, "[spfas] level 0 AMG: %s\n", w.amg.describe().c_str());
@@ -479,7 +479,7 @@ static void launch_sub(int64_t n, const double* a, const double* b, double* out,
 
 static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* dx, double step) {
   CoarseLevel& C = *h.coarse[l - 1];
-  const int G = launch_coarse_resid(C, h.fine.alpha, x, dx, step, C.b.p, nullptr, h.dpin, h.stream);
+  const int G = launch_coarse_resid(C, h.fine.kf, x, dx, step, C.b.p, nullptr, h.dpin, h.stream);
   return std::sqrt(h.host_sum(G));   // may be non-finite inside Alg. 1 trials
 }
 
@@ -488,7 +488,7 @@ static double coarse_rnorm(Hierarchy& h, int l, const double* x, const double* d
 static void coarse_rnorm_trials(Hierarchy& h, int l, const double* x, const double* dx, const double* steps, int k,
                                 double* out) {
   CoarseLevel& C = *h.coarse[l - 1];
-  const int G = launch_coarse_resid_trials(C, h.fine.alpha, x, dx, steps, k, C.b.p, h.dpin, h.stream);
+  const int G = launch_coarse_resid_trials(C, h.fine.kf, x, dx, steps, k, C.b.p, h.dpin, h.stream);
   h.host_sums(G, k, out);
   for (int t = 0; t < k; ++t) out[t] = std::sqrt(out[t]);
 }
@@ -500,10 +500,10 @@ static double coarse_smooth(Hierarchy& h, int l, const Opts& o, double r_x, spfa
   if (moved) *moved = false;
   CoarseLevel& C = *h.coarse[l - 1];
   hipStream_t s = h.stream;
-  const double alpha = h.fine.alpha;
+  const KappaFam& kf = h.fine.kf;
   const double t0 = trace_on() ? trace_clock(s) : 0.0;
-  launch_coarse_resid(C, alpha, C.x.p, nullptr, 0.0, C.b.p, C.r.p, h.parts.p, s);
-  launch_coarse_local(C, alpha, o.newton, C.x.p, C.r.p, s);
+  launch_coarse_resid(C, kf, C.x.p, nullptr, 0.0, C.b.p, C.r.p, h.parts.p, s);
+  launch_coarse_local(C, kf, o.newton, C.x.p, C.r.p, s);
   int it = 0;
   if (C.nl > 0) {
     launch_H_assemble(C, s);
@@ -577,7 +577,7 @@ static double nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, 
   }
   FineWork& w = h.fw;
   FineDev& f = h.fine;
-  const double alpha = f.alpha;
+  const KappaFam& kf = f.kf;
   double* x = l == 0 ? w.x.p : h.coarse[l - 1]->x.p;
   double* dx = l == 0 ? w.dx.p : h.coarse[l - 1]->dx.p;
   double* r = l == 0 ? w.xt.p : h.coarse[l - 1]->r.p;
@@ -597,7 +597,7 @@ static double nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, 
     launch_div_fine(f.n, f.cfptr.p, f.cfcode.p, x, div, s);
   } else {
     CoarseLevel& C = *h.coarse[l - 1];
-    launch_coarse_resid(C, alpha, x, nullptr, 0.0, C.b.p, r, h.parts.p, s);
+    launch_coarse_resid(C, kf, x, nullptr, 0.0, C.b.p, r, h.parts.p, s);
     launch_div_coarse(C, x, div, s);
   }
   CoarseLevel& Cc = *h.coarse[l];
@@ -606,7 +606,7 @@ static double nonlinear_mg(Hierarchy& h, int l, const Opts& o, spfas_stats& st, 
   launch_project(T, Cc, x, div, Cc.x.p, s);
   launch_copy(nc, Cc.x.p, Cc.x0.p, s);
   launch_restrict(T, Cc, r, Cc.b.p, s);
-  launch_coarse_resid(Cc, alpha, Cc.x.p, nullptr, 0.0, Cc.zeros.p, Cc.ax.p, h.parts.p, s);
+  launch_coarse_resid(Cc, kf, Cc.x.p, nullptr, 0.0, Cc.zeros.p, Cc.ax.p, h.parts.p, s);
   launch_sub(nc, Cc.ax.p, Cc.b.p, Cc.b.p, s);
   nonlinear_mg(h, l + 1, o, st, 0.0, stopped);
   // coarse correction P(y - Q x) with Alg. 1 on level l
@@ -667,7 +667,7 @@ static int run_cascadic(Hierarchy& h, const Opts& o_in, spfas_stats& st, int32_t
   const int L = h.n_levels;
   FineWork& w = h.fw;
   FineDev& f = h.fine;
-  const double alpha = f.alpha;
+  const KappaFam& kf = f.kf;
   auto state = [&](int l) { return l == 0 ? w.x.p : h.coarse[l - 1]->x.p; };
   auto size = [&](int l) -> int64_t {
     return l == 0 ? f.nf + f.n : h.coarse[l - 1]->nf + h.coarse[l - 1]->np;
@@ -687,7 +687,7 @@ static int run_cascadic(Hierarchy& h, const Opts& o_in, spfas_stats& st, int32_t
       launch_fine_resid(f.view(), w.x.p, nullptr, 0.0, r, h.parts.p, s);
     } else {
       CoarseLevel& C = *h.coarse[l - 1];
-      launch_coarse_resid(C, alpha, C.x.p, nullptr, 0.0, C.b.p, r, h.parts.p, s);
+      launch_coarse_resid(C, kf, C.x.p, nullptr, 0.0, C.b.p, r, h.parts.p, s);
     }
     launch_restrict(*h.trans[l], Cc, r, Cc.b.p, s);
     launch_sub(Cc.nf + Cc.np, Cc.zeros.p, Cc.b.p, Cc.b.p, s);

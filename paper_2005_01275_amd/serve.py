@@ -56,8 +56,14 @@ class Server:
         src = np.ascontiguousarray(prob.source, dtype=np.float64)
         gd = np.ascontiguousarray(prob.g_dirichlet, dtype=np.float64)
         gn = np.ascontiguousarray(prob.g_neumann, dtype=np.float64)
+        shift = getattr(prob, "shift", None)
+        sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
         cp = N.spfas_problem(alpha=prob.alpha, source=src.ctypes.data, g_dirichlet=gd.ctypes.data,
-                             g_neumann=gn.ctypes.data, mem=N.SPFAS_MEM_HOST)
+                             g_neumann=gn.ctypes.data, mem=N.SPFAS_MEM_HOST,
+                             kappa_kind=N.KAPPA_KINDS[getattr(prob, "kappa_kind", "exp")],
+                             kappa_a=float(getattr(prob, "kappa_a", 1.0)),
+                             kappa_beta=float(getattr(prob, "kappa_beta", 2.0)),
+                             shift=None if sh is None else sh.ctypes.data)
         o = opts.c()
         t = C.c_int64()
         _check(self._L.spfas_server_submit(self.s, model_id, C.byref(cp), C.byref(o), kind, C.byref(t)))
