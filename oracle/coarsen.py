@@ -251,11 +251,25 @@ def aggregate_data(level: Level, agg: np.ndarray, A: int, cells) -> AggData:
                    dir_dofs=dir_dofs, dofs=dofs, M=M, D=D)
 
 
-def local_spectral(level: Level, ad: AggData, m: int):
+def eig_count(lam: np.ndarray, m: int, threshold: float = 0.0, m_min: int = 2) -> int:
+    """Number of local eigenvectors kept for an aggregate whose ascending
+    eigenvalues are lam.  threshold <= 0: the uniform count m (the paper's
+    m_A).  threshold > 0: the eigenvalues up to threshold times the largest
+    (lambda_1 = 0 included), clamped to [m_min, m]; either way at most the
+    number of pressure unknowns of the aggregate."""
+    if threshold > 0.0:
+        cnt = int(np.count_nonzero(lam <= threshold * lam[-1]))
+        mA = min(max(cnt, m_min), m)
+    else:
+        mA = m
+    return min(mA, lam.size)
+
+
+def local_spectral(level: Level, ad: AggData, m: int, threshold: float = 0.0, m_min: int = 2):
     """Eigen-decomposition of L_A = D|_A (M|_int(A))^{-1} D|_A^T with the
     static (kappa = 1) matrices (eq. local-eigenvalue-problem) and
     P_A = [q_PV, v_2, ..., v_m] (eqs. structure_pressure_interpolation and
-    definition_q_pv)."""
+    definition_q_pv); m per eig_count."""
     ni = ad.int_dofs.size
     Mi = ad.M[:ni, :ni]
     Di = ad.D[:, :ni]
@@ -267,7 +281,7 @@ def local_spectral(level: Level, ad: AggData, m: int):
     lam, V = np.linalg.eigh(L)
     one = level.ones[ad.pd]
     q = one / np.linalg.norm(one)
-    mA = min(m, ad.pd.size)
+    mA = eig_count(lam, m, threshold, m_min)
     cols = [q]
     for i in range(1, mA):
         v = V[:, i] - (q @ V[:, i]) * q
@@ -362,7 +376,7 @@ class Transfer:
         return np.concatenate([self.P_sig.T @ r[:nf], self.P_p.T @ r[nf:]])
 
 
-def coarsen(level: Level, agg: np.ndarray, cshape, m: int):
+def coarsen(level: Level, agg: np.ndarray, cshape, m: int, threshold: float = 0.0, m_min: int = 2):
     n_agg = int(agg.max()) + 1
     cell_order, flux_order = renumber(level, agg)
     members = [np.sort(np.nonzero(agg == A)[0]) for A in range(n_agg)]
@@ -370,7 +384,7 @@ def coarsen(level: Level, agg: np.ndarray, cshape, m: int):
     for A in range(n_agg):
         if members[A].size == 0:
             raise ValueError("empty aggregate")
-        ads[A] = local_spectral(level, aggregate_data(level, agg, A, members[A]), m)
+        ads[A] = local_spectral(level, aggregate_data(level, agg, A, members[A]), m, threshold, m_min)
     # coarse flux numbering: interior interfaces (A<B), Dirichlet groups, bubbles
     pairs = sorted({(A, B) for A in range(n_agg) for B in ads[A].faces if A < B})
     dirs = [A for A in range(n_agg) if ads[A].dir_dofs.size]
@@ -477,17 +491,24 @@ class Hierarchy:
     finemap: object
 
 
-def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, user_agg=None) -> Hierarchy:
+def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, user_agg=None,
+                    eig_threshold=None, m_min=None) -> Hierarchy:
     """Levels and transfers of ``prob``.  Aggregation: boxes on the level
     lattice by default; ``greedy_size`` > 0 selects ``greedy_aggregate``;
     ``user_agg`` (one array per coarsened level) gives it explicitly.
-    Defaults come from the problem's own configuration."""
+    ``eig_threshold`` > 0 selects the eigenvalue-threshold count of
+    ``eig_count`` (m is then the upper clamp).  Defaults come from the
+    problem's own configuration."""
     from .fv import fine_level
     n_levels = prob.n_levels if n_levels is None else n_levels
     box = prob.box if box is None else box
     m = prob.m if m is None else m
     if greedy_size is None:
         greedy_size = getattr(prob, "greedy_size", 0)
+    if eig_threshold is None:
+        eig_threshold = getattr(prob, "eig_threshold", 0.0)
+    if m_min is None:
+        m_min = getattr(prob, "m_min", 2)
     lev, b0, fm = fine_level(prob)
     levels, transfers = [lev], []
     for l in range(n_levels - 1):
@@ -500,7 +521,7 @@ def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, use
             if cur.lattice_shape is None:
                 raise ValueError("box aggregation needs a Cartesian lattice")
             agg, cshape = box_aggregate(cur.lattice_shape, cur.lattice_index, box)
-        coarse, tr = coarsen(cur, agg, cshape, m)
+        coarse, tr = coarsen(cur, agg, cshape, m, eig_threshold, m_min)
         levels.append(coarse)
         transfers.append(tr)
     return Hierarchy(levels=levels, transfers=transfers, b0=b0, alpha=kappa_of(prob), finemap=fm)

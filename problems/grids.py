@@ -62,6 +62,10 @@ class Problem:
     n_levels: int = 2
     dp_cap_c: float = 5.0          # cap constant c: max |dp| <= ln(c)/alpha
     greedy_size: int = 0           # > 0: greedy aggregates of about this many cells (unstructured meshes)
+    # > 0: eigenvectors per aggregate by the eigenvalue threshold (lambda <=
+    # eig_threshold * lambda_max), clamped to [m_min, m]
+    eig_threshold: float = 0.0
+    m_min: int = 2
     # kappa family: "exp" (exp(alpha psi)) or "richards" (a / (a + |psi|^beta)),
     # evaluated at psi = p - shift (shift per cell, None = 0)
     kappa_kind: str = "exp"
@@ -363,7 +367,7 @@ def bilinear_sample(field: np.ndarray, xy: np.ndarray) -> np.ndarray:
 
 def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, corr_len: float = 0.01,
                     alpha: float = 2.0, lattice: int = 0, rate: Optional[float] = None, n_levels: int = 3,
-                    greedy_size: int = 64, m: int = 3) -> Problem:
+                    greedy_size: int = 64, m: int = 3, eig_threshold: float = 0.0, m_min: int = 2) -> Problem:
     """Unstructured 2-D problem on the Voronoi mesh of ``n_points`` seeded
     uniform points in the unit square: ln k = sigma G, G a standardised
     Gaussian random field of correlation length ``corr_len`` (in units of
@@ -375,7 +379,9 @@ def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, cor
     1.0): with kappa = exp(alpha p) a strong sink leaves the problem without a
     solution, and the rule used with these meshes is alpha max|p| = 0.5 for
     the kappa = 1 pressure (p is linear in the rate there).  Greedy
-    aggregates of about ``greedy_size`` cells, m local eigenvectors."""
+    aggregates of about ``greedy_size`` cells, m local eigenvectors (with
+    eig_threshold > 0: those with eigenvalue up to eig_threshold times the
+    largest, between m_min and m)."""
     rng = np.random.default_rng(seed)
     pts = rng.random((n_points, 2))
     if lattice <= 0:
@@ -392,7 +398,7 @@ def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, cor
     prob = Problem(mesh=mesh, alpha=alpha, source=src, g_dirichlet=np.zeros(mesh.n_faces),
                    g_neumann=np.zeros(mesh.n_faces), name=f"voronoi_2d_{n_points}", box=(), m=m,
                    n_levels=n_levels, dp_cap_c=5.0)
-    return dataclasses.replace(prob, greedy_size=greedy_size)
+    return dataclasses.replace(prob, greedy_size=greedy_size, eig_threshold=eig_threshold, m_min=m_min)
 
 
 def served_problem(seed: int, n_min: int = 32 ** 2, n_max: int = 64 ** 3, dims=(2, 3), sigma: float = 2.0,

@@ -301,3 +301,57 @@ def test_cap():
     assert cap_scale(np.array([0.1, -2 * cap]), cap) == pytest.approx(0.5)
     assert math.isinf(cap_value(0.0, 5.0))
     assert cap_value(2.0, 1.5) == pytest.approx(math.log(1.5) / 2.0)
+
+
+# ------------------------------------------------------------- eigenvector count by threshold
+
+def test_eig_count_hand_cases():
+    from oracle.coarsen import eig_count
+    lam = np.array([0.0, 0.05, 0.09, 0.1, 0.5, 1.0])
+    assert eig_count(lam, 6, 0.1) == 4          # 0, 0.05, 0.09, 0.1 <= 0.1 * 1.0
+    assert eig_count(lam, 3, 0.1) == 3          # upper clamp m
+    assert eig_count(np.array([0.0, 0.5, 1.0]), 6, 0.1) == 2     # lower clamp m_min
+    assert eig_count(np.array([0.0, 0.5, 1.0]), 6, 0.1, m_min=1) == 1
+    assert eig_count(np.array([0.0]), 6, 0.1) == 1               # at most the unknowns of the aggregate
+    assert eig_count(lam, 5, 0.0) == 5          # threshold off: the uniform count
+    assert eig_count(np.r_[np.linspace(0.0, 0.01, 9), 1.0], 6, 0.1) == 6          # 9 below: upper clamp
+
+
+def test_threshold_count_on_uniform_boxes_closed_form():
+    """Uniform k: the eigenvalues of each box are the Kronecker sums of the
+    path-graph spectra, so the count kept by the threshold rule is known in
+    closed form; every aggregate of the hierarchy keeps exactly that many,
+    and the coarse level has that many pressure unknowns per cell."""
+    for shape, box, spacing, thr in [((8, 8), (4, 4), (0.5, 0.25), 0.1), ((8, 8), (4, 4), (0.5, 0.25), 0.15),
+                                     ((8, 8), (4, 4), (0.25, 0.25), 0.3), ((4, 6, 4), (4, 3, 2), (1.0, 0.5, 0.2), 0.1),
+                                     ((4, 6, 4), (4, 3, 2), (1.0, 0.5, 0.2), 0.06)]:
+        prob = small_problem(shape, seed=0, sigma=0.0, box=box, m=6, n_levels=2, spacing=spacing)
+        h = build_hierarchy(prob, eig_threshold=thr, m_min=2)
+        dim = len(shape)
+        h_ = np.array(spacing)
+        w = (np.prod(h_) / h_) / h_
+        grids = np.meshgrid(*[2 * w[a] * (1 - np.cos(np.arange(box[a]) * math.pi / box[a]))
+                              for a in range(dim)], indexing="ij")
+        ref = np.sort(sum(g.ravel() for g in grids))
+        want = min(max(int(np.sum(ref <= thr * ref[-1] * (1 + 1e-12))), 2), 6)
+        counts = np.diff(h.levels[1].pdof_ptr)
+        assert np.all(counts == want), (shape, thr, counts, want)
+
+
+def test_threshold_hierarchy_invariants_and_root():
+    """Heterogeneous k, counts varying per aggregate: Q_p P_p = I, the
+    commuting property, and FAS reaching the same root as with a fixed m."""
+    prob = small_problem((12, 12), seed=8, sigma=1.5, box=(4, 4), m=6, n_levels=3, alpha=1.0, src_scale=3.0)
+    h = build_hierarchy(prob, eig_threshold=0.1, m_min=2)
+    counts = np.diff(h.levels[1].pdof_ptr)
+    assert counts.min() >= 2 and counts.max() <= 6 and counts.min() < counts.max()
+    for l, tr in enumerate(h.transfers):
+        lev, clev = h.levels[l], h.levels[l + 1]
+        np.testing.assert_allclose((tr.Q_p @ tr.P_p).toarray(), np.eye(clev.n_p), atol=1e-12)
+        np.testing.assert_allclose((tr.Q_sig @ tr.P_sig).toarray(), np.eye(clev.n_flux), atol=1e-11)
+        rhs = (tr.Q_p @ lev.D).toarray()
+        np.testing.assert_allclose((clev.D @ tr.Q_sig).toarray(), rhs, atol=1e-10 * np.abs(rhs).max())
+    xs = result_solve(h)
+    x, st = fas_solve(h, Opts(newton=True, rtol=1e-13, atol=0.0, max_it=60))
+    assert st.converged
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
