@@ -139,6 +139,16 @@ typedef enum {
  *             aggregate below greedy_size/2 cells, in ascending id, joins the
  *             neighbouring aggregate it shares the most interior faces with
  *             (ties: lower id); ids are compacted in ascending order
+ *   eig_threshold  > 0: the number of eigenvectors of each aggregate is
+ *             the number of eigenvalues of its local problem (eq.
+ *             local-eigenvalue-problem, lambda_1 = 0 included) up to
+ *             eig_threshold times its largest eigenvalue, clamped to
+ *             [m_min, m] and to the aggregate's unknowns; a varying count
+ *             per aggregate is allowed by Appendix A (m_A per aggregate).
+ *             The setup then solves each level's eigenproblems once more to
+ *             count before it builds the coarser level.  Not with
+ *             host_only.  <= 0: the uniform m above.
+ *   m_min     lower clamp of the threshold count (1 <= m_min <= m)
  */
 typedef struct {
   int32_t n_levels;
@@ -149,6 +159,8 @@ typedef struct {
   const int32_t* user_agg;
   int64_t user_agg_len;
   int32_t greedy_size;
+  double eig_threshold;
+  int32_t m_min;
 } spfas_coarsen_opts;
 
 /*
@@ -484,7 +496,8 @@ typedef enum {
   SPFAS_OP_MLOC = 3,     /* level l+1: static M^{l+1}_A blocks (k_A x k_A, row-major), canonical order     */
   SPFAS_OP_DLOC = 4,     /* level l+1: D^{l+1}_A blocks (m_A x k_A, row-major), canonical order            */
   SPFAS_OP_W = 5,        /* level l+1: projector weights w_A, concatenated, canonical order                */
-  SPFAS_OP_QSIGMA = 6    /* level l: Q_sigma as dense [n_flux(l+1) x n_flux(l)], row-major, canonical      */
+  SPFAS_OP_QSIGMA = 6,   /* level l: Q_sigma as dense [n_flux(l+1) x n_flux(l)], row-major, canonical      */
+  SPFAS_OP_MCOUNT = 7    /* level l: m_A of each aggregate (as doubles), canonical aggregate order         */
 } spfas_level_op;
 
 /* Copies the operator `what` between `level` and level+1 into out[count]

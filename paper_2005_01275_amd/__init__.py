@@ -93,11 +93,13 @@ class Hierarchy:
     ``problems.Mesh`` (numpy host arrays)."""
 
     def __init__(self, mesh, n_levels: int, box=(), m: int = 1, host_only: bool = False, stream=None,
-                 agg_kind: int = N.SPFAS_AGG_BOX, user_agg=None, greedy_size: int = 0, allocator=None):
+                 agg_kind: int = N.SPFAS_AGG_BOX, user_agg=None, greedy_size: int = 0, allocator=None,
+                 eig_threshold: float = 0.0, m_min: int = 2):
         """allocator: None (hipMalloc) or "torch" (PyTorch's caching
         allocator owns the hierarchy's device memory).  user_agg: for
         agg_kind USER, the aggregation of every coarsened level,
-        concatenated."""
+        concatenated.  eig_threshold > 0: eigenvectors per aggregate by the
+        eigenvalue threshold, between m_min and m."""
         L = N.lib()
         self._keep = []
         ms, arrays = _mesh_struct(mesh)
@@ -110,7 +112,8 @@ class Hierarchy:
         op = N.spfas_coarsen_opts(n_levels=n_levels, box=(C.c_int32 * 3)(*box), m=m, host_only=int(host_only),
                                   agg_kind=agg_kind,
                                   user_agg=ua.ctypes.data_as(C.POINTER(C.c_int32)) if ua is not None else None,
-                                  user_agg_len=0 if ua is None else ua.size, greedy_size=greedy_size)
+                                  user_agg_len=0 if ua is None else ua.size, greedy_size=greedy_size,
+                                  eig_threshold=float(eig_threshold), m_min=int(m_min))
         if allocator not in (None, "torch"):
             raise ValueError("allocator must be None or 'torch'")
         alloc = C.byref(N.TORCH_ALLOCATOR) if allocator == "torch" else None

@@ -15,7 +15,7 @@ SPFAS_MEM_HOST, SPFAS_MEM_DEVICE = 0, 1
 SPFAS_NEWTON, SPFAS_PICARD = 0, 1
 SPFAS_PREC_FP64, SPFAS_PREC_MIXED = 0, 1
 SPFAS_AGG_BOX, SPFAS_AGG_USER, SPFAS_AGG_GREEDY = 0, 1, 2
-SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SPFAS_OP_W, SPFAS_OP_QSIGMA = range(7)
+SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SPFAS_OP_W, SPFAS_OP_QSIGMA, SPFAS_OP_MCOUNT = range(8)
 
 EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solve", "spfas_cascadic_solve",
             "spfas_picard_solve", "spfas_newton_solve", "spfas_eval_residual", "spfas_eval_residual_noalloc",
@@ -51,7 +51,7 @@ class spfas_mesh(C.Structure):
 class spfas_coarsen_opts(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("box", C.c_int32 * 3), ("m", C.c_int32), ("host_only", C.c_int32),
                 ("agg_kind", C.c_int32), ("user_agg", _ip), ("user_agg_len", C.c_int64),
-                ("greedy_size", C.c_int32)]
+                ("greedy_size", C.c_int32), ("eig_threshold", C.c_double), ("m_min", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)

@@ -80,6 +80,7 @@ struct TransferDev {
   DVec<int> fgrp_ptr, fgrp_list, grp_pos_A, grp_pos_B, smap_ptr, smap;
   DVec<int> Pptr, Eptr;
   DVec<double> P, E, trace, omega, eig;
+  DVec<double> lmax;              // counting pass of the threshold rule: largest eigenvalue per aggregate
   // prolongation helpers
   DVec<int> pd_agg, pd_row;       // per entry of pd_list
   DVec<int> int_agg, int_row;     // per interior entry (int parts of dof_list, concatenated)

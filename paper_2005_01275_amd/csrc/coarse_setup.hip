@@ -203,7 +203,8 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
                                                       const double* __restrict__ trace, double* __restrict__ omega,
                                                       const int* __restrict__ Pptr, double* __restrict__ P,
                                                       const int* __restrict__ Eptr, double* __restrict__ E,
-                                                      double* __restrict__ eig, CoarseOut co,
+                                                      double* __restrict__ eig, double* __restrict__ lmax,
+                                                      CoarseOut co,
                                                       double* __restrict__ scratch, ScratchB sb, int* __restrict__ bad,
                                                       unsigned long long* __restrict__ phase_ns) {
   __shared__ int flag;
@@ -362,6 +363,59 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       }
     }
     wg_sync();
+    if (lmax) {
+      // counting pass of the eigenvalue-threshold rule: the mA smallest
+      // eigenvalues are in eig; the largest is the top of the Jacobi
+      // spectrum, or the limit of a power iteration on L (stopped when
+      // ||L y - rho y|| <= 1e-9 rho ||y||: the Rayleigh quotient rho is then
+      // within about 1e-18 rho^2 / gap of an eigenvalue, the largest for a
+      // start with a component along its eigenvector)
+      if (!sub) {
+        if (threadIdx.x == 0) {
+          double mx = L[0];
+          for (int i = 1; i < npA; ++i) mx = fmax(mx, L[i * npA + i]);
+          scal[5] = mx;
+        }
+      } else {
+        for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = ((r & 1) ? -1.0 : 1.0) * (1.0 + 0.25 * (r % 3));
+        wg_sync();
+        for (int it = 0; it < 5000; ++it) {
+          double a = 0.0, b = 0.0;
+          for (int r = threadIdx.x; r < npA; r += blockDim.x) {
+            double acc = 0.0;
+            for (int c = 0; c < npA; ++c) acc = fma(L[r * npA + c], y0[c], acc);
+            y1[r] = acc;
+            a = fma(y0[r], acc, a);
+            b = fma(y0[r], y0[r], b);
+          }
+          a = block_sum(a, red);
+          b = block_sum(b, red);
+          if (threadIdx.x == 0) scal[5] = a / b;
+          wg_sync();
+          const double rho = scal[5];
+          double e = 0.0, c2 = 0.0;
+          for (int r = threadIdx.x; r < npA; r += blockDim.x) {
+            const double d = y1[r] - rho * y0[r];
+            e = fma(d, d, e);
+            c2 = fma(y1[r], y1[r], c2);
+          }
+          e = block_sum(e, red);
+          c2 = block_sum(c2, red);
+          if (threadIdx.x == 0) {
+            scal[6] = (e <= 1e-18 * rho * rho * b || it == 4999 || c2 == 0.0) ? 1.0 : 0.0;
+            scal[7] = sqrt(c2);
+          }
+          wg_sync();
+          if (scal[6] != 0.0) break;
+          const double inv = 1.0 / scal[7];
+          for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = y1[r] * inv;
+          wg_sync();
+        }
+      }
+      if (threadIdx.x == 0) lmax[A] = scal[5];
+      wg_sync();
+      continue;
+    }
     const int i0 = idx_small[0];
     // eigenvector j >= 1 of the ascending order, entry r
     auto evec = [&](int r, int j) -> double { return sub ? EX[r * nbs + (j - 1)] : V[r * npA + idx_small[j]]; };
@@ -597,7 +651,12 @@ void setup_coarse_levels(Hierarchy& h) {
   DVec<double> ones0;
   ones0.alloc(n0);
   launch_fill(n0, 1.0, ones0.p, s);
+  // eigenvalue-threshold count: each level first runs the aggregate kernel
+  // in its counting mode on the provisional coarse topology, then (when the
+  // counts differ) rebuilds the coarser topologies and runs again
+  std::vector<char> counted(L, 0);
   for (int l = 0; l + 1 < L; ++l) {
+    const bool counting = h.copts.eig_threshold > 0.0 && !counted[l];
     const Topo& tf = h.topo[l];
     const Topo& tc = h.topo[l + 1];
     std::vector<int64_t> dev_cell, dev_p, dev_flux, dcfptr, dcfidx;
@@ -748,7 +807,7 @@ void setup_coarse_levels(Hierarchy& h) {
     // ---- phase A: PV traces
     int n_faces_c = 0;
     while (n_faces_c < C.nf && C.h_kind[n_faces_c] != FK_BUBBLE) ++n_faces_c;
-    if (n_faces_c > 0) {
+    if (n_faces_c > 0 && !counting) {
       size_t mx_ns = 0, mx_npU = 0;
       for (int J = 0; J < n_faces_c; ++J) {
         const int A = C.h_c1[J], B = C.h_c2[J];
@@ -802,9 +861,10 @@ void setup_coarse_levels(Hierarchy& h) {
       co.lfptr = C.lfptr.p; co.lfidx = C.lfidx.p; co.c1 = C.c1.p; co.pptr = C.pptr.p; co.mptr = C.mptr.p;
       co.dptr = C.dptr.p; co.M = C.M.p; co.D = C.D.p; co.w = C.w.p; co.ones = C.ones.p; co.u = C.u.p;
       co.vol = C.vol.p;
+      if (counting) T.lmax.alloc(T.n_agg);
       hipLaunchKernelGGL(k_agg_setup, dim3((unsigned)slots), dim3(kBlock), 0, s, lv, pv, T.n_agg, ones_l, u_l, vol_l,
-                         T.trace.p, T.omega.p, T.Pptr.p, T.P.p, T.Eptr.p, T.E.p, T.eig.p, co, scr.p, sb, bad.p,
-                         tr_on ? phase_ns.p : nullptr);
+                         T.trace.p, T.omega.p, T.Pptr.p, T.P.p, T.Eptr.p, T.E.p, T.eig.p,
+                         counting ? T.lmax.p : nullptr, co, scr.p, sb, bad.p, tr_on ? phase_ns.p : nullptr);
       LAUNCHCHECK();
       HIPCHECK(hipStreamSynchronize(s));
       if (tr_on) {
@@ -826,6 +886,32 @@ void setup_coarse_levels(Hierarchy& h) {
                     "local problem of the hierarchy setup is not positive definite (level %d, site %d, item %d, "
                     "pivot %d, %d failures)", l, hb[1], hb[2], hb[3], hb[0]);
       fail(SPFAS_ERR_INVALID, buf);
+    }
+    if (counting) {
+      // m_A = #{lambda <= eig_threshold lambda_max}, clamped to [m_min, m]
+      // and to the aggregate's unknowns (the provisional count computed
+      // min(m, unknowns) eigenvalues, enough for the upper clamp)
+      const std::vector<double> all = T.eig.download(s), lm = T.lmax.download(s);
+      const std::vector<int64_t> npA = aggregate_unknowns(tf);
+      std::vector<int64_t> mA(T.n_agg);
+      bool same = true;
+      for (int A = 0; A < T.n_agg; ++A) {
+        int cnt = 0;
+        for (int j = 0; j < plan.mA[A]; ++j) cnt += all[plan.pd_ptr[A] + j] <= h.copts.eig_threshold * lm[A];
+        mA[A] = std::min<int64_t>(std::min(std::max(cnt, h.copts.m_min), h.copts.m), npA[A]);
+        same = same && mA[A] == plan.mA[A];
+      }
+      if (tr_on) {
+        std::vector<int> hist(h.copts.m + 1, 0);
+        for (int A = 0; A < T.n_agg; ++A) ++hist[mA[A]];
+        std::fprintf(stderr, "[spfas] setup level %d->%d eigenvector counts:", l, l + 1);
+        for (int k = 1; k <= h.copts.m; ++k) std::fprintf(stderr, " %d:%d", k, hist[k]);
+        std::fprintf(stderr, "\n");
+      }
+      counted[l] = 1;
+      if (!same) h.rebuild_coarse_topology(l, mA);
+      --l;   // this level again, on the final coarse topology
+      continue;
     }
     {   // the mA smallest eigenvalues of every aggregate, ascending
       const std::vector<double> all = T.eig.download(s);

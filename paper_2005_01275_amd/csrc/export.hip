@@ -51,6 +51,11 @@ void export_level_operator(const Hierarchy& h, int l, int what, double* out, siz
       std::copy(D.begin(), D.end(), out);
       break;
     }
+    case SPFAS_OP_MCOUNT: {
+      need((size_t)C.n);
+      for (int A = 0; A < C.n; ++A) out[A] = (double)(C.h_pptr[A + 1] - C.h_pptr[A]);
+      break;
+    }
     case SPFAS_OP_W: {
       std::vector<double> w = C.w.download(s);
       need(w.size());

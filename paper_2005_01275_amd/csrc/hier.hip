@@ -131,20 +131,20 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   }
   stamp("lattice");
   // ---------------- coarse topologies, aggregation, renumbering
-  int64_t user_off = 0;
+  copts = o;
+  if (o.eig_threshold > 0.0) {
+    require(std::isfinite(o.eig_threshold), "eig_threshold must be finite");
+    require(o.m_min >= 1 && o.m_min <= o.m, "m_min must be in [1, m]");
+    require(!host_only, "eig_threshold needs the device setup (not host_only)");
+  }
+  // with the threshold count the coarse topologies built here are
+  // provisional (min(m, unknowns) per aggregate); setup_coarse_levels
+  // replaces each before its numerics
+  user_off.assign(n_levels, 0);
   for (int l = 0; l + 1 < n_levels; ++l) {
-    if (o.agg_kind == SPFAS_AGG_USER) {
-      require(user_off + topo[l].n_cells <= o.user_agg_len, "user_agg is shorter than the cells of a coarsened level");
-      user_aggregate(topo[l], o.user_agg + user_off, topo[l].n_cells);
-      user_off += topo[l].n_cells;
-    } else if (o.agg_kind == SPFAS_AGG_GREEDY) {
-      greedy_aggregate(topo[l], o.greedy_size);
-    } else {
-      box_aggregate(topo[l], o.box);
-    }
-    stamp("aggregation");
-    renumber(topo[l]);
-    stamp("renumbering");
+    if (l > 0) user_off[l] = user_off[l - 1] + topo[l - 1].n_cells;
+    aggregate_level(l);
+    stamp("aggregation, renumbering");
     Topo c = coarse_topology(topo[l], m);
     topo.push_back(std::move(c));
     stamp("coarse topology");
@@ -290,6 +290,27 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   setup_coarse_levels(*this);
   if (tr_on) std::fprintf(stderr, "[spfas] setup: coarse levels %.1f ms\n", now_ms() - tp);
   HIPCHECK(hipStreamSynchronize(s));
+}
+
+void Hierarchy::aggregate_level(int l) {
+  const spfas_coarsen_opts& o = copts;
+  if (o.agg_kind == SPFAS_AGG_USER) {
+    require(user_off[l] + topo[l].n_cells <= o.user_agg_len, "user_agg is shorter than the cells of a coarsened level");
+    user_aggregate(topo[l], o.user_agg + user_off[l], topo[l].n_cells);
+  } else if (o.agg_kind == SPFAS_AGG_GREEDY) {
+    greedy_aggregate(topo[l], o.greedy_size);
+  } else {
+    box_aggregate(topo[l], o.box);
+  }
+  renumber(topo[l]);
+}
+
+void Hierarchy::rebuild_coarse_topology(int l, const std::vector<int64_t>& mA) {
+  topo[l + 1] = coarse_topology(topo[l], mA);
+  if (l + 2 < n_levels) {
+    aggregate_level(l + 1);
+    topo[l + 2] = coarse_topology(topo[l + 1], m);
+  }
 }
 
 void Hierarchy::set_problem(const spfas_problem& P) {

@@ -84,8 +84,19 @@ struct Hierarchy {
   int launches = 0;
   KernelProf prof;                         // event timing of instrumented kernels
 
+  // coarsening options of the setup (the threshold count rebuilds coarse
+  // topologies level by level during setup_coarse_levels)
+  spfas_coarsen_opts copts{};
+  std::vector<int64_t> user_off;          // USER: offset of level l's ids in user_agg
+
   ~Hierarchy();
   void setup(const spfas_mesh& mesh, const spfas_coarsen_opts& o);
+  // aggregates and renumbers topo[l] by the coarsening options
+  void aggregate_level(int l);
+  // replaces topo[l+1] by the coarse topology of topo[l] with mA[A]
+  // eigenvectors per aggregate, aggregates and renumbers it when a coarser
+  // level follows, and rebuilds topo[l+2] with the uniform provisional count
+  void rebuild_coarse_topology(int l, const std::vector<int64_t>& mA);
   // stream of the current call, also handed to the allocator callbacks
   void use_stream(hipStream_t s) { stream = s; mem.stream = s; }
   void set_problem(const spfas_problem& prob);

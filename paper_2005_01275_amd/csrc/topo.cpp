@@ -261,17 +261,29 @@ void build_cell_lists(Topo& t) {
   }
 }
 
+std::vector<int64_t> aggregate_unknowns(const Topo& f) {
+  std::vector<int64_t> npA(f.n_agg, 0);
+  for (int64_t i = 0; i < f.n_cells; ++i) npA[f.agg[i]] += f.pptr[i + 1] - f.pptr[i];
+  for (int64_t A = 0; A < f.n_agg; ++A)
+    if (npA[A] == 0) fail(SPFAS_ERR_INVALID, "empty aggregate");
+  return npA;
+}
+
 Topo coarse_topology(const Topo& f, int m) {
+  std::vector<int64_t> mA = aggregate_unknowns(f);
+  for (auto& v : mA) v = std::min<int64_t>(m, v);
+  return coarse_topology(f, mA);
+}
+
+Topo coarse_topology(const Topo& f, const std::vector<int64_t>& mA) {
   Topo c;
   const int64_t na = f.n_agg;
   c.n_cells = na;
-  std::vector<int64_t> npA(na, 0);
-  for (int64_t i = 0; i < f.n_cells; ++i) npA[f.agg[i]] += f.pptr[i + 1] - f.pptr[i];
+  const std::vector<int64_t> npA = aggregate_unknowns(f);
+  require((int64_t)mA.size() == na, "one eigenvector count per aggregate");
   c.pptr.assign(na + 1, 0);
-  std::vector<int64_t> mA(na);
   for (int64_t A = 0; A < na; ++A) {
-    if (npA[A] == 0) fail(SPFAS_ERR_INVALID, "empty aggregate");
-    mA[A] = std::min<int64_t>(m, npA[A]);
+    require(mA[A] >= 1 && mA[A] <= npA[A], "eigenvector count out of range");
     c.pptr[A + 1] = c.pptr[A] + mA[A];
   }
   std::vector<std::pair<int64_t, int64_t>> pairs;

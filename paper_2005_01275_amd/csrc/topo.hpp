@@ -46,7 +46,10 @@ void greedy_aggregate(Topo& t, int target);
 void renumber(Topo& t);
 void build_cell_lists(Topo& t);  // cfptr/cfidx from c1/c2
 // Coarse topology from an aggregated level; m = eigenvectors per aggregate.
-Topo coarse_topology(const Topo& fine, int m);
+Topo coarse_topology(const Topo& fine, int m);   // min(m, unknowns of A) eigenvectors per aggregate A
+Topo coarse_topology(const Topo& fine, const std::vector<int64_t>& mA);   // mA[A] per aggregate
+// pressure unknowns of each aggregate of an aggregated level
+std::vector<int64_t> aggregate_unknowns(const Topo& fine);
 
 // Per-transfer index plan, level l (device numbering `dev_cell`/`dev_p`/
 // `dev_flux` = canonical id -> device index) to level l+1 (canonical).
