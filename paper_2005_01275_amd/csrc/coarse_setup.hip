@@ -178,9 +178,10 @@ struct ScratchB {
   size_t total;
 };
 
-// Local problems with more pressure unknowns than this use block inverse
-// iteration for their smallest eigenpairs (falling back to the full Jacobi
-// decomposition if it does not converge); smaller ones use Jacobi.
+// Local problems with more pressure unknowns than this take the tridiagonal
+// route for their smallest eigenpairs (falling back to the full Jacobi
+// decomposition if the shifted Cholesky factorisation fails); smaller ones
+// use Jacobi.
 constexpr int kSmallEig = 32;
 
 struct CoarseOut {
@@ -228,6 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
   double* EG = ELX + 2 * kBlock * kSubMax;
   double* EW = EG + kSubMax * kSubMax;
   double* Eth = EW + kSubMax * kSubMax;
+  double* TRI = Eth + kSubMax + 8;   // tridiagonal route: diagonal, subdiagonal, reflector scales
   // optional phase timing (diagnostics): wall-clock ticks (10 ns) per phase, summed by thread 0
   unsigned long long tick = wall_clock64();
   auto phase = [&](int id) {
@@ -317,35 +319,88 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
     wg_sync();
     for (int r = threadIdx.x; r < npA; r += blockDim.x) q[r] = ones[pdA[r]] / scal[0];
     wg_sync();
-    // 4-5. the mA smallest eigenpairs of L_A: lambda_1 = 0 with eigenvector q,
-    // then block inverse iteration on L_A + rho q q^T (Cholesky factor in V);
-    // small or non-converging problems take the full Jacobi decomposition.
+    // 4-5. the mA smallest eigenpairs of L_A.  Larger problems: Householder
+    // reduction to tridiagonal form (L is overwritten), bisection on Sturm
+    // counts for the eigenvalues (and the largest one), inverse iteration on
+    // the tridiagonal for the eigenvectors 2..mA (the first is the null
+    // vector q), back-transformation by the reflectors; the pseudo-inverse of
+    // L_A is applied through the Cholesky factor of L_A + rho q q^T (in V).
+    // Small problems, or a factorisation that fails, take the full Jacobi
+    // decomposition.
     const int nev = mA - 1;
     const int nbs = min(npA - 1, min(kSubMax, nev + 6));
     bool sub = false;
-    if (npA > kSmallEig && nev >= 1) {
+    double* lam = eig + pl.pd_ptr[A];
+    if (npA > kSmallEig && nev >= 1 && nev <= kSubMax) {
       const double rho = scal[4];
       for (int e = threadIdx.x; e < npA * npA; e += blockDim.x) V[e] = L[e] + rho * q[e / npA] * q[e % npA];
       wg_sync();
-      if (wg_chol(V, npA, npA, &flag))
-        // residual tolerance a few times the rounding level of an npA-row
-        // product: the eigenvector error is about residual / gap, and the
-        // gaps below lambda_m can be 1e-3 rho and smaller on irregular
-        // aggregates
-        sub = wg_subspace_eig(L, V, q, npA, nbs, nev, rho, fmax(1e-14, 4.4e-16 * npA), 300, EX, EY, ELX, EG, EW, Eth,
-                              cs, prs, red, &flag);
-    }
-    double* lam = eig + pl.pd_ptr[A];
-    if (sub) {
-      if (threadIdx.x == 0) {
-        double qlq = 0.0;
-        for (int r = 0; r < npA; ++r)
-          for (int c = 0; c < npA; ++c) qlq += q[r] * L[r * npA + c] * q[c];
-        lam[0] = qlq;
-        for (int j = 1; j < mA; ++j) lam[j] = Eth[j - 1];
-        for (int j = 0; j < mA && j < 64; ++j) idx_small[j] = j;
+      if (wg_chol(V, npA, npA, &flag)) {
+        double* td = TRI;
+        double* te = TRI + npA;
+        double* tt = TRI + 2 * npA;
+        wg_tridiag(L, npA, td, te, tt, y0, y1, red);
+        if (threadIdx.x == 0) {   // Gershgorin interval of the tridiagonal
+          double lo = td[0], hi = td[0];
+          for (int i = 0; i < npA; ++i) {
+            const double r = (i > 0 ? fabs(te[i - 1]) : 0.0) + (i + 1 < npA ? fabs(te[i]) : 0.0);
+            lo = fmin(lo, td[i] - r);
+            hi = fmax(hi, td[i] + r);
+          }
+          EG[0] = lo;
+          EG[1] = hi;
+          EG[2] = 1e-16 * (fabs(lo) + fabs(hi)) + 1e-300;
+        }
+        wg_sync();
+        const double glo = EG[0], ghi = EG[1], tiny = EG[2];
+        // eigenvalues 0..nev, one thread each; the largest by the last thread
+        for (int j = threadIdx.x; j <= nev; j += blockDim.x) {
+          const double v = tri_bisect(td, te, npA, j, glo, ghi, tiny);
+          if (j == 0) lam[0] = v;
+          else Eth[j - 1] = v;
+        }
+        if (threadIdx.x == blockDim.x - 1) scal[5] = tri_bisect(td, te, npA, npA - 1, glo, ghi, tiny);
+        wg_sync();
+        // eigenvectors of the tridiagonal, as many at a time as the scratch
+        // (6 npA doubles each) holds
+        const int grp = max(1, (int)((4 * kBlock * kSubMax) / (6 * npA)));
+        for (int c0 = 0; c0 < nev; c0 += grp) {
+          const int c = c0 + (int)threadIdx.x;
+          if ((int)threadIdx.x < grp && c < nev) {
+            double* y = EY + (size_t)threadIdx.x * 6 * npA;
+            tri_invit(td, te, npA, Eth[c], 2.2e-16 * (fabs(glo) + fabs(ghi)), y, y + npA);
+            for (int r = 0; r < npA; ++r) EX[r * nbs + c] = y[r];
+          }
+          wg_sync();
+        }
+        // close eigenvalues: Gram-Schmidt within the cluster (ascending order)
+        if (threadIdx.x == 0) {
+          const double ctol = 1e-3 * (fabs(glo) + fabs(ghi));
+          for (int c = 1; c < nev; ++c) {
+            bool any = false;
+            for (int b = 0; b < c; ++b) {
+              if (!(fabs(Eth[c] - Eth[b]) < ctol)) continue;
+              any = true;
+              double dd = 0.0;
+              for (int r = 0; r < npA; ++r) dd += EX[r * nbs + b] * EX[r * nbs + c];
+              for (int r = 0; r < npA; ++r) EX[r * nbs + c] -= dd * EX[r * nbs + b];
+            }
+            if (any) {
+              double nn = 0.0;
+              for (int r = 0; r < npA; ++r) nn += EX[r * nbs + c] * EX[r * nbs + c];
+              const double inv = 1.0 / sqrt(nn);
+              for (int r = 0; r < npA; ++r) EX[r * nbs + c] *= inv;
+            }
+          }
+          for (int j = 1; j < mA; ++j) lam[j] = Eth[j - 1];
+          for (int j = 0; j < mA && j < 64; ++j) idx_small[j] = j;
+        }
+        wg_sync();
+        wg_tridiag_backtransform(L, npA, tt, EX, nev, nbs);
+        sub = true;
       }
-    } else {
+    }
+    if (!sub) {
       wg_jacobi_eig(L, npA, V, npA, npA, cs, prs, red);
       // order the spectrum (thread 0; small sizes)
       if (threadIdx.x == 0) {
@@ -366,52 +421,13 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
     if (lmax) {
       // counting pass of the eigenvalue-threshold rule: the mA smallest
       // eigenvalues are in eig; the largest is the top of the Jacobi
-      // spectrum, or the limit of a power iteration on L (stopped when
-      // ||L y - rho y|| <= 1e-9 rho ||y||: the Rayleigh quotient rho is then
-      // within about 1e-18 rho^2 / gap of an eigenvalue, the largest for a
-      // start with a component along its eigenvector)
-      if (!sub) {
-        if (threadIdx.x == 0) {
-          double mx = L[0];
-          for (int i = 1; i < npA; ++i) mx = fmax(mx, L[i * npA + i]);
-          scal[5] = mx;
-        }
-      } else {
-        for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = ((r & 1) ? -1.0 : 1.0) * (1.0 + 0.25 * (r % 3));
-        wg_sync();
-        for (int it = 0; it < 5000; ++it) {
-          double a = 0.0, b = 0.0;
-          for (int r = threadIdx.x; r < npA; r += blockDim.x) {
-            double acc = 0.0;
-            for (int c = 0; c < npA; ++c) acc = fma(L[r * npA + c], y0[c], acc);
-            y1[r] = acc;
-            a = fma(y0[r], acc, a);
-            b = fma(y0[r], y0[r], b);
-          }
-          a = block_sum(a, red);
-          b = block_sum(b, red);
-          if (threadIdx.x == 0) scal[5] = a / b;
-          wg_sync();
-          const double rho = scal[5];
-          double e = 0.0, c2 = 0.0;
-          for (int r = threadIdx.x; r < npA; r += blockDim.x) {
-            const double d = y1[r] - rho * y0[r];
-            e = fma(d, d, e);
-            c2 = fma(y1[r], y1[r], c2);
-          }
-          e = block_sum(e, red);
-          c2 = block_sum(c2, red);
-          if (threadIdx.x == 0) {
-            scal[6] = (e <= 1e-18 * rho * rho * b || it == 4999 || c2 == 0.0) ? 1.0 : 0.0;
-            scal[7] = sqrt(c2);
-          }
-          wg_sync();
-          if (scal[6] != 0.0) break;
-          const double inv = 1.0 / scal[7];
-          for (int r = threadIdx.x; r < npA; r += blockDim.x) y0[r] = y1[r] * inv;
-          wg_sync();
-        }
+      // spectrum, or the bisection's (tridiagonal route, already in scal[5])
+      if (!sub && threadIdx.x == 0) {
+        double mx = L[0];
+        for (int i = 1; i < npA; ++i) mx = fmax(mx, L[i * npA + i]);
+        scal[5] = mx;
       }
+      wg_sync();
       if (threadIdx.x == 0) lmax[A] = scal[5];
       wg_sync();
       continue;
@@ -847,7 +863,7 @@ void setup_coarse_levels(Hierarchy& h) {
       sb.pl = mx_nd * mx_k;
       sb.tmp = std::max(mx_nd, mx_np + 8) * std::max<size_t>(mx_k, 1) + 8;
       sb.vec = 3 * mx_np + std::max(mx_nd, mx_np) + 8;
-      sb.ev = 3 * (size_t)(2 * kBlock) * kSubMax + 2 * kSubMax * kSubMax + kSubMax + 8;
+      sb.ev = 3 * (size_t)(2 * kBlock) * kSubMax + 2 * kSubMax * kSubMax + kSubMax + 8 + 3 * mx_np + 8;
       sb.total = sb.ma + sb.da + sb.ci + sb.t + sb.l + sb.v + sb.pl + sb.tmp + sb.vec + sb.ev + 8;
       const size_t slots = slots_for(sb.total, T.n_agg);
       DVec<double> scr;

@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "kern.hpp"
+
 namespace spfas {
 
 __device__ inline void wg_sync() { __syncthreads(); }
@@ -272,113 +274,195 @@ __device__ inline void wg_jacobi_eig(double* A, int lda, double* V, int ldv, int
 
 // ------------------------------------------------------------------ smallest eigenpairs
 
-constexpr int kSubMax = 16;   // largest block of the subspace iteration
+constexpr int kSubMax = 16;   // most eigenvectors per aggregate taken by the tridiagonal route
 
-// Y (n x nb, ld nb) <- Y - q (q^T Y) for a unit vector q.
-__device__ inline void wg_project_out(const double* q, double* Y, int n, int nb) {
-  __shared__ double dots[kSubMax];
-  for (int c = threadIdx.x; c < nb; c += blockDim.x) {
+}  // namespace spfas
+
+// ------------------------------------------------------------------ tridiagonal route
+
+namespace spfas {
+
+// Householder reduction of the symmetric A (n x n, row-major, full storage,
+// overwritten) to the tridiagonal T = Q^T A Q with Q = H_0 H_1 ... H_{n-3},
+// H_k = I - tau_k v_k v_k^T acting on entries k+1 .. n-1, v_k[k+1] = 1 and
+// v_k[i] = A[i][k] for i > k+1 on return.  d[0..n) and e[0..n-1) receive
+// T's diagonal and subdiagonal, tau[0..n-2) the reflector scales.  vb, pb:
+// n doubles of scratch each; red: blockDim doubles of shared memory.
+__device__ inline void wg_tridiag(double* A, int n, double* d, double* e, double* tau, double* vb, double* pb,
+                                  double* red) {
+  __shared__ double sc[3];
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;                  // trailing block rows/cols k+1 .. n-1
+    double* a22 = A + (size_t)(k + 1) * n + (k + 1);
     double s = 0.0;
-    for (int i = 0; i < n; ++i) s += q[i] * Y[i * nb + c];
-    dots[c] = s;
-  }
-  wg_sync();
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) Y[e] -= q[e / nb] * dots[e % nb];
-  wg_sync();
-}
-
-// Orthonormal columns by Cholesky QR: G = Y^T Y = R^T R, Y <- Y R^{-1}.
-// Returns false when G is not numerically positive definite.
-__device__ inline bool wg_cholqr(double* Y, int n, int nb, double* G, int* flag) {
-  wg_gemm(Y, nb, true, Y, nb, false, G, nb, nb, nb, n);
-  if (threadIdx.x == 0) *flag = 0;
-  wg_sync();
-  if (!wg_chol_unblocked(G, nb, nb, flag, 0)) return false;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    double* row = Y + i * nb;
-    for (int j = 0; j < nb; ++j) {
-      double v = row[j];
-      for (int l = 0; l < j; ++l) v -= row[l] * G[j * nb + l];
-      row[j] = v / G[j * nb + j];
+    for (int i = 1 + threadIdx.x; i < m; i += blockDim.x) {
+      const double x = A[(size_t)(k + 1 + i) * n + k];
+      s += x * x;
     }
-  }
-  wg_sync();
-  return true;
-}
-
-// Smallest eigenpairs, other than the null vector, of a symmetric positive
-// semidefinite L (n x n, row-major) whose null space is spanned by the unit
-// vector q: block inverse iteration on Lreg = L + rho q q^T (C = its lower
-// Cholesky factor) with a Rayleigh-Ritz step every iteration; the nb
-// iterated vectors are kept orthogonal to q.  On success X (n x nb, ld nb)
-// holds the Ritz vectors and theta[0..nb) the Ritz values, ascending, and
-// the first nev pairs satisfy ||L x - theta x||_2 <= tol * rho.  Returns
-// false when that is not reached within maxit iterations (or the block
-// loses rank).  Scratch: Y, LX (n x nb), G, W (nb x nb); cs, pr, red as for
-// wg_jacobi_eig.
-__device__ inline bool wg_subspace_eig(const double* L, const double* C, const double* q, int n, int nb, int nev,
-                                       double rho, double tol, int maxit, double* X, double* Y, double* LX, double* G,
-                                       double* W, double* theta, double* cs, int* pr, double* red, int* flag) {
-  __shared__ int ord[kSubMax];
-  __shared__ int done;
-  // deterministic start: distinct low-discrepancy columns, then orthogonal to q
-  for (int e = threadIdx.x; e < n * nb; e += blockDim.x) {
-    const int i = e / nb, j = e % nb;
-    const double u = (double)((i + 1) * (2 * j + 3) % 97) / 97.0;
-    X[e] = u - 0.5 + 0.01 * (double)(j + 1) * (double)((i % (j + 2)) == 0);
-  }
-  wg_sync();
-  wg_project_out(q, X, n, nb);
-  if (!wg_cholqr(X, n, nb, G, flag)) return false;
-  for (int it = 0; it < maxit; ++it) {
-    for (int e = threadIdx.x; e < n * nb; e += blockDim.x) Y[e] = X[e];
-    wg_sync();
-    wg_chol_solve(C, n, n, Y, nb, nb);
-    wg_project_out(q, Y, n, nb);
-    if (!wg_cholqr(Y, n, nb, G, flag) || !wg_cholqr(Y, n, nb, G, flag)) return false;
-    // Rayleigh-Ritz: G = Y^T L Y, eigenvectors W
-    wg_gemm(L, n, false, Y, nb, false, LX, nb, n, nb, n);
-    wg_gemm(Y, nb, true, LX, nb, false, G, nb, nb, nb, n);
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-      const int i = e / nb, j = e % nb;
-      if (i < j) {
-        const double sy = 0.5 * (G[i * nb + j] + G[j * nb + i]);
-        G[i * nb + j] = sy;
-        G[j * nb + i] = sy;
-      }
-    }
-    wg_sync();
-    wg_jacobi_eig(G, nb, W, nb, nb, cs, pr, red);
+    s = block_sum(s, red);
     if (threadIdx.x == 0) {
-      for (int i = 0; i < nb; ++i) ord[i] = i;
-      for (int i = 1; i < nb; ++i) {
-        const int oi = ord[i];
-        int j = i - 1;
-        while (j >= 0 && G[ord[j] * nb + ord[j]] > G[oi * nb + oi]) { ord[j + 1] = ord[j]; --j; }
-        ord[j + 1] = oi;
+      const double x0 = A[(size_t)(k + 1) * n + k];
+      double beta = x0, t = 0.0, scale = 0.0;
+      if (s > 0.0) {
+        beta = -copysign(sqrt(x0 * x0 + s), x0);
+        t = (beta - x0) / beta;
+        scale = 1.0 / (x0 - beta);
       }
-      for (int i = 0; i < nb; ++i) theta[i] = G[ord[i] * nb + ord[i]];
+      e[k] = beta;
+      tau[k] = t;
+      sc[0] = t;
+      sc[1] = scale;
     }
     wg_sync();
-    // X = Y W, LX = (L Y) W with the columns of W in ascending order
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) G[e] = W[(e / nb) * nb + ord[e % nb]];
-    wg_sync();
-    wg_gemm(Y, nb, false, G, nb, false, X, nb, n, nb, nb);
-    wg_gemm(LX, nb, false, G, nb, false, Y, nb, n, nb, nb);   // Y <- L X
-    if (threadIdx.x == 0) done = 1;
-    wg_sync();
-    for (int c = threadIdx.x; c < nev; c += blockDim.x) {
-      double r2 = 0.0;
-      for (int i = 0; i < n; ++i) {
-        const double d = Y[i * nb + c] - theta[c] * X[i * nb + c];
-        r2 += d * d;
+    const double t = sc[0], scale = sc[1];
+    if (t == 0.0) continue;                    // already reduced in this column (uniform branch)
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      double v = 1.0;
+      if (i > 0) {
+        v = A[(size_t)(k + 1 + i) * n + k] * scale;
+        A[(size_t)(k + 1 + i) * n + k] = v;
       }
-      if (!(sqrt(r2) <= tol * rho)) done = 0;
+      vb[i] = v;
     }
     wg_sync();
-    if (done) return true;
+    // p = tau A22 v, K = tau/2 v^T p
+    double kv = 0.0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+      const double* row = a22 + (size_t)i * n;
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc = fma(row[j], vb[j], acc);
+      acc *= t;
+      pb[i] = acc;
+      kv = fma(vb[i], acc, kv);
+    }
+    kv = block_sum(kv, red);
+    if (threadIdx.x == 0) sc[2] = 0.5 * t * kv;
+    wg_sync();
+    const double K = sc[2];
+    // A22 -= v w^T + w v^T with w = p - K v
+    for (int q = threadIdx.x; q < m * m; q += blockDim.x) {
+      const int i = q / m, j = q % m;
+      const double wi = pb[i] - K * vb[i], wj = pb[j] - K * vb[j];
+      a22[(size_t)i * n + j] -= vb[i] * wj + wi * vb[j];
+    }
+    wg_sync();
   }
-  return false;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = A[(size_t)i * n + i];
+  if (threadIdx.x == 0 && n >= 2) e[n - 2] = A[(size_t)(n - 1) * n + (n - 2)];
+  wg_sync();
+}
+
+// Number of eigenvalues of the tridiagonal (d, e) below x (Sturm sequence of
+// the LDL^T pivots; a zero pivot is replaced by -tiny).
+__device__ inline int tri_count(const double* d, const double* e, int n, double x, double tiny) {
+  int c = 0;
+  double q = d[0] - x;
+  for (int i = 0;; ++i) {
+    if (q == 0.0) q = -tiny;
+    if (q < 0.0) ++c;
+    if (i + 1 == n) break;
+    q = d[i + 1] - x - e[i] * e[i] / q;
+  }
+  return c;
+}
+
+// The j-th smallest eigenvalue (0-based) of the tridiagonal (d, e) by
+// bisection on [lo, hi] (Gershgorin bounds) to the rounding level.
+__device__ inline double tri_bisect(const double* d, const double* e, int n, int j, double lo, double hi,
+                                    double tiny) {
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (hi - lo <= 4.4e-16 * fmax(fabs(lo), fabs(hi)) + tiny) break;
+    if (tri_count(d, e, n, mid, tiny) > j) hi = mid; else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+// Eigenvector of the tridiagonal (d, e) for the eigenvalue lam by inverse
+// iteration (three solves of (T - lam I) y = y with Gaussian elimination
+// and partial pivoting; zero pivots replaced by tiny), unit 2-norm.
+// w: 5n doubles of scratch (u0, u1, u2, l, pivot flags).
+__device__ inline void tri_invit(const double* d, const double* e, int n, double lam, double tiny, double* y,
+                                 double* w) {
+  double *u0 = w, *u1 = w + n, *u2 = w + 2 * n, *l = w + 3 * n, *pv = w + 4 * n;
+  for (int i = 0; i < n; ++i) {
+    u0[i] = d[i] - lam;
+    u1[i] = i + 1 < n ? e[i] : 0.0;
+    u2[i] = 0.0;
+  }
+  for (int i = 0; i + 1 < n; ++i) {
+    const double s = e[i], a0 = u0[i], a1 = u1[i], b0 = u0[i + 1], b1 = u1[i + 1];
+    if (fabs(a0) >= fabs(s)) {
+      const double li = a0 != 0.0 ? s / a0 : 0.0;
+      l[i] = li;
+      pv[i] = 0.0;
+      u0[i + 1] = b0 - li * a1;
+    } else {
+      const double li = a0 / s;
+      l[i] = li;
+      pv[i] = 1.0;
+      u0[i] = s;
+      u1[i] = b0;
+      u2[i] = b1;
+      u0[i + 1] = a1 - li * b0;
+      u1[i + 1] = -li * b1;
+    }
+    if (u0[i] == 0.0) u0[i] = tiny;
+  }
+  if (u0[n - 1] == 0.0) u0[n - 1] = tiny;
+  for (int i = 0; i < n; ++i) y[i] = 1.0 + 0.01 * (double)(i % 7);
+  for (int it = 0; it < 3; ++it) {
+    for (int i = 0; i + 1 < n; ++i) {
+      if (pv[i] != 0.0) { const double t = y[i]; y[i] = y[i + 1]; y[i + 1] = t; }
+      y[i + 1] -= l[i] * y[i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = y[i];
+      if (i + 1 < n) v -= u1[i] * y[i + 1];
+      if (i + 2 < n) v -= u2[i] * y[i + 2];
+      y[i] = v / u0[i];
+    }
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(y[i]));
+    const double inv = mx > 0.0 ? 1.0 / mx : 1.0;
+    for (int i = 0; i < n; ++i) y[i] *= inv;
+  }
+  double nn = 0.0;
+  for (int i = 0; i < n; ++i) nn += y[i] * y[i];
+  const double inv = 1.0 / sqrt(nn);
+  for (int i = 0; i < n; ++i) y[i] *= inv;
+}
+
+// Y (n x nc, ld ldy) <- Q Y with Q = H_0 ... H_{n-3} from wg_tridiag (the
+// reflectors applied last to first).  Column dot products are wave
+// reductions (fixed order).
+__device__ inline void wg_tridiag_backtransform(const double* A, int n, const double* tau, double* Y, int nc,
+                                                int ldy) {
+  __shared__ double dots[kSubMax];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int k = n - 3; k >= 0; --k) {
+    const double t = tau[k];
+    if (t == 0.0) continue;
+    const int m = n - k - 1;
+    for (int c = wv; c < nc; c += nw) {
+      double s = 0.0;
+      for (int i = lane; i < m; i += 64) {
+        const double v = i == 0 ? 1.0 : A[(size_t)(k + 1 + i) * n + k];
+        s = fma(v, Y[(size_t)(k + 1 + i) * ldy + c], s);
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+      if (lane == 0) dots[c] = t * s;
+    }
+    wg_sync();
+    for (int q = threadIdx.x; q < m * nc; q += blockDim.x) {
+      const int i = q / nc, c = q % nc;
+      const double v = i == 0 ? 1.0 : A[(size_t)(k + 1 + i) * n + k];
+      Y[(size_t)(k + 1 + i) * ldy + c] -= dots[c] * v;
+    }
+    wg_sync();
+  }
 }
 
 }  // namespace spfas
