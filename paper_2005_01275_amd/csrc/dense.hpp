@@ -23,24 +23,32 @@ constexpr int kGemmKc = 16;     // depth of one staged slice
 constexpr int kCholNb = 32;     // panel width of the blocked factorisation and solves
 
 // C (m x n) = alpha op(A) op(B) + beta C, op = transpose when the flag is set
-// (A is m x k or k x m, B is k x n or n x k).  64 x 64 output tiles, 4 x 4
-// per thread, depth-16 slices of A and B staged in LDS.  lower_only skips
-// the tiles strictly above the diagonal (updates whose upper part is never
-// read).  C is not read when beta == 0: it may hold any bit pattern.
+// (A is m x k or k x m, B is k x n or n x k).  64 x 64 output tiles; depth-16
+// slices of A and B staged in LDS; each of the 4 waves computes one 32 x 32
+// quadrant as 2 x 2 FP64 matrix-core products (v_mfma_f64_16x16x4f64, four
+// per slice and sub-tile).  Operand layout of that instruction: A[i][k] in
+// lane i + 16k, B[k][j] in lane j + 16k, D[i][j] in lane j + 16 (i mod 4),
+// accumulator register i / 4.  lower_only skips the tiles strictly above the
+// diagonal (updates whose upper part is never read).  C is not read when
+// beta == 0: it may hold any bit pattern.
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 __device__ inline void wg_gemm_acc(const double* A, int lda, bool ta, const double* B, int ldb, bool tb, double* C,
                                    int ldc, int m, int n, int k, double alpha, double beta, bool lower_only) {
   __shared__ double As[kGemmKc][kGemmTile + 1];
   __shared__ double Bs[kGemmKc][kGemmTile + 1];
   const int t = threadIdx.x;
-  const int tr = t >> 4, tc = t & 15;
+  const int lane = t & 63, wv = t >> 6;
+  const int wr = wv >> 1, wc = wv & 1;          // quadrant of this wave
+  const int li = lane & 15, lk = lane >> 4;     // row/column and depth index of the operands
   for (int i0 = 0; i0 < m; i0 += kGemmTile)
     for (int j0 = 0; j0 < n; j0 += kGemmTile) {
       if (lower_only && j0 > i0) continue;
-      double acc[4][4];
+      dbl4 acc[2][2];
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+        for (int b = 0; b < 2; ++b) acc[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
       for (int q0 = 0; q0 < k; q0 += kGemmKc) {
         for (int e = t; e < kGemmKc * kGemmTile; e += 256) {
           // contiguous memory runs along the fastest-varying index of the thread
@@ -54,30 +62,32 @@ __device__ inline void wg_gemm_acc(const double* A, int lda, bool ta, const doub
           Bs[q2][j] = (gj < n && gq2 < k) ? (tb ? B[(size_t)gj * ldb + gq2] : B[(size_t)gq2 * ldb + gj]) : 0.0;
         }
         __syncthreads();
-#pragma unroll 4
-        for (int q = 0; q < kGemmKc; ++q) {
-          double av[4], bv[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) av[r] = As[q][tr * 4 + r];
+        for (int ks = 0; ks < kGemmKc; ks += 4) {
+          double af[2], bf[2];
 #pragma unroll
-          for (int c = 0; c < 4; ++c) bv[c] = Bs[q][tc * 4 + c];
+          for (int a = 0; a < 2; ++a) af[a] = As[ks + lk][32 * wr + 16 * a + li];
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
+          for (int b = 0; b < 2; ++b) bf[b] = Bs[ks + lk][32 * wc + 16 * b + li];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) acc[r][c] += av[r] * bv[c];
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int gi = i0 + tr * 4 + r, gj = j0 + tc * 4 + c;
-          if (gi < m && gj < n) {
-            double* cp = C + (size_t)gi * ldc + gj;
-            *cp = (beta == 0.0) ? alpha * acc[r][c] : beta * *cp + alpha * acc[r][c];
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gi = i0 + 32 * wr + 16 * a + 4 * r + lk, gj = j0 + 32 * wc + 16 * b + li;
+            if (gi < m && gj < n) {
+              double* cp = C + (size_t)gi * ldc + gj;
+              *cp = (beta == 0.0) ? alpha * acc[a][b][r] : beta * *cp + alpha * acc[a][b][r];
+            }
           }
-        }
     }
   __syncthreads();
 }
@@ -145,17 +155,35 @@ __device__ inline bool wg_chol(double* A, int n, int ld, int* flag) {
 
 // B <- (L L^T)^{-1} B for B of n rows and nrhs columns (row-major, ldb):
 // forward then backward substitution in 32-row blocks, the off-diagonal
-// block updates on the tiled product.
+// block updates on the tiled product.  Diagonal blocks: with few right-hand
+// sides (nrhs <= kFewRhs) 32-lane groups solve one column each (8 at a time
+// per block of 256 threads: lane r holds row r, each solved entry is
+// broadcast by a shuffle, no barrier inside the block); with more, a thread
+// per column substitutes sequentially.
+constexpr int kFewRhs = 32;
+
 __device__ inline void wg_chol_solve(const double* L, int n, int ld, double* B, int nrhs, int ldb) {
+  const int r = threadIdx.x & 31, grp = threadIdx.x >> 5, ngrp = blockDim.x >> 5;
+  const bool few = nrhs <= kFewRhs;
   for (int k0 = 0; k0 < n; k0 += kCholNb) {
     const int kb = min(kCholNb, n - k0);
     const double* L11 = L + (size_t)k0 * ld + k0;
-    for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+    if (!few)
+      for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+        for (int j = 0; j < kb; ++j) {
+          double v = B[(size_t)(k0 + j) * ldb + c];
+          for (int l = 0; l < j; ++l) v -= L11[j * ld + l] * B[(size_t)(k0 + l) * ldb + c];
+          B[(size_t)(k0 + j) * ldb + c] = v / L11[j * ld + j];
+        }
+    for (int c = grp; few && c < nrhs; c += ngrp) {
+      double b = r < kb ? B[(size_t)(k0 + r) * ldb + c] : 0.0;
       for (int j = 0; j < kb; ++j) {
-        double v = B[(size_t)(k0 + j) * ldb + c];
-        for (int l = 0; l < j; ++l) v -= L11[j * ld + l] * B[(size_t)(k0 + l) * ldb + c];
-        B[(size_t)(k0 + j) * ldb + c] = v / L11[j * ld + j];
+        const double xj = __shfl(b, j, 32) / L11[j * ld + j];
+        if (r == j) b = xj;
+        else if (r > j && r < kb) b -= L11[r * ld + j] * xj;
       }
+      if (r < kb) B[(size_t)(k0 + r) * ldb + c] = b;
+    }
     wg_sync();
     const int rem = n - k0 - kb;
     if (rem > 0)
@@ -167,12 +195,22 @@ __device__ inline void wg_chol_solve(const double* L, int n, int ld, double* B, 
     const int k0 = bk * kCholNb;
     const int kb = min(kCholNb, n - k0);
     const double* L11 = L + (size_t)k0 * ld + k0;
-    for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+    if (!few)
+      for (int c = threadIdx.x; c < nrhs; c += blockDim.x)
+        for (int j = kb - 1; j >= 0; --j) {
+          double v = B[(size_t)(k0 + j) * ldb + c];
+          for (int l = j + 1; l < kb; ++l) v -= L11[l * ld + j] * B[(size_t)(k0 + l) * ldb + c];
+          B[(size_t)(k0 + j) * ldb + c] = v / L11[j * ld + j];
+        }
+    for (int c = grp; few && c < nrhs; c += ngrp) {
+      double b = r < kb ? B[(size_t)(k0 + r) * ldb + c] : 0.0;
       for (int j = kb - 1; j >= 0; --j) {
-        double v = B[(size_t)(k0 + j) * ldb + c];
-        for (int l = j + 1; l < kb; ++l) v -= L11[l * ld + j] * B[(size_t)(k0 + l) * ldb + c];
-        B[(size_t)(k0 + j) * ldb + c] = v / L11[j * ld + j];
+        const double xj = __shfl(b, j, 32) / L11[j * ld + j];
+        if (r == j) b = xj;
+        else if (r < j) b -= L11[j * ld + r] * xj;
       }
+      if (r < kb) B[(size_t)(k0 + r) * ldb + c] = b;
+    }
     wg_sync();
     if (k0 > 0)
       wg_gemm_acc(L + (size_t)k0 * ld, ld, true, B + (size_t)k0 * ldb, ldb, false, B, ldb, k0, nrhs, kb, -1.0, 1.0,
