@@ -71,12 +71,31 @@ void launch_halftrans(int64_t nf, int dim, const int* fc, const double* area, co
 // (mass-balance rows).  The row values come from the two routines below,
 // shared by the single-step and the multi-step kernels (multiply-adds as
 // explicit fma) so that a trial step gives the same bits in both.
+// 1/kappa at a cell value p and its derivative: with GK false the
+// exponential family without shift, exp(-alpha p) as written; otherwise
+// the general family of KappaFam at p - z_c.
+template <bool GK>
+__device__ inline double fine_kinv(const FineView& v, double p, int c) {
+  if constexpr (GK) return kap_inv(v.kf, kap_psi(v.z, p, c));
+  else return exp(-v.kf.alpha * p);
+}
+template <bool GK>
+__device__ inline double fine_dkinv(const FineView& v, double p, int c, double kinv) {
+  if constexpr (GK) return kap_dinv(v.kf, kap_psi(v.z, p, c), kinv);
+  else return -v.kf.alpha * kinv;
+}
+
+// kernels instantiated for the general kappa family when the problem is not
+// the exponential without shift
+inline bool general_kappa(const FineView& v) { return v.kf.kind != 0 || v.z != nullptr; }
+
+template <bool GK>
 __device__ inline double flux_row(const FineView& v, int64_t i, double pK, double pL, double sj) {
-  const int K = v.K[i], L = v.L[i];
-  double m = kap_inv(v.kf, kap_psi(v.z, pK, K)) * v.TKi[i];
+  const int L = v.L[i];
+  double m = fine_kinv<GK>(v, pK, GK ? v.K[i] : 0) * v.TKi[i];
   double dtp = -pK;
   if (L >= 0) {
-    m = fma(kap_inv(v.kf, kap_psi(v.z, pL, L)), v.TLi[i], m);
+    m = fma(fine_kinv<GK>(v, pL, L), v.TLi[i], m);
     dtp += pL;
   }
   return fma(m, sj, dtp) + v.g[i];
@@ -87,7 +106,7 @@ __device__ inline double stepped(double a, double s, double d) { return fma(s, d
 
 // Writes r if `r` is non-null and the per-block sum of squares to
 // parts[blockIdx.x].
-template <bool STEP>
+template <bool STEP, bool GK>
 __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double* __restrict__ x,
                                                        const double* __restrict__ dx, double s,
                                                        double* __restrict__ r, double* __restrict__ parts) {
@@ -108,7 +127,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid(FineView v, const double*
         if (L >= 0) pL = stepped(pL, s, dp[L]);
         sj = stepped(sj, s, dsig[i]);
       }
-      ri = flux_row(v, i, pK, pL, sj);
+      ri = flux_row<GK>(v, i, pK, pL, sj);
     } else {
       const int64_t c = i - nf;
       double div = 0.0;
@@ -134,7 +153,7 @@ struct TrialSteps {
   double s[kMaxTrials];
 };
 
-template <int NT>
+template <int NT, bool GK>
 __global__ void __launch_bounds__(kBlock) k_fine_resid_trials(FineView v, const double* __restrict__ x,
                                                               const double* __restrict__ dx, TrialSteps st,
                                                               double* __restrict__ parts) {
@@ -155,7 +174,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid_trials(FineView v, const 
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const double pL = L >= 0 ? stepped(pL0, st.s[t], dL) : 0.0;
-        const double ri = flux_row(v, i, stepped(pK0, st.s[t], dK), pL, stepped(sj0, st.s[t], ds));
+        const double ri = flux_row<GK>(v, i, stepped(pK0, st.s[t], dK), pL, stepped(sj0, st.s[t], ds));
         acc[t] = fma(ri, ri, acc[t]);
       }
     } else {
@@ -194,11 +213,20 @@ int launch_fine_resid_trials(const FineView& v, const double* x, const double* d
   const int G = reduce_grid(v.nf + v.n);
   TrialSteps ts{};
   for (int t = 0; t < nt; ++t) ts.s[t] = steps[t];
-  switch (nt) {
-    case 1: hipLaunchKernelGGL(k_fine_resid_trials<1>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
-    case 2: hipLaunchKernelGGL(k_fine_resid_trials<2>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
-    case 3: hipLaunchKernelGGL(k_fine_resid_trials<3>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
-    default: hipLaunchKernelGGL(k_fine_resid_trials<4>, dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+  if (general_kappa(v)) {
+    switch (nt) {
+      case 1: hipLaunchKernelGGL((k_fine_resid_trials<1, true>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+      case 2: hipLaunchKernelGGL((k_fine_resid_trials<2, true>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+      case 3: hipLaunchKernelGGL((k_fine_resid_trials<3, true>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+      default: hipLaunchKernelGGL((k_fine_resid_trials<4, true>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+    }
+  } else {
+    switch (nt) {
+      case 1: hipLaunchKernelGGL((k_fine_resid_trials<1, false>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+      case 2: hipLaunchKernelGGL((k_fine_resid_trials<2, false>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+      case 3: hipLaunchKernelGGL((k_fine_resid_trials<3, false>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+      default: hipLaunchKernelGGL((k_fine_resid_trials<4, false>), dim3(G), dim3(kBlock), 0, st, v, x, dx, ts, parts); break;
+    }
   }
   LAUNCHCHECK();
   return G;
@@ -207,10 +235,15 @@ int launch_fine_resid_trials(const FineView& v, const double* x, const double* d
 int launch_fine_resid(const FineView& v, const double* x, const double* dx, double s, double* r, double* parts,
                       hipStream_t st) {
   const int G = reduce_grid(v.nf + v.n);
-  if (dx)
-    hipLaunchKernelGGL(k_fine_resid<true>, dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
+  const bool gk = general_kappa(v);
+  if (dx && gk)
+    hipLaunchKernelGGL((k_fine_resid<true, true>), dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
+  else if (dx)
+    hipLaunchKernelGGL((k_fine_resid<true, false>), dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
+  else if (gk)
+    hipLaunchKernelGGL((k_fine_resid<false, true>), dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
   else
-    hipLaunchKernelGGL(k_fine_resid<false>, dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
+    hipLaunchKernelGGL((k_fine_resid<false, false>), dim3(G), dim3(kBlock), 0, st, v, x, dx, s, r, parts);
   LAUNCHCHECK();
   return G;
 }
@@ -237,7 +270,7 @@ constexpr int kLinG = 8;
 
 // TV: storage of the SELL values and of the right-hand side (FP64, or FP32
 // in mixed precision); everything is computed in FP64.
-template <bool NEWTON, bool SELL, class TV>
+template <bool NEWTON, bool SELL, class TV, bool GK>
 __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const double* __restrict__ x,
                                                            const int* __restrict__ sptr, double* __restrict__ diag,
                                                            double* __restrict__ off, TV* __restrict__ sval,
@@ -257,14 +290,12 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
     const int j = code >> 1;
     const int K = v.K[j], L = v.L[j];
     const double pK = p[K];
-    const double psK = kap_psi(v.z, pK, K);
-    const double iK = kap_inv(v.kf, psK);
+    const double iK = fine_kinv<GK>(v, pK, K);
     const double eK = iK * v.TKi[j];
-    double eL = 0.0, pL = 0.0, psL = 0.0, iL = 0.0;
+    double eL = 0.0, pL = 0.0, iL = 0.0;
     if (L >= 0) {
       pL = p[L];
-      psL = kap_psi(v.z, pL, L);
-      iL = kap_inv(v.kf, psL);
+      iL = fine_kinv<GK>(v, pL, L);
       eL = iL * v.TLi[j];
     }
     const double m = eK + eL;
@@ -272,8 +303,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
     const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[j];
     double EK = -1.0, EL = 1.0;
     if (NEWTON) {   // d r_sigma / d p_K = d(1/kappa_K)/dp Tbar_K^{-1} sigma - 1 (Prop. 3 on level 0)
-      EK += kap_dinv(v.kf, psK, iK) * v.TKi[j] * sj;
-      if (L >= 0) EL += kap_dinv(v.kf, psL, iL) * v.TLi[j] * sj;
+      EK += fine_dkinv<GK>(v, pK, K, iK) * v.TKi[j] * sj;
+      if (L >= 0) EL += fine_dkinv<GK>(v, pL, L, iL) * v.TLi[j] * sj;
     }
     const double ainv = 1.0 / m;
     const double uk = ainv * EK, ul = ainv * EL, vs = sj - ainv * rs;
@@ -302,25 +333,32 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
   }
 }
 
+template <class TV, bool GK>
+static void lin_cells_launch(const FineView& v, bool newton, const double* x, const int* sell_ptr, TV* sell_val,
+                             double* diag, double* off, TV* rhs, hipStream_t s) {
+  const dim3 g(grid_for((size_t)v.n * kLinG, kBlock)), b(kBlock);
+  if (sell_ptr) {
+    if (newton)
+      hipLaunchKernelGGL((k_fine_lin_cells<true, true, TV, GK>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr,
+                         sell_val, rhs);
+    else
+      hipLaunchKernelGGL((k_fine_lin_cells<false, true, TV, GK>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr,
+                         sell_val, rhs);
+  } else {
+    if (newton)
+      hipLaunchKernelGGL((k_fine_lin_cells<true, false, TV, GK>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
+    else
+      hipLaunchKernelGGL((k_fine_lin_cells<false, false, TV, GK>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
+  }
+  LAUNCHCHECK();
+}
+
 template <class TV>
 static void lin_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr, TV* sell_val,
                       double* diag, double* off, TV* rhs, hipStream_t s) {
   if (v.n == 0) return;
-  const dim3 g(grid_for((size_t)v.n * kLinG, kBlock)), b(kBlock);
-  if (sell_ptr) {
-    if (newton)
-      hipLaunchKernelGGL((k_fine_lin_cells<true, true, TV>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr, sell_val,
-                         rhs);
-    else
-      hipLaunchKernelGGL((k_fine_lin_cells<false, true, TV>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr, sell_val,
-                         rhs);
-  } else {
-    if (newton)
-      hipLaunchKernelGGL((k_fine_lin_cells<true, false, TV>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
-    else
-      hipLaunchKernelGGL((k_fine_lin_cells<false, false, TV>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
-  }
-  LAUNCHCHECK();
+  if (general_kappa(v)) lin_cells_launch<TV, true>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
+  else lin_cells_launch<TV, false>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
 }
 
 void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
@@ -345,7 +383,7 @@ void launch_widen(int64_t n, const float* a, double* b, hipStream_t s) {
 }
 
 // dsigma = -M^{-1} (r_sigma + E dp) on faces; per-block max |dp| on cells.
-template <bool NEWTON>
+template <bool NEWTON, bool GK>
 __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const double* __restrict__ x,
                                                          double* __restrict__ dx, double* __restrict__ parts) {
   __shared__ double sh[kBlock / 64];
@@ -358,14 +396,12 @@ __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const doubl
     if (i < nf) {
       const int K = v.K[i], L = v.L[i];
       const double pK = p[K];
-      const double psK = kap_psi(v.z, pK, K);
-      const double iK = kap_inv(v.kf, psK);
+      const double iK = fine_kinv<GK>(v, pK, K);
       const double eK = iK * v.TKi[i];
-      double eL = 0.0, pL = 0.0, dpL = 0.0, psL = 0.0, iL = 0.0;
+      double eL = 0.0, pL = 0.0, dpL = 0.0, iL = 0.0;
       if (L >= 0) {
         pL = p[L];
-        psL = kap_psi(v.z, pL, L);
-        iL = kap_inv(v.kf, psL);
+        iL = fine_kinv<GK>(v, pL, L);
         eL = iL * v.TLi[i];
         dpL = dp[L];
       }
@@ -374,8 +410,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const doubl
       const double rs = m * sj + (L >= 0 ? pL : 0.0) - pK + v.g[i];
       double EK = -1.0, EL = 1.0;
       if (NEWTON) {
-        EK += kap_dinv(v.kf, psK, iK) * v.TKi[i] * sj;
-        if (L >= 0) EL += kap_dinv(v.kf, psL, iL) * v.TLi[i] * sj;
+        EK += fine_dkinv<GK>(v, pK, K, iK) * v.TKi[i] * sj;
+        if (L >= 0) EL += fine_dkinv<GK>(v, pL, L, iL) * v.TLi[i] * sj;
       }
       dx[i] = -(rs + EK * dp[K] + (L >= 0 ? EL * dpL : 0.0)) / m;
     } else {
@@ -390,10 +426,15 @@ __global__ void __launch_bounds__(kBlock) k_fine_backsub(FineView v, const doubl
 int launch_fine_backsub(const FineView& v, bool newton, const double* x, double* dx, double* parts,
                         hipStream_t s) {
   const int G = reduce_grid(v.nf + v.n);
-  if (newton)
-    hipLaunchKernelGGL(k_fine_backsub<true>, dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
+  const bool gk = general_kappa(v);
+  if (newton && gk)
+    hipLaunchKernelGGL((k_fine_backsub<true, true>), dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
+  else if (newton)
+    hipLaunchKernelGGL((k_fine_backsub<true, false>), dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
+  else if (gk)
+    hipLaunchKernelGGL((k_fine_backsub<false, true>), dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
   else
-    hipLaunchKernelGGL(k_fine_backsub<false>, dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
+    hipLaunchKernelGGL((k_fine_backsub<false, false>), dim3(G), dim3(kBlock), 0, s, v, x, dx, parts);
   LAUNCHCHECK();
   return G;
 }
