@@ -13,7 +13,8 @@ Beside the headline the line carries: the same solves in mixed precision
 (FP32 level-0 linear solves inside the FP64 residual and update), the GPU
 single-level Newton/Picard and cascadic comparators (medians after a
 warm-up), seeds 1-4 of the workload recipe, the 32x32 workload (C1: us per
-V-cycle), a served stream (Poisson arrivals over several models through the
+V-cycle), the unstructured configuration (Voronoi mesh, greedy aggregates,
+eigenvector counts by threshold, mixed precision), a served stream (Poisson arrivals over several models through the
 native serving runtime, p50/p99 latency) and a batched setup-and-solve of
 independent problems with an autotuned number of solves in flight, and the
 CPU oracle on a bounded sample.
@@ -203,6 +204,67 @@ def c1_leg(torch, pk, c1_problem, steps=200):
             "solves_per_s": steps / t, "ms_per_solve_p50": percentile(ms, 0.5), "ms_per_solve_p99": percentile(ms, 0.99),
             "vcycles": st["iterations"], "us_per_vcycle": 1000.0 * percentile(ms, 0.5) / max(st["iterations"], 1),
             "krylov_iters": st["lin_iters"], "cell_updates_per_s": prob.mesh.n_cells * st["iterations"] * steps / t}
+
+
+def unstructured_leg(torch, pk, n_points=200000, seed=3, steps=3):
+    """The unstructured configuration at 1/10 of its 2,000,000 points (so the
+    bench stays within minutes): a bounded Voronoi mesh of seeded points,
+    ln k = 3G with correlation length 0.01, kappa = exp(2p), greedy
+    aggregates of about 64 cells on 2 levels (a third level would group 64
+    coarse cells of up to 6 unknowns each, beyond the 512 unknowns the local
+    dense solvers take), eigenvectors per aggregate by
+    the threshold 0.1 clamped to [2, 6], mixed-precision FAS-Newton to rtol
+    1e-8.  The source pair is scaled by a linear (alpha = 0) solve on the
+    GPU so that alpha max|p_lin| = 0.5.  The mixed-precision result is
+    compared with the FP64 solve on the same hierarchy, which the parity
+    tests tie to the oracle's root."""
+    import numpy as np
+    from problems.grids import voronoi_problem
+    from paper_2005_01275_amd import _native as N
+    log(f"unstructured: Voronoi mesh of {n_points} points")
+    t0 = time.perf_counter()
+    prob = voronoi_problem(n_points=n_points, seed=seed, sigma=3.0, corr_len=0.01, alpha=2.0, n_levels=2,
+                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2)
+    t_mesh = time.perf_counter() - t0
+    log("unstructured: hierarchy (greedy aggregates, threshold counts)")
+    t0 = time.perf_counter()
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, m=prob.m, agg_kind=N.SPFAS_AGG_GREEDY, greedy_size=prob.greedy_size,
+                     eig_threshold=prob.eig_threshold, m_min=prob.m_min)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    counts = []
+    for l in range(prob.n_levels - 1):
+        n_agg = H.level_sizes(l + 1)[0]
+        counts.append(np.bincount(H.level_operator(l, N.SPFAS_OP_MCOUNT, n_agg).astype(int), minlength=7)[1:].tolist())
+    lin = pk.SolveOpts(smoother=pk.SPFAS_PICARD, rtol=1e-10, atol=0.0, max_it=5, lin_rtol=1e-12, lin_max_it=2000)
+    p_lin, _, _ = H.fas_solve(dataclasses.replace(prob, alpha=0.0), lin)
+    rate = 0.5 / (prob.alpha * float(np.abs(p_lin).max()))
+    prob = dataclasses.replace(prob, source=prob.source * rate)
+    cprob, keep = H._problem(prob, device=True)
+    base = dict(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=1e-5, lin_max_it=400,
+                lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1, amg_reuse=-1, lin_max_it_coarse=10,
+                coarsest_atol=1e-10, dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
+    out = {"workload": f"voronoi_2d_{n_points} (1/10 of the 2,000,000-point configuration), ln k = 3G, "
+                       "kappa = exp(2p), greedy aggregates of 64, 2 levels, eigenvector counts by threshold 0.1 "
+                       "in [2, 6], FAS-Newton rtol 1e-8",
+           "cells": prob.mesh.n_cells, "mesh_s": t_mesh, "setup_s": t_setup, "eig_counts_per_level": counts}
+    res = {}
+    for name, prec in (("mixed", pk.SPFAS_PREC_MIXED), ("fp64", pk.SPFAS_PREC_FP64)):
+        o = pk.SolveOpts(precision=prec, **base)
+        log(f"unstructured: {name} solves")
+        try:
+            ms, st = timed_solves(torch, lambda: H.fas_solve(prob, o, device=True, cprob=cprob), steps)
+            p, s, _ = H.fas_solve(prob, o)
+            res[name] = p
+            out[name] = {"ms_per_solve_p50": percentile(ms, 0.5), "solves_per_s": 1000.0 / percentile(ms, 0.5),
+                         "vcycles": st["iterations"], "krylov_iters": st["lin_iters"], "converged": st["converged"]}
+        except pk.SpfasError as e:
+            out[name] = {"error": str(e)}
+    if "mixed" in res and "fp64" in res:
+        out["mixed_vs_fp64_max_rel_err"] = float(np.abs(res["mixed"] - res["fp64"]).max() /
+                                                 np.abs(res["fp64"]).max())
+    H.close()
+    return out
 
 
 def served_leg(pk, n_requests, seed=7, n_models=10, n_slots=6):
@@ -516,6 +578,11 @@ def main():
                         "all_converged": all(v.get("converged", False) for v in sd.values())}
         torch.cuda.empty_cache()
         out["c1"] = c1_leg(torch, pk, c1_problem)
+        torch.cuda.empty_cache()
+        try:
+            out["unstructured"] = unstructured_leg(torch, pk)
+        except pk.SpfasError as e:   # reported, not fatal
+            out["unstructured"] = {"error": str(e)}
         out["served"] = served_leg(pk, args.served_requests)
         out["batched"] = batched_leg(pk, args.batch_problems)
 

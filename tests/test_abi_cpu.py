@@ -129,6 +129,21 @@ def test_invalid_options_and_empty_mesh_rejected():
         pk.Hierarchy(empty, 1, (2, 2), 1, host_only=True)
 
 
+def test_threshold_count_options_rejected():
+    """The eigenvalue-threshold count needs the device setup and a lower
+    clamp in [1, m]; both are checked before any work (CPU)."""
+    import paper_2005_01275_amd as pk
+    prob = small_problem((8, 8), seed=0)
+    with pytest.raises(pk.SpfasError, match="host_only"):
+        pk.Hierarchy(prob.mesh, 2, (4, 4), 6, host_only=True, eig_threshold=0.1, m_min=2)
+    with pytest.raises(pk.SpfasError, match="m_min"):
+        pk.Hierarchy(prob.mesh, 2, (4, 4), 3, host_only=True, eig_threshold=0.1, m_min=4)
+    with pytest.raises(pk.SpfasError, match="m_min"):
+        pk.Hierarchy(prob.mesh, 2, (4, 4), 3, host_only=True, eig_threshold=0.1, m_min=0)
+    # threshold off: host_only works and m_min is not read
+    pk.Hierarchy(prob.mesh, 2, (4, 4), 3, host_only=True, eig_threshold=0.0, m_min=0).close()
+
+
 def test_levels_beyond_the_lattice_keep_one_aggregate():
     """Asking for more levels than the boxes can coarsen leaves single-cell
     levels (each the one aggregate of the level above), as in the oracle."""

@@ -107,3 +107,26 @@ def test_kappa_family_residual_elementwise():
     scale = max(np.abs(rs_ref).max(), np.abs(rp_ref).max())
     np.testing.assert_allclose(rp, rp_ref, rtol=0, atol=1e-13 * scale)
     np.testing.assert_allclose(rs[ff], rs_ref, rtol=0, atol=1e-13 * scale)
+
+
+def test_kappa_arguments_checked():
+    """Invalid family parameters are rejected with ERR_INVALID before any
+    work: an unknown kind, a <= 0, beta < 1."""
+    import ctypes as C
+    import dataclasses
+    import paper_2005_01275_amd as pk
+    from paper_2005_01275_amd import _native as N
+    prob = CASES["loam"]()
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    p = np.zeros(prob.mesh.n_cells)
+    s = np.zeros(prob.mesh.n_faces)
+    for bad, what in [(dict(kappa_a=0.0), "kappa_a"), (dict(kappa_beta=0.5), "kappa_beta")]:
+        with pytest.raises(pk.SpfasError, match=what):
+            H.eval_residual(dataclasses.replace(prob, **bad), p, s)
+    cp, keep = H._problem(prob, device=False)
+    cp.kappa_kind = 7
+    rp, rs = np.zeros(prob.mesh.n_cells), np.zeros(prob.mesh.n_faces)
+    rc = N.lib().spfas_eval_residual(H.h, C.byref(cp), p.ctypes.data, s.ctypes.data, rp.ctypes.data,
+                                     rs.ctypes.data, N.SPFAS_MEM_HOST, None)
+    assert rc == N.SPFAS_ERR_INVALID
+    assert b"kappa_kind" in N.lib().spfas_last_error()

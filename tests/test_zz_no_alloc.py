@@ -77,3 +77,23 @@ def test_noalloc_rejects_host_problem_data():
                                        C.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert rc == N.SPFAS_ERR_INVALID
     assert b"device memory" in L.spfas_last_error()
+
+
+def test_noalloc_rejects_a_kappa_shift():
+    """A shift of the kappa argument would need a device buffer of its own:
+    the no-allocation entry point refuses it before any work."""
+    import dataclasses
+    import torch
+    import paper_2005_01275_amd as pk
+    from paper_2005_01275_amd import _native as N
+    L = pk.lib()
+    base = small_problem((8, 8), seed=3, box=(4, 4), m=2, n_levels=2)
+    prob = dataclasses.replace(base, shift=np.linspace(0.0, 1.0, base.mesh.n_cells))
+    H = pk.Hierarchy(prob.mesh, prob.n_levels, prob.box, prob.m)
+    cp, keep = H._problem(prob, device=True)
+    p = torch.zeros(H.n_cells, dtype=torch.float64, device="cuda")
+    s = torch.zeros(H.n_faces, dtype=torch.float64, device="cuda")
+    rc = L.spfas_eval_residual_noalloc(H.h, C.byref(cp), p.data_ptr(), s.data_ptr(), p.data_ptr(), s.data_ptr(),
+                                       C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == N.SPFAS_ERR_INVALID
+    assert b"shift" in L.spfas_last_error()
