@@ -149,6 +149,11 @@ typedef enum {
  *             count before it builds the coarser level.  Not with
  *             host_only.  <= 0: the uniform m above.
  *   m_min     lower clamp of the threshold count (1 <= m_min <= m)
+ *   m_f       coarse flux unknowns per coarse interface (Appendix A, the
+ *             edge-based flux space): 1, the PV trace only (0 means 1).
+ *             Several traces per interface (eigenvector traces on extended
+ *             aggregates with an SVD) are not built: other values are
+ *             rejected with ERR_INVALID.
  */
 typedef struct {
   int32_t n_levels;
@@ -161,6 +166,7 @@ typedef struct {
   int32_t greedy_size;
   double eig_threshold;
   int32_t m_min;
+  int32_t m_f;
 } spfas_coarsen_opts;
 
 /*

@@ -67,6 +67,7 @@ static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
           "mesh arrays must not be NULL");
   require(o.n_levels >= 1 && o.n_levels <= 16, "n_levels must be in [1, 16]");
   require(o.m >= 1 && o.m <= 64, "m must be in [1, 64]");
+  require(o.m_f == 0 || o.m_f == 1, "m_f must be 1 (one flux unknown per coarse interface; more are not built)");
   if (o.agg_kind == SPFAS_AGG_BOX)
     for (int a = 0; a < M.dim; ++a) require(o.box[a] >= 1, "box edges must be >= 1");
   int64_t ndir = 0;

@@ -142,6 +142,9 @@ def test_threshold_count_options_rejected():
         pk.Hierarchy(prob.mesh, 2, (4, 4), 3, host_only=True, eig_threshold=0.1, m_min=0)
     # threshold off: host_only works and m_min is not read
     pk.Hierarchy(prob.mesh, 2, (4, 4), 3, host_only=True, eig_threshold=0.0, m_min=0).close()
+    # one flux unknown per coarse interface only
+    with pytest.raises(pk.SpfasError, match="m_f"):
+        pk.Hierarchy(prob.mesh, 2, (4, 4), 3, host_only=True, m_f=3)
 
 
 def test_levels_beyond_the_lattice_keep_one_aggregate():
