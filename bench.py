@@ -312,32 +312,46 @@ def served_leg(pk, n_requests, seed=7, n_models=10, n_slots=6):
         for t in burst:
             S.wait(t)
         capacity = len(burst) / (time.perf_counter() - t0)
+
+        def stream(rate, rq):
+            """Poisson arrivals at `rate` of the requests rq: latencies
+            (submission to completion), converged and failed counts, span."""
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, len(rq)))
+            tickets = [None] * len(rq)
+            start = time.perf_counter()
+
+            def feeder():
+                for k, (i, pr) in enumerate(rq):
+                    d = arrivals[k] - (time.perf_counter() - start)
+                    if d > 0:
+                        time.sleep(d)
+                    tickets[k] = S.submit(ids[i], pr, opts(pk.SPFAS_PREC_MIXED))
+
+            th = threading.Thread(target=feeder)
+            th.start()
+            th.join()
+            lat, ok, fail = [], 0, 0
+            for t in tickets:
+                try:
+                    _, _, st, info = S.wait(t)
+                    lat.append(info["total_ms"])
+                    ok += int(st["converged"])
+                except ServerError:
+                    fail += 1
+            return lat, ok, fail, time.perf_counter() - start
+
         rate = 0.7 * capacity
         log(f"served: capacity {capacity:.1f} solves/s, Poisson stream at {rate:.1f}/s")
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, n_requests))
-        tickets = [None] * n_requests
-        start = time.perf_counter()
-
-        def feeder():
-            for k, (i, pr) in enumerate(reqs):
-                d = arrivals[k] - (time.perf_counter() - start)
-                if d > 0:
-                    time.sleep(d)
-                tickets[k] = S.submit(ids[i], pr, opts(pk.SPFAS_PREC_MIXED))
-
-        th = threading.Thread(target=feeder)
-        th.start()
-        th.join()
-        lat, ok, fail = [], 0, 0
-        for t in tickets:
-            try:
-                _, _, st, info = S.wait(t)
-                lat.append(info["total_ms"])
-                ok += int(st["converged"])
-            except ServerError:
-                fail += 1
-        span = time.perf_counter() - start
+        lat, ok, fail, span = stream(rate, reqs)
         cnt = S.counters()
+        # the offered load swept around it (fewer requests per point)
+        sweep = []
+        for frac in (0.3, 0.5, 0.9, 1.1):
+            log(f"served: rate sweep at {frac:.1f} x capacity")
+            l2, ok2, f2, sp2 = stream(frac * capacity, reqs[:n_requests // 3])
+            sweep.append({"fraction_of_capacity": frac, "arrival_rate": frac * capacity,
+                          "solves_per_s": len(l2) / sp2, "latency_ms_p50": percentile(l2, 0.5),
+                          "latency_ms_p99": percentile(l2, 0.99), "converged": ok2, "failed": f2})
     # the same requests one at a time, FP64, hierarchies cached
     log("served: the same requests one at a time in FP64")
     Hs = {}
@@ -358,6 +372,7 @@ def served_leg(pk, n_requests, seed=7, n_models=10, n_slots=6):
             "cells": [m.mesh.n_cells for m in models], "capacity_solves_per_s": capacity, "arrival_rate": rate,
             "solves_per_s": len(lat) / span, "latency_ms_p50": percentile(lat, 0.5),
             "latency_ms_p99": percentile(lat, 0.99), "converged": ok, "failed": fail, "counters": cnt,
+            "rate_sweep": sweep,
             "fp64_one_at_a_time": {"solves_per_s": 1000.0 * len(seq) / sum(seq),
                                    "service_ms_p50": percentile(seq, 0.5), "service_ms_p99": percentile(seq, 0.99)}}
 
