@@ -292,6 +292,8 @@ typedef struct {
   double solve_ms;          /* wall time of the call (host clock)           */
   int32_t rejected_steps;   /* smoothing steps dropped because the linearised
                                system or its solve was not finite            */
+  int32_t refine_steps;     /* mixed precision: FP32 correction solves of the
+                               level-0 iterative refinement                  */
 } spfas_stats;
 
 /* Fills *o with the paper's settings (Section 4): Newton, rtol 1e-8, atol

@@ -86,7 +86,7 @@ class spfas_stats(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("lin_iters", C.c_int32), ("bt_halvings", C.c_int32),
                 ("smoothing_steps", C.c_int32), ("stopped_after_presmooth", C.c_int32),
                 ("r0", C.c_double), ("r_final", C.c_double), ("solve_ms", C.c_double),
-                ("rejected_steps", C.c_int32)]
+                ("rejected_steps", C.c_int32), ("refine_steps", C.c_int32)]
 
 
 class spfas_server_opts(C.Structure):

@@ -14,6 +14,8 @@
 #include "fine.hpp"
 #include "kappa.hpp"
 
+#include <type_traits>
+
 #include "kern.hpp"
 
 namespace spfas {
@@ -274,7 +276,10 @@ template <bool NEWTON, bool SELL, class TV, bool GK>
 __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const double* __restrict__ x,
                                                            const int* __restrict__ sptr, double* __restrict__ diag,
                                                            double* __restrict__ off, TV* __restrict__ sval,
-                                                           TV* __restrict__ rhs) {
+                                                           TV* __restrict__ rhs, double* __restrict__ sval64,
+                                                           double* __restrict__ rhs64) {
+  // FP32 values also go out in FP64 (the refinement residual of mixed precision)
+  constexpr bool DUAL = std::is_same_v<TV, float>;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = t / kLinG;
   const int g = (int)(t % kLinG);
@@ -283,8 +288,10 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
   const double* p = x + v.nf;
   const int k0 = v.cfptr[c], k1 = v.cfptr[c + 1];
   TV* row = nullptr;
+  double* row64 = nullptr;
   if constexpr (SELL) row = sval + sptr[c >> 6] + (c & 63);   // slot k of the row: row[64 k]
-  double dg = 0.0, rh = 0.0;
+  if constexpr (SELL && DUAL) row64 = sval64 + sptr[c >> 6] + (c & 63);
+  double dg = 0.0, rh = 0.0, so = 0.0;   // so: sum of the off-diagonal entries (FP32 row-sum form)
   for (int k = k0 + g; k < k1; k += kLinG) {
     const int code = v.cfcode[k];
     const int j = code >> 1;
@@ -318,67 +325,91 @@ __global__ void __launch_bounds__(kBlock) k_fine_lin_cells(FineView v, const dou
       o = L >= 0 ? -ul : 0.0;
       rh -= vs;
     }
-    if constexpr (SELL) row[(size_t)(1 + k - k0) << 6] = (TV)o;
-    else off[k] = o;
+    if constexpr (SELL) {
+      row[(size_t)(1 + k - k0) << 6] = (TV)o;
+      if constexpr (DUAL) {
+        row64[(size_t)(1 + k - k0) << 6] = o;
+        so += o;
+      }
+    } else {
+      off[k] = o;
+    }
   }
 #pragma unroll
   for (int o = kLinG / 2; o > 0; o >>= 1) {
     dg += __shfl_xor(dg, o, kLinG);
     rh += __shfl_xor(rh, o, kLinG);
+    if constexpr (SELL && DUAL) so += __shfl_xor(so, o, kLinG);
   }
   if (g == 0) {
-    if constexpr (SELL) row[0] = (TV)dg;
-    else diag[c] = dg;
-    rhs[c] = (TV)(v.f[c] + rh);
+    if constexpr (SELL && DUAL) {   // FP32 rows keep the row sum in slot 0 (Sell32View)
+      row[0] = (TV)(dg + so);
+      row64[0] = dg;
+    } else if constexpr (SELL) {
+      row[0] = (TV)dg;
+    } else {
+      diag[c] = dg;
+    }
+    const double b = v.f[c] + rh;
+    rhs[c] = (TV)b;
+    if constexpr (DUAL) rhs64[c] = b;
   }
 }
 
 template <class TV, bool GK>
 static void lin_cells_launch(const FineView& v, bool newton, const double* x, const int* sell_ptr, TV* sell_val,
-                             double* diag, double* off, TV* rhs, hipStream_t s) {
+                             double* diag, double* off, TV* rhs, double* sell64, double* rhs64, hipStream_t s) {
   const dim3 g(grid_for((size_t)v.n * kLinG, kBlock)), b(kBlock);
   if (sell_ptr) {
     if (newton)
       hipLaunchKernelGGL((k_fine_lin_cells<true, true, TV, GK>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr,
-                         sell_val, rhs);
+                         sell_val, rhs, sell64, rhs64);
     else
       hipLaunchKernelGGL((k_fine_lin_cells<false, true, TV, GK>), g, b, 0, s, v, x, sell_ptr, nullptr, nullptr,
-                         sell_val, rhs);
+                         sell_val, rhs, sell64, rhs64);
   } else {
     if (newton)
-      hipLaunchKernelGGL((k_fine_lin_cells<true, false, TV, GK>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
+      hipLaunchKernelGGL((k_fine_lin_cells<true, false, TV, GK>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs,
+                         nullptr, rhs64);
     else
-      hipLaunchKernelGGL((k_fine_lin_cells<false, false, TV, GK>), g, b, 0, s, v, x, nullptr, diag, off, nullptr, rhs);
+      hipLaunchKernelGGL((k_fine_lin_cells<false, false, TV, GK>), g, b, 0, s, v, x, nullptr, diag, off, nullptr,
+                         rhs, nullptr, rhs64);
   }
   LAUNCHCHECK();
 }
 
 template <class TV>
 static void lin_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr, TV* sell_val,
-                      double* diag, double* off, TV* rhs, hipStream_t s) {
+                      double* diag, double* off, TV* rhs, double* sell64, double* rhs64, hipStream_t s) {
   if (v.n == 0) return;
-  if (general_kappa(v)) lin_cells_launch<TV, true>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
-  else lin_cells_launch<TV, false>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
+  if (general_kappa(v)) lin_cells_launch<TV, true>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, sell64, rhs64, s);
+  else lin_cells_launch<TV, false>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, sell64, rhs64, s);
 }
 
 void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
                                  double* sell_val, double* diag, double* off, double* rhs, hipStream_t s) {
-  lin_cells<double>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
+  lin_cells<double>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, nullptr, nullptr, s);
 }
 
 void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
-                                 float* sell_val, double* diag, double* off, float* rhs, hipStream_t s) {
-  lin_cells<float>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, s);
+                                 float* sell_val, double* sell_val64, double* diag, double* off, float* rhs,
+                                 double* rhs64, hipStream_t s) {
+  require(rhs64 && (!sell_ptr || sell_val64), "mixed linearisation without its FP64 outputs");
+  lin_cells<float>(v, newton, x, sell_ptr, sell_val, diag, off, rhs, sell_val64, rhs64, s);
 }
 
+template <bool ADD>
 __global__ void __launch_bounds__(kBlock) k_widen(int64_t n, const float* __restrict__ a, double* __restrict__ b) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = (double)a[i];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (ADD) b[i] += (double)a[i];
+    else b[i] = (double)a[i];
+  }
 }
 
-void launch_widen(int64_t n, const float* a, double* b, hipStream_t s) {
+void launch_widen(int64_t n, const float* a, double* b, hipStream_t s, bool add) {
   if (!n) return;
-  hipLaunchKernelGGL(k_widen, dim3(reduce_grid(n)), dim3(kBlock), 0, s, n, a, b);
+  if (add) hipLaunchKernelGGL(k_widen<true>, dim3(reduce_grid(n)), dim3(kBlock), 0, s, n, a, b);
+  else hipLaunchKernelGGL(k_widen<false>, dim3(reduce_grid(n)), dim3(kBlock), 0, s, n, a, b);
   LAUNCHCHECK();
 }
 

@@ -45,12 +45,15 @@ int launch_fine_resid_trials(const FineView& v, const double* x, const double* d
 // diag/off (DIA+CSR on the cell-face lists).
 void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
                                  double* sell_val, double* diag, double* off, double* rhs, hipStream_t s);
-// mixed precision: SELL values and right-hand side stored in FP32 (the
-// DIA+CSR values, when there is no SELL copy, stay FP64)
+// mixed precision: SELL values and right-hand side stored in FP32 for the
+// linear solves and in FP64 (sell_val64, rhs64) for the residual of the
+// iterative refinement (the DIA+CSR values, when there is no SELL copy,
+// are FP64 only)
 void launch_fine_linearize_cells(const FineView& v, bool newton, const double* x, const int* sell_ptr,
-                                 float* sell_val, double* diag, double* off, float* rhs, hipStream_t s);
-// b = (double) a
-void launch_widen(int64_t n, const float* a, double* b, hipStream_t s);
+                                 float* sell_val, double* sell_val64, double* diag, double* off, float* rhs,
+                                 double* rhs64, hipStream_t s);
+// b = (double) a, or b += (double) a when `add`
+void launch_widen(int64_t n, const float* a, double* b, hipStream_t s, bool add = false);
 int launch_fine_backsub(const FineView& v, bool newton, const double* x, double* dx, double* parts,
                         hipStream_t s);
 void launch_fine_problem(const FineView& v, const int* cell_in, const int* flux_in, const double* vol,

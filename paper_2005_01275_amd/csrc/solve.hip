@@ -150,14 +150,16 @@ constexpr int kPcgStall = 5;
 // Krylov solve of a linearised system: PCG for Picard (symmetric);
 // BiCGStab for Newton, or PCG first with BiCGStab from scratch when PCG
 // breaks down, stalls or does not converge; the limit counts the iterations
-// of both.
+// of both.  `refine`: the first FP32 solve of mixed precision, where a
+// stalled PCG (Picard or Newton) returns and the FP64-residual refinement
+// goes on from its result.
 template <class T>
 static int krylov_solve(KrylovT<T>& kry, const CsrView& A, Amg* M, const T* b, T* x, double rtol, const Opts& o,
-                        hipStream_t s) {
-  if (!o.newton) return kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
-  if (o.newton_pcg) {
+                        hipStream_t s, bool refine = false) {
+  if (!o.newton && !refine) return kry.pcg(A, M, b, x, rtol, o.lin_max_it, s);
+  if (!o.newton || o.newton_pcg) {
     const int it = kry.pcg(A, M, b, x, rtol, o.lin_max_it, s, kPcgStall);
-    if (kry.converged) return it;
+    if (kry.converged || refine) return it;
     // the hand-over gets what is left of the solve's iteration limit
     const int left = o.lin_max_it - it;
     if (left <= 0) return it;
@@ -309,6 +311,42 @@ static double fine_rnorm(Hierarchy& h, const double* x, const double* dx, double
   return std::sqrt(h.host_sum(G));   // may be non-finite inside Alg. 1 trials
 }
 
+// Refinement steps of a mixed-precision level-0 solve: the residual of the
+// FP64 system S dp = rhs at the FP32 solution is formed in FP64 and, while
+// it exceeds kRefineSlack eta ||rhs||, an FP32 solve of S c = r (tolerance
+// eta ||rhs|| / ||r||, at most 0.5) adds its correction c to dp.  The slack
+// accepts the FP32 solutions whose residual is near the target, where one
+// more solve would cost more than the inexact step; FP32 vectors cannot
+// hold a solution whose residual is below about 2^-24 ||S|| ||dp||, so on
+// high-contrast systems the FP32 solve alone can end orders of magnitude
+// above eta.  Returns the Krylov iterations it spent.
+constexpr int kRefineMax = 3;
+constexpr double kRefineSlack = 10.0;
+
+static int mixed_refine(Hierarchy& h, const Opts& o, double eta, const Sell64View* sv, double* dp,
+                        spfas_stats& st) {
+  FineWork& w = h.fw;
+  hipStream_t s = h.stream;
+  const int64_t n = h.fine.n;
+  int it = 0;
+  for (int k = 0; k <= kRefineMax; ++k) {
+    const int G = launch_resid64(w.S, sv, dp, w.rhs.p, w.rhs32.p, h.dpin, s);
+    double rb[2];
+    h.host_sums(G, 2, rb);
+    if (trace_on())
+      std::fprintf(stderr, "[spfas] level 0 mixed: refinement %d, ||r||/||b|| = %.3e (eta %.1e)\n", k,
+                   std::sqrt(rb[0] / rb[1]), eta);
+    // done (or a non-finite residual, which the back-substitution rejects)
+    if (!(rb[0] > kRefineSlack * kRefineSlack * eta * eta * rb[1]) || k == kRefineMax) break;
+    const double ec = std::min(0.5, std::max(eta, eta * std::sqrt(rb[1] / rb[0])));
+    it += krylov_solve(w.kry32, w.S, &w.amg, w.rhs32.p, w.dp32.p, ec, o, s);
+    st.refine_steps++;
+    if (w.kry32.failed) break;   // keep the solution so far
+    launch_widen(n, w.dp32.p, dp, s, true);
+  }
+  return it;
+}
+
 // One Picard or Newton step on level 0 (Section 3.3): solve the linearised
 // system (flux block eliminated exactly, M is diagonal on level 0), cap,
 // Alg. 1.  `r_x` = ||r(x)|| on entry; returns ||r|| after the step.
@@ -323,16 +361,17 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
   // codes; outputs the values of S (diagonal + one per incidence) and rhs
   // one pass over the cells; with a SELL copy S goes straight into it.
   // Mixed precision: S (in the SELL layout) and the right-hand side are
-  // stored in FP32 and the linear system is solved in FP32; the residual,
-  // the back-substitution, Alg. 1 and the update stay FP64, so each step
-  // corrects the FP64 defect (defect correction).
+  // stored in FP32 and FP64; the linear system is solved in FP32 and refined
+  // against the FP64 system; the nonlinear residual, the back-substitution,
+  // Alg. 1 and the update stay FP64, so each step corrects the FP64 defect
+  // (defect correction).
   const bool mixed = o.mixed && w.amg.classical;
   const Sell64View* sv = w.amg.sell_source ? &w.amg.lv[0].sell64 : nullptr;
-  w.amg.sell_src32 = mixed && sv ? w.sval32.p : nullptr;
   h.prof.run(SPFAS_PROF_FINE_LINEARIZE, 40.0 * nf + 36.0 * n + 12.0 * (double)f.cfcode.n, s, [&] {
     if (mixed)
       launch_fine_linearize_cells(f.view(), o.newton, w.x.p, sv ? sv->sptr : nullptr, sv ? w.sval32.p : nullptr,
-                                  w.Sdiag.p, w.Soff.p, w.rhs32.p, s);
+                                  sv ? const_cast<double*>(sv->val) : nullptr, w.Sdiag.p, w.Soff.p, w.rhs32.p,
+                                  w.rhs.p, s);
     else
       launch_fine_linearize_cells(f.view(), o.newton, w.x.p, sv ? sv->sptr : nullptr,
                                   sv ? const_cast<double*>(sv->val) : nullptr, w.Sdiag.p, w.Soff.p, w.rhs.p, s);
@@ -345,9 +384,12 @@ static double fine_smooth(Hierarchy& h, const Opts& o, double r_x, spfas_stats& 
     eta = std::max(eta, std::min(0.1, o.lin_target * o.stop_tol / r_x));
   bool failed;
   if (mixed) {
-    it = krylov_solve(w.kry32, w.S, &w.amg, w.rhs32.p, w.dp32.p, eta, o, s);
+    it = krylov_solve(w.kry32, w.S, &w.amg, w.rhs32.p, w.dp32.p, eta, o, s, true);
     failed = w.kry32.failed;
-    if (!failed) launch_widen(n, w.dp32.p, dp, s);
+    if (!failed) {
+      launch_widen(n, w.dp32.p, dp, s);
+      it += mixed_refine(h, o, eta, sv, dp, st);
+    }
   } else {
     it = krylov_solve(w.kry, w.S, &w.amg, w.rhs.p, dp, eta, o, s);
     failed = w.kry.failed;

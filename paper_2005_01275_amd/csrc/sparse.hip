@@ -61,8 +61,20 @@ __device__ inline double row_dot_sell(const Mat& A, int i, const T* __restrict__
 
 template <class T>
 __device__ inline double row_dot(const Sell64View& A, int i, const T* __restrict__ x) { return row_dot_sell(A, i, x); }
+// Row-sum form (entry 0 is the row sum, see Sell32View)
 template <class T>
-__device__ inline double row_dot(const Sell32View& A, int i, const T* __restrict__ x) { return row_dot_sell(A, i, x); }
+__device__ inline double row_dot(const Sell32View& A, int i, const T* __restrict__ x) {
+  const int sl = i >> 6;
+  const int a0 = A.sptr[sl];
+  const int width = (A.sptr[sl + 1] - a0) >> 6;
+  int e = a0 + (i & 63);
+  const double xi = (double)x[i];
+  double a = (double)ld_stream(A.val + e) * xi;
+  e += 64;
+#pragma unroll 4
+  for (int k = 1; k < width; ++k, e += 64) a += (double)ld_stream(A.val + e) * ((double)x[ld_stream(A.col + e)] - xi);
+  return a;
+}
 
 // Rows [lo, hi) of the logical block: contiguous chunks (multiples of
 // `align` rows) in XCD-aware order.
@@ -119,6 +131,31 @@ __global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_spmv_dot2(Mat A, const T*
   a0 = block_sum(a0, sh);
   a1 = block_sum(a1, sh);
   if (threadIdx.x == 0) { parts0[lb] = a0; parts1[lb] = a1; }
+}
+
+// r = b - A x in FP64 with r stored in FP32 (the right-hand side of a
+// refinement step of mixed precision); parts[lb] = r.r, parts[G + lb] = b.b
+template <class Mat>
+__global__ void __launch_bounds__(SpmvBlock<Mat>::v) k_resid64(Mat A, const double* __restrict__ x,
+                                                               const double* __restrict__ b, float* __restrict__ r,
+                                                               double* __restrict__ parts) {
+  __shared__ double sh[SpmvBlock<Mat>::v / 64];
+  int lb, lo, hi;
+  block_rows(A.n, lb, lo, hi, 64);
+  double rr = 0.0, bb = 0.0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += blockDim.x) {
+    const double bi = b[i];
+    const double ri = bi - row_dot(A, i, x);
+    r[i] = (float)ri;
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+  rr = block_sum(rr, sh);
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    parts[lb] = rr;
+    parts[gridDim.x + lb] = bb;
+  }
 }
 
 template <class T>
@@ -1282,15 +1319,14 @@ void Amg::numeric(hipStream_t s) {
   dense_numeric(s);
 }
 
-template <class V>
 __global__ void __launch_bounds__(kBlock) k_sell_to_csr(int ne, const int* __restrict__ smap,
-                                                        const V* __restrict__ val, double* __restrict__ diag,
+                                                        const double* __restrict__ val, double* __restrict__ diag,
                                                         double* __restrict__ off) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= ne) return;
   const int m = smap[e];
-  if (m >= 0) off[m] = (double)val[e];
-  else if (m != kSellPad) diag[-1 - m] = (double)val[e];
+  if (m >= 0) off[m] = val[e];
+  else if (m != kSellPad) diag[-1 - m] = val[e];
 }
 
 void Amg::sell_to_csr(hipStream_t s) {
@@ -1299,12 +1335,8 @@ void Amg::sell_to_csr(hipStream_t s) {
   require(ne > 0, "sell_to_csr without a SELL copy");
   double* diag = const_cast<double*>(F.view.diag);
   double* off = const_cast<double*>(F.view.val);
-  if (sell_src32)
-    hipLaunchKernelGGL(k_sell_to_csr<float>, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, sell_src32,
-                       diag, off);
-  else
-    hipLaunchKernelGGL(k_sell_to_csr<double>, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p,
-                       F.sval64.p, diag, off);
+  hipLaunchKernelGGL(k_sell_to_csr, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.smap.p, F.sval64.p, diag,
+                     off);
   LAUNCHCHECK();
 }
 
@@ -1782,5 +1814,18 @@ int KrylovT<T>::bicgstab(const CsrView& A, Amg* M, const T* b, T* x, double rtol
 
 template struct KrylovT<double>;
 template struct KrylovT<float>;
+
+int launch_resid64(const CsrView& A, const Sell64View* As, const double* x, const double* b, float* r, double* parts,
+                   hipStream_t s) {
+  const int G = reduce_grid(A.n);
+  if (As) {
+    require(As->n == A.n, "SELL copy of another matrix");
+    hipLaunchKernelGGL(k_resid64<Sell64View>, dim3(G), dim3(SpmvBlock<Sell64View>::v), 0, s, *As, x, b, r, parts);
+  } else {
+    hipLaunchKernelGGL(k_resid64<CsrView>, dim3(G), dim3(SpmvBlock<CsrView>::v), 0, s, A, x, b, r, parts);
+  }
+  LAUNCHCHECK();
+  return G;
+}
 
 }  // namespace spfas

@@ -77,7 +77,13 @@ struct Sell64View {
   const double* val = nullptr;
 };
 
-// The same pattern with FP32 values (level 0 in mixed precision).
+// The same pattern with FP32 values (level 0 in mixed precision), except
+// that entry 0 of row i holds the row sum s_i = sum_j a_ij instead of the
+// diagonal; products are formed as y_i = s_i x_i + sum_{j != i} a_ij (x_j -
+// x_i).  Rounding to FP32 then perturbs each coupling and each row sum by a
+// relative 2^-24, as a relative change of the coefficients would; a rounded
+// diagonal would not, since on high-contrast systems it nearly cancels the
+// couplings of its row.
 struct Sell32View {
   int n = 0;
   const int* sptr = nullptr;
@@ -192,9 +198,6 @@ struct Amg {
   void numeric_classical(hipStream_t s);
   template <class T>
   void apply_classical(const T* b, T* x, hipStream_t s);
-  // level-0 values the caller writes in FP32 (mixed precision): sell_to_csr
-  // reads them instead of sval64
-  const float* sell_src32 = nullptr;
   void dense_numeric(hipStream_t s);
   int n_levels() const { return (int)lv.size(); }
   std::string describe() const;       // "n/nnz" per level, for diagnostics
@@ -244,5 +247,10 @@ using Krylov32 = KrylovT<float>;
 
 // y = A x
 void launch_spmv(const CsrView& A, const double* x, double* y, hipStream_t s);
+// r = b - A x (FP64 products, r stored in FP32), reading the SELL copy As
+// of A when given; per-block partial sums of r.r then b.b in parts[0, 2G);
+// returns G (at least 1, also for n = 0)
+int launch_resid64(const CsrView& A, const Sell64View* As, const double* x, const double* b, float* r, double* parts,
+                   hipStream_t s);
 
 }  // namespace spfas
