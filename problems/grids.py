@@ -149,10 +149,18 @@ def cartesian_mesh(shape, spacing, k_cells, dirichlet=((0, 0),)) -> Mesh:
                 face_bc=np.concatenate(fbc), shape=shape)
 
 
-def voronoi_mesh(points: np.ndarray, k_cells: np.ndarray, dirichlet_x0: bool = True) -> Mesh:
+def voronoi_mesh(points: np.ndarray, k_cells: np.ndarray, dirichlet_x0: bool = True,
+                 band: Optional[float] = None) -> Mesh:
     """Bounded Voronoi tessellation of the unit square from generator
-    points: each point is mirrored across the four sides, so the cells of
-    the original points are clipped to the square (qhull through SciPy).
+    points: points are mirrored across the four sides, so the cells of the
+    original points are clipped to the square (qhull through SciPy).
+
+    Only the points within ``band`` of a side are mirrored (default 8 point
+    spacings; ``band`` >= 1 mirrors all of them).  Within the square a point
+    is never farther from an original generator than from that generator's
+    mirror image, so a cell computed with a subset of the mirrors contains
+    the exact clipped cell, and equals it once it lies inside the square;
+    when some cell does not, the band is doubled and the diagram recomputed.
 
     Geometry as the two-point flux needs it on a Voronoi mesh: the cell
     "centroid" is its generator point (the face between two cells is then
@@ -160,34 +168,52 @@ def voronoi_mesh(points: np.ndarray, k_cells: np.ndarray, dirichlet_x0: bool = T
     midpoint of that segment (on the bisector), the normal points from K to
     L, the face measure is the Voronoi edge length.  Boundary faces are the
     edges shared with a mirror point.  Dirichlet on the side x = 0 when
-    ``dirichlet_x0``, Neumann elsewhere.  Cell volumes are polygon areas."""
+    ``dirichlet_x0``, Neumann elsewhere.  Cell volumes are polygon areas,
+    summed as the triangles between the generator and each edge (a Voronoi
+    cell is convex and holds its generator)."""
     from scipy.spatial import Voronoi
     pts = np.asarray(points, dtype=np.float64)
     n = pts.shape[0]
-    mir = [pts, np.c_[-pts[:, 0], pts[:, 1]], np.c_[2.0 - pts[:, 0], pts[:, 1]],
-           np.c_[pts[:, 0], -pts[:, 1]], np.c_[pts[:, 0], 2.0 - pts[:, 1]]]
-    vor = Voronoi(np.concatenate(mir))
-    V = vor.vertices
-    # cell areas by the shoelace formula over each region's ordered vertices
-    vol = np.empty(n)
-    for i in range(n):
-        reg = vor.regions[vor.point_region[i]]
-        xy = V[reg]
-        vol[i] = 0.5 * abs(np.dot(xy[:, 0], np.roll(xy[:, 1], -1)) - np.dot(xy[:, 1], np.roll(xy[:, 0], -1)))
-    rp = vor.ridge_points
-    rv = np.asarray(vor.ridge_vertices, dtype=np.int64)
-    a, b = rp[:, 0], rp[:, 1]
-    keep = (a < n) | (b < n)
-    a, b, rv = a[keep], b[keep], rv[keep]
+    h = 8.0 / math.sqrt(max(n, 1)) if band is None else float(band)
+    while True:
+        sides = [(pts[:, 0] < h, lambda q: np.c_[-q[:, 0], q[:, 1]]),
+                 (pts[:, 0] > 1.0 - h, lambda q: np.c_[2.0 - q[:, 0], q[:, 1]]),
+                 (pts[:, 1] < h, lambda q: np.c_[q[:, 0], -q[:, 1]]),
+                 (pts[:, 1] > 1.0 - h, lambda q: np.c_[q[:, 0], 2.0 - q[:, 1]])]
+        allp = np.concatenate([pts] + [f(pts[sel]) for sel, f in sides])
+        vor = Voronoi(allp)
+        V = vor.vertices
+        rp = vor.ridge_points
+        rv = np.asarray(vor.ridge_vertices, dtype=np.int64)
+        keep = (rp[:, 0] < n) | (rp[:, 1] < n)
+        if h >= 1.0:
+            break
+        # every original cell bounded and inside the square: the diagram is exact
+        rk = rv[keep]
+        if (rk >= 0).all():
+            xy = V[np.unique(rk)]
+            if (xy >= -1e-9).all() and (xy <= 1.0 + 1e-9).all():
+                break
+        h *= 2.0
+    a, b, rv = rp[keep, 0], rp[keep, 1], rv[keep]
     # orient every ridge with an original point first
     sw = a >= n
     a, b = np.where(sw, b, a), np.where(sw, a, b)
-    length = np.linalg.norm(V[rv[:, 0]] - V[rv[:, 1]], axis=1)
+    v0, v1 = V[rv[:, 0]], V[rv[:, 1]]
+    length = np.linalg.norm(v0 - v1, axis=1)
+
+    def fan(c):   # area of the triangle (generator c, edge end points)
+        e0, e1 = v0 - pts[c], v1 - pts[c]
+        return 0.5 * np.abs(e0[:, 0] * e1[:, 1] - e0[:, 1] * e1[:, 0])
+
+    vol = np.zeros(n)
+    np.add.at(vol, a, fan(a))
     inner = b < n
+    np.add.at(vol, b[inner], fan(np.where(inner, b, 0))[inner])
     # drop degenerate ridges (zero length) between two original cells
     ok = length > 1e-14
     a, b, length, inner = a[ok], b[ok], length[ok], inner[ok]
-    other = np.concatenate(mir)[b]   # the neighbour's generator (or the mirror image across the boundary)
+    other = allp[b]   # the neighbour's generator (or the mirror image across the boundary)
     d = other - pts[a]
     normal = d / np.linalg.norm(d, axis=1)[:, None]
     point = 0.5 * (pts[a] + other)
