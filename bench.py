@@ -206,25 +206,20 @@ def c1_leg(torch, pk, c1_problem, steps=200):
             "krylov_iters": st["lin_iters"], "cell_updates_per_s": prob.mesh.n_cells * st["iterations"] * steps / t}
 
 
-def unstructured_leg(torch, pk, n_points=200000, seed=3, steps=3):
-    """The unstructured configuration at 1/10 of its 2,000,000 points (so the
-    bench stays within minutes): a bounded Voronoi mesh of seeded points,
-    ln k = 3G with correlation length 0.01, kappa = exp(2p), greedy
-    aggregates of about 64 cells on 2 levels (a third level would group 64
-    coarse cells of up to 6 unknowns each, beyond the 512 unknowns the local
-    dense solvers take), eigenvectors per aggregate by
-    the threshold 0.1 clamped to [2, 6], mixed-precision FAS-Newton to rtol
-    1e-8.  The source pair is scaled by a linear (alpha = 0) solve on the
-    GPU so that alpha max|p_lin| = 0.5.  The mixed-precision result is
-    compared with the FP64 solve on the same hierarchy, which the parity
-    tests tie to the oracle's root."""
+def unstructured_leg(torch, pk, steps=3):
+    """The unstructured configuration at its full size: the bounded Voronoi
+    mesh of 2,000,000 seeded points, ln k = 3G with correlation length 0.01,
+    kappa = exp(2p), greedy aggregates of about 64 cells on 2 levels,
+    eigenvectors per aggregate by the threshold 0.1 clamped to [2, 6],
+    mixed-precision FAS-Newton to rtol 1e-8 beside the FP64 solve on the same
+    hierarchy (which the parity tests tie to the oracle); the source rate is
+    the oracle-calibrated one (alpha max |p_lin| = 0.5)."""
     import numpy as np
-    from problems.grids import voronoi_problem
+    from problems.grids import c3_problem
     from paper_2005_01275_amd import _native as N
-    log(f"unstructured: Voronoi mesh of {n_points} points")
+    log("unstructured: Voronoi mesh of 2,000,000 points")
     t0 = time.perf_counter()
-    prob = voronoi_problem(n_points=n_points, seed=seed, sigma=3.0, corr_len=0.01, alpha=2.0, n_levels=2,
-                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2)
+    prob = c3_problem()
     t_mesh = time.perf_counter() - t0
     log("unstructured: hierarchy (greedy aggregates, threshold counts)")
     t0 = time.perf_counter()
@@ -236,17 +231,12 @@ def unstructured_leg(torch, pk, n_points=200000, seed=3, steps=3):
     for l in range(prob.n_levels - 1):
         n_agg = H.level_sizes(l + 1)[0]
         counts.append(np.bincount(H.level_operator(l, N.SPFAS_OP_MCOUNT, n_agg).astype(int), minlength=7)[1:].tolist())
-    lin = pk.SolveOpts(smoother=pk.SPFAS_PICARD, rtol=1e-10, atol=0.0, max_it=5, lin_rtol=1e-12, lin_max_it=2000)
-    p_lin, _, _ = H.fas_solve(dataclasses.replace(prob, alpha=0.0), lin)
-    rate = 0.5 / (prob.alpha * float(np.abs(p_lin).max()))
-    prob = dataclasses.replace(prob, source=prob.source * rate)
     cprob, keep = H._problem(prob, device=True)
     base = dict(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=1e-5, lin_max_it=400,
                 lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1, amg_reuse=-1, lin_max_it_coarse=10,
                 coarsest_atol=1e-10, dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
-    out = {"workload": f"voronoi_2d_{n_points} (1/10 of the 2,000,000-point configuration), ln k = 3G, "
-                       "kappa = exp(2p), greedy aggregates of 64, 2 levels, eigenvector counts by threshold 0.1 "
-                       "in [2, 6], FAS-Newton rtol 1e-8",
+    out = {"workload": "voronoi_2d_2000000, ln k = 3G, kappa = exp(2p), greedy aggregates of 64, 2 levels, "
+                       "eigenvector counts by threshold 0.1 in [2, 6], FAS-Newton rtol 1e-8",
            "cells": prob.mesh.n_cells, "mesh_s": t_mesh, "setup_s": t_setup, "eig_counts_per_level": counts}
     res = {}
     for name, prec in (("mixed", pk.SPFAS_PREC_MIXED), ("fp64", pk.SPFAS_PREC_FP64)):

@@ -456,6 +456,26 @@ def served_problem(seed: int, n_min: int = 32 ** 2, n_max: int = 64 ** 3, dims=(
                    n_levels=levels, dp_cap_c=5.0)
 
 
+# Source rate of the 2,000,000-point Voronoi workload (seed 3), chosen so that
+# alpha max |p| = 0.5 for the linear (kappa = 1) pressure; written by the
+# calibration script tests/golden/calibrate_c3_rate.py (stored in
+# tests/golden/c3_rate.json).
+C3_RATE = 0.17304720191344097
+
+
+def c3_problem(rate: Optional[float] = None) -> Problem:
+    """The unstructured workload: the Voronoi mesh of 2,000,000 seeded uniform
+    points in the unit square (seed 3), ln k = 3G with correlation length
+    0.01, kappa = exp(2p), p = 0 on x = 0, a source pair near (0.05, 0.05)
+    and (0.95, 0.95); greedy aggregates of about 64 cells on 2 levels, 2 to 6
+    eigenvectors per aggregate by the threshold 0.1."""
+    q = C3_RATE if rate is None else rate
+    if q is None:
+        raise ValueError("C3_RATE is not calibrated")
+    return voronoi_problem(n_points=2000000, seed=3, sigma=3.0, corr_len=0.01, alpha=2.0, rate=q, n_levels=2,
+                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2)
+
+
 def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=None, m=2,
                   n_levels=2, spacing=None, g_d_scale=0.0, g_n_scale=0.0, src_scale=1.0,
                   anisotropic=False, permute=False, dp_cap_c=5.0) -> Problem:
