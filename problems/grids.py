@@ -456,6 +456,48 @@ def served_problem(seed: int, n_min: int = 32 ** 2, n_max: int = 64 ** 3, dims=(
                    n_levels=levels, dp_cap_c=5.0)
 
 
+def c4_problem(i: int, seed: int = 4) -> Problem:
+    """Instance i of the batched workload (512 instances): a box of
+    n_x x n_y x n_z cubic cells with every edge drawn from U{16..96}, ln k =
+    2G with correlation length 5 cells, kappa = exp(p), p = 0 on x = 0, no
+    flow elsewhere, a zero-mean random source density (the caller scales
+    it: the rule used is max|p| = 0.25 for the kappa = 1 pressure); box
+    aggregates of edge a ~ U{4..8} (64 to 512 cells) with 3 local
+    eigenvectors; 2 levels when a >= 5 (a coarse aggregate of up to
+    (a + 2)^3 coarse cells of 3 unknowns each would exceed the 512 unknowns
+    the local dense solvers take), else levels until the coarsest has at
+    most 400 cells (at most 4).  An edge
+    whose remainder the box rule would merge into a block of more than 8
+    cells (a = 7 or 8 with 0 < n mod a < a/2) is drawn again, so that no
+    aggregate exceeds 512 cells."""
+    rng = np.random.default_rng([seed, i])
+    a = int(rng.integers(4, 9))
+    shape = []
+    while len(shape) < 3:
+        n = int(rng.integers(16, 97))
+        r = n % a
+        if 0 < r and 2 * r < a and a + r > 8:
+            continue
+        shape.append(n)
+    shape = tuple(shape)
+    h = 1.0 / max(shape)
+    k = np.exp(2.0 * _flat(gaussian_field(shape, 5.0, rng)))
+    mesh = cartesian_mesh(shape, (h, h, h), k, dirichlet=((0, 0),))
+    n = mesh.n_cells
+    src = rng.standard_normal(n)
+    src -= src.mean()
+    if a >= 5:
+        levels = 2
+    else:
+        levels, c = 1, n
+        while c > 400 and levels < 4:
+            c //= a ** 3
+            levels += 1
+    return Problem(mesh=mesh, alpha=1.0, source=src, g_dirichlet=np.zeros(mesh.n_faces),
+                   g_neumann=np.zeros(mesh.n_faces), name=f"c4_{i}_{'x'.join(map(str, shape))}_a{a}",
+                   box=(a, a, a), m=3, n_levels=levels, dp_cap_c=5.0)
+
+
 # Source rate of the 2,000,000-point Voronoi workload (seed 3), chosen so that
 # alpha max |p| = 0.5 for the linear (kappa = 1) pressure; written by the
 # calibration script tests/golden/calibrate_c3_rate.py (stored in

@@ -21,6 +21,12 @@ CASES = [
     # level-1 -> 2 local problems of 64 coarse cells (192 pressure unknowns,
     # interface problems of 384): the blocked dense routines of the setup
     dict(shape=(32, 16, 16), box=(4, 4, 4), m=3, n_levels=3, seed=5, anisotropic=True, permute=True),
+    # the largest aggregates the batched workload draws: 8^3 = 512 cells
+    # (interface problems over 1,024 cells), and 6^3 / 7^3 boxes with
+    # remainder blocks merged into their neighbours
+    dict(shape=(16, 16, 16), box=(8, 8, 8), m=3, n_levels=2, seed=6, sigma=2.0, permute=True),
+    dict(shape=(16, 13, 9), box=(6, 6, 6), m=3, n_levels=2, seed=7, sigma=2.0),
+    dict(shape=(14, 11, 7), box=(7, 7, 7), m=3, n_levels=2, seed=8, sigma=1.5, anisotropic=True),
 ]
 
 
