@@ -322,6 +322,11 @@ int spfas_setup_hierarchy(const spfas_mesh* mesh, const spfas_coarsen_opts* opts
  * (*peak), counting everything allocated through its allocator. */
 int spfas_hierarchy_device_bytes(const spfas_hierarchy* h, int64_t* bytes, int64_t* peak);
 
+/* Sets the peak that spfas_hierarchy_device_bytes reports to the bytes held
+ * now, so that the peak of what follows (a solve's temporaries) can be
+ * measured.  Not to be called while a solve on h is running. */
+int spfas_hierarchy_reset_peak(spfas_hierarchy* h);
+
 /*
  * Solves the nonlinear system (eq. nonlinear_system_residual_form) with FAS
  * V-cycles (Alg. 2): Picard or Newton smoothing with the step cap and Alg. 1,

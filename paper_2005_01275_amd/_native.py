@@ -19,7 +19,7 @@ SPFAS_OP_EIGVALS, SPFAS_OP_PP, SPFAS_OP_PSIGMA, SPFAS_OP_MLOC, SPFAS_OP_DLOC, SP
 
 EXPORTED = ["spfas_default_solve_opts", "spfas_setup_hierarchy", "spfas_fas_solve", "spfas_cascadic_solve",
             "spfas_picard_solve", "spfas_newton_solve", "spfas_eval_residual", "spfas_eval_residual_noalloc",
-            "spfas_level_sizes", "spfas_hierarchy_device_bytes",
+            "spfas_level_sizes", "spfas_hierarchy_device_bytes", "spfas_hierarchy_reset_peak",
             "spfas_get_aggregation",
             "spfas_get_permutation", "spfas_get_level_operator", "spfas_destroy", "spfas_last_error",
             "spfas_version", "spfas_profile_enable", "spfas_profile_read",
@@ -146,6 +146,8 @@ def lib():
     L.spfas_level_sizes.restype = C.c_int
     L.spfas_hierarchy_device_bytes.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
     L.spfas_hierarchy_device_bytes.restype = C.c_int
+    L.spfas_hierarchy_reset_peak.argtypes = [vp]
+    L.spfas_hierarchy_reset_peak.restype = C.c_int
     L.spfas_get_aggregation.argtypes = [vp, C.c_int32, _ip]
     L.spfas_get_aggregation.restype = C.c_int
     L.spfas_get_permutation.argtypes = [vp, C.c_int32, _ip, _ip]

@@ -93,6 +93,14 @@ int spfas_hierarchy_device_bytes(const spfas_hierarchy* h, int64_t* bytes, int64
   });
 }
 
+int spfas_hierarchy_reset_peak(spfas_hierarchy* h) {
+  return guarded([&] {
+    require(h != nullptr, "NULL hierarchy");
+    h->h.mem.peak.store(h->h.mem.bytes.load());
+    return SPFAS_OK;
+  });
+}
+
 void spfas_destroy(spfas_hierarchy* h) {
   if (!h) return;
   try {

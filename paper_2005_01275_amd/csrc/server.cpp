@@ -43,7 +43,8 @@ struct Instance {
   bool busy = false;
   bool building = false;
   uint64_t last_used = 0;
-  int64_t bytes = 0;              // reserved or measured device bytes
+  int64_t bytes = 0;              // device bytes reserved now (held, plus a running solve's temporaries)
+  int64_t solve_extra = 0;        // measured temporaries of a solve beyond what the hierarchy holds
 };
 
 struct Model {
@@ -150,6 +151,10 @@ struct spfas_server {
       }
       if (m->inst) {
         if (m->inst->busy) { ++it; continue; }
+        const int64_t extra = m->inst->solve_extra;
+        if (extra > 0 && !make_room(extra, m)) { ++it; continue; }
+        used += extra;
+        m->inst->bytes += extra;
         m->inst->busy = true;
         r->cache_hit = true;
       } else {
@@ -183,12 +188,20 @@ struct spfas_server {
       Instance* in = m->inst.get();
       int rc = SPFAS_OK;
       std::string err;
+      int64_t build_peak = 0;
       if (in->building) {
         const spfas_mesh mesh = m->mesh();
         spfas_hierarchy* h = nullptr;
         rc = spfas_setup_hierarchy(&mesh, &m->co, nullptr, (void*)s, &h);
         if (rc < 0) err = spfas_last_error();
         in->h = h;
+        if (h) spfas_hierarchy_device_bytes(h, nullptr, &build_peak);
+      }
+      // the solve's own peak (the setup's scratch is gone by now)
+      int64_t held0 = 0;
+      if (in->h) {
+        spfas_hierarchy_reset_peak(in->h);
+        spfas_hierarchy_device_bytes(in->h, &held0, nullptr);
       }
       r->t_solve = now_ms();
       if (rc >= 0) {
@@ -230,10 +243,14 @@ struct spfas_server {
           used -= in->bytes;
           m->inst.reset();
         } else {
-          // what the instance holds at most (setup and a solve's temporaries)
-          used += peak - in->bytes;
-          in->bytes = peak;
-          if (!m->measured || peak > m->est_bytes) m->est_bytes = peak;
+          // idle, the instance holds `bytes`; a later solve reserves its
+          // temporaries on top, a rebuild the larger of the build's and the
+          // solve's peaks
+          used += bytes - in->bytes;
+          in->bytes = bytes;
+          in->solve_extra = std::max(in->solve_extra, std::max<int64_t>(0, peak - std::min(held0, bytes)));
+          const int64_t need = std::max(build_peak, peak);
+          if (!m->measured || need > m->est_bytes) m->est_bytes = need;
           m->measured = true;
           in->busy = false;
           in->last_used = ++clock;
