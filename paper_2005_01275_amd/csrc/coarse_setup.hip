@@ -57,6 +57,78 @@ struct ScratchA {
   size_t total;
 };
 
+// Position of local flux i of a cell of side `side` (0: A, 1: B) among the
+// unknowns of the union problem [int(A), int(B), F], or -1 when the flux is
+// not one of them (faces to other aggregates, Dirichlet faces).
+__device__ inline int union_pos(const int* sm, int i, int side, int nIA, int nIB, int nF, int gA, int gB) {
+  const int q = sm[i];
+  if (side == 0) {
+    if (q < nIA) return q;
+    if (q >= gA && q < gA + nF) return nIA + nIB + (q - gA);
+    return -1;
+  }
+  if (q < nIB) return nIA + q;
+  if (q >= gB && q < gB + nF) return nIA + nIB + (q - gB);
+  return -1;
+}
+
+// Level 0 (M diagonal, one pressure unknown per cell, D entries -1 / +1):
+// L = D M^{-1} D^T of the union problem is assembled from the two incidences
+// of each flux, without the dense D, M^{-1} D^T and their product.  `inc`
+// holds per flux the two (row, sign) pairs [row0 | sign0 | row1 | sign1],
+// row -1 when absent.
+__device__ inline void pv_union_level0(const LocalView& lv, const PlanView& pl, int A, int B, int nIA, int nIB, int nF,
+                                       int gA, int gB, int ns, int npA, int npU, double* Mu, double* inc, double* L) {
+  for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+    Mu[s] = 0.0;
+    inc[s] = -1.0;
+    inc[ns + s] = 0.0;
+    inc[2 * ns + s] = -1.0;
+    inc[3 * ns + s] = 0.0;
+  }
+  wg_sync();
+  int row = 0;
+  for (int side = 0; side < (B >= 0 ? 2 : 1); ++side) {
+    const int X = side == 0 ? A : B;
+    for (int ci = pl.cell_ptr[X]; ci < pl.cell_ptr[X + 1]; ++ci, ++row) {
+      const int c = pl.cell_list[ci];
+      const int k = lv_k(lv, c);
+      const int* sm = pl.smap + pl.smap_ptr[ci];
+      // a cell's local fluxes are distinct, so the threads touch distinct pi
+      for (int i = threadIdx.x; i < k; i += blockDim.x) {
+        const int pi = union_pos(sm, i, side, nIA, nIB, nF, gA, gB);
+        if (pi < 0) continue;
+        Mu[pi] += lv_M(lv, c, i, i);
+        const int slot = inc[pi] < 0.0 ? 0 : 2 * ns;
+        inc[slot + pi] = (double)row;
+        inc[slot + ns + pi] = lv_D(lv, c, 0, i);
+      }
+      wg_sync();
+    }
+  }
+  // row r of L from the fluxes of its cell, in the cell's local order
+  for (int r = threadIdx.x; r < npU; r += blockDim.x) {
+    const int side = r < npA ? 0 : 1;
+    const int ci = side == 0 ? pl.cell_ptr[A] + r : pl.cell_ptr[B] + (r - npA);
+    const int c = pl.cell_list[ci];
+    const int k = lv_k(lv, c);
+    const int* sm = pl.smap + pl.smap_ptr[ci];
+    double* Lr = L + (size_t)r * npU;
+    for (int q = 0; q < npU; ++q) Lr[q] = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const int pi = union_pos(sm, i, side, nIA, nIB, nF, gA, gB);
+      if (pi < 0) continue;
+      const double w = 1.0 / Mu[pi];
+      const bool first = (int)inc[pi] == r;
+      const double sr = first ? inc[ns + pi] : inc[3 * ns + pi];
+      const int o = (int)(first ? inc[2 * ns + pi] : inc[pi]);
+      Lr[r] += w;
+      if (o >= 0) Lr[o] += w * sr * (first ? inc[3 * ns + pi] : inc[ns + pi]);
+    }
+  }
+  wg_sync();
+}
+
 __global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, int n_faces, const int* __restrict__ fc1,
                                                      const int* __restrict__ fc2, const double* __restrict__ ones,
                                                      double* __restrict__ trace, double* __restrict__ scratch,
@@ -76,65 +148,51 @@ __global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, 
     const int npB = B >= 0 ? pl.pd_ptr[B + 1] - pl.pd_ptr[B] : 0;
     const int npU = npA + npB;
     const int gA = pl.grp_pos_A[F], gB = B >= 0 ? pl.grp_pos_B[F] : -1;
-    const int ldm = lv.level0 ? 1 : ns;
-    wg_fill(Mu, lv.level0 ? ns : ns * ns, 0.0);
-    wg_fill(Du, npU * ns, 0.0);
-    // assemble cell by cell (deterministic: cells in order, entries of one cell in parallel)
-    int rowbase = 0;
-    for (int side = 0; side < (B >= 0 ? 2 : 1); ++side) {
-      const int X = side == 0 ? A : B;
-      for (int ci = pl.cell_ptr[X]; ci < pl.cell_ptr[X + 1]; ++ci) {
-        const int c = pl.cell_list[ci];
-        const int k = lv_k(lv, c), m = lv_m(lv, c);
-        const int* sm = pl.smap + pl.smap_ptr[ci];
-        auto posU = [&](int i) -> int {
-          const int q = sm[i];
-          if (side == 0) {
-            if (q < nIA) return q;
-            if (q >= gA && q < gA + nF) return nIA + nIB + (q - gA);
-            return -1;
-          }
-          if (q < nIB) return nIA + q;
-          if (q >= gB && q < gB + nF) return nIA + nIB + (q - gB);
-          return -1;
-        };
-        if (lv.level0) {
-          for (int i = threadIdx.x; i < k; i += blockDim.x) {
-            const int pi = posU(i);
-            if (pi >= 0) Mu[pi] += lv_M(lv, c, i, i);
-          }
-        } else {
+    if (lv.level0) {
+      pv_union_level0(lv, pl, A, B, nIA, nIB, nF, gA, gB, ns, npA, npU, Mu, Du, L);
+    } else {
+      const int ldm = ns;
+      wg_fill(Mu, ns * ns, 0.0);
+      wg_fill(Du, npU * ns, 0.0);
+      // assemble cell by cell (deterministic: cells in order, entries of one cell in parallel)
+      int rowbase = 0;
+      for (int side = 0; side < (B >= 0 ? 2 : 1); ++side) {
+        const int X = side == 0 ? A : B;
+        for (int ci = pl.cell_ptr[X]; ci < pl.cell_ptr[X + 1]; ++ci) {
+          const int c = pl.cell_list[ci];
+          const int k = lv_k(lv, c), m = lv_m(lv, c);
+          const int* sm = pl.smap + pl.smap_ptr[ci];
           for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
             const int i = e / k, j = e % k;
-            const int pi = posU(i), pj = posU(j);
+            const int pi = union_pos(sm, i, side, nIA, nIB, nF, gA, gB);
+            const int pj = union_pos(sm, j, side, nIA, nIB, nF, gA, gB);
             if (pi >= 0 && pj >= 0) Mu[pi * ldm + pj] += lv_M(lv, c, i, j);
           }
+          for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+            const int r = e / k, i = e % k;
+            const int pi = union_pos(sm, i, side, nIA, nIB, nF, gA, gB);
+            if (pi >= 0) Du[(rowbase + r) * ns + pi] += lv_D(lv, c, r, i);
+          }
+          rowbase += m;
+          wg_sync();
         }
-        for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
-          const int r = e / k, i = e % k;
-          const int pi = posU(i);
-          if (pi >= 0) Du[(rowbase + r) * ns + pi] += lv_D(lv, c, r, i);
-        }
-        rowbase += m;
-        wg_sync();
       }
-    }
-    // T = Mu^{-1} Du^T  (ns x npU)
-    for (int e = threadIdx.x; e < ns * npU; e += blockDim.x) {
-      const int s = e / npU, r = e % npU;
-      T[s * npU + r] = lv.level0 ? Du[r * ns + s] / Mu[s] : Du[r * ns + s];
-    }
-    wg_sync();
-    if (!lv.level0) {
+      // T = Mu^{-1} Du^T  (ns x npU)
+      for (int e = threadIdx.x; e < ns * npU; e += blockDim.x) {
+        const int s = e / npU, r = e % npU;
+        T[s * npU + r] = Du[r * ns + s];
+      }
+      wg_sync();
       if (!wg_chol(Mu, ns, ns, &flag)) {
         if (threadIdx.x == 0) { atomicAdd(bad, 1); bad[1] = 1; bad[2] = F; bad[3] = flag; }
         continue;
       }
       wg_chol_solve(Mu, ns, ns, T, npU, npU);
+      // L = Du T
+      wg_gemm(Du, ns, false, T, npU, false, L, npU, npU, npU, ns);
     }
-    // L = Du T (+ rho u u^T on interior interfaces: pure Neumann union)
-    wg_gemm(Du, ns, false, T, npU, false, L, npU, npU, npU, ns);
-    // right-hand side -f_F and the regularisation
+    // right-hand side -f_F and the regularisation rho u u^T on interior
+    // interfaces (pure Neumann union)
     double na = 0.0, nb = 0.0;
     for (int r = 0; r < npA; ++r) { const double o = ones[pl.pd_list[pl.pd_ptr[A] + r]]; na += o * o; }
     for (int r = 0; r < npB; ++r) { const double o = ones[pl.pd_list[pl.pd_ptr[B] + r]]; nb += o * o; }
@@ -160,11 +218,18 @@ __global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, 
       continue;
     }
     wg_chol_solve(L, npU, npU, y, 1, 1);
-    // sigma = -T p, restricted to F
+    // sigma = -M^{-1} D^T p, restricted to F
     for (int q = threadIdx.x; q < nF; q += blockDim.x) {
       const int s = nIA + nIB + q;
       double acc = 0.0;
-      for (int r = 0; r < npU; ++r) acc += T[s * npU + r] * y[r];
+      if (lv.level0) {
+        const double* inc = Du;
+        acc = inc[ns + s] * y[(int)inc[s]];
+        if (inc[2 * ns + s] >= 0.0) acc += inc[3 * ns + s] * y[(int)inc[2 * ns + s]];
+        acc /= Mu[s];
+      } else {
+        for (int r = 0; r < npU; ++r) acc += T[s * npU + r] * y[r];
+      }
       trace[pl.fgrp_list[pl.fgrp_ptr[F] + q]] = -acc;
     }
     wg_sync();
@@ -294,8 +359,28 @@ __global__ void __launch_bounds__(kBlock) k_agg_setup(LocalView lv, PlanView pl,
       }
       wg_chol_solve(Ci, nI, nI, T, npA, npA);
     }
-    // L = D_int T
-    wg_gemm(DA, nd, false, T, npA, false, L, npA, npA, npA, nI);
+    // L = D_int T; on level 0 from the nonzeros only (each row of T holds
+    // the two incidences of its flux), row r from the fluxes of its cell
+    if (lv.level0) {
+      for (int r = threadIdx.x; r < npA; r += blockDim.x) {
+        const int ci = pl.cell_ptr[A] + r;
+        const int k = lv_k(lv, pl.cell_list[ci]);
+        const int* sm = pl.smap + pl.smap_ptr[ci];
+        double* Lr = L + (size_t)r * npA;
+        for (int q2 = 0; q2 < npA; ++q2) Lr[q2] = 0.0;
+        for (int i = 0; i < k; ++i) {
+          const int sf = sm[i];
+          if (sf >= nI) continue;
+          const double d = DA[r * nd + sf];
+          const double* Ts = T + (size_t)sf * npA;
+          for (int q2 = 0; q2 < npA; ++q2)
+            if (Ts[q2] != 0.0) Lr[q2] += d * Ts[q2];
+        }
+      }
+      wg_sync();
+    } else {
+      wg_gemm(DA, nd, false, T, npA, false, L, npA, npA, npA, nI);
+    }
     // symmetrise
     for (int e = threadIdx.x; e < npA * npA; e += blockDim.x) {
       const int i = e / npA, j = e % npA;
@@ -834,8 +919,8 @@ void setup_coarse_levels(Hierarchy& h) {
       }
       ScratchA sa;
       sa.mu = l == 0 ? mx_ns : mx_ns * mx_ns;
-      sa.du = mx_npU * mx_ns;
-      sa.t = mx_ns * mx_npU;
+      sa.du = l == 0 ? 4 * mx_ns : mx_npU * mx_ns;   // level 0: the incidence pairs of the fluxes
+      sa.t = l == 0 ? 0 : mx_ns * mx_npU;
       sa.l = mx_npU * mx_npU;
       sa.y = mx_npU;
       sa.total = sa.mu + sa.du + sa.t + sa.l + sa.y + 8;
