@@ -456,6 +456,26 @@ def served_problem(seed: int, n_min: int = 32 ** 2, n_max: int = 64 ** 3, dims=(
                    n_levels=levels, dp_cap_c=5.0)
 
 
+def _c4_shape(rng):
+    """Aggregate edge a ~ U{4..8}, then the three box edges from U{16..96},
+    an edge drawn again when the box rule would merge its remainder into a
+    block of more than 8 cells."""
+    a = int(rng.integers(4, 9))
+    shape = []
+    while len(shape) < 3:
+        n = int(rng.integers(16, 97))
+        r = n % a
+        if 0 < r and 2 * r < a and a + r > 8:
+            continue
+        shape.append(n)
+    return tuple(shape), a
+
+
+def c4_shape(i: int, seed: int = 4):
+    """(shape, a) of instance i of the batched workload, without its mesh."""
+    return _c4_shape(np.random.default_rng([seed, i]))
+
+
 def c4_problem(i: int, seed: int = 4) -> Problem:
     """Instance i of the batched workload (512 instances): a box of
     n_x x n_y x n_z cubic cells with every edge drawn from U{16..96}, ln k =
@@ -471,15 +491,7 @@ def c4_problem(i: int, seed: int = 4) -> Problem:
     cells (a = 7 or 8 with 0 < n mod a < a/2) is drawn again, so that no
     aggregate exceeds 512 cells."""
     rng = np.random.default_rng([seed, i])
-    a = int(rng.integers(4, 9))
-    shape = []
-    while len(shape) < 3:
-        n = int(rng.integers(16, 97))
-        r = n % a
-        if 0 < r and 2 * r < a and a + r > 8:
-            continue
-        shape.append(n)
-    shape = tuple(shape)
+    shape, a = _c4_shape(rng)
     h = 1.0 / max(shape)
     k = np.exp(2.0 * _flat(gaussian_field(shape, 5.0, rng)))
     mesh = cartesian_mesh(shape, (h, h, h), k, dirichlet=((0, 0),))
