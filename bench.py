@@ -212,7 +212,8 @@ def c1_leg(torch, pk, c1_problem, steps=200):
 def unstructured_leg(torch, pk, steps=3):
     """The unstructured configuration at its full size: the bounded Voronoi
     mesh of 2,000,000 seeded points, ln k = 3G with correlation length 0.01,
-    kappa = exp(2p), greedy aggregates of about 64 cells on 2 levels,
+    kappa = exp(2p), greedy aggregates of about 64 cells, then of about 16
+    coarse cells (3 levels),
     eigenvectors per aggregate by the threshold 0.1 clamped to [2, 6],
     mixed-precision FAS-Newton to rtol 1e-8 beside the FP64 solve on the same
     hierarchy (which the parity tests tie to the oracle); the source rate is
@@ -227,7 +228,7 @@ def unstructured_leg(torch, pk, steps=3):
     log("unstructured: hierarchy (greedy aggregates, threshold counts)")
     t0 = time.perf_counter()
     H = pk.Hierarchy(prob.mesh, prob.n_levels, m=prob.m, agg_kind=N.SPFAS_AGG_GREEDY, greedy_size=prob.greedy_size,
-                     eig_threshold=prob.eig_threshold, m_min=prob.m_min)
+                     eig_threshold=prob.eig_threshold, m_min=prob.m_min, greedy_size_coarse=prob.greedy_size_coarse)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
     counts = []
@@ -238,7 +239,7 @@ def unstructured_leg(torch, pk, steps=3):
     base = dict(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=1e-5, lin_max_it=400,
                 lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1, amg_reuse=-1, lin_max_it_coarse=10,
                 coarsest_atol=1e-10, dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
-    out = {"workload": "voronoi_2d_2000000, ln k = 3G, kappa = exp(2p), greedy aggregates of 64, 2 levels, "
+    out = {"workload": "voronoi_2d_2000000, ln k = 3G, kappa = exp(2p), greedy aggregates of 64 then 16, 3 levels, "
                        "eigenvector counts by threshold 0.1 in [2, 6], FAS-Newton rtol 1e-8",
            "cells": prob.mesh.n_cells, "mesh_s": t_mesh, "setup_s": t_setup, "eig_counts_per_level": counts}
     res = {}

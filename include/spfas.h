@@ -139,6 +139,9 @@ typedef enum {
  *             aggregate below greedy_size/2 cells, in ascending id, joins the
  *             neighbouring aggregate it shares the most interior faces with
  *             (ties: lower id); ids are compacted in ascending order
+ *   greedy_size_coarse  GREEDY: the target on levels 1 and up (0: greedy_size);
+ *             coarse cells carry several unknowns each, so a smaller target
+ *             keeps the local problems of deeper levels small
  *   eig_threshold  > 0: the number of eigenvectors of each aggregate is
  *             the number of eigenvalues of its local problem (eq.
  *             local-eigenvalue-problem, lambda_1 = 0 included) up to
@@ -167,6 +170,7 @@ typedef struct {
   double eig_threshold;
   int32_t m_min;
   int32_t m_f;
+  int32_t greedy_size_coarse;
 } spfas_coarsen_opts;
 
 /*

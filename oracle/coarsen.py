@@ -492,9 +492,11 @@ class Hierarchy:
 
 
 def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, user_agg=None,
-                    eig_threshold=None, m_min=None) -> Hierarchy:
+                    eig_threshold=None, m_min=None, greedy_size_coarse=None) -> Hierarchy:
     """Levels and transfers of ``prob``.  Aggregation: boxes on the level
-    lattice by default; ``greedy_size`` > 0 selects ``greedy_aggregate``;
+    lattice by default; ``greedy_size`` > 0 selects ``greedy_aggregate``
+    (with the target ``greedy_size_coarse`` on levels 1 and up when that is
+    > 0);
     ``user_agg`` (one array per coarsened level) gives it explicitly.
     ``eig_threshold`` > 0 selects the eigenvalue-threshold count of
     ``eig_count`` (m is then the upper clamp).  Defaults come from the
@@ -505,6 +507,8 @@ def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, use
     m = prob.m if m is None else m
     if greedy_size is None:
         greedy_size = getattr(prob, "greedy_size", 0)
+    if greedy_size_coarse is None:
+        greedy_size_coarse = getattr(prob, "greedy_size_coarse", 0)
     if eig_threshold is None:
         eig_threshold = getattr(prob, "eig_threshold", 0.0)
     if m_min is None:
@@ -516,7 +520,8 @@ def build_hierarchy(prob, n_levels=None, box=None, m=None, greedy_size=None, use
         if user_agg is not None:
             agg, cshape = np.asarray(user_agg[l], dtype=np.int64), ()
         elif greedy_size:
-            agg, cshape = greedy_aggregate(cur, greedy_size), ()
+            target = greedy_size_coarse if l > 0 and greedy_size_coarse > 0 else greedy_size
+            agg, cshape = greedy_aggregate(cur, target), ()
         else:
             if cur.lattice_shape is None:
                 raise ValueError("box aggregation needs a Cartesian lattice")

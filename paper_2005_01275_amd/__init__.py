@@ -94,12 +94,13 @@ class Hierarchy:
 
     def __init__(self, mesh, n_levels: int, box=(), m: int = 1, host_only: bool = False, stream=None,
                  agg_kind: int = N.SPFAS_AGG_BOX, user_agg=None, greedy_size: int = 0, allocator=None,
-                 eig_threshold: float = 0.0, m_min: int = 2, m_f: int = 1):
+                 eig_threshold: float = 0.0, m_min: int = 2, m_f: int = 1, greedy_size_coarse: int = 0):
         """allocator: None (hipMalloc) or "torch" (PyTorch's caching
         allocator owns the hierarchy's device memory).  user_agg: for
         agg_kind USER, the aggregation of every coarsened level,
         concatenated.  eig_threshold > 0: eigenvectors per aggregate by the
-        eigenvalue threshold, between m_min and m."""
+        eigenvalue threshold, between m_min and m.  greedy_size_coarse:
+        the greedy target on levels 1 and up (0: greedy_size)."""
         L = N.lib()
         self._keep = []
         ms, arrays = _mesh_struct(mesh)
@@ -113,7 +114,8 @@ class Hierarchy:
                                   agg_kind=agg_kind,
                                   user_agg=ua.ctypes.data_as(C.POINTER(C.c_int32)) if ua is not None else None,
                                   user_agg_len=0 if ua is None else ua.size, greedy_size=greedy_size,
-                                  eig_threshold=float(eig_threshold), m_min=int(m_min), m_f=int(m_f))
+                                  eig_threshold=float(eig_threshold), m_min=int(m_min), m_f=int(m_f),
+                                  greedy_size_coarse=int(greedy_size_coarse))
         if allocator not in (None, "torch"):
             raise ValueError("allocator must be None or 'torch'")
         alloc = C.byref(N.TORCH_ALLOCATOR) if allocator == "torch" else None

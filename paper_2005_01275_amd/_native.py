@@ -52,7 +52,7 @@ class spfas_coarsen_opts(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("box", C.c_int32 * 3), ("m", C.c_int32), ("host_only", C.c_int32),
                 ("agg_kind", C.c_int32), ("user_agg", _ip), ("user_agg_len", C.c_int64),
                 ("greedy_size", C.c_int32), ("eig_threshold", C.c_double), ("m_min", C.c_int32),
-                ("m_f", C.c_int32)]
+                ("m_f", C.c_int32), ("greedy_size_coarse", C.c_int32)]
 
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)

@@ -299,7 +299,7 @@ void Hierarchy::aggregate_level(int l) {
     require(user_off[l] + topo[l].n_cells <= o.user_agg_len, "user_agg is shorter than the cells of a coarsened level");
     user_aggregate(topo[l], o.user_agg + user_off[l], topo[l].n_cells);
   } else if (o.agg_kind == SPFAS_AGG_GREEDY) {
-    greedy_aggregate(topo[l], o.greedy_size);
+    greedy_aggregate(topo[l], l > 0 && o.greedy_size_coarse > 0 ? o.greedy_size_coarse : o.greedy_size);
   } else {
     box_aggregate(topo[l], o.box);
   }

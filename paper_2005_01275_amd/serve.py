@@ -40,14 +40,15 @@ class Server:
         self._models = {}
         self._pending = {}
 
-    def add_model(self, mesh, n_levels, box=(), m=1, agg_kind=N.SPFAS_AGG_BOX, greedy_size=0, user_agg=None):
+    def add_model(self, mesh, n_levels, box=(), m=1, agg_kind=N.SPFAS_AGG_BOX, greedy_size=0, user_agg=None,
+                  greedy_size_coarse=0):
         ms, keep = _mesh_struct(mesh)
         ua = None if user_agg is None else np.ascontiguousarray(user_agg, dtype=np.int32)
         box = tuple(box) + (1,) * (3 - len(box))
         co = N.spfas_coarsen_opts(n_levels=n_levels, box=(C.c_int32 * 3)(*box), m=m, host_only=0, agg_kind=agg_kind,
                                   user_agg=ua.ctypes.data_as(C.POINTER(C.c_int32)) if ua is not None else None,
                                   user_agg_len=0 if ua is None else ua.size, greedy_size=greedy_size,
-                                  eig_threshold=0.0, m_min=1)
+                                  eig_threshold=0.0, m_min=1, greedy_size_coarse=greedy_size_coarse)
         mid = C.c_int64()
         _check(self._L.spfas_server_add_model(self.s, C.byref(ms), C.byref(co), C.byref(mid)))
         self._models[mid.value] = (mesh.n_cells, mesh.n_faces)

@@ -62,6 +62,7 @@ class Problem:
     n_levels: int = 2
     dp_cap_c: float = 5.0          # cap constant c: max |dp| <= ln(c)/alpha
     greedy_size: int = 0           # > 0: greedy aggregates of about this many cells (unstructured meshes)
+    greedy_size_coarse: int = 0    # > 0: the greedy target on levels 1 and up
     # > 0: eigenvectors per aggregate by the eigenvalue threshold (lambda <=
     # eig_threshold * lambda_max), clamped to [m_min, m]
     eig_threshold: float = 0.0
@@ -393,7 +394,8 @@ def bilinear_sample(field: np.ndarray, xy: np.ndarray) -> np.ndarray:
 
 def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, corr_len: float = 0.01,
                     alpha: float = 2.0, lattice: int = 0, rate: Optional[float] = None, n_levels: int = 3,
-                    greedy_size: int = 64, m: int = 3, eig_threshold: float = 0.0, m_min: int = 2) -> Problem:
+                    greedy_size: int = 64, m: int = 3, eig_threshold: float = 0.0, m_min: int = 2,
+                    greedy_size_coarse: int = 0) -> Problem:
     """Unstructured 2-D problem on the Voronoi mesh of ``n_points`` seeded
     uniform points in the unit square: ln k = sigma G, G a standardised
     Gaussian random field of correlation length ``corr_len`` (in units of
@@ -424,7 +426,8 @@ def voronoi_problem(n_points: int = 2000, seed: int = 0, sigma: float = 3.0, cor
     prob = Problem(mesh=mesh, alpha=alpha, source=src, g_dirichlet=np.zeros(mesh.n_faces),
                    g_neumann=np.zeros(mesh.n_faces), name=f"voronoi_2d_{n_points}", box=(), m=m,
                    n_levels=n_levels, dp_cap_c=5.0)
-    return dataclasses.replace(prob, greedy_size=greedy_size, eig_threshold=eig_threshold, m_min=m_min)
+    return dataclasses.replace(prob, greedy_size=greedy_size, eig_threshold=eig_threshold, m_min=m_min,
+                               greedy_size_coarse=greedy_size_coarse)
 
 
 def served_problem(seed: int, n_min: int = 32 ** 2, n_max: int = 64 ** 3, dims=(2, 3), sigma: float = 2.0,
@@ -521,13 +524,14 @@ def c3_problem(rate: Optional[float] = None) -> Problem:
     """The unstructured workload: the Voronoi mesh of 2,000,000 seeded uniform
     points in the unit square (seed 3), ln k = 3G with correlation length
     0.01, kappa = exp(2p), p = 0 on x = 0, a source pair near (0.05, 0.05)
-    and (0.95, 0.95); greedy aggregates of about 64 cells on 2 levels, 2 to 6
-    eigenvectors per aggregate by the threshold 0.1."""
+    and (0.95, 0.95); greedy aggregates of about 64 cells, then of about 16
+    coarse cells (3 levels), 2 to 6 eigenvectors per aggregate by the
+    threshold 0.1."""
     q = C3_RATE if rate is None else rate
     if q is None:
         raise ValueError("C3_RATE is not calibrated")
-    return voronoi_problem(n_points=2000000, seed=3, sigma=3.0, corr_len=0.01, alpha=2.0, rate=q, n_levels=2,
-                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2)
+    return voronoi_problem(n_points=2000000, seed=3, sigma=3.0, corr_len=0.01, alpha=2.0, rate=q, n_levels=3,
+                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2, greedy_size_coarse=16)
 
 
 def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=None, m=2,

@@ -34,6 +34,9 @@ def voronoi(**kw):
 CASES = {
     "voronoi": lambda: (voronoi(n_points=2000, seed=1, n_levels=3, m=3, alpha=2.0, sigma=1.0), 64),
     "voronoi-m2": lambda: (voronoi(n_points=1200, seed=4, n_levels=2, m=2, alpha=1.0, sigma=1.0), 32),
+    # a smaller greedy target on the coarse levels (coarse cells of 3 unknowns each)
+    "voronoi-coarse16": lambda: (voronoi(n_points=3000, seed=6, n_levels=3, m=3, alpha=2.0, sigma=1.0,
+                                         greedy_size_coarse=16), 64),
     "cart-greedy": lambda: (small_problem((12, 10), seed=2, m=2, n_levels=3, permute=True, alpha=1.5,
                                           src_scale=2.0), 8),
 }
@@ -44,7 +47,8 @@ ROOT_CASES = dict(CASES, **{
 def gpu_hierarchy(prob, target, **kw):
     import paper_2005_01275_amd as pk
     from paper_2005_01275_amd import _native as N
-    return pk.Hierarchy(prob.mesh, prob.n_levels, m=prob.m, agg_kind=N.SPFAS_AGG_GREEDY, greedy_size=target, **kw)
+    return pk.Hierarchy(prob.mesh, prob.n_levels, m=prob.m, agg_kind=N.SPFAS_AGG_GREEDY, greedy_size=target,
+                        greedy_size_coarse=prob.greedy_size_coarse, **kw)
 
 
 @pytest.mark.parametrize("case", list(CASES))
