@@ -664,6 +664,23 @@ __global__ void __launch_bounds__(kBlock) k_fill_cmv(CycView M, const int* __res
   for (int e = M.ptr[i] + g; e < M.ptr[i + 1]; e += kVecG) val[e] = cm_value(src[e], appidx, pval, apv, wi);
 }
 
+// G = P^T (I - A diag(w)) in FP16, one thread per entry (CSR order):
+// G_cj = P_jc - w_j sum_i P_ic a_ij over the entry's product list
+__global__ void __launch_bounds__(kBlock) k_fill_g(int ne, const int* __restrict__ col, const int* __restrict__ rt,
+                                                   const int* __restrict__ lptr, const int* __restrict__ lp,
+                                                   const int* __restrict__ la, CsrView A,
+                                                   const double* __restrict__ pval, const double* __restrict__ w,
+                                                   cyc_t* __restrict__ val) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne) return;
+  double s = 0.0;
+  for (int t = lptr[e]; t < lptr[e + 1]; ++t) {
+    const int c = la[t];
+    s += pval[lp[t]] * ((c & 1) ? A.val[c >> 1] : A.diag[c >> 1]);
+  }
+  val[e] = to_cyc((rt[e] >= 0 ? pval[rt[e]] : 0.0) - w[col[e]] * s);
+}
+
 // R = P^T in FP16 (filled once at setup), one thread per stored slot
 __global__ void __launch_bounds__(kBlock) k_fill_rm(int ne, const int* __restrict__ src,
                                                     const double* __restrict__ pval, cyc_t* __restrict__ val) {
@@ -718,6 +735,30 @@ __global__ void __launch_bounds__(kBlock) k_cycv(CycView M, const CycX<Op, TB>* 
     if constexpr (Op == 0) y[i] = (TY)((double)b[i] - acc);
     else if constexpr (Op == 1) y[i] = (TY)acc;
     else y[i] = (TY)(w[i] * ((double)b[i] + (double)r[i]) + acc);
+  }
+}
+
+// The down leg of a small level in one launch: rows [0, n) y = b - M b
+// (pre-sweep from zero + residual, M = A diag(w)), rows [n, n + nc)
+// yc = G b with G = P^T (I - A diag(w)), the restriction of that residual.
+template <int LG>
+__global__ void __launch_bounds__(kBlock) k_cycv_down(CycView M, CycView G, const float* __restrict__ b,
+                                                      float* __restrict__ y, float* __restrict__ yc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t / LG, g = t % LG;
+  if (i >= M.n + G.n) return;   // the whole group leaves together
+  const bool fine = i < M.n;
+  const int row = fine ? i : i - M.n;
+  const int* ptr = fine ? M.ptr : G.ptr;
+  const int* col = fine ? M.col : G.col;
+  const cyc_t* val = fine ? M.val : G.val;
+  double acc = 0.0;
+  for (int e = ptr[row] + g; e < ptr[row + 1]; e += LG) acc += (double)val[e] * (double)b[col[e]];
+#pragma unroll
+  for (int o = LG / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, LG);
+  if (g == 0) {
+    if (fine) y[row] = (float)((double)b[row] - acc);
+    else yc[row] = (float)acc;
   }
 }
 
@@ -1049,6 +1090,62 @@ void build_cyc(int n, const std::vector<int>& ptr, const std::vector<int>& col, 
 
 CycView cyc_view(const CycMat& M) { return CycView{M.n, M.ptr.p, M.col.p, M.val.p}; }
 
+// Pattern and product lists of G = P^T (I - A diag(w)) for the fused down
+// leg: row c of G collects, for every fine row i of P^T's row c (P entry
+// pe), the P^T term at column i and the products pe x a_ij over row i of A
+// (diagonal first, then the off-diagonal entries in CSR order); columns
+// ascending, each entry's products in that traversal order.
+void build_fused(const HostCsr& A, const ClassicalLevel& CL, AmgLevel& F, hipStream_t s) {
+  const int nc = CL.nc;
+  std::vector<int> gptr(nc + 1, 0), gcol, grt, glptr(1, 0), glp, gla, src;
+  std::vector<int> slot(A.n, -1);
+  std::vector<int> cols, rt;
+  std::vector<std::vector<std::pair<int, int>>> prods;
+  for (int c = 0; c < nc; ++c) {
+    cols.clear();
+    rt.clear();
+    prods.clear();
+    auto at = [&](int j) -> int {
+      if (slot[j] < 0) {
+        slot[j] = (int)cols.size();
+        cols.push_back(j);
+        rt.push_back(-1);
+        prods.emplace_back();
+      }
+      return slot[j];
+    };
+    for (int t = CL.rptr[c]; t < CL.rptr[c + 1]; ++t) {
+      const int i = CL.rcol[t], pe = CL.rsrc[t];
+      rt[at(i)] = pe;
+      prods[at(i)].emplace_back(pe, dia_code(i));
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) prods[at(A.col[k])].emplace_back(pe, off_code(k));
+    }
+    std::vector<int> order(cols.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return cols[a] < cols[b]; });
+    for (int q : order) {
+      gcol.push_back(cols[q]);
+      grt.push_back(rt[q]);
+      for (const auto& pr : prods[q]) {
+        glp.push_back(pr.first);
+        gla.push_back(pr.second);
+      }
+      glptr.push_back((int)glp.size());
+    }
+    for (int j : cols) slot[j] = -1;
+    gptr[c + 1] = (int)gcol.size();
+  }
+  src.resize(gcol.size());
+  std::iota(src.begin(), src.end(), 0);
+  build_cyc(nc, gptr, gcol, src, F.gm, s);
+  require(!F.gm.sell, "fused restriction operator on SELL");
+  F.grt.upload(grt, s);
+  F.glptr.upload(glptr, s);
+  F.glp.upload(glp, s);
+  F.gla.upload(gla, s);
+  F.fused = true;
+}
+
 // device storage of a coarse level's DIA+CSR matrix (values filled by numeric())
 void coarse_storage(AmgLevel& Cl, const HostCsr& C, hipStream_t s) {
   Cl.n = C.n;
@@ -1111,6 +1208,7 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bo
       build_cyc(H.n, p, c, src, F.aw, s);
     }
     build_cyc(CL.nc, CL.rptr, CL.rcol, CL.rsrc, F.rm, s);
+    if (lv.size() > 1 && H.n <= kFuseRows && H.n < kSellRows) build_fused(H, CL, F, s);
     {
       std::vector<int> src(CL.apcol.size());
       std::iota(src.begin(), src.end(), 0);
@@ -1375,6 +1473,13 @@ void Amg::numeric_classical(hipStream_t s) {
     hipLaunchKernelGGL(k_fill_aw, dim3(grid_for(F.aw.src.n, kBlock)), dim3(kBlock), 0, s, (int)F.aw.src.n,
                        F.aw.col.p, F.aw.src.p, F.view, F.invd.p, F.aw.val.p);
     LAUNCHCHECK();
+    if (F.fused) {
+      const int ne = (int)F.gm.nnz;
+      if (ne > 0)
+        hipLaunchKernelGGL(k_fill_g, dim3(grid_for(ne, kBlock)), dim3(kBlock), 0, s, ne, F.gm.col.p, F.grt.p,
+                           F.glptr.p, F.glp.p, F.gla.p, F.view, F.pval.p, F.invd.p, F.gm.val.p);
+      LAUNCHCHECK();
+    }
     if (F.cm.sell)
       hipLaunchKernelGGL(k_fill_cm, dim3(grid_for(F.n, kBlock)), dim3(kBlock), 0, s, cyc_view(F.cm), F.cm.src.p,
                          F.appidx.p, F.pval.p, F.apv.p, F.invd.p, F.cm.val.p);
@@ -1425,6 +1530,20 @@ static void launch_cyc(const CycMat& M, bool finest, const CycX<Op, TB>* x, cons
   }
 }
 
+// The fused down leg of a small level (k_cycv_down), with the lane group of
+// the longer rows of the two operators.
+static void launch_cyc_down(const CycMat& M, const CycMat& G, const float* b, float* y, float* yc, hipStream_t s) {
+  require(!M.sell && !G.sell, "fused down leg on SELL operators");
+  const int lanes = std::max(M.lanes, G.lanes);
+  const unsigned g = grid_for((size_t)(M.n + G.n) * lanes, kBlock);
+  const CycView vm = cyc_view(M), vg = cyc_view(G);
+  switch (lanes) {
+    case 16: hipLaunchKernelGGL(k_cycv_down<16>, dim3(g), dim3(kBlock), 0, s, vm, vg, b, y, yc); break;
+    case 32: hipLaunchKernelGGL(k_cycv_down<32>, dim3(g), dim3(kBlock), 0, s, vm, vg, b, y, yc); break;
+    default: hipLaunchKernelGGL(k_cycv_down<8>, dim3(g), dim3(kBlock), 0, s, vm, vg, b, y, yc); break;
+  }
+}
+
 // One V(1,1) cycle of the classical hierarchy, three kernels per level:
 // down [pre-sweep + residual] [restriction], up [prolongation + post-sweep].
 // FP64 b and x on level 0, FP32 vectors on the levels below and for the
@@ -1445,6 +1564,12 @@ void Amg::apply_classical(const T* b, T* x, hipStream_t s) {
     AmgLevel& C = lv[k + 1];
     timed(lvprof.get(), 3 * k, 0.0, s, [&] {
       const double n = (double)F.n;
+      if (F.fused) {   // residual and its restriction in one launch (k >= 1)
+        timed(hook.prof, hook.tail_down_id, 6.0 * (double)(F.aw.nnz + F.gm.nnz) + 8.0 * n + 4.0 * C.n, s, [&] {
+          launch_cyc_down(F.aw, F.gm, F.b32.p, F.r32.p, C.b32.p, s);
+        });
+        return;
+      }
       // r = b - A diag(w) b: b read (sizeof(T) bytes on level 0, 4 below), r written in FP32
       const double bsz = k == 0 ? (double)sizeof(T) : 4.0;
       timed(hook.prof, k == 0 ? hook.down_id : hook.tail_down_id, 6.0 * (double)F.aw.nnz + (bsz + 4.0) * n, s, [&] {

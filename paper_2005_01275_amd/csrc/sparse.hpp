@@ -46,6 +46,10 @@ constexpr int kVecRows = 150000;
 // On the 60x220x85 hierarchy the 207,000-row level pads SELL-64 to about
 // twice its entries and runs faster as CSR.
 constexpr int kSellRows = 250000;
+// Classical levels with at most this many rows (latency-bound launches)
+// compute the restricted residual in the same launch as the residual, from
+// G = P^T (I - A diag(w)) applied to the level's right-hand side.
+constexpr int kFuseRows = 65536;
 
 struct CsrView {
   int n = 0;
@@ -145,6 +149,12 @@ struct AmgLevel {
   DVec<double> apv;                   // A P values
   DVec<int> clptr, clr, clq;          // next level's off entries then diagonal -> (P entry, A P entry)
   CycMat aw, rm, cm;                  // cycle operators A diag(w), R = P^T, P - diag(w) A P
+  // fused down leg (n <= kFuseRows): G = P^T (I - A diag(w)) in FP16 and its
+  // products: per entry the P entry of its P^T term (-1: none) and the list
+  // of (P entry, A entry code) of its (P^T A) sum
+  bool fused = false;
+  CycMat gm;
+  DVec<int> grt, glptr, glp, gla;
   DVec<double> x, b, r, t;            // work vectors (x, b, r: aggregation AMG)
   DVec<float> x32, b32, r32;          // classical cycle: FP32 vectors inside the cycle
 };
