@@ -212,8 +212,7 @@ def c1_leg(torch, pk, c1_problem, steps=200):
 def unstructured_leg(torch, pk, steps=3):
     """The unstructured configuration at its full size: the bounded Voronoi
     mesh of 2,000,000 seeded points, ln k = 3G with correlation length 0.01,
-    kappa = exp(2p), greedy aggregates of about 64 cells, then of about 16
-    coarse cells (3 levels),
+    kappa = exp(2p), greedy aggregates of about 64 cells on 2 levels,
     eigenvectors per aggregate by the threshold 0.1 clamped to [2, 6],
     mixed-precision FAS-Newton to rtol 1e-8 beside the FP64 solve on the same
     hierarchy (which the parity tests tie to the oracle); the source rate is
@@ -239,7 +238,7 @@ def unstructured_leg(torch, pk, steps=3):
     base = dict(smoother=pk.SPFAS_NEWTON, rtol=1e-8, atol=0.0, max_it=50, lin_rtol=1e-5, lin_max_it=400,
                 lin_rtol_coarse=1e-2, lin_target=0.03, newton_pcg=1, amg_reuse=-1, lin_max_it_coarse=10,
                 coarsest_atol=1e-10, dp_cap=math.log(prob.dp_cap_c) / prob.alpha)
-    out = {"workload": "voronoi_2d_2000000, ln k = 3G, kappa = exp(2p), greedy aggregates of 64 then 16, 3 levels, "
+    out = {"workload": "voronoi_2d_2000000, ln k = 3G, kappa = exp(2p), greedy aggregates of 64, 2 levels, "
                        "eigenvector counts by threshold 0.1 in [2, 6], FAS-Newton rtol 1e-8",
            "cells": prob.mesh.n_cells, "mesh_s": t_mesh, "setup_s": t_setup, "eig_counts_per_level": counts}
     res = {}

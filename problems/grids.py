@@ -524,14 +524,13 @@ def c3_problem(rate: Optional[float] = None) -> Problem:
     """The unstructured workload: the Voronoi mesh of 2,000,000 seeded uniform
     points in the unit square (seed 3), ln k = 3G with correlation length
     0.01, kappa = exp(2p), p = 0 on x = 0, a source pair near (0.05, 0.05)
-    and (0.95, 0.95); greedy aggregates of about 64 cells, then of about 16
-    coarse cells (3 levels), 2 to 6 eigenvectors per aggregate by the
-    threshold 0.1."""
+    and (0.95, 0.95); greedy aggregates of about 64 cells on 2 levels, 2 to 6
+    eigenvectors per aggregate by the threshold 0.1."""
     q = C3_RATE if rate is None else rate
     if q is None:
         raise ValueError("C3_RATE is not calibrated")
-    return voronoi_problem(n_points=2000000, seed=3, sigma=3.0, corr_len=0.01, alpha=2.0, rate=q, n_levels=3,
-                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2, greedy_size_coarse=16)
+    return voronoi_problem(n_points=2000000, seed=3, sigma=3.0, corr_len=0.01, alpha=2.0, rate=q, n_levels=2,
+                           greedy_size=64, m=6, eig_threshold=0.1, m_min=2)
 
 
 def small_problem(shape, seed=0, sigma=1.0, alpha=1.0, dirichlet=((0, 0),), box=None, m=2,
