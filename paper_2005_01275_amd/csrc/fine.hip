@@ -260,15 +260,16 @@ int launch_fine_resid(const FineView& v, const double* x, const double* dx, doub
 // contributes u_K = E_K / m_j, u_L = E_L / m_j and v = sigma_j - r_j / m_j
 // with the orientation d = -1 (cell K) or +1 (cell L): diag += d u_own,
 // off = d u_other, rhs += d v.
-// One pass over the cells, a group of kLinG lanes per cell and one
-// incidence per lane: each lane evaluates the coefficients of its face
+// One pass over the cells, a group of kLinG lanes per cell, each lane
+// taking every kLinG-th incidence (4 lanes measured 15 % faster than one
+// lane per incidence with 8): each lane evaluates the coefficients of a face
 // (a face's m, E_K, E_L and r are computed by both of its cells instead of
 // being stored and gathered back) and writes its entry of the cell's row
 // of S straight into the layout the Krylov products read: the SELL-64 slots
 // of the level-0 matrix (diagonal in entry 0, the incidences in list order
 // in entries 1, 2, ...), or the DIA+CSR arrays when there is no SELL copy.
 // The diagonal and the right-hand side are group sums (fixed order).
-constexpr int kLinG = 8;
+constexpr int kLinG = 4;
 
 // TV: storage of the SELL values and of the right-hand side (FP64, or FP32
 // in mixed precision); everything is computed in FP64.
