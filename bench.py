@@ -430,22 +430,22 @@ def c4_leg(pk, n_problems=512, slots=4, window=64):
     t0 = time.perf_counter()
     with Server(n_slots=slots) as S:
         def finish_one():
-            i, n, t = fas_q.popleft()
+            i, n, setup_ms, t = fas_q.popleft()
             try:
                 _, _, st, info = S.wait(t)
-                done.append((i, n, st["converged"], st["iterations"], info["setup_ms"], info["solve_ms"]))
+                done.append((i, n, st["converged"], st["iterations"], setup_ms + info["setup_ms"], info["solve_ms"]))
             except ServerError as e:
                 failed.append((i, str(e)))
 
         def scale_one():
             i, mid, pr, t = lin_q.popleft()
             try:
-                p_lin, _, _, _ = S.wait(t)
+                p_lin, _, _, info = S.wait(t)
             except ServerError as e:
                 failed.append((i, str(e)))
                 return
             pr = dataclasses.replace(pr, source=pr.source * (0.25 / float(np.abs(p_lin).max())))
-            fas_q.append((i, pr.mesh.n_cells, S.submit(mid, pr, o, FAS)))
+            fas_q.append((i, pr.mesh.n_cells, info["setup_ms"], S.submit(mid, pr, o, FAS)))
 
         for i in range(n_problems):
             pr = c4_problem(i)
