@@ -406,19 +406,17 @@ def batched_leg(pk, n_problems, seed=11):
             "converged": sum(int(r[2]["converged"]) for r in res), "counters": cnt}
 
 
-def c4_leg(pk, n_problems=512, slots=4, window=64, gen_workers=8):
+def c4_leg(pk, n_problems=512, slots=4, window=64):
     """The batched configuration at its full size: 512 independent boxes of
-    16..96 cells per edge (about 1.0e8 cells), each with its own k field and
+    16..96 cells per edge (about 9.5e7 cells), each with its own k field and
     box aggregates of 4..8 cells per edge.  The instances stream through the
-    native runtime: each is generated on the host (by a pool of
-    `gen_workers` processes, in instance order), registered, solved linearly
-    (alpha = 0) to fix its source scale (max |p| = 0.25), then solved by
-    mixed-precision FAS-Newton to rtol 1e-8; at most `window` instances are
-    in the pipeline, and cached hierarchies are evicted when the
-    device-memory budget is reached.  The wall time covers generation,
+    native runtime: each is generated on the host, registered, solved
+    linearly (alpha = 0) to fix its source scale (max |p| = 0.25), then
+    solved by mixed-precision FAS-Newton to rtol 1e-8; at most `window`
+    instances are in the pipeline, and cached hierarchies are evicted when
+    the device-memory budget is reached.  The wall time covers generation,
     every setup and both solves of every instance."""
     import collections
-    import multiprocessing as mp
     import numpy as np
     from problems.grids import c4_problem
     from paper_2005_01275_amd.serve import Server, ServerError, FAS
@@ -449,8 +447,8 @@ def c4_leg(pk, n_problems=512, slots=4, window=64, gen_workers=8):
             pr = dataclasses.replace(pr, source=pr.source * (0.25 / float(np.abs(p_lin).max())))
             fas_q.append((i, pr.mesh.n_cells, info["setup_ms"], S.submit(mid, pr, o, FAS)))
 
-        pool = mp.get_context("spawn").Pool(gen_workers)
-        for i, pr in enumerate(pool.imap(c4_problem, range(n_problems), chunksize=2)):
+        for i in range(n_problems):
+            pr = c4_problem(i)
             cells += pr.mesh.n_cells
             mid = S.add_model(pr.mesh, pr.n_levels, pr.box, pr.m)
             lin_q.append((i, mid, pr, S.submit(mid, dataclasses.replace(pr, alpha=0.0), lo, FAS)))
@@ -460,8 +458,6 @@ def c4_leg(pk, n_problems=512, slots=4, window=64, gen_workers=8):
                 finish_one()
             if (i + 1) % 64 == 0:
                 log(f"c4: {i + 1} instances generated and submitted, {len(done)} finished")
-        pool.close()
-        pool.join()
         while lin_q:
             scale_one()
         while fas_q:
