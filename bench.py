@@ -408,7 +408,7 @@ def batched_leg(pk, n_problems, seed=11):
 
 def c4_leg(pk, n_problems=512, slots=4, window=64):
     """The batched configuration at its full size: 512 independent boxes of
-    16..96 cells per edge (about 9.5e7 cells), each with its own k field and
+    16..96 cells per edge (about 1.0e8 cells), each with its own k field and
     box aggregates of 4..8 cells per edge.  The instances stream through the
     native runtime: each is generated on the host, registered, solved
     linearly (alpha = 0) to fix its source scale (max |p| = 0.25), then
