@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--served-requests", type=int, default=200)
     ap.add_argument("--batch-problems", type=int, default=24)
     ap.add_argument("--c4", action="store_true",
-                    help="also run the batched configuration at its full size (512 instances, about 9.5e7 cells; "
+                    help="also run the batched configuration at its full size (512 instances, about 1.0e8 cells; "
                          "several minutes)")
     return ap.parse_args()
 
