@@ -756,7 +756,12 @@ void setup_coarse_levels(Hierarchy& h) {
   // in its counting mode on the provisional coarse topology, then (when the
   // counts differ) rebuilds the coarser topologies and runs again
   std::vector<char> counted(L, 0);
+  const bool trace = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
+  auto clock_ms = [] {
+    return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  };
   for (int l = 0; l + 1 < L; ++l) {
+    const double t_level = clock_ms();
     const bool counting = h.copts.eig_threshold > 0.0 && !counted[l];
     const Topo& tf = h.topo[l];
     const Topo& tc = h.topo[l + 1];
@@ -779,6 +784,7 @@ void setup_coarse_levels(Hierarchy& h) {
       dcfidx = tf.cfidx;
     }
     TransferPlan plan = make_plan(tf, tc, dev_cell, dev_p, dev_flux, dcfptr, dcfidx);
+    if (trace) std::fprintf(stderr, "[spfas] setup level %d->%d host: plan at %.1f ms\n", l, l + 1, clock_ms() - t_level);
     auto tr = std::make_unique<TransferDev>();
     TransferDev& T = *tr;
     T.n_agg = (int)plan.n_agg;
@@ -1051,9 +1057,14 @@ void setup_coarse_levels(Hierarchy& h) {
     h.trans.push_back(std::move(tr));
     h.coarse.push_back(std::move(cl));
     HIPCHECK(hipStreamSynchronize(s));
+    if (trace) std::fprintf(stderr, "[spfas] setup level %d->%d: %.1f ms\n", l, l + 1, clock_ms() - t_level);
   }
   // hot-path work buffers and the hybridised solvers of the coarse levels
-  for (int l = 1; l < L; ++l) setup_coarse_solver(h, l);
+  for (int l = 1; l < L; ++l) {
+    const double t0 = clock_ms();
+    setup_coarse_solver(h, l);
+    if (trace) std::fprintf(stderr, "[spfas] setup level %d solver: %.1f ms\n", l, clock_ms() - t0);
+  }
 }
 
 }  // namespace spfas

@@ -334,46 +334,71 @@ TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>&
   TransferPlan P;
   const int64_t na = c.n_cells;
   P.n_agg = na;
-  // cells of each aggregate, ascending canonical id
-  std::vector<std::vector<int64_t>> members(na);
-  for (int64_t i = 0; i < f.n_cells; ++i) members[f.agg[i]].push_back(i);
-  // coarse flux (canonical) -> level-l flux ids of its group
-  std::vector<std::vector<int64_t>> grp(c.n_flux);
+  // Lists in CSR form by counting sorts, each filled in the order the plan
+  // needs: cells of each aggregate by ascending canonical id; the fine
+  // fluxes of each coarse face group and the interior fluxes int(A) of each
+  // aggregate in the renumbered order of level l.
+  auto csr = [](int64_t nb, const std::vector<int64_t>& key, std::vector<int64_t>& ptr) {
+    ptr.assign(nb + 1, 0);
+    for (int64_t k : key)
+      if (k >= 0) ptr[k + 1]++;
+    for (int64_t b = 0; b < nb; ++b) ptr[b + 1] += ptr[b];
+  };
+  std::vector<int64_t> mem_ptr, members;
+  {
+    std::vector<int64_t> key(f.agg.begin(), f.agg.end());
+    csr(na, key, mem_ptr);
+    members.resize(mem_ptr[na]);
+    std::vector<int64_t> fill(mem_ptr.begin(), mem_ptr.end() - 1);
+    for (int64_t i = 0; i < f.n_cells; ++i) members[fill[f.agg[i]]++] = i;
+  }
+  // coarse group of every fine flux (-1: none) and int(A) membership
+  std::vector<int64_t> grp_of(f.n_flux, -1), int_of(f.n_flux, -1);
   {
     // map (a,b) pair -> coarse face id; Dirichlet A -> coarse id
     std::vector<int64_t> dir_id(na, -1);
     for (int64_t J = 0; J < c.n_flux; ++J)
       if (c.kind[J] == FK_DIRICHLET) dir_id[c.c1[J]] = J;
-    // interior pairs are sorted; binary search
+    // interior pairs are sorted by (lower, higher) aggregate: the pairs of
+    // each lower aggregate form one range, searched linearly
     int64_t n_pairs = 0;
     while (n_pairs < c.n_flux && c.kind[n_pairs] == FK_INTERIOR) ++n_pairs;
+    std::vector<int64_t> lo_ptr(na + 1, 0);
+    for (int64_t J = 0; J < n_pairs; ++J) lo_ptr[c.c1[J] + 1]++;
+    for (int64_t A = 0; A < na; ++A) lo_ptr[A + 1] += lo_ptr[A];
     for (int64_t j = 0; j < f.n_flux; ++j) {
-      if (f.kind[j] == FK_INTERIOR) {
-        int64_t a = f.agg[f.c1[j]], b = f.agg[f.c2[j]];
-        if (a == b) continue;
-        int64_t lo = std::min(a, b), hi = std::max(a, b);
-        int64_t L = 0, R = n_pairs;
-        while (L < R) {
-          int64_t mid = (L + R) / 2;
-          if (std::make_pair(c.c1[mid], c.c2[mid]) < std::make_pair(lo, hi)) L = mid + 1; else R = mid;
+      const int8_t k = f.kind[j];
+      const int64_t a1 = f.agg[f.c1[j]];
+      if (k == FK_BUBBLE) {
+        int_of[j] = a1;
+      } else if (k == FK_INTERIOR) {
+        const int64_t a2 = f.agg[f.c2[j]];
+        if (a1 == a2) {
+          int_of[j] = a1;
+          continue;
         }
-        grp[L].push_back(j);
-      } else if (f.kind[j] == FK_DIRICHLET) {
-        grp[dir_id[f.agg[f.c1[j]]]].push_back(j);
+        const int64_t lo = std::min(a1, a2), hi = std::max(a1, a2);
+        int64_t J = lo_ptr[lo];
+        while (J < lo_ptr[lo + 1] && c.c2[J] != hi) ++J;
+        if (J == lo_ptr[lo + 1]) fail(SPFAS_ERR_INVALID, "fine face between aggregates without a coarse face");
+        grp_of[j] = J;
+      } else if (k == FK_DIRICHLET) {
+        grp_of[j] = dir_id[a1];
       }
     }
   }
-  // order inside a group: the renumbered order of level l
-  std::vector<int64_t> fpos(f.n_flux);
-  for (int64_t i = 0; i < f.n_flux; ++i) fpos[f.flux_order[i]] = i;
-  for (auto& g : grp) std::sort(g.begin(), g.end(), [&](int64_t a, int64_t b) { return fpos[a] < fpos[b]; });
-  // int(A) lists in renumbered order
-  std::vector<std::vector<int64_t>> ints(na);
-  for (int64_t i = 0; i < f.n_flux; ++i) {
-    int64_t j = f.flux_order[i];
-    int8_t k = f.kind[j];
-    int64_t a1 = f.agg[f.c1[j]];
-    if (k == FK_BUBBLE || (k == FK_INTERIOR && f.agg[f.c2[j]] == a1)) ints[a1].push_back(j);
+  std::vector<int64_t> grp_ptr, grp_list, int_ptr, int_list;
+  csr(c.n_flux, grp_of, grp_ptr);
+  csr(na, int_of, int_ptr);
+  grp_list.resize(grp_ptr[c.n_flux]);
+  int_list.resize(int_ptr[na]);
+  {
+    std::vector<int64_t> gfill(grp_ptr.begin(), grp_ptr.end() - 1), ifill(int_ptr.begin(), int_ptr.end() - 1);
+    for (int64_t i = 0; i < f.n_flux; ++i) {   // renumbered order of level l
+      const int64_t j = f.flux_order[i];
+      if (grp_of[j] >= 0) grp_list[gfill[grp_of[j]]++] = j;
+      if (int_of[j] >= 0) int_list[ifill[int_of[j]]++] = j;
+    }
   }
   P.cell_ptr.assign(na + 1, 0);
   P.pd_ptr.assign(na + 1, 0);
@@ -384,42 +409,54 @@ TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>&
   P.fgrp_ptr.assign(c.n_flux + 1, 0);
   P.grp_pos_A.assign(c.n_flux, -1);
   P.grp_pos_B.assign(c.n_flux, -1);
-  for (int64_t J = 0; J < c.n_flux; ++J) P.fgrp_ptr[J + 1] = P.fgrp_ptr[J] + (int64_t)grp[J].size();
-  P.fgrp_list.resize(P.fgrp_ptr.back());
-  for (int64_t J = 0; J < c.n_flux; ++J)
-    for (size_t q = 0; q < grp[J].size(); ++q) P.fgrp_list[P.fgrp_ptr[J] + q] = dev_flux[grp[J][q]];
+  P.fgrp_ptr = grp_ptr;
+  P.fgrp_list.resize(grp_list.size());
+  for (size_t q = 0; q < grp_list.size(); ++q) P.fgrp_list[q] = dev_flux[grp_list[q]];
+  P.cell_list.reserve(f.n_cells);
+  P.pd_list.reserve(f.n_p());
+  P.smap.reserve(f.cfidx.size());
+  P.smap_ptr.reserve(f.n_cells + 1);
+  std::vector<int64_t> dofs;
   P.smap_ptr.assign(1, 0);
   std::vector<int64_t> where(f.n_flux, -1);
+  // device flux id -> canonical id (the device local lists are read in
+  // device order, which is ascending device id within each cell)
+  std::vector<int64_t> canon_of_dev(f.n_flux, -1);
+  for (int64_t j = 0; j < f.n_flux; ++j) canon_of_dev[dev_flux[j]] = j;
   for (int64_t A = 0; A < na; ++A) {
     P.mA[A] = (int32_t)(c.pptr[A + 1] - c.pptr[A]);
-    for (int64_t cell : members[A]) {
+    for (int64_t m = mem_ptr[A]; m < mem_ptr[A + 1]; ++m) {
+      const int64_t cell = members[m];
       P.cell_list.push_back(dev_cell[cell]);
       for (int64_t q = f.pptr[cell]; q < f.pptr[cell + 1]; ++q) P.pd_list.push_back(dev_p[q]);
     }
     P.cell_ptr[A + 1] = (int64_t)P.cell_list.size();
     P.pd_ptr[A + 1] = (int64_t)P.pd_list.size();
     // dofs(A): int(A), then the groups of A's coarse faces in A's local order
-    std::vector<int64_t> dofs(ints[A]);
-    P.n_int[A] = (int32_t)ints[A].size();
+    dofs.assign(int_list.begin() + int_ptr[A], int_list.begin() + int_ptr[A + 1]);
+    P.n_int[A] = (int32_t)(int_ptr[A + 1] - int_ptr[A]);
     for (int64_t q = c.cfptr[A]; q < c.cfptr[A + 1]; ++q) {
       int64_t J = c.cfidx[q];
       if (c.kind[J] == FK_BUBBLE) continue;
       int64_t off = (int64_t)dofs.size();
       if (c.c1[J] == A) P.grp_pos_A[J] = off; else P.grp_pos_B[J] = off;
-      dofs.insert(dofs.end(), grp[J].begin(), grp[J].end());
+      dofs.insert(dofs.end(), grp_list.begin() + grp_ptr[J], grp_list.begin() + grp_ptr[J + 1]);
     }
     for (size_t q = 0; q < dofs.size(); ++q) where[dofs[q]] = (int64_t)q;
-    for (int64_t cell : members[A]) {
+    for (int64_t m = mem_ptr[A]; m < mem_ptr[A + 1]; ++m) {
+      const int64_t cell = members[m];
       int64_t dc = dev_cell[cell];
-      // canonical list of the cell, then reorder to the device local order
-      std::vector<std::pair<int64_t, int64_t>> loc;  // (device flux id, canonical flux id)
-      for (int64_t q = f.cfptr[cell]; q < f.cfptr[cell + 1]; ++q) loc.emplace_back(dev_flux[f.cfidx[q]], f.cfidx[q]);
-      std::sort(loc.begin(), loc.end());
+      // the cell's fluxes in the device local order (ascending device id)
       int64_t k = dev_cfptr[dc + 1] - dev_cfptr[dc];
-      if ((int64_t)loc.size() != k) fail(SPFAS_ERR_INVALID, "local flux list mismatch");
+      if (f.cfptr[cell + 1] - f.cfptr[cell] != k) fail(SPFAS_ERR_INVALID, "local flux list mismatch");
+      int64_t prev = -1;
       for (int64_t q = 0; q < k; ++q) {
-        if (dev_cfidx[dev_cfptr[dc] + q] != loc[q].first) fail(SPFAS_ERR_INVALID, "device local order mismatch");
-        int64_t w = where[loc[q].second];
+        const int64_t d = dev_cfidx[dev_cfptr[dc] + q];
+        if (d <= prev || d < 0 || d >= f.n_flux) fail(SPFAS_ERR_INVALID, "device local order mismatch");
+        prev = d;
+        const int64_t j = canon_of_dev[d];
+        if (f.c1[j] != cell && f.c2[j] != cell) fail(SPFAS_ERR_INVALID, "device local list holds a foreign flux");
+        int64_t w = where[j];
         if (w < 0) fail(SPFAS_ERR_INVALID, "flux of an aggregate cell outside dofs(A)");
         P.smap.push_back((int32_t)w);
       }
