@@ -947,7 +947,7 @@ void setup_coarse_solver(Hierarchy& h, int l) {
     launch_H_assemble(C, s);
     HIPCHECK(hipStreamSynchronize(s));
     C.amg.setup(C.H, s);
-    if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
+    if (trace_level() > 0)
       std::fprintf(stderr, "[spfas] hybridised system of level %d AMG: %s\n", l, C.amg.describe().c_str());
   }
 }

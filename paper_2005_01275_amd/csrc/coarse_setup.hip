@@ -756,12 +756,9 @@ void setup_coarse_levels(Hierarchy& h) {
   // in its counting mode on the provisional coarse topology, then (when the
   // counts differ) rebuilds the coarser topologies and runs again
   std::vector<char> counted(L, 0);
-  const bool trace = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
-  auto clock_ms = [] {
-    return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-  };
+  const bool trace = trace_level() > 0;
   for (int l = 0; l + 1 < L; ++l) {
-    const double t_level = clock_ms();
+    const double t_level = wall_ms();
     const bool counting = h.copts.eig_threshold > 0.0 && !counted[l];
     const Topo& tf = h.topo[l];
     const Topo& tc = h.topo[l + 1];
@@ -784,7 +781,7 @@ void setup_coarse_levels(Hierarchy& h) {
       dcfidx = tf.cfidx;
     }
     TransferPlan plan = make_plan(tf, tc, dev_cell, dev_p, dev_flux, dcfptr, dcfidx);
-    if (trace) std::fprintf(stderr, "[spfas] setup level %d->%d host: plan at %.1f ms\n", l, l + 1, clock_ms() - t_level);
+    if (trace) std::fprintf(stderr, "[spfas] setup level %d->%d host: plan at %.1f ms\n", l, l + 1, wall_ms() - t_level);
     auto tr = std::make_unique<TransferDev>();
     TransferDev& T = *tr;
     T.n_agg = (int)plan.n_agg;
@@ -906,11 +903,8 @@ void setup_coarse_levels(Hierarchy& h) {
     bad.alloc(4);
     bad.zero(s);
     PlanView pv = plan_view(T);
-    const bool tr_on = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
-    auto now_ms = [] {
-      return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-    };
-    double t_a = now_ms();
+    const bool tr_on = trace_level() > 0;
+    double t_a = wall_ms();
     // ---- phase A: PV traces
     int n_faces_c = 0;
     while (n_faces_c < C.nf && C.h_kind[n_faces_c] != FK_BUBBLE) ++n_faces_c;
@@ -939,9 +933,9 @@ void setup_coarse_levels(Hierarchy& h) {
       HIPCHECK(hipStreamSynchronize(s));
       if (tr_on)
         std::fprintf(stderr, "[spfas] setup level %d->%d PV traces: %d interfaces, max ns %zu, max npU %zu, %zu "
-                     "workgroups: %.1f ms\n", l, l + 1, n_faces_c, mx_ns, mx_npU, slots, now_ms() - t_a);
+                     "workgroups: %.1f ms\n", l, l + 1, n_faces_c, mx_ns, mx_npU, slots, wall_ms() - t_a);
     }
-    const double t_b = now_ms();
+    const double t_b = wall_ms();
     // ---- phase B: per aggregate
     {
       ScratchB sb;
@@ -984,7 +978,7 @@ void setup_coarse_levels(Hierarchy& h) {
       }
       if (tr_on)
         std::fprintf(stderr, "[spfas] setup level %d->%d aggregates: %d, max np %zu, max nd %zu, max nI %zu, %zu "
-                     "workgroups: %.1f ms\n", l, l + 1, T.n_agg, mx_np, mx_nd, mx_nI, slots, now_ms() - t_b);
+                     "workgroups: %.1f ms\n", l, l + 1, T.n_agg, mx_np, mx_nd, mx_nI, slots, wall_ms() - t_b);
     }
     std::vector<int> hb = bad.download(s);
     if (hb[0] != 0) {
@@ -1057,13 +1051,13 @@ void setup_coarse_levels(Hierarchy& h) {
     h.trans.push_back(std::move(tr));
     h.coarse.push_back(std::move(cl));
     HIPCHECK(hipStreamSynchronize(s));
-    if (trace) std::fprintf(stderr, "[spfas] setup level %d->%d: %.1f ms\n", l, l + 1, clock_ms() - t_level);
+    if (trace) std::fprintf(stderr, "[spfas] setup level %d->%d: %.1f ms\n", l, l + 1, wall_ms() - t_level);
   }
   // hot-path work buffers and the hybridised solvers of the coarse levels
   for (int l = 1; l < L; ++l) {
-    const double t0 = clock_ms();
+    const double t0 = wall_ms();
     setup_coarse_solver(h, l);
-    if (trace) std::fprintf(stderr, "[spfas] setup level %d solver: %.1f ms\n", l, clock_ms() - t0);
+    if (trace) std::fprintf(stderr, "[spfas] setup level %d solver: %.1f ms\n", l, wall_ms() - t0);
   }
 }
 

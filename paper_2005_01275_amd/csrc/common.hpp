@@ -5,7 +5,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdint>
 #include <cstdlib>
 #include <type_traits>
@@ -82,6 +84,20 @@ inline void dev_free(AllocCtx* c, void* p, size_t bytes) noexcept {
     (void)hipFree(p);
   }
   if (c) c->bytes.fetch_sub((int64_t)bytes);
+}
+
+// SPFAS_TRACE=1 prints setup timings and solver events to stderr; 2 also
+// times the AMG levels with events.
+inline int trace_level() {
+  static const int lv = [] {
+    const char* e = std::getenv("SPFAS_TRACE");
+    return (e && e[0] && e[0] != '0') ? std::max(1, std::atoi(e)) : 0;
+  }();
+  return lv;
+}
+
+inline double wall_ms() {
+  return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 inline bool poison_on() {

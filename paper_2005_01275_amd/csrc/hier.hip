@@ -88,7 +88,7 @@ static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
 }
 
 void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
-  const double t_start = 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  const double t_start = wall_ms();
   validate_mesh(M, o);
   dim = M.dim;
   n_cells_in = M.n_cells;
@@ -114,12 +114,10 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
     t0.c2.push_back(M.face_cells[2 * f + 1]);
   }
   t0.n_flux = (int64_t)flux_face.size();
-  const bool trace = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
+  const bool trace = trace_level() > 0;
   auto stamp = [&](const char* what) {
     if (trace)
-      std::fprintf(stderr, "[spfas] setup host: %s at %.1f ms\n", what,
-                   1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() -
-                       t_start);
+      std::fprintf(stderr, "[spfas] setup host: %s at %.1f ms\n", what, wall_ms() - t_start);
   };
   stamp("level-0 face lists");
   build_cell_lists(t0);
@@ -150,10 +148,8 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
     topo.push_back(std::move(c));
     stamp("coarse topology");
   }
-  if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
-    std::fprintf(stderr, "[spfas] setup: host topology, aggregation, renumbering %.1f ms\n",
-                 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() -
-                     t_start);
+  if (trace_level() > 0)
+    std::fprintf(stderr, "[spfas] setup: host topology, aggregation, renumbering %.1f ms\n", wall_ms() - t_start);
   if (host_only) return;
   HIPCHECK(hipHostMalloc((void**)&hpin, kMaxParts * sizeof(double) * 4, hipHostMallocMapped | hipHostMallocCoherent));
   HIPCHECK(hipHostGetDevicePointer((void**)&dpin, hpin, 0));
@@ -280,16 +276,13 @@ void Hierarchy::setup(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   fine.f.zero(s);
   fine.g.zero(s);
   // ---------------- fine smoother (eliminated system and its AMG), coarse levels
-  const bool tr_on = [] { const char* e = std::getenv("SPFAS_TRACE"); return e && e[0] && e[0] != '0'; }();
-  auto now_ms = [] {
-    return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-  };
-  double tp = now_ms();
+  const bool tr_on = trace_level() > 0;
+  double tp = wall_ms();
   setup_fine_solver(*this);
-  if (tr_on) std::fprintf(stderr, "[spfas] setup: fine solver (S pattern, AMG) %.1f ms\n", now_ms() - tp);
-  tp = now_ms();
+  if (tr_on) std::fprintf(stderr, "[spfas] setup: fine solver (S pattern, AMG) %.1f ms\n", wall_ms() - tp);
+  tp = wall_ms();
   setup_coarse_levels(*this);
-  if (tr_on) std::fprintf(stderr, "[spfas] setup: coarse levels %.1f ms\n", now_ms() - tp);
+  if (tr_on) std::fprintf(stderr, "[spfas] setup: coarse levels %.1f ms\n", wall_ms() - tp);
   HIPCHECK(hipStreamSynchronize(s));
 }
 

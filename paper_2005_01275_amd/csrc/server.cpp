@@ -34,10 +34,6 @@ using namespace spfas;
 
 namespace {
 
-double now_ms() {
-  return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
 struct Instance {
   spfas_hierarchy* h = nullptr;
   bool busy = false;
@@ -142,7 +138,7 @@ struct spfas_server {
         r->rc = SPFAS_ERR_OOM;
         r->err = "the model's hierarchy needs " + std::to_string(m->est_bytes) + " bytes, more than the budget of " +
                  std::to_string(o.hbm_budget);
-        r->t_start = r->t_solve = r->t_end = now_ms();
+        r->t_start = r->t_solve = r->t_end = wall_ms();
         r->done = true;
         cnt.completed++;
         it = queue.erase(it);
@@ -183,7 +179,7 @@ struct spfas_server {
         cv_work.wait(lk, [&] { return stop || (r = admit()) != nullptr; });
         if (!r) return;
         m = models.at(r->model).get();
-        r->t_start = now_ms();
+        r->t_start = wall_ms();
       }
       Instance* in = m->inst.get();
       int rc = SPFAS_OK;
@@ -203,7 +199,7 @@ struct spfas_server {
         spfas_hierarchy_reset_peak(in->h);
         spfas_hierarchy_device_bytes(in->h, &held0, nullptr);
       }
-      r->t_solve = now_ms();
+      r->t_solve = wall_ms();
       if (rc >= 0) {
         spfas_problem pb;
         pb.alpha = r->alpha;
@@ -258,7 +254,7 @@ struct spfas_server {
         cnt.peak_bytes = std::max(cnt.peak_bytes, used);
         r->rc = rc;
         r->err = err;
-        r->t_end = now_ms();
+        r->t_end = wall_ms();
         r->done = true;
         cnt.completed++;
       }
@@ -372,7 +368,7 @@ int spfas_server_submit(spfas_server* S, int64_t model_id, const spfas_problem* 
     r->alpha = prob->alpha;
     r->opts = *opts;
     r->ticket = S->next_ticket++;
-    r->t_submit = now_ms();
+    r->t_submit = wall_ms();
     *ticket = r->ticket;
     S->queue.push_back(r.get());
     S->reqs[r->ticket] = std::move(r);

@@ -164,7 +164,7 @@ static int krylov_solve(KrylovT<T>& kry, const CsrView& A, Amg* M, const T* b, T
     const int left = o.lin_max_it - it;
     if (left <= 0) return it;
     const int it2 = kry.bicgstab(A, M, b, x, rtol, left, s);
-    if (const char* e = std::getenv("SPFAS_TRACE"); e && e[0] && e[0] != '0')
+    if (trace_level() > 0)
       std::fprintf(stderr, "[spfas] PCG stopped after %d iterations without convergence; BiCGStab %d\n", it, it2);
     return it + it2;
   }
@@ -197,18 +197,12 @@ static void prec_record(PrecReuse& pr, bool fresh, int it, bool failed) {
 }
 
 // SPFAS_TRACE=1 prints one line per smoothing step to stderr.
-static bool trace_on() {
-  static const bool on = [] {
-    const char* e = std::getenv("SPFAS_TRACE");
-    return e && e[0] && e[0] != '0';
-  }();
-  return on;
-}
+static bool trace_on() { return trace_level() > 0; }
 
 // wall-clock milliseconds after draining the stream (trace output only)
 static double trace_clock(hipStream_t s) {
   HIPCHECK(hipStreamSynchronize(s));
-  return 1e3 * std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+  return wall_ms();
 }
 
 static double check_finite(double v, const char* what) {

@@ -1163,7 +1163,7 @@ void coarse_storage(AmgLevel& Cl, const HostCsr& C, hipStream_t s) {
 }  // namespace
 
 void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bool classical_) {
-  if (const char* e = std::getenv("SPFAS_TRACE"); e && std::atoi(e) >= 2) {
+  if (trace_level() >= 2) {
     lvprof = std::make_shared<KernelProf>(64);
     lvprof->on = true;
   }
