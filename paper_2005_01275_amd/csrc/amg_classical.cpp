@@ -14,6 +14,38 @@ namespace spfas {
 
 namespace {
 
+// Host threads for the row-parallel setup steps (at most 16).
+int host_threads() {
+  const unsigned hc = std::thread::hardware_concurrency();
+  return (int)std::max(1u, std::min(16u, hc));
+}
+
+// f(t, lo, hi) on nth contiguous, ordered chunks of [0, n), one thread each.
+template <class F>
+void parallel_chunks(int n, int nth, F&& f) {
+  std::vector<std::thread> th;
+  const int per = (n + nth - 1) / nth;
+  for (int t = 0; t < nth; ++t) {
+    const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    th.emplace_back([&f, t, lo, hi] { f(t, lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// f(t) for t < nth, one thread each.
+template <class F>
+void per_chunk(int nth, F&& f) {
+  parallel_chunks(nth, nth, [&f](int t, int, int) { f(t); });
+}
+
+// Exclusive prefix sums of per-chunk sizes: off[t] is where chunk t starts.
+template <class Size>
+std::vector<size_t> chunk_offsets(int nth, Size size) {
+  std::vector<size_t> off(nth + 1, 0);
+  for (int t = 0; t < nth; ++t) off[t + 1] = off[t] + size(t);
+  return off;
+}
+
 // splitmix64 (Steele, Lea, Flood 2014): the PMIS tie-breaking measure
 double unit_hash(uint64_t seed, uint64_t i) {
   uint64_t z = seed + 0x9E3779B97F4A7C15ULL * (i + 1);
@@ -29,18 +61,31 @@ struct Strength {
 };
 
 Strength strength(const HostCsr& A, double theta) {
-  const int n = A.n;
+  const int n = A.n, nth = host_threads();
   Strength S;
-  S.ptr.assign(n + 1, 0);
-  for (int i = 0; i < n; ++i) {
+  // strong dependences of row i, in column order: counted, then written
+  auto row = [&](int i, int* out) {
     double mx = 0.0;
     for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
       if (A.col[k] != i) mx = std::max(mx, -A.val[k]);
+    int c = 0;
     if (mx > 0.0)
       for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-        if (A.col[k] != i && -A.val[k] >= theta * mx) S.col.push_back(A.col[k]);
-    S.ptr[i + 1] = (int)S.col.size();
-  }
+        if (A.col[k] != i && -A.val[k] >= theta * mx) {
+          if (out) out[c] = A.col[k];
+          ++c;
+        }
+    return c;
+  };
+  S.ptr.assign(n + 1, 0);
+  parallel_chunks(n, nth, [&](int, int lo, int hi) {
+    for (int i = lo; i < hi; ++i) S.ptr[i + 1] = row(i, nullptr);
+  });
+  for (int i = 0; i < n; ++i) S.ptr[i + 1] += S.ptr[i];
+  S.col.resize(S.ptr[n]);
+  parallel_chunks(n, nth, [&](int, int lo, int hi) {
+    for (int i = lo; i < hi; ++i) row(i, S.col.data() + S.ptr[i]);
+  });
   S.tptr.assign(n + 1, 0);
   for (int j : S.col) S.tptr[j + 1]++;
   for (int i = 0; i < n; ++i) S.tptr[i + 1] += S.tptr[i];
@@ -51,37 +96,58 @@ Strength strength(const HostCsr& A, double theta) {
   return S;
 }
 
-// state: 1 = C, -1 = F
+// state: 1 = C, -1 = F.  Each round's selection and F-marking read only the
+// state of the previous step, so rows are split over host threads and the
+// per-chunk lists joined in row order.
 std::vector<int> pmis(const Strength& S, int n, uint64_t seed) {
+  const int nth = host_threads();
   std::vector<double> lam(n);
   std::vector<int> state(n, 0);
-  for (int i = 0; i < n; ++i) {
-    const int ns = S.ptr[i + 1] - S.ptr[i], nt = S.tptr[i + 1] - S.tptr[i];
-    lam[i] = nt + unit_hash(seed, (uint64_t)i);
-    if (ns == 0 && nt == 0) state[i] = -1;   // isolated point: smoothing only
-  }
+  parallel_chunks(n, nth, [&](int, int lo, int hi) {
+    for (int i = lo; i < hi; ++i) {
+      const int ns = S.ptr[i + 1] - S.ptr[i], nt = S.tptr[i + 1] - S.tptr[i];
+      lam[i] = nt + unit_hash(seed, (uint64_t)i);
+      if (ns == 0 && nt == 0) state[i] = -1;   // isolated point: smoothing only
+    }
+  });
   std::vector<int> und;
   for (int i = 0; i < n; ++i)
     if (state[i] == 0) und.push_back(i);
   std::vector<char> newc(n, 0);
+  std::vector<std::vector<int>> part(nth);
+  auto join = [&](std::vector<int>& out) {
+    const std::vector<size_t> off = chunk_offsets(nth, [&](int t) { return part[t].size(); });
+    out.resize(off[nth]);
+    per_chunk(nth, [&](int t) { std::copy(part[t].begin(), part[t].end(), out.begin() + off[t]); });
+  };
+  std::vector<int> sel, rest;
   while (!und.empty()) {
+    const int nu = (int)und.size();
     auto beats = [&](int j, int i) { return state[j] == 0 && (lam[j] > lam[i] || (lam[j] == lam[i] && j > i)); };
-    std::vector<int> sel;
-    for (int i : und) {
-      bool mx = true;
-      for (int q = S.ptr[i]; q < S.ptr[i + 1] && mx; ++q) mx = !beats(S.col[q], i);
-      for (int q = S.tptr[i]; q < S.tptr[i + 1] && mx; ++q) mx = !beats(S.tcol[q], i);
-      if (mx) sel.push_back(i);
-    }
+    parallel_chunks(nu, nth, [&](int t, int lo, int hi) {
+      part[t].clear();
+      for (int u = lo; u < hi; ++u) {
+        const int i = und[u];
+        bool mx = true;
+        for (int q = S.ptr[i]; q < S.ptr[i + 1] && mx; ++q) mx = !beats(S.col[q], i);
+        for (int q = S.tptr[i]; q < S.tptr[i + 1] && mx; ++q) mx = !beats(S.tcol[q], i);
+        if (mx) part[t].push_back(i);
+      }
+    });
+    join(sel);
     for (int i : sel) { state[i] = 1; newc[i] = 1; }
-    std::vector<int> rest;
-    for (int i : und) {
-      if (state[i] != 0) continue;
-      bool dep = false;
-      for (int q = S.ptr[i]; q < S.ptr[i + 1] && !dep; ++q) dep = newc[S.col[q]];
-      if (dep) state[i] = -1;
-      else rest.push_back(i);
-    }
+    parallel_chunks(nu, nth, [&](int t, int lo, int hi) {
+      part[t].clear();
+      for (int u = lo; u < hi; ++u) {
+        const int i = und[u];
+        if (state[i] != 0) continue;
+        bool dep = false;
+        for (int q = S.ptr[i]; q < S.ptr[i + 1] && !dep; ++q) dep = newc[S.col[q]];
+        if (dep) state[i] = -1;
+        else part[t].push_back(i);
+      }
+    });
+    join(rest);
     for (int i : sel) newc[i] = 0;
     und.swap(rest);
   }
@@ -89,24 +155,6 @@ std::vector<int> pmis(const Strength& S, int n, uint64_t seed) {
 }
 
 }  // namespace
-
-// Host threads for the row-parallel product construction (at most 16).
-static int host_threads() {
-  const unsigned hc = std::thread::hardware_concurrency();
-  return (int)std::max(1u, std::min(16u, hc));
-}
-
-// f(t, lo, hi) on nth contiguous, ordered chunks of [0, n), one thread each.
-template <class F>
-static void parallel_chunks(int n, int nth, F&& f) {
-  std::vector<std::thread> th;
-  const int per = (n + nth - 1) / nth;
-  for (int t = 0; t < nth; ++t) {
-    const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
-    th.emplace_back([&f, t, lo, hi] { f(t, lo, hi); });
-  }
-  for (auto& x : th) x.join();
-}
 
 // Groups the products of one output row by column: columns ascending, each
 // column's products in generation order; start[c] ends column c's products.
@@ -244,14 +292,22 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
       out.rowlen.push_back((int)(out.col.size() - len0));
     }
   });
-  L.pptr.assign(n + 1, 0);
+  // The chunks are joined in row order by parallel copies to offsets from
+  // per-chunk prefix sums (here and for the products below).
+  const std::vector<size_t> row0 = chunk_offsets(nth, [&](int t) { return pch[t].rowlen.size(); });
   {
-    int r = 0;
-    for (const PChunk& ch : pch) {
-      for (int len : ch.rowlen) { L.pptr[r + 1] = L.pptr[r] + len; ++r; }
-      L.pcol.insert(L.pcol.end(), ch.col.begin(), ch.col.end());
-      L.pval.insert(L.pval.end(), ch.val.begin(), ch.val.end());
-    }
+    const std::vector<size_t> eo = chunk_offsets(nth, [&](int t) { return pch[t].col.size(); });
+    L.pptr.assign(n + 1, 0);
+    L.pcol.resize(eo[nth]);
+    L.pval.resize(eo[nth]);
+    per_chunk(nth, [&](int t) {
+      PChunk& ch = pch[t];
+      std::copy(ch.col.begin(), ch.col.end(), L.pcol.begin() + eo[t]);
+      std::copy(ch.val.begin(), ch.val.end(), L.pval.begin() + eo[t]);
+      size_t e = eo[t];
+      for (size_t r = 0; r < ch.rowlen.size(); ++r) L.pptr[row0[t] + r + 1] = (int)(e += ch.rowlen[r]);
+      ch = PChunk();
+    });
   }
 
 
@@ -279,6 +335,20 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
   std::vector<ApChunk> apc(nth);
   parallel_chunks(n, nth, [&](int t, int lo, int hi) {
     ApChunk& ch = apc[t];
+    {   // capacity: the chunk's products bound its entries (untouched capacity costs no memory)
+      size_t np = 0;
+      for (int i = lo; i < hi; ++i) {
+        np += L.pptr[i + 1] - L.pptr[i];
+        for (int q = A.ptr[i]; q < A.ptr[i + 1]; ++q) np += L.pptr[A.col[q] + 1] - L.pptr[A.col[q]];
+      }
+      ch.la.reserve(np);
+      ch.lp.reserve(np);
+      ch.col.reserve(np);
+      ch.pidx.reserve(np);
+      ch.nprod.reserve(np);
+      ch.val.reserve(np);
+      ch.rowlen.reserve(hi - lo);
+    }
     RowGrouper g(nc);
     for (int i = lo; i < hi; ++i) {
       g.items.clear();
@@ -311,29 +381,30 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
     }
   });
   // ---- A P: pattern, products, values (joined in row order)
-  L.apptr.assign(n + 1, 0);
-  L.aplptr.assign(1, 0);
-  std::vector<double> apv;
+  HostArray<double> apv;
   {
-    size_t ne = 0, np = 0;
-    for (const ApChunk& ch : apc) { ne += ch.col.size(); np += ch.la.size(); }
-    L.apcol.reserve(ne);
-    L.appidx.reserve(ne);
-    apv.reserve(ne);
-    L.aplptr.reserve(ne + 1);
-    L.apla.reserve(np);
-    L.aplp.reserve(np);
-    int row = 0;
-    for (const ApChunk& ch : apc) {
-      for (int len : ch.rowlen) { L.apptr[row + 1] = L.apptr[row] + len; ++row; }
-      L.apcol.insert(L.apcol.end(), ch.col.begin(), ch.col.end());
-      L.appidx.insert(L.appidx.end(), ch.pidx.begin(), ch.pidx.end());
-      apv.insert(apv.end(), ch.val.begin(), ch.val.end());
-      L.apla.insert(L.apla.end(), ch.la.begin(), ch.la.end());
-      L.aplp.insert(L.aplp.end(), ch.lp.begin(), ch.lp.end());
-      for (int np : ch.nprod) L.aplptr.push_back(L.aplptr.back() + np);
-    }
-    apc.clear();
+    const std::vector<size_t> eo = chunk_offsets(nth, [&](int t) { return apc[t].col.size(); });
+    const std::vector<size_t> po = chunk_offsets(nth, [&](int t) { return apc[t].la.size(); });
+    L.apptr.assign(n + 1, 0);
+    L.apcol.resize(eo[nth]);
+    L.appidx.resize(eo[nth]);
+    apv.resize(eo[nth]);
+    L.aplptr.resize(eo[nth] + 1);
+    L.aplptr[0] = 0;
+    L.apla.resize(po[nth]);
+    L.aplp.resize(po[nth]);
+    per_chunk(nth, [&](int t) {
+      ApChunk& ch = apc[t];
+      std::copy(ch.col.begin(), ch.col.end(), L.apcol.begin() + eo[t]);
+      std::copy(ch.pidx.begin(), ch.pidx.end(), L.appidx.data() + eo[t]);
+      std::copy(ch.val.begin(), ch.val.end(), apv.data() + eo[t]);
+      std::copy(ch.la.begin(), ch.la.end(), L.apla.data() + po[t]);
+      std::copy(ch.lp.begin(), ch.lp.end(), L.aplp.data() + po[t]);
+      size_t e = eo[t], q = po[t];
+      for (size_t r = 0; r < ch.rowlen.size(); ++r) L.apptr[row0[t] + r + 1] = (int)(e += ch.rowlen[r]);
+      for (size_t k = 0; k < ch.nprod.size(); ++k) L.aplptr[eo[t] + k + 1] = (int)(q += ch.nprod[k]);
+      ch = ApChunk();
+    });
   }
 
   // ---- P^T (A P): coarse pattern, products (off-diagonal entries, then the diagonal), values
@@ -344,6 +415,15 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
   std::vector<RapChunk> rpc(nth);
   parallel_chunks(nc, nth, [&](int t, int lo, int hi) {
     RapChunk& ch = rpc[t];
+    {
+      size_t np = 0;
+      for (int I = lo; I < hi; ++I)
+        for (int e = L.rptr[I]; e < L.rptr[I + 1]; ++e) np += L.apptr[L.rcol[e] + 1] - L.apptr[L.rcol[e]];
+      for (auto* v : {&ch.col, &ch.nprod, &ch.r, &ch.q, &ch.dr, &ch.dq}) v->reserve(np);
+      ch.val.reserve(np);
+      ch.rowlen.reserve(hi - lo);
+      ch.ndiag.reserve(hi - lo);
+    }
     RowGrouper g(nc);
     for (int I = lo; I < hi; ++I) {
       g.items.clear();
@@ -377,39 +457,38 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
       ch.ndiag.push_back(ndg);
     }
   });
-  std::vector<int> dptr(nc + 1, 0), dr, dq;
-  L.clptr.assign(1, 0);
+  // products: the off-diagonal entries' lists in CSR order, then the
+  // diagonal's lists row by row; clptr ends every entry's list
   {
-    size_t ne = 0, np = 0, nd = 0;
-    for (const RapChunk& ch : rpc) { ne += ch.col.size(); np += ch.r.size(); nd += ch.dr.size(); }
-    C.col.reserve(ne);
-    C.val.reserve(ne);
-    L.clptr.reserve(ne + nc + 1);
-    L.clr.reserve(np + nd);
-    L.clq.reserve(np + nd);
-    dr.reserve(nd);
-    dq.reserve(nd);
-    int row = 0;
-    for (const RapChunk& ch : rpc) {
-      for (size_t t = 0; t < ch.rowlen.size(); ++t) {
-        C.ptr[row + 1] = C.ptr[row] + ch.rowlen[t];
-        dptr[row + 1] = dptr[row] + ch.ndiag[t];
-        ++row;
+    const std::vector<size_t> crow0 = chunk_offsets(nth, [&](int t) { return rpc[t].rowlen.size(); });
+    const std::vector<size_t> eo = chunk_offsets(nth, [&](int t) { return rpc[t].col.size(); });
+    const std::vector<size_t> po = chunk_offsets(nth, [&](int t) { return rpc[t].r.size(); });
+    const std::vector<size_t> dof = chunk_offsets(nth, [&](int t) { return rpc[t].dr.size(); });
+    const size_t ne = eo[nth], base = po[nth];
+    C.col.resize(ne);
+    C.val.resize(ne);
+    L.clptr.resize(ne + 1 + nc);
+    L.clptr[0] = 0;
+    L.clr.resize(base + dof[nth]);
+    L.clq.resize(base + dof[nth]);
+    per_chunk(nth, [&](int t) {
+      RapChunk& ch = rpc[t];
+      std::copy(ch.col.begin(), ch.col.end(), C.col.begin() + eo[t]);
+      std::copy(ch.val.begin(), ch.val.end(), C.val.begin() + eo[t]);
+      std::copy(ch.r.begin(), ch.r.end(), L.clr.data() + po[t]);
+      std::copy(ch.q.begin(), ch.q.end(), L.clq.data() + po[t]);
+      std::copy(ch.dr.begin(), ch.dr.end(), L.clr.data() + base + dof[t]);
+      std::copy(ch.dq.begin(), ch.dq.end(), L.clq.data() + base + dof[t]);
+      size_t e = eo[t], q = po[t], d = base + dof[t];
+      for (size_t k = 0; k < ch.nprod.size(); ++k) L.clptr[eo[t] + k + 1] = (int)(q += ch.nprod[k]);
+      for (size_t r = 0; r < ch.rowlen.size(); ++r) {
+        const size_t I = crow0[t] + r;
+        C.ptr[I + 1] = (int)(e += ch.rowlen[r]);
+        L.clptr[ne + 1 + I] = (int)(d += ch.ndiag[r]);
       }
-      C.col.insert(C.col.end(), ch.col.begin(), ch.col.end());
-      C.val.insert(C.val.end(), ch.val.begin(), ch.val.end());
-      L.clr.insert(L.clr.end(), ch.r.begin(), ch.r.end());
-      L.clq.insert(L.clq.end(), ch.q.begin(), ch.q.end());
-      for (int np : ch.nprod) L.clptr.push_back(L.clptr.back() + np);
-      dr.insert(dr.end(), ch.dr.begin(), ch.dr.end());
-      dq.insert(dq.end(), ch.dq.begin(), ch.dq.end());
-    }
-    rpc.clear();
+      ch = RapChunk();
+    });
   }
-  const int base = (int)L.clr.size();
-  for (int I = 0; I < nc; ++I) L.clptr.push_back(base + dptr[I + 1]);
-  L.clr.insert(L.clr.end(), dr.begin(), dr.end());
-  L.clq.insert(L.clq.end(), dq.begin(), dq.end());
   return true;
 }
 

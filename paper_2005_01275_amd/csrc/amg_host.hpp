@@ -7,7 +7,9 @@
 // every linearisation from the product lists built here.
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <vector>
 
 namespace spfas {
@@ -24,6 +26,24 @@ struct HostCsr {
 inline int dia_code(int i) { return i << 1; }
 inline int off_code(int k) { return (k << 1) | 1; }
 
+// Host array whose resize leaves the elements uninitialised: the product
+// lists are written in full by the threads that fill them, which then also
+// take the first-touch page faults in parallel.
+template <class T>
+struct HostArray {
+  std::unique_ptr<T[]> a;
+  size_t n = 0;
+  void resize(size_t m) {
+    a.reset(m ? new T[m] : nullptr);
+    n = m;
+  }
+  size_t size() const { return n; }
+  T* data() { return a.get(); }
+  const T* data() const { return a.get(); }
+  T& operator[](size_t i) { return a[i]; }
+  const T& operator[](size_t i) const { return a[i]; }
+};
+
 struct ClassicalLevel {
   int n = 0, nc = 0;
   // interpolation P (n x nc), CSR with ascending columns in each row
@@ -33,11 +53,12 @@ struct ClassicalLevel {
   std::vector<int> rptr, rcol, rsrc;
   // A P (n x nc): CSR pattern with ascending columns; products per entry
   // (A entry code, P entry); appidx[e] = P entry at the same position or -1
-  std::vector<int> apptr, apcol, aplptr, apla, aplp, appidx;
+  std::vector<int> apptr, apcol;
+  HostArray<int> aplptr, apla, aplp, appidx;
   // next level: DIA+CSR matrix and products per entry, off-diagonal entries
   // first (in CSR order) then the diagonal: (P entry, A P entry)
   HostCsr C;
-  std::vector<int> clptr, clr, clq;
+  HostArray<int> clptr, clr, clq;
 };
 
 // Strength of connection of the classical coarsening: j is a strong

@@ -1188,9 +1188,13 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bo
     HIPCHECK(hipStreamSynchronize(s));
   }
   classical = classical_;
+  double t_prod = 0.0, t_ops = 0.0;   // host coarsening and product lists; operators and uploads
   while (classical && H.n > dense_max) {
     ClassicalLevel CL;
+    const double t0 = wall_ms();
     if (!classical_level(H, kClassicalStrength, 0x5EED0000ULL + lv.size(), CL)) break;
+    const double t1 = wall_ms();
+    t_prod += t1 - t0;
     AmgLevel& F = lv.back();
     {   // A diag(w): every row as [diagonal, off-diagonal entries]
       std::vector<int> p(H.n + 1, 0), c, src;
@@ -1225,14 +1229,14 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bo
       F.sell64.val = F.sval64.p;
     }
     F.pval.upload(CL.pval, s);
-    F.aplptr.upload(CL.aplptr, s);
-    F.apla.upload(CL.apla, s);
-    F.aplp.upload(CL.aplp, s);
-    F.appidx.upload(CL.appidx, s);
+    F.aplptr.upload(CL.aplptr.data(), CL.aplptr.size(), s);
+    F.apla.upload(CL.apla.data(), CL.apla.size(), s);
+    F.aplp.upload(CL.aplp.data(), CL.aplp.size(), s);
+    F.appidx.upload(CL.appidx.data(), CL.appidx.size(), s);
     F.apv.alloc(std::max<size_t>(CL.apcol.size(), 1));
-    F.clptr.upload(CL.clptr, s);
-    F.clr.upload(CL.clr, s);
-    F.clq.upload(CL.clq, s);
+    F.clptr.upload(CL.clptr.data(), CL.clptr.size(), s);
+    F.clr.upload(CL.clr.data(), CL.clr.size(), s);
+    F.clq.upload(CL.clq.data(), CL.clq.size(), s);
     hipLaunchKernelGGL(k_fill_rm, dim3(grid_for(F.rm.src.n, kBlock)), dim3(kBlock), 0, s, (int)F.rm.src.n,
                        F.rm.src.p, F.pval.p, F.rm.val.p);
     LAUNCHCHECK();
@@ -1240,7 +1244,11 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bo
     coarse_storage(lv.back(), CL.C, s);
     HIPCHECK(hipStreamSynchronize(s));
     H = std::move(CL.C);
+    t_ops += wall_ms() - t1;
   }
+  if (classical && trace_level() > 0)
+    std::fprintf(stderr, "[spfas] classical AMG setup: coarsening and product lists %.1f ms, operators and uploads %.1f ms\n",
+                 t_prod, t_ops);
   if (classical && lv.size() == 1 && H.n > dense_max) classical = false;   // no classical coarsening: aggregation
   while (!classical && H.n > dense_max) {
     std::vector<int> agg;
