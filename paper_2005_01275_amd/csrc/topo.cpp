@@ -3,28 +3,49 @@
 
 #include <algorithm>
 #include <numeric>
+#include <thread>
 #include <tuple>
+#include <unordered_set>
 
 #include "common.hpp"
 
 namespace spfas {
+
+// f(lo, hi) on contiguous, ordered ranges of [0, n), one host thread each
+// (at most 16); every range writes only its own part of the output.
+template <class F>
+static void parallel_ranges(int64_t n, F&& f) {
+  const int64_t nth = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), n}));
+  const int64_t per = (n + nth - 1) / nth;
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nth; ++t) {
+    const int64_t lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    th.emplace_back([&f, lo, hi] { f(lo, hi); });
+  }
+  for (auto& x : th) x.join();
+}
 
 bool lattice_from_centroids(int dim, int64_t n, const double* centroid, std::vector<int>& shape,
                             std::vector<int64_t>& index) {
   shape.assign(dim, 0);
   index.assign(n, 0);
   int64_t stride = 1;
-  std::vector<double> vals(n);
   for (int a = 0; a < dim; ++a) {
-    for (int64_t i = 0; i < n; ++i) vals[i] = centroid[i * dim + a];
-    std::vector<double> u(vals);
-    std::sort(u.begin(), u.end());
-    u.erase(std::unique(u.begin(), u.end()), u.end());
-    shape[a] = (int)u.size();
+    // distinct coordinate values along axis a, ascending (a lattice has few)
+    std::unordered_set<double> seen_v;
     for (int64_t i = 0; i < n; ++i) {
-      int64_t r = std::lower_bound(u.begin(), u.end(), vals[i]) - u.begin();
-      index[i] += r * stride;
+      seen_v.insert(centroid[i * dim + a]);
+      if ((int64_t)seen_v.size() > n) return false;
     }
+    std::vector<double> u(seen_v.begin(), seen_v.end());
+    std::sort(u.begin(), u.end());
+    shape[a] = (int)u.size();
+    parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+      for (int64_t i = lo; i < hi; ++i) {
+        const int64_t r = std::lower_bound(u.begin(), u.end(), centroid[i * dim + a]) - u.begin();
+        index[i] += r * stride;
+      }
+    });
     stride *= (int64_t)u.size();
   }
   if (stride != n) return false;
@@ -206,7 +227,8 @@ void renumber(Topo& t) {
   const int64_t nf = t.n_flux;
   struct Key { int64_t g0, g1, g2, kr, lo, hi, id; };
   std::vector<Key> keys(nf);
-  for (int64_t j = 0; j < nf; ++j) {
+  parallel_ranges(nf, [&](int64_t jlo, int64_t jhi) {
+  for (int64_t j = jlo; j < jhi; ++j) {
     const int64_t a = t.c1[j], b = t.c2[j];
     const int8_t k = t.kind[j];
     const int64_t a1 = t.agg[a];
@@ -225,6 +247,7 @@ void renumber(Topo& t) {
     key.id = j;
     keys[j] = key;
   }
+  });
   // Same order as sorting the whole key tuple, in two passes: a counting
   // sort on (group, first aggregate), then a sort of each (small) bucket on
   // the remaining fields.
@@ -237,12 +260,15 @@ void renumber(Topo& t) {
     std::vector<int64_t> fill(bptr.begin(), bptr.end() - 1);
     for (const Key& k : keys) sorted[fill[k.g0 * na + k.g1]++] = k;
   }
-  for (int64_t b = 0; b < 3 * na; ++b)
-    std::sort(sorted.begin() + bptr[b], sorted.begin() + bptr[b + 1], [](const Key& x, const Key& y) {
-      return std::tie(x.g2, x.kr, x.lo, x.hi, x.id) < std::tie(y.g2, y.kr, y.lo, y.hi, y.id);
-    });
   t.flux_order.resize(nf);
-  for (int64_t i = 0; i < nf; ++i) t.flux_order[i] = sorted[i].id;
+  parallel_ranges(3 * na, [&](int64_t blo, int64_t bhi) {
+    for (int64_t b = blo; b < bhi; ++b) {
+      std::sort(sorted.begin() + bptr[b], sorted.begin() + bptr[b + 1], [](const Key& x, const Key& y) {
+        return std::tie(x.g2, x.kr, x.lo, x.hi, x.id) < std::tie(y.g2, y.kr, y.lo, y.hi, y.id);
+      });
+      for (int64_t i = bptr[b]; i < bptr[b + 1]; ++i) t.flux_order[i] = sorted[i].id;
+    }
+  });
 }
 
 void build_cell_lists(Topo& t) {
