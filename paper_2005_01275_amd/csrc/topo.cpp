@@ -2,7 +2,11 @@
 #include "topo.hpp"
 
 #include <algorithm>
+#include <atomic>
+#include <climits>
+#include <mutex>
 #include <numeric>
+#include <string>
 #include <thread>
 #include <tuple>
 #include <unordered_set>
@@ -392,7 +396,9 @@ TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>&
     std::vector<int64_t> lo_ptr(na + 1, 0);
     for (int64_t J = 0; J < n_pairs; ++J) lo_ptr[c.c1[J] + 1]++;
     for (int64_t A = 0; A < na; ++A) lo_ptr[A + 1] += lo_ptr[A];
-    for (int64_t j = 0; j < f.n_flux; ++j) {
+    std::atomic<bool> orphan{false};
+    parallel_ranges(f.n_flux, [&](int64_t jlo, int64_t jhi) {
+    for (int64_t j = jlo; j < jhi; ++j) {
       const int8_t k = f.kind[j];
       const int64_t a1 = f.agg[f.c1[j]];
       if (k == FK_BUBBLE) {
@@ -406,12 +412,14 @@ TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>&
         const int64_t lo = std::min(a1, a2), hi = std::max(a1, a2);
         int64_t J = lo_ptr[lo];
         while (J < lo_ptr[lo + 1] && c.c2[J] != hi) ++J;
-        if (J == lo_ptr[lo + 1]) fail(SPFAS_ERR_INVALID, "fine face between aggregates without a coarse face");
-        grp_of[j] = J;
+        if (J == lo_ptr[lo + 1]) orphan = true;
+        else grp_of[j] = J;
       } else if (k == FK_DIRICHLET) {
         grp_of[j] = dir_id[a1];
       }
     }
+    });
+    if (orphan) fail(SPFAS_ERR_INVALID, "fine face between aggregates without a coarse face");
   }
   std::vector<int64_t> grp_ptr, grp_list, int_ptr, int_list;
   csr(c.n_flux, grp_of, grp_ptr);
@@ -438,63 +446,94 @@ TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>&
   P.fgrp_ptr = grp_ptr;
   P.fgrp_list.resize(grp_list.size());
   for (size_t q = 0; q < grp_list.size(); ++q) P.fgrp_list[q] = dev_flux[grp_list[q]];
-  P.cell_list.reserve(f.n_cells);
-  P.pd_list.reserve(f.n_p());
-  P.smap.reserve(f.cfidx.size());
-  P.smap_ptr.reserve(f.n_cells + 1);
-  std::vector<int64_t> dofs;
-  P.smap_ptr.assign(1, 0);
-  std::vector<int64_t> where(f.n_flux, -1);
   // device flux id -> canonical id (the device local lists are read in
   // device order, which is ascending device id within each cell)
   std::vector<int64_t> canon_of_dev(f.n_flux, -1);
-  for (int64_t j = 0; j < f.n_flux; ++j) canon_of_dev[dev_flux[j]] = j;
+  parallel_ranges(f.n_flux, [&](int64_t jlo, int64_t jhi) {
+    for (int64_t j = jlo; j < jhi; ++j) canon_of_dev[dev_flux[j]] = j;
+  });
+  // list offsets of every aggregate (cells, p unknowns, dofs) and of every
+  // member cell's scatter entries, so the aggregates fill their parts of
+  // the lists on host threads
+  P.cell_ptr = mem_ptr;
+  P.int_ptr = int_ptr;
+  const int64_t n_mem = mem_ptr[na];
+  P.smap_ptr.assign(n_mem + 1, 0);
   for (int64_t A = 0; A < na; ++A) {
-    P.mA[A] = (int32_t)(c.pptr[A + 1] - c.pptr[A]);
+    int64_t npd = 0, nd = int_ptr[A + 1] - int_ptr[A];
     for (int64_t m = mem_ptr[A]; m < mem_ptr[A + 1]; ++m) {
       const int64_t cell = members[m];
-      P.cell_list.push_back(dev_cell[cell]);
-      for (int64_t q = f.pptr[cell]; q < f.pptr[cell + 1]; ++q) P.pd_list.push_back(dev_p[q]);
+      npd += f.pptr[cell + 1] - f.pptr[cell];
+      P.smap_ptr[m + 1] = P.smap_ptr[m] + (f.cfptr[cell + 1] - f.cfptr[cell]);
     }
-    P.cell_ptr[A + 1] = (int64_t)P.cell_list.size();
-    P.pd_ptr[A + 1] = (int64_t)P.pd_list.size();
-    // dofs(A): int(A), then the groups of A's coarse faces in A's local order
-    dofs.assign(int_list.begin() + int_ptr[A], int_list.begin() + int_ptr[A + 1]);
-    P.n_int[A] = (int32_t)(int_ptr[A + 1] - int_ptr[A]);
     for (int64_t q = c.cfptr[A]; q < c.cfptr[A + 1]; ++q) {
-      int64_t J = c.cfidx[q];
-      if (c.kind[J] == FK_BUBBLE) continue;
-      int64_t off = (int64_t)dofs.size();
-      if (c.c1[J] == A) P.grp_pos_A[J] = off; else P.grp_pos_B[J] = off;
-      dofs.insert(dofs.end(), grp_list.begin() + grp_ptr[J], grp_list.begin() + grp_ptr[J + 1]);
+      const int64_t J = c.cfidx[q];
+      if (c.kind[J] != FK_BUBBLE) nd += grp_ptr[J + 1] - grp_ptr[J];
     }
-    for (size_t q = 0; q < dofs.size(); ++q) where[dofs[q]] = (int64_t)q;
-    for (int64_t m = mem_ptr[A]; m < mem_ptr[A + 1]; ++m) {
-      const int64_t cell = members[m];
-      int64_t dc = dev_cell[cell];
-      // the cell's fluxes in the device local order (ascending device id)
-      int64_t k = dev_cfptr[dc + 1] - dev_cfptr[dc];
-      if (f.cfptr[cell + 1] - f.cfptr[cell] != k) fail(SPFAS_ERR_INVALID, "local flux list mismatch");
-      int64_t prev = -1;
-      for (int64_t q = 0; q < k; ++q) {
-        const int64_t d = dev_cfidx[dev_cfptr[dc] + q];
-        if (d <= prev || d < 0 || d >= f.n_flux) fail(SPFAS_ERR_INVALID, "device local order mismatch");
-        prev = d;
-        const int64_t j = canon_of_dev[d];
-        if (f.c1[j] != cell && f.c2[j] != cell) fail(SPFAS_ERR_INVALID, "device local list holds a foreign flux");
-        int64_t w = where[j];
-        if (w < 0) fail(SPFAS_ERR_INVALID, "flux of an aggregate cell outside dofs(A)");
-        P.smap.push_back((int32_t)w);
-      }
-      P.smap_ptr.push_back((int64_t)P.smap.size());
-    }
-    for (int64_t j : dofs) {
-      where[j] = -1;
-      P.dof_list.push_back(dev_flux[j]);
-    }
-    P.int_ptr[A + 1] = P.int_ptr[A] + P.n_int[A];
-    P.dof_ptr[A + 1] = (int64_t)P.dof_list.size();
+    P.pd_ptr[A + 1] = P.pd_ptr[A] + npd;
+    P.dof_ptr[A + 1] = P.dof_ptr[A] + nd;
   }
+  P.cell_list.resize(n_mem);
+  P.pd_list.resize(P.pd_ptr[na]);
+  P.dof_list.resize(P.dof_ptr[na]);
+  P.smap.resize(P.smap_ptr[n_mem]);
+  std::mutex err_mu;
+  std::string err;   // first error of any thread, raised after the join
+  parallel_ranges(na, [&](int64_t alo, int64_t ahi) {
+    std::vector<int64_t> dofs;
+    std::vector<std::pair<int64_t, int64_t>> pos;   // (flux, position in dofs(A)) sorted by flux
+    try {
+      for (int64_t A = alo; A < ahi; ++A) {
+        P.mA[A] = (int32_t)(c.pptr[A + 1] - c.pptr[A]);
+        int64_t pq = P.pd_ptr[A];
+        for (int64_t m = mem_ptr[A]; m < mem_ptr[A + 1]; ++m) {
+          const int64_t cell = members[m];
+          P.cell_list[m] = dev_cell[cell];
+          for (int64_t q = f.pptr[cell]; q < f.pptr[cell + 1]; ++q) P.pd_list[pq++] = dev_p[q];
+        }
+        // dofs(A): int(A), then the groups of A's coarse faces in A's local order
+        dofs.assign(int_list.begin() + int_ptr[A], int_list.begin() + int_ptr[A + 1]);
+        P.n_int[A] = (int32_t)(int_ptr[A + 1] - int_ptr[A]);
+        for (int64_t q = c.cfptr[A]; q < c.cfptr[A + 1]; ++q) {
+          const int64_t J = c.cfidx[q];
+          if (c.kind[J] == FK_BUBBLE) continue;
+          const int64_t off = (int64_t)dofs.size();
+          if (c.c1[J] == A) P.grp_pos_A[J] = off; else P.grp_pos_B[J] = off;
+          dofs.insert(dofs.end(), grp_list.begin() + grp_ptr[J], grp_list.begin() + grp_ptr[J + 1]);
+        }
+        pos.resize(dofs.size());
+        for (size_t q = 0; q < dofs.size(); ++q) {
+          pos[q] = {dofs[q], (int64_t)q};
+          P.dof_list[P.dof_ptr[A] + q] = dev_flux[dofs[q]];
+        }
+        std::sort(pos.begin(), pos.end());
+        for (int64_t m = mem_ptr[A]; m < mem_ptr[A + 1]; ++m) {
+          const int64_t cell = members[m];
+          const int64_t dc = dev_cell[cell];
+          // the cell's fluxes in the device local order (ascending device id)
+          const int64_t k = dev_cfptr[dc + 1] - dev_cfptr[dc];
+          if (P.smap_ptr[m + 1] - P.smap_ptr[m] != k) fail(SPFAS_ERR_INVALID, "local flux list mismatch");
+          int64_t prev = -1;
+          for (int64_t q = 0; q < k; ++q) {
+            const int64_t d = dev_cfidx[dev_cfptr[dc] + q];
+            if (d <= prev || d < 0 || d >= f.n_flux) fail(SPFAS_ERR_INVALID, "device local order mismatch");
+            prev = d;
+            const int64_t j = canon_of_dev[d];
+            if (f.c1[j] != cell && f.c2[j] != cell) fail(SPFAS_ERR_INVALID, "device local list holds a foreign flux");
+            // the last position of j in dofs(A)
+            auto it = std::upper_bound(pos.begin(), pos.end(), std::make_pair(j, INT64_MAX));
+            if (it == pos.begin() || (it - 1)->first != j)
+              fail(SPFAS_ERR_INVALID, "flux of an aggregate cell outside dofs(A)");
+            P.smap[P.smap_ptr[m] + q] = (int32_t)(it - 1)->second;
+          }
+        }
+      }
+    } catch (const Error& e) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (err.empty()) err = e.what();
+    }
+  });
+  if (!err.empty()) fail(SPFAS_ERR_INVALID, err);
   return P;
 }
 
