@@ -15,6 +15,7 @@
 #include <cstring>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/spfas.h"
@@ -94,6 +95,20 @@ inline int trace_level() {
     return (e && e[0] && e[0] != '0') ? std::max(1, std::atoi(e)) : 0;
   }();
   return lv;
+}
+
+// f(lo, hi) on contiguous, ordered ranges of [0, n), one host thread each
+// (at most 16); every range writes only its own part of the output.
+template <class F>
+void parallel_ranges(int64_t n, F&& f) {
+  const int64_t nth = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), n}));
+  const int64_t per = (n + nth - 1) / nth;
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nth; ++t) {
+    const int64_t lo = std::min(n, t * per), hi = std::min(n, lo + per);
+    th.emplace_back([&f, lo, hi] { f(lo, hi); });
+  }
+  for (auto& x : th) x.join();
 }
 
 inline double wall_ms() {

@@ -13,6 +13,7 @@
 #include "amg_host.hpp"
 #include "kern.hpp"
 #include "prof.hpp"
+#include "sell_layout.hpp"
 
 namespace spfas {
 
@@ -995,32 +996,10 @@ int aggregate(const HostCsr& A, double theta, std::vector<int>& agg) {
 // SELL-64 pattern of a level (diagonal first in every row) and the map from
 // each stored entry to its FP64 source value.
 void build_sell(const HostCsr& H, AmgLevel& F, hipStream_t s) {
-  const int n = H.n, ns = (n + 63) / 64;
-  std::vector<int> sptr(ns + 1, 0);
-  for (int sl = 0; sl < ns; ++sl) {
-    int width = 1;
-    for (int i = sl * 64; i < std::min(n, sl * 64 + 64); ++i) width = std::max(width, 1 + H.ptr[i + 1] - H.ptr[i]);
-    require((long long)sptr[sl] + 64LL * width < INT_MAX, "AMG level too large for 32-bit SELL offsets");
-    sptr[sl + 1] = sptr[sl] + 64 * width;
-  }
-  const int ne = sptr[ns];
-  std::vector<int> col(ne, 0), map(ne, kSellPad);
-  for (int sl = 0; sl < ns; ++sl) {
-    const int width = (sptr[sl + 1] - sptr[sl]) / 64;
-    for (int lane = 0; lane < 64; ++lane) {
-      const int i = sl * 64 + lane;
-      const int base = sptr[sl] + lane;
-      if (i >= n) continue;   // lanes past the last row are never read
-      col[base] = i;
-      map[base] = -1 - i;
-      int k = 1;
-      for (int q = H.ptr[i]; q < H.ptr[i + 1]; ++q, ++k) {
-        col[base + 64 * k] = H.col[q];
-        map[base + 64 * k] = q;
-      }
-      for (; k < width; ++k) col[base + 64 * k] = i;
-    }
-  }
+  const int n = H.n;
+  std::vector<int> sptr, col, map;
+  sell_matrix_layout(n, H.ptr, H.col, kSellPad, sptr, col, map);
+  const int ne = (int)col.size();
   F.sptr.upload(sptr, s);
   F.scol.upload(col, s);
   F.smap.upload(map, s);
@@ -1055,33 +1034,9 @@ void build_cyc(int n, const std::vector<int>& ptr, const std::vector<int>& col, 
     M.val.alloc(std::max<size_t>(col.size(), 1));
     return;
   }
-  const int ns = (n + 63) / 64;
-  std::vector<int> sptr(ns + 1, 0);
-  for (int sl = 0; sl < ns; ++sl) {
-    int width = 1;
-    for (int i = sl * 64; i < std::min(n, sl * 64 + 64); ++i) width = std::max(width, ptr[i + 1] - ptr[i]);
-    require((long long)sptr[sl] + 64LL * width < INT_MAX, "AMG operator too large for 32-bit SELL offsets");
-    sptr[sl + 1] = sptr[sl] + 64 * width;
-  }
-  const int ne = sptr[ns];
-  std::vector<int> scol(ne, 0), ssrc(ne, -1);
-  for (int sl = 0; sl < ns; ++sl) {
-    const int width = (sptr[sl + 1] - sptr[sl]) / 64;
-    for (int lane = 0; lane < 64; ++lane) {
-      const int i = sl * 64 + lane;
-      if (i >= n) continue;
-      const int pad = ptr[i + 1] > ptr[i] ? col[ptr[i]] : 0;
-      for (int k = 0; k < width; ++k) {
-        const int slot = sptr[sl] + 64 * k + lane;
-        if (ptr[i] + k < ptr[i + 1]) {
-          scol[slot] = col[ptr[i] + k];
-          ssrc[slot] = src[ptr[i] + k];
-        } else {
-          scol[slot] = pad;
-        }
-      }
-    }
-  }
+  std::vector<int> sptr, scol, ssrc;
+  sell_cyc_layout(n, ptr, col, src, sptr, scol, ssrc);
+  const int ne = (int)scol.size();
   M.ptr.upload(sptr, s);
   M.col.upload(scol, s);
   M.src.upload(ssrc, s);
@@ -1097,43 +1052,74 @@ CycView cyc_view(const CycMat& M) { return CycView{M.n, M.ptr.p, M.col.p, M.val.
 // ascending, each entry's products in that traversal order.
 void build_fused(const HostCsr& A, const ClassicalLevel& CL, AmgLevel& F, hipStream_t s) {
   const int nc = CL.nc;
+  // rows of G in 16 ordered chunks on host threads, joined in row order
+  constexpr int kChunks = 16;
+  struct GChunk {
+    std::vector<int> col, rt, nprod, lp, la, rowlen;
+  };
+  std::vector<GChunk> gch(kChunks);
+  const int per = (nc + kChunks - 1) / kChunks;
+  parallel_ranges(kChunks, [&](int64_t tlo, int64_t thi) {
+    std::vector<int> slot(A.n, -1), cols, rt, cnt, start, order;
+    struct Item { int q, pe, code; };
+    std::vector<Item> items;
+    std::vector<std::pair<int, int>> grouped;
+    for (int64_t t = tlo; t < thi; ++t) {
+      GChunk& ch = gch[t];
+      for (int c = std::min(nc, (int)t * per); c < std::min(nc, (int)(t + 1) * per); ++c) {
+        cols.clear();
+        rt.clear();
+        items.clear();
+        auto at = [&](int j) -> int {
+          if (slot[j] < 0) {
+            slot[j] = (int)cols.size();
+            cols.push_back(j);
+            rt.push_back(-1);
+          }
+          return slot[j];
+        };
+        for (int e = CL.rptr[c]; e < CL.rptr[c + 1]; ++e) {
+          const int i = CL.rcol[e], pe = CL.rsrc[e];
+          const int qi = at(i);
+          rt[qi] = pe;
+          items.push_back({qi, pe, dia_code(i)});
+          for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) items.push_back({at(A.col[k]), pe, off_code(k)});
+        }
+        // products grouped by column, in generation order within a column
+        cnt.assign(cols.size() + 1, 0);
+        for (const Item& it : items) cnt[it.q + 1]++;
+        for (size_t q = 0; q < cols.size(); ++q) cnt[q + 1] += cnt[q];
+        start.assign(cnt.begin(), cnt.end() - 1);
+        grouped.resize(items.size());
+        for (const Item& it : items) grouped[start[it.q]++] = {it.pe, it.code};
+        order.resize(cols.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int x, int y) { return cols[x] < cols[y]; });
+        for (int q : order) {
+          ch.col.push_back(cols[q]);
+          ch.rt.push_back(rt[q]);
+          ch.nprod.push_back(cnt[q + 1] - cnt[q]);
+          for (int k = cnt[q]; k < cnt[q + 1]; ++k) {
+            ch.lp.push_back(grouped[k].first);
+            ch.la.push_back(grouped[k].second);
+          }
+        }
+        for (int j : cols) slot[j] = -1;
+        ch.rowlen.push_back((int)cols.size());
+      }
+    }
+  });
   std::vector<int> gptr(nc + 1, 0), gcol, grt, glptr(1, 0), glp, gla, src;
-  std::vector<int> slot(A.n, -1);
-  std::vector<int> cols, rt;
-  std::vector<std::vector<std::pair<int, int>>> prods;
-  for (int c = 0; c < nc; ++c) {
-    cols.clear();
-    rt.clear();
-    prods.clear();
-    auto at = [&](int j) -> int {
-      if (slot[j] < 0) {
-        slot[j] = (int)cols.size();
-        cols.push_back(j);
-        rt.push_back(-1);
-        prods.emplace_back();
-      }
-      return slot[j];
-    };
-    for (int t = CL.rptr[c]; t < CL.rptr[c + 1]; ++t) {
-      const int i = CL.rcol[t], pe = CL.rsrc[t];
-      rt[at(i)] = pe;
-      prods[at(i)].emplace_back(pe, dia_code(i));
-      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) prods[at(A.col[k])].emplace_back(pe, off_code(k));
+  {
+    int row = 0;
+    for (const GChunk& ch : gch) {
+      for (int len : ch.rowlen) { gptr[row + 1] = gptr[row] + len; ++row; }
+      gcol.insert(gcol.end(), ch.col.begin(), ch.col.end());
+      grt.insert(grt.end(), ch.rt.begin(), ch.rt.end());
+      glp.insert(glp.end(), ch.lp.begin(), ch.lp.end());
+      gla.insert(gla.end(), ch.la.begin(), ch.la.end());
+      for (int np : ch.nprod) glptr.push_back(glptr.back() + np);
     }
-    std::vector<int> order(cols.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::sort(order.begin(), order.end(), [&](int a, int b) { return cols[a] < cols[b]; });
-    for (int q : order) {
-      gcol.push_back(cols[q]);
-      grt.push_back(rt[q]);
-      for (const auto& pr : prods[q]) {
-        glp.push_back(pr.first);
-        gla.push_back(pr.second);
-      }
-      glptr.push_back((int)glp.size());
-    }
-    for (int j : cols) slot[j] = -1;
-    gptr[c + 1] = (int)gcol.size();
   }
   src.resize(gcol.size());
   std::iota(src.begin(), src.end(), 0);
@@ -1197,18 +1183,8 @@ void Amg::setup(const CsrView& A0, hipStream_t s, bool sell64, int dense_max, bo
     t_prod += t1 - t0;
     AmgLevel& F = lv.back();
     {   // A diag(w): every row as [diagonal, off-diagonal entries]
-      std::vector<int> p(H.n + 1, 0), c, src;
-      c.reserve(H.n + H.col.size());
-      src.reserve(H.n + H.col.size());
-      for (int i = 0; i < H.n; ++i) {
-        c.push_back(i);
-        src.push_back(dia_code(i));
-        for (int k = H.ptr[i]; k < H.ptr[i + 1]; ++k) {
-          c.push_back(H.col[k]);
-          src.push_back(off_code(k));
-        }
-        p[i + 1] = (int)c.size();
-      }
+      std::vector<int> p, c, src;
+      aw_rows(H.n, H.ptr, H.col, p, c, src, dia_code, off_code);
       build_cyc(H.n, p, c, src, F.aw, s);
     }
     build_cyc(CL.nc, CL.rptr, CL.rcol, CL.rsrc, F.rm, s);

@@ -7,27 +7,12 @@
 #include <mutex>
 #include <numeric>
 #include <string>
-#include <thread>
 #include <tuple>
 #include <unordered_set>
 
 #include "common.hpp"
 
 namespace spfas {
-
-// f(lo, hi) on contiguous, ordered ranges of [0, n), one host thread each
-// (at most 16); every range writes only its own part of the output.
-template <class F>
-static void parallel_ranges(int64_t n, F&& f) {
-  const int64_t nth = std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), n}));
-  const int64_t per = (n + nth - 1) / nth;
-  std::vector<std::thread> th;
-  for (int64_t t = 0; t < nth; ++t) {
-    const int64_t lo = std::min(n, t * per), hi = std::min(n, lo + per);
-    th.emplace_back([&f, lo, hi] { f(lo, hi); });
-  }
-  for (auto& x : th) x.join();
-}
 
 bool lattice_from_centroids(int dim, int64_t n, const double* centroid, std::vector<int>& shape,
                             std::vector<int64_t>& index) {
