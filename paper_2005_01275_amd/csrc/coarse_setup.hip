@@ -905,6 +905,7 @@ void setup_coarse_levels(Hierarchy& h) {
     PlanView pv = plan_view(T);
     const bool tr_on = trace_level() > 0;
     double t_a = wall_ms();
+    if (tr_on) std::fprintf(stderr, "[spfas] setup level %d->%d host: uploads at %.1f ms\n", l, l + 1, t_a - t_level);
     // ---- phase A: PV traces
     int n_faces_c = 0;
     while (n_faces_c < C.nf && C.h_kind[n_faces_c] != FK_BUBBLE) ++n_faces_c;
@@ -980,6 +981,7 @@ void setup_coarse_levels(Hierarchy& h) {
         std::fprintf(stderr, "[spfas] setup level %d->%d aggregates: %d, max np %zu, max nd %zu, max nI %zu, %zu "
                      "workgroups: %.1f ms\n", l, l + 1, T.n_agg, mx_np, mx_nd, mx_nI, slots, wall_ms() - t_b);
     }
+    if (tr_on) std::fprintf(stderr, "[spfas] setup level %d->%d: aggregates done at %.1f ms\n", l, l + 1, wall_ms() - t_level);
     std::vector<int> hb = bad.download(s);
     if (hb[0] != 0) {
       char buf[200];
