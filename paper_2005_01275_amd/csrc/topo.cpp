@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <atomic>
 #include <climits>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -80,21 +81,38 @@ void box_aggregate(Topo& t, const int box[3]) {
 // level's interior flux unknowns.
 static void cell_neighbours(const Topo& t, std::vector<int64_t>& ptr, std::vector<int64_t>& nb) {
   const int64_t n = t.n_cells;
-  std::vector<std::vector<int64_t>> lists(n);
+  // both cells of every interior flux, grouped by cell (flux order)
+  std::vector<int64_t> deg(n + 1, 0);
   for (int64_t j = 0; j < t.n_flux; ++j)
     if (t.kind[j] == FK_INTERIOR && t.c2[j] >= 0) {
-      lists[t.c1[j]].push_back(t.c2[j]);
-      lists[t.c2[j]].push_back(t.c1[j]);
+      deg[t.c1[j] + 1]++;
+      deg[t.c2[j] + 1]++;
     }
-  ptr.assign(n + 1, 0);
-  nb.clear();
-  for (int64_t c = 0; c < n; ++c) {
-    auto& v = lists[c];
-    std::sort(v.begin(), v.end());
-    v.erase(std::unique(v.begin(), v.end()), v.end());
-    nb.insert(nb.end(), v.begin(), v.end());
-    ptr[c + 1] = (int64_t)nb.size();
+  for (int64_t c = 0; c < n; ++c) deg[c + 1] += deg[c];
+  std::unique_ptr<int64_t[]> raw(new int64_t[deg[n]]);   // every entry written below
+  {
+    std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
+    for (int64_t j = 0; j < t.n_flux; ++j)
+      if (t.kind[j] == FK_INTERIOR && t.c2[j] >= 0) {
+        raw[fill[t.c1[j]]++] = t.c2[j];
+        raw[fill[t.c2[j]]++] = t.c1[j];
+      }
   }
+  // each row sorted without repeats (rows on host threads), then compacted
+  ptr.assign(n + 1, 0);
+  parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t c = lo; c < hi; ++c) {
+      int64_t *b = raw.get() + deg[c], *e = raw.get() + deg[c + 1];
+      std::sort(b, e);
+      ptr[c + 1] = std::unique(b, e) - b;
+    }
+  });
+  for (int64_t c = 0; c < n; ++c) ptr[c + 1] += ptr[c];
+  nb.resize(ptr[n]);
+  parallel_ranges(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t c = lo; c < hi; ++c)
+      std::copy(raw.get() + deg[c], raw.get() + deg[c] + (ptr[c + 1] - ptr[c]), nb.begin() + ptr[c]);
+  });
 }
 
 void user_aggregate(Topo& t, const int32_t* agg, int64_t len) {
@@ -165,6 +183,9 @@ void greedy_aggregate(Topo& t, int target) {
   // the surviving aggregates
   std::vector<int64_t> label(na0);
   std::iota(label.begin(), label.end(), 0);
+  // original ids carrying each surviving label
+  std::vector<std::vector<int64_t>> carried(na0);
+  for (int64_t A = 0; A < na0; ++A) carried[A].assign(1, A);
   std::vector<char> alive(na0, 1);
   std::vector<int64_t> count(na0, 0), touched;
   for (int64_t A = 0; A < na0; ++A) {
@@ -187,8 +208,9 @@ void greedy_aggregate(Topo& t, int target) {
     for (int64_t u : members[A]) members[best].push_back(u);
     members[A].clear();
     alive[A] = 0;
-    for (int64_t X = 0; X < na0; ++X)
-      if (label[X] == A) label[X] = best;
+    for (int64_t X : carried[A]) label[X] = best;
+    carried[best].insert(carried[best].end(), carried[A].begin(), carried[A].end());
+    carried[A].clear();
   }
   // compact ids in ascending order of the surviving labels
   std::vector<int64_t> newid(na0, -1);
@@ -214,45 +236,47 @@ void renumber(Topo& t) {
   std::vector<int64_t> pos(n);
   for (int64_t i = 0; i < n; ++i) pos[t.cell_order[i]] = i;
   const int64_t nf = t.n_flux;
-  struct Key { int64_t g0, g1, g2, kr, lo, hi, id; };
-  std::vector<Key> keys(nf);
-  parallel_ranges(nf, [&](int64_t jlo, int64_t jhi) {
-  for (int64_t j = jlo; j < jhi; ++j) {
-    const int64_t a = t.c1[j], b = t.c2[j];
-    const int8_t k = t.kind[j];
-    const int64_t a1 = t.agg[a];
-    const int64_t a2 = b >= 0 ? t.agg[b] : -1;
-    const bool inside = (k == FK_BUBBLE) || (k == FK_INTERIOR && a1 == a2);
-    const bool cross = (k == FK_INTERIOR && a1 != a2);
-    Key key;
-    key.g0 = inside ? 0 : (cross ? 1 : 2);
-    key.g1 = cross ? std::min(a1, a2) : a1;
-    key.g2 = cross ? std::max(a1, a2) : 0;
-    key.kr = (k == FK_BUBBLE) ? 1 : 0;
-    const int64_t p1 = pos[a];
-    const int64_t p2 = b >= 0 ? pos[b] : p1;
-    key.lo = std::min(p1, p2);
-    key.hi = std::max(p1, p2);
-    key.id = j;
-    keys[j] = key;
-  }
-  });
-  // Same order as sorting the whole key tuple, in two passes: a counting
-  // sort on (group, first aggregate), then a sort of each (small) bucket on
-  // the remaining fields.
+  // Same order as sorting the whole key tuple (group, first aggregate,
+  // second aggregate, bubble, lo, hi, id), in two passes: a counting sort on
+  // the bucket (group, first aggregate), then a sort of each (small) bucket
+  // on the remaining fields, which id makes a total order.
   const int64_t na = t.n_agg;
+  struct Key { int64_t g2, kr, lo, hi, id; };
+  // uninitialised: every entry is written by the threads below
+  std::unique_ptr<Key[]> keys(new Key[nf]);
+  std::unique_ptr<int64_t[]> bkt(new int64_t[nf]);
+  parallel_ranges(nf, [&](int64_t jlo, int64_t jhi) {
+    for (int64_t j = jlo; j < jhi; ++j) {
+      const int64_t a = t.c1[j], b = t.c2[j];
+      const int8_t k = t.kind[j];
+      const int64_t a1 = t.agg[a];
+      const int64_t a2 = b >= 0 ? t.agg[b] : -1;
+      const bool inside = (k == FK_BUBBLE) || (k == FK_INTERIOR && a1 == a2);
+      const bool cross = (k == FK_INTERIOR && a1 != a2);
+      const int64_t g0 = inside ? 0 : (cross ? 1 : 2);
+      const int64_t g1 = cross ? std::min(a1, a2) : a1;
+      const int64_t p1 = pos[a];
+      const int64_t p2 = b >= 0 ? pos[b] : p1;
+      bkt[j] = g0 * na + g1;
+      keys[j] = Key{cross ? std::max(a1, a2) : 0, (k == FK_BUBBLE) ? 1 : 0, std::min(p1, p2), std::max(p1, p2), j};
+    }
+  });
   std::vector<int64_t> bptr(3 * na + 1, 0);
-  for (const Key& k : keys) bptr[k.g0 * na + k.g1 + 1]++;
+  for (int64_t j = 0; j < nf; ++j) bptr[bkt[j] + 1]++;
   for (int64_t b = 0; b < 3 * na; ++b) bptr[b + 1] += bptr[b];
-  std::vector<Key> sorted(nf);
+  std::unique_ptr<Key[]> sorted(new Key[nf]);
   {
-    std::vector<int64_t> fill(bptr.begin(), bptr.end() - 1);
-    for (const Key& k : keys) sorted[fill[k.g0 * na + k.g1]++] = k;
+    // scattered on host threads: the order inside a bucket is fixed by the sort below
+    std::vector<std::atomic<int64_t>> fill(3 * na);
+    for (int64_t b = 0; b < 3 * na; ++b) fill[b].store(bptr[b], std::memory_order_relaxed);
+    parallel_ranges(nf, [&](int64_t jlo, int64_t jhi) {
+      for (int64_t j = jlo; j < jhi; ++j) sorted[fill[bkt[j]].fetch_add(1, std::memory_order_relaxed)] = keys[j];
+    });
   }
   t.flux_order.resize(nf);
   parallel_ranges(3 * na, [&](int64_t blo, int64_t bhi) {
     for (int64_t b = blo; b < bhi; ++b) {
-      std::sort(sorted.begin() + bptr[b], sorted.begin() + bptr[b + 1], [](const Key& x, const Key& y) {
+      std::sort(sorted.get() + bptr[b], sorted.get() + bptr[b + 1], [](const Key& x, const Key& y) {
         return std::tie(x.g2, x.kr, x.lo, x.hi, x.id) < std::tie(y.g2, y.kr, y.lo, y.hi, y.id);
       });
       for (int64_t i = bptr[b]; i < bptr[b + 1]; ++i) t.flux_order[i] = sorted[i].id;
