@@ -314,7 +314,8 @@ void spfas_default_solve_opts(spfas_solve_opts* o);
  * hierarchy depends on the mesh only and serves any number of solves.
  * allocator: see spfas_allocator; NULL for hipMalloc / hipFree.
  * Errors: ERR_INVALID for a malformed mesh (index out of range, non-positive
- * volume or half-transmissibility, no Dirichlet face, n_levels < 1, a lattice
+ * volume, face area or half-transmissibility, a non-finite centroid, no
+ * Dirichlet face, n_levels < 1, a lattice
  * that cannot be recovered from the centroids for BOX, a malformed USER
  * aggregation), ERR_OOM, ERR_DEVICE.
  * *out receives a handle to be released with spfas_destroy.

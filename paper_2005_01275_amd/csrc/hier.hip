@@ -73,6 +73,8 @@ static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
   int64_t ndir = 0;
   for (int64_t c = 0; c < M.n_cells; ++c)
     require(M.cell_volume[c] > 0.0 && std::isfinite(M.cell_volume[c]), "cell volumes must be positive");
+  for (int64_t i = 0; i < M.n_cells * M.dim; ++i)
+    require(std::isfinite(M.cell_centroid[i]), "cell centroids must be finite");
   for (int64_t f = 0; f < M.n_faces; ++f) {
     const int K = M.face_cells[2 * f], L = M.face_cells[2 * f + 1];
     const int k = M.face_kind[f];
@@ -81,7 +83,7 @@ static void validate_mesh(const spfas_mesh& M, const spfas_coarsen_opts& o) {
     require(k >= 0 && k <= 2, "face_kind must be 0, 1 or 2");
     require((k == SPFAS_FACE_INTERIOR) == (L >= 0), "interior faces need L >= 0, boundary faces L = -1");
     require(L != K, "a face must join two different cells");
-    require(M.face_area[f] > 0.0, "face areas must be positive");
+    require(M.face_area[f] > 0.0 && std::isfinite(M.face_area[f]), "face areas must be positive and finite");
     ndir += (k == SPFAS_FACE_DIRICHLET);
   }
   require(ndir > 0, "at least one Dirichlet face is required");

@@ -47,6 +47,16 @@ def test_invalid_mesh_rejected():
     bad3 = type(m)(**{**m.__dict__, "face_cells": fc})
     with pytest.raises(pk.SpfasError, match="out of range"):
         pk.Hierarchy(bad3, 2, (2, 2), 2, host_only=True)
+    cen = m.cell_centroid.copy()
+    cen[3, 1] = np.nan   # refused up front: the lattice recovery sorts the centroid values
+    bad4 = type(m)(**{**m.__dict__, "cell_centroid": cen})
+    with pytest.raises(pk.SpfasError, match="centroids must be finite"):
+        pk.Hierarchy(bad4, 2, (2, 2), 2, host_only=True)
+    area = m.face_area.copy()
+    area[2] = np.inf
+    bad5 = type(m)(**{**m.__dict__, "face_area": area})
+    with pytest.raises(pk.SpfasError, match="face areas"):
+        pk.Hierarchy(bad5, 2, (2, 2), 2, host_only=True)
 
 
 def oracle_topology(prob, n_levels, box, m):
