@@ -20,11 +20,24 @@ int host_threads() {
   return (int)std::max(1u, std::min(16u, hc));
 }
 
-// f(t, lo, hi) on nth contiguous, ordered chunks of [0, n), one thread each.
+// Below this many rows (or units of work) a step runs its chunks in order
+// in the calling thread: thread start-up would cost more than it saves.
+constexpr int kGrain = 16384;
+
+// f(t, lo, hi) on nth contiguous, ordered chunks of [0, n), one thread each
+// (in the calling thread, one after the other, when n is small; the chunks
+// and so the results are the same).
 template <class F>
 void parallel_chunks(int n, int nth, F&& f) {
-  std::vector<std::thread> th;
   const int per = (n + nth - 1) / nth;
+  if (n < kGrain) {
+    for (int t = 0; t < nth; ++t) {
+      const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
+      f(t, lo, hi);
+    }
+    return;
+  }
+  std::vector<std::thread> th;
   for (int t = 0; t < nth; ++t) {
     const int lo = std::min(n, t * per), hi = std::min(n, lo + per);
     th.emplace_back([&f, t, lo, hi] { f(t, lo, hi); });
@@ -32,10 +45,16 @@ void parallel_chunks(int n, int nth, F&& f) {
   for (auto& x : th) x.join();
 }
 
-// f(t) for t < nth, one thread each.
+// f(t) for t < nth, one thread each when `work` is large enough.
 template <class F>
-void per_chunk(int nth, F&& f) {
-  parallel_chunks(nth, nth, [&f](int t, int, int) { f(t); });
+void per_chunk(int nth, size_t work, F&& f) {
+  if (work < (size_t)kGrain) {
+    for (int t = 0; t < nth; ++t) f(t);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 0; t < nth; ++t) th.emplace_back([&f, t] { f(t); });
+  for (auto& x : th) x.join();
 }
 
 // Exclusive prefix sums of per-chunk sizes: off[t] is where chunk t starts.
@@ -118,7 +137,7 @@ std::vector<int> pmis(const Strength& S, int n, uint64_t seed) {
   auto join = [&](std::vector<int>& out) {
     const std::vector<size_t> off = chunk_offsets(nth, [&](int t) { return part[t].size(); });
     out.resize(off[nth]);
-    per_chunk(nth, [&](int t) { std::copy(part[t].begin(), part[t].end(), out.begin() + off[t]); });
+    per_chunk(nth, off[nth], [&](int t) { std::copy(part[t].begin(), part[t].end(), out.begin() + off[t]); });
   };
   std::vector<int> sel, rest;
   while (!und.empty()) {
@@ -300,7 +319,7 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
     L.pptr.assign(n + 1, 0);
     L.pcol.resize(eo[nth]);
     L.pval.resize(eo[nth]);
-    per_chunk(nth, [&](int t) {
+    per_chunk(nth, eo[nth], [&](int t) {
       PChunk& ch = pch[t];
       std::copy(ch.col.begin(), ch.col.end(), L.pcol.begin() + eo[t]);
       std::copy(ch.val.begin(), ch.val.end(), L.pval.begin() + eo[t]);
@@ -393,7 +412,7 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
     L.aplptr[0] = 0;
     L.apla.resize(po[nth]);
     L.aplp.resize(po[nth]);
-    per_chunk(nth, [&](int t) {
+    per_chunk(nth, po[nth], [&](int t) {
       ApChunk& ch = apc[t];
       std::copy(ch.col.begin(), ch.col.end(), L.apcol.begin() + eo[t]);
       std::copy(ch.pidx.begin(), ch.pidx.end(), L.appidx.data() + eo[t]);
@@ -471,7 +490,7 @@ bool classical_level(const HostCsr& A, double theta, uint64_t seed, ClassicalLev
     L.clptr[0] = 0;
     L.clr.resize(base + dof[nth]);
     L.clq.resize(base + dof[nth]);
-    per_chunk(nth, [&](int t) {
+    per_chunk(nth, base + dof[nth], [&](int t) {
       RapChunk& ch = rpc[t];
       std::copy(ch.col.begin(), ch.col.end(), C.col.begin() + eo[t]);
       std::copy(ch.val.begin(), ch.val.end(), C.val.begin() + eo[t]);

@@ -16,10 +16,13 @@ template <class Len>
 std::vector<int> sell_slice_ptr(int n, Len len, const char* what) {
   const int ns = (n + 63) / 64;
   std::vector<int> width(ns, 1);
-  parallel_ranges(ns, [&](int64_t lo, int64_t hi) {
-    for (int64_t sl = lo; sl < hi; ++sl)
-      for (int i = (int)sl * 64; i < std::min(n, (int)sl * 64 + 64); ++i) width[sl] = std::max(width[sl], len(i));
-  });
+  parallel_ranges(
+      ns,
+      [&](int64_t lo, int64_t hi) {
+        for (int64_t sl = lo; sl < hi; ++sl)
+          for (int i = (int)sl * 64; i < std::min(n, (int)sl * 64 + 64); ++i) width[sl] = std::max(width[sl], len(i));
+      },
+      n);
   std::vector<int> sptr(ns + 1, 0);
   long long off = 0;
   for (int sl = 0; sl < ns; ++sl) {
@@ -57,7 +60,7 @@ inline void sell_matrix_layout(int n, const std::vector<int>& ptr, const std::ve
         for (; k < width; ++k) col[base + 64 * k] = i;
       }
     }
-  });
+  }, (int64_t)col.size());
 }
 
 // SELL layout of CSR rows with a source code per entry: padding slots read
@@ -88,7 +91,7 @@ inline void sell_cyc_layout(int n, const std::vector<int>& ptr, const std::vecto
         }
       }
     }
-  });
+  }, (int64_t)scol.size());
 }
 
 // CSR rows of A diag(w) for a DIA+CSR matrix: every row as [diagonal,
@@ -109,7 +112,7 @@ inline void aw_rows(int n, const std::vector<int>& ptr, const std::vector<int>& 
         src[e] = off(k);
       }
     }
-  });
+  }, (int64_t)c.size());
 }
 
 }  // namespace spfas

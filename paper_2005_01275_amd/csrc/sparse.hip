@@ -1108,7 +1108,7 @@ void build_fused(const HostCsr& A, const ClassicalLevel& CL, AmgLevel& F, hipStr
         ch.rowlen.push_back((int)cols.size());
       }
     }
-  });
+  }, (int64_t)A.n + A.ptr[A.n]);
   std::vector<int> gptr(nc + 1, 0), gcol, grt, glptr(1, 0), glp, gla, src;
   {
     int row = 0;

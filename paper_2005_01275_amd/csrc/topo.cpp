@@ -281,7 +281,7 @@ void renumber(Topo& t) {
       });
       for (int64_t i = bptr[b]; i < bptr[b + 1]; ++i) t.flux_order[i] = sorted[i].id;
     }
-  });
+  }, nf);
 }
 
 void build_cell_lists(Topo& t) {
@@ -541,7 +541,7 @@ TransferPlan make_plan(const Topo& f, const Topo& c, const std::vector<int64_t>&
       std::lock_guard<std::mutex> lk(err_mu);
       if (err.empty()) err = e.what();
     }
-  });
+  }, f.n_flux);
   if (!err.empty()) fail(SPFAS_ERR_INVALID, err);
   return P;
 }
