@@ -10,7 +10,7 @@ import pytest
 from problems import small_problem
 from problems.grids import voronoi_problem
 from oracle.fv import fine_level
-from oracle.coarsen import greedy_aggregate, build_hierarchy, box_aggregate
+from oracle.coarsen import greedy_aggregate, build_hierarchy, box_aggregate, renumber
 
 
 def level0(prob):
@@ -101,6 +101,23 @@ def test_greedy_bit_exact(case):
         np.testing.assert_array_equal(f, tr.flux_order)
         clev = h.levels[l + 1]
         assert H.level_sizes(l + 1) == (clev.n_cells, clev.n_p, clev.n_flux)
+
+
+def test_greedy_bit_exact_on_the_threaded_host_path():
+    """40,000 Voronoi cells: above the size from which the library's host
+    steps (neighbour lists, renumbering keys and bucket sorts) run on
+    several threads; level-0 aggregation and renumbering against the
+    oracle's, bit for bit."""
+    from paper_2005_01275_amd import _native as N
+    prob = voronoi_problem(40000, seed=5, n_levels=2)
+    lev = level0(prob)
+    agg = greedy_aggregate(lev, 64)
+    co, fo = renumber(lev, agg)
+    H = host_handle(prob, 2, agg_kind=N.SPFAS_AGG_GREEDY, greedy_size=64)
+    np.testing.assert_array_equal(H.aggregation(0), agg)
+    c, f = H.permutation(0)
+    np.testing.assert_array_equal(c, co)
+    np.testing.assert_array_equal(f, fo)
 
 
 def test_user_aggregation_equal_to_boxes_gives_the_box_topology():
