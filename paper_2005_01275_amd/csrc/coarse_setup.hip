@@ -129,7 +129,10 @@ __device__ inline void pv_union_level0(const LocalView& lv, const PlanView& pl, 
   wg_sync();
 }
 
-__global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, int n_faces, const int* __restrict__ fc1,
+// order: the interfaces in processing order (largest first, so that the
+// workgroups that take a second interface take small ones), or null.
+__global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, int n_faces, const int* __restrict__ order,
+                                                     const int* __restrict__ fc1,
                                                      const int* __restrict__ fc2, const double* __restrict__ ones,
                                                      double* __restrict__ trace, double* __restrict__ scratch,
                                                      ScratchA sa, int* __restrict__ bad) {
@@ -139,7 +142,8 @@ __global__ void __launch_bounds__(kBlock) k_pv_trace(LocalView lv, PlanView pl, 
   double* T = Du + sa.du;
   double* L = T + sa.t;
   double* y = L + sa.l;
-  for (int F = blockIdx.x; F < n_faces; F += gridDim.x) {
+  for (int Fi = blockIdx.x; Fi < n_faces; Fi += gridDim.x) {
+    const int F = order ? order[Fi] : Fi;
     const int A = fc1[F], B = fc2[F];
     const int nIA = pl.n_int[A], nIB = B >= 0 ? pl.n_int[B] : 0;
     const int nF = pl.fgrp_ptr[F + 1] - pl.fgrp_ptr[F];
@@ -928,8 +932,24 @@ void setup_coarse_levels(Hierarchy& h) {
       const size_t slots = slots_for(sa.total, n_faces_c);
       DVec<double> scr;
       scr.alloc(slots * sa.total);
-      hipLaunchKernelGGL(k_pv_trace, dim3((unsigned)slots), dim3(kBlock), 0, s, lv, pv, n_faces_c, C.c1.p, C.c2.p,
-                         ones_l, T.trace.p, scr.p, sa, bad.p);
+      // with fewer workgroups than interfaces, the largest (by the cube of
+      // the local problem size) go first
+      DVec<int> order;
+      if (slots < (size_t)n_faces_c) {
+        std::vector<double> cost(n_faces_c);
+        for (int J = 0; J < n_faces_c; ++J) {
+          const int A = C.h_c1[J], B = C.h_c2[J];
+          const double ns = (double)(plan.n_int[A] + (B >= 0 ? plan.n_int[B] : 0) +
+                                     (plan.fgrp_ptr[J + 1] - plan.fgrp_ptr[J]));
+          cost[J] = ns * ns * ns;
+        }
+        std::vector<int> ord(n_faces_c);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        order.upload(ord, s);
+      }
+      hipLaunchKernelGGL(k_pv_trace, dim3((unsigned)slots), dim3(kBlock), 0, s, lv, pv, n_faces_c,
+                         (const int*)order.p, C.c1.p, C.c2.p, ones_l, T.trace.p, scr.p, sa, bad.p);
       LAUNCHCHECK();
       HIPCHECK(hipStreamSynchronize(s));
       if (tr_on)
