@@ -14,11 +14,8 @@ namespace spfas {
 
 namespace {
 
-// Host threads for the row-parallel setup steps (at most 16).
-int host_threads() {
-  const unsigned hc = std::thread::hardware_concurrency();
-  return (int)std::max(1u, std::min(16u, hc));
-}
+// Host threads for the row-parallel setup steps.
+int host_threads() { return host_thread_limit(); }
 
 // Below this many rows (or units of work) a step runs its chunks in order
 // in the calling thread: thread start-up would cost more than it saves.

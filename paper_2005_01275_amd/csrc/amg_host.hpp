@@ -7,12 +7,25 @@
 // every linearisation from the product lists built here.
 #pragma once
 
+#include <algorithm>
 #include <cstddef>
 #include <cstdint>
 #include <memory>
+#include <thread>
 #include <vector>
 
 namespace spfas {
+
+// Host threads one setup step may use: at most 16, and at most
+// tl_host_threads when a caller sets it (a serving worker takes its share,
+// so that setups running side by side do not oversubscribe the host).
+constexpr int kMaxHostThreads = 16;
+inline thread_local int tl_host_threads = 0;
+inline int host_thread_limit() {
+  const int hc = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int lim = std::min(kMaxHostThreads, hc);
+  return tl_host_threads > 0 ? std::min(lim, tl_host_threads) : lim;
+}
 
 // DIA+CSR matrix on the host: diagonal separately, off-diagonal entries in CSR.
 struct HostCsr {

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "../../include/spfas.h"
+#include "amg_host.hpp"
 
 namespace spfas {
 
@@ -98,15 +99,14 @@ inline int trace_level() {
 }
 
 // f(lo, hi) on contiguous, ordered ranges of [0, n), one host thread each
-// (at most 16, and at most one per kParGrain units of `work`, which defaults
+// (at most host_thread_limit(), and at most one per kParGrain units of `work`, which defaults
 // to n: small inputs run inline, without thread start-up); every range
 // writes only its own part of the output.
 constexpr int64_t kParGrain = 16384;
 template <class F>
 void parallel_ranges(int64_t n, F&& f, int64_t work = -1) {
   const int64_t w = work < 0 ? n : work;
-  const int64_t nth =
-      std::max<int64_t>(1, std::min<int64_t>({16, (int64_t)std::thread::hardware_concurrency(), n, w / kParGrain}));
+  const int64_t nth = std::max<int64_t>(1, std::min<int64_t>({(int64_t)host_thread_limit(), n, w / kParGrain}));
   if (nth <= 1) {
     f((int64_t)0, n);
     return;

@@ -171,6 +171,8 @@ struct spfas_server {
   void work(int w) {
     hipStream_t s = streams[w];
     (void)hipSetDevice(o.device);
+    // this worker's share of the host threads for the setups it runs
+    tl_host_threads = std::max(1, kMaxHostThreads / std::max(1, o.n_slots));
     for (;;) {
       Request* r = nullptr;
       Model* m = nullptr;
